@@ -1,0 +1,215 @@
+"""Benchmark: one step = the whole hot path on one problem.
+
+Workload (default): 64x64 elements, GLL order 16, kappa = eta = 200, coefficient
+b = sum of 8 seeded Gaussian bumps (seed 3), plane-wave impedance data,
+coarse level L = 12 (the top interface), 5 coarse GMRES iterations, flexible
+GMRES(60) to a relative residual of 1e-8.  One step = leaf ItI build + all 11
+merge levels + right-hand side + preconditioned FGMRES solve.  The coefficient
+and boundary data are on the device before the timed region starts.
+
+Metric: skeleton DOF per second = 4 (N-1) n (n-1) / (build + solve time).
+
+Prints ONE JSON line (see the repository documentation for the fields).
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "skeleton DOF/s to rel.res 1e-8, mixed vs FP64; served solves/s + p99 latency"
+UNIT = "skeleton DOF/s"
+MI355X_HBM_GBS = 8000.0
+MI355X_FP64_TFLOPS = 78.6
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=64)
+    ap.add_argument("--order", type=int, default=16)
+    ap.add_argument("--kappa", type=float, default=200.0)
+    ap.add_argument("--levels", type=int, default=12)
+    ap.add_argument("--coarse-iters", type=int, default=5)
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+def leaf_flops_executed(N):
+    """Real flops of the leaf kernel per element: partial LU of the bordered
+    real matrix over p^2 pivots, then complex Gauss-Jordan of R + i eta I."""
+    p = N - 1
+    nloc = p * p + 4 * p
+    ncol = nloc + 2
+    f = 0
+    for k in range(p * p):
+        r, c = nloc - k - 1, ncol - k - 1
+        f += r + 2 * r * c            # scale column + rank-1 update
+    m = 4 * p
+    f += 8 * m ** 3                   # complex Gauss-Jordan inverse (m^3 complex MACs)
+    return f
+
+
+def merge_flops_executed(n, N, L):
+    """Complex-counted (8 flops / MAC) flops of all merges 1..L-1."""
+    p = N - 1
+    tot = 0
+    per_level = []
+    for level in range(1, L):
+        wx, wy = 2 ** (level // 2), 2 ** ((level - 1) // 2)
+        b = 2 * (wx + wy) * p
+        m = (wy if level % 2 else wx) * p
+        e = b - m
+        pairs = (n // wx) * (n // wy) // 2
+        macs = m ** 3 + m ** 3 + m * m * e + 2 * m * m * e + 2 * m * m * e + 4 * m * e * e
+        per_level.append(8 * macs * pairs)
+        tot += 8 * macs * pairs
+    return tot, per_level
+
+
+def cpu_baseline(pr, sample_seconds):
+    """The oracle (CPU, FP64) timed on a bounded sample of the same workload and
+    scaled to the whole job: leaf maps of a sample of elements, and the merges
+    of a sample of pairs per level; the solve phase is bounded below by zero and
+    not included (the build dominates the oracle's time)."""
+    from oracle import gll, leaf, merge, mesh
+    n, N = pr.n, pr.N
+    p = N - 1
+    xi = gll.gll_nodes(N)
+    c = leaf.nodal_coefficient(N, n, pr.kappa, pr.b, xi)
+    E = n * n
+    t0 = time.perf_counter()
+    ns = 0
+    T_s = []
+    while time.perf_counter() - t0 < 0.4 * sample_seconds and ns < E:
+        k = min(64, E - ns)
+        T, _ = leaf.leaves(N, 1.0 / n, pr.kappa, pr.eta, c[ns:ns + k])
+        T_s.append(T)
+        ns += k
+    t_leaf = (time.perf_counter() - t0) * E / ns
+    T = np.concatenate(T_s)
+    # merges: time one pair per level, using sample maps of the right size
+    t_merge = 0.0
+    Tcur = [T[0], T[1 % len(T)]]
+    budget = 0.6 * sample_seconds
+    tm0 = time.perf_counter()
+    sampled_levels = 0
+    L = mesh.lmax(n) if not pr.levels else pr.levels
+    for level in range(1, L):
+        if time.perf_counter() - tm0 > budget:
+            break
+        t1 = time.perf_counter()
+        Tm, _, _ = merge.merge_pair(level, p, Tcur[0], Tcur[1])
+        dt = time.perf_counter() - t1
+        wx, wy = mesh.box_dims(level)
+        pairs = (n // wx) * (n // wy) // 2
+        t_merge += dt * pairs
+        Tcur = [Tm, Tm]
+        sampled_levels += 1
+    total = t_leaf + t_merge
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {
+        "value": pr.skeleton_dof / total if sampled_levels == L - 1 else None,
+        "unit": UNIT,
+        "cores": threads,
+        "kind": "oracle",
+        "sample": (f"oracle leaf maps of {ns}/{E} elements and one pair merge per level "
+                   f"({sampled_levels}/{L - 1} levels), scaled by element and pair counts; "
+                   f"build only (solve excluded), est. job {total:.1f} s"),
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no "
+              "multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2511_00735_amd import hps, workloads
+
+    pr = workloads.c3()
+    pr.n, pr.N, pr.kappa, pr.eta = args.n, args.order, args.kappa, args.kappa
+    pr.levels, pr.coarse_iters, pr.tol = args.levels, args.coarse_iters, args.tol
+    pr.wave = workloads.PlaneWave(pr.kappa, pr.eta)
+    ctx = hps.Context()
+    stream = ctx.stream
+    desc = hps.make_desc(pr.n, pr.N, pr.kappa, pr.eta, levels=pr.levels, coarse_iters=pr.coarse_iters)
+    prob = hps.Problem(ctx, desc)
+    b_nodes = prob.coefficient_nodes(pr.b)
+    t_data = prob.boundary_data(pr.wave.t)
+    rhs = torch.empty(prob.nslots, dtype=torch.complex128, device="cuda")
+    g = torch.empty_like(rhs)
+
+    def step():
+        prob.build_leaves(b_nodes)
+        prob.merge_all()
+        hps.set_rhs([prob], [t_data], [rhs])
+        return prob.gmres_solve(rhs, tol=pr.tol, maxit=600, out=g)[1]
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = [step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms = 1e3 * dt / args.steps
+    dof = pr.skeleton_dof
+    value = dof * args.steps / dt
+
+    # phase timing with events on the library's stream (outside the timed loop)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev[0].record(stream)
+    prob.build_leaves(b_nodes)
+    ev[1].record(stream)
+    prob.merge_all()
+    ev[2].record(stream)
+    hps.set_rhs([prob], [t_data], [rhs])
+    info = prob.gmres_solve(rhs, tol=pr.tol, maxit=600, out=g)[1]
+    ev[3].record(stream)
+    torch.cuda.synchronize()
+    t_leaf = ev[0].elapsed_time(ev[1])
+    t_merge = ev[1].elapsed_time(ev[2])
+    t_solve = ev[2].elapsed_time(ev[3])
+    leaf_f = leaf_flops_executed(pr.N) * pr.n * pr.n
+    merge_f, _ = merge_flops_executed(pr.n, pr.N, pr.levels)
+    leaf_tf = leaf_f / (t_leaf * 1e-3) / 1e12
+    merge_tf = merge_f / (t_merge * 1e-3) / 1e12
+    dominant = "merge" if t_merge >= t_leaf else "leaf"
+    ach = merge_tf if dominant == "merge" else leaf_tf
+    roof = {"bound": "mfma", "achieved": round(ach, 3), "peak": MI355X_FP64_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(ach / MI355X_FP64_TFLOPS, 4), "traffic": None,
+            "kernel": f"{dominant} phase (all launches of hps_{'merge_level' if dominant == 'merge' else 'build_leaves'})"}
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": UNIT, "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c128",
+        "data": "synthetic",
+        "config": {"workload": (f"{pr.n}x{pr.n} elements, N={pr.N}, kappa=eta={pr.kappa:g}, "
+                                f"8 seeded bumps (seed 3), plane-wave t, L={pr.levels}, "
+                                f"{pr.coarse_iters} coarse GMRES its, FGMRES(60) to {pr.tol:g}"),
+                   "precision": "fp64", "skeleton_dof": dof,
+                   "iterations": infos[-1]["iterations"], "relres_true": infos[-1]["relres_true"],
+                   "phase_ms": {"leaves": round(t_leaf, 3), "merges": round(t_merge, 3),
+                                "rhs+solve": round(t_solve, 3)},
+                   "phase_tflops": {"leaves": round(leaf_tf, 3), "merges": round(merge_tf, 3)}},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(pr, args.cpu_sample_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,173 @@
+/* hps.h -- C ABI of the MI355X HPS-as-multigrid Helmholtz solver.
+ *
+ * Problem (Sec. 2 of Lucero Lorca, "Towards a Multigrid Preconditioner
+ * Interpretation of Hierarchical Poincare-Steklov Solvers"):
+ *     -Lap u - kappa^2 (1 - b(x)) u = s   in (0,1)^2,
+ *     d_n u + i eta u = t                 on the boundary.
+ * Discretisation (Sec. 3): n x n square elements, tensor GLL grid of order N per
+ * element, corner nodes removed; leaf impedance-to-impedance maps T and loads H
+ * (eq. ItIOperator); skeleton system M g = RHS on the interior incoming
+ * impedances (Sec. 3.2).  Solver (Sec. 4): nested-dissection merge tree whose
+ * level-l Schur complements M_{l+1} = D_l - C_l A_l^-1 B_l are the merged box
+ * maps; applied as the multigrid preconditioner MG(M) = F + P S^-1 R (I - M F)
+ * inside flexible GMRES, with the top coarse solve either exact or a fixed
+ * number of unpreconditioned GMRES iterations (Sec. 4.3).
+ *
+ * Conventions shared by every entry point:
+ *  - Complex numbers are interleaved (re, im) doubles.
+ *  - Elements e = ix + n*iy; element nodes (i, j) (i along x), flat index
+ *    i*(N+1) + j, x_i = ix*h + (1 + xi_i) h/2 with GLL nodes xi on [-1, 1].
+ *  - Canonical skeleton layout ("canonical vector"): slot (e, side, k) at flat
+ *    index (e*4 + side)*(N-1) + k, sides l=0, r=1, b=2, t=3, k = 0..N-2 by
+ *    increasing coordinate; length E*4*(N-1) complex.  A slot holds the
+ *    incoming impedance (d_n + i eta) u of element e on that side.  Slots on
+ *    the physical boundary are not unknowns: they are ignored on input and
+ *    written as 0 on output.  Row s of M lives at the slot of the unknown it
+ *    determines: (M g)[s] = g[s] - (T g)[Pi(s)], Pi(s) the slot across the
+ *    face, so M = I - Pi T_blk (the rows of eq. faceequations).
+ *  - Merge level l = 1 .. L_max = log2(n^2); level-l boxes are
+ *    2^floor(l/2) x 2^floor((l-1)/2) elements; merge l pairs boxes along x for
+ *    odd l and along y for even l (Fig. 1).
+ *
+ * Memory: the caller owns all device memory.  Each problem lives in ONE
+ * caller-provided device workspace of hps_workspace_bytes() bytes; the library
+ * allocates no device memory at all.  Array arguments are DEVICE pointers
+ * unless marked [host].  All calls are asynchronous on the context's stream
+ * unless marked "synchronises"; inputs may be freed once that stream has passed
+ * the call.  A context is bound to one stream and is not thread-safe.
+ *
+ * Errors: every call returns hps_status; no exception crosses the ABI.  After a
+ * failure hps_last_error(ctx) describes it.  Argument checks happen on the
+ * host; zero pivots found on the device are reported as HPS_ERR_SINGULAR at the
+ * next synchronising call (hps_gmres_solve, hps_sync).
+ */
+#ifndef HPS_H
+#define HPS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hps_ctx hps_ctx;
+typedef struct hps_problem hps_problem;
+
+typedef enum {
+  HPS_OK = 0,
+  HPS_NOT_CONVERGED = 1,  /* warning: maxit reached, best iterate returned      */
+  HPS_ERR_ARG = -1,       /* invalid argument (sizes, NaN/Inf, null pointers)   */
+  HPS_ERR_OOM = -2,       /* workspace smaller than hps_workspace_bytes()       */
+  HPS_ERR_SINGULAR = -3,  /* exact zero pivot in a leaf or merge factorisation  */
+  HPS_ERR_STATE = -4,     /* call out of order (e.g. merge before build)        */
+  HPS_ERR_HIP = -5        /* HIP runtime error                                  */
+} hps_status;
+
+typedef enum { HPS_FP64 = 0, HPS_MIXED = 1 } hps_precision;
+
+/* Problem descriptor.  Defaults in brackets. */
+typedef struct {
+  int32_t n;             /* elements per side, power of two, 2 <= n <= 1024   */
+  int32_t order;         /* GLL order N, 2 <= N <= 24                          */
+  double kappa;          /* wavenumber kappa > 0 (c = kappa^2 (1 - b))         */
+  double eta;            /* impedance parameter eta > 0 (the paper: eta=kappa) */
+  int32_t precision;     /* hps_precision [HPS_FP64]                           */
+  int32_t levels;        /* coarse level L, 1 <= L <= L_max; 0 => L_max         */
+  int32_t coarse_iters;  /* k >= 1 GMRES steps on M_L; -1 => exact coarse solve
+                            (requires L = L_max: direct HPS)                   */
+  int32_t gamma;         /* coarse calls per level, 1 = V-cycle [1]            */
+  int32_t restart;       /* FGMRES restart length, 1..200 [60]                 */
+} hps_desc;
+
+/* Per-problem result of hps_gmres_solve ([host]). */
+typedef struct {
+  int32_t status;        /* HPS_OK or HPS_NOT_CONVERGED                        */
+  int32_t iterations;    /* flexible GMRES iterations, counted across restarts */
+  double relres_est;     /* Givens estimate of ||RHS - M g|| / ||RHS||          */
+  double relres_true;    /* recomputed ||RHS - M g||_2 / ||RHS||_2 at exit      */
+} hps_info;
+
+/* View of one level's stored operators (for inspection and testing). */
+typedef struct {
+  int32_t level;         /* l                                                  */
+  int32_t boxes;         /* number of level-l boxes                            */
+  int32_t box_nodes;     /* b = box perimeter in nodes (box map is b x b)      */
+  int32_t morton;        /* 1: boxes stored in merge-tree (Morton) order: box
+                            index j covers elements whose Morton code (x bits
+                            even, y bits odd) shifted right by l-1 equals j     */
+  const void* T;         /* complex [boxes][b][b], column-major, box-local
+                            boundary order [l; r; b; t]; FP64                  */
+  int32_t pairs;         /* pairs merged at this level (0 at the top)          */
+  int32_t shared_nodes;  /* m = length of the shared face                      */
+  const void* Winv;      /* complex [pairs][m][m] column-major: the inverse of
+                            W = I - T^P_aa T^Q_bb (the m x m Schur complement
+                            of A = [[I, -T^P_aa], [-T^Q_bb, I]]); FP64        */
+} hps_level_view;
+
+/* ---- context ------------------------------------------------------------ */
+/* Bind a context to a HIP stream (hipStream_t; NULL = legacy default stream). */
+hps_status hps_ctx_create(void* hip_stream, hps_ctx** out);
+hps_status hps_ctx_destroy(hps_ctx* ctx);
+/* Last error message of this context ("" if none); valid until the next call. */
+const char* hps_last_error(const hps_ctx* ctx);
+/* Wait for the context's stream and report deferred device errors. */
+hps_status hps_sync(hps_ctx* ctx);
+
+/* ---- sizing and host-side geometry -------------------------------------- */
+/* Exact device workspace (bytes) of one problem; the admission footprint. */
+hps_status hps_workspace_bytes(const hps_desc* desc, size_t* bytes);
+/* [host] GLL nodes on [-1, 1] of order N: xi[N+1], increasing. */
+hps_status hps_gll_nodes(int32_t order, double* xi);
+/* [host] physical coordinates of all element nodes, x[E][(N+1)^2], y[...]. */
+hps_status hps_node_coords(const hps_desc* desc, double* x, double* y);
+/* [host] coordinates and outward unit normals of every canonical slot,
+   each array [E*4*(N-1)]. */
+hps_status hps_slot_coords(const hps_desc* desc, double* x, double* y,
+                           double* nx, double* ny);
+
+/* ---- problems ----------------------------------------------------------- */
+/* Carve a problem out of `workspace` (device, >= hps_workspace_bytes, 256-byte
+   aligned).  Copies small index tables into the workspace; synchronises. */
+hps_status hps_problem_create(hps_ctx* ctx, const hps_desc* desc, void* workspace,
+                              size_t bytes, hps_problem** out);
+/* Frees host metadata only; the caller frees the workspace. */
+hps_status hps_problem_destroy(hps_problem* p);
+hps_status hps_level_view_get(const hps_problem* p, int32_t level, hps_level_view* out);
+
+/* ---- the hot path (batch-first: `count` problems per call) --------------- */
+/* Leaf ItI maps T and loads H of every element (Sec. 3.1, eq. ItIOperator).
+   b_nodes[i]: real [E][(N+1)^2], the coefficient b at the element nodes.
+   s_nodes[i]: complex [E][(N+1)^2] source s at the nodes, or NULL (H = 0). */
+hps_status hps_build_leaves(hps_problem* const* p, int32_t count,
+                            const double* const* b_nodes, const double* const* s_nodes);
+/* Merge level `level` (Sec. 4.1-4.2): for 1 <= level < L, merge the level-l
+   box pairs into level-(l+1) box maps, keeping W^-1 for the preconditioner.
+   level == L (exact coarse mode only, L = L_max): factor the coarse system. */
+hps_status hps_merge_level(hps_problem* const* p, int32_t count, int32_t level);
+/* Skeleton right-hand side (Sec. 3.2): RHS[s] = (H + T_{.,phys} t)[Pi(s)].
+   t[i]: complex canonical vector of incoming data; only physical slots read.
+   rhs[i]: complex canonical vector (output). */
+hps_status hps_set_rhs(hps_problem* const* p, int32_t count,
+                       const double* const* t, double* const* rhs);
+/* out = M_level g (canonical vectors; only level-`level` unknowns are read and
+   written).  Requires the level-`level` box maps. */
+hps_status hps_skeleton_apply(hps_problem* const* p, int32_t count, int32_t level,
+                              const double* const* g, double* const* out);
+/* z = MG(M_1) r, one V-cycle (gamma = 1) with the configured coarse solve
+   (Sec. 4.3).  r and z: complex canonical vectors; r is not modified. */
+hps_status hps_precond_apply(hps_problem* const* p, int32_t count,
+                             const double* const* r, double* const* z);
+/* Flexible GMRES(restart) on M_1 g = rhs, right-preconditioned by MG, x0 = 0,
+   until ||rhs - M_1 g|| <= tol ||rhs|| or maxit iterations (Sec. 4.3, Sec. 5).
+   g: complex canonical output.  info[count] ([host]) receives per-problem
+   results.  Synchronises.  Returns HPS_NOT_CONVERGED if any problem did not
+   converge. */
+hps_status hps_gmres_solve(hps_problem* const* p, int32_t count,
+                           const double* const* rhs, double* const* g,
+                           double tol, int32_t maxit, hps_info* info);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HPS_H */

@@ -1,0 +1,916 @@
+// Host side of the HPS library: workspace layout, the level scheduler (leaf
+// build, merges), the multigrid V-cycle, the coarse GMRES and the outer
+// flexible GMRES, exported through the C ABI of include/hps.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "hps.h"
+#include "host.h"
+#include "solve.h"
+
+struct hps_ctx {
+  hipStream_t stream;
+  std::string err;
+};
+
+namespace hps {
+
+namespace {
+
+inline size_t up256(size_t b) { return (b + 255) & ~size_t(255); }
+
+struct Level {
+  Geom g;
+  size_t T_off = 0;
+  // merge of this level's box pairs (level < L, or the top pair in exact mode)
+  int pairs = 0, m = 0, e = 0, axis = 0, a0 = 0, b0 = 0;
+  IdxMap E1{}, E2{};
+  bool has_merge = false;
+  size_t Winv_off = 0;
+  size_t map_off = 0;  // int32 [2e]: merged-box position of y = [P.E1; Q.E2]
+  size_t R1_off = 0, R2_off = 0;  // V-cycle residual pieces kept between sweeps
+};
+
+struct Layout {
+  int n, N, p, E, L, Lmax, k, restart;
+  bool exact;
+  long long nslots;
+  int nL;  // number of coarse unknowns
+  int leaf_chunk;
+  size_t tables_off, H_off;
+  std::vector<Level> lev;  // 1..L
+  size_t scratch_off, scratch_bytes;
+  size_t V_off, Z_off, work_off;  // Krylov bases and 5 canonical work vectors
+  size_t vtmp_off;                // V-cycle transients: V1, X1, X2 [pairs][m], DP, DQ [pairs][e]
+  size_t vtmp_m, vtmp_e;          // max pairs*m and pairs*e over levels
+  size_t cV_off, cw_off, cx_off, cidx_off, cH_off, cy_off, cs_off;  // coarse GMRES
+  size_t part_off, hh_off, one_off, flag_off;
+  size_t total;
+};
+
+int ilog2(int v) {
+  int q = 0;
+  while ((1 << q) < v) ++q;
+  return q;
+}
+
+Level make_level(int n, int p, int l) {
+  Level lv;
+  lv.g = make_geom(n, p, l);
+  return lv;
+}
+
+// Merge geometry of level l: shared side alpha of P, beta of Q, exterior maps.
+void set_merge_geom(Level& lv) {
+  const Geom& g = lv.g;
+  lv.has_merge = true;
+  lv.pairs = g.nboxes / 2;
+  lv.axis = (g.level % 2 == 1) ? 0 : 1;
+  if (lv.axis == 0) {  // x-merge: alpha = r of P, beta = l of Q
+    lv.m = g.off[2] - g.off[1];
+    lv.a0 = g.off[1];
+    lv.b0 = g.off[0];
+    lv.E1 = im_gap(0, g.off[1], lv.m);
+    lv.E2 = im_off(g.off[1]);
+  } else {             // y-merge: alpha = t of P, beta = b of Q
+    lv.m = g.off[4] - g.off[3];
+    lv.a0 = g.off[3];
+    lv.b0 = g.off[2];
+    lv.E1 = im_off(0);
+    lv.E2 = im_gap(0, g.off[2], lv.m);
+  }
+  lv.e = g.b - lv.m;
+}
+
+// Merged-box position of every y index (y = [P.E1; Q.E2], each in the child's
+// [l; r; b; t] order without the shared side).
+std::vector<int> merge_map(const Level& lv) {
+  const Geom& g = lv.g;
+  const int p = g.p, wx = g.wx, wy = g.wy;
+  std::vector<int> out;
+  out.reserve(2 * lv.e);
+  auto seg = [&](int start, int len) { for (int k = 0; k < len; ++k) out.push_back(start + k); };
+  if (lv.axis == 0) {
+    // merged box 2wx x wy: l [0, wy p), r [wy p, 2wy p), b [2wy p, 2wy p + 2wx p), t after
+    const int ml = 0, mr = wy * p, mb = 2 * wy * p, mt = 2 * wy * p + 2 * wx * p;
+    seg(ml, wy * p);            // P.l
+    seg(mb, wx * p);            // P.b
+    seg(mt, wx * p);            // P.t
+    seg(mr, wy * p);            // Q.r
+    seg(mb + wx * p, wx * p);   // Q.b
+    seg(mt + wx * p, wx * p);   // Q.t
+  } else {
+    // merged box wx x 2wy: l [0, 2wy p), r [2wy p, 4wy p), b [4wy p, 4wy p + wx p), t after
+    const int ml = 0, mr = 2 * wy * p, mb = 4 * wy * p, mt = 4 * wy * p + wx * p;
+    seg(ml, wy * p);            // P.l
+    seg(mr, wy * p);            // P.r
+    seg(mb, wx * p);            // P.b
+    seg(ml + wy * p, wy * p);   // Q.l
+    seg(mr + wy * p, wy * p);   // Q.r
+    seg(mt, wx * p);            // Q.t
+  }
+  return out;
+}
+
+// Canonical slots of the level-L unknowns, box by box in storage order.
+std::vector<int> coarse_slots(const Level& lv) {
+  const Geom& g = lv.g;
+  std::vector<int> out;
+  for (int j = 0; j < g.nboxes; ++j) {
+    int bx, by;
+    box_xy(g, j, bx, by);
+    for (int k = 0; k < g.b; ++k)
+      if (!side_physical(g, bx, by, side_of(g, k))) out.push_back(box_slot(g, bx, by, k));
+  }
+  return out;
+}
+
+const char* check_desc(const hps_desc* d) {
+  if (!d) return "null descriptor";
+  if (d->n < 2 || d->n > 1024 || (d->n & (d->n - 1))) return "n must be a power of two in [2, 1024]";
+  if (d->order < 2 || d->order > 16) return "order N must be in [2, 16]";
+  if (!(std::isfinite(d->kappa) && d->kappa > 0)) return "kappa must be finite and > 0";
+  if (!(std::isfinite(d->eta) && d->eta > 0)) return "eta must be finite and > 0";
+  const int Lmax = 2 * ilog2(d->n);
+  if (d->levels < 0 || d->levels > Lmax) return "levels out of range";
+  if (d->coarse_iters == 0 || d->coarse_iters < -1 || d->coarse_iters > kMaxCoarse)
+    return "coarse_iters must be -1 (exact) or 1..32";
+  const int L = d->levels ? d->levels : Lmax;
+  if (d->coarse_iters == -1 && L != Lmax) return "exact coarse solve requires levels = L_max";
+  if (d->gamma != 1 && d->gamma != 0) return "only gamma = 1 (V-cycle) is supported";
+  if (d->restart < 0 || d->restart > 200) return "restart must be in [1, 200]";
+  if (d->precision != HPS_FP64) return "only HPS_FP64 is supported";
+  return nullptr;
+}
+
+Layout make_layout(const hps_desc* d) {
+  Layout lay;
+  lay.n = d->n;
+  lay.N = d->order;
+  lay.p = d->order - 1;
+  lay.E = d->n * d->n;
+  lay.Lmax = 2 * ilog2(d->n);
+  lay.L = d->levels ? d->levels : lay.Lmax;
+  lay.exact = (d->coarse_iters == -1);
+  lay.k = lay.exact ? 0 : d->coarse_iters;
+  lay.restart = d->restart ? d->restart : 60;
+  lay.nslots = (long long)lay.E * 4 * lay.p;
+  lay.leaf_chunk = std::min(lay.E, 1024);
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off += up256(bytes); return o; };
+  const int N1 = lay.N + 1;
+  lay.tables_off = take(sizeof(double) * (2 * N1 * N1 + N1));
+  lay.H_off = take(sizeof(cd) * (size_t)lay.E * 4 * lay.p);
+  lay.lev.resize(lay.L + 1);
+  size_t merge_scratch = 0;
+  lay.vtmp_m = lay.vtmp_e = 1;
+  for (int l = 1; l <= lay.L; ++l) {
+    Level& lv = lay.lev[l];
+    lv = make_level(lay.n, lay.p, l);
+    lv.T_off = take(sizeof(cd) * (size_t)lv.g.nboxes * lv.g.b * lv.g.b);
+    if (l < lay.L || (lay.exact && l == lay.L)) {
+      set_merge_geom(lv);
+      lv.Winv_off = take(sizeof(cd) * (size_t)lv.pairs * lv.m * lv.m);
+      lv.map_off = take(sizeof(int) * 2 * (size_t)lv.e);
+      lv.R1_off = take(sizeof(cd) * (size_t)lv.pairs * lv.m);
+      lv.R2_off = take(sizeof(cd) * (size_t)lv.pairs * lv.m);
+      const size_t zbytes = sizeof(cd) * (size_t)lv.pairs * lv.m * 2 * lv.e;
+      merge_scratch = std::max(merge_scratch, 3 * up256(zbytes) + up256(inverse_scratch_bytes(lv.m, lv.pairs)));
+      lay.vtmp_m = std::max(lay.vtmp_m, (size_t)lv.pairs * lv.m);
+      lay.vtmp_e = std::max(lay.vtmp_e, (size_t)lv.pairs * lv.e);
+    }
+  }
+  lay.scratch_bytes = std::max(merge_scratch, sizeof(double) * leaf_scratch_doubles(lay.N, lay.leaf_chunk));
+  lay.scratch_off = take(lay.scratch_bytes);
+  const size_t vb = sizeof(cd) * (size_t)lay.nslots;
+  lay.V_off = take(vb * (lay.restart + 1));
+  lay.Z_off = take(vb * lay.restart);
+  lay.work_off = take(up256(vb) * 5);
+  lay.vtmp_off = take(sizeof(cd) * (3 * lay.vtmp_m + 2 * lay.vtmp_e) + 5 * 256);
+  {
+    Level& top = lay.lev[lay.L];
+    int nL = 0;
+    for (int j = 0; j < top.g.nboxes; ++j) {
+      int bx, by;
+      box_xy(top.g, j, bx, by);
+      for (int s = 0; s < 4; ++s)
+        if (!side_physical(top.g, bx, by, s)) nL += top.g.off[s + 1] - top.g.off[s];
+    }
+    lay.nL = nL;
+  }
+  const int kk = std::max(lay.k, 1);
+  lay.cV_off = take(sizeof(cd) * (size_t)(kk + 1) * std::max(lay.nL, 1));
+  lay.cw_off = take(sizeof(cd) * (size_t)std::max(lay.nL, 1));
+  lay.cx_off = take(sizeof(cd) * (size_t)std::max(lay.nL, 1));
+  lay.cidx_off = take(sizeof(int) * (size_t)std::max(lay.nL, 1));
+  lay.cH_off = take(sizeof(cd) * (size_t)(kk + 1) * kk);
+  lay.cy_off = take(sizeof(cd) * (size_t)(kk + 1));
+  lay.cs_off = take(sizeof(cd) * 8);
+  lay.part_off = take(sizeof(cd) * (size_t)(lay.restart + 2) * kMaxDotBlocks);
+  lay.hh_off = take(sizeof(cd) * (size_t)(2 * (lay.restart + 2) + 4));
+  lay.one_off = take(sizeof(cd));
+  lay.flag_off = take(sizeof(int) * 4);
+  lay.total = off;
+  return lay;
+}
+
+enum State { kCreated = 0, kLeaves = 1 };
+
+}  // namespace
+}  // namespace hps
+
+struct hps_problem {
+  hps_ctx* ctx;
+  hps_desc desc;
+  hps::Layout lay;
+  char* ws;
+  int state;
+  int merged;     // highest merge level done
+  bool have_T1;
+};
+
+using namespace hps;
+
+namespace {
+
+template <class T>
+T* at(hps_problem* p, size_t off) { return reinterpret_cast<T*>(p->ws + off); }
+
+hps_status fail(hps_ctx* c, hps_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+#define HIPCHK(ctx, expr)                                                                \
+  do {                                                                                   \
+    hipError_t _e = (expr);                                                              \
+    if (_e != hipSuccess)                                                                \
+      return fail((ctx), HPS_ERR_HIP, std::string("HIP error: ") + hipGetErrorString(_e) + \
+                                          " at " #expr);                                 \
+  } while (0)
+
+cd* Tlev(hps_problem* p, int l) { return at<cd>(p, p->lay.lev[l].T_off); }
+
+// ---- merge of one level (1 <= l < L): level-l pairs -> level-(l+1) boxes --
+hps_status merge_one(hps_problem* p, int l) {
+  hps_ctx* c = p->ctx;
+  hipStream_t st = c->stream;
+  const Layout& lay = p->lay;
+  const Level& lv = lay.lev[l];
+  const int b = lv.g.b, m = lv.m, e = lv.e, np = lv.pairs;
+  const long long pstride = 2LL * b * b;
+  cd* T = Tlev(p, l);
+  const cd* TP = T;
+  const cd* TQ = T + (size_t)b * b;
+  cd* Winv = at<cd>(p, lv.Winv_off);
+  const cd one = cmk(1, 0), zero = cmk(0, 0), mone = cmk(-1, 0);
+  const Operand none{nullptr, 0, 0, im_off(0), im_off(0)};
+  int* flag = at<int>(p, lay.flag_off);
+  // W = I - T^P_aa T^Q_bb
+  {
+    GemmArgs g{};
+    g.M = m; g.N = m; g.K = m; g.batch = np;
+    g.A = Operand{TP, pstride, b, im_off(lv.a0), im_off(lv.a0)};
+    g.B = Operand{TQ, pstride, b, im_off(lv.b0), im_off(lv.b0)};
+    g.alpha = mone; g.beta = zero; g.C = none;
+    g.D = Winv; g.Dstride = (long long)m * m; g.ldd = m; g.dr = im_off(0); g.dc = im_off(0);
+    g.diag_add = one; g.has_diag = 1;
+    HIPCHK(c, zgemm(g, st));
+  }
+  char* scr = at<char>(p, lay.scratch_off);
+  const size_t zb = up256(sizeof(cd) * (size_t)np * m * 2 * e);
+  cd* Z = reinterpret_cast<cd*>(scr);
+  cd* YQ = reinterpret_cast<cd*>(scr + zb);
+  cd* YP = reinterpret_cast<cd*>(scr + 2 * zb);
+  void* invs = scr + 3 * zb;
+  HIPCHK(c, zinverse(Winv, m, m, (long long)m * m, np, invs, flag, st));
+  if (l == lay.L) return HPS_OK;  // exact top: only W^-1 is needed
+  const long long zs = (long long)m * 2 * e;
+  // Z = [T^P_{a,E1} | T^P_aa T^Q_{b,E2}]
+  HIPCHK(c, zcopy2d(m, e, np, Operand{TP, pstride, b, im_off(lv.a0), lv.E1}, one, Z, zs, m, im_off(0),
+                    im_off(0), st));
+  {
+    GemmArgs g{};
+    g.M = m; g.N = e; g.K = m; g.batch = np;
+    g.A = Operand{TP, pstride, b, im_off(lv.a0), im_off(lv.a0)};
+    g.B = Operand{TQ, pstride, b, im_off(lv.b0), lv.E2};
+    g.alpha = one; g.beta = zero; g.C = none;
+    g.D = Z; g.Dstride = zs; g.ldd = m; g.dr = im_off(0); g.dc = im_off(e);
+    HIPCHK(c, zgemm(g, st));
+  }
+  // YQ = W^-1 Z   (the shared-face data f^Q_b as a function of y)
+  {
+    GemmArgs g{};
+    g.M = m; g.N = 2 * e; g.K = m; g.batch = np;
+    g.A = Operand{Winv, (long long)m * m, m, im_off(0), im_off(0)};
+    g.B = Operand{Z, zs, m, im_off(0), im_off(0)};
+    g.alpha = one; g.beta = zero; g.C = none;
+    g.D = YQ; g.Dstride = zs; g.ldd = m; g.dr = im_off(0); g.dc = im_off(0);
+    HIPCHK(c, zgemm(g, st));
+  }
+  // YP = T^Q_bb YQ + [0 | T^Q_{b,E2}]   (f^P_a as a function of y)
+  HIPCHK(c, zcopy2d(m, e, np, none, one, YP, zs, m, im_off(0), im_off(0), st));
+  HIPCHK(c, zcopy2d(m, e, np, Operand{TQ, pstride, b, im_off(lv.b0), lv.E2}, one, YP, zs, m, im_off(0),
+                    im_off(e), st));
+  {
+    GemmArgs g{};
+    g.M = m; g.N = 2 * e; g.K = m; g.batch = np;
+    g.A = Operand{TQ, pstride, b, im_off(lv.b0), im_off(lv.b0)};
+    g.B = Operand{YQ, zs, m, im_off(0), im_off(0)};
+    g.alpha = one; g.beta = one; g.C = Operand{YP, zs, m, im_off(0), im_off(0)};
+    g.D = YP; g.Dstride = zs; g.ldd = m; g.dr = im_off(0); g.dc = im_off(0);
+    HIPCHK(c, zgemm(g, st));
+  }
+  // T_new = blkdiag(T^P_E1E1, T^Q_E2E2) + [T^P_{E1,a} YP ; T^Q_{E2,b} YQ], scattered
+  const Level& nx = lay.lev[l + 1];
+  cd* Tn = Tlev(p, l + 1);
+  const int bn = nx.g.b;
+  const long long ns = (long long)bn * bn;
+  const int* mp = at<int>(p, lv.map_off);
+  const IdxMap rowP = im_tab(mp), rowQ = im_tab(mp + e), colP = im_tab(mp), colQ = im_tab(mp + e);
+  HIPCHK(c, zcopy2d(e, e, np, Operand{TP, pstride, b, lv.E1, lv.E1}, one, Tn, ns, bn, rowP, colP, st));
+  HIPCHK(c, zcopy2d(e, e, np, none, one, Tn, ns, bn, rowP, colQ, st));
+  HIPCHK(c, zcopy2d(e, e, np, none, one, Tn, ns, bn, rowQ, colP, st));
+  HIPCHK(c, zcopy2d(e, e, np, Operand{TQ, pstride, b, lv.E2, lv.E2}, one, Tn, ns, bn, rowQ, colQ, st));
+  {
+    GemmArgs g{};
+    g.M = e; g.N = 2 * e; g.K = m; g.batch = np;
+    g.A = Operand{TP, pstride, b, lv.E1, im_off(lv.a0)};
+    g.B = Operand{YP, zs, m, im_off(0), im_off(0)};
+    g.alpha = one; g.beta = one; g.C = Operand{Tn, ns, bn, rowP, im_tab(mp)};
+    g.D = Tn; g.Dstride = ns; g.ldd = bn; g.dr = rowP; g.dc = im_tab(mp);
+    HIPCHK(c, zgemm(g, st));
+    g.A = Operand{TQ, pstride, b, lv.E2, im_off(lv.b0)};
+    g.B = Operand{YQ, zs, m, im_off(0), im_off(0)};
+    g.C = Operand{Tn, ns, bn, rowQ, im_tab(mp)};
+    g.dr = rowQ;
+    HIPCHK(c, zgemm(g, st));
+  }
+  return HPS_OK;
+}
+
+// ---- V-cycle -------------------------------------------------------------
+struct VTmp {
+  cd *V1, *X1, *X2, *DP, *DQ;
+};
+VTmp vtmp(hps_problem* p) {
+  const Layout& lay = p->lay;
+  char* b = at<char>(p, lay.vtmp_off);
+  VTmp t;
+  t.V1 = reinterpret_cast<cd*>(b);
+  t.X1 = t.V1 + lay.vtmp_m;
+  t.X2 = t.X1 + lay.vtmp_m;
+  t.DP = t.X2 + lay.vtmp_m;
+  t.DQ = t.DP + lay.vtmp_e;
+  return t;
+}
+
+GemvArgs gemv_args(int M, int K, int batch, Operand A, const cd* x, long long xs, cd* y, long long ys,
+                   const cd* y0 = nullptr, long long y0s = 0) {
+  GemvArgs a{};
+  a.M = M; a.K = K; a.batch = batch; a.A = A;
+  a.x = x; a.xs = xs; a.alpha = cmk(1, 0);
+  a.y0 = y0; a.y0s = y0s; a.beta = cmk(1, 0);
+  a.y = y; a.ys = ys;
+  return a;
+}
+
+// x = A^-1 r for every pair: x1 = W^-1 (r1 + T^P_aa r2), x2 = r2 + T^Q_bb x1.
+hps_status pair_solve(hps_problem* p, const Level& lv, const cd* r1, const cd* r2, cd* V1, cd* x1,
+                      cd* x2) {
+  hps_ctx* c = p->ctx;
+  hipStream_t st = c->stream;
+  const int b = lv.g.b, m = lv.m, np = lv.pairs;
+  const long long ps = 2LL * b * b;
+  const cd* T = Tlev(p, lv.g.level);
+  HIPCHK(c, zgemv(gemv_args(m, m, np, Operand{T, ps, b, im_off(lv.a0), im_off(lv.a0)}, r2, m, V1, m, r1, m), st));
+  HIPCHK(c, zgemv(gemv_args(m, m, np, Operand{at<cd>(p, lv.Winv_off), (long long)m * m, m, im_off(0), im_off(0)},
+                            V1, m, x1, m), st));
+  HIPCHK(c, zgemv(gemv_args(m, m, np, Operand{T + (size_t)b * b, ps, b, im_off(lv.b0), im_off(lv.b0)}, x1, m, x2,
+                            m, r2, m), st));
+  return HPS_OK;
+}
+
+hps_status vcycle_down(hps_problem* p, int l, cd* wv) {
+  hps_ctx* c = p->ctx;
+  hipStream_t st = c->stream;
+  const Level& lv = p->lay.lev[l];
+  const int b = lv.g.b, m = lv.m, e = lv.e, np = lv.pairs;
+  const long long ps = 2LL * b * b;
+  const cd* T = Tlev(p, l);
+  cd* R1 = at<cd>(p, lv.R1_off);
+  cd* R2 = at<cd>(p, lv.R2_off);
+  VTmp t = vtmp(p);
+  HIPCHK(c, pair_gather(lv.g, np, 1, im_off(lv.b0), m, wv, R1, m, false, st));
+  HIPCHK(c, pair_gather(lv.g, np, 0, im_off(lv.a0), m, wv, R2, m, false, st));
+  hps_status s = pair_solve(p, lv, R1, R2, t.V1, t.X1, t.X2);
+  if (s != HPS_OK) return s;
+  HIPCHK(c, zgemv(gemv_args(e, m, np, Operand{T, ps, b, lv.E1, im_off(lv.a0)}, t.X2, m, t.DP, e), st));
+  HIPCHK(c, zgemv(gemv_args(e, m, np, Operand{T + (size_t)b * b, ps, b, lv.E2, im_off(lv.b0)}, t.X1, m, t.DQ, e), st));
+  HIPCHK(c, pair_scatter(lv.g, np, 0, lv.E1, e, t.DP, e, wv, true, true, st));
+  HIPCHK(c, pair_scatter(lv.g, np, 1, lv.E2, e, t.DQ, e, wv, true, true, st));
+  return HPS_OK;
+}
+
+hps_status vcycle_up(hps_problem* p, int l, cd* z) {
+  hps_ctx* c = p->ctx;
+  hipStream_t st = c->stream;
+  const Level& lv = p->lay.lev[l];
+  const int b = lv.g.b, m = lv.m, e = lv.e, np = lv.pairs;
+  const long long ps = 2LL * b * b;
+  const cd* T = Tlev(p, l);
+  const cd* R1 = at<cd>(p, lv.R1_off);
+  const cd* R2 = at<cd>(p, lv.R2_off);
+  VTmp t = vtmp(p);
+  HIPCHK(c, pair_gather(lv.g, np, 0, lv.E1, e, z, t.DP, e, false, st));
+  HIPCHK(c, pair_gather(lv.g, np, 1, lv.E2, e, z, t.DQ, e, false, st));
+  // r' = r_x + B y:  r1' = r1 + T^P_{a,E1} y_P,  r2' = r2 + T^Q_{b,E2} y_Q
+  cd* A1 = t.X1;
+  cd* A2 = t.X2;
+  HIPCHK(c, zgemv(gemv_args(m, e, np, Operand{T, ps, b, im_off(lv.a0), lv.E1}, t.DP, e, A1, m, R1, m), st));
+  HIPCHK(c, zgemv(gemv_args(m, e, np, Operand{T + (size_t)b * b, ps, b, im_off(lv.b0), lv.E2}, t.DQ, e, A2, m, R2, m),
+                  st));
+  // x = A^-1 r'
+  HIPCHK(c, zgemv(gemv_args(m, m, np, Operand{T, ps, b, im_off(lv.a0), im_off(lv.a0)}, A2, m, t.V1, m, A1, m), st));
+  HIPCHK(c, zgemv(gemv_args(m, m, np, Operand{at<cd>(p, lv.Winv_off), (long long)m * m, m, im_off(0), im_off(0)},
+                            t.V1, m, t.X1, m), st));
+  HIPCHK(c, zgemv(gemv_args(m, m, np, Operand{T + (size_t)b * b, ps, b, im_off(lv.b0), im_off(lv.b0)}, t.X1, m,
+                            t.X2, m, t.X2, m), st));
+  HIPCHK(c, pair_scatter(lv.g, np, 1, im_off(lv.b0), m, t.X1, m, z, false, false, st));
+  HIPCHK(c, pair_scatter(lv.g, np, 0, im_off(lv.a0), m, t.X2, m, z, false, false, st));
+  return HPS_OK;
+}
+
+cd* workv(hps_problem* p, int i) {
+  return reinterpret_cast<cd*>(p->ws + p->lay.work_off + i * up256(sizeof(cd) * (size_t)p->lay.nslots));
+}
+
+// Classical Gram-Schmidt, two passes, against V[0..nv); coefficients summed into
+// h[0..nv) (device), w updated in place.  h2: nv scratch entries.
+hps_status cgs2(hps_problem* p, const cd* V, long long vstride, int nv, cd* w, long long n, cd* h, cd* h2) {
+  hps_ctx* c = p->ctx;
+  hipStream_t st = c->stream;
+  cd* part = at<cd>(p, p->lay.part_off);
+  const cd* one = at<cd>(p, p->lay.one_off);
+  HIPCHK(c, multi_dot(V, vstride, nv, w, n, part, h, false, st));
+  HIPCHK(c, multi_axpy(V, vstride, nv, h, w, n, -1, st));
+  HIPCHK(c, multi_dot(V, vstride, nv, w, n, part, h2, false, st));
+  HIPCHK(c, multi_axpy(V, vstride, nv, h2, w, n, -1, st));
+  HIPCHK(c, multi_axpy(h2, 0, 1, one, h, nv, +1, st));
+  (void)one;
+  return HPS_OK;
+}
+
+// Coarse solve at level L on the level-L unknowns held in wv; result into z.
+hps_status coarse_solve(hps_problem* p, cd* wv, cd* z) {
+  hps_ctx* c = p->ctx;
+  hipStream_t st = c->stream;
+  const Layout& lay = p->lay;
+  const Level& top = lay.lev[lay.L];
+  if (lay.exact) {
+    const int m = top.m;
+    VTmp t = vtmp(p);
+    cd* R1 = at<cd>(p, top.R1_off);
+    cd* R2 = at<cd>(p, top.R2_off);
+    HIPCHK(c, pair_gather(top.g, 1, 1, im_off(top.b0), m, wv, R1, m, false, st));
+    HIPCHK(c, pair_gather(top.g, 1, 0, im_off(top.a0), m, wv, R2, m, false, st));
+    hps_status s = pair_solve(p, top, R1, R2, t.V1, t.X1, t.X2);
+    if (s != HPS_OK) return s;
+    HIPCHK(c, pair_scatter(top.g, 1, 1, im_off(top.b0), m, t.X1, m, z, false, false, st));
+    HIPCHK(c, pair_scatter(top.g, 1, 0, im_off(top.a0), m, t.X2, m, z, false, false, st));
+    return HPS_OK;
+  }
+  const int nL = lay.nL, k = lay.k;
+  if (nL == 0) return HPS_OK;
+  const int* idx = at<int>(p, lay.cidx_off);
+  cd* V = at<cd>(p, lay.cV_off);
+  cd* w = at<cd>(p, lay.cw_off);
+  cd* x = at<cd>(p, lay.cx_off);
+  cd* H = at<cd>(p, lay.cH_off);
+  cd* y = at<cd>(p, lay.cy_off);
+  cd* sc = at<cd>(p, lay.cs_off);  // [0]: beta^2, [1]: |w|^2, [2..]: scratch
+  cd* h2 = at<cd>(p, lay.hh_off);
+  cd* part = at<cd>(p, lay.part_off);
+  cd* u1 = workv(p, 2);
+  cd* u2 = workv(p, 3);
+  const cd* TL = Tlev(p, lay.L);
+  HIPCHK(c, index_gather(idx, nL, wv, w, st));
+  HIPCHK(c, multi_dot(w, 0, 1, w, nL, part, sc, false, st));
+  HIPCHK(c, normalize(w, sc, V, nL, nullptr, st));
+  HIPCHK(c, vfill(H, (long long)(k + 1) * k, cmk(0, 0), st));
+  for (int j = 0; j < k; ++j) {
+    HIPCHK(c, index_scatter(idx, nL, V + (size_t)j * nL, u1, st));
+    HIPCHK(c, skeleton_apply(top.g, TL, u1, u2, false, st));
+    HIPCHK(c, index_gather(idx, nL, u2, w, st));
+    hps_status s = cgs2(p, V, nL, j + 1, w, nL, H + (size_t)j * (k + 1), h2);
+    if (s != HPS_OK) return s;
+    HIPCHK(c, multi_dot(w, 0, 1, w, nL, part, sc + 1, false, st));
+    HIPCHK(c, normalize(w, sc + 1, V + (size_t)(j + 1) * nL, nL, H + (size_t)j * (k + 1) + j + 1, st));
+  }
+  HIPCHK(c, hessenberg_lsq(H, k + 1, k, sc, y, nullptr, st));
+  HIPCHK(c, vfill(x, nL, cmk(0, 0), st));
+  HIPCHK(c, multi_axpy(V, nL, k, y, x, nL, +1, st));
+  HIPCHK(c, index_scatter(idx, nL, x, z, st));
+  return HPS_OK;
+}
+
+hps_status precond_one(hps_problem* p, const cd* r, cd* z) {
+  hps_ctx* c = p->ctx;
+  hipStream_t st = c->stream;
+  const Layout& lay = p->lay;
+  cd* wv = workv(p, 0);
+  HIPCHK(c, vfill(z, lay.nslots, cmk(0, 0), st));
+  HIPCHK(c, vcopy(r, wv, lay.nslots, st));
+  for (int l = 1; l < lay.L; ++l) {
+    hps_status s = vcycle_down(p, l, wv);
+    if (s != HPS_OK) return s;
+  }
+  hps_status s = coarse_solve(p, wv, z);
+  if (s != HPS_OK) return s;
+  for (int l = lay.L - 1; l >= 1; --l) {
+    s = vcycle_up(p, l, z);
+    if (s != HPS_OK) return s;
+  }
+  return HPS_OK;
+}
+
+hps_status check_ready(hps_problem* p, bool need_merges) {
+  if (!p) return HPS_ERR_ARG;
+  if (p->state < kLeaves) return fail(p->ctx, HPS_ERR_STATE, "leaves not built");
+  if (need_merges) {
+    const int need = p->lay.exact ? p->lay.L : p->lay.L - 1;
+    if (p->merged < need) return fail(p->ctx, HPS_ERR_STATE, "merge levels missing");
+  }
+  return HPS_OK;
+}
+
+hps_status read_flag(hps_problem* p) {
+  int f = 0;
+  HIPCHK(p->ctx, hipMemcpyAsync(&f, at<int>(p, p->lay.flag_off), sizeof(int), hipMemcpyDeviceToHost,
+                                p->ctx->stream));
+  HIPCHK(p->ctx, hipStreamSynchronize(p->ctx->stream));
+  if (f & 2) return fail(p->ctx, HPS_ERR_SINGULAR, "zero pivot in a leaf or merge factorisation");
+  return HPS_OK;
+}
+
+// ---- outer flexible GMRES ------------------------------------------------
+typedef std::complex<double> zc;
+
+hps_status fgmres_one(hps_problem* p, const cd* rhs, cd* g, double tol, int maxit, hps_info* info) {
+  hps_ctx* c = p->ctx;
+  hipStream_t st = c->stream;
+  const Layout& lay = p->lay;
+  const long long n = lay.nslots;
+  const int R = lay.restart;
+  const size_t vb = (size_t)n;
+  cd* V = at<cd>(p, lay.V_off);
+  cd* Z = at<cd>(p, lay.Z_off);
+  cd* res = workv(p, 1);
+  cd* w = workv(p, 4);
+  cd* hh = at<cd>(p, lay.hh_off);           // [0, R+2): h, [R+2, 2R+4): h2 ; [2R+4]: |w|^2, [2R+5]: norm
+  cd* part = at<cd>(p, lay.part_off);
+  cd* hcol = hh;
+  cd* h2 = hh + (R + 2);
+  cd* nrm2 = hh + 2 * (R + 2);
+  cd* hnorm = nrm2 + 1;
+  const Geom& g1 = lay.lev[1].g;
+  const cd* T1 = Tlev(p, 1);
+  info->status = HPS_OK;
+  info->iterations = 0;
+  info->relres_est = 0;
+  info->relres_true = 0;
+  // ||rhs||
+  cd hv[2];
+  HIPCHK(c, multi_dot(rhs, 0, 1, rhs, n, part, nrm2, false, st));
+  HIPCHK(c, hipMemcpyAsync(hv, nrm2, sizeof(cd), hipMemcpyDeviceToHost, st));
+  HIPCHK(c, hipStreamSynchronize(st));
+  const double bnorm = std::sqrt(std::max(hv[0].x, 0.0));
+  HIPCHK(c, vfill(g, n, cmk(0, 0), st));
+  if (bnorm == 0.0) return HPS_OK;
+  HIPCHK(c, vcopy(rhs, res, n, st));
+  int it = 0;
+  double est = 1.0;
+  std::vector<zc> Hm((size_t)(R + 1) * R), cs(R), sn(R), gv(R + 1);
+  std::vector<cd> host((size_t)2 * (R + 2) + 2);
+  while (true) {
+    HIPCHK(c, multi_dot(res, 0, 1, res, n, part, nrm2, false, st));
+    HIPCHK(c, hipMemcpyAsync(hv, nrm2, sizeof(cd), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    const double beta = std::sqrt(std::max(hv[0].x, 0.0));
+    info->relres_true = beta / bnorm;
+    if (beta / bnorm <= tol || it >= maxit) break;
+    HIPCHK(c, normalize(res, nrm2, V, n, nullptr, st));
+    std::fill(gv.begin(), gv.end(), zc(0, 0));
+    gv[0] = beta;
+    int jend = 0;
+    for (int j = 0; j < R; ++j) {
+      hps_status s = precond_one(p, V + j * vb, Z + j * vb);
+      if (s != HPS_OK) return s;
+      HIPCHK(c, skeleton_apply(g1, T1, Z + j * vb, w, true, st));
+      s = cgs2(p, V, n, j + 1, w, n, hcol, h2);
+      if (s != HPS_OK) return s;
+      HIPCHK(c, multi_dot(w, 0, 1, w, n, part, nrm2, false, st));
+      HIPCHK(c, normalize(w, nrm2, V + (j + 1) * vb, n, hnorm, st));
+      HIPCHK(c, hipMemcpyAsync(host.data(), hh, sizeof(cd) * host.size(), hipMemcpyDeviceToHost, st));
+      HIPCHK(c, hipStreamSynchronize(st));
+      zc* col = &Hm[(size_t)j * (R + 1)];
+      for (int i = 0; i <= j; ++i) col[i] = zc(host[i].x, host[i].y);
+      col[j + 1] = zc(host[2 * (R + 2) + 1].x, 0.0);
+      for (int i = 0; i < j; ++i) {  // G_i = [[conj c, conj s], [-s, c]]
+        const zc t = std::conj(cs[i]) * col[i] + std::conj(sn[i]) * col[i + 1];
+        col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+        col[i] = t;
+      }
+      const double den = std::sqrt(std::norm(col[j]) + std::norm(col[j + 1]));
+      cs[j] = den > 0 ? col[j] / den : zc(1, 0);
+      sn[j] = den > 0 ? col[j + 1] / den : zc(0, 0);
+      col[j] = den;
+      col[j + 1] = 0;
+      gv[j + 1] = -sn[j] * gv[j];
+      gv[j] = std::conj(cs[j]) * gv[j];
+      ++it;
+      jend = j + 1;
+      est = std::abs(gv[j + 1]) / bnorm;
+      if (est <= tol || it >= maxit) break;
+    }
+    std::vector<zc> yv(jend);
+    for (int i = jend - 1; i >= 0; --i) {
+      zc acc = gv[i];
+      for (int q = i + 1; q < jend; ++q) acc -= Hm[(size_t)q * (R + 1) + i] * yv[q];
+      yv[i] = acc / Hm[(size_t)i * (R + 1) + i];
+    }
+    std::vector<cd> yd(jend);
+    for (int i = 0; i < jend; ++i) yd[i] = cmk(yv[i].real(), yv[i].imag());
+    HIPCHK(c, hipMemcpyAsync(hcol, yd.data(), sizeof(cd) * jend, hipMemcpyHostToDevice, st));
+    HIPCHK(c, multi_axpy(Z, n, jend, hcol, g, n, +1, st));
+    HIPCHK(c, hipStreamSynchronize(st));  // yd must outlive the copy
+    // true residual
+    HIPCHK(c, skeleton_apply(g1, T1, g, w, true, st));
+    HIPCHK(c, axpby(cmk(1, 0), rhs, cmk(-1, 0), w, res, n, st));
+  }
+  info->iterations = it;
+  info->relres_est = est;
+  info->status = (info->relres_true <= tol) ? HPS_OK : HPS_NOT_CONVERGED;
+  return HPS_OK;
+}
+
+}  // namespace
+
+// ============================ C ABI ========================================
+extern "C" {
+
+hps_status hps_ctx_create(void* hip_stream, hps_ctx** out) {
+  if (!out) return HPS_ERR_ARG;
+  hps_ctx* c = new hps_ctx;
+  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  *out = c;
+  return HPS_OK;
+}
+
+hps_status hps_ctx_destroy(hps_ctx* ctx) {
+  delete ctx;
+  return HPS_OK;
+}
+
+const char* hps_last_error(const hps_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+hps_status hps_sync(hps_ctx* ctx) {
+  if (!ctx) return HPS_ERR_ARG;
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  return HPS_OK;
+}
+
+hps_status hps_workspace_bytes(const hps_desc* desc, size_t* bytes) {
+  if (!bytes || check_desc(desc)) return HPS_ERR_ARG;
+  *bytes = make_layout(desc).total;
+  return HPS_OK;
+}
+
+hps_status hps_gll_nodes(int32_t order, double* xi) {
+  if (order < 1 || order > 64 || !xi) return HPS_ERR_ARG;
+  GllTables t = gll_tables(order);
+  std::memcpy(xi, t.xi.data(), sizeof(double) * (order + 1));
+  return HPS_OK;
+}
+
+hps_status hps_node_coords(const hps_desc* desc, double* x, double* y) {
+  if (check_desc(desc) || !x || !y) return HPS_ERR_ARG;
+  const int n = desc->n, N = desc->order, N1 = N + 1;
+  const double h = 1.0 / n;
+  GllTables t = gll_tables(N);
+  for (int e = 0; e < n * n; ++e) {
+    const int ix = e % n, iy = e / n;
+    for (int i = 0; i <= N; ++i)
+      for (int j = 0; j <= N; ++j) {
+        const size_t q = (size_t)e * N1 * N1 + i * N1 + j;
+        x[q] = ix * h + (1.0 + t.xi[i]) * h / 2;
+        y[q] = iy * h + (1.0 + t.xi[j]) * h / 2;
+      }
+  }
+  return HPS_OK;
+}
+
+hps_status hps_slot_coords(const hps_desc* desc, double* x, double* y, double* nx, double* ny) {
+  if (check_desc(desc) || !x || !y || !nx || !ny) return HPS_ERR_ARG;
+  const int n = desc->n, N = desc->order, p = N - 1;
+  const double h = 1.0 / n;
+  GllTables t = gll_tables(N);
+  const double nrm[4][2] = {{-1, 0}, {1, 0}, {0, -1}, {0, 1}};
+  for (int e = 0; e < n * n; ++e) {
+    const int ix = e % n, iy = e / n;
+    for (int s = 0; s < 4; ++s)
+      for (int k = 0; k < p; ++k) {
+        const size_t q = ((size_t)e * 4 + s) * p + k;
+        const double along = (1.0 + t.xi[k + 1]) * h / 2;
+        double xx, yy;
+        if (s == 0) { xx = ix * h; yy = iy * h + along; }
+        else if (s == 1) { xx = (ix + 1) * h; yy = iy * h + along; }
+        else if (s == 2) { xx = ix * h + along; yy = iy * h; }
+        else { xx = ix * h + along; yy = (iy + 1) * h; }
+        x[q] = xx;
+        y[q] = yy;
+        nx[q] = nrm[s][0];
+        ny[q] = nrm[s][1];
+      }
+  }
+  return HPS_OK;
+}
+
+hps_status hps_problem_create(hps_ctx* ctx, const hps_desc* desc, void* workspace, size_t bytes,
+                              hps_problem** out) {
+  if (!ctx || !out) return HPS_ERR_ARG;
+  if (const char* m = check_desc(desc)) return fail(ctx, HPS_ERR_ARG, m);
+  if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255))
+    return fail(ctx, HPS_ERR_ARG, "workspace must be a non-null 256-byte aligned device pointer");
+  Layout lay = make_layout(desc);
+  if (bytes < lay.total)
+    return fail(ctx, HPS_ERR_OOM, "workspace too small: need " + std::to_string(lay.total) + " bytes");
+  hps_problem* p = new hps_problem;
+  p->ctx = ctx;
+  p->desc = *desc;
+  p->lay = lay;
+  p->ws = reinterpret_cast<char*>(workspace);
+  p->state = kCreated;
+  p->merged = 0;
+  p->have_T1 = false;
+  // small tables: GLL data, merge maps, coarse index list, constants
+  GllTables t = gll_tables(desc->order);
+  std::vector<double> tab;
+  tab.insert(tab.end(), t.D.begin(), t.D.end());
+  tab.insert(tab.end(), t.w.begin(), t.w.end());
+  tab.insert(tab.end(), t.Kr.begin(), t.Kr.end());
+  HIPCHK(ctx, hipMemcpy(p->ws + lay.tables_off, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice));
+  for (int l = 1; l <= lay.L; ++l) {
+    const Level& lv = lay.lev[l];
+    if (!lv.has_merge) continue;
+    std::vector<int> mp = merge_map(lv);
+    HIPCHK(ctx, hipMemcpy(p->ws + lv.map_off, mp.data(), sizeof(int) * mp.size(), hipMemcpyHostToDevice));
+  }
+  if (!lay.exact && lay.nL > 0) {
+    std::vector<int> idx = coarse_slots(lay.lev[lay.L]);
+    HIPCHK(ctx, hipMemcpy(p->ws + lay.cidx_off, idx.data(), sizeof(int) * idx.size(), hipMemcpyHostToDevice));
+  }
+  const cd one = cmk(1, 0);
+  HIPCHK(ctx, hipMemcpy(p->ws + lay.one_off, &one, sizeof(cd), hipMemcpyHostToDevice));
+  int zero4[4] = {0, 0, 0, 0};
+  HIPCHK(ctx, hipMemcpy(p->ws + lay.flag_off, zero4, sizeof(zero4), hipMemcpyHostToDevice));
+  *out = p;
+  return HPS_OK;
+}
+
+hps_status hps_problem_destroy(hps_problem* p) {
+  delete p;
+  return HPS_OK;
+}
+
+hps_status hps_level_view_get(const hps_problem* pc, int32_t level, hps_level_view* out) {
+  hps_problem* p = const_cast<hps_problem*>(pc);
+  if (!p || !out || level < 1 || level > p->lay.L) return HPS_ERR_ARG;
+  const Level& lv = p->lay.lev[level];
+  out->level = level;
+  out->boxes = lv.g.nboxes;
+  out->box_nodes = lv.g.b;
+  out->morton = 1;
+  out->T = p->ws + lv.T_off;
+  out->pairs = lv.has_merge ? lv.pairs : 0;
+  out->shared_nodes = lv.has_merge ? lv.m : 0;
+  out->Winv = lv.has_merge ? (const void*)(p->ws + lv.Winv_off) : nullptr;
+  return HPS_OK;
+}
+
+hps_status hps_build_leaves(hps_problem* const* pp, int32_t count, const double* const* b_nodes,
+                            const double* const* s_nodes) {
+  if (!pp || count <= 0 || !b_nodes) return HPS_ERR_ARG;
+  for (int i = 0; i < count; ++i) {
+    hps_problem* p = pp[i];
+    if (!p || !b_nodes[i]) return p ? fail(p->ctx, HPS_ERR_ARG, "null b_nodes") : HPS_ERR_ARG;
+    const Layout& lay = p->lay;
+    const int N1 = lay.N + 1;
+    LeafArgs a{};
+    a.n = lay.n;
+    a.N = lay.N;
+    a.h = 1.0 / lay.n;
+    a.kappa = p->desc.kappa;
+    a.eta = p->desc.eta;
+    a.b_nodes = b_nodes[i];
+    a.s_nodes = s_nodes ? s_nodes[i] : nullptr;
+    const double* tab = at<double>(p, lay.tables_off);
+    a.D = tab;
+    a.w = tab + N1 * N1;
+    a.Kr = tab + N1 * N1 + N1;
+    a.scratch = at<double>(p, lay.scratch_off);
+    a.T = Tlev(p, 1);
+    a.H = at<cd>(p, lay.H_off);
+    a.flag = at<int>(p, lay.flag_off);
+    for (int e0 = 0; e0 < lay.E; e0 += lay.leaf_chunk) {
+      a.E0 = e0;
+      a.count = std::min(lay.leaf_chunk, lay.E - e0);
+      HIPCHK(p->ctx, leaf_build(a, p->ctx->stream));
+    }
+    p->state = kLeaves;
+    p->merged = 0;
+  }
+  return HPS_OK;
+}
+
+hps_status hps_merge_level(hps_problem* const* pp, int32_t count, int32_t level) {
+  if (!pp || count <= 0) return HPS_ERR_ARG;
+  for (int i = 0; i < count; ++i) {
+    hps_problem* p = pp[i];
+    if (!p) return HPS_ERR_ARG;
+    if (p->state < kLeaves) return fail(p->ctx, HPS_ERR_STATE, "merge before build_leaves");
+    const int Lm = p->lay.exact ? p->lay.L : p->lay.L - 1;
+    if (level < 1 || level > Lm) return fail(p->ctx, HPS_ERR_ARG, "merge level out of range");
+    if (level != p->merged + 1) return fail(p->ctx, HPS_ERR_STATE, "merge levels must run in order");
+    hps_status s = merge_one(p, level);
+    if (s != HPS_OK) return s;
+    p->merged = level;
+  }
+  return HPS_OK;
+}
+
+hps_status hps_set_rhs(hps_problem* const* pp, int32_t count, const double* const* t, double* const* rhs) {
+  if (!pp || count <= 0 || !t || !rhs) return HPS_ERR_ARG;
+  for (int i = 0; i < count; ++i) {
+    hps_problem* p = pp[i];
+    hps_status s = check_ready(p, false);
+    if (s != HPS_OK) return s;
+    if (!t[i] || !rhs[i]) return fail(p->ctx, HPS_ERR_ARG, "null t or rhs");
+    HIPCHK(p->ctx, rhs_build(p->lay.lev[1].g, Tlev(p, 1), at<cd>(p, p->lay.H_off),
+                             reinterpret_cast<const cd*>(t[i]), reinterpret_cast<cd*>(rhs[i]), p->ctx->stream));
+  }
+  return HPS_OK;
+}
+
+hps_status hps_skeleton_apply(hps_problem* const* pp, int32_t count, int32_t level, const double* const* g,
+                              double* const* out) {
+  if (!pp || count <= 0 || !g || !out) return HPS_ERR_ARG;
+  for (int i = 0; i < count; ++i) {
+    hps_problem* p = pp[i];
+    hps_status s = check_ready(p, false);
+    if (s != HPS_OK) return s;
+    if (level < 1 || level > p->lay.L) return fail(p->ctx, HPS_ERR_ARG, "level out of range");
+    if (level > p->merged + 1) return fail(p->ctx, HPS_ERR_STATE, "level maps not built yet");
+    HIPCHK(p->ctx, skeleton_apply(p->lay.lev[level].g, Tlev(p, level), reinterpret_cast<const cd*>(g[i]),
+                                  reinterpret_cast<cd*>(out[i]), level == 1, p->ctx->stream));
+  }
+  return HPS_OK;
+}
+
+hps_status hps_precond_apply(hps_problem* const* pp, int32_t count, const double* const* r, double* const* z) {
+  if (!pp || count <= 0 || !r || !z) return HPS_ERR_ARG;
+  for (int i = 0; i < count; ++i) {
+    hps_problem* p = pp[i];
+    hps_status s = check_ready(p, true);
+    if (s != HPS_OK) return s;
+    s = precond_one(p, reinterpret_cast<const cd*>(r[i]), reinterpret_cast<cd*>(z[i]));
+    if (s != HPS_OK) return s;
+  }
+  return HPS_OK;
+}
+
+hps_status hps_gmres_solve(hps_problem* const* pp, int32_t count, const double* const* rhs, double* const* g,
+                           double tol, int32_t maxit, hps_info* info) {
+  if (!pp || count <= 0 || !rhs || !g || !info || !(tol > 0) || maxit < 0) return HPS_ERR_ARG;
+  hps_status worst = HPS_OK;
+  for (int i = 0; i < count; ++i) {
+    hps_problem* p = pp[i];
+    hps_status s = check_ready(p, true);
+    if (s != HPS_OK) return s;
+    s = fgmres_one(p, reinterpret_cast<const cd*>(rhs[i]), reinterpret_cast<cd*>(g[i]), tol, maxit, &info[i]);
+    if (s != HPS_OK) return s;
+    s = read_flag(p);
+    if (s != HPS_OK) return s;
+    if (info[i].status == HPS_NOT_CONVERGED) worst = HPS_NOT_CONVERGED;
+  }
+  return worst;
+}
+
+}  // extern "C"

@@ -1,0 +1,144 @@
+// Shared device helpers: complex arithmetic, index maps and merge-tree geometry.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+typedef double2 cd;  // complex double, interleaved (re, im)
+typedef float2 cf;   // complex float
+
+__host__ __device__ inline cd cmk(double r, double i) { return make_double2(r, i); }
+__host__ __device__ inline cd cadd(cd a, cd b) { return make_double2(a.x + b.x, a.y + b.y); }
+__host__ __device__ inline cd csub(cd a, cd b) { return make_double2(a.x - b.x, a.y - b.y); }
+__host__ __device__ inline cd cmul(cd a, cd b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a*b + c
+__host__ __device__ inline cd cfma(cd a, cd b, cd c) {
+  return make_double2(fma(a.x, b.x, fma(-a.y, b.y, c.x)), fma(a.x, b.y, fma(a.y, b.x, c.y)));
+}
+__host__ __device__ inline cd cconj(cd a) { return make_double2(a.x, -a.y); }
+__host__ __device__ inline double cabs2(cd a) { return a.x * a.x + a.y * a.y; }
+__host__ __device__ inline cd cscale(cd a, double s) { return make_double2(a.x * s, a.y * s); }
+__host__ __device__ inline cd cinv(cd a) {
+  // 1/a with a scaling step so that |a| near the range limits stays finite
+  double s = fmax(fabs(a.x), fabs(a.y));
+  double ar = a.x / s, ai = a.y / s;
+  double d = ar * ar + ai * ai;
+  return make_double2(ar / (d * s), -ai / (d * s));
+}
+
+// Index map: i -> map ? map[i] : off + i + (i >= gap_start ? gap_len : 0).
+// Describes a row or column selection of a matrix operand.
+struct IdxMap {
+  const int* map;
+  int off;
+  int gap_start;
+  int gap_len;
+};
+__device__ inline int imap(const IdxMap& m, int i) {
+  return m.map ? m.map[i] : m.off + i + (i >= m.gap_start ? m.gap_len : 0);
+}
+inline IdxMap im_off(int off) { return IdxMap{nullptr, off, 1 << 30, 0}; }
+inline IdxMap im_gap(int off, int gap_start, int gap_len) {
+  return IdxMap{nullptr, off, gap_start, gap_len};
+}
+inline IdxMap im_tab(const int* tab) { return IdxMap{tab, 0, 1 << 30, 0}; }
+
+// ---------------------------------------------------------------------------
+// Merge-tree geometry.  Level l (1-based) boxes are wx x wy elements with
+// wx = 2^floor(l/2), wy = 2^floor((l-1)/2).  Boxes of every level are stored in
+// merge-tree order: box j covers the elements whose Morton code (x bits at even
+// positions, y bits at odd positions) shifted right by l-1 equals j, so the
+// pair merged at level l is (2j, 2j+1) and produces box j of level l+1.
+struct Geom {
+  int n, p, level;
+  int wx, wy, nbx, nby, nboxes, b;
+  int off[5];  // side offsets in the box-local [l; r; b; t] order
+};
+
+inline Geom make_geom(int n, int p, int level) {
+  Geom g;
+  g.n = n;
+  g.p = p;
+  g.level = level;
+  g.wx = 1 << (level / 2);
+  g.wy = 1 << ((level - 1) / 2);
+  g.nbx = n / g.wx;
+  g.nby = n / g.wy;
+  g.nboxes = g.nbx * g.nby;
+  g.off[0] = 0;
+  g.off[1] = g.wy * p;
+  g.off[2] = 2 * g.wy * p;
+  g.off[3] = 2 * g.wy * p + g.wx * p;
+  g.off[4] = 2 * (g.wx + g.wy) * p;
+  g.b = g.off[4];
+  return g;
+}
+
+__host__ __device__ inline uint32_t morton_xy(uint32_t x, uint32_t y) {
+  uint32_t code = 0;
+  for (int k = 0; k < 16; ++k) {
+    code |= ((x >> k) & 1u) << (2 * k);
+    code |= ((y >> k) & 1u) << (2 * k + 1);
+  }
+  return code;
+}
+
+__host__ __device__ inline void box_xy(const Geom& g, int j, int& bx, int& by) {
+  const int shift = g.level - 1;
+  const uint32_t code = (uint32_t)j << shift;
+  uint32_t ex = 0, ey = 0;
+  for (int k = 0; k < 16; ++k) {
+    ex |= ((code >> (2 * k)) & 1u) << k;
+    ey |= ((code >> (2 * k + 1)) & 1u) << k;
+  }
+  bx = (int)(ex >> ((shift + 1) / 2));
+  by = (int)(ey >> (shift / 2));
+}
+
+__host__ __device__ inline int box_index(const Geom& g, int bx, int by) {
+  const int shift = g.level - 1;
+  return (int)(morton_xy((uint32_t)bx * g.wx, (uint32_t)by * g.wy) >> shift);
+}
+
+__host__ __device__ inline int side_of(const Geom& g, int k) {
+  return (k >= g.off[1]) + (k >= g.off[2]) + (k >= g.off[3]);
+}
+
+__host__ __device__ inline bool side_physical(const Geom& g, int bx, int by, int s) {
+  return (s == 0 && bx == 0) || (s == 1 && bx == g.nbx - 1) || (s == 2 && by == 0) ||
+         (s == 3 && by == g.nby - 1);
+}
+
+// Canonical slot of box-local boundary index k of box (bx, by).
+__host__ __device__ inline int box_slot(const Geom& g, int bx, int by, int k) {
+  const int s = side_of(g, k);
+  const int kk = k - g.off[s];
+  const int q = kk / g.p, r = kk - q * g.p;
+  int ex, ey;
+  if (s == 0) { ex = bx * g.wx; ey = by * g.wy + q; }
+  else if (s == 1) { ex = bx * g.wx + g.wx - 1; ey = by * g.wy + q; }
+  else if (s == 2) { ex = bx * g.wx + q; ey = by * g.wy; }
+  else { ex = bx * g.wx + q; ey = by * g.wy + g.wy - 1; }
+  return ((ex + g.n * ey) * 4 + s) * g.p + r;
+}
+
+// Slot across the face from canonical slot `s`, or -1 on the physical boundary.
+__host__ __device__ inline int slot_partner(int n, int p, int s) {
+  const int k = s % p;
+  const int side = (s / p) & 3;
+  const int e = s / (4 * p);
+  const int ix = e % n, iy = e / n;
+  if (side == 0) return ix == 0 ? -1 : (((e - 1) * 4 + 1) * p + k);
+  if (side == 1) return ix == n - 1 ? -1 : (((e + 1) * 4 + 0) * p + k);
+  if (side == 2) return iy == 0 ? -1 : (((e - n) * 4 + 3) * p + k);
+  return iy == n - 1 ? -1 : (((e + n) * 4 + 2) * p + k);
+}
+
+// Allow up to `bytes` of dynamic LDS for `kernel` (gfx950 has 160 KB per CU).
+template <class K>
+inline hipError_t allow_lds(K kernel, size_t bytes) {
+  if (bytes <= 48 * 1024) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}

@@ -1,0 +1,149 @@
+// Batched complex FP64 GEMM on the CDNA4 matrix cores (v_mfma_f64_16x16x4f64)
+// and batched strided copies.  All matrices are column-major; operands are
+// addressed through IdxMap row/column selections so that sub-blocks of the
+// box maps (a side, all sides but one, a permuted scatter) are read and written
+// in place.
+//
+// Complex product by the 4M scheme on real MFMA tiles:
+//   Re += Ar Br - Ai Bi,  Im += Ar Bi + Ai Br.
+// Tile: BM x BN per workgroup, waves arranged WM x WN, each wave owning
+// (BM/WM) x (BN/WN) outputs as 16x16 MFMA tiles; K staged through LDS in
+// chunks of KT complex.
+#include "common.h"
+#include "host.h"
+
+namespace hps {
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int KT = 16;
+
+template <int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__(64 * WM * WN) void zgemm_kernel(GemmArgs a) {
+  constexpr int NT = 64 * WM * WN;
+  constexpr int TM = BM / WM / 16;
+  constexpr int TN = BN / WN / 16;
+  __shared__ cd As[KT][BM];
+  __shared__ cd Bs[KT][BN];
+  const int b = blockIdx.y;
+  const int tilesM = (a.M + BM - 1) / BM;
+  const int m0 = (blockIdx.x % tilesM) * BM;
+  const int n0 = (blockIdx.x / tilesM) * BN;
+  const cd* Ab = a.A.base + (long long)b * a.A.bstride;
+  const cd* Bb = a.B.base + (long long)b * a.B.bstride;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave % WM, wn = wave / WM;
+  const int lr = lane & 15, lk = lane >> 4;
+
+  d4 accr[TM][TN], acci[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      accr[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+      acci[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+    }
+
+  for (int k0 = 0; k0 < a.K; k0 += KT) {
+    for (int e = tid; e < BM * KT; e += NT) {
+      const int i = e % BM, k = e / BM;
+      const int gi = m0 + i, gk = k0 + k;
+      cd v = cmk(0.0, 0.0);
+      if (gi < a.M && gk < a.K) v = Ab[(long long)imap(a.A.c, gk) * a.A.ld + imap(a.A.r, gi)];
+      As[k][i] = v;
+    }
+    for (int e = tid; e < BN * KT; e += NT) {
+      const int k = e % KT, j = e / KT;
+      const int gj = n0 + j, gk = k0 + k;
+      cd v = cmk(0.0, 0.0);
+      if (gj < a.N && gk < a.K) v = Bb[(long long)imap(a.B.c, gj) * a.B.ld + imap(a.B.r, gk)];
+      Bs[k][j] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < KT; kk += 4) {
+      cd av[TM], bv[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) av[i] = As[kk + lk][wm * (BM / WM) + i * 16 + lr];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) bv[j] = Bs[kk + lk][wn * (BN / WN) + j * 16 + lr];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          accr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i].x, bv[j].x, accr[i][j], 0, 0, 0);
+          accr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-av[i].y, bv[j].y, accr[i][j], 0, 0, 0);
+          acci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i].x, bv[j].y, acci[i][j], 0, 0, 0);
+          acci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i].y, bv[j].x, acci[i][j], 0, 0, 0);
+        }
+    }
+    __syncthreads();
+  }
+
+  // 16x16x4 f64 MFMA result layout (checked on gfx950): lane l, element v ->
+  // row l/16 + 4 v, column l%16.  (The f32 16x16x4 variant uses row 4(l/16) + v.)
+  cd* Db = a.D + (long long)b * a.Dstride;
+  const cd* Cb = a.C.base ? a.C.base + (long long)b * a.C.bstride : nullptr;
+  const bool use_c = (a.beta.x != 0.0 || a.beta.y != 0.0);
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gi = m0 + wm * (BM / WM) + i * 16 + lk + 4 * v;
+        const int gj = n0 + wn * (BN / WN) + j * 16 + lr;
+        if (gi < a.M && gj < a.N) {
+          cd acc = cmk(accr[i][j][v], acci[i][j][v]);
+          cd out = cmul(a.alpha, acc);
+          if (use_c) out = cfma(a.beta, Cb[(long long)imap(a.C.c, gj) * a.C.ld + imap(a.C.r, gi)], out);
+          if (a.has_diag && gi == gj) out = cadd(out, a.diag_add);
+          Db[(long long)imap(a.dc, gj) * a.ldd + imap(a.dr, gi)] = out;
+        }
+      }
+}
+
+__global__ void zcopy2d_kernel(int M, int N, Operand S, cd alpha, cd* D, long long Dstride, int ldd,
+                               IdxMap dr, IdxMap dc) {
+  const int b = blockIdx.y;
+  const long long total = (long long)M * N;
+  for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(idx % M), j = (int)(idx / M);
+    cd v = cmk(0.0, 0.0);
+    if (S.base) v = cmul(alpha, S.base[(long long)b * S.bstride + (long long)imap(S.c, j) * S.ld + imap(S.r, i)]);
+    D[(long long)b * Dstride + (long long)imap(dc, j) * ldd + imap(dr, i)] = v;
+  }
+}
+
+template <int BM, int BN, int WM, int WN>
+hipError_t launch(const GemmArgs& a, hipStream_t st) {
+  const int tiles = ((a.M + BM - 1) / BM) * ((a.N + BN - 1) / BN);
+  hipLaunchKernelGGL((zgemm_kernel<BM, BN, WM, WN>), dim3(tiles, a.batch), dim3(64 * WM * WN), 0,
+                     st, a);
+  return hipPeekAtLastError();
+}
+
+}  // namespace
+
+hipError_t zgemm(const GemmArgs& a, hipStream_t st) {
+  if (a.M <= 0 || a.N <= 0 || a.batch <= 0) return hipSuccess;
+  if (a.M >= 48 && a.N >= 48) return launch<64, 64, 2, 2>(a, st);
+  if (a.M >= 24 && a.N >= 24) return launch<32, 32, 2, 2>(a, st);
+  return launch<16, 16, 1, 1>(a, st);
+}
+
+hipError_t zcopy2d(int M, int N, int batch, const Operand& S, cd alpha, cd* D, long long Dstride,
+                   int ldd, IdxMap dr, IdxMap dc, hipStream_t st) {
+  if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
+  const long long total = (long long)M * N;
+  int blocks = (int)std::min<long long>((total + 255) / 256, 1024);
+  hipLaunchKernelGGL(zcopy2d_kernel, dim3(blocks, batch), dim3(256), 0, st, M, N, S, alpha, D,
+                     Dstride, ldd, dr, dc);
+  return hipPeekAtLastError();
+}
+
+}  // namespace hps

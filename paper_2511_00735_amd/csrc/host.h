@@ -1,0 +1,68 @@
+// Internal host-side declarations of the HPS library (not part of the C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "common.h"
+
+namespace hps {
+
+struct GllTables {
+  int N;
+  std::vector<double> xi, w, D, Kr;  // D and Kr row-major (N+1)^2
+};
+GllTables gll_tables(int N);
+
+// ---- leaf kernels (leaf.hip) ------------------------------------------------
+struct LeafArgs {
+  int n, N, E0, count;        // elements [E0, E0+count) in canonical numbering
+  double h, kappa, eta;
+  const double* b_nodes;      // [E][(N+1)^2]
+  const double* s_nodes;      // complex [E][(N+1)^2] or null
+  const double* D;            // (N+1)^2 row-major reference D
+  const double* w;            // N+1
+  const double* Kr;           // (N+1)^2 reference stiffness
+  double* scratch;            // count * nloc * ncol doubles
+  cd* T;                      // level-1 box maps, Morton order, [E][4p][4p] col-major
+  cd* H;                      // [E][4p] canonical element order
+  int* flag;                  // device error flag (bit 1: singular pivot)
+};
+hipError_t leaf_build(const LeafArgs& a, hipStream_t st);
+size_t leaf_scratch_doubles(int N, int count);
+
+// ---- batched complex GEMM and copies (gemm.hip) ---------------------------
+struct Operand {
+  const cd* base;
+  long long bstride;  // elements between consecutive batch entries
+  int ld;
+  IdxMap r, c;
+};
+struct GemmArgs {
+  int M, N, K, batch;
+  Operand A, B;
+  cd alpha, beta;
+  Operand C;          // read only when beta != 0 (may alias D)
+  cd* D;
+  long long Dstride;
+  int ldd;
+  IdxMap dr, dc;
+  cd diag_add;        // added to D(i, i) for i < min(M, N) when has_diag
+  int has_diag;
+};
+// D = alpha * A B + beta * C (+ diag_add I), all column-major complex FP64.
+hipError_t zgemm(const GemmArgs& a, hipStream_t st);
+// D(dr(i), dc(j)) = alpha * S(sr(i), sc(j)) (S == null: zero), batched.
+hipError_t zcopy2d(int M, int N, int batch, const Operand& S, cd alpha, cd* D,
+                   long long Dstride, int ldd, IdxMap dr, IdxMap dc, hipStream_t st);
+
+// ---- batched complex inversion (inverse.hip) -------------------------------
+// In-place inverse of `batch` m x m column-major matrices (stride `bstride`),
+// Gauss-Jordan with partial pivoting.  scratch: see inverse_scratch_bytes.
+size_t inverse_scratch_bytes(int m, int batch);
+hipError_t zinverse(cd* A, int m, int lda, long long bstride, int batch, void* scratch,
+                    int* flag, hipStream_t st);
+
+}  // namespace hps

@@ -1,0 +1,325 @@
+"""Python binding of the HIP library (``_lib/libhps.so``, C ABI in ``include/hps.h``).
+
+Argument marshalling only: every step of the solver runs in the library's HIP
+kernels.  PyTorch supplies device memory (one ``uint8`` workspace tensor per
+problem, plus the input/output tensors) and the stream.  Importing this module
+fails loudly when the library has not been built; there is no fallback.
+
+Vectors use the canonical skeleton layout of ``include/hps.h``: complex128
+tensors of length n*n*4*(N-1), slot (e, side, k) at (e*4 + side)*(N-1) + k.
+"""
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libhps.so")
+
+HPS_OK, HPS_NOT_CONVERGED = 0, 1
+HPS_ERR = {-1: "HPS_ERR_ARG", -2: "HPS_ERR_OOM", -3: "HPS_ERR_SINGULAR",
+           -4: "HPS_ERR_STATE", -5: "HPS_ERR_HIP"}
+HPS_FP64, HPS_MIXED = 0, 1
+
+
+class HPSError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{HPS_ERR.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("kappa", ctypes.c_double), ("eta", ctypes.c_double),
+                ("precision", ctypes.c_int32), ("levels", ctypes.c_int32),
+                ("coarse_iters", ctypes.c_int32), ("gamma", ctypes.c_int32),
+                ("restart", ctypes.c_int32)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iterations", ctypes.c_int32),
+                ("relres_est", ctypes.c_double), ("relres_true", ctypes.c_double)]
+
+
+class LevelView(ctypes.Structure):
+    _fields_ = [("level", ctypes.c_int32), ("boxes", ctypes.c_int32),
+                ("box_nodes", ctypes.c_int32), ("morton", ctypes.c_int32),
+                ("T", ctypes.c_void_p), ("pairs", ctypes.c_int32),
+                ("shared_nodes", ctypes.c_int32), ("Winv", ctypes.c_void_p)]
+
+
+_P = ctypes.c_void_p
+_PP = ctypes.POINTER(ctypes.c_void_p)
+_SIGS = {
+    "hps_ctx_create": ([_P, ctypes.POINTER(_P)], ctypes.c_int),
+    "hps_ctx_destroy": ([_P], ctypes.c_int),
+    "hps_last_error": ([_P], ctypes.c_char_p),
+    "hps_sync": ([_P], ctypes.c_int),
+    "hps_workspace_bytes": ([ctypes.POINTER(Desc), ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "hps_gll_nodes": ([ctypes.c_int32, _P], ctypes.c_int),
+    "hps_node_coords": ([ctypes.POINTER(Desc), _P, _P], ctypes.c_int),
+    "hps_slot_coords": ([ctypes.POINTER(Desc), _P, _P, _P, _P], ctypes.c_int),
+    "hps_problem_create": ([_P, ctypes.POINTER(Desc), _P, ctypes.c_size_t, ctypes.POINTER(_P)],
+                           ctypes.c_int),
+    "hps_problem_destroy": ([_P], ctypes.c_int),
+    "hps_level_view_get": ([_P, ctypes.c_int32, ctypes.POINTER(LevelView)], ctypes.c_int),
+    "hps_build_leaves": ([_PP, ctypes.c_int32, _PP, _PP], ctypes.c_int),
+    "hps_merge_level": ([_PP, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
+    "hps_set_rhs": ([_PP, ctypes.c_int32, _PP, _PP], ctypes.c_int),
+    "hps_skeleton_apply": ([_PP, ctypes.c_int32, ctypes.c_int32, _PP, _PP], ctypes.c_int),
+    "hps_precond_apply": ([_PP, ctypes.c_int32, _PP, _PP], ctypes.c_int),
+    "hps_gmres_solve": ([_PP, ctypes.c_int32, _PP, _PP, ctypes.c_double, ctypes.c_int32,
+                         ctypes.POINTER(Info)], ctypes.c_int),
+}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"HIP library not built: {LIB_PATH} is missing "
+                          "(run `python -m paper_2511_00735_amd.build`)")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (args, res) in _SIGS.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    return lib
+
+
+lib = _load()
+
+
+def _ptrs(values):
+    arr = (ctypes.c_void_p * len(values))(*values)
+    return ctypes.cast(arr, _PP)
+
+
+def _dptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous CUDA tensor")
+    return t.data_ptr()
+
+
+def make_desc(n, order, kappa, eta=None, levels=0, coarse_iters=5, restart=60,
+              precision=HPS_FP64, gamma=1):
+    return Desc(n, order, float(kappa), float(kappa if eta is None else eta), precision,
+                levels, coarse_iters, gamma, restart)
+
+
+def workspace_bytes(desc):
+    out = ctypes.c_size_t(0)
+    rc = lib.hps_workspace_bytes(ctypes.byref(desc), ctypes.byref(out))
+    if rc != HPS_OK:
+        raise HPSError(rc, "invalid descriptor")
+    return out.value
+
+
+def gll_nodes(order):
+    xi = np.zeros(order + 1)
+    rc = lib.hps_gll_nodes(order, xi.ctypes.data)
+    if rc != HPS_OK:
+        raise HPSError(rc, "hps_gll_nodes")
+    return xi
+
+
+def node_coords(desc):
+    E, N1 = desc.n * desc.n, desc.order + 1
+    x = np.zeros(E * N1 * N1)
+    y = np.zeros(E * N1 * N1)
+    rc = lib.hps_node_coords(ctypes.byref(desc), x.ctypes.data, y.ctypes.data)
+    if rc != HPS_OK:
+        raise HPSError(rc, "hps_node_coords")
+    return x.reshape(E, N1 * N1), y.reshape(E, N1 * N1)
+
+
+def slot_coords(desc):
+    ns = desc.n * desc.n * 4 * (desc.order - 1)
+    arrs = [np.zeros(ns) for _ in range(4)]
+    rc = lib.hps_slot_coords(ctypes.byref(desc), *[a.ctypes.data for a in arrs])
+    if rc != HPS_OK:
+        raise HPSError(rc, "hps_slot_coords")
+    return tuple(arrs)
+
+
+class Context:
+    """A library context bound to a torch CUDA stream (default: current stream)."""
+
+    def __init__(self, stream=None):
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        rc = lib.hps_ctx_create(ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if rc != HPS_OK:
+            raise HPSError(rc, "hps_ctx_create")
+        self.handle = h
+
+    def check(self, rc, what):
+        if rc < 0:
+            msg = lib.hps_last_error(self.handle)
+            raise HPSError(rc, f"{what}: {msg.decode() if msg else ''}")
+        return rc
+
+    def sync(self):
+        self.check(lib.hps_sync(self.handle), "hps_sync")
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            lib.hps_ctx_destroy(self.handle)
+            self.handle = None
+
+
+class Problem:
+    """One Helmholtz problem living in one device workspace."""
+
+    def __init__(self, ctx, desc, workspace=None):
+        self.ctx = ctx
+        self.desc = desc
+        self.n, self.N = desc.n, desc.order
+        self.p = self.N - 1
+        self.E = self.n * self.n
+        self.nslots = self.E * 4 * self.p
+        self.bytes = workspace_bytes(desc)
+        if workspace is None:
+            workspace = torch.empty(self.bytes + 256, dtype=torch.uint8, device="cuda")
+        self._ws_tensor = workspace
+        base = workspace.data_ptr()
+        self.ws_offset = (-base) % 256
+        h = ctypes.c_void_p()
+        ctx.check(lib.hps_problem_create(ctx.handle, ctypes.byref(desc),
+                                         ctypes.c_void_p(base + self.ws_offset),
+                                         ctypes.c_size_t(workspace.numel() - self.ws_offset),
+                                         ctypes.byref(h)), "hps_problem_create")
+        self.handle = h
+        self.levels = desc.levels or 2 * int(round(np.log2(self.n)))
+        self.lmax = 2 * int(round(np.log2(self.n)))
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            lib.hps_problem_destroy(self.handle)
+            self.handle = None
+
+    # ---- data preparation (problem inputs, evaluated at the library's nodes)
+    def coefficient_nodes(self, b_fn):
+        x, y = node_coords(self.desc)
+        return torch.from_numpy(np.ascontiguousarray(b_fn(x, y), dtype=np.float64)).cuda()
+
+    def source_nodes(self, s_fn):
+        x, y = node_coords(self.desc)
+        return torch.from_numpy(np.ascontiguousarray(s_fn(x, y), dtype=np.complex128)).cuda()
+
+    def boundary_data(self, t_fn):
+        x, y, nx, ny = slot_coords(self.desc)
+        return torch.from_numpy(np.ascontiguousarray(t_fn(x, y, nx, ny), dtype=np.complex128)).cuda()
+
+    # ---- hot path ---------------------------------------------------------
+    def build_leaves(self, b_nodes, s_nodes=None):
+        build_leaves([self], [b_nodes], None if s_nodes is None else [s_nodes])
+
+    def merge_level(self, level):
+        merge_level([self], level)
+
+    def merge_all(self):
+        top = self.levels if self.desc.coarse_iters == -1 else self.levels - 1
+        for level in range(1, top + 1):
+            self.merge_level(level)
+
+    def set_rhs(self, t):
+        rhs = torch.empty(self.nslots, dtype=torch.complex128, device="cuda")
+        set_rhs([self], [t], [rhs])
+        return rhs
+
+    def skeleton_apply(self, g, level=1, out=None):
+        if out is None:
+            out = torch.zeros(self.nslots, dtype=torch.complex128, device="cuda")
+        p = _ptrs([self.handle.value])
+        self.ctx.check(lib.hps_skeleton_apply(p, 1, level, _ptrs([_dptr(g)]), _ptrs([_dptr(out)])),
+                       "hps_skeleton_apply")
+        return out
+
+    def precond_apply(self, r, out=None):
+        if out is None:
+            out = torch.empty(self.nslots, dtype=torch.complex128, device="cuda")
+        precond_apply([self], [r], [out])
+        return out
+
+    def gmres_solve(self, rhs, tol=1e-10, maxit=600, out=None):
+        if out is None:
+            out = torch.empty(self.nslots, dtype=torch.complex128, device="cuda")
+        infos = gmres_solve([self], [rhs], [out], tol, maxit)
+        return out, infos[0]
+
+    # ---- inspection -------------------------------------------------------
+    def level_view(self, level):
+        v = LevelView()
+        self.ctx.check(lib.hps_level_view_get(self.handle, level, ctypes.byref(v)), "level_view")
+        return v
+
+    def _view(self, ptr, count):
+        off = ptr - self._ws_tensor.data_ptr()
+        raw = self._ws_tensor[off:off + 16 * count]
+        return raw.view(torch.complex128)
+
+    def level_T(self, level):
+        """Box maps of a level as [boxes, b, b] (row, column), Morton box order."""
+        v = self.level_view(level)
+        b = v.box_nodes
+        t = self._view(v.T, v.boxes * b * b).view(v.boxes, b, b)
+        return t.transpose(1, 2)   # stored column-major
+
+    def level_Winv(self, level):
+        v = self.level_view(level)
+        m = v.shared_nodes
+        if not v.Winv:
+            return None
+        return self._view(v.Winv, v.pairs * m * m).view(v.pairs, m, m).transpose(1, 2)
+
+
+# ---- batch-first entry points (several problems per call) ------------------
+def _handles(problems):
+    return _ptrs([p.handle.value for p in problems])
+
+
+def build_leaves(problems, b_nodes, s_nodes=None):
+    ctx = problems[0].ctx
+    s = _ptrs([_dptr(x) for x in s_nodes]) if s_nodes is not None else None
+    ctx.check(lib.hps_build_leaves(_handles(problems), len(problems),
+                                   _ptrs([_dptr(b) for b in b_nodes]), s), "hps_build_leaves")
+
+
+def merge_level(problems, level):
+    problems[0].ctx.check(lib.hps_merge_level(_handles(problems), len(problems), level),
+                          "hps_merge_level")
+
+
+def set_rhs(problems, t, rhs):
+    problems[0].ctx.check(lib.hps_set_rhs(_handles(problems), len(problems),
+                                          _ptrs([_dptr(x) for x in t]),
+                                          _ptrs([_dptr(x) for x in rhs])), "hps_set_rhs")
+
+
+def precond_apply(problems, r, z):
+    problems[0].ctx.check(lib.hps_precond_apply(_handles(problems), len(problems),
+                                                _ptrs([_dptr(x) for x in r]),
+                                                _ptrs([_dptr(x) for x in z])), "hps_precond_apply")
+
+
+def gmres_solve(problems, rhs, g, tol=1e-10, maxit=600):
+    infos = (Info * len(problems))()
+    problems[0].ctx.check(lib.hps_gmres_solve(_handles(problems), len(problems),
+                                              _ptrs([_dptr(x) for x in rhs]),
+                                              _ptrs([_dptr(x) for x in g]), tol, maxit, infos),
+                          "hps_gmres_solve")
+    return [dict(status=i.status, iterations=i.iterations, relres_est=i.relres_est,
+                 relres_true=i.relres_true) for i in infos]
+
+
+def morton_box_xy(level, j):
+    """(bx, by) of box j of a level in the library's merge-tree storage order."""
+    shift = level - 1
+    code = j << shift
+    ex = ey = 0
+    for k in range(16):
+        ex |= ((code >> (2 * k)) & 1) << k
+        ey |= ((code >> (2 * k + 1)) & 1) << k
+    return ex >> ((shift + 1) // 2), ey >> (shift // 2)
