@@ -69,7 +69,7 @@ typedef enum { HPS_FP64 = 0, HPS_MIXED = 1 } hps_precision;
 /* Problem descriptor.  Defaults in brackets. */
 typedef struct {
   int32_t n;             /* elements per side, power of two, 2 <= n <= 1024   */
-  int32_t order;         /* GLL order N, 2 <= N <= 24                          */
+  int32_t order;         /* GLL order N, 2 <= N <= 16                          */
   double kappa;          /* wavenumber kappa > 0 (c = kappa^2 (1 - b))         */
   double eta;            /* impedance parameter eta > 0 (the paper: eta=kappa) */
   int32_t precision;     /* hps_precision [HPS_FP64]                           */
@@ -113,6 +113,11 @@ hps_status hps_ctx_destroy(hps_ctx* ctx);
 const char* hps_last_error(const hps_ctx* ctx);
 /* Wait for the context's stream and report deferred device errors. */
 hps_status hps_sync(hps_ctx* ctx);
+/* Options.  HPS_OPT_GRAPHS (default 1): replay the multigrid V-cycle from a HIP
+   graph captured once per problem (on a private capture stream) instead of
+   launching its kernels one by one.  Results are bitwise identical either way. */
+enum { HPS_OPT_GRAPHS = 1 };
+hps_status hps_set_option(hps_ctx* ctx, int32_t option, int32_t value);
 
 /* ---- sizing and host-side geometry -------------------------------------- */
 /* Exact device workspace (bytes) of one problem; the admission footprint. */

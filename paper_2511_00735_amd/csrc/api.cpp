@@ -14,10 +14,13 @@
 #include "hps.h"
 #include "host.h"
 #include "solve.h"
+#include "gemv.h"
 
 struct hps_ctx {
   hipStream_t stream;
   std::string err;
+  hipStream_t cap_stream = nullptr;  // private stream used only to capture graphs
+  int use_graphs = 1;
 };
 
 namespace hps {
@@ -52,6 +55,7 @@ struct Layout {
   size_t vtmp_m, vtmp_e;          // max pairs*m and pairs*e over levels
   size_t cV_off, cw_off, cx_off, cidx_off, cH_off, cy_off, cs_off;  // coarse GMRES
   size_t part_off, hh_off, one_off, flag_off;
+  size_t gpart_off, gpart_elems;  // split-K GEMV partial sums
   size_t total;
 };
 
@@ -192,7 +196,7 @@ Layout make_layout(const hps_desc* d) {
   const size_t vb = sizeof(cd) * (size_t)lay.nslots;
   lay.V_off = take(vb * (lay.restart + 1));
   lay.Z_off = take(vb * lay.restart);
-  lay.work_off = take(up256(vb) * 5);
+  lay.work_off = take(up256(vb) * 7);
   lay.vtmp_off = take(sizeof(cd) * (3 * lay.vtmp_m + 2 * lay.vtmp_e) + 5 * 256);
   {
     Level& top = lay.lev[lay.L];
@@ -216,6 +220,25 @@ Layout make_layout(const hps_desc* d) {
   lay.part_off = take(sizeof(cd) * (size_t)(lay.restart + 2) * kMaxDotBlocks);
   lay.hh_off = take(sizeof(cd) * (size_t)(2 * (lay.restart + 2) + 4));
   lay.one_off = take(sizeof(cd));
+  {
+    // split-K GEMV partials: at most two descriptors per launch, of the shapes
+    // (m x m), (e x m), (m x e) per merge level and (nL/2 x nL/2) for the coarse pair
+    size_t mx = 0;
+    auto need = [&](int M, int K, int batch) {
+      const int ns = gemv_nsplit(M, K, batch);
+      if (ns > 1) mx = std::max(mx, (size_t)ns * batch * M);
+    };
+    for (int l = 1; l <= lay.L; ++l) {
+      const Level& lv = lay.lev[l];
+      if (!lv.has_merge) continue;
+      need(lv.m, lv.m, lv.pairs);
+      need(lv.e, lv.m, lv.pairs);
+      need(lv.m, lv.e, lv.pairs);
+    }
+    if (lay.nL > 0) need(lay.nL / 2, lay.nL / 2, 1);
+    lay.gpart_elems = 2 * mx + 64;
+    lay.gpart_off = take(sizeof(cd) * lay.gpart_elems);
+  }
   lay.flag_off = take(sizeof(int) * 4);
   lay.total = off;
   return lay;
@@ -234,6 +257,8 @@ struct hps_problem {
   int state;
   int merged;     // highest merge level done
   bool have_T1;
+  hipGraphExec_t pgraph = nullptr;  // captured V-cycle (work vector 5 -> 6)
+  bool graph_failed = false;
 };
 
 using namespace hps;
@@ -293,9 +318,24 @@ hps_status merge_one(hps_problem* p, int l) {
   HIPCHK(c, zinverse(Winv, m, m, (long long)m * m, np, invs, flag, st));
   if (l == lay.L) return HPS_OK;  // exact top: only W^-1 is needed
   const long long zs = (long long)m * 2 * e;
+  const Level& nx = lay.lev[l + 1];
+  const int* mp = at<int>(p, lv.map_off);
+  // only rows/columns of the merged boxes' interior sides are ever needed
+  auto skip = [&](int row_y, int row_off, int col_y, int col_off) {
+    PhysSkip k{};
+    k.enabled = 1;
+    k.g = nx.g;
+    k.ymap = mp;
+    k.row_y = row_y;
+    k.row_off = row_off;
+    k.col_y = col_y;
+    k.col_off = col_off;
+    return k;
+  };
+  const PhysSkip sk_c0 = skip(0, 0, 1, 0), sk_ce = skip(0, 0, 1, e);
   // Z = [T^P_{a,E1} | T^P_aa T^Q_{b,E2}]
   HIPCHK(c, zcopy2d(m, e, np, Operand{TP, pstride, b, im_off(lv.a0), lv.E1}, one, Z, zs, m, im_off(0),
-                    im_off(0), st));
+                    im_off(0), st, &sk_c0));
   {
     GemmArgs g{};
     g.M = m; g.N = e; g.K = m; g.batch = np;
@@ -303,6 +343,7 @@ hps_status merge_one(hps_problem* p, int l) {
     g.B = Operand{TQ, pstride, b, im_off(lv.b0), lv.E2};
     g.alpha = one; g.beta = zero; g.C = none;
     g.D = Z; g.Dstride = zs; g.ldd = m; g.dr = im_off(0); g.dc = im_off(e);
+    g.skip = sk_ce;
     HIPCHK(c, zgemm(g, st));
   }
   // YQ = W^-1 Z   (the shared-face data f^Q_b as a function of y)
@@ -313,12 +354,13 @@ hps_status merge_one(hps_problem* p, int l) {
     g.B = Operand{Z, zs, m, im_off(0), im_off(0)};
     g.alpha = one; g.beta = zero; g.C = none;
     g.D = YQ; g.Dstride = zs; g.ldd = m; g.dr = im_off(0); g.dc = im_off(0);
+    g.skip = sk_c0;
     HIPCHK(c, zgemm(g, st));
   }
   // YP = T^Q_bb YQ + [0 | T^Q_{b,E2}]   (f^P_a as a function of y)
-  HIPCHK(c, zcopy2d(m, e, np, none, one, YP, zs, m, im_off(0), im_off(0), st));
+  HIPCHK(c, zcopy2d(m, e, np, none, one, YP, zs, m, im_off(0), im_off(0), st, &sk_c0));
   HIPCHK(c, zcopy2d(m, e, np, Operand{TQ, pstride, b, im_off(lv.b0), lv.E2}, one, YP, zs, m, im_off(0),
-                    im_off(e), st));
+                    im_off(e), st, &sk_ce));
   {
     GemmArgs g{};
     g.M = m; g.N = 2 * e; g.K = m; g.batch = np;
@@ -326,19 +368,19 @@ hps_status merge_one(hps_problem* p, int l) {
     g.B = Operand{YQ, zs, m, im_off(0), im_off(0)};
     g.alpha = one; g.beta = one; g.C = Operand{YP, zs, m, im_off(0), im_off(0)};
     g.D = YP; g.Dstride = zs; g.ldd = m; g.dr = im_off(0); g.dc = im_off(0);
+    g.skip = sk_c0;
     HIPCHK(c, zgemm(g, st));
   }
   // T_new = blkdiag(T^P_E1E1, T^Q_E2E2) + [T^P_{E1,a} YP ; T^Q_{E2,b} YQ], scattered
-  const Level& nx = lay.lev[l + 1];
   cd* Tn = Tlev(p, l + 1);
   const int bn = nx.g.b;
   const long long ns = (long long)bn * bn;
-  const int* mp = at<int>(p, lv.map_off);
   const IdxMap rowP = im_tab(mp), rowQ = im_tab(mp + e), colP = im_tab(mp), colQ = im_tab(mp + e);
-  HIPCHK(c, zcopy2d(e, e, np, Operand{TP, pstride, b, lv.E1, lv.E1}, one, Tn, ns, bn, rowP, colP, st));
-  HIPCHK(c, zcopy2d(e, e, np, none, one, Tn, ns, bn, rowP, colQ, st));
-  HIPCHK(c, zcopy2d(e, e, np, none, one, Tn, ns, bn, rowQ, colP, st));
-  HIPCHK(c, zcopy2d(e, e, np, Operand{TQ, pstride, b, lv.E2, lv.E2}, one, Tn, ns, bn, rowQ, colQ, st));
+  const PhysSkip s00 = skip(1, 0, 1, 0), s0e = skip(1, 0, 1, e), se0 = skip(1, e, 1, 0), see = skip(1, e, 1, e);
+  HIPCHK(c, zcopy2d(e, e, np, Operand{TP, pstride, b, lv.E1, lv.E1}, one, Tn, ns, bn, rowP, colP, st, &s00));
+  HIPCHK(c, zcopy2d(e, e, np, none, one, Tn, ns, bn, rowP, colQ, st, &s0e));
+  HIPCHK(c, zcopy2d(e, e, np, none, one, Tn, ns, bn, rowQ, colP, st, &se0));
+  HIPCHK(c, zcopy2d(e, e, np, Operand{TQ, pstride, b, lv.E2, lv.E2}, one, Tn, ns, bn, rowQ, colQ, st, &see));
   {
     GemmArgs g{};
     g.M = e; g.N = 2 * e; g.K = m; g.batch = np;
@@ -346,11 +388,13 @@ hps_status merge_one(hps_problem* p, int l) {
     g.B = Operand{YP, zs, m, im_off(0), im_off(0)};
     g.alpha = one; g.beta = one; g.C = Operand{Tn, ns, bn, rowP, im_tab(mp)};
     g.D = Tn; g.Dstride = ns; g.ldd = bn; g.dr = rowP; g.dc = im_tab(mp);
+    g.skip = s00;
     HIPCHK(c, zgemm(g, st));
     g.A = Operand{TQ, pstride, b, lv.E2, im_off(lv.b0)};
     g.B = Operand{YQ, zs, m, im_off(0), im_off(0)};
     g.C = Operand{Tn, ns, bn, rowQ, im_tab(mp)};
     g.dr = rowQ;
+    g.skip = se0;
     HIPCHK(c, zgemm(g, st));
   }
   return HPS_OK;
@@ -382,19 +426,93 @@ GemvArgs gemv_args(int M, int K, int batch, Operand A, const cd* x, long long xs
   return a;
 }
 
-// x = A^-1 r for every pair: x1 = W^-1 (r1 + T^P_aa r2), x2 = r2 + T^Q_bb x1.
-hps_status pair_solve(hps_problem* p, const Level& lv, const cd* r1, const cd* r2, cd* V1, cd* x1,
-                      cd* x2) {
+bool small_level(const Level& lv) {
+  return lv.pairs >= 128 && lv.m <= 256 && small_level_lds(lv.m, lv.e) <= 64 * 1024;
+}
+
+SmallLevel small_args(hps_problem* p, const Level& lv) {
+  SmallLevel a;
+  a.g = lv.g;
+  a.m = lv.m;
+  a.e = lv.e;
+  a.a0 = lv.a0;
+  a.b0 = lv.b0;
+  a.E1 = lv.E1;
+  a.E2 = lv.E2;
+  a.T = Tlev(p, lv.g.level);
+  a.Winv = at<cd>(p, lv.Winv_off);
+  a.R1 = at<cd>(p, lv.R1_off);
+  a.R2 = at<cd>(p, lv.R2_off);
+  return a;
+}
+
+VecIn vin_compact(const cd* ptr, long long stride) {
+  VecIn v{};
+  v.p = ptr;
+  v.stride = stride;
+  return v;
+}
+VecIn vin_gather(const cd* vec, const Geom& g, int which, IdxMap local, bool partner) {
+  VecIn v{};
+  v.vec = vec;
+  v.g = g;
+  v.which = which;
+  v.local = local;
+  v.partner = partner ? 1 : 0;
+  return v;
+}
+VecOut vout_compact(cd* ptr, long long stride, const cd* y0 = nullptr, long long y0s = 0) {
+  VecOut v{};
+  v.p = ptr;
+  v.stride = stride;
+  v.y0 = y0;
+  v.y0stride = y0s;
+  v.beta = cmk(1, 0);
+  return v;
+}
+void vout_scatter(VecOut& v, cd* vec, const Geom& g, int which, IdxMap local, bool partner, bool add) {
+  v.vec = vec;
+  v.g = g;
+  v.which = which;
+  v.local = local;
+  v.partner = partner ? 1 : 0;
+  v.add = add ? 1 : 0;
+}
+GemvDesc gdesc(int M, int K, Operand A, VecIn x, VecOut y, cd alpha = cmk(1, 0)) {
+  GemvDesc d{};
+  d.M = M;
+  d.K = K;
+  d.A = A;
+  d.alpha = alpha;
+  d.x = x;
+  d.y = y;
+  return d;
+}
+
+// Shared-face solve x = A^-1 r for every pair of a level, r = (r1 at Q.beta,
+// r2 at P.alpha) compact: x1 = W^-1 (r1 + T^P_aa r2), x2 = r2 + T^Q_bb x1.
+// x1 and x2 go to compact buffers and, when zout != null, into zout at Q.beta
+// and P.alpha.
+hps_status pair_solve(hps_problem* p, const Level& lv, const cd* r1, const cd* r2, cd* V1, cd* x1, cd* x2,
+                      cd* zout) {
   hps_ctx* c = p->ctx;
   hipStream_t st = c->stream;
   const int b = lv.g.b, m = lv.m, np = lv.pairs;
   const long long ps = 2LL * b * b;
   const cd* T = Tlev(p, lv.g.level);
-  HIPCHK(c, zgemv(gemv_args(m, m, np, Operand{T, ps, b, im_off(lv.a0), im_off(lv.a0)}, r2, m, V1, m, r1, m), st));
-  HIPCHK(c, zgemv(gemv_args(m, m, np, Operand{at<cd>(p, lv.Winv_off), (long long)m * m, m, im_off(0), im_off(0)},
-                            V1, m, x1, m), st));
-  HIPCHK(c, zgemv(gemv_args(m, m, np, Operand{T + (size_t)b * b, ps, b, im_off(lv.b0), im_off(lv.b0)}, x1, m, x2,
-                            m, r2, m), st));
+  cd* part = at<cd>(p, p->lay.gpart_off);
+  GemvDesc d = gdesc(m, m, Operand{T, ps, b, im_off(lv.a0), im_off(lv.a0)}, vin_compact(r2, m),
+                     vout_compact(V1, m, r1, m));
+  HIPCHK(c, zgemv_batched(&d, 1, np, part, st));
+  VecOut o1 = vout_compact(x1, m);
+  if (zout) vout_scatter(o1, zout, lv.g, 1, im_off(lv.b0), false, false);
+  d = gdesc(m, m, Operand{at<cd>(p, lv.Winv_off), (long long)m * m, m, im_off(0), im_off(0)},
+            vin_compact(V1, m), o1);
+  HIPCHK(c, zgemv_batched(&d, 1, np, part, st));
+  VecOut o2 = vout_compact(x2, m, r2, m);
+  if (zout) vout_scatter(o2, zout, lv.g, 0, im_off(lv.a0), false, false);
+  d = gdesc(m, m, Operand{T + (size_t)b * b, ps, b, im_off(lv.b0), im_off(lv.b0)}, vin_compact(x1, m), o2);
+  HIPCHK(c, zgemv_batched(&d, 1, np, part, st));
   return HPS_OK;
 }
 
@@ -402,6 +520,10 @@ hps_status vcycle_down(hps_problem* p, int l, cd* wv) {
   hps_ctx* c = p->ctx;
   hipStream_t st = c->stream;
   const Level& lv = p->lay.lev[l];
+  if (small_level(lv)) {
+    HIPCHK(c, vc_down_small(small_args(p, lv), lv.pairs, wv, st));
+    return HPS_OK;
+  }
   const int b = lv.g.b, m = lv.m, e = lv.e, np = lv.pairs;
   const long long ps = 2LL * b * b;
   const cd* T = Tlev(p, l);
@@ -410,12 +532,16 @@ hps_status vcycle_down(hps_problem* p, int l, cd* wv) {
   VTmp t = vtmp(p);
   HIPCHK(c, pair_gather(lv.g, np, 1, im_off(lv.b0), m, wv, R1, m, false, st));
   HIPCHK(c, pair_gather(lv.g, np, 0, im_off(lv.a0), m, wv, R2, m, false, st));
-  hps_status s = pair_solve(p, lv, R1, R2, t.V1, t.X1, t.X2);
+  hps_status s = pair_solve(p, lv, R1, R2, t.V1, t.X1, t.X2, nullptr);
   if (s != HPS_OK) return s;
-  HIPCHK(c, zgemv(gemv_args(e, m, np, Operand{T, ps, b, lv.E1, im_off(lv.a0)}, t.X2, m, t.DP, e), st));
-  HIPCHK(c, zgemv(gemv_args(e, m, np, Operand{T + (size_t)b * b, ps, b, lv.E2, im_off(lv.b0)}, t.X1, m, t.DQ, e), st));
-  HIPCHK(c, pair_scatter(lv.g, np, 0, lv.E1, e, t.DP, e, wv, true, true, st));
-  HIPCHK(c, pair_scatter(lv.g, np, 1, lv.E2, e, t.DQ, e, wv, true, true, st));
+  // deposits C~ x0 into the rows of the kept faces: w[Pi(P.E1)] += T^P_{E1,a} x2,
+  // w[Pi(Q.E2)] += T^Q_{E2,b} x1
+  VecOut oP{}, oQ{};
+  vout_scatter(oP, wv, lv.g, 0, lv.E1, true, true);
+  vout_scatter(oQ, wv, lv.g, 1, lv.E2, true, true);
+  GemvDesc d[2] = {gdesc(e, m, Operand{T, ps, b, lv.E1, im_off(lv.a0)}, vin_compact(t.X2, m), oP),
+                   gdesc(e, m, Operand{T + (size_t)b * b, ps, b, lv.E2, im_off(lv.b0)}, vin_compact(t.X1, m), oQ)};
+  HIPCHK(c, zgemv_batched(d, 2, np, at<cd>(p, p->lay.gpart_off), st));
   return HPS_OK;
 }
 
@@ -423,31 +549,24 @@ hps_status vcycle_up(hps_problem* p, int l, cd* z) {
   hps_ctx* c = p->ctx;
   hipStream_t st = c->stream;
   const Level& lv = p->lay.lev[l];
+  if (small_level(lv)) {
+    HIPCHK(c, vc_up_small(small_args(p, lv), lv.pairs, z, st));
+    return HPS_OK;
+  }
   const int b = lv.g.b, m = lv.m, e = lv.e, np = lv.pairs;
   const long long ps = 2LL * b * b;
   const cd* T = Tlev(p, l);
   const cd* R1 = at<cd>(p, lv.R1_off);
   const cd* R2 = at<cd>(p, lv.R2_off);
   VTmp t = vtmp(p);
-  HIPCHK(c, pair_gather(lv.g, np, 0, lv.E1, e, z, t.DP, e, false, st));
-  HIPCHK(c, pair_gather(lv.g, np, 1, lv.E2, e, z, t.DQ, e, false, st));
-  // r' = r_x + B y:  r1' = r1 + T^P_{a,E1} y_P,  r2' = r2 + T^Q_{b,E2} y_Q
-  cd* A1 = t.X1;
-  cd* A2 = t.X2;
-  HIPCHK(c, zgemv(gemv_args(m, e, np, Operand{T, ps, b, im_off(lv.a0), lv.E1}, t.DP, e, A1, m, R1, m), st));
-  HIPCHK(c, zgemv(gemv_args(m, e, np, Operand{T + (size_t)b * b, ps, b, im_off(lv.b0), lv.E2}, t.DQ, e, A2, m, R2, m),
-                  st));
-  // x = A^-1 r'
-  HIPCHK(c, zgemv(gemv_args(m, m, np, Operand{T, ps, b, im_off(lv.a0), im_off(lv.a0)}, A2, m, t.V1, m, A1, m), st));
-  HIPCHK(c, zgemv(gemv_args(m, m, np, Operand{at<cd>(p, lv.Winv_off), (long long)m * m, m, im_off(0), im_off(0)},
-                            t.V1, m, t.X1, m), st));
-  HIPCHK(c, zgemv(gemv_args(m, m, np, Operand{T + (size_t)b * b, ps, b, im_off(lv.b0), im_off(lv.b0)}, t.X1, m,
-                            t.X2, m, t.X2, m), st));
-  HIPCHK(c, pair_scatter(lv.g, np, 1, im_off(lv.b0), m, t.X1, m, z, false, false, st));
-  HIPCHK(c, pair_scatter(lv.g, np, 0, im_off(lv.a0), m, t.X2, m, z, false, false, st));
-  return HPS_OK;
+  // r' = r_x + B y with y the kept-face data already in z
+  GemvDesc d[2] = {gdesc(m, e, Operand{T, ps, b, im_off(lv.a0), lv.E1}, vin_gather(z, lv.g, 0, lv.E1, false),
+                         vout_compact(t.DP, m, R1, m)),
+                   gdesc(m, e, Operand{T + (size_t)b * b, ps, b, im_off(lv.b0), lv.E2},
+                         vin_gather(z, lv.g, 1, lv.E2, false), vout_compact(t.DQ, m, R2, m))};
+  HIPCHK(c, zgemv_batched(d, 2, np, at<cd>(p, p->lay.gpart_off), st));
+  return pair_solve(p, lv, t.DP, t.DQ, t.V1, t.X1, t.X2, z);
 }
-
 cd* workv(hps_problem* p, int i) {
   return reinterpret_cast<cd*>(p->ws + p->lay.work_off + i * up256(sizeof(cd) * (size_t)p->lay.nslots));
 }
@@ -468,6 +587,36 @@ hps_status cgs2(hps_problem* p, const cd* V, long long vstride, int nv, cd* w, l
   return HPS_OK;
 }
 
+// Coarse matvec w = M_L v on compact coarse vectors.  At the top level the
+// coarse system is the single pair's A_L; with the compact order [P.alpha; Q.beta]
+// it reads [v_P - T^Q_bb v_Q ; v_Q - T^P_aa v_P].  Below the top, the level-L
+// skeleton matvec runs on canonical scratch vectors.
+hps_status coarse_matvec(hps_problem* p, const cd* v, cd* w) {
+  hps_ctx* c = p->ctx;
+  hipStream_t st = c->stream;
+  const Layout& lay = p->lay;
+  const Level& top = lay.lev[lay.L];
+  if (lay.L == lay.Lmax) {
+    const int b = top.g.b;
+    const int m = lay.nL / 2;
+    const cd* T = Tlev(p, lay.L);
+    const int aP = top.g.off[3], bQ = top.g.off[2];   // P's top side, Q's bottom side
+    GemvDesc d[2] = {gdesc(m, m, Operand{T + (size_t)b * b, 0, b, im_off(bQ), im_off(bQ)}, vin_compact(v + m, 0),
+                           vout_compact(w, 0, v, 0), cmk(-1, 0)),
+                     gdesc(m, m, Operand{T, 0, b, im_off(aP), im_off(aP)}, vin_compact(v, 0),
+                           vout_compact(w + m, 0, v + m, 0), cmk(-1, 0))};
+    HIPCHK(c, zgemv_batched(d, 2, 1, at<cd>(p, lay.gpart_off), st));
+    return HPS_OK;
+  }
+  const int* idx = at<int>(p, lay.cidx_off);
+  cd* u1 = workv(p, 2);
+  cd* u2 = workv(p, 3);
+  HIPCHK(c, index_scatter(idx, lay.nL, v, u1, st));
+  HIPCHK(c, skeleton_apply(top.g, Tlev(p, lay.L), u1, u2, false, st));
+  HIPCHK(c, index_gather(idx, lay.nL, u2, w, st));
+  return HPS_OK;
+}
+
 // Coarse solve at level L on the level-L unknowns held in wv; result into z.
 hps_status coarse_solve(hps_problem* p, cd* wv, cd* z) {
   hps_ctx* c = p->ctx;
@@ -481,11 +630,7 @@ hps_status coarse_solve(hps_problem* p, cd* wv, cd* z) {
     cd* R2 = at<cd>(p, top.R2_off);
     HIPCHK(c, pair_gather(top.g, 1, 1, im_off(top.b0), m, wv, R1, m, false, st));
     HIPCHK(c, pair_gather(top.g, 1, 0, im_off(top.a0), m, wv, R2, m, false, st));
-    hps_status s = pair_solve(p, top, R1, R2, t.V1, t.X1, t.X2);
-    if (s != HPS_OK) return s;
-    HIPCHK(c, pair_scatter(top.g, 1, 1, im_off(top.b0), m, t.X1, m, z, false, false, st));
-    HIPCHK(c, pair_scatter(top.g, 1, 0, im_off(top.a0), m, t.X2, m, z, false, false, st));
-    return HPS_OK;
+    return pair_solve(p, top, R1, R2, t.V1, t.X1, t.X2, z);
   }
   const int nL = lay.nL, k = lay.k;
   if (nL == 0) return HPS_OK;
@@ -495,21 +640,17 @@ hps_status coarse_solve(hps_problem* p, cd* wv, cd* z) {
   cd* x = at<cd>(p, lay.cx_off);
   cd* H = at<cd>(p, lay.cH_off);
   cd* y = at<cd>(p, lay.cy_off);
-  cd* sc = at<cd>(p, lay.cs_off);  // [0]: beta^2, [1]: |w|^2, [2..]: scratch
+  cd* sc = at<cd>(p, lay.cs_off);  // [0]: beta^2, [1]: |w|^2
   cd* h2 = at<cd>(p, lay.hh_off);
   cd* part = at<cd>(p, lay.part_off);
-  cd* u1 = workv(p, 2);
-  cd* u2 = workv(p, 3);
-  const cd* TL = Tlev(p, lay.L);
   HIPCHK(c, index_gather(idx, nL, wv, w, st));
   HIPCHK(c, multi_dot(w, 0, 1, w, nL, part, sc, false, st));
   HIPCHK(c, normalize(w, sc, V, nL, nullptr, st));
   HIPCHK(c, vfill(H, (long long)(k + 1) * k, cmk(0, 0), st));
   for (int j = 0; j < k; ++j) {
-    HIPCHK(c, index_scatter(idx, nL, V + (size_t)j * nL, u1, st));
-    HIPCHK(c, skeleton_apply(top.g, TL, u1, u2, false, st));
-    HIPCHK(c, index_gather(idx, nL, u2, w, st));
-    hps_status s = cgs2(p, V, nL, j + 1, w, nL, H + (size_t)j * (k + 1), h2);
+    hps_status s = coarse_matvec(p, V + (size_t)j * nL, w);
+    if (s != HPS_OK) return s;
+    s = cgs2(p, V, nL, j + 1, w, nL, H + (size_t)j * (k + 1), h2);
     if (s != HPS_OK) return s;
     HIPCHK(c, multi_dot(w, 0, 1, w, nL, part, sc + 1, false, st));
     HIPCHK(c, normalize(w, sc + 1, V + (size_t)(j + 1) * nL, nL, H + (size_t)j * (k + 1) + j + 1, st));
@@ -539,6 +680,50 @@ hps_status precond_one(hps_problem* p, const cd* r, cd* z) {
     if (s != HPS_OK) return s;
   }
   return HPS_OK;
+}
+
+// The V-cycle is a fixed sequence of launches for a given problem, so it is
+// captured once into a HIP graph (reading work vector 5, writing work vector 6)
+// and replayed; this removes the host launch cost of ~10^2 small kernels per
+// application.  The graph holds no memset nodes and no host synchronisation.
+hps_status precond_graphed(hps_problem* p, const cd* r, cd* z) {
+  hps_ctx* c = p->ctx;
+  const long long n = p->lay.nslots;
+  cd* rin = workv(p, 5);
+  cd* zout = workv(p, 6);
+  if (!p->pgraph && !p->graph_failed) {
+    if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    // run once eagerly so that every kernel attribute is set outside the capture
+    HIPCHK(c, vcopy(r, rin, n, c->stream));
+    hps_status s = precond_one(p, rin, zout);
+    if (s != HPS_OK) return s;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    hipStream_t saved = c->stream;
+    c->stream = c->cap_stream;
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed);
+    if (e == hipSuccess) {
+      s = precond_one(p, rin, zout);
+      e = hipStreamEndCapture(c->stream, &graph);
+    }
+    c->stream = saved;
+    if (e == hipSuccess && s == HPS_OK && graph) e = hipGraphInstantiate(&p->pgraph, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (e != hipSuccess || s != HPS_OK || !p->pgraph) {
+      p->pgraph = nullptr;
+      p->graph_failed = true;
+      (void)hipGetLastError();
+    }
+  }
+  if (!p->pgraph) return precond_one(p, r, z);
+  HIPCHK(c, vcopy(r, rin, n, c->stream));
+  HIPCHK(c, hipGraphLaunch(p->pgraph, c->stream));
+  HIPCHK(c, vcopy(zout, z, n, c->stream));
+  return HPS_OK;
+}
+
+hps_status precond_any(hps_problem* p, const cd* r, cd* z) {
+  return p->ctx->use_graphs ? precond_graphed(p, r, z) : precond_one(p, r, z);
 }
 
 hps_status check_ready(hps_problem* p, bool need_merges) {
@@ -611,7 +796,7 @@ hps_status fgmres_one(hps_problem* p, const cd* rhs, cd* g, double tol, int maxi
     gv[0] = beta;
     int jend = 0;
     for (int j = 0; j < R; ++j) {
-      hps_status s = precond_one(p, V + j * vb, Z + j * vb);
+      hps_status s = precond_any(p, V + j * vb, Z + j * vb);
       if (s != HPS_OK) return s;
       HIPCHK(c, skeleton_apply(g1, T1, Z + j * vb, w, true, st));
       s = cgs2(p, V, n, j + 1, w, n, hcol, h2);
@@ -675,8 +860,18 @@ hps_status hps_ctx_create(void* hip_stream, hps_ctx** out) {
 }
 
 hps_status hps_ctx_destroy(hps_ctx* ctx) {
+  if (ctx && ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   delete ctx;
   return HPS_OK;
+}
+
+hps_status hps_set_option(hps_ctx* ctx, int32_t option, int32_t value) {
+  if (!ctx) return HPS_ERR_ARG;
+  if (option == HPS_OPT_GRAPHS) {
+    ctx->use_graphs = value ? 1 : 0;
+    return HPS_OK;
+  }
+  return fail(ctx, HPS_ERR_ARG, "unknown option");
 }
 
 const char* hps_last_error(const hps_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
@@ -779,13 +974,22 @@ hps_status hps_problem_create(hps_ctx* ctx, const hps_desc* desc, void* workspac
   }
   const cd one = cmk(1, 0);
   HIPCHK(ctx, hipMemcpy(p->ws + lay.one_off, &one, sizeof(cd), hipMemcpyHostToDevice));
+  // Box maps of merged levels: entries on physical sides are never computed;
+  // they are kept at zero so that products with zero data stay zero.
+  for (int l = 2; l <= lay.L; ++l) {
+    const Level& lv = lay.lev[l];
+    HIPCHK(ctx, vfill(Tlev(p, l), (long long)lv.g.nboxes * lv.g.b * lv.g.b, cmk(0, 0), ctx->stream));
+  }
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
   int zero4[4] = {0, 0, 0, 0};
   HIPCHK(ctx, hipMemcpy(p->ws + lay.flag_off, zero4, sizeof(zero4), hipMemcpyHostToDevice));
+
   *out = p;
   return HPS_OK;
 }
 
 hps_status hps_problem_destroy(hps_problem* p) {
+  if (p && p->pgraph) (void)hipGraphExecDestroy(p->pgraph);
   delete p;
   return HPS_OK;
 }
@@ -890,7 +1094,7 @@ hps_status hps_precond_apply(hps_problem* const* pp, int32_t count, const double
     hps_problem* p = pp[i];
     hps_status s = check_ready(p, true);
     if (s != HPS_OK) return s;
-    s = precond_one(p, reinterpret_cast<const cd*>(r[i]), reinterpret_cast<cd*>(z[i]));
+    s = precond_any(p, reinterpret_cast<const cd*>(r[i]), reinterpret_cast<cd*>(z[i]));
     if (s != HPS_OK) return s;
   }
   return HPS_OK;

@@ -38,11 +38,11 @@ struct IdxMap {
 __device__ inline int imap(const IdxMap& m, int i) {
   return m.map ? m.map[i] : m.off + i + (i >= m.gap_start ? m.gap_len : 0);
 }
-inline IdxMap im_off(int off) { return IdxMap{nullptr, off, 1 << 30, 0}; }
-inline IdxMap im_gap(int off, int gap_start, int gap_len) {
+__host__ __device__ inline IdxMap im_off(int off) { return IdxMap{nullptr, off, 1 << 30, 0}; }
+__host__ __device__ inline IdxMap im_gap(int off, int gap_start, int gap_len) {
   return IdxMap{nullptr, off, gap_start, gap_len};
 }
-inline IdxMap im_tab(const int* tab) { return IdxMap{tab, 0, 1 << 30, 0}; }
+__host__ __device__ inline IdxMap im_tab(const int* tab) { return IdxMap{tab, 0, 1 << 30, 0}; }
 
 // ---------------------------------------------------------------------------
 // Merge-tree geometry.  Level l (1-based) boxes are wx x wy elements with

@@ -31,9 +31,27 @@ __global__ __launch_bounds__(64 * WM * WN) void zgemm_kernel(GemmArgs a) {
   const int tilesM = (a.M + BM - 1) / BM;
   const int m0 = (blockIdx.x % tilesM) * BM;
   const int n0 = (blockIdx.x / tilesM) * BN;
+  const int tid = threadIdx.x;
+  if (a.skip.enabled) {
+    __shared__ int live_r, live_c;
+    int bx, by;
+    box_xy(a.skip.g, b, bx, by);
+    if (tid == 0) {
+      live_r = a.skip.row_y ? 0 : 1;
+      live_c = a.skip.col_y ? 0 : 1;
+    }
+    __syncthreads();
+    if (a.skip.row_y && tid < BM && m0 + tid < a.M &&
+        !y_physical(a.skip, bx, by, m0 + tid + a.skip.row_off))
+      live_r = 1;
+    if (a.skip.col_y && tid < BN && n0 + tid < a.N &&
+        !y_physical(a.skip, bx, by, n0 + tid + a.skip.col_off))
+      live_c = 1;
+    __syncthreads();
+    if (!live_r || !live_c) return;
+  }
   const cd* Ab = a.A.base + (long long)b * a.A.bstride;
   const cd* Bb = a.B.base + (long long)b * a.B.bstride;
-  const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave % WM, wn = wave / WM;
   const int lr = lane & 15, lk = lane >> 4;
@@ -107,12 +125,17 @@ __global__ __launch_bounds__(64 * WM * WN) void zgemm_kernel(GemmArgs a) {
 }
 
 __global__ void zcopy2d_kernel(int M, int N, Operand S, cd alpha, cd* D, long long Dstride, int ldd,
-                               IdxMap dr, IdxMap dc) {
+                               IdxMap dr, IdxMap dc, PhysSkip skip) {
   const int b = blockIdx.y;
   const long long total = (long long)M * N;
+  int bx = 0, by = 0;
+  if (skip.enabled) box_xy(skip.g, b, bx, by);
   for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
        idx += (long long)gridDim.x * blockDim.x) {
     const int i = (int)(idx % M), j = (int)(idx / M);
+    if (skip.enabled && ((skip.row_y && y_physical(skip, bx, by, i + skip.row_off)) ||
+                         (skip.col_y && y_physical(skip, bx, by, j + skip.col_off))))
+      continue;
     cd v = cmk(0.0, 0.0);
     if (S.base) v = cmul(alpha, S.base[(long long)b * S.bstride + (long long)imap(S.c, j) * S.ld + imap(S.r, i)]);
     D[(long long)b * Dstride + (long long)imap(dc, j) * ldd + imap(dr, i)] = v;
@@ -137,12 +160,14 @@ hipError_t zgemm(const GemmArgs& a, hipStream_t st) {
 }
 
 hipError_t zcopy2d(int M, int N, int batch, const Operand& S, cd alpha, cd* D, long long Dstride,
-                   int ldd, IdxMap dr, IdxMap dc, hipStream_t st) {
+                   int ldd, IdxMap dr, IdxMap dc, hipStream_t st, const PhysSkip* skip) {
+  PhysSkip none{};
+  const PhysSkip sk = skip ? *skip : none;
   if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
   const long long total = (long long)M * N;
   int blocks = (int)std::min<long long>((total + 255) / 256, 1024);
   hipLaunchKernelGGL(zcopy2d_kernel, dim3(blocks, batch), dim3(256), 0, st, M, N, S, alpha, D,
-                     Dstride, ldd, dr, dc);
+                     Dstride, ldd, dr, dc, sk);
   return hipPeekAtLastError();
 }
 

@@ -1,0 +1,76 @@
+// Internal declarations of the V-cycle streaming kernels (gemv.hip).
+#pragma once
+#include "host.h"
+
+namespace hps {
+
+constexpr int kGemvMaxDesc = 4;          // GEMVs fused into one launch
+constexpr int kGemvKChunkMax = 2048;     // K entries staged in LDS per split
+constexpr int kGemvTargetBlocks = 1024;  // split-K aims at this many workgroups
+
+// Source of a GEMV's x vector for batch entry (pair) b: a compact array
+// p[b*stride + k], or the canonical vector gathered at the slots of box
+// 2b + which (box-local index local(k)), optionally across the face; physical
+// entries read as 0.
+struct VecIn {
+  const cd* p;
+  long long stride;
+  const cd* vec;
+  Geom g;
+  int which;
+  IdxMap local;
+  int partner;
+};
+
+// Destination of y = alpha A x (+ beta y0): a compact array and/or a scatter into
+// the canonical vector (assign or add; physical entries skipped).
+struct VecOut {
+  cd* p;
+  long long stride;
+  const cd* y0;
+  long long y0stride;
+  cd beta;
+  cd* vec;
+  Geom g;
+  int which;
+  IdxMap local;
+  int partner;
+  int add;
+};
+
+struct GemvDesc {
+  int M, K;
+  Operand A;
+  cd alpha;
+  VecIn x;
+  VecOut y;
+};
+
+struct GemvBatch {
+  GemvDesc d[kGemvMaxDesc];
+  int nsplit[kGemvMaxDesc];
+  long long poff[kGemvMaxDesc];   // partial-sum offsets
+  int batch;
+};
+
+int gemv_nsplit(int M, int K, int batch);
+size_t gemv_partial_elems(const GemvDesc* d, int nd, int batch);
+// nd GEMVs of the same batch size in one launch, plus one reduction launch when
+// any of them is split along K (partial: gemv_partial_elems(d, nd, batch) entries).
+hipError_t zgemv_batched(const GemvDesc* d, int nd, int batch, cd* partial, hipStream_t st);
+
+// One V-cycle level with one workgroup per pair (levels with many small pairs).
+struct SmallLevel {
+  Geom g;
+  int m, e, a0, b0;
+  IdxMap E1, E2;
+  const cd* T;
+  const cd* Winv;
+  cd* R1;
+  cd* R2;
+};
+size_t small_level_lds(int m, int e);
+hipError_t vc_down_small(const SmallLevel& a, int pairs, cd* vec, hipStream_t st);
+hipError_t vc_up_small(const SmallLevel& a, int pairs, cd* z, hipStream_t st);
+
+}  // namespace hps

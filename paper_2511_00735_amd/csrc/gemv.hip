@@ -1,0 +1,289 @@
+// Streaming kernels of the multigrid V-cycle (Sec. 4.3): batched split-K complex
+// GEMVs with the gathers from / scatters to the canonical skeleton vector fused
+// into their load and store paths, and one-workgroup-per-pair kernels that run a
+// whole level of the V-cycle for levels with many small pairs.
+//
+// All of this is HBM-bound: every stored operator is read once per application,
+// 16 bytes per complex entry, with column-major tiles read 64 rows at a time so
+// that a wavefront loads 1 KB contiguous per column.
+#include "common.h"
+#include "gemv.h"
+
+namespace hps {
+
+namespace {
+
+constexpr int kRowsT = 64;   // rows per tile (one per lane)
+constexpr int kThreads = 256;
+
+__device__ inline cd load_x(const VecIn& x, int b, int k) {
+  if (x.p) return x.p[(long long)b * x.stride + k];
+  int bx, by;
+  box_xy(x.g, 2 * b + x.which, bx, by);
+  const int lk = imap(x.local, k);
+  if (side_physical(x.g, bx, by, side_of(x.g, lk))) return cmk(0.0, 0.0);
+  int s = box_slot(x.g, bx, by, lk);
+  if (x.partner) s = slot_partner(x.g.n, x.g.p, s);
+  return x.vec[s];
+}
+
+__device__ inline void store_y(const VecOut& y, int b, int i, cd v) {
+  if (y.y0) v = cfma(y.beta, y.y0[(long long)b * y.y0stride + i], v);
+  if (y.p) y.p[(long long)b * y.stride + i] = v;
+  if (y.vec) {
+    int bx, by;
+    box_xy(y.g, 2 * b + y.which, bx, by);
+    const int lk = imap(y.local, i);
+    if (side_physical(y.g, bx, by, side_of(y.g, lk))) return;
+    int s = box_slot(y.g, bx, by, lk);
+    if (y.partner) s = slot_partner(y.g.n, y.g.p, s);
+    y.vec[s] = y.add ? cadd(y.vec[s], v) : v;
+  }
+}
+
+// grid: x = row tile * nsplit (flattened), y = batch, z = descriptor.
+__global__ __launch_bounds__(kThreads) void gemv_kernel(GemvBatch gb, cd* partial) {
+  __shared__ cd xs[kGemvKChunkMax];
+  __shared__ cd red[4][kRowsT];
+  const GemvDesc& d = gb.d[blockIdx.z];
+  const int tiles = (d.M + kRowsT - 1) / kRowsT;
+  const int nsplit = gb.nsplit[blockIdx.z];
+  if ((int)blockIdx.x >= tiles * nsplit) return;
+  const int tile = blockIdx.x % tiles, split = blockIdx.x / tiles;
+  const int b = blockIdx.y;
+  const int kc = (d.K + nsplit - 1) / nsplit;
+  const int k0 = split * kc;
+  const int k1 = min(d.K, k0 + kc);
+  const int t = threadIdx.x, lane = t & 63, grp = t >> 6;
+  for (int k = k0 + t; k < k1; k += kThreads) xs[k - k0] = load_x(d.x, b, k);
+  __syncthreads();
+  const int r = tile * kRowsT + lane;
+  cd acc = cmk(0.0, 0.0);
+  if (r < d.M) {
+    const cd* Ab = d.A.base + (long long)b * d.A.bstride;
+    const long long row = imap(d.A.r, r);
+    int k = k0 + grp;
+    for (; k + 12 < k1; k += 16) {
+      const cd a0 = Ab[(long long)imap(d.A.c, k) * d.A.ld + row];
+      const cd a1 = Ab[(long long)imap(d.A.c, k + 4) * d.A.ld + row];
+      const cd a2 = Ab[(long long)imap(d.A.c, k + 8) * d.A.ld + row];
+      const cd a3 = Ab[(long long)imap(d.A.c, k + 12) * d.A.ld + row];
+      acc = cfma(a0, xs[k - k0], acc);
+      acc = cfma(a1, xs[k + 4 - k0], acc);
+      acc = cfma(a2, xs[k + 8 - k0], acc);
+      acc = cfma(a3, xs[k + 12 - k0], acc);
+    }
+    for (; k < k1; k += 4) acc = cfma(Ab[(long long)imap(d.A.c, k) * d.A.ld + row], xs[k - k0], acc);
+  }
+  red[grp][lane] = acc;
+  __syncthreads();
+  if (nsplit == 1) {
+    if (grp == 0 && r < d.M) {
+      const cd s = cadd(cadd(red[0][lane], red[1][lane]), cadd(red[2][lane], red[3][lane]));
+      store_y(d.y, b, r, cmul(d.alpha, s));
+    }
+    return;
+  }
+  if (grp == 0 && r < d.M) {
+    const cd s = cadd(cadd(red[0][lane], red[1][lane]), cadd(red[2][lane], red[3][lane]));
+    partial[gb.poff[blockIdx.z] + ((long long)split * gb.batch + b) * d.M + r] = s;
+  }
+}
+
+// Sum the split-K partials in split order (deterministic) and apply the epilogue.
+// (A device-scope fence per workgroup to let the last split reduce in place
+// forces an L2 write-back on this chip and costs more than this launch.)
+__global__ void gemv_reduce_kernel(GemvBatch gb, const cd* partial) {
+  const GemvDesc& d = gb.d[blockIdx.z];
+  const int nsplit = gb.nsplit[blockIdx.z];
+  if (nsplit == 1) return;
+  const int b = blockIdx.y;
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < d.M; r += gridDim.x * blockDim.x) {
+    cd s = cmk(0.0, 0.0);
+    for (int q = 0; q < nsplit; ++q)
+      s = cadd(s, partial[gb.poff[blockIdx.z] + ((long long)q * gb.batch + b) * d.M + r]);
+    store_y(d.y, b, r, cmul(d.alpha, s));
+  }
+}
+
+// ---- one workgroup per pair: a whole V-cycle level ---------------------------
+// y[i] = (y0 ? y0[i] : 0) + sum_k A(rm(i), cm(k)) x[k]; x, y0, y in LDS.
+__device__ void wg_gemv(const cd* A, int ld, IdxMap rm, IdxMap cm, int M, int K, const cd* x,
+                        const cd* y0, cd* y, cd* red) {
+  const int t = threadIdx.x;
+  const int RT = M < kRowsT ? M : kRowsT;
+  const int G = kThreads / RT;
+  const int r = t % RT, g = t / RT;
+  for (int r0 = 0; r0 < M; r0 += RT) {
+    const int row = r0 + r;
+    cd acc = cmk(0.0, 0.0);
+    if (g < G && row < M) {
+      const long long ar = imap(rm, row);
+      for (int c = g; c < K; c += G) acc = cfma(A[(long long)imap(cm, c) * ld + ar], x[c], acc);
+    }
+    if (g < G) red[g * RT + r] = acc;
+    __syncthreads();
+    if (t < RT && r0 + t < M) {
+      cd s = y0 ? y0[r0 + t] : cmk(0.0, 0.0);
+      for (int q = 0; q < G; ++q) s = cadd(s, red[q * RT + t]);
+      y[r0 + t] = s;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void vc_down_small_kernel(SmallLevel a, cd* vec) {
+  extern __shared__ cd sm[];
+  const int m = a.m, e = a.e;
+  cd* r1 = sm;
+  cd* r2 = r1 + m;
+  cd* v1 = r2 + m;
+  cd* x1 = v1 + m;
+  cd* x2 = x1 + m;
+  cd* dd = x2 + m;
+  cd* red = dd + e;
+  const int j = blockIdx.x, t = threadIdx.x;
+  const Geom& g = a.g;
+  int px, py, qx, qy;
+  box_xy(g, 2 * j, px, py);
+  box_xy(g, 2 * j + 1, qx, qy);
+  const long long bb = (long long)g.b * g.b;
+  const cd* TP = a.T + (2LL * j) * bb;
+  const cd* TQ = TP + bb;
+  for (int i = t; i < m; i += kThreads) {
+    const cd u = vec[box_slot(g, qx, qy, a.b0 + i)];
+    const cd w = vec[box_slot(g, px, py, a.a0 + i)];
+    r1[i] = u;
+    r2[i] = w;
+    a.R1[(long long)j * m + i] = u;
+    a.R2[(long long)j * m + i] = w;
+  }
+  __syncthreads();
+  wg_gemv(TP, g.b, im_off(a.a0), im_off(a.a0), m, m, r2, r1, v1, red);
+  wg_gemv(a.Winv + (long long)j * m * m, m, im_off(0), im_off(0), m, m, v1, nullptr, x1, red);
+  wg_gemv(TQ, g.b, im_off(a.b0), im_off(a.b0), m, m, x1, r2, x2, red);
+  wg_gemv(TP, g.b, a.E1, im_off(a.a0), e, m, x2, nullptr, dd, red);
+  for (int i = t; i < e; i += kThreads) {
+    const int k = imap(a.E1, i);
+    if (side_physical(g, px, py, side_of(g, k))) continue;
+    const int s = slot_partner(g.n, g.p, box_slot(g, px, py, k));
+    vec[s] = cadd(vec[s], dd[i]);
+  }
+  __syncthreads();
+  wg_gemv(TQ, g.b, a.E2, im_off(a.b0), e, m, x1, nullptr, dd, red);
+  for (int i = t; i < e; i += kThreads) {
+    const int k = imap(a.E2, i);
+    if (side_physical(g, qx, qy, side_of(g, k))) continue;
+    const int s = slot_partner(g.n, g.p, box_slot(g, qx, qy, k));
+    vec[s] = cadd(vec[s], dd[i]);
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void vc_up_small_kernel(SmallLevel a, cd* z) {
+  extern __shared__ cd sm[];
+  const int m = a.m, e = a.e;
+  cd* zp = sm;
+  cd* zq = zp + e;
+  cd* a1 = zq + e;
+  cd* a2 = a1 + m;
+  cd* v1 = a2 + m;
+  cd* x1 = v1 + m;
+  cd* x2 = x1 + m;
+  cd* r1 = x2 + m;
+  cd* r2 = r1 + m;
+  cd* red = r2 + m;
+  const int j = blockIdx.x, t = threadIdx.x;
+  const Geom& g = a.g;
+  int px, py, qx, qy;
+  box_xy(g, 2 * j, px, py);
+  box_xy(g, 2 * j + 1, qx, qy);
+  const long long bb = (long long)g.b * g.b;
+  const cd* TP = a.T + (2LL * j) * bb;
+  const cd* TQ = TP + bb;
+  for (int i = t; i < e; i += kThreads) {
+    const int kp = imap(a.E1, i), kq = imap(a.E2, i);
+    zp[i] = side_physical(g, px, py, side_of(g, kp)) ? cmk(0.0, 0.0) : z[box_slot(g, px, py, kp)];
+    zq[i] = side_physical(g, qx, qy, side_of(g, kq)) ? cmk(0.0, 0.0) : z[box_slot(g, qx, qy, kq)];
+  }
+  for (int i = t; i < m; i += kThreads) {
+    r1[i] = a.R1[(long long)j * m + i];
+    r2[i] = a.R2[(long long)j * m + i];
+  }
+  __syncthreads();
+  wg_gemv(TP, g.b, im_off(a.a0), a.E1, m, e, zp, r1, a1, red);
+  wg_gemv(TQ, g.b, im_off(a.b0), a.E2, m, e, zq, r2, a2, red);
+  wg_gemv(TP, g.b, im_off(a.a0), im_off(a.a0), m, m, a2, a1, v1, red);
+  wg_gemv(a.Winv + (long long)j * m * m, m, im_off(0), im_off(0), m, m, v1, nullptr, x1, red);
+  wg_gemv(TQ, g.b, im_off(a.b0), im_off(a.b0), m, m, x1, a2, x2, red);
+  for (int i = t; i < m; i += kThreads) {
+    z[box_slot(g, qx, qy, a.b0 + i)] = x1[i];
+    z[box_slot(g, px, py, a.a0 + i)] = x2[i];
+  }
+}
+
+}  // namespace
+
+int gemv_nsplit(int M, int K, int batch) {
+  const int tiles = (M + kRowsT - 1) / kRowsT;
+  int ns = (kGemvTargetBlocks + tiles * batch - 1) / (tiles * batch);
+  ns = std::max(1, std::min(ns, (K + 63) / 64));
+  while ((K + ns - 1) / ns > kGemvKChunkMax) ++ns;
+  return ns;
+}
+
+size_t gemv_partial_elems(const GemvDesc* d, int nd, int batch) {
+  size_t tot = 0;
+  for (int i = 0; i < nd; ++i) {
+    const int ns = gemv_nsplit(d[i].M, d[i].K, batch);
+    if (ns > 1) tot += (size_t)ns * batch * d[i].M;
+  }
+  return tot;
+}
+
+hipError_t zgemv_batched(const GemvDesc* d, int nd, int batch, cd* partial, hipStream_t st) {
+  if (nd <= 0 || nd > kGemvMaxDesc || batch <= 0) return hipErrorInvalidValue;
+  GemvBatch gb{};
+  gb.batch = batch;
+  int gx = 0;
+  long long poff = 0;
+  bool any_split = false;
+  for (int i = 0; i < nd; ++i) {
+    gb.d[i] = d[i];
+    const int tiles = (d[i].M + kRowsT - 1) / kRowsT;
+    const int ns = gemv_nsplit(d[i].M, d[i].K, batch);
+    gb.nsplit[i] = ns;
+    gb.poff[i] = poff;
+    if (ns > 1) { poff += (long long)ns * batch * d[i].M; any_split = true; }
+    gx = std::max(gx, tiles * ns);
+  }
+  if (any_split && !partial) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(gemv_kernel, dim3(gx, batch, nd), dim3(kThreads), 0, st, gb, partial);
+  hipError_t err = hipPeekAtLastError();
+  if (err != hipSuccess || !any_split) return err;
+  int maxM = 0;
+  for (int i = 0; i < nd; ++i) maxM = std::max(maxM, d[i].M);
+  hipLaunchKernelGGL(gemv_reduce_kernel, dim3((maxM + 255) / 256, batch, nd), dim3(256), 0, st, gb, partial);
+  return hipPeekAtLastError();
+}
+
+size_t small_level_lds(int m, int e) {
+  return sizeof(cd) * (size_t)(std::max(5 * m + e, 2 * e + 7 * m) + kThreads);
+}
+
+hipError_t vc_down_small(const SmallLevel& a, int pairs, cd* vec, hipStream_t st) {
+  const size_t lds = small_level_lds(a.m, a.e);
+  hipError_t err = allow_lds(vc_down_small_kernel, lds);
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(vc_down_small_kernel, dim3(pairs), dim3(kThreads), lds, st, a, vec);
+  return hipPeekAtLastError();
+}
+
+hipError_t vc_up_small(const SmallLevel& a, int pairs, cd* z, hipStream_t st) {
+  const size_t lds = small_level_lds(a.m, a.e);
+  hipError_t err = allow_lds(vc_up_small_kernel, lds);
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(vc_up_small_kernel, dim3(pairs), dim3(kThreads), lds, st, a, z);
+  return hipPeekAtLastError();
+}
+
+}  // namespace hps

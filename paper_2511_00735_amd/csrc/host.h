@@ -40,6 +40,19 @@ struct Operand {
   int ld;
   IdxMap r, c;
 };
+// Output tiles of a merge whose rows (or columns) all lie on physical sides of
+// the merged box are never needed: the skeleton unknowns are interior
+// impedances only.  Batch entry b writes merged box b of level g.level; a y
+// index i (rows: i + row_off when row_y, columns: j + col_off when col_y) lands
+// at box-local position ymap[i].
+struct PhysSkip {
+  int enabled;
+  Geom g;
+  const int* ymap;
+  int row_y, col_y;
+  int row_off, col_off;
+};
+
 struct GemmArgs {
   int M, N, K, batch;
   Operand A, B;
@@ -51,12 +64,19 @@ struct GemmArgs {
   IdxMap dr, dc;
   cd diag_add;        // added to D(i, i) for i < min(M, N) when has_diag
   int has_diag;
+  PhysSkip skip;
 };
 // D = alpha * A B + beta * C (+ diag_add I), all column-major complex FP64.
 hipError_t zgemm(const GemmArgs& a, hipStream_t st);
 // D(dr(i), dc(j)) = alpha * S(sr(i), sc(j)) (S == null: zero), batched.
 hipError_t zcopy2d(int M, int N, int batch, const Operand& S, cd alpha, cd* D,
-                   long long Dstride, int ldd, IdxMap dr, IdxMap dc, hipStream_t st);
+                   long long Dstride, int ldd, IdxMap dr, IdxMap dc, hipStream_t st,
+                   const PhysSkip* skip = nullptr);
+// true when y index `yi` of merged box (bx, by) lies on a physical side
+__host__ __device__ inline bool y_physical(const PhysSkip& s, int bx, int by, int yi) {
+  const int k = s.ymap[yi];
+  return side_physical(s.g, bx, by, side_of(s.g, k));
+}
 
 // ---- batched complex inversion (inverse.hip) -------------------------------
 // In-place inverse of `batch` m x m column-major matrices (stride `bstride`),

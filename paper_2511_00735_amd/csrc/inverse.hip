@@ -27,9 +27,18 @@ __global__ __launch_bounds__(256) void inv_small_kernel(cd* A, int m, int lda, l
   __shared__ int ipiv[64];
   __shared__ cd colk[64];
   cd* Ab = A + (long long)blockIdx.x * bstride;
-  for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
-    const int r = idx % m, c = idx / m;
-    S[idx] = Ab[(long long)c * lda + r];
+  for (int base = 0; base < m * m; base += 4 * 256) {
+    cd v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = base + q * 256 + threadIdx.x;
+      v[q] = idx < m * m ? Ab[(long long)(idx / m) * lda + idx % m] : cmk(0.0, 0.0);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = base + q * 256 + threadIdx.x;
+      if (idx < m * m) S[idx] = v[q];
+    }
   }
   __syncthreads();
   gj_inplace_small(S, m, ipiv, colk, flag);
@@ -59,20 +68,30 @@ inline BlockScratch carve(void* base, int m, int batch) {
   return s;
 }
 
-// Panel LU (partial pivoting) on a copy of A[k0:m, k0:k0+kb]; records the
-// absolute pivot rows in ipiv[k0 .. k0+kb).
-__global__ __launch_bounds__(256) void panel_pivot_kernel(const cd* A, int m, int lda, long long bstride,
-                                                          int k0, int kb, cd* panel, int* ipiv,
-                                                          int* flag) {
+// Panel LU (partial pivoting) of A[k0:m, k0:k0+kb], held in LDS: records the
+// absolute pivot rows in ipiv[k0 .. k0+kb) and writes Dinv = (L11 U11)^-1, the
+// inverse of the pivot block once its rows are swapped into place.
+__global__ __launch_bounds__(256) void panel_lds_kernel(const cd* A, int m, int lda, long long bstride,
+                                                        int k0, int kb, int* ipiv, cd* dinv, int* flag) {
+  extern __shared__ cd Pn[];          // rows x kb, column-major (ld = rows)
   __shared__ int pr_s;
+  __shared__ cd Li[kNB * kNB];        // L11^-1 (unit lower), column-major kb x kb
   const cd* Ab = A + (long long)blockIdx.x * bstride;
-  cd* Pn = panel + (long long)blockIdx.x * m * kNB;
   int* ip = ipiv + (long long)blockIdx.x * m;
   const int rows = m - k0;
   const int tid = threadIdx.x;
-  for (int idx = tid; idx < rows * kb; idx += blockDim.x) {
-    const int r = idx % rows, c = idx / rows;
-    Pn[(long long)c * m + r] = Ab[(long long)(k0 + c) * lda + k0 + r];
+  for (int base = 0; base < rows * kb; base += 4 * 256) {
+    cd v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = base + q * 256 + tid;
+      v[q] = idx < rows * kb ? Ab[(long long)(k0 + idx / rows) * lda + k0 + idx % rows] : cmk(0.0, 0.0);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = base + q * 256 + tid;
+      if (idx < rows * kb) Pn[(idx / rows) * rows + idx % rows] = v[q];
+    }
   }
   __syncthreads();
   for (int c = 0; c < kb; ++c) {
@@ -80,7 +99,7 @@ __global__ __launch_bounds__(256) void panel_pivot_kernel(const cd* A, int m, in
       double best = -1.0;
       int bi = c;
       for (int r = c + tid; r < rows; r += 64) {
-        const double v = cabs2(Pn[(long long)c * m + r]);
+        const double v = cabs2(Pn[c * rows + r]);
         if (v > best) { best = v; bi = r; }
       }
       for (int off = 32; off > 0; off >>= 1) {
@@ -98,22 +117,51 @@ __global__ __launch_bounds__(256) void panel_pivot_kernel(const cd* A, int m, in
     const int pr = pr_s;
     if (pr != c) {
       for (int j = tid; j < kb; j += blockDim.x) {
-        const cd t = Pn[(long long)j * m + c];
-        Pn[(long long)j * m + c] = Pn[(long long)j * m + pr];
-        Pn[(long long)j * m + pr] = t;
+        const cd t = Pn[j * rows + c];
+        Pn[j * rows + c] = Pn[j * rows + pr];
+        Pn[j * rows + pr] = t;
       }
       __syncthreads();
     }
-    const cd d = Pn[(long long)c * m + c];
+    const cd d = Pn[c * rows + c];
     const cd inv = cabs2(d) > 0.0 ? cinv(d) : cmk(0.0, 0.0);
     for (int r = c + 1 + tid; r < rows; r += blockDim.x) {
-      const cd l = cmul(Pn[(long long)c * m + r], inv);
-      Pn[(long long)c * m + r] = l;
-      for (int j = c + 1; j < kb; ++j)
-        Pn[(long long)j * m + r] = csub(Pn[(long long)j * m + r], cmul(l, Pn[(long long)j * m + c]));
+      const cd l = cmul(Pn[c * rows + r], inv);
+      Pn[c * rows + r] = l;
+      for (int j = c + 1; j < kb; ++j) Pn[j * rows + r] = csub(Pn[j * rows + r], cmul(l, Pn[j * rows + c]));
     }
     __syncthreads();
   }
+  // Li = L11^-1 column by column (unit lower triangular forward substitution)
+  if (tid < kb) {
+    const int j = tid;
+    for (int i = 0; i < kb; ++i) {
+      cd v = (i == j) ? cmk(1.0, 0.0) : cmk(0.0, 0.0);
+      for (int q = j; q < i; ++q) v = csub(v, cmul(Pn[q * rows + i], Li[j * kNB + q]));
+      Li[j * kNB + i] = (i < j) ? cmk(0.0, 0.0) : v;
+    }
+  }
+  __syncthreads();
+  // Dinv = U11^-1 Li: back substitution on each column of Li
+  cd* Db = dinv + (long long)blockIdx.x * kNB * kNB;
+  if (tid < kb) {
+    const int j = tid;
+    cd x[kNB];
+    for (int i = kb - 1; i >= 0; --i) {
+      cd v = Li[j * kNB + i];
+      for (int q = i + 1; q < kb; ++q) v = csub(v, cmul(Pn[q * rows + i], x[q]));
+      const cd u = Pn[i * rows + i];
+      x[i] = cabs2(u) > 0.0 ? cmul(v, cinv(u)) : cmk(0.0, 0.0);
+    }
+    for (int i = 0; i < kb; ++i) Db[j * kb + i] = x[i];
+  }
+}
+
+// Panel width: the panel (m rows x nb complex) must fit in about 123 KB of LDS.
+int panel_width(int m) {
+  int nb = kNB;
+  while (nb > 4 && (size_t)m * nb * sizeof(cd) > 126 * 1024) nb /= 2;
+  return nb;
 }
 
 // Apply the interchanges rows k0+j <-> ipiv[k0+j], j = 0..kb-1, in order, to all columns.
@@ -150,37 +198,21 @@ __global__ void unswap_cols_kernel(cd* A, int m, int lda, long long bstride, con
   }
 }
 
-__global__ __launch_bounds__(256) void diag_inv_kernel(const cd* A, int lda, long long bstride, int k0,
-                                                       int kb, cd* dinv, int* flag) {
-  __shared__ cd S[kNB * kNB];
-  __shared__ int ipiv[64];
-  __shared__ cd colk[64];
-  const cd* Ab = A + (long long)blockIdx.x * bstride;
-  for (int idx = threadIdx.x; idx < kb * kb; idx += blockDim.x) {
-    const int r = idx % kb, c = idx / kb;
-    S[idx] = Ab[(long long)(k0 + c) * lda + k0 + r];
-  }
-  __syncthreads();
-  gj_inplace_small(S, kb, ipiv, colk, flag);
-  cd* Db = dinv + (long long)blockIdx.x * kNB * kNB;
-  for (int idx = threadIdx.x; idx < kb * kb; idx += blockDim.x) Db[idx] = S[idx];
-}
-
 hipError_t inverse_blocked(cd* A, int m, int lda, long long bstride, int batch, void* scratch,
                            int* flag, hipStream_t st) {
   BlockScratch s = carve(scratch, m, batch);
   const cd one = cmk(1.0, 0.0), zero = cmk(0.0, 0.0), mone = cmk(-1.0, 0.0);
   hipError_t err;
-  for (int k0 = 0; k0 < m; k0 += kNB) {
-    const int kb = std::min(kNB, m - k0);
-    hipLaunchKernelGGL(panel_pivot_kernel, dim3(batch), dim3(256), 0, st, A, m, lda, bstride, k0, kb,
-                       s.panel, s.ipiv, flag);
+  const int nbw = panel_width(m);
+  const size_t plds = (size_t)m * nbw * sizeof(cd);
+  if ((err = allow_lds(panel_lds_kernel, plds)) != hipSuccess) return err;
+  for (int k0 = 0; k0 < m; k0 += nbw) {
+    const int kb = std::min(nbw, m - k0);
+    hipLaunchKernelGGL(panel_lds_kernel, dim3(batch), dim3(256), (size_t)(m - k0) * kb * sizeof(cd), st, A,
+                       m, lda, bstride, k0, kb, s.ipiv, s.dinv, flag);
     if ((err = hipPeekAtLastError()) != hipSuccess) return err;
     hipLaunchKernelGGL(swap_rows_kernel, dim3((m + 255) / 256, batch), dim3(256), 0, st, A, m, lda,
                        bstride, k0, kb, s.ipiv);
-    if ((err = hipPeekAtLastError()) != hipSuccess) return err;
-    hipLaunchKernelGGL(diag_inv_kernel, dim3(batch), dim3(256), 0, st, A, lda, bstride, k0, kb,
-                       s.dinv, flag);
     if ((err = hipPeekAtLastError()) != hipSuccess) return err;
     const int mr = m - kb;  // rows / columns outside the block
     if (mr > 0) {

@@ -56,6 +56,7 @@ _SIGS = {
     "hps_ctx_destroy": ([_P], ctypes.c_int),
     "hps_last_error": ([_P], ctypes.c_char_p),
     "hps_sync": ([_P], ctypes.c_int),
+    "hps_set_option": ([_P, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
     "hps_workspace_bytes": ([ctypes.POINTER(Desc), ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "hps_gll_nodes": ([ctypes.c_int32, _P], ctypes.c_int),
     "hps_node_coords": ([ctypes.POINTER(Desc), _P, _P], ctypes.c_int),
@@ -162,6 +163,10 @@ class Context:
 
     def sync(self):
         self.check(lib.hps_sync(self.handle), "hps_sync")
+
+    def set_graphs(self, on):
+        """Replay the V-cycle from a captured HIP graph (default) or launch eagerly."""
+        self.check(lib.hps_set_option(self.handle, 1, 1 if on else 0), "hps_set_option")
 
     def __del__(self):
         if getattr(self, "handle", None):
