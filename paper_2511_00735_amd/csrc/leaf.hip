@@ -258,13 +258,10 @@ hipError_t leaf_build(const LeafArgs& a, hipStream_t st) {
   const size_t lds1 = ((size_t)nloc * kNB + (size_t)kNB * ncol) * sizeof(double);
   hipError_t e0 = allow_lds(leaf_schur_kernel, lds1);
   if (e0 != hipSuccess) return e0;
-  hipError_t e0 = allow_lds(leaf_schur_kernel, lds1);
-  if (e0 != hipSuccess) return e0;
   hipLaunchKernelGGL(leaf_schur_kernel, dim3(a.count), dim3(kThreads), lds1, st, a);
   hipError_t err = hipPeekAtLastError();
   if (err != hipSuccess) return err;
   const size_t lds2 = (size_t)(4 * p) * (4 * p) * sizeof(cd);
-  if ((err = allow_lds(leaf_cayley_kernel, lds2)) != hipSuccess) return err;
   if ((err = allow_lds(leaf_cayley_kernel, lds2)) != hipSuccess) return err;
   hipLaunchKernelGGL(leaf_cayley_kernel, dim3(a.count), dim3(kThreads), lds2, st, a);
   return hipPeekAtLastError();
