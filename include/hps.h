@@ -66,7 +66,12 @@ typedef enum {
 
 typedef enum { HPS_FP64 = 0, HPS_MIXED = 1 } hps_precision;
 
-/* Problem descriptor.  Defaults in brackets. */
+/* Problem descriptor.  Defaults in brackets.
+   Precision HPS_MIXED: the leaf maps are computed in FP64 (they define the outer
+   operator M_1, which must stay FP64 for the outer iteration to refine toward
+   the FP64 solution) and copied to FP32; merges 1..L-3 and the V-cycle on those
+   levels run in complex FP32 (FP32 MFMA, FP64 vectors); merges L-2 and L-1,
+   the coarse solve, Arnoldi and all residuals run in FP64. */
 typedef struct {
   int32_t n;             /* elements per side, power of two, 2 <= n <= 1024   */
   int32_t order;         /* GLL order N, 2 <= N <= 16                          */
@@ -102,7 +107,10 @@ typedef struct {
   int32_t shared_nodes;  /* m = length of the shared face                      */
   const void* Winv;      /* complex [pairs][m][m] column-major: the inverse of
                             W = I - T^P_aa T^Q_bb (the m x m Schur complement
-                            of A = [[I, -T^P_aa], [-T^Q_bb, I]]); FP64        */
+                            of A = [[I, -T^P_aa], [-T^Q_bb, I]])              */
+  int32_t fp32;          /* 1: T and Winv are complex FP32 (mixed precision,
+                            levels 1 .. L-3; level 1 then shows the FP32 copy
+                            used by the preconditioner); 0: complex FP64      */
 } hps_level_view;
 
 /* ---- context ------------------------------------------------------------ */
@@ -156,7 +164,8 @@ hps_status hps_merge_level(hps_problem* const* p, int32_t count, int32_t level);
 hps_status hps_set_rhs(hps_problem* const* p, int32_t count,
                        const double* const* t, double* const* rhs);
 /* out = M_level g (canonical vectors; only level-`level` unknowns are read and
-   written).  Requires the level-`level` box maps. */
+   written).  Requires the level-`level` box maps in FP64 (always true for
+   level 1 and the coarse level; HPS_ERR_ARG for FP32 levels of mixed mode). */
 hps_status hps_skeleton_apply(hps_problem* const* p, int32_t count, int32_t level,
                               const double* const* g, double* const* out);
 /* z = MG(M_1) r, one V-cycle (gamma = 1) with the configured coarse solve

@@ -31,7 +31,9 @@ inline size_t up256(size_t b) { return (b + 255) & ~size_t(255); }
 
 struct Level {
   Geom g;
-  size_t T_off = 0;
+  size_t T_off = 0;     // box maps: complex FP64, or FP32 when f32 (level 1: always FP64)
+  bool f32 = false;     // mixed precision: this level's merge and V-cycle run in FP32
+  size_t T32_off = 0;   // level 1 in mixed mode: FP32 copy of the leaf maps
   // merge of this level's box pairs (level < L, or the top pair in exact mode)
   int pairs = 0, m = 0, e = 0, axis = 0, a0 = 0, b0 = 0;
   IdxMap E1{}, E2{};
@@ -43,7 +45,8 @@ struct Level {
 
 struct Layout {
   int n, N, p, E, L, Lmax, k, restart;
-  bool exact;
+  bool exact, mixed;
+  size_t stage_off = 0;  // FP32 output of the last FP32 merge, widened into FP64 maps
   long long nslots;
   int nL;  // number of coarse unknowns
   int leaf_chunk;
@@ -150,7 +153,7 @@ const char* check_desc(const hps_desc* d) {
   if (d->coarse_iters == -1 && L != Lmax) return "exact coarse solve requires levels = L_max";
   if (d->gamma != 1 && d->gamma != 0) return "only gamma = 1 (V-cycle) is supported";
   if (d->restart < 0 || d->restart > 200) return "restart must be in [1, 200]";
-  if (d->precision != HPS_FP64) return "only HPS_FP64 is supported";
+  if (d->precision != HPS_FP64 && d->precision != HPS_MIXED) return "precision must be HPS_FP64 or HPS_MIXED";
   return nullptr;
 }
 
@@ -163,6 +166,7 @@ Layout make_layout(const hps_desc* d) {
   lay.Lmax = 2 * ilog2(d->n);
   lay.L = d->levels ? d->levels : lay.Lmax;
   lay.exact = (d->coarse_iters == -1);
+  lay.mixed = (d->precision == HPS_MIXED);
   lay.k = lay.exact ? 0 : d->coarse_iters;
   lay.restart = d->restart ? d->restart : 60;
   lay.nslots = (long long)lay.E * 4 * lay.p;
@@ -178,15 +182,21 @@ Layout make_layout(const hps_desc* d) {
   for (int l = 1; l <= lay.L; ++l) {
     Level& lv = lay.lev[l];
     lv = make_level(lay.n, lay.p, l);
-    lv.T_off = take(sizeof(cd) * (size_t)lv.g.nboxes * lv.g.b * lv.g.b);
+    // mixed precision: merges 1 .. L-3 (and the V-cycle on those levels) in FP32,
+    // the top two merges, the coarse level and the outer operator in FP64
+    lv.f32 = lay.mixed && l <= lay.L - 3;
+    const size_t nmap = (size_t)lv.g.nboxes * lv.g.b * lv.g.b;
+    lv.T_off = take((l == 1 || !lv.f32 ? sizeof(cd) : sizeof(cf)) * nmap);
+    if (l == 1 && lv.f32) lv.T32_off = take(sizeof(cf) * nmap);
+    if (lay.mixed && l == lay.L - 2 && l >= 2) lay.stage_off = take(sizeof(cf) * nmap);
     if (l < lay.L || (lay.exact && l == lay.L)) {
       set_merge_geom(lv);
-      lv.Winv_off = take(sizeof(cd) * (size_t)lv.pairs * lv.m * lv.m);
+      lv.Winv_off = take((lv.f32 ? sizeof(cf) : sizeof(cd)) * (size_t)lv.pairs * lv.m * lv.m);
       lv.map_off = take(sizeof(int) * 2 * (size_t)lv.e);
       lv.R1_off = take(sizeof(cd) * (size_t)lv.pairs * lv.m);
       lv.R2_off = take(sizeof(cd) * (size_t)lv.pairs * lv.m);
       const size_t zbytes = sizeof(cd) * (size_t)lv.pairs * lv.m * 2 * lv.e;
-      merge_scratch = std::max(merge_scratch, 3 * up256(zbytes) + up256(inverse_scratch_bytes(lv.m, lv.pairs)));
+      merge_scratch = std::max(merge_scratch, 3 * up256(zbytes) + up256(inverse_scratch_bytes<cd>(lv.m, lv.pairs)));
       lay.vtmp_m = std::max(lay.vtmp_m, (size_t)lv.pairs * lv.m);
       lay.vtmp_e = std::max(lay.vtmp_e, (size_t)lv.pairs * lv.e);
     }
@@ -284,18 +294,22 @@ hps_status fail(hps_ctx* c, hps_status s, const std::string& msg) {
 cd* Tlev(hps_problem* p, int l) { return at<cd>(p, p->lay.lev[l].T_off); }
 
 // ---- merge of one level (1 <= l < L): level-l pairs -> level-(l+1) boxes --
-hps_status merge_one(hps_problem* p, int l) {
+// T is the precision of this merge (complex FP64 or FP32); Tin are the level-l
+// box maps and Tout receives the level-(l+1) maps, both in that precision.
+template <class T>
+hps_status merge_impl(hps_problem* p, int l, const T* Tin, T* Tout) {
+  typedef OperandT<T> Operand;
+  typedef GemmArgsT<T> GemmArgs;
   hps_ctx* c = p->ctx;
   hipStream_t st = c->stream;
   const Layout& lay = p->lay;
   const Level& lv = lay.lev[l];
   const int b = lv.g.b, m = lv.m, e = lv.e, np = lv.pairs;
   const long long pstride = 2LL * b * b;
-  cd* T = Tlev(p, l);
-  const cd* TP = T;
-  const cd* TQ = T + (size_t)b * b;
-  cd* Winv = at<cd>(p, lv.Winv_off);
-  const cd one = cmk(1, 0), zero = cmk(0, 0), mone = cmk(-1, 0);
+  const T* TP = Tin;
+  const T* TQ = Tin + (size_t)b * b;
+  T* Winv = at<T>(p, lv.Winv_off);
+  const T one = cx<T>::make(1, 0), zero = cx<T>::make(0, 0), mone = cx<T>::make(-1, 0);
   const Operand none{nullptr, 0, 0, im_off(0), im_off(0)};
   int* flag = at<int>(p, lay.flag_off);
   // W = I - T^P_aa T^Q_bb
@@ -311,11 +325,11 @@ hps_status merge_one(hps_problem* p, int l) {
   }
   char* scr = at<char>(p, lay.scratch_off);
   const size_t zb = up256(sizeof(cd) * (size_t)np * m * 2 * e);
-  cd* Z = reinterpret_cast<cd*>(scr);
-  cd* YQ = reinterpret_cast<cd*>(scr + zb);
-  cd* YP = reinterpret_cast<cd*>(scr + 2 * zb);
+  T* Z = reinterpret_cast<T*>(scr);
+  T* YQ = reinterpret_cast<T*>(scr + zb);
+  T* YP = reinterpret_cast<T*>(scr + 2 * zb);
   void* invs = scr + 3 * zb;
-  HIPCHK(c, zinverse(Winv, m, m, (long long)m * m, np, invs, flag, st));
+  HIPCHK(c, zinverse<T>(Winv, m, m, (long long)m * m, np, invs, flag, st));
   if (l == lay.L) return HPS_OK;  // exact top: only W^-1 is needed
   const long long zs = (long long)m * 2 * e;
   const Level& nx = lay.lev[l + 1];
@@ -372,7 +386,7 @@ hps_status merge_one(hps_problem* p, int l) {
     HIPCHK(c, zgemm(g, st));
   }
   // T_new = blkdiag(T^P_E1E1, T^Q_E2E2) + [T^P_{E1,a} YP ; T^Q_{E2,b} YQ], scattered
-  cd* Tn = Tlev(p, l + 1);
+  T* Tn = Tout;
   const int bn = nx.g.b;
   const long long ns = (long long)bn * bn;
   const IdxMap rowP = im_tab(mp), rowQ = im_tab(mp + e), colP = im_tab(mp), colQ = im_tab(mp + e);
@@ -400,6 +414,28 @@ hps_status merge_one(hps_problem* p, int l) {
   return HPS_OK;
 }
 
+template <class M>
+M* Tmat(hps_problem* p, int l) {
+  const Level& lv = p->lay.lev[l];
+  return at<M>(p, (l == 1 && lv.f32) ? lv.T32_off : lv.T_off);
+}
+
+hps_status merge_one(hps_problem* p, int l) {
+  const Layout& lay = p->lay;
+  const Level& lv = lay.lev[l];
+  if (!lv.f32) {
+    cd* out = (l < lay.L) ? Tlev(p, l + 1) : nullptr;
+    return merge_impl<cd>(p, l, Tlev(p, l), out);
+  }
+  const Level& nx = lay.lev[l + 1];
+  cf* out = nx.f32 ? at<cf>(p, nx.T_off) : at<cf>(p, lay.stage_off);
+  hps_status s = merge_impl<cf>(p, l, Tmat<cf>(p, l), out);
+  if (s != HPS_OK || nx.f32) return s;
+  // the next merge runs in FP64: widen the level-(l+1) maps
+  HIPCHK(p->ctx, convert_c32_c64(out, Tlev(p, l + 1), (long long)nx.g.nboxes * nx.g.b * nx.g.b, p->ctx->stream));
+  return HPS_OK;
+}
+
 // ---- V-cycle -------------------------------------------------------------
 struct VTmp {
   cd *V1, *X1, *X2, *DP, *DQ;
@@ -416,22 +452,13 @@ VTmp vtmp(hps_problem* p) {
   return t;
 }
 
-GemvArgs gemv_args(int M, int K, int batch, Operand A, const cd* x, long long xs, cd* y, long long ys,
-                   const cd* y0 = nullptr, long long y0s = 0) {
-  GemvArgs a{};
-  a.M = M; a.K = K; a.batch = batch; a.A = A;
-  a.x = x; a.xs = xs; a.alpha = cmk(1, 0);
-  a.y0 = y0; a.y0s = y0s; a.beta = cmk(1, 0);
-  a.y = y; a.ys = ys;
-  return a;
-}
-
 bool small_level(const Level& lv) {
   return lv.pairs >= 128 && lv.m <= 256 && small_level_lds(lv.m, lv.e) <= 64 * 1024;
 }
 
-SmallLevel small_args(hps_problem* p, const Level& lv) {
-  SmallLevel a;
+template <class M>
+SmallLevelT<M> small_args(hps_problem* p, const Level& lv) {
+  SmallLevelT<M> a;
   a.g = lv.g;
   a.m = lv.m;
   a.e = lv.e;
@@ -439,8 +466,8 @@ SmallLevel small_args(hps_problem* p, const Level& lv) {
   a.b0 = lv.b0;
   a.E1 = lv.E1;
   a.E2 = lv.E2;
-  a.T = Tlev(p, lv.g.level);
-  a.Winv = at<cd>(p, lv.Winv_off);
+  a.T = Tmat<M>(p, lv.g.level);
+  a.Winv = at<M>(p, lv.Winv_off);
   a.R1 = at<cd>(p, lv.R1_off);
   a.R2 = at<cd>(p, lv.R2_off);
   return a;
@@ -478,9 +505,10 @@ void vout_scatter(VecOut& v, cd* vec, const Geom& g, int which, IdxMap local, bo
   v.partner = partner ? 1 : 0;
   v.add = add ? 1 : 0;
 }
-GemvDesc gdesc(int M, int K, Operand A, VecIn x, VecOut y, cd alpha = cmk(1, 0)) {
-  GemvDesc d{};
-  d.M = M;
+template <class M>
+GemvDescT<M> gdesc(int Mr, int K, OperandT<M> A, VecIn x, VecOut y, cd alpha = cmk(1, 0)) {
+  GemvDescT<M> d{};
+  d.M_ = Mr;
   d.K = K;
   d.A = A;
   d.alpha = alpha;
@@ -492,81 +520,94 @@ GemvDesc gdesc(int M, int K, Operand A, VecIn x, VecOut y, cd alpha = cmk(1, 0))
 // Shared-face solve x = A^-1 r for every pair of a level, r = (r1 at Q.beta,
 // r2 at P.alpha) compact: x1 = W^-1 (r1 + T^P_aa r2), x2 = r2 + T^Q_bb x1.
 // x1 and x2 go to compact buffers and, when zout != null, into zout at Q.beta
-// and P.alpha.
+// and P.alpha.  M is the storage precision of the level's operators.
+template <class M>
 hps_status pair_solve(hps_problem* p, const Level& lv, const cd* r1, const cd* r2, cd* V1, cd* x1, cd* x2,
                       cd* zout) {
   hps_ctx* c = p->ctx;
   hipStream_t st = c->stream;
   const int b = lv.g.b, m = lv.m, np = lv.pairs;
   const long long ps = 2LL * b * b;
-  const cd* T = Tlev(p, lv.g.level);
+  const M* T = Tmat<M>(p, lv.g.level);
+  const M* Wi = at<M>(p, lv.Winv_off);
   cd* part = at<cd>(p, p->lay.gpart_off);
-  GemvDesc d = gdesc(m, m, Operand{T, ps, b, im_off(lv.a0), im_off(lv.a0)}, vin_compact(r2, m),
-                     vout_compact(V1, m, r1, m));
+  GemvDescT<M> d = gdesc<M>(m, m, OperandT<M>{T, ps, b, im_off(lv.a0), im_off(lv.a0)}, vin_compact(r2, m),
+                            vout_compact(V1, m, r1, m));
   HIPCHK(c, zgemv_batched(&d, 1, np, part, st));
   VecOut o1 = vout_compact(x1, m);
   if (zout) vout_scatter(o1, zout, lv.g, 1, im_off(lv.b0), false, false);
-  d = gdesc(m, m, Operand{at<cd>(p, lv.Winv_off), (long long)m * m, m, im_off(0), im_off(0)},
-            vin_compact(V1, m), o1);
+  d = gdesc<M>(m, m, OperandT<M>{Wi, (long long)m * m, m, im_off(0), im_off(0)}, vin_compact(V1, m), o1);
   HIPCHK(c, zgemv_batched(&d, 1, np, part, st));
   VecOut o2 = vout_compact(x2, m, r2, m);
   if (zout) vout_scatter(o2, zout, lv.g, 0, im_off(lv.a0), false, false);
-  d = gdesc(m, m, Operand{T + (size_t)b * b, ps, b, im_off(lv.b0), im_off(lv.b0)}, vin_compact(x1, m), o2);
+  d = gdesc<M>(m, m, OperandT<M>{T + (size_t)b * b, ps, b, im_off(lv.b0), im_off(lv.b0)}, vin_compact(x1, m), o2);
   HIPCHK(c, zgemv_batched(&d, 1, np, part, st));
   return HPS_OK;
 }
 
-hps_status vcycle_down(hps_problem* p, int l, cd* wv) {
+template <class M>
+hps_status vcycle_down_t(hps_problem* p, int l, cd* wv) {
   hps_ctx* c = p->ctx;
   hipStream_t st = c->stream;
   const Level& lv = p->lay.lev[l];
   if (small_level(lv)) {
-    HIPCHK(c, vc_down_small(small_args(p, lv), lv.pairs, wv, st));
+    HIPCHK(c, vc_down_small(small_args<M>(p, lv), lv.pairs, wv, st));
     return HPS_OK;
   }
   const int b = lv.g.b, m = lv.m, e = lv.e, np = lv.pairs;
   const long long ps = 2LL * b * b;
-  const cd* T = Tlev(p, l);
+  const M* T = Tmat<M>(p, l);
   cd* R1 = at<cd>(p, lv.R1_off);
   cd* R2 = at<cd>(p, lv.R2_off);
   VTmp t = vtmp(p);
   HIPCHK(c, pair_gather(lv.g, np, 1, im_off(lv.b0), m, wv, R1, m, false, st));
   HIPCHK(c, pair_gather(lv.g, np, 0, im_off(lv.a0), m, wv, R2, m, false, st));
-  hps_status s = pair_solve(p, lv, R1, R2, t.V1, t.X1, t.X2, nullptr);
+  hps_status s = pair_solve<M>(p, lv, R1, R2, t.V1, t.X1, t.X2, nullptr);
   if (s != HPS_OK) return s;
   // deposits C~ x0 into the rows of the kept faces: w[Pi(P.E1)] += T^P_{E1,a} x2,
   // w[Pi(Q.E2)] += T^Q_{E2,b} x1
   VecOut oP{}, oQ{};
   vout_scatter(oP, wv, lv.g, 0, lv.E1, true, true);
   vout_scatter(oQ, wv, lv.g, 1, lv.E2, true, true);
-  GemvDesc d[2] = {gdesc(e, m, Operand{T, ps, b, lv.E1, im_off(lv.a0)}, vin_compact(t.X2, m), oP),
-                   gdesc(e, m, Operand{T + (size_t)b * b, ps, b, lv.E2, im_off(lv.b0)}, vin_compact(t.X1, m), oQ)};
+  GemvDescT<M> d[2] = {gdesc<M>(e, m, OperandT<M>{T, ps, b, lv.E1, im_off(lv.a0)}, vin_compact(t.X2, m), oP),
+                       gdesc<M>(e, m, OperandT<M>{T + (size_t)b * b, ps, b, lv.E2, im_off(lv.b0)},
+                                vin_compact(t.X1, m), oQ)};
   HIPCHK(c, zgemv_batched(d, 2, np, at<cd>(p, p->lay.gpart_off), st));
   return HPS_OK;
 }
 
-hps_status vcycle_up(hps_problem* p, int l, cd* z) {
+template <class M>
+hps_status vcycle_up_t(hps_problem* p, int l, cd* z) {
   hps_ctx* c = p->ctx;
   hipStream_t st = c->stream;
   const Level& lv = p->lay.lev[l];
   if (small_level(lv)) {
-    HIPCHK(c, vc_up_small(small_args(p, lv), lv.pairs, z, st));
+    HIPCHK(c, vc_up_small(small_args<M>(p, lv), lv.pairs, z, st));
     return HPS_OK;
   }
   const int b = lv.g.b, m = lv.m, e = lv.e, np = lv.pairs;
   const long long ps = 2LL * b * b;
-  const cd* T = Tlev(p, l);
+  const M* T = Tmat<M>(p, l);
   const cd* R1 = at<cd>(p, lv.R1_off);
   const cd* R2 = at<cd>(p, lv.R2_off);
   VTmp t = vtmp(p);
   // r' = r_x + B y with y the kept-face data already in z
-  GemvDesc d[2] = {gdesc(m, e, Operand{T, ps, b, im_off(lv.a0), lv.E1}, vin_gather(z, lv.g, 0, lv.E1, false),
-                         vout_compact(t.DP, m, R1, m)),
-                   gdesc(m, e, Operand{T + (size_t)b * b, ps, b, im_off(lv.b0), lv.E2},
-                         vin_gather(z, lv.g, 1, lv.E2, false), vout_compact(t.DQ, m, R2, m))};
+  GemvDescT<M> d[2] = {gdesc<M>(m, e, OperandT<M>{T, ps, b, im_off(lv.a0), lv.E1}, vin_gather(z, lv.g, 0, lv.E1, false),
+                                vout_compact(t.DP, m, R1, m)),
+                       gdesc<M>(m, e, OperandT<M>{T + (size_t)b * b, ps, b, im_off(lv.b0), lv.E2},
+                                vin_gather(z, lv.g, 1, lv.E2, false), vout_compact(t.DQ, m, R2, m))};
   HIPCHK(c, zgemv_batched(d, 2, np, at<cd>(p, p->lay.gpart_off), st));
-  return pair_solve(p, lv, t.DP, t.DQ, t.V1, t.X1, t.X2, z);
+  return pair_solve<M>(p, lv, t.DP, t.DQ, t.V1, t.X1, t.X2, z);
 }
+
+hps_status vcycle_down(hps_problem* p, int l, cd* wv) {
+  return p->lay.lev[l].f32 ? vcycle_down_t<cf>(p, l, wv) : vcycle_down_t<cd>(p, l, wv);
+}
+
+hps_status vcycle_up(hps_problem* p, int l, cd* z) {
+  return p->lay.lev[l].f32 ? vcycle_up_t<cf>(p, l, z) : vcycle_up_t<cd>(p, l, z);
+}
+
 cd* workv(hps_problem* p, int i) {
   return reinterpret_cast<cd*>(p->ws + p->lay.work_off + i * up256(sizeof(cd) * (size_t)p->lay.nslots));
 }
@@ -601,9 +642,9 @@ hps_status coarse_matvec(hps_problem* p, const cd* v, cd* w) {
     const int m = lay.nL / 2;
     const cd* T = Tlev(p, lay.L);
     const int aP = top.g.off[3], bQ = top.g.off[2];   // P's top side, Q's bottom side
-    GemvDesc d[2] = {gdesc(m, m, Operand{T + (size_t)b * b, 0, b, im_off(bQ), im_off(bQ)}, vin_compact(v + m, 0),
+    GemvDesc d[2] = {gdesc<cd>(m, m, Operand{T + (size_t)b * b, 0, b, im_off(bQ), im_off(bQ)}, vin_compact(v + m, 0),
                            vout_compact(w, 0, v, 0), cmk(-1, 0)),
-                     gdesc(m, m, Operand{T, 0, b, im_off(aP), im_off(aP)}, vin_compact(v, 0),
+                     gdesc<cd>(m, m, Operand{T, 0, b, im_off(aP), im_off(aP)}, vin_compact(v, 0),
                            vout_compact(w + m, 0, v + m, 0), cmk(-1, 0))};
     HIPCHK(c, zgemv_batched(d, 2, 1, at<cd>(p, lay.gpart_off), st));
     return HPS_OK;
@@ -630,7 +671,7 @@ hps_status coarse_solve(hps_problem* p, cd* wv, cd* z) {
     cd* R2 = at<cd>(p, top.R2_off);
     HIPCHK(c, pair_gather(top.g, 1, 1, im_off(top.b0), m, wv, R1, m, false, st));
     HIPCHK(c, pair_gather(top.g, 1, 0, im_off(top.a0), m, wv, R2, m, false, st));
-    return pair_solve(p, top, R1, R2, t.V1, t.X1, t.X2, z);
+    return pair_solve<cd>(p, top, R1, R2, t.V1, t.X1, t.X2, z);
   }
   const int nL = lay.nL, k = lay.k;
   if (nL == 0) return HPS_OK;
@@ -978,7 +1019,10 @@ hps_status hps_problem_create(hps_ctx* ctx, const hps_desc* desc, void* workspac
   // they are kept at zero so that products with zero data stay zero.
   for (int l = 2; l <= lay.L; ++l) {
     const Level& lv = lay.lev[l];
-    HIPCHK(ctx, vfill(Tlev(p, l), (long long)lv.g.nboxes * lv.g.b * lv.g.b, cmk(0, 0), ctx->stream));
+    const long long nmap = (long long)lv.g.nboxes * lv.g.b * lv.g.b;
+    HIPCHK(ctx, vfill(Tlev(p, l), lv.f32 ? (nmap + 1) / 2 : nmap, cmk(0, 0), ctx->stream));
+    if (lay.mixed && l == lay.L - 2 && l >= 2)
+      HIPCHK(ctx, vfill(at<cd>(p, lay.stage_off), (nmap + 1) / 2, cmk(0, 0), ctx->stream));
   }
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
   int zero4[4] = {0, 0, 0, 0};
@@ -1002,7 +1046,8 @@ hps_status hps_level_view_get(const hps_problem* pc, int32_t level, hps_level_vi
   out->boxes = lv.g.nboxes;
   out->box_nodes = lv.g.b;
   out->morton = 1;
-  out->T = p->ws + lv.T_off;
+  out->T = p->ws + ((level == 1 && lv.f32) ? lv.T32_off : lv.T_off);
+  out->fp32 = lv.f32 ? 1 : 0;
   out->pairs = lv.has_merge ? lv.pairs : 0;
   out->shared_nodes = lv.has_merge ? lv.m : 0;
   out->Winv = lv.has_merge ? (const void*)(p->ws + lv.Winv_off) : nullptr;
@@ -1037,6 +1082,13 @@ hps_status hps_build_leaves(hps_problem* const* pp, int32_t count, const double*
       a.E0 = e0;
       a.count = std::min(lay.leaf_chunk, lay.E - e0);
       HIPCHK(p->ctx, leaf_build(a, p->ctx->stream));
+    }
+    if (lay.lev[1].f32) {
+      // FP64 leaf maps serve the outer operator M_1; the FP32 copy feeds the
+      // FP32 merges and the FP32 levels of the V-cycle
+      const Level& l1 = lay.lev[1];
+      HIPCHK(p->ctx, convert_c64_c32(Tlev(p, 1), at<cf>(p, l1.T32_off),
+                                     (long long)l1.g.nboxes * l1.g.b * l1.g.b, p->ctx->stream));
     }
     p->state = kLeaves;
     p->merged = 0;
@@ -1082,6 +1134,8 @@ hps_status hps_skeleton_apply(hps_problem* const* pp, int32_t count, int32_t lev
     if (s != HPS_OK) return s;
     if (level < 1 || level > p->lay.L) return fail(p->ctx, HPS_ERR_ARG, "level out of range");
     if (level > p->merged + 1) return fail(p->ctx, HPS_ERR_STATE, "level maps not built yet");
+    if (level > 1 && p->lay.lev[level].f32)
+      return fail(p->ctx, HPS_ERR_ARG, "this level's maps are stored in FP32 (mixed precision)");
     HIPCHK(p->ctx, skeleton_apply(p->lay.lev[level].g, Tlev(p, level), reinterpret_cast<const cd*>(g[i]),
                                   reinterpret_cast<cd*>(out[i]), level == 1, p->ctx->stream));
   }

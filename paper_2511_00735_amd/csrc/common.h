@@ -27,6 +27,41 @@ __host__ __device__ inline cd cinv(cd a) {
   return make_double2(ar / (d * s), -ai / (d * s));
 }
 
+// complex float counterparts
+__host__ __device__ inline cf cmkf(float r, float i) { return make_float2(r, i); }
+__host__ __device__ inline cf cadd(cf a, cf b) { return make_float2(a.x + b.x, a.y + b.y); }
+__host__ __device__ inline cf csub(cf a, cf b) { return make_float2(a.x - b.x, a.y - b.y); }
+__host__ __device__ inline cf cmul(cf a, cf b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__host__ __device__ inline cf cfma(cf a, cf b, cf c) {
+  return make_float2(fmaf(a.x, b.x, fmaf(-a.y, b.y, c.x)), fmaf(a.x, b.y, fmaf(a.y, b.x, c.y)));
+}
+__host__ __device__ inline float cabs2(cf a) { return a.x * a.x + a.y * a.y; }
+__host__ __device__ inline cf cinv(cf a) {
+  const float s = fmaxf(fabsf(a.x), fabsf(a.y));
+  const float ar = a.x / s, ai = a.y / s;
+  const float d = ar * ar + ai * ai;
+  return make_float2(ar / (d * s), -ai / (d * s));
+}
+// widening / narrowing
+__host__ __device__ inline cd to_cd(cd a) { return a; }
+__host__ __device__ inline cd to_cd(cf a) { return make_double2((double)a.x, (double)a.y); }
+__host__ __device__ inline cf to_cf(cd a) { return make_float2((float)a.x, (float)a.y); }
+
+// Traits of the two complex storage types.
+template <class T> struct cx;
+template <> struct cx<cd> {
+  typedef double real;
+  __host__ __device__ static cd make(double r, double i) { return make_double2(r, i); }
+  __host__ __device__ static cd from(cd a) { return a; }
+};
+template <> struct cx<cf> {
+  typedef float real;
+  __host__ __device__ static cf make(double r, double i) { return make_float2((float)r, (float)i); }
+  __host__ __device__ static cf from(cd a) { return to_cf(a); }
+};
+
 // Index map: i -> map ? map[i] : off + i + (i >= gap_start ? gap_len : 0).
 // Describes a row or column selection of a matrix operand.
 struct IdxMap {

@@ -17,21 +17,46 @@ namespace hps {
 namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int KT = 16;
 
-template <int BM, int BN, int WM, int WN>
-__global__ __launch_bounds__(64 * WM * WN) void zgemm_kernel(GemmArgs a) {
+// One 16x16x4 real MFMA per precision, and where its result lands: lane l,
+// element v -> row(l, v), column l % 16 (the two layouts differ; both were
+// checked on gfx950).
+template <class T> struct Mfma;
+template <> struct Mfma<cd> {
+  typedef d4 acc;
+  __device__ static acc mma(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static int row(int lk, int v) { return lk + 4 * v; }
+};
+template <> struct Mfma<cf> {
+  typedef f4 acc;
+  __device__ static acc mma(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static int row(int lk, int v) { return 4 * lk + v; }
+};
+
+template <class T, int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__(64 * WM * WN) void zgemm_kernel(GemmArgsT<T> a) {
+  typedef typename Mfma<T>::acc acc_t;
   constexpr int NT = 64 * WM * WN;
   constexpr int TM = BM / WM / 16;
   constexpr int TN = BN / WN / 16;
-  __shared__ cd As[KT][BM];
-  __shared__ cd Bs[KT][BN];
+  __shared__ T As[KT][BM];
+  __shared__ T Bs[KT][BN];
   const int b = blockIdx.y;
   const int tilesM = (a.M + BM - 1) / BM;
   const int m0 = (blockIdx.x % tilesM) * BM;
   const int n0 = (blockIdx.x / tilesM) * BN;
   const int tid = threadIdx.x;
+  // Physical rows/columns of a live tile are written as exact zeros: their
+  // inputs (skipped entries of earlier products) are never computed, so they
+  // must not leak into the stored maps, where they meet zero data.
+  __shared__ unsigned char dead_r[BM], dead_c[BN];
   if (a.skip.enabled) {
     __shared__ int live_r, live_c;
     int bx, by;
@@ -41,49 +66,55 @@ __global__ __launch_bounds__(64 * WM * WN) void zgemm_kernel(GemmArgs a) {
       live_c = a.skip.col_y ? 0 : 1;
     }
     __syncthreads();
-    if (a.skip.row_y && tid < BM && m0 + tid < a.M &&
-        !y_physical(a.skip, bx, by, m0 + tid + a.skip.row_off))
-      live_r = 1;
-    if (a.skip.col_y && tid < BN && n0 + tid < a.N &&
-        !y_physical(a.skip, bx, by, n0 + tid + a.skip.col_off))
-      live_c = 1;
+    if (tid < BM) {
+      const bool dead = a.skip.row_y && m0 + tid < a.M &&
+                        y_physical(a.skip, bx, by, m0 + tid + a.skip.row_off);
+      dead_r[tid] = dead;
+      if (a.skip.row_y && m0 + tid < a.M && !dead) live_r = 1;
+    }
+    if (tid < BN) {
+      const bool dead = a.skip.col_y && n0 + tid < a.N &&
+                        y_physical(a.skip, bx, by, n0 + tid + a.skip.col_off);
+      dead_c[tid] = dead;
+      if (a.skip.col_y && n0 + tid < a.N && !dead) live_c = 1;
+    }
     __syncthreads();
     if (!live_r || !live_c) return;
   }
-  const cd* Ab = a.A.base + (long long)b * a.A.bstride;
-  const cd* Bb = a.B.base + (long long)b * a.B.bstride;
+  const T* Ab = a.A.base + (long long)b * a.A.bstride;
+  const T* Bb = a.B.base + (long long)b * a.B.bstride;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave % WM, wn = wave / WM;
   const int lr = lane & 15, lk = lane >> 4;
 
-  d4 accr[TM][TN], acci[TM][TN];
+  acc_t accr[TM][TN], acci[TM][TN];
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
     for (int j = 0; j < TN; ++j) {
-      accr[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-      acci[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+      accr[i][j] = acc_t{0, 0, 0, 0};
+      acci[i][j] = acc_t{0, 0, 0, 0};
     }
 
   for (int k0 = 0; k0 < a.K; k0 += KT) {
     for (int e = tid; e < BM * KT; e += NT) {
       const int i = e % BM, k = e / BM;
       const int gi = m0 + i, gk = k0 + k;
-      cd v = cmk(0.0, 0.0);
+      T v = cx<T>::make(0.0, 0.0);
       if (gi < a.M && gk < a.K) v = Ab[(long long)imap(a.A.c, gk) * a.A.ld + imap(a.A.r, gi)];
       As[k][i] = v;
     }
     for (int e = tid; e < BN * KT; e += NT) {
       const int k = e % KT, j = e / KT;
       const int gj = n0 + j, gk = k0 + k;
-      cd v = cmk(0.0, 0.0);
+      T v = cx<T>::make(0.0, 0.0);
       if (gj < a.N && gk < a.K) v = Bb[(long long)imap(a.B.c, gj) * a.B.ld + imap(a.B.r, gk)];
       Bs[k][j] = v;
     }
     __syncthreads();
 #pragma unroll
     for (int kk = 0; kk < KT; kk += 4) {
-      cd av[TM], bv[TN];
+      T av[TM], bv[TN];
 #pragma unroll
       for (int i = 0; i < TM; ++i) av[i] = As[kk + lk][wm * (BM / WM) + i * 16 + lr];
 #pragma unroll
@@ -92,19 +123,17 @@ __global__ __launch_bounds__(64 * WM * WN) void zgemm_kernel(GemmArgs a) {
       for (int i = 0; i < TM; ++i)
 #pragma unroll
         for (int j = 0; j < TN; ++j) {
-          accr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i].x, bv[j].x, accr[i][j], 0, 0, 0);
-          accr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-av[i].y, bv[j].y, accr[i][j], 0, 0, 0);
-          acci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i].x, bv[j].y, acci[i][j], 0, 0, 0);
-          acci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i].y, bv[j].x, acci[i][j], 0, 0, 0);
+          accr[i][j] = Mfma<T>::mma(av[i].x, bv[j].x, accr[i][j]);
+          accr[i][j] = Mfma<T>::mma(-av[i].y, bv[j].y, accr[i][j]);
+          acci[i][j] = Mfma<T>::mma(av[i].x, bv[j].y, acci[i][j]);
+          acci[i][j] = Mfma<T>::mma(av[i].y, bv[j].x, acci[i][j]);
         }
     }
     __syncthreads();
   }
 
-  // 16x16x4 f64 MFMA result layout (checked on gfx950): lane l, element v ->
-  // row l/16 + 4 v, column l%16.  (The f32 16x16x4 variant uses row 4(l/16) + v.)
-  cd* Db = a.D + (long long)b * a.Dstride;
-  const cd* Cb = a.C.base ? a.C.base + (long long)b * a.C.bstride : nullptr;
+  T* Db = a.D + (long long)b * a.Dstride;
+  const T* Cb = a.C.base ? a.C.base + (long long)b * a.C.bstride : nullptr;
   const bool use_c = (a.beta.x != 0.0 || a.beta.y != 0.0);
 #pragma unroll
   for (int i = 0; i < TM; ++i)
@@ -112,11 +141,15 @@ __global__ __launch_bounds__(64 * WM * WN) void zgemm_kernel(GemmArgs a) {
     for (int j = 0; j < TN; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int gi = m0 + wm * (BM / WM) + i * 16 + lk + 4 * v;
+        const int gi = m0 + wm * (BM / WM) + i * 16 + Mfma<T>::row(lk, v);
         const int gj = n0 + wn * (BN / WN) + j * 16 + lr;
         if (gi < a.M && gj < a.N) {
-          cd acc = cmk(accr[i][j][v], acci[i][j][v]);
-          cd out = cmul(a.alpha, acc);
+          if (a.skip.enabled && (dead_r[gi - m0] || dead_c[gj - n0])) {
+            Db[(long long)imap(a.dc, gj) * a.ldd + imap(a.dr, gi)] = cx<T>::make(0.0, 0.0);
+            continue;
+          }
+          T acc = cx<T>::make(accr[i][j][v], acci[i][j][v]);
+          T out = cmul(a.alpha, acc);
           if (use_c) out = cfma(a.beta, Cb[(long long)imap(a.C.c, gj) * a.C.ld + imap(a.C.r, gi)], out);
           if (a.has_diag && gi == gj) out = cadd(out, a.diag_add);
           Db[(long long)imap(a.dc, gj) * a.ldd + imap(a.dr, gi)] = out;
@@ -124,7 +157,8 @@ __global__ __launch_bounds__(64 * WM * WN) void zgemm_kernel(GemmArgs a) {
       }
 }
 
-__global__ void zcopy2d_kernel(int M, int N, Operand S, cd alpha, cd* D, long long Dstride, int ldd,
+template <class T>
+__global__ void zcopy2d_kernel(int M, int N, OperandT<T> S, T alpha, T* D, long long Dstride, int ldd,
                                IdxMap dr, IdxMap dc, PhysSkip skip) {
   const int b = blockIdx.y;
   const long long total = (long long)M * N;
@@ -136,39 +170,72 @@ __global__ void zcopy2d_kernel(int M, int N, Operand S, cd alpha, cd* D, long lo
     if (skip.enabled && ((skip.row_y && y_physical(skip, bx, by, i + skip.row_off)) ||
                          (skip.col_y && y_physical(skip, bx, by, j + skip.col_off))))
       continue;
-    cd v = cmk(0.0, 0.0);
+    T v = cx<T>::make(0.0, 0.0);
     if (S.base) v = cmul(alpha, S.base[(long long)b * S.bstride + (long long)imap(S.c, j) * S.ld + imap(S.r, i)]);
     D[(long long)b * Dstride + (long long)imap(dc, j) * ldd + imap(dr, i)] = v;
   }
 }
 
-template <int BM, int BN, int WM, int WN>
-hipError_t launch(const GemmArgs& a, hipStream_t st) {
+__global__ void convert_64_32_kernel(const cd* src, cf* dst, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    dst[i] = to_cf(src[i]);
+}
+
+__global__ void convert_32_64_kernel(const cf* src, cd* dst, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    dst[i] = to_cd(src[i]);
+}
+
+template <class T, int BM, int BN, int WM, int WN>
+hipError_t launch(const GemmArgsT<T>& a, hipStream_t st) {
   const int tiles = ((a.M + BM - 1) / BM) * ((a.N + BN - 1) / BN);
-  hipLaunchKernelGGL((zgemm_kernel<BM, BN, WM, WN>), dim3(tiles, a.batch), dim3(64 * WM * WN), 0,
+  hipLaunchKernelGGL((zgemm_kernel<T, BM, BN, WM, WN>), dim3(tiles, a.batch), dim3(64 * WM * WN), 0,
                      st, a);
   return hipPeekAtLastError();
 }
 
 }  // namespace
 
-hipError_t zgemm(const GemmArgs& a, hipStream_t st) {
+template <class T>
+hipError_t zgemm(const GemmArgsT<T>& a, hipStream_t st) {
   if (a.M <= 0 || a.N <= 0 || a.batch <= 0) return hipSuccess;
-  if (a.M >= 48 && a.N >= 48) return launch<64, 64, 2, 2>(a, st);
-  if (a.M >= 24 && a.N >= 24) return launch<32, 32, 2, 2>(a, st);
-  return launch<16, 16, 1, 1>(a, st);
+  if (a.M >= 48 && a.N >= 48) return launch<T, 64, 64, 2, 2>(a, st);
+  if (a.M >= 24 && a.N >= 24) return launch<T, 32, 32, 2, 2>(a, st);
+  return launch<T, 16, 16, 1, 1>(a, st);
 }
 
-hipError_t zcopy2d(int M, int N, int batch, const Operand& S, cd alpha, cd* D, long long Dstride,
+hipError_t convert_c64_c32(const cd* src, cf* dst, long long n, hipStream_t st) {
+  const int blocks = (int)std::min<long long>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(convert_64_32_kernel, dim3(std::max(blocks, 1)), dim3(256), 0, st, src, dst, n);
+  return hipPeekAtLastError();
+}
+
+hipError_t convert_c32_c64(const cf* src, cd* dst, long long n, hipStream_t st) {
+  const int blocks = (int)std::min<long long>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(convert_32_64_kernel, dim3(std::max(blocks, 1)), dim3(256), 0, st, src, dst, n);
+  return hipPeekAtLastError();
+}
+
+template <class T>
+hipError_t zcopy2d(int M, int N, int batch, const OperandT<T>& S, T alpha, T* D, long long Dstride,
                    int ldd, IdxMap dr, IdxMap dc, hipStream_t st, const PhysSkip* skip) {
   PhysSkip none{};
   const PhysSkip sk = skip ? *skip : none;
   if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
   const long long total = (long long)M * N;
   int blocks = (int)std::min<long long>((total + 255) / 256, 1024);
-  hipLaunchKernelGGL(zcopy2d_kernel, dim3(blocks, batch), dim3(256), 0, st, M, N, S, alpha, D,
+  hipLaunchKernelGGL(zcopy2d_kernel<T>, dim3(blocks, batch), dim3(256), 0, st, M, N, S, alpha, D,
                      Dstride, ldd, dr, dc, sk);
   return hipPeekAtLastError();
 }
+
+template hipError_t zgemm<cd>(const GemmArgsT<cd>&, hipStream_t);
+template hipError_t zgemm<cf>(const GemmArgsT<cf>&, hipStream_t);
+template hipError_t zcopy2d<cd>(int, int, int, const OperandT<cd>&, cd, cd*, long long, int, IdxMap,
+                                IdxMap, hipStream_t, const PhysSkip*);
+template hipError_t zcopy2d<cf>(int, int, int, const OperandT<cf>&, cf, cf*, long long, int, IdxMap,
+                                IdxMap, hipStream_t, const PhysSkip*);
 
 }  // namespace hps

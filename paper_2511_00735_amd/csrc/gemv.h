@@ -38,39 +38,47 @@ struct VecOut {
   int add;
 };
 
-struct GemvDesc {
-  int M, K;
-  Operand A;
+// The matrix may be stored in complex FP64 (M = cd) or FP32 (M = cf); x, y and
+// the accumulation are always FP64.
+template <class M>
+struct GemvDescT {
+  int M_, K;
+  OperandT<M> A;
   cd alpha;
   VecIn x;
   VecOut y;
 };
+typedef GemvDescT<cd> GemvDesc;
 
-struct GemvBatch {
-  GemvDesc d[kGemvMaxDesc];
+template <class M>
+struct GemvBatchT {
+  GemvDescT<M> d[kGemvMaxDesc];
   int nsplit[kGemvMaxDesc];
   long long poff[kGemvMaxDesc];   // partial-sum offsets
   int batch;
 };
 
 int gemv_nsplit(int M, int K, int batch);
-size_t gemv_partial_elems(const GemvDesc* d, int nd, int batch);
 // nd GEMVs of the same batch size in one launch, plus one reduction launch when
-// any of them is split along K (partial: gemv_partial_elems(d, nd, batch) entries).
-hipError_t zgemv_batched(const GemvDesc* d, int nd, int batch, cd* partial, hipStream_t st);
+// any of them is split along K (partial sums: at most gemv_nsplit * batch * M each).
+template <class M>
+hipError_t zgemv_batched(const GemvDescT<M>* d, int nd, int batch, cd* partial, hipStream_t st);
 
 // One V-cycle level with one workgroup per pair (levels with many small pairs).
-struct SmallLevel {
+template <class M>
+struct SmallLevelT {
   Geom g;
   int m, e, a0, b0;
   IdxMap E1, E2;
-  const cd* T;
-  const cd* Winv;
+  const M* T;
+  const M* Winv;
   cd* R1;
   cd* R2;
 };
 size_t small_level_lds(int m, int e);
-hipError_t vc_down_small(const SmallLevel& a, int pairs, cd* vec, hipStream_t st);
-hipError_t vc_up_small(const SmallLevel& a, int pairs, cd* z, hipStream_t st);
+template <class M>
+hipError_t vc_down_small(const SmallLevelT<M>& a, int pairs, cd* vec, hipStream_t st);
+template <class M>
+hipError_t vc_up_small(const SmallLevelT<M>& a, int pairs, cd* z, hipStream_t st);
 
 }  // namespace hps

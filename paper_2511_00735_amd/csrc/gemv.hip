@@ -42,11 +42,12 @@ __device__ inline void store_y(const VecOut& y, int b, int i, cd v) {
 }
 
 // grid: x = row tile * nsplit (flattened), y = batch, z = descriptor.
-__global__ __launch_bounds__(kThreads) void gemv_kernel(GemvBatch gb, cd* partial) {
+template <class Mt>
+__global__ __launch_bounds__(kThreads) void gemv_kernel(GemvBatchT<Mt> gb, cd* partial) {
   __shared__ cd xs[kGemvKChunkMax];
   __shared__ cd red[4][kRowsT];
-  const GemvDesc& d = gb.d[blockIdx.z];
-  const int tiles = (d.M + kRowsT - 1) / kRowsT;
+  const GemvDescT<Mt>& d = gb.d[blockIdx.z];
+  const int tiles = (d.M_ + kRowsT - 1) / kRowsT;
   const int nsplit = gb.nsplit[blockIdx.z];
   if ((int)blockIdx.x >= tiles * nsplit) return;
   const int tile = blockIdx.x % tiles, split = blockIdx.x / tiles;
@@ -59,56 +60,58 @@ __global__ __launch_bounds__(kThreads) void gemv_kernel(GemvBatch gb, cd* partia
   __syncthreads();
   const int r = tile * kRowsT + lane;
   cd acc = cmk(0.0, 0.0);
-  if (r < d.M) {
-    const cd* Ab = d.A.base + (long long)b * d.A.bstride;
+  if (r < d.M_) {
+    const Mt* Ab = d.A.base + (long long)b * d.A.bstride;
     const long long row = imap(d.A.r, r);
     int k = k0 + grp;
     for (; k + 12 < k1; k += 16) {
-      const cd a0 = Ab[(long long)imap(d.A.c, k) * d.A.ld + row];
-      const cd a1 = Ab[(long long)imap(d.A.c, k + 4) * d.A.ld + row];
-      const cd a2 = Ab[(long long)imap(d.A.c, k + 8) * d.A.ld + row];
-      const cd a3 = Ab[(long long)imap(d.A.c, k + 12) * d.A.ld + row];
+      const cd a0 = to_cd(Ab[(long long)imap(d.A.c, k) * d.A.ld + row]);
+      const cd a1 = to_cd(Ab[(long long)imap(d.A.c, k + 4) * d.A.ld + row]);
+      const cd a2 = to_cd(Ab[(long long)imap(d.A.c, k + 8) * d.A.ld + row]);
+      const cd a3 = to_cd(Ab[(long long)imap(d.A.c, k + 12) * d.A.ld + row]);
       acc = cfma(a0, xs[k - k0], acc);
       acc = cfma(a1, xs[k + 4 - k0], acc);
       acc = cfma(a2, xs[k + 8 - k0], acc);
       acc = cfma(a3, xs[k + 12 - k0], acc);
     }
-    for (; k < k1; k += 4) acc = cfma(Ab[(long long)imap(d.A.c, k) * d.A.ld + row], xs[k - k0], acc);
+    for (; k < k1; k += 4) acc = cfma(to_cd(Ab[(long long)imap(d.A.c, k) * d.A.ld + row]), xs[k - k0], acc);
   }
   red[grp][lane] = acc;
   __syncthreads();
   if (nsplit == 1) {
-    if (grp == 0 && r < d.M) {
+    if (grp == 0 && r < d.M_) {
       const cd s = cadd(cadd(red[0][lane], red[1][lane]), cadd(red[2][lane], red[3][lane]));
       store_y(d.y, b, r, cmul(d.alpha, s));
     }
     return;
   }
-  if (grp == 0 && r < d.M) {
+  if (grp == 0 && r < d.M_) {
     const cd s = cadd(cadd(red[0][lane], red[1][lane]), cadd(red[2][lane], red[3][lane]));
-    partial[gb.poff[blockIdx.z] + ((long long)split * gb.batch + b) * d.M + r] = s;
+    partial[gb.poff[blockIdx.z] + ((long long)split * gb.batch + b) * d.M_ + r] = s;
   }
 }
 
 // Sum the split-K partials in split order (deterministic) and apply the epilogue.
 // (A device-scope fence per workgroup to let the last split reduce in place
 // forces an L2 write-back on this chip and costs more than this launch.)
-__global__ void gemv_reduce_kernel(GemvBatch gb, const cd* partial) {
-  const GemvDesc& d = gb.d[blockIdx.z];
+template <class Mt>
+__global__ void gemv_reduce_kernel(GemvBatchT<Mt> gb, const cd* partial) {
+  const GemvDescT<Mt>& d = gb.d[blockIdx.z];
   const int nsplit = gb.nsplit[blockIdx.z];
   if (nsplit == 1) return;
   const int b = blockIdx.y;
-  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < d.M; r += gridDim.x * blockDim.x) {
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < d.M_; r += gridDim.x * blockDim.x) {
     cd s = cmk(0.0, 0.0);
     for (int q = 0; q < nsplit; ++q)
-      s = cadd(s, partial[gb.poff[blockIdx.z] + ((long long)q * gb.batch + b) * d.M + r]);
+      s = cadd(s, partial[gb.poff[blockIdx.z] + ((long long)q * gb.batch + b) * d.M_ + r]);
     store_y(d.y, b, r, cmul(d.alpha, s));
   }
 }
 
 // ---- one workgroup per pair: a whole V-cycle level ---------------------------
 // y[i] = (y0 ? y0[i] : 0) + sum_k A(rm(i), cm(k)) x[k]; x, y0, y in LDS.
-__device__ void wg_gemv(const cd* A, int ld, IdxMap rm, IdxMap cm, int M, int K, const cd* x,
+template <class Mt>
+__device__ void wg_gemv(const Mt* A, int ld, IdxMap rm, IdxMap cm, int M, int K, const cd* x,
                         const cd* y0, cd* y, cd* red) {
   const int t = threadIdx.x;
   const int RT = M < kRowsT ? M : kRowsT;
@@ -119,7 +122,7 @@ __device__ void wg_gemv(const cd* A, int ld, IdxMap rm, IdxMap cm, int M, int K,
     cd acc = cmk(0.0, 0.0);
     if (g < G && row < M) {
       const long long ar = imap(rm, row);
-      for (int c = g; c < K; c += G) acc = cfma(A[(long long)imap(cm, c) * ld + ar], x[c], acc);
+      for (int c = g; c < K; c += G) acc = cfma(to_cd(A[(long long)imap(cm, c) * ld + ar]), x[c], acc);
     }
     if (g < G) red[g * RT + r] = acc;
     __syncthreads();
@@ -132,7 +135,8 @@ __device__ void wg_gemv(const cd* A, int ld, IdxMap rm, IdxMap cm, int M, int K,
   }
 }
 
-__global__ __launch_bounds__(kThreads) void vc_down_small_kernel(SmallLevel a, cd* vec) {
+template <class Mt>
+__global__ __launch_bounds__(kThreads) void vc_down_small_kernel(SmallLevelT<Mt> a, cd* vec) {
   extern __shared__ cd sm[];
   const int m = a.m, e = a.e;
   cd* r1 = sm;
@@ -148,8 +152,8 @@ __global__ __launch_bounds__(kThreads) void vc_down_small_kernel(SmallLevel a, c
   box_xy(g, 2 * j, px, py);
   box_xy(g, 2 * j + 1, qx, qy);
   const long long bb = (long long)g.b * g.b;
-  const cd* TP = a.T + (2LL * j) * bb;
-  const cd* TQ = TP + bb;
+  const Mt* TP = a.T + (2LL * j) * bb;
+  const Mt* TQ = TP + bb;
   for (int i = t; i < m; i += kThreads) {
     const cd u = vec[box_slot(g, qx, qy, a.b0 + i)];
     const cd w = vec[box_slot(g, px, py, a.a0 + i)];
@@ -179,7 +183,8 @@ __global__ __launch_bounds__(kThreads) void vc_down_small_kernel(SmallLevel a, c
   }
 }
 
-__global__ __launch_bounds__(kThreads) void vc_up_small_kernel(SmallLevel a, cd* z) {
+template <class Mt>
+__global__ __launch_bounds__(kThreads) void vc_up_small_kernel(SmallLevelT<Mt> a, cd* z) {
   extern __shared__ cd sm[];
   const int m = a.m, e = a.e;
   cd* zp = sm;
@@ -198,8 +203,8 @@ __global__ __launch_bounds__(kThreads) void vc_up_small_kernel(SmallLevel a, cd*
   box_xy(g, 2 * j, px, py);
   box_xy(g, 2 * j + 1, qx, qy);
   const long long bb = (long long)g.b * g.b;
-  const cd* TP = a.T + (2LL * j) * bb;
-  const cd* TQ = TP + bb;
+  const Mt* TP = a.T + (2LL * j) * bb;
+  const Mt* TQ = TP + bb;
   for (int i = t; i < e; i += kThreads) {
     const int kp = imap(a.E1, i), kq = imap(a.E2, i);
     zp[i] = side_physical(g, px, py, side_of(g, kp)) ? cmk(0.0, 0.0) : z[box_slot(g, px, py, kp)];
@@ -231,38 +236,30 @@ int gemv_nsplit(int M, int K, int batch) {
   return ns;
 }
 
-size_t gemv_partial_elems(const GemvDesc* d, int nd, int batch) {
-  size_t tot = 0;
-  for (int i = 0; i < nd; ++i) {
-    const int ns = gemv_nsplit(d[i].M, d[i].K, batch);
-    if (ns > 1) tot += (size_t)ns * batch * d[i].M;
-  }
-  return tot;
-}
-
-hipError_t zgemv_batched(const GemvDesc* d, int nd, int batch, cd* partial, hipStream_t st) {
+template <class Mt>
+hipError_t zgemv_batched(const GemvDescT<Mt>* d, int nd, int batch, cd* partial, hipStream_t st) {
   if (nd <= 0 || nd > kGemvMaxDesc || batch <= 0) return hipErrorInvalidValue;
-  GemvBatch gb{};
+  GemvBatchT<Mt> gb{};
   gb.batch = batch;
   int gx = 0;
   long long poff = 0;
   bool any_split = false;
   for (int i = 0; i < nd; ++i) {
     gb.d[i] = d[i];
-    const int tiles = (d[i].M + kRowsT - 1) / kRowsT;
-    const int ns = gemv_nsplit(d[i].M, d[i].K, batch);
+    const int tiles = (d[i].M_ + kRowsT - 1) / kRowsT;
+    const int ns = gemv_nsplit(d[i].M_, d[i].K, batch);
     gb.nsplit[i] = ns;
     gb.poff[i] = poff;
-    if (ns > 1) { poff += (long long)ns * batch * d[i].M; any_split = true; }
+    if (ns > 1) { poff += (long long)ns * batch * d[i].M_; any_split = true; }
     gx = std::max(gx, tiles * ns);
   }
   if (any_split && !partial) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(gemv_kernel, dim3(gx, batch, nd), dim3(kThreads), 0, st, gb, partial);
+  hipLaunchKernelGGL(gemv_kernel<Mt>, dim3(gx, batch, nd), dim3(kThreads), 0, st, gb, partial);
   hipError_t err = hipPeekAtLastError();
   if (err != hipSuccess || !any_split) return err;
   int maxM = 0;
-  for (int i = 0; i < nd; ++i) maxM = std::max(maxM, d[i].M);
-  hipLaunchKernelGGL(gemv_reduce_kernel, dim3((maxM + 255) / 256, batch, nd), dim3(256), 0, st, gb, partial);
+  for (int i = 0; i < nd; ++i) maxM = std::max(maxM, d[i].M_);
+  hipLaunchKernelGGL(gemv_reduce_kernel<Mt>, dim3((maxM + 255) / 256, batch, nd), dim3(256), 0, st, gb, partial);
   return hipPeekAtLastError();
 }
 
@@ -270,20 +267,29 @@ size_t small_level_lds(int m, int e) {
   return sizeof(cd) * (size_t)(std::max(5 * m + e, 2 * e + 7 * m) + kThreads);
 }
 
-hipError_t vc_down_small(const SmallLevel& a, int pairs, cd* vec, hipStream_t st) {
+template <class Mt>
+hipError_t vc_down_small(const SmallLevelT<Mt>& a, int pairs, cd* vec, hipStream_t st) {
   const size_t lds = small_level_lds(a.m, a.e);
-  hipError_t err = allow_lds(vc_down_small_kernel, lds);
+  hipError_t err = allow_lds(vc_down_small_kernel<Mt>, lds);
   if (err != hipSuccess) return err;
-  hipLaunchKernelGGL(vc_down_small_kernel, dim3(pairs), dim3(kThreads), lds, st, a, vec);
+  hipLaunchKernelGGL(vc_down_small_kernel<Mt>, dim3(pairs), dim3(kThreads), lds, st, a, vec);
   return hipPeekAtLastError();
 }
 
-hipError_t vc_up_small(const SmallLevel& a, int pairs, cd* z, hipStream_t st) {
+template <class Mt>
+hipError_t vc_up_small(const SmallLevelT<Mt>& a, int pairs, cd* z, hipStream_t st) {
   const size_t lds = small_level_lds(a.m, a.e);
-  hipError_t err = allow_lds(vc_up_small_kernel, lds);
+  hipError_t err = allow_lds(vc_up_small_kernel<Mt>, lds);
   if (err != hipSuccess) return err;
-  hipLaunchKernelGGL(vc_up_small_kernel, dim3(pairs), dim3(kThreads), lds, st, a, z);
+  hipLaunchKernelGGL(vc_up_small_kernel<Mt>, dim3(pairs), dim3(kThreads), lds, st, a, z);
   return hipPeekAtLastError();
 }
+
+template hipError_t zgemv_batched<cd>(const GemvDescT<cd>*, int, int, cd*, hipStream_t);
+template hipError_t zgemv_batched<cf>(const GemvDescT<cf>*, int, int, cd*, hipStream_t);
+template hipError_t vc_down_small<cd>(const SmallLevelT<cd>&, int, cd*, hipStream_t);
+template hipError_t vc_down_small<cf>(const SmallLevelT<cf>&, int, cd*, hipStream_t);
+template hipError_t vc_up_small<cd>(const SmallLevelT<cd>&, int, cd*, hipStream_t);
+template hipError_t vc_up_small<cf>(const SmallLevelT<cf>&, int, cd*, hipStream_t);
 
 }  // namespace hps

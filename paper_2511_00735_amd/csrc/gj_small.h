@@ -6,53 +6,55 @@
 // S: m x m column-major in LDS (ld = m), inverted in place.
 // ipiv: LDS int[m]; colk: LDS cd[m]; must be called by all threads of the block
 // (blockDim.x >= 64).  Sets bit 2 of *flag on an exactly zero pivot.
-__device__ inline void gj_inplace_small(cd* S, int m, int* ipiv, cd* colk, int* flag) {
+template <class T>
+__device__ inline void gj_inplace_small(T* S, int m, int* ipiv, T* colk, int* flag) {
+  typedef typename cx<T>::real R;
   const int tid = threadIdx.x;
   const int nt = blockDim.x;
   for (int k = 0; k < m; ++k) {
     if (tid < 64) {
-      double best = -1.0;
+      R best = -1;
       int bi = k;
       for (int r = k + tid; r < m; r += 64) {
-        const double v = cabs2(S[k * m + r]);
+        const R v = cabs2(S[k * m + r]);
         if (v > best) { best = v; bi = r; }
       }
       for (int off = 32; off > 0; off >>= 1) {
-        const double ov = __shfl_xor(best, off);
+        const R ov = __shfl_xor(best, off);
         const int oi = __shfl_xor(bi, off);
         if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
       }
       if (tid == 0) {
         ipiv[k] = bi;
-        if (!(best > 0.0)) atomicOr(flag, 2);
+        if (!(best > 0)) atomicOr(flag, 2);
       }
     }
     __syncthreads();
     const int pr = ipiv[k];
     if (pr != k) {
       for (int j = tid; j < m; j += nt) {
-        const cd t = S[j * m + k];
+        const T t = S[j * m + k];
         S[j * m + k] = S[j * m + pr];
         S[j * m + pr] = t;
       }
       __syncthreads();
     }
-    const cd d = S[k * m + k];
-    const cd inv = (cabs2(d) > 0.0) ? cinv(d) : cmk(0.0, 0.0);
+    const T d = S[k * m + k];
+    const T inv = (cabs2(d) > 0) ? cinv(d) : cx<T>::make(0.0, 0.0);
     __syncthreads();
     for (int j = tid; j < m; j += nt) {
       // row k scaled by 1/d (its diagonal becomes 1/d); column k saved
-      const cd v = (j == k) ? cmk(1.0, 0.0) : S[j * m + k];
+      const T v = (j == k) ? cx<T>::make(1.0, 0.0) : S[j * m + k];
       S[j * m + k] = cmul(v, inv);
-      colk[j] = (j == k) ? cmk(0.0, 0.0) : S[k * m + j];
+      colk[j] = (j == k) ? cx<T>::make(0.0, 0.0) : S[k * m + j];
     }
     __syncthreads();
     for (int idx = tid; idx < m * m; idx += nt) {
       const int i = idx % m, j = idx / m;
       if (i == k) continue;
-      const cd base = (j == k) ? cmk(0.0, 0.0) : S[j * m + i];
-      const cd f = colk[i];
-      const cd rk = S[j * m + k];
+      const T base = (j == k) ? cx<T>::make(0.0, 0.0) : S[j * m + i];
+      const T f = colk[i];
+      const T rk = S[j * m + k];
       S[j * m + i] = csub(base, cmul(f, rk));
     }
     __syncthreads();
@@ -62,7 +64,7 @@ __device__ inline void gj_inplace_small(cd* S, int m, int* ipiv, cd* colk, int* 
     for (int k = m - 1; k >= 0; --k) {
       const int pr = ipiv[k];
       if (pr != k) {
-        const cd t = S[k * m + i];
+        const T t = S[k * m + i];
         S[k * m + i] = S[pr * m + i];
         S[pr * m + i] = t;
       }

@@ -34,12 +34,16 @@ hipError_t leaf_build(const LeafArgs& a, hipStream_t st);
 size_t leaf_scratch_doubles(int N, int count);
 
 // ---- batched complex GEMM and copies (gemm.hip) ---------------------------
-struct Operand {
-  const cd* base;
+// T is cd (complex FP64) or cf (complex FP32).
+template <class T>
+struct OperandT {
+  const T* base;
   long long bstride;  // elements between consecutive batch entries
   int ld;
   IdxMap r, c;
 };
+typedef OperandT<cd> Operand;
+typedef OperandT<cf> OperandF;
 // Output tiles of a merge whose rows (or columns) all lie on physical sides of
 // the merged box are never needed: the skeleton unknowns are interior
 // impedances only.  Batch entry b writes merged box b of level g.level; a y
@@ -53,25 +57,32 @@ struct PhysSkip {
   int row_off, col_off;
 };
 
-struct GemmArgs {
+template <class T>
+struct GemmArgsT {
   int M, N, K, batch;
-  Operand A, B;
-  cd alpha, beta;
-  Operand C;          // read only when beta != 0 (may alias D)
-  cd* D;
+  OperandT<T> A, B;
+  T alpha, beta;
+  OperandT<T> C;      // read only when beta != 0 (may alias D)
+  T* D;
   long long Dstride;
   int ldd;
   IdxMap dr, dc;
-  cd diag_add;        // added to D(i, i) for i < min(M, N) when has_diag
+  T diag_add;         // added to D(i, i) for i < min(M, N) when has_diag
   int has_diag;
   PhysSkip skip;
 };
-// D = alpha * A B + beta * C (+ diag_add I), all column-major complex FP64.
-hipError_t zgemm(const GemmArgs& a, hipStream_t st);
+typedef GemmArgsT<cd> GemmArgs;
+// D = alpha * A B + beta * C (+ diag_add I), all column-major; complex MFMA.
+template <class T>
+hipError_t zgemm(const GemmArgsT<T>& a, hipStream_t st);
 // D(dr(i), dc(j)) = alpha * S(sr(i), sc(j)) (S == null: zero), batched.
-hipError_t zcopy2d(int M, int N, int batch, const Operand& S, cd alpha, cd* D,
+template <class T>
+hipError_t zcopy2d(int M, int N, int batch, const OperandT<T>& S, T alpha, T* D,
                    long long Dstride, int ldd, IdxMap dr, IdxMap dc, hipStream_t st,
                    const PhysSkip* skip = nullptr);
+// dst[i] = src[i] converted between complex FP64 and FP32
+hipError_t convert_c64_c32(const cd* src, cf* dst, long long n, hipStream_t st);
+hipError_t convert_c32_c64(const cf* src, cd* dst, long long n, hipStream_t st);
 // true when y index `yi` of merged box (bx, by) lies on a physical side
 __host__ __device__ inline bool y_physical(const PhysSkip& s, int bx, int by, int yi) {
   const int k = s.ymap[yi];
@@ -81,8 +92,10 @@ __host__ __device__ inline bool y_physical(const PhysSkip& s, int bx, int by, in
 // ---- batched complex inversion (inverse.hip) -------------------------------
 // In-place inverse of `batch` m x m column-major matrices (stride `bstride`),
 // Gauss-Jordan with partial pivoting.  scratch: see inverse_scratch_bytes.
+template <class T>
 size_t inverse_scratch_bytes(int m, int batch);
-hipError_t zinverse(cd* A, int m, int lda, long long bstride, int batch, void* scratch,
+template <class T>
+hipError_t zinverse(T* A, int m, int lda, long long bstride, int batch, void* scratch,
                     int* flag, hipStream_t st);
 
 }  // namespace hps

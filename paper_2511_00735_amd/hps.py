@@ -46,7 +46,8 @@ class LevelView(ctypes.Structure):
     _fields_ = [("level", ctypes.c_int32), ("boxes", ctypes.c_int32),
                 ("box_nodes", ctypes.c_int32), ("morton", ctypes.c_int32),
                 ("T", ctypes.c_void_p), ("pairs", ctypes.c_int32),
-                ("shared_nodes", ctypes.c_int32), ("Winv", ctypes.c_void_p)]
+                ("shared_nodes", ctypes.c_int32), ("Winv", ctypes.c_void_p),
+                ("fp32", ctypes.c_int32)]
 
 
 _P = ctypes.c_void_p
@@ -260,16 +261,18 @@ class Problem:
         self.ctx.check(lib.hps_level_view_get(self.handle, level, ctypes.byref(v)), "level_view")
         return v
 
-    def _view(self, ptr, count):
+    def _view(self, ptr, count, fp32=False):
         off = ptr - self._ws_tensor.data_ptr()
-        raw = self._ws_tensor[off:off + 16 * count]
-        return raw.view(torch.complex128)
+        size = 8 if fp32 else 16
+        raw = self._ws_tensor[off:off + size * count]
+        return raw.view(torch.complex64 if fp32 else torch.complex128)
 
     def level_T(self, level):
-        """Box maps of a level as [boxes, b, b] (row, column), Morton box order."""
+        """Box maps of a level as [boxes, b, b] (row, column), Morton box order
+        (complex64 for the FP32 levels of mixed precision)."""
         v = self.level_view(level)
         b = v.box_nodes
-        t = self._view(v.T, v.boxes * b * b).view(v.boxes, b, b)
+        t = self._view(v.T, v.boxes * b * b, bool(v.fp32)).view(v.boxes, b, b)
         return t.transpose(1, 2)   # stored column-major
 
     def level_Winv(self, level):
@@ -277,7 +280,7 @@ class Problem:
         m = v.shared_nodes
         if not v.Winv:
             return None
-        return self._view(v.Winv, v.pairs * m * m).view(v.pairs, m, m).transpose(1, 2)
+        return self._view(v.Winv, v.pairs * m * m, bool(v.fp32)).view(v.pairs, m, m).transpose(1, 2)
 
 
 # ---- batch-first entry points (several problems per call) ------------------

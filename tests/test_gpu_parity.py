@@ -230,3 +230,58 @@ def test_graph_replays_match_eager(hps, ctx):
                 prob.skeleton_apply(r)          # unrelated eager work between replays
     finally:
         ctx.set_graphs(True)
+
+
+# ---- mixed precision: FP32 lower merges, FP64 top merges / coarse / outer ----
+
+def _mixed_problem(hps, ctx, pr, coarse_iters, levels=0):
+    desc = hps.make_desc(pr.n, pr.N, pr.kappa, pr.eta, levels=levels, coarse_iters=coarse_iters,
+                         precision=hps.HPS_MIXED)
+    prob = hps.Problem(ctx, desc)
+    prob.build_leaves(prob.coefficient_nodes(pr.b))
+    prob.merge_all()
+    return prob
+
+
+def test_mixed_levels_are_fp32_and_close(hps, ctx):
+    from oracle import mesh as omesh
+    n, N, kappa = 16, 6, 30.0
+    wave = workloads.PlaneWave(kappa, kappa)
+    oc = oracle_case(n, N, kappa, _bump, wave.t, None, with_direct=False)
+    desc = hps.make_desc(n, N, kappa, coarse_iters=-1, precision=hps.HPS_MIXED)
+    prob = hps.Problem(ctx, desc)
+    prob.build_leaves(prob.coefficient_nodes(_bump))
+    prob.merge_all()
+    L = prob.lmax
+    To = oracle_hierarchy(oc, L)
+    for level in range(1, L + 1):
+        v = prob.level_view(level)
+        assert v.fp32 == (1 if level <= L - 3 else 0), level
+        Tg = box_maps_by_xy(hps, prob, level)
+        for key, Tref in To[level - 1].items():
+            keep = np.arange(Tref.shape[0])
+            if level > 1:
+                keep = np.nonzero(~omesh.box_local_physical_mask(n, N - 1, level, *key))[0]
+            err = rel(Tg[key][np.ix_(keep, keep)].astype(np.complex128), Tref[np.ix_(keep, keep)])
+            # every merged level inherits the FP32 accuracy of the merges below it
+            assert err < 2e-5 * level, (level, key, err)
+
+
+def test_mixed_before_and_after_refinement(hps, ctx):
+    pr = workloads.c2()
+    oc = oracle_case(pr.n, pr.N, pr.kappa, pr.b, pr.wave.t)
+    # direct HPS with the mixed-precision tree: one V-cycle with the exact top solve
+    prob = _mixed_problem(hps, ctx, pr, coarse_iters=-1)
+    rhs = prob.set_rhs(prob.boundary_data(pr.wave.t))
+    g0 = prob.precond_apply(rhs).cpu().numpy()
+    before = rel(g0, oc["g"])
+    assert before < 1e-5, before
+    g, info = prob.gmres_solve(rhs, tol=1e-12)
+    after = rel(g.cpu().numpy(), oc["g"])
+    assert info["relres_true"] <= 1e-12 and after < 1e-10, (after, info)
+    print(f"[mixed c2] before refinement {before:.2e}, after {after:.2e}, its {info['iterations']}")
+    # iterative coarse solve (k = 5) in mixed precision reaches the same solution
+    prob5 = _mixed_problem(hps, ctx, pr, coarse_iters=5, levels=8)
+    rhs5 = prob5.set_rhs(prob5.boundary_data(pr.wave.t))
+    g5, info5 = prob5.gmres_solve(rhs5, tol=1e-12)
+    assert rel(g5.cpu().numpy(), oc["g"]) < 1e-10, info5
