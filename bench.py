@@ -40,6 +40,9 @@ def parse():
     ap.add_argument("--levels", type=int, default=12)
     ap.add_argument("--coarse-iters", type=int, default=5)
     ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the plain FP64 run of the same workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-seconds", type=float, default=15.0)
     return ap.parse_args()
@@ -129,22 +132,14 @@ def cpu_baseline(pr, sample_seconds):
     }
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no "
-              "multi-GPU path", file=sys.stderr)
-        sys.exit(2)
-    import torch
-    from paper_2511_00735_amd import hps, workloads
-
-    pr = workloads.c3()
-    pr.n, pr.N, pr.kappa, pr.eta = args.n, args.order, args.kappa, args.kappa
-    pr.levels, pr.coarse_iters, pr.tol = args.levels, args.coarse_iters, args.tol
-    pr.wave = workloads.PlaneWave(pr.kappa, pr.eta)
+def run_precision(args, pr, precision, hps, torch):
+    """Build + solve the workload `steps` times (after `warmup` untimed steps)
+    in one precision; returns timings, per-phase event times and the solution."""
     ctx = hps.Context()
     stream = ctx.stream
-    desc = hps.make_desc(pr.n, pr.N, pr.kappa, pr.eta, levels=pr.levels, coarse_iters=pr.coarse_iters)
+    prec = hps.HPS_MIXED if precision == "mixed" else hps.HPS_FP64
+    desc = hps.make_desc(pr.n, pr.N, pr.kappa, pr.eta, levels=pr.levels,
+                         coarse_iters=pr.coarse_iters, precision=prec)
     prob = hps.Problem(ctx, desc)
     b_nodes = prob.coefficient_nodes(pr.b)
     t_data = prob.boundary_data(pr.wave.t)
@@ -164,9 +159,6 @@ def main():
     infos = [step() for _ in range(args.steps)]
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    ms = 1e3 * dt / args.steps
-    dof = pr.skeleton_dof
-    value = dof * args.steps / dt
 
     # phase timing with events on the library's stream (outside the timed loop)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
@@ -176,12 +168,38 @@ def main():
     prob.merge_all()
     ev[2].record(stream)
     hps.set_rhs([prob], [t_data], [rhs])
-    info = prob.gmres_solve(rhs, tol=pr.tol, maxit=600, out=g)[1]
+    prob.gmres_solve(rhs, tol=pr.tol, maxit=600, out=g)
     ev[3].record(stream)
     torch.cuda.synchronize()
-    t_leaf = ev[0].elapsed_time(ev[1])
-    t_merge = ev[1].elapsed_time(ev[2])
-    t_solve = ev[2].elapsed_time(ev[3])
+    return {
+        "ms": 1e3 * dt / args.steps,
+        "value": pr.skeleton_dof * args.steps / dt,
+        "info": infos[-1],
+        "phase_ms": [ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2]), ev[2].elapsed_time(ev[3])],
+        "g": g.clone(),
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no "
+              "multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2511_00735_amd import hps, workloads
+
+    pr = workloads.c3()
+    pr.n, pr.N, pr.kappa, pr.eta = args.n, args.order, args.kappa, args.kappa
+    pr.levels, pr.coarse_iters, pr.tol = args.levels, args.coarse_iters, args.tol
+    pr.wave = workloads.PlaneWave(pr.kappa, pr.eta)
+    dof = pr.skeleton_dof
+
+    main_run = run_precision(args, pr, args.precision, hps, torch)
+    ref = None
+    if args.precision == "mixed" and not args.no_compare:
+        ref = run_precision(args, pr, "fp64", hps, torch)
+    t_leaf, t_merge, t_solve = main_run["phase_ms"]
     leaf_f = leaf_flops_executed(pr.N) * pr.n * pr.n
     merge_f, _ = merge_flops_executed(pr.n, pr.N, pr.levels)
     leaf_tf = leaf_f / (t_leaf * 1e-3) / 1e12
@@ -191,20 +209,30 @@ def main():
     roof = {"bound": "mfma", "achieved": round(ach, 3), "peak": MI355X_FP64_TFLOPS, "unit": "TFLOP/s",
             "frac": round(ach / MI355X_FP64_TFLOPS, 4), "traffic": None,
             "kernel": f"{dominant} phase (all launches of hps_{'merge_level' if dominant == 'merge' else 'build_leaves'})"}
+    info = main_run["info"]
+    cfg = {"workload": (f"{pr.n}x{pr.n} elements, N={pr.N}, kappa=eta={pr.kappa:g}, "
+                        f"8 seeded bumps (seed 3), plane-wave t, L={pr.levels}, "
+                        f"{pr.coarse_iters} coarse GMRES its, FGMRES(60) to {pr.tol:g}"),
+           "precision": args.precision, "skeleton_dof": dof,
+           "iterations": info["iterations"], "relres_true": info["relres_true"],
+           "phase_ms": {"leaves": round(t_leaf, 3), "merges": round(t_merge, 3),
+                        "rhs+solve": round(t_solve, 3)},
+           "phase_tflops": {"leaves": round(leaf_tf, 3), "merges": round(merge_tf, 3)}}
+    if ref is not None:
+        gm, gf = main_run["g"], ref["g"]
+        cfg["fp64_same_gpu"] = {
+            "value": round(ref["value"], 1), "ms_per_step": round(ref["ms"], 3),
+            "iterations": ref["info"]["iterations"], "relres_true": ref["info"]["relres_true"],
+            "phase_ms": {"leaves": round(ref["phase_ms"][0], 3), "merges": round(ref["phase_ms"][1], 3),
+                         "rhs+solve": round(ref["phase_ms"][2], 3)}}
+        cfg["mixed_over_fp64"] = round(main_run["value"] / ref["value"], 3)
+        cfg["rel_diff_mixed_vs_fp64_solution"] = float(torch.linalg.norm(gm - gf) / torch.linalg.norm(gf))
     out = {
-        "metric": METRIC, "value": round(value, 1), "unit": UNIT, "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c128",
-        "data": "synthetic",
-        "config": {"workload": (f"{pr.n}x{pr.n} elements, N={pr.N}, kappa=eta={pr.kappa:g}, "
-                                f"8 seeded bumps (seed 3), plane-wave t, L={pr.levels}, "
-                                f"{pr.coarse_iters} coarse GMRES its, FGMRES(60) to {pr.tol:g}"),
-                   "precision": "fp64", "skeleton_dof": dof,
-                   "iterations": infos[-1]["iterations"], "relres_true": infos[-1]["relres_true"],
-                   "phase_ms": {"leaves": round(t_leaf, 3), "merges": round(t_merge, 3),
-                                "rhs+solve": round(t_solve, 3)},
-                   "phase_tflops": {"leaves": round(leaf_tf, 3), "merges": round(merge_tf, 3)}},
-        "roofline": roof,
+        "metric": METRIC, "value": round(main_run["value"], 1), "unit": UNIT, "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(main_run["ms"], 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "c64+c128" if args.precision == "mixed" else "c128",
+        "data": "synthetic", "config": cfg, "roofline": roof,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pr, args.cpu_sample_seconds)

@@ -105,10 +105,16 @@ typedef struct {
                             boundary order [l; r; b; t]; FP64                  */
   int32_t pairs;         /* pairs merged at this level (0 at the top)          */
   int32_t shared_nodes;  /* m = length of the shared face                      */
-  const void* Winv;      /* complex [pairs][m][m] column-major: the inverse of
-                            W = I - T^P_aa T^Q_bb (the m x m Schur complement
-                            of A = [[I, -T^P_aa], [-T^Q_bb, I]])              */
-  int32_t fp32;          /* 1: T and Winv are complex FP32 (mixed precision,
+  /* Pair j merges boxes P = 2j and Q = 2j+1.  Its shared-face unknowns are
+     x = [f^Q_beta; f^P_alpha] (2m) and its kept faces y = [P.E1; Q.E2] (2e,
+     each child's sides in [l; r; b; t] order without the shared side).        */
+  const void* Ainv;      /* complex [pairs][2m][2m] column-major: A^-1 with
+                            A = [[I, -T^P_aa], [-T^Q_bb, I]] (the shared-face
+                            block of the level's skeleton system)              */
+  const void* X;         /* complex [pairs][2m][2e] column-major: A^-1 B with
+                            B = blkdiag(T^P_{a,E1}, T^Q_{b,E2}); columns of y on
+                            physical sides are 0.  NULL at the top.           */
+  int32_t fp32;          /* 1: T, Ainv and X are complex FP32 (mixed precision,
                             levels 1 .. L-3; level 1 then shows the FP32 copy
                             used by the preconditioner); 0: complex FP64      */
 } hps_level_view;

@@ -38,9 +38,14 @@ struct Level {
   int pairs = 0, m = 0, e = 0, axis = 0, a0 = 0, b0 = 0;
   IdxMap E1{}, E2{};
   bool has_merge = false;
-  size_t Winv_off = 0;
-  size_t map_off = 0;  // int32 [2e]: merged-box position of y = [P.E1; Q.E2]
-  size_t R1_off = 0, R2_off = 0;  // V-cycle residual pieces kept between sweeps
+  // Per pair, with x = [Q.beta; P.alpha] (2m) and y = [P.E1; Q.E2] (2e):
+  size_t Ainv_off = 0;  // [pairs][2m][2m] A^-1, A = [[I, -T^P_aa], [-T^Q_bb, I]]
+  size_t X_off = 0;     // [pairs][2m][2e] A^-1 B (the shared-face data as a function of y)
+  size_t map_off = 0;   // int32 [2e]: merged-box position of y
+  size_t xtab_off = 0;  // int32 [pairs][2m]: canonical slots of x
+  size_t ytab_off = 0;  // int32 [pairs][2e]: canonical slots of y (-1: physical)
+  size_t dtab_off = 0;  // int32 [pairs][2e]: slots across the face of y (-1: physical)
+  size_t Z0_off = 0;    // complex FP64 [pairs][2m]: A^-1 r_x of the down sweep
 };
 
 struct Layout {
@@ -54,8 +59,6 @@ struct Layout {
   std::vector<Level> lev;  // 1..L
   size_t scratch_off, scratch_bytes;
   size_t V_off, Z_off, work_off;  // Krylov bases and 5 canonical work vectors
-  size_t vtmp_off;                // V-cycle transients: V1, X1, X2 [pairs][m], DP, DQ [pairs][e]
-  size_t vtmp_m, vtmp_e;          // max pairs*m and pairs*e over levels
   size_t cV_off, cw_off, cx_off, cidx_off, cH_off, cy_off, cs_off;  // coarse GMRES
   size_t part_off, hh_off, one_off, flag_off;
   size_t gpart_off, gpart_elems;  // split-K GEMV partial sums
@@ -139,6 +142,38 @@ std::vector<int> coarse_slots(const Level& lv) {
   return out;
 }
 
+// Slot tables of a level's pairs (pair j: P = box 2j, Q = box 2j+1):
+// x = [Q.beta; P.alpha] (never physical), y = [P.E1; Q.E2] and the slots
+// across the face of y; physical entries of y are -1.
+void pair_tables(const Level& lv, std::vector<int>& xt, std::vector<int>& yt, std::vector<int>& dt) {
+  const Geom& g = lv.g;
+  xt.clear();
+  yt.clear();
+  dt.clear();
+  for (int j = 0; j < lv.pairs; ++j) {
+    int px, py, qx, qy;
+    box_xy(g, 2 * j, px, py);
+    box_xy(g, 2 * j + 1, qx, qy);
+    for (int i = 0; i < lv.m; ++i) xt.push_back(box_slot(g, qx, qy, lv.b0 + i));
+    for (int i = 0; i < lv.m; ++i) xt.push_back(box_slot(g, px, py, lv.a0 + i));
+    for (int side = 0; side < 2; ++side) {
+      const int bx = side ? qx : px, by = side ? qy : py;
+      const IdxMap& E = side ? lv.E2 : lv.E1;
+      for (int i = 0; i < lv.e; ++i) {
+        const int k = imap(E, i);
+        if (side_physical(g, bx, by, side_of(g, k))) {
+          yt.push_back(-1);
+          dt.push_back(-1);
+        } else {
+          const int s = box_slot(g, bx, by, k);
+          yt.push_back(s);
+          dt.push_back(slot_partner(g.n, g.p, s));
+        }
+      }
+    }
+  }
+}
+
 const char* check_desc(const hps_desc* d) {
   if (!d) return "null descriptor";
   if (d->n < 2 || d->n > 1024 || (d->n & (d->n - 1))) return "n must be a power of two in [2, 1024]";
@@ -178,7 +213,6 @@ Layout make_layout(const hps_desc* d) {
   lay.H_off = take(sizeof(cd) * (size_t)lay.E * 4 * lay.p);
   lay.lev.resize(lay.L + 1);
   size_t merge_scratch = 0;
-  lay.vtmp_m = lay.vtmp_e = 1;
   for (int l = 1; l <= lay.L; ++l) {
     Level& lv = lay.lev[l];
     lv = make_level(lay.n, lay.p, l);
@@ -191,14 +225,16 @@ Layout make_layout(const hps_desc* d) {
     if (lay.mixed && l == lay.L - 2 && l >= 2) lay.stage_off = take(sizeof(cf) * nmap);
     if (l < lay.L || (lay.exact && l == lay.L)) {
       set_merge_geom(lv);
-      lv.Winv_off = take((lv.f32 ? sizeof(cf) : sizeof(cd)) * (size_t)lv.pairs * lv.m * lv.m);
+      const size_t es = lv.f32 ? sizeof(cf) : sizeof(cd);
+      lv.Ainv_off = take(es * (size_t)lv.pairs * 4 * lv.m * lv.m);
+      if (l < lay.L) lv.X_off = take(es * (size_t)lv.pairs * 4 * lv.m * lv.e);
       lv.map_off = take(sizeof(int) * 2 * (size_t)lv.e);
-      lv.R1_off = take(sizeof(cd) * (size_t)lv.pairs * lv.m);
-      lv.R2_off = take(sizeof(cd) * (size_t)lv.pairs * lv.m);
+      lv.xtab_off = take(sizeof(int) * (size_t)lv.pairs * 2 * lv.m);
+      lv.ytab_off = take(sizeof(int) * (size_t)lv.pairs * 2 * lv.e);
+      lv.dtab_off = take(sizeof(int) * (size_t)lv.pairs * 2 * lv.e);
+      lv.Z0_off = take(sizeof(cd) * (size_t)lv.pairs * 2 * lv.m);
       const size_t zbytes = sizeof(cd) * (size_t)lv.pairs * lv.m * 2 * lv.e;
-      merge_scratch = std::max(merge_scratch, 3 * up256(zbytes) + up256(inverse_scratch_bytes<cd>(lv.m, lv.pairs)));
-      lay.vtmp_m = std::max(lay.vtmp_m, (size_t)lv.pairs * lv.m);
-      lay.vtmp_e = std::max(lay.vtmp_e, (size_t)lv.pairs * lv.e);
+      merge_scratch = std::max(merge_scratch, up256(zbytes) + up256(inverse_scratch_bytes<cd>(lv.m, lv.pairs)));
     }
   }
   lay.scratch_bytes = std::max(merge_scratch, sizeof(double) * leaf_scratch_doubles(lay.N, lay.leaf_chunk));
@@ -207,7 +243,6 @@ Layout make_layout(const hps_desc* d) {
   lay.V_off = take(vb * (lay.restart + 1));
   lay.Z_off = take(vb * lay.restart);
   lay.work_off = take(up256(vb) * 7);
-  lay.vtmp_off = take(sizeof(cd) * (3 * lay.vtmp_m + 2 * lay.vtmp_e) + 5 * 256);
   {
     Level& top = lay.lev[lay.L];
     int nL = 0;
@@ -232,7 +267,8 @@ Layout make_layout(const hps_desc* d) {
   lay.one_off = take(sizeof(cd));
   {
     // split-K GEMV partials: at most two descriptors per launch, of the shapes
-    // (m x m), (e x m), (m x e) per merge level and (nL/2 x nL/2) for the coarse pair
+    // (2m x 2m), (e x m), (2m x 2e) per merge level and (nL/2 x nL/2) for the
+    // coarse pair
     size_t mx = 0;
     auto need = [&](int M, int K, int batch) {
       const int ns = gemv_nsplit(M, K, batch);
@@ -241,9 +277,9 @@ Layout make_layout(const hps_desc* d) {
     for (int l = 1; l <= lay.L; ++l) {
       const Level& lv = lay.lev[l];
       if (!lv.has_merge) continue;
-      need(lv.m, lv.m, lv.pairs);
+      need(2 * lv.m, 2 * lv.m, lv.pairs);
       need(lv.e, lv.m, lv.pairs);
-      need(lv.m, lv.e, lv.pairs);
+      need(2 * lv.m, 2 * lv.e, lv.pairs);
     }
     if (lay.nL > 0) need(lay.nL / 2, lay.nL / 2, 1);
     lay.gpart_elems = 2 * mx + 64;
@@ -296,6 +332,10 @@ cd* Tlev(hps_problem* p, int l) { return at<cd>(p, p->lay.lev[l].T_off); }
 // ---- merge of one level (1 <= l < L): level-l pairs -> level-(l+1) boxes --
 // T is the precision of this merge (complex FP64 or FP32); Tin are the level-l
 // box maps and Tout receives the level-(l+1) maps, both in that precision.
+// Besides the merged maps it leaves, per pair, the explicit A^-1 and X = A^-1 B
+// that the V-cycle applies (Sec. 4.3): with W = I - T^P_aa T^Q_bb,
+//   A^-1 = [[W^-1, W^-1 T^P_aa], [T^Q_bb W^-1, I + T^Q_bb W^-1 T^P_aa]].
+// At the top of an exact solve (l == L) only A^-1 is formed.
 template <class T>
 hps_status merge_impl(hps_problem* p, int l, const T* Tin, T* Tout) {
   typedef OperandT<T> Operand;
@@ -304,33 +344,55 @@ hps_status merge_impl(hps_problem* p, int l, const T* Tin, T* Tout) {
   hipStream_t st = c->stream;
   const Layout& lay = p->lay;
   const Level& lv = lay.lev[l];
-  const int b = lv.g.b, m = lv.m, e = lv.e, np = lv.pairs;
+  const int b = lv.g.b, m = lv.m, e = lv.e, np = lv.pairs, m2 = 2 * m;
   const long long pstride = 2LL * b * b;
   const T* TP = Tin;
   const T* TQ = Tin + (size_t)b * b;
-  T* Winv = at<T>(p, lv.Winv_off);
+  T* Ai = at<T>(p, lv.Ainv_off);
+  const long long as = (long long)m2 * m2;
+  T* A11 = Ai;
+  T* A21 = Ai + m;
+  T* A12 = Ai + (size_t)m * m2;
+  T* A22 = A12 + m;
   const T one = cx<T>::make(1, 0), zero = cx<T>::make(0, 0), mone = cx<T>::make(-1, 0);
   const Operand none{nullptr, 0, 0, im_off(0), im_off(0)};
   int* flag = at<int>(p, lay.flag_off);
-  // W = I - T^P_aa T^Q_bb
+  // W = I - T^P_aa T^Q_bb, inverted in place in the (1,1) block of A^-1
   {
     GemmArgs g{};
     g.M = m; g.N = m; g.K = m; g.batch = np;
     g.A = Operand{TP, pstride, b, im_off(lv.a0), im_off(lv.a0)};
     g.B = Operand{TQ, pstride, b, im_off(lv.b0), im_off(lv.b0)};
     g.alpha = mone; g.beta = zero; g.C = none;
-    g.D = Winv; g.Dstride = (long long)m * m; g.ldd = m; g.dr = im_off(0); g.dc = im_off(0);
+    g.D = A11; g.Dstride = as; g.ldd = m2; g.dr = im_off(0); g.dc = im_off(0);
     g.diag_add = one; g.has_diag = 1;
     HIPCHK(c, zgemm(g, st));
   }
   char* scr = at<char>(p, lay.scratch_off);
   const size_t zb = up256(sizeof(cd) * (size_t)np * m * 2 * e);
   T* Z = reinterpret_cast<T*>(scr);
-  T* YQ = reinterpret_cast<T*>(scr + zb);
-  T* YP = reinterpret_cast<T*>(scr + 2 * zb);
-  void* invs = scr + 3 * zb;
-  HIPCHK(c, zinverse<T>(Winv, m, m, (long long)m * m, np, invs, flag, st));
-  if (l == lay.L) return HPS_OK;  // exact top: only W^-1 is needed
+  void* invs = scr + zb;
+  HIPCHK(c, zinverse<T>(A11, m, m2, as, np, invs, flag, st));
+  // A12 = W^-1 T^P_aa, A21 = T^Q_bb W^-1, A22 = I + T^Q_bb A12
+  {
+    GemmArgs g{};
+    g.M = m; g.N = m; g.K = m; g.batch = np;
+    g.alpha = one; g.beta = zero; g.C = none;
+    g.Dstride = as; g.ldd = m2; g.dr = im_off(0); g.dc = im_off(0);
+    g.A = Operand{A11, as, m2, im_off(0), im_off(0)};
+    g.B = Operand{TP, pstride, b, im_off(lv.a0), im_off(lv.a0)};
+    g.D = A12;
+    HIPCHK(c, zgemm(g, st));
+    g.A = Operand{TQ, pstride, b, im_off(lv.b0), im_off(lv.b0)};
+    g.B = Operand{A11, as, m2, im_off(0), im_off(0)};
+    g.D = A21;
+    HIPCHK(c, zgemm(g, st));
+    g.B = Operand{A12, as, m2, im_off(0), im_off(0)};
+    g.D = A22;
+    g.diag_add = one; g.has_diag = 1;
+    HIPCHK(c, zgemm(g, st));
+  }
+  if (l == lay.L) return HPS_OK;  // exact top: only A^-1 is needed
   const long long zs = (long long)m * 2 * e;
   const Level& nx = lay.lev[l + 1];
   const int* mp = at<int>(p, lv.map_off);
@@ -360,28 +422,32 @@ hps_status merge_impl(hps_problem* p, int l, const T* Tin, T* Tout) {
     g.skip = sk_ce;
     HIPCHK(c, zgemm(g, st));
   }
-  // YQ = W^-1 Z   (the shared-face data f^Q_b as a function of y)
+  // X = A^-1 B: rows [0, m) YQ = W^-1 Z (f^Q_b as a function of y), rows
+  // [m, 2m) YP = T^Q_bb YQ + [0 | T^Q_{b,E2}] (f^P_a)
+  T* X = at<T>(p, lv.X_off);
+  const long long xs = (long long)m2 * 2 * e;
+  T* YQ = X;
+  T* YP = X + m;
   {
     GemmArgs g{};
     g.M = m; g.N = 2 * e; g.K = m; g.batch = np;
-    g.A = Operand{Winv, (long long)m * m, m, im_off(0), im_off(0)};
+    g.A = Operand{A11, as, m2, im_off(0), im_off(0)};
     g.B = Operand{Z, zs, m, im_off(0), im_off(0)};
     g.alpha = one; g.beta = zero; g.C = none;
-    g.D = YQ; g.Dstride = zs; g.ldd = m; g.dr = im_off(0); g.dc = im_off(0);
+    g.D = YQ; g.Dstride = xs; g.ldd = m2; g.dr = im_off(0); g.dc = im_off(0);
     g.skip = sk_c0;
     HIPCHK(c, zgemm(g, st));
   }
-  // YP = T^Q_bb YQ + [0 | T^Q_{b,E2}]   (f^P_a as a function of y)
-  HIPCHK(c, zcopy2d(m, e, np, none, one, YP, zs, m, im_off(0), im_off(0), st, &sk_c0));
-  HIPCHK(c, zcopy2d(m, e, np, Operand{TQ, pstride, b, im_off(lv.b0), lv.E2}, one, YP, zs, m, im_off(0),
+  HIPCHK(c, zcopy2d(m, e, np, none, one, YP, xs, m2, im_off(0), im_off(0), st, &sk_c0));
+  HIPCHK(c, zcopy2d(m, e, np, Operand{TQ, pstride, b, im_off(lv.b0), lv.E2}, one, YP, xs, m2, im_off(0),
                     im_off(e), st, &sk_ce));
   {
     GemmArgs g{};
     g.M = m; g.N = 2 * e; g.K = m; g.batch = np;
     g.A = Operand{TQ, pstride, b, im_off(lv.b0), im_off(lv.b0)};
-    g.B = Operand{YQ, zs, m, im_off(0), im_off(0)};
-    g.alpha = one; g.beta = one; g.C = Operand{YP, zs, m, im_off(0), im_off(0)};
-    g.D = YP; g.Dstride = zs; g.ldd = m; g.dr = im_off(0); g.dc = im_off(0);
+    g.B = Operand{YQ, xs, m2, im_off(0), im_off(0)};
+    g.alpha = one; g.beta = one; g.C = Operand{YP, xs, m2, im_off(0), im_off(0)};
+    g.D = YP; g.Dstride = xs; g.ldd = m2; g.dr = im_off(0); g.dc = im_off(0);
     g.skip = sk_c0;
     HIPCHK(c, zgemm(g, st));
   }
@@ -399,13 +465,13 @@ hps_status merge_impl(hps_problem* p, int l, const T* Tin, T* Tout) {
     GemmArgs g{};
     g.M = e; g.N = 2 * e; g.K = m; g.batch = np;
     g.A = Operand{TP, pstride, b, lv.E1, im_off(lv.a0)};
-    g.B = Operand{YP, zs, m, im_off(0), im_off(0)};
+    g.B = Operand{YP, xs, m2, im_off(0), im_off(0)};
     g.alpha = one; g.beta = one; g.C = Operand{Tn, ns, bn, rowP, im_tab(mp)};
     g.D = Tn; g.Dstride = ns; g.ldd = bn; g.dr = rowP; g.dc = im_tab(mp);
     g.skip = s00;
     HIPCHK(c, zgemm(g, st));
     g.A = Operand{TQ, pstride, b, lv.E2, im_off(lv.b0)};
-    g.B = Operand{YQ, zs, m, im_off(0), im_off(0)};
+    g.B = Operand{YQ, xs, m2, im_off(0), im_off(0)};
     g.C = Operand{Tn, ns, bn, rowQ, im_tab(mp)};
     g.dr = rowQ;
     g.skip = se0;
@@ -437,21 +503,6 @@ hps_status merge_one(hps_problem* p, int l) {
 }
 
 // ---- V-cycle -------------------------------------------------------------
-struct VTmp {
-  cd *V1, *X1, *X2, *DP, *DQ;
-};
-VTmp vtmp(hps_problem* p) {
-  const Layout& lay = p->lay;
-  char* b = at<char>(p, lay.vtmp_off);
-  VTmp t;
-  t.V1 = reinterpret_cast<cd*>(b);
-  t.X1 = t.V1 + lay.vtmp_m;
-  t.X2 = t.X1 + lay.vtmp_m;
-  t.DP = t.X2 + lay.vtmp_m;
-  t.DQ = t.DP + lay.vtmp_e;
-  return t;
-}
-
 bool small_level(const Level& lv) {
   return lv.pairs >= 128 && lv.m <= 256 && small_level_lds(lv.m, lv.e) <= 64 * 1024;
 }
@@ -467,9 +518,12 @@ SmallLevelT<M> small_args(hps_problem* p, const Level& lv) {
   a.E1 = lv.E1;
   a.E2 = lv.E2;
   a.T = Tmat<M>(p, lv.g.level);
-  a.Winv = at<M>(p, lv.Winv_off);
-  a.R1 = at<cd>(p, lv.R1_off);
-  a.R2 = at<cd>(p, lv.R2_off);
+  a.Ainv = at<M>(p, lv.Ainv_off);
+  a.X = lv.X_off ? at<M>(p, lv.X_off) : nullptr;
+  a.xtab = at<int>(p, lv.xtab_off);
+  a.ytab = at<int>(p, lv.ytab_off);
+  a.dtab = at<int>(p, lv.dtab_off);
+  a.Z0 = at<cd>(p, lv.Z0_off);
   return a;
 }
 
@@ -487,6 +541,19 @@ VecIn vin_gather(const cd* vec, const Geom& g, int which, IdxMap local, bool par
   v.local = local;
   v.partner = partner ? 1 : 0;
   return v;
+}
+VecIn vin_table(const cd* vec, const int* tab, long long tstride) {
+  VecIn v{};
+  v.vec = vec;
+  v.tab = tab;
+  v.tstride = tstride;
+  return v;
+}
+void vout_table(VecOut& v, cd* vec, const int* tab, long long tstride, bool add) {
+  v.vec = vec;
+  v.tab = tab;
+  v.tstride = tstride;
+  v.add = add ? 1 : 0;
 }
 VecOut vout_compact(cd* ptr, long long stride, const cd* y0 = nullptr, long long y0s = 0) {
   VecOut v{};
@@ -517,34 +584,10 @@ GemvDescT<M> gdesc(int Mr, int K, OperandT<M> A, VecIn x, VecOut y, cd alpha = c
   return d;
 }
 
-// Shared-face solve x = A^-1 r for every pair of a level, r = (r1 at Q.beta,
-// r2 at P.alpha) compact: x1 = W^-1 (r1 + T^P_aa r2), x2 = r2 + T^Q_bb x1.
-// x1 and x2 go to compact buffers and, when zout != null, into zout at Q.beta
-// and P.alpha.  M is the storage precision of the level's operators.
-template <class M>
-hps_status pair_solve(hps_problem* p, const Level& lv, const cd* r1, const cd* r2, cd* V1, cd* x1, cd* x2,
-                      cd* zout) {
-  hps_ctx* c = p->ctx;
-  hipStream_t st = c->stream;
-  const int b = lv.g.b, m = lv.m, np = lv.pairs;
-  const long long ps = 2LL * b * b;
-  const M* T = Tmat<M>(p, lv.g.level);
-  const M* Wi = at<M>(p, lv.Winv_off);
-  cd* part = at<cd>(p, p->lay.gpart_off);
-  GemvDescT<M> d = gdesc<M>(m, m, OperandT<M>{T, ps, b, im_off(lv.a0), im_off(lv.a0)}, vin_compact(r2, m),
-                            vout_compact(V1, m, r1, m));
-  HIPCHK(c, zgemv_batched(&d, 1, np, part, st));
-  VecOut o1 = vout_compact(x1, m);
-  if (zout) vout_scatter(o1, zout, lv.g, 1, im_off(lv.b0), false, false);
-  d = gdesc<M>(m, m, OperandT<M>{Wi, (long long)m * m, m, im_off(0), im_off(0)}, vin_compact(V1, m), o1);
-  HIPCHK(c, zgemv_batched(&d, 1, np, part, st));
-  VecOut o2 = vout_compact(x2, m, r2, m);
-  if (zout) vout_scatter(o2, zout, lv.g, 0, im_off(lv.a0), false, false);
-  d = gdesc<M>(m, m, OperandT<M>{T + (size_t)b * b, ps, b, im_off(lv.b0), im_off(lv.b0)}, vin_compact(x1, m), o2);
-  HIPCHK(c, zgemv_batched(&d, 1, np, part, st));
-  return HPS_OK;
-}
-
+// Down sweep of level l on the residual w (canonical, updated in place):
+// z0 = A^-1 r_x for every pair (kept in Z0), then the rows across the kept
+// faces receive C~ z0: w[Pi(P.E1)] += T^P_{E1,a} z0_P, w[Pi(Q.E2)] += T^Q_{E2,b} z0_Q.
+// M is the storage precision of the level's operators.
 template <class M>
 hps_status vcycle_down_t(hps_problem* p, int l, cd* wv) {
   hps_ctx* c = p->ctx;
@@ -554,28 +597,27 @@ hps_status vcycle_down_t(hps_problem* p, int l, cd* wv) {
     HIPCHK(c, vc_down_small(small_args<M>(p, lv), lv.pairs, wv, st));
     return HPS_OK;
   }
-  const int b = lv.g.b, m = lv.m, e = lv.e, np = lv.pairs;
+  const int b = lv.g.b, m = lv.m, e = lv.e, np = lv.pairs, m2 = 2 * m;
   const long long ps = 2LL * b * b;
   const M* T = Tmat<M>(p, l);
-  cd* R1 = at<cd>(p, lv.R1_off);
-  cd* R2 = at<cd>(p, lv.R2_off);
-  VTmp t = vtmp(p);
-  HIPCHK(c, pair_gather(lv.g, np, 1, im_off(lv.b0), m, wv, R1, m, false, st));
-  HIPCHK(c, pair_gather(lv.g, np, 0, im_off(lv.a0), m, wv, R2, m, false, st));
-  hps_status s = pair_solve<M>(p, lv, R1, R2, t.V1, t.X1, t.X2, nullptr);
-  if (s != HPS_OK) return s;
-  // deposits C~ x0 into the rows of the kept faces: w[Pi(P.E1)] += T^P_{E1,a} x2,
-  // w[Pi(Q.E2)] += T^Q_{E2,b} x1
+  cd* Z0 = at<cd>(p, lv.Z0_off);
+  const int* dtab = at<int>(p, lv.dtab_off);
+  cd* part = at<cd>(p, p->lay.gpart_off);
+  GemvDescT<M> d0 = gdesc<M>(m2, m2, OperandT<M>{at<M>(p, lv.Ainv_off), (long long)m2 * m2, m2, im_off(0), im_off(0)},
+                             vin_table(wv, at<int>(p, lv.xtab_off), m2), vout_compact(Z0, m2));
+  HIPCHK(c, zgemv_batched(&d0, 1, np, part, st));
   VecOut oP{}, oQ{};
-  vout_scatter(oP, wv, lv.g, 0, lv.E1, true, true);
-  vout_scatter(oQ, wv, lv.g, 1, lv.E2, true, true);
-  GemvDescT<M> d[2] = {gdesc<M>(e, m, OperandT<M>{T, ps, b, lv.E1, im_off(lv.a0)}, vin_compact(t.X2, m), oP),
+  vout_table(oP, wv, dtab, 2 * e, true);
+  vout_table(oQ, wv, dtab + e, 2 * e, true);
+  GemvDescT<M> d[2] = {gdesc<M>(e, m, OperandT<M>{T, ps, b, lv.E1, im_off(lv.a0)}, vin_compact(Z0 + m, m2), oP),
                        gdesc<M>(e, m, OperandT<M>{T + (size_t)b * b, ps, b, lv.E2, im_off(lv.b0)},
-                                vin_compact(t.X1, m), oQ)};
-  HIPCHK(c, zgemv_batched(d, 2, np, at<cd>(p, p->lay.gpart_off), st));
+                                vin_compact(Z0, m2), oQ)};
+  HIPCHK(c, zgemv_batched(d, 2, np, part, st));
   return HPS_OK;
 }
 
+// Up sweep of level l: x = z0 + X y with y the kept-face values already in z,
+// written into z at the shared-face slots.
 template <class M>
 hps_status vcycle_up_t(hps_problem* p, int l, cd* z) {
   hps_ctx* c = p->ctx;
@@ -585,19 +627,14 @@ hps_status vcycle_up_t(hps_problem* p, int l, cd* z) {
     HIPCHK(c, vc_up_small(small_args<M>(p, lv), lv.pairs, z, st));
     return HPS_OK;
   }
-  const int b = lv.g.b, m = lv.m, e = lv.e, np = lv.pairs;
-  const long long ps = 2LL * b * b;
-  const M* T = Tmat<M>(p, l);
-  const cd* R1 = at<cd>(p, lv.R1_off);
-  const cd* R2 = at<cd>(p, lv.R2_off);
-  VTmp t = vtmp(p);
-  // r' = r_x + B y with y the kept-face data already in z
-  GemvDescT<M> d[2] = {gdesc<M>(m, e, OperandT<M>{T, ps, b, im_off(lv.a0), lv.E1}, vin_gather(z, lv.g, 0, lv.E1, false),
-                                vout_compact(t.DP, m, R1, m)),
-                       gdesc<M>(m, e, OperandT<M>{T + (size_t)b * b, ps, b, im_off(lv.b0), lv.E2},
-                                vin_gather(z, lv.g, 1, lv.E2, false), vout_compact(t.DQ, m, R2, m))};
-  HIPCHK(c, zgemv_batched(d, 2, np, at<cd>(p, p->lay.gpart_off), st));
-  return pair_solve<M>(p, lv, t.DP, t.DQ, t.V1, t.X1, t.X2, z);
+  const int m2 = 2 * lv.m, e2 = 2 * lv.e, np = lv.pairs;
+  const cd* Z0 = at<cd>(p, lv.Z0_off);
+  VecOut o = vout_compact(nullptr, 0, Z0, m2);
+  vout_table(o, z, at<int>(p, lv.xtab_off), m2, false);
+  GemvDescT<M> d = gdesc<M>(m2, e2, OperandT<M>{at<M>(p, lv.X_off), (long long)m2 * e2, m2, im_off(0), im_off(0)},
+                            vin_table(z, at<int>(p, lv.ytab_off), e2), o);
+  HIPCHK(c, zgemv_batched(&d, 1, np, at<cd>(p, p->lay.gpart_off), st));
+  return HPS_OK;
 }
 
 hps_status vcycle_down(hps_problem* p, int l, cd* wv) {
@@ -665,13 +702,15 @@ hps_status coarse_solve(hps_problem* p, cd* wv, cd* z) {
   const Layout& lay = p->lay;
   const Level& top = lay.lev[lay.L];
   if (lay.exact) {
-    const int m = top.m;
-    VTmp t = vtmp(p);
-    cd* R1 = at<cd>(p, top.R1_off);
-    cd* R2 = at<cd>(p, top.R2_off);
-    HIPCHK(c, pair_gather(top.g, 1, 1, im_off(top.b0), m, wv, R1, m, false, st));
-    HIPCHK(c, pair_gather(top.g, 1, 0, im_off(top.a0), m, wv, R2, m, false, st));
-    return pair_solve<cd>(p, top, R1, R2, t.V1, t.X1, t.X2, z);
+    // z at the top pair's shared face = A_L^-1 r_x
+    const int m2 = 2 * top.m;
+    const int* xtab = at<int>(p, top.xtab_off);
+    VecOut o = vout_compact(nullptr, 0);
+    vout_table(o, z, xtab, m2, false);
+    GemvDesc d = gdesc<cd>(m2, m2, Operand{at<cd>(p, top.Ainv_off), (long long)m2 * m2, m2, im_off(0), im_off(0)},
+                           vin_table(wv, xtab, m2), o);
+    HIPCHK(c, zgemv_batched(&d, 1, 1, at<cd>(p, lay.gpart_off), st));
+    return HPS_OK;
   }
   const int nL = lay.nL, k = lay.k;
   if (nL == 0) return HPS_OK;
@@ -1008,6 +1047,11 @@ hps_status hps_problem_create(hps_ctx* ctx, const hps_desc* desc, void* workspac
     if (!lv.has_merge) continue;
     std::vector<int> mp = merge_map(lv);
     HIPCHK(ctx, hipMemcpy(p->ws + lv.map_off, mp.data(), sizeof(int) * mp.size(), hipMemcpyHostToDevice));
+    std::vector<int> xt, yt, dt;
+    pair_tables(lv, xt, yt, dt);
+    HIPCHK(ctx, hipMemcpy(p->ws + lv.xtab_off, xt.data(), sizeof(int) * xt.size(), hipMemcpyHostToDevice));
+    HIPCHK(ctx, hipMemcpy(p->ws + lv.ytab_off, yt.data(), sizeof(int) * yt.size(), hipMemcpyHostToDevice));
+    HIPCHK(ctx, hipMemcpy(p->ws + lv.dtab_off, dt.data(), sizeof(int) * dt.size(), hipMemcpyHostToDevice));
   }
   if (!lay.exact && lay.nL > 0) {
     std::vector<int> idx = coarse_slots(lay.lev[lay.L]);
@@ -1023,6 +1067,12 @@ hps_status hps_problem_create(hps_ctx* ctx, const hps_desc* desc, void* workspac
     HIPCHK(ctx, vfill(Tlev(p, l), lv.f32 ? (nmap + 1) / 2 : nmap, cmk(0, 0), ctx->stream));
     if (lay.mixed && l == lay.L - 2 && l >= 2)
       HIPCHK(ctx, vfill(at<cd>(p, lay.stage_off), (nmap + 1) / 2, cmk(0, 0), ctx->stream));
+  }
+  // Columns of X = A^-1 B on physical sides are likewise never computed.
+  for (int l = 1; l < lay.L; ++l) {
+    const Level& lv = lay.lev[l];
+    const long long nx = (long long)lv.pairs * 4 * lv.m * lv.e;
+    HIPCHK(ctx, vfill(at<cd>(p, lv.X_off), lv.f32 ? (nx + 1) / 2 : nx, cmk(0, 0), ctx->stream));
   }
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
   int zero4[4] = {0, 0, 0, 0};
@@ -1050,7 +1100,8 @@ hps_status hps_level_view_get(const hps_problem* pc, int32_t level, hps_level_vi
   out->fp32 = lv.f32 ? 1 : 0;
   out->pairs = lv.has_merge ? lv.pairs : 0;
   out->shared_nodes = lv.has_merge ? lv.m : 0;
-  out->Winv = lv.has_merge ? (const void*)(p->ws + lv.Winv_off) : nullptr;
+  out->Ainv = lv.has_merge ? (const void*)(p->ws + lv.Ainv_off) : nullptr;
+  out->X = (lv.has_merge && lv.X_off) ? (const void*)(p->ws + lv.X_off) : nullptr;
   return HPS_OK;
 }
 

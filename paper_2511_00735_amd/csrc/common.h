@@ -70,7 +70,7 @@ struct IdxMap {
   int gap_start;
   int gap_len;
 };
-__device__ inline int imap(const IdxMap& m, int i) {
+__host__ __device__ inline int imap(const IdxMap& m, int i) {
   return m.map ? m.map[i] : m.off + i + (i >= m.gap_start ? m.gap_len : 0);
 }
 __host__ __device__ inline IdxMap im_off(int off) { return IdxMap{nullptr, off, 1 << 30, 0}; }

@@ -9,13 +9,16 @@ constexpr int kGemvKChunkMax = 2048;     // K entries staged in LDS per split
 constexpr int kGemvTargetBlocks = 1024;  // split-K aims at this many workgroups
 
 // Source of a GEMV's x vector for batch entry (pair) b: a compact array
-// p[b*stride + k], or the canonical vector gathered at the slots of box
-// 2b + which (box-local index local(k)), optionally across the face; physical
-// entries read as 0.
+// p[b*stride + k]; or the canonical vector gathered through a slot table,
+// vec[tab[b*tstride + k]] (negative slot: 0); or the canonical vector gathered
+// at the slots of box 2b + which (box-local index local(k)), optionally across
+// the face, physical entries reading as 0.
 struct VecIn {
   const cd* p;
   long long stride;
   const cd* vec;
+  const int* tab;
+  long long tstride;
   Geom g;
   int which;
   IdxMap local;
@@ -23,7 +26,8 @@ struct VecIn {
 };
 
 // Destination of y = alpha A x (+ beta y0): a compact array and/or a scatter into
-// the canonical vector (assign or add; physical entries skipped).
+// the canonical vector (assign or add), through a slot table (negative slots
+// skipped) or through box-side geometry (physical entries skipped).
 struct VecOut {
   cd* p;
   long long stride;
@@ -31,6 +35,8 @@ struct VecOut {
   long long y0stride;
   cd beta;
   cd* vec;
+  const int* tab;
+  long long tstride;
   Geom g;
   int which;
   IdxMap local;
@@ -65,15 +71,24 @@ template <class M>
 hipError_t zgemv_batched(const GemvDescT<M>* d, int nd, int batch, cd* partial, hipStream_t st);
 
 // One V-cycle level with one workgroup per pair (levels with many small pairs).
+// Per pair j (children P = box 2j, Q = box 2j+1 of level g.level):
+//   Ainv  [2m][2m]  inverse of A = [[I, -T^P_aa], [-T^Q_bb, I]] on x = [Q.beta; P.alpha]
+//   X     [2m][2e]  A^-1 B, columns y = [P.E1; Q.E2]
+//   xtab  [2m]      canonical slots of x;  ytab [2e] slots of y (-1: physical);
+//   dtab  [2e]      slots across the face of y (-1: physical)
+//   Z0    [2m]      the down sweep's A^-1 r_x, kept for the up sweep.
 template <class M>
 struct SmallLevelT {
   Geom g;
   int m, e, a0, b0;
   IdxMap E1, E2;
   const M* T;
-  const M* Winv;
-  cd* R1;
-  cd* R2;
+  const M* Ainv;
+  const M* X;
+  const int* xtab;
+  const int* ytab;
+  const int* dtab;
+  cd* Z0;
 };
 size_t small_level_lds(int m, int e);
 template <class M>

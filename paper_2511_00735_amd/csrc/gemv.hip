@@ -18,6 +18,10 @@ constexpr int kThreads = 256;
 
 __device__ inline cd load_x(const VecIn& x, int b, int k) {
   if (x.p) return x.p[(long long)b * x.stride + k];
+  if (x.tab) {
+    const int s = x.tab[(long long)b * x.tstride + k];
+    return s >= 0 ? x.vec[s] : cmk(0.0, 0.0);
+  }
   int bx, by;
   box_xy(x.g, 2 * b + x.which, bx, by);
   const int lk = imap(x.local, k);
@@ -30,7 +34,10 @@ __device__ inline cd load_x(const VecIn& x, int b, int k) {
 __device__ inline void store_y(const VecOut& y, int b, int i, cd v) {
   if (y.y0) v = cfma(y.beta, y.y0[(long long)b * y.y0stride + i], v);
   if (y.p) y.p[(long long)b * y.stride + i] = v;
-  if (y.vec) {
+  if (y.vec && y.tab) {
+    const int s = y.tab[(long long)b * y.tstride + i];
+    if (s >= 0) y.vec[s] = y.add ? cadd(y.vec[s], v) : v;
+  } else if (y.vec) {
     int bx, by;
     box_xy(y.g, 2 * b + y.which, bx, by);
     const int lk = imap(y.local, i);
@@ -64,15 +71,13 @@ __global__ __launch_bounds__(kThreads) void gemv_kernel(GemvBatchT<Mt> gb, cd* p
     const Mt* Ab = d.A.base + (long long)b * d.A.bstride;
     const long long row = imap(d.A.r, r);
     int k = k0 + grp;
-    for (; k + 12 < k1; k += 16) {
-      const cd a0 = to_cd(Ab[(long long)imap(d.A.c, k) * d.A.ld + row]);
-      const cd a1 = to_cd(Ab[(long long)imap(d.A.c, k + 4) * d.A.ld + row]);
-      const cd a2 = to_cd(Ab[(long long)imap(d.A.c, k + 8) * d.A.ld + row]);
-      const cd a3 = to_cd(Ab[(long long)imap(d.A.c, k + 12) * d.A.ld + row]);
-      acc = cfma(a0, xs[k - k0], acc);
-      acc = cfma(a1, xs[k + 4 - k0], acc);
-      acc = cfma(a2, xs[k + 8 - k0], acc);
-      acc = cfma(a3, xs[k + 12 - k0], acc);
+    constexpr int U = 8;  // independent loads in flight per thread
+    for (; k + 4 * (U - 1) < k1; k += 4 * U) {
+      Mt a[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) a[u] = Ab[(long long)imap(d.A.c, k + 4 * u) * d.A.ld + row];
+#pragma unroll
+      for (int u = 0; u < U; ++u) acc = cfma(to_cd(a[u]), xs[k + 4 * u - k0], acc);
     }
     for (; k < k1; k += 4) acc = cfma(to_cd(Ab[(long long)imap(d.A.c, k) * d.A.ld + row]), xs[k - k0], acc);
   }
@@ -117,12 +122,21 @@ __device__ void wg_gemv(const Mt* A, int ld, IdxMap rm, IdxMap cm, int M, int K,
   const int RT = M < kRowsT ? M : kRowsT;
   const int G = kThreads / RT;
   const int r = t % RT, g = t / RT;
+  constexpr int U = 8;  // independent loads in flight per thread
   for (int r0 = 0; r0 < M; r0 += RT) {
     const int row = r0 + r;
     cd acc = cmk(0.0, 0.0);
     if (g < G && row < M) {
       const long long ar = imap(rm, row);
-      for (int c = g; c < K; c += G) acc = cfma(to_cd(A[(long long)imap(cm, c) * ld + ar]), x[c], acc);
+      int c = g;
+      for (; c + (U - 1) * G < K; c += U * G) {
+        Mt a[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) a[u] = A[(long long)imap(cm, c + u * G) * ld + ar];
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc = cfma(to_cd(a[u]), x[c + u * G], acc);
+      }
+      for (; c < K; c += G) acc = cfma(to_cd(A[(long long)imap(cm, c) * ld + ar]), x[c], acc);
     }
     if (g < G) red[g * RT + r] = acc;
     __syncthreads();
@@ -135,95 +149,60 @@ __device__ void wg_gemv(const Mt* A, int ld, IdxMap rm, IdxMap cm, int M, int K,
   }
 }
 
+// Down sweep of one pair: z0 = A^-1 r_x (kept in Z0), then the exterior
+// residual rows across the kept faces receive C~ z0:
+// w[dtab(P.E1)] += T^P_{E1,a} z0_P, w[dtab(Q.E2)] += T^Q_{E2,b} z0_Q.
 template <class Mt>
 __global__ __launch_bounds__(kThreads) void vc_down_small_kernel(SmallLevelT<Mt> a, cd* vec) {
   extern __shared__ cd sm[];
-  const int m = a.m, e = a.e;
-  cd* r1 = sm;
-  cd* r2 = r1 + m;
-  cd* v1 = r2 + m;
-  cd* x1 = v1 + m;
-  cd* x2 = x1 + m;
-  cd* dd = x2 + m;
+  const int m = a.m, e = a.e, m2 = 2 * m;
+  cd* r = sm;
+  cd* z0 = r + m2;
+  cd* dd = z0 + m2;
   cd* red = dd + e;
   const int j = blockIdx.x, t = threadIdx.x;
-  const Geom& g = a.g;
-  int px, py, qx, qy;
-  box_xy(g, 2 * j, px, py);
-  box_xy(g, 2 * j + 1, qx, qy);
-  const long long bb = (long long)g.b * g.b;
+  const long long bb = (long long)a.g.b * a.g.b;
   const Mt* TP = a.T + (2LL * j) * bb;
   const Mt* TQ = TP + bb;
-  for (int i = t; i < m; i += kThreads) {
-    const cd u = vec[box_slot(g, qx, qy, a.b0 + i)];
-    const cd w = vec[box_slot(g, px, py, a.a0 + i)];
-    r1[i] = u;
-    r2[i] = w;
-    a.R1[(long long)j * m + i] = u;
-    a.R2[(long long)j * m + i] = w;
+  const int* xt = a.xtab + (long long)j * m2;
+  const int* dt = a.dtab + (long long)j * 2 * e;
+  for (int i = t; i < m2; i += kThreads) r[i] = vec[xt[i]];
+  __syncthreads();
+  wg_gemv(a.Ainv + (long long)j * m2 * m2, m2, im_off(0), im_off(0), m2, m2, r, nullptr, z0, red);
+  for (int i = t; i < m2; i += kThreads) a.Z0[(long long)j * m2 + i] = z0[i];
+  wg_gemv(TP, a.g.b, a.E1, im_off(a.a0), e, m, z0 + m, nullptr, dd, red);
+  for (int i = t; i < e; i += kThreads) {
+    const int s = dt[i];
+    if (s >= 0) vec[s] = cadd(vec[s], dd[i]);
   }
   __syncthreads();
-  wg_gemv(TP, g.b, im_off(a.a0), im_off(a.a0), m, m, r2, r1, v1, red);
-  wg_gemv(a.Winv + (long long)j * m * m, m, im_off(0), im_off(0), m, m, v1, nullptr, x1, red);
-  wg_gemv(TQ, g.b, im_off(a.b0), im_off(a.b0), m, m, x1, r2, x2, red);
-  wg_gemv(TP, g.b, a.E1, im_off(a.a0), e, m, x2, nullptr, dd, red);
+  wg_gemv(TQ, a.g.b, a.E2, im_off(a.b0), e, m, z0, nullptr, dd, red);
   for (int i = t; i < e; i += kThreads) {
-    const int k = imap(a.E1, i);
-    if (side_physical(g, px, py, side_of(g, k))) continue;
-    const int s = slot_partner(g.n, g.p, box_slot(g, px, py, k));
-    vec[s] = cadd(vec[s], dd[i]);
-  }
-  __syncthreads();
-  wg_gemv(TQ, g.b, a.E2, im_off(a.b0), e, m, x1, nullptr, dd, red);
-  for (int i = t; i < e; i += kThreads) {
-    const int k = imap(a.E2, i);
-    if (side_physical(g, qx, qy, side_of(g, k))) continue;
-    const int s = slot_partner(g.n, g.p, box_slot(g, qx, qy, k));
-    vec[s] = cadd(vec[s], dd[i]);
+    const int s = dt[e + i];
+    if (s >= 0) vec[s] = cadd(vec[s], dd[i]);
   }
 }
 
+// Up sweep of one pair: x = z0 + X y with y the kept-face values of z.
 template <class Mt>
 __global__ __launch_bounds__(kThreads) void vc_up_small_kernel(SmallLevelT<Mt> a, cd* z) {
   extern __shared__ cd sm[];
-  const int m = a.m, e = a.e;
-  cd* zp = sm;
-  cd* zq = zp + e;
-  cd* a1 = zq + e;
-  cd* a2 = a1 + m;
-  cd* v1 = a2 + m;
-  cd* x1 = v1 + m;
-  cd* x2 = x1 + m;
-  cd* r1 = x2 + m;
-  cd* r2 = r1 + m;
-  cd* red = r2 + m;
+  const int m = a.m, e = a.e, m2 = 2 * m, e2 = 2 * e;
+  cd* y = sm;
+  cd* z0 = y + e2;
+  cd* x = z0 + m2;
+  cd* red = x + m2;
   const int j = blockIdx.x, t = threadIdx.x;
-  const Geom& g = a.g;
-  int px, py, qx, qy;
-  box_xy(g, 2 * j, px, py);
-  box_xy(g, 2 * j + 1, qx, qy);
-  const long long bb = (long long)g.b * g.b;
-  const Mt* TP = a.T + (2LL * j) * bb;
-  const Mt* TQ = TP + bb;
-  for (int i = t; i < e; i += kThreads) {
-    const int kp = imap(a.E1, i), kq = imap(a.E2, i);
-    zp[i] = side_physical(g, px, py, side_of(g, kp)) ? cmk(0.0, 0.0) : z[box_slot(g, px, py, kp)];
-    zq[i] = side_physical(g, qx, qy, side_of(g, kq)) ? cmk(0.0, 0.0) : z[box_slot(g, qx, qy, kq)];
+  const int* yt = a.ytab + (long long)j * e2;
+  const int* xt = a.xtab + (long long)j * m2;
+  for (int i = t; i < e2; i += kThreads) {
+    const int s = yt[i];
+    y[i] = s >= 0 ? z[s] : cmk(0.0, 0.0);
   }
-  for (int i = t; i < m; i += kThreads) {
-    r1[i] = a.R1[(long long)j * m + i];
-    r2[i] = a.R2[(long long)j * m + i];
-  }
+  for (int i = t; i < m2; i += kThreads) z0[i] = a.Z0[(long long)j * m2 + i];
   __syncthreads();
-  wg_gemv(TP, g.b, im_off(a.a0), a.E1, m, e, zp, r1, a1, red);
-  wg_gemv(TQ, g.b, im_off(a.b0), a.E2, m, e, zq, r2, a2, red);
-  wg_gemv(TP, g.b, im_off(a.a0), im_off(a.a0), m, m, a2, a1, v1, red);
-  wg_gemv(a.Winv + (long long)j * m * m, m, im_off(0), im_off(0), m, m, v1, nullptr, x1, red);
-  wg_gemv(TQ, g.b, im_off(a.b0), im_off(a.b0), m, m, x1, a2, x2, red);
-  for (int i = t; i < m; i += kThreads) {
-    z[box_slot(g, qx, qy, a.b0 + i)] = x1[i];
-    z[box_slot(g, px, py, a.a0 + i)] = x2[i];
-  }
+  wg_gemv(a.X + (long long)j * m2 * e2, m2, im_off(0), im_off(0), m2, e2, y, z0, x, red);
+  for (int i = t; i < m2; i += kThreads) z[xt[i]] = x[i];
 }
 
 }  // namespace
@@ -264,7 +243,7 @@ hipError_t zgemv_batched(const GemvDescT<Mt>* d, int nd, int batch, cd* partial,
 }
 
 size_t small_level_lds(int m, int e) {
-  return sizeof(cd) * (size_t)(std::max(5 * m + e, 2 * e + 7 * m) + kThreads);
+  return sizeof(cd) * (size_t)(std::max(4 * m + e, 2 * e + 4 * m) + kThreads);
 }
 
 template <class Mt>

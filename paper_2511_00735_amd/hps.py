@@ -46,8 +46,8 @@ class LevelView(ctypes.Structure):
     _fields_ = [("level", ctypes.c_int32), ("boxes", ctypes.c_int32),
                 ("box_nodes", ctypes.c_int32), ("morton", ctypes.c_int32),
                 ("T", ctypes.c_void_p), ("pairs", ctypes.c_int32),
-                ("shared_nodes", ctypes.c_int32), ("Winv", ctypes.c_void_p),
-                ("fp32", ctypes.c_int32)]
+                ("shared_nodes", ctypes.c_int32), ("Ainv", ctypes.c_void_p),
+                ("X", ctypes.c_void_p), ("fp32", ctypes.c_int32)]
 
 
 _P = ctypes.c_void_p
@@ -275,12 +275,22 @@ class Problem:
         t = self._view(v.T, v.boxes * b * b, bool(v.fp32)).view(v.boxes, b, b)
         return t.transpose(1, 2)   # stored column-major
 
-    def level_Winv(self, level):
+    def level_Ainv(self, level):
+        """Per-pair A^-1 as [pairs, 2m, 2m] (x = [Q.beta; P.alpha]), or None."""
         v = self.level_view(level)
-        m = v.shared_nodes
-        if not v.Winv:
+        m2 = 2 * v.shared_nodes
+        if not v.Ainv:
             return None
-        return self._view(v.Winv, v.pairs * m * m, bool(v.fp32)).view(v.pairs, m, m).transpose(1, 2)
+        return self._view(v.Ainv, v.pairs * m2 * m2, bool(v.fp32)).view(v.pairs, m2, m2).transpose(1, 2)
+
+    def level_X(self, level):
+        """Per-pair X = A^-1 B as [pairs, 2m, 2e] (columns y = [P.E1; Q.E2]), or None."""
+        v = self.level_view(level)
+        if not v.X:
+            return None
+        m2 = 2 * v.shared_nodes
+        e2 = 2 * (v.box_nodes - v.shared_nodes)
+        return self._view(v.X, v.pairs * m2 * e2, bool(v.fp32)).view(v.pairs, e2, m2).transpose(1, 2)
 
 
 # ---- batch-first entry points (several problems per call) ------------------

@@ -105,19 +105,29 @@ def test_merge_levels(hps, ctx, name, n, N, kappa):
             if level > 1:
                 keep = np.nonzero(~omesh.box_local_physical_mask(n, N - 1, level, *key))[0]
             assert rel(Tg[key][np.ix_(keep, keep)], Tref[np.ix_(keep, keep)]) < 1e-10, (level, key)
-    # W^-1 inverts W = I - T^P_aa T^Q_bb built from the oracle's box maps
+    # A^-1 and X = A^-1 B of every pair, against the blocks of the oracle's
+    # box maps; columns of y on physical sides are never computed (stored 0)
     from oracle import merge as omerge
     for level in range(1, L + 1):
-        Wi = prob.level_Winv(level).cpu().numpy()
+        Ai = prob.level_Ainv(level).cpu().numpy()
+        X = prob.level_X(level)
+        X = None if X is None else X.cpu().numpy()
         v = prob.level_view(level)
         boxes = prob.level_T(level).shape[0]
         for j in range(min(v.pairs, 6)):
             P = hps.morton_box_xy(level, 2 * j)
             Q = hps.morton_box_xy(level, 2 * j + 1)
             blk = omerge.pair_blocks(level, N - 1, To[level - 1][P], To[level - 1][Q])
-            ia, ib = blk["ia"], blk["ib"]
-            W = np.eye(len(ia)) - To[level - 1][P][np.ix_(ia, ia)] @ To[level - 1][Q][np.ix_(ib, ib)]
-            assert np.abs(W @ Wi[j] - np.eye(len(ia))).max() < 1e-10, (level, j)
+            m2 = 2 * blk["m"]
+            assert np.abs(blk["A"] @ Ai[j] - np.eye(m2)).max() < 1e-10, (level, j)
+            if level < L:
+                phys = np.concatenate([omesh.box_local_physical_mask(n, N - 1, level, *P)[blk["E1"]],
+                                       omesh.box_local_physical_mask(n, N - 1, level, *Q)[blk["E2"]]])
+                Xref = np.linalg.solve(blk["A"], blk["B"])
+                assert rel(X[j][:, ~phys], Xref[:, ~phys]) < 1e-10, (level, j)
+                assert np.all(X[j][:, phys] == 0), (level, j)
+            else:
+                assert X is None
         assert boxes == 2 * v.pairs
 
 
