@@ -1,16 +1,19 @@
-// Batched in-place inversion of complex FP64 matrices by Gauss-Jordan
-// elimination with partial pivoting.
+// Batched in-place inversion of complex matrices (FP64 or FP32) by
+// Gauss-Jordan elimination with partial pivoting.
 //
 // m <= 64: the whole matrix sits in LDS, one workgroup per matrix.
-// m  > 64: blocked Gauss-Jordan.  For each block column C = [k0, k0+nb):
-//   1. partial-pivoting LU of the panel A[k0:m, C] (a copy) selects nb pivot
-//      rows among the rows not yet used as pivots;
-//   2. those rows are swapped into P = [k0, k0+nb);
-//   3. Dinv = A[P, C]^-1 (small in-LDS Gauss-Jordan);
-//   4. X = Dinv A[P, ~C],  Y = -A[~P, C] Dinv,  A[~P, ~C] -= A[~P, C] X,
-//      then A[P, ~C] = X, A[~P, C] = Y, A[P, C] = Dinv  (MFMA GEMMs);
-// and finally the row interchanges are undone as column interchanges in
-// reverse order.  Work: m^3 complex multiply-adds, nearly all in GEMMs.
+// m  > 64: blocked Gauss-Jordan, two launches per block column C = [k0, k0+nb):
+//   1. gj_panel: partial-pivoting LU of the panel A[k0:m, C] in LDS picks nb
+//      pivot rows (as the row map of this step) and forms Dinv, the inverse of
+//      the pivot block, by an in-LDS Gauss-Jordan on those rows;
+//   2. gj_update: one pass over the whole matrix, out of place (two buffers),
+//      rows read through the row map, P = C, X = Dinv A'[P, :]:
+//        rows in P:      out = X           (Dinv on the C columns)
+//        rows not in P:  out = A'[i, ~C] - A'[i, C] X   (-A'[i, C] Dinv on C).
+// The row interchanges of all steps compose to one map rho; the inverse of the
+// original matrix is the result with column j moved to column rho[j], which the
+// last update (or a final copy) applies.  Work: m^3 complex multiply-adds in
+// 2 m / nb launches.
 #include "common.h"
 #include "gj_small.h"
 #include "host.h"
@@ -19,7 +22,8 @@ namespace hps {
 
 namespace {
 
-constexpr int kNB = 32;
+constexpr int kNB = 32;        // widest block column
+constexpr int kPanelThreads = 1024;
 
 template <class T>
 __global__ __launch_bounds__(256) void inv_small_kernel(T* A, int m, int lda, long long bstride,
@@ -50,13 +54,296 @@ __global__ __launch_bounds__(256) void inv_small_kernel(T* A, int m, int lda, lo
   }
 }
 
+// LDS bytes of gj_panel for m - k0 = rows and block width kb.
+template <class T>
+size_t panel_lds_bytes(int rows, int kb) {
+  return sizeof(T) * ((size_t)rows * kb + (size_t)kb * kb + 2 * kb) + sizeof(int) * rows;
+}
+
+// Block width: the panel of the first step (m rows) must fit in about 150 KB.
+template <class T>
+int panel_width(int m) {
+  int nb = kNB;
+  while (nb > 4 && panel_lds_bytes<T>(m, nb) > 150 * 1024) nb /= 2;
+  return nb;
+}
+
+// 1/a for matrix entries of moderate magnitude (one real division).
+template <class T>
+__device__ inline T crecip(T a) {
+  typedef typename cx<T>::real R;
+  const R n = a.x * a.x + a.y * a.y;
+  const R s = n > 0 ? R(1) / n : R(0);
+  return cx<T>::make(a.x * s, -a.y * s);
+}
+
+// Pivot key: 1 + the FP32 bits of |v|^2 (monotonic for non-negative values;
+// 0 means "no candidate") in the high word, the complemented row in the low.
+template <class R>
+__device__ inline unsigned long long pivot_key(R v2, int r) {
+  const unsigned hi = __float_as_uint((float)v2) + 1u;
+  return ((unsigned long long)hi << 32) | (unsigned int)(0xFFFFFFFFu - (unsigned int)r);
+}
+
+// Largest key of the wave (every lane must call): maximum of the high words by
+// DPP row shifts within each 16-lane row and read-lanes across rows; among the
+// lanes holding that maximum, the lowest lane's key.
+__device__ inline unsigned long long wave_max_key(unsigned long long key) {
+  const unsigned hi = (unsigned)(key >> 32);
+  unsigned h = hi;
+  h = max(h, (unsigned)__builtin_amdgcn_update_dpp((int)h, (int)h, 0x111, 0xF, 0xF, false));
+  h = max(h, (unsigned)__builtin_amdgcn_update_dpp((int)h, (int)h, 0x112, 0xF, 0xF, false));
+  h = max(h, (unsigned)__builtin_amdgcn_update_dpp((int)h, (int)h, 0x114, 0xF, 0xF, false));
+  h = max(h, (unsigned)__builtin_amdgcn_update_dpp((int)h, (int)h, 0x118, 0xF, 0xF, false));
+  const unsigned m = max(max((unsigned)__builtin_amdgcn_readlane((int)h, 15), (unsigned)__builtin_amdgcn_readlane((int)h, 31)),
+                         max((unsigned)__builtin_amdgcn_readlane((int)h, 47), (unsigned)__builtin_amdgcn_readlane((int)h, 63)));
+  const unsigned long long bal = __ballot(hi == m);
+  const int l = __ffsll((long long)bal) - 1;
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)key, l);
+  return ((unsigned long long)m << 32) | lo;
+}
+
+// Step 1 of a block column: the panel A[k0:m, k0:k0+kb] of matrix blockIdx.x.
+// A partial-pivoting LU of the panel (rank-1 updates spread over (row, column
+// group) threads; the next pivot found during the update by a per-wave DPP
+// arg-max) selects the pivot rows; Dinv = (pivot block)^-1 then comes from an
+// in-LDS Gauss-Jordan on the original pivot rows.  Writes Dinv [kb][kb]
+// (column-major), rowmap (row i of the next matrix is row rowmap[i] of this
+// one) and the composed map rho (row i then holds row rho[i] of the original).
+template <class T>
+__global__ __launch_bounds__(kPanelThreads) void gj_panel_kernel(const T* A, int m, int lda, long long bstride,
+                                                                 int k0, int kb, const int* rho_prev, int* rho,
+                                                                 int* rowmap, T* dinv, int* flag) {
+  extern __shared__ char smem[];
+  const int rows = m - k0;
+  T* Pn = reinterpret_cast<T*>(smem);          // rows x kb, column-major (ld rows)
+  T* S = Pn + (size_t)rows * kb;               // kb x kb pivot block
+  T* colk = S + kb * kb;                       // kb: column k of S
+  T* rowk = colk + kb;                         // kb: row k of S
+  int* perm = reinterpret_cast<int*>(rowk + kb);  // rows: local row order
+  __shared__ unsigned long long kw[kPanelThreads / 64];  // per-wave best pivot key
+  const T* Ab = A + (long long)blockIdx.x * bstride;
+  const int tid = threadIdx.x, nt = blockDim.x, nw = nt / 64;
+  // rank-1 updates: thread (rr, g) takes rows rr, rr + RT, ... and columns
+  // c+1+g, c+1+g+G, ...
+  const int RT = rows < nt ? rows : nt;
+  const int G = nt / RT;
+  const int rr = tid % RT, g = tid / RT;
+  {
+    unsigned long long best = 0;
+    constexpr int U = 8;
+    for (int base = 0; base < rows * kb; base += U * nt) {
+      T v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int idx = base + u * nt + tid;
+        v[u] = idx < rows * kb ? Ab[(long long)(k0 + idx / rows) * lda + k0 + idx % rows] : cx<T>::make(0.0, 0.0);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int idx = base + u * nt + tid;
+        if (idx < rows * kb) {
+          Pn[idx] = v[u];
+          if (idx < rows) best = max(best, pivot_key(cabs2(v[u]), idx));
+        }
+      }
+    }
+    best = wave_max_key(best);
+    if ((tid & 63) == 0) kw[tid >> 6] = best;
+  }
+  for (int r = tid; r < rows; r += nt) perm[r] = r;
+  __syncthreads();
+  // Only the pivot choice is taken from this factorisation (multipliers are not
+  // kept): the block inverse below starts again from the original pivot rows.
+  for (int c = 0; c < kb; ++c) {
+    unsigned long long kk = 0;
+    for (int w = 0; w < nw; ++w) kk = max(kk, kw[w]);
+    int pr = (int)(0xFFFFFFFFu - (unsigned int)(kk & 0xFFFFFFFFull));
+    const bool bad = (kk >> 32) <= 1u || pr < c || pr >= rows;
+    if (bad) pr = c;
+    if (tid == 0 && bad) atomicOr(flag, 2);
+    if (pr != c) {
+      if (tid < kb) {
+        const T t = Pn[tid * rows + c];
+        Pn[tid * rows + c] = Pn[tid * rows + pr];
+        Pn[tid * rows + pr] = t;
+      } else if (tid == kb) {
+        const int t = perm[c];
+        perm[c] = perm[pr];
+        perm[pr] = t;
+      }
+    }
+    __syncthreads();
+    if (c + 1 < kb) {
+      const T inv = crecip(Pn[c * rows + c]);
+      unsigned long long best = 0;
+      if (g < G) {
+        for (int r = rr; r < rows; r += RT) {
+          if (r <= c) continue;
+          const T l = cmul(Pn[c * rows + r], inv);
+          for (int j = c + 1 + g; j < kb; j += G) {
+            const T v = csub(Pn[j * rows + r], cmul(l, Pn[j * rows + c]));
+            Pn[j * rows + r] = v;
+            if (j == c + 1) best = max(best, pivot_key(cabs2(v), r));
+          }
+        }
+      }
+      best = wave_max_key(best);
+      if ((tid & 63) == 0) kw[tid >> 6] = best;
+      __syncthreads();
+    }
+  }
+  int* rm = rowmap + (long long)blockIdx.x * m;
+  int* ro = rho + (long long)blockIdx.x * m;
+  const int* rp = rho_prev ? rho_prev + (long long)blockIdx.x * m : nullptr;
+  for (int i = tid; i < m; i += nt) {
+    const int src = i < k0 ? i : k0 + perm[i - k0];
+    rm[i] = src;
+    ro[i] = rp ? rp[src] : src;
+  }
+  for (int idx = tid; idx < kb * kb; idx += nt) {
+    const int r = idx % kb, c = idx / kb;
+    S[idx] = Ab[(long long)(k0 + c) * lda + k0 + perm[r]];
+  }
+  __syncthreads();
+  // Gauss-Jordan on the pivot block; its rows are already in pivot order, so
+  // the diagonal pivots are the ones the panel factorisation chose
+  for (int k = 0; k < kb; ++k) {
+    const T inv = crecip(S[k * kb + k]);
+    if (tid < kb) {
+      colk[tid] = tid == k ? cx<T>::make(0.0, 0.0) : S[k * kb + tid];
+      rowk[tid] = tid == k ? inv : cmul(S[tid * kb + k], inv);
+    }
+    __syncthreads();
+    for (int idx = tid; idx < kb * kb; idx += nt) {
+      const int i = idx % kb, j = idx / kb;
+      const T rk = rowk[j];  // row k scaled by the pivot's inverse
+      if (i == k) {
+        S[idx] = rk;
+      } else {
+        const T base = j == k ? cx<T>::make(0.0, 0.0) : S[idx];
+        S[idx] = csub(base, cmul(colk[i], rk));
+      }
+    }
+    __syncthreads();
+  }
+  T* Db = dinv + (long long)blockIdx.x * kNB * kNB;
+  for (int idx = tid; idx < kb * kb; idx += nt) Db[idx] = S[idx];
+}
+
+// Step 2 of a block column: out-of-place update of the whole matrix, 64 x 64
+// tiles, 256 threads, each thread 4 x 4 outputs (rows i0 + tx + 16u, columns
+// j0 + ty + 16v), rows read through rowmap, P = C = [k0, k0+kb):
+//   X = Dinv A'[P, :] (Dinv on the C columns); rows in P: out = X;
+//   other rows: out = A'[i, ~C] - A'[i, C] X  (-A'[i, C] Dinv on C).
+// With colmap the output column j is written at colmap[j].
+template <class T>
+__global__ __launch_bounds__(256) void gj_update_kernel(const T* A, int lda, long long astride, T* O, int ldo,
+                                                        long long ostride, int m, int k0, int kb,
+                                                        const int* rowmap, const T* dinv, const int* colmap) {
+  constexpr int BT = 64;
+  __shared__ T Ds[kNB * kNB];
+  __shared__ T Xs[kNB][BT];
+  __shared__ T Bp[kNB][BT];     // A'[P, jtile]
+  __shared__ T Ac[kNB][BT + 1]; // A'[itile, C], transposed
+  const int tiles = (m + BT - 1) / BT;
+  const int i0 = (blockIdx.x % tiles) * BT, j0 = (blockIdx.x / tiles) * BT;
+  const int b = blockIdx.y;
+  const T* Ab = A + (long long)b * astride;
+  T* Ob = O + (long long)b * ostride;
+  const int* rm = rowmap + (long long)b * m;
+  const T* Db = dinv + (long long)b * kNB * kNB;
+  const int tid = threadIdx.x;
+  const int tx = tid % 16, ty = tid / 16;
+  const T zero = cx<T>::make(0.0, 0.0);
+  T aout[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int gi = i0 + tx + 16 * u;
+    const bool rowok = gi < m && !(gi >= k0 && gi < k0 + kb);
+    const int src = gi < m ? rm[gi] : 0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int gj = j0 + ty + 16 * v;
+      const bool ok = rowok && gj < m && !(gj >= k0 && gj < k0 + kb);
+      aout[u][v] = ok ? Ab[(long long)gj * lda + src] : zero;
+    }
+  }
+  for (int idx = tid; idx < kb * kb; idx += 256) Ds[(idx / kb) * kNB + idx % kb] = Db[idx];
+  for (int idx = tid; idx < kb * BT; idx += 256) {
+    const int q = idx % kb, j = idx / kb;
+    const int gj = j0 + j;
+    Bp[q][j] = (gj < m) ? Ab[(long long)gj * lda + rm[k0 + q]] : zero;
+  }
+  for (int idx = tid; idx < BT * kb; idx += 256) {
+    const int i = idx % BT, q = idx / BT;
+    const int gi = i0 + i;
+    Ac[q][i] = (gi < m) ? Ab[(long long)(k0 + q) * lda + rm[gi]] : zero;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < kb * BT; idx += 256) {
+    const int j = idx % BT, q = idx / BT;
+    const int gj = j0 + j;
+    T v = zero;
+    if (gj >= k0 && gj < k0 + kb) {
+      v = Ds[(gj - k0) * kNB + q];
+    } else if (gj < m) {
+      for (int r = 0; r < kb; ++r) v = cfma(Ds[r * kNB + q], Bp[r][j], v);
+    }
+    Xs[q][j] = v;
+  }
+  __syncthreads();
+  T acc[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[u][v] = zero;
+  for (int q = 0; q < kb; ++q) {
+    T a[4], x[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) a[u] = Ac[q][tx + 16 * u];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) x[v] = Xs[q][ty + 16 * v];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[u][v] = cfma(a[u], x[v], acc[u][v]);
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int gi = i0 + tx + 16 * u;
+    if (gi >= m) continue;
+    const bool inP = gi >= k0 && gi < k0 + kb;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int j = ty + 16 * v;
+      const int gj = j0 + j;
+      if (gj >= m) continue;
+      const int oc = colmap ? colmap[(long long)b * m + gj] : gj;
+      Ob[(long long)oc * ldo + gi] = inP ? Xs[gi - k0][j] : csub(aout[u][v], acc[u][v]);
+    }
+  }
+}
+
+// dst(:, colmap[j]) = src(:, j): the inverse of the row-interchanged matrix
+// becomes the inverse of the original one.
+template <class T>
+__global__ void permute_cols_kernel(const T* S, int lds, long long sstride, T* A, int lda, long long bstride,
+                                    int m, const int* colmap) {
+  const int b = blockIdx.z, j = blockIdx.y;
+  const T* Sb = S + (long long)b * sstride;
+  T* Ab = A + (long long)b * bstride;
+  const int oc = colmap[(long long)b * m + j];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x)
+    Ab[(long long)oc * lda + i] = Sb[(long long)j * lds + i];
+}
+
 template <class T>
 struct BlockScratch {
-  T* panel;   // [batch][m][nb]   (ld m)
-  T* dinv;    // [batch][nb][nb]
-  T* X;       // [batch][nb][m]   (nb x (m - kb), ld nb)
-  T* Y;       // [batch][m][nb]   ((m - kb) x kb, ld m)
-  int* ipiv;  // [batch][m]
+  T* buf;       // [batch][m][m] second buffer (ld m)
+  T* dinv;      // [batch][kNB][kNB]
+  int* rho[2];  // [batch][m] composed row maps (alternating)
+  int* rowmap;  // [batch][m]
 };
 
 template <class T>
@@ -64,212 +351,52 @@ inline BlockScratch<T> carve(void* base, int m, int batch) {
   BlockScratch<T> s;
   char* p = (char*)base;
   auto take = [&](size_t bytes) { char* q = p; p += (bytes + 255) & ~size_t(255); return q; };
-  s.panel = (T*)take(sizeof(T) * (size_t)batch * m * kNB);
+  s.buf = (T*)take(sizeof(T) * (size_t)batch * m * m);
   s.dinv = (T*)take(sizeof(T) * (size_t)batch * kNB * kNB);
-  s.X = (T*)take(sizeof(T) * (size_t)batch * kNB * m);
-  s.Y = (T*)take(sizeof(T) * (size_t)batch * m * kNB);
-  s.ipiv = (int*)take(sizeof(int) * (size_t)batch * m);
+  s.rho[0] = (int*)take(sizeof(int) * (size_t)batch * m);
+  s.rho[1] = (int*)take(sizeof(int) * (size_t)batch * m);
+  s.rowmap = (int*)take(sizeof(int) * (size_t)batch * m);
   return s;
-}
-
-// Panel LU (partial pivoting) of A[k0:m, k0:k0+kb], held in LDS: records the
-// absolute pivot rows in ipiv[k0 .. k0+kb) and writes Dinv = (L11 U11)^-1, the
-// inverse of the pivot block once its rows are swapped into place.
-template <class T>
-__global__ __launch_bounds__(256) void panel_lds_kernel(const T* A, int m, int lda, long long bstride,
-                                                        int k0, int kb, int* ipiv, T* dinv, int* flag) {
-  typedef typename cx<T>::real R;
-  extern __shared__ char smem[];
-  T* Pn = reinterpret_cast<T*>(smem);  // rows x kb, column-major (ld = rows)
-  __shared__ int pr_s;
-  __shared__ T Li[kNB * kNB];          // L11^-1 (unit lower), column-major kb x kb
-  const T* Ab = A + (long long)blockIdx.x * bstride;
-  int* ip = ipiv + (long long)blockIdx.x * m;
-  const int rows = m - k0;
-  const int tid = threadIdx.x;
-  for (int base = 0; base < rows * kb; base += 4 * 256) {
-    T v[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int idx = base + q * 256 + tid;
-      v[q] = idx < rows * kb ? Ab[(long long)(k0 + idx / rows) * lda + k0 + idx % rows] : cx<T>::make(0.0, 0.0);
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int idx = base + q * 256 + tid;
-      if (idx < rows * kb) Pn[(idx / rows) * rows + idx % rows] = v[q];
-    }
-  }
-  __syncthreads();
-  for (int c = 0; c < kb; ++c) {
-    if (tid < 64) {
-      R best = -1;
-      int bi = c;
-      for (int r = c + tid; r < rows; r += 64) {
-        const R v = cabs2(Pn[c * rows + r]);
-        if (v > best) { best = v; bi = r; }
-      }
-      for (int off = 32; off > 0; off >>= 1) {
-        const R ov = __shfl_xor(best, off);
-        const int oi = __shfl_xor(bi, off);
-        if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
-      }
-      if (tid == 0) {
-        pr_s = bi;
-        ip[k0 + c] = k0 + bi;
-        if (!(best > 0)) atomicOr(flag, 2);
-      }
-    }
-    __syncthreads();
-    const int pr = pr_s;
-    if (pr != c) {
-      for (int j = tid; j < kb; j += blockDim.x) {
-        const T t = Pn[j * rows + c];
-        Pn[j * rows + c] = Pn[j * rows + pr];
-        Pn[j * rows + pr] = t;
-      }
-      __syncthreads();
-    }
-    const T d = Pn[c * rows + c];
-    const T inv = cabs2(d) > 0 ? cinv(d) : cx<T>::make(0.0, 0.0);
-    for (int r = c + 1 + tid; r < rows; r += blockDim.x) {
-      const T l = cmul(Pn[c * rows + r], inv);
-      Pn[c * rows + r] = l;
-      for (int j = c + 1; j < kb; ++j) Pn[j * rows + r] = csub(Pn[j * rows + r], cmul(l, Pn[j * rows + c]));
-    }
-    __syncthreads();
-  }
-  // Li = L11^-1 column by column (unit lower triangular forward substitution)
-  if (tid < kb) {
-    const int j = tid;
-    for (int i = 0; i < kb; ++i) {
-      T v = (i == j) ? cx<T>::make(1.0, 0.0) : cx<T>::make(0.0, 0.0);
-      for (int q = j; q < i; ++q) v = csub(v, cmul(Pn[q * rows + i], Li[j * kNB + q]));
-      Li[j * kNB + i] = (i < j) ? cx<T>::make(0.0, 0.0) : v;
-    }
-  }
-  __syncthreads();
-  // Dinv = U11^-1 Li: back substitution on each column of Li
-  T* Db = dinv + (long long)blockIdx.x * kNB * kNB;
-  if (tid < kb) {
-    const int j = tid;
-    T x[kNB];
-    for (int i = kb - 1; i >= 0; --i) {
-      T v = Li[j * kNB + i];
-      for (int q = i + 1; q < kb; ++q) v = csub(v, cmul(Pn[q * rows + i], x[q]));
-      const T u = Pn[i * rows + i];
-      x[i] = cabs2(u) > 0 ? cmul(v, cinv(u)) : cx<T>::make(0.0, 0.0);
-    }
-    for (int i = 0; i < kb; ++i) Db[j * kb + i] = x[i];
-  }
-}
-
-// Panel width: the panel (m rows x nb complex) must fit in about 123 KB of LDS.
-template <class T>
-int panel_width(int m) {
-  int nb = kNB;
-  while (nb > 4 && (size_t)m * nb * sizeof(T) > 126 * 1024) nb /= 2;
-  return nb;
-}
-
-// Apply the interchanges rows k0+j <-> ipiv[k0+j], j = 0..kb-1, in order, to all columns.
-template <class T>
-__global__ void swap_rows_kernel(T* A, int m, int lda, long long bstride, int k0, int kb,
-                                 const int* ipiv) {
-  T* Ab = A + (long long)blockIdx.y * bstride;
-  const int* ip = ipiv + (long long)blockIdx.y * m;
-  for (int col = blockIdx.x * blockDim.x + threadIdx.x; col < m; col += gridDim.x * blockDim.x) {
-    T* Ac = Ab + (long long)col * lda;
-    for (int j = 0; j < kb; ++j) {
-      const int pr = ip[k0 + j];
-      if (pr != k0 + j) {
-        const T t = Ac[k0 + j];
-        Ac[k0 + j] = Ac[pr];
-        Ac[pr] = t;
-      }
-    }
-  }
-}
-
-// Undo all row interchanges as column interchanges, last one first.
-template <class T>
-__global__ void unswap_cols_kernel(T* A, int m, int lda, long long bstride, const int* ipiv) {
-  T* Ab = A + (long long)blockIdx.y * bstride;
-  const int* ip = ipiv + (long long)blockIdx.y * m;
-  for (int row = blockIdx.x * blockDim.x + threadIdx.x; row < m; row += gridDim.x * blockDim.x) {
-    for (int k = m - 1; k >= 0; --k) {
-      const int pr = ip[k];
-      if (pr != k) {
-        const T t = Ab[(long long)k * lda + row];
-        Ab[(long long)k * lda + row] = Ab[(long long)pr * lda + row];
-        Ab[(long long)pr * lda + row] = t;
-      }
-    }
-  }
 }
 
 template <class T>
 hipError_t inverse_blocked(T* A, int m, int lda, long long bstride, int batch, void* scratch,
                            int* flag, hipStream_t st) {
   BlockScratch<T> s = carve<T>(scratch, m, batch);
-  const T one = cx<T>::make(1.0, 0.0), zero = cx<T>::make(0.0, 0.0), mone = cx<T>::make(-1.0, 0.0);
   hipError_t err;
   const int nbw = panel_width<T>(m);
-  const size_t plds = (size_t)m * nbw * sizeof(T);
-  if ((err = allow_lds(panel_lds_kernel<T>, plds)) != hipSuccess) return err;
-  for (int k0 = 0; k0 < m; k0 += nbw) {
+  if ((err = allow_lds(gj_panel_kernel<T>, panel_lds_bytes<T>(m, nbw))) != hipSuccess) return err;
+  T* cur = A;
+  int ldc = lda;
+  long long cs = bstride;
+  T* nxt = s.buf;
+  int ldn = m;
+  long long ns = (long long)m * m;
+  const int tiles = (m + 63) / 64;
+  const int steps = (m + nbw - 1) / nbw;
+  for (int s_ = 0; s_ < steps; ++s_) {
+    const int k0 = s_ * nbw;
     const int kb = std::min(nbw, m - k0);
-    hipLaunchKernelGGL(panel_lds_kernel<T>, dim3(batch), dim3(256), (size_t)(m - k0) * kb * sizeof(T), st, A,
-                       m, lda, bstride, k0, kb, s.ipiv, s.dinv, flag);
+    const int* rho_prev = s_ ? s.rho[(s_ - 1) & 1] : nullptr;
+    int* rho = s.rho[s_ & 1];
+    hipLaunchKernelGGL(gj_panel_kernel<T>, dim3(batch), dim3(kPanelThreads), panel_lds_bytes<T>(m - k0, kb), st,
+                       cur, m, ldc, cs, k0, kb, rho_prev, rho, s.rowmap, s.dinv, flag);
     if ((err = hipPeekAtLastError()) != hipSuccess) return err;
-    hipLaunchKernelGGL(swap_rows_kernel<T>, dim3((m + 255) / 256, batch), dim3(256), 0, st, A, m, lda,
-                       bstride, k0, kb, s.ipiv);
+    // the last step writes straight into A, columns permuted, when it can
+    const bool last_into_A = (s_ == steps - 1) && nxt == A;
+    hipLaunchKernelGGL(gj_update_kernel<T>, dim3(tiles * tiles, batch), dim3(256), 0, st, cur, ldc, cs, nxt,
+                       ldn, ns, m, k0, kb, s.rowmap, s.dinv, last_into_A ? rho : nullptr);
     if ((err = hipPeekAtLastError()) != hipSuccess) return err;
-    const int mr = m - kb;  // rows / columns outside the block
-    if (mr > 0) {
-      // X = Dinv * A[P, ~C]   (kb x mr)
-      GemmArgsT<T> g{};
-      g.M = kb; g.N = mr; g.K = kb; g.batch = batch;
-      g.A = OperandT<T>{s.dinv, (long long)kNB * kNB, kb, im_off(0), im_off(0)};
-      g.B = OperandT<T>{A, bstride, lda, im_off(k0), im_gap(0, k0, kb)};
-      g.alpha = one; g.beta = zero;
-      g.C = OperandT<T>{nullptr, 0, 0, im_off(0), im_off(0)};
-      g.D = s.X; g.Dstride = (long long)kNB * m; g.ldd = kb; g.dr = im_off(0); g.dc = im_off(0);
-      if ((err = zgemm(g, st)) != hipSuccess) return err;
-      // Y = -A[~P, C] * Dinv   (mr x kb)
-      GemmArgsT<T> y{};
-      y.M = mr; y.N = kb; y.K = kb; y.batch = batch;
-      y.A = OperandT<T>{A, bstride, lda, im_gap(0, k0, kb), im_off(k0)};
-      y.B = OperandT<T>{s.dinv, (long long)kNB * kNB, kb, im_off(0), im_off(0)};
-      y.alpha = mone; y.beta = zero;
-      y.C = OperandT<T>{nullptr, 0, 0, im_off(0), im_off(0)};
-      y.D = s.Y; y.Dstride = (long long)m * kNB; y.ldd = m; y.dr = im_off(0); y.dc = im_off(0);
-      if ((err = zgemm(y, st)) != hipSuccess) return err;
-      // A[~P, ~C] -= A[~P, C] * X
-      GemmArgsT<T> u{};
-      u.M = mr; u.N = mr; u.K = kb; u.batch = batch;
-      u.A = OperandT<T>{A, bstride, lda, im_gap(0, k0, kb), im_off(k0)};
-      u.B = OperandT<T>{s.X, (long long)kNB * m, kb, im_off(0), im_off(0)};
-      u.alpha = mone; u.beta = one;
-      u.C = OperandT<T>{A, bstride, lda, im_gap(0, k0, kb), im_gap(0, k0, kb)};
-      u.D = A; u.Dstride = bstride; u.ldd = lda; u.dr = im_gap(0, k0, kb); u.dc = im_gap(0, k0, kb);
-      if ((err = zgemm(u, st)) != hipSuccess) return err;
-      // A[P, ~C] = X ; A[~P, C] = Y
-      if ((err = zcopy2d(kb, mr, batch, OperandT<T>{s.X, (long long)kNB * m, kb, im_off(0), im_off(0)}, one,
-                         A, bstride, lda, im_off(k0), im_gap(0, k0, kb), st)) != hipSuccess)
-        return err;
-      if ((err = zcopy2d(mr, kb, batch, OperandT<T>{s.Y, (long long)m * kNB, m, im_off(0), im_off(0)}, one,
-                         A, bstride, lda, im_gap(0, k0, kb), im_off(k0), st)) != hipSuccess)
-        return err;
-    }
-    // A[P, C] = Dinv
-    if ((err = zcopy2d(kb, kb, batch, OperandT<T>{s.dinv, (long long)kNB * kNB, kb, im_off(0), im_off(0)},
-                       one, A, bstride, lda, im_off(k0), im_off(k0), st)) != hipSuccess)
-      return err;
+    std::swap(cur, nxt);
+    std::swap(ldc, ldn);
+    std::swap(cs, ns);
   }
-  hipLaunchKernelGGL(unswap_cols_kernel<T>, dim3((m + 255) / 256, batch), dim3(256), 0, st, A, m, lda,
-                     bstride, s.ipiv);
-  return hipPeekAtLastError();
+  if (cur != A) {
+    hipLaunchKernelGGL(permute_cols_kernel<T>, dim3((m + 255) / 256, m, batch), dim3(256), 0, st, cur, ldc, cs, A,
+                       lda, bstride, m, s.rho[(steps - 1) & 1]);
+    if ((err = hipPeekAtLastError()) != hipSuccess) return err;
+  }
+  return hipSuccess;
 }
 
 }  // namespace
@@ -278,9 +405,8 @@ template <class T>
 size_t inverse_scratch_bytes(int m, int batch) {
   if (m <= 64) return 0;
   auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
-  return up(sizeof(T) * (size_t)batch * m * kNB) + up(sizeof(T) * (size_t)batch * kNB * kNB) +
-         up(sizeof(T) * (size_t)batch * kNB * m) + up(sizeof(T) * (size_t)batch * m * kNB) +
-         up(sizeof(int) * (size_t)batch * m);
+  return up(sizeof(T) * (size_t)batch * m * m) + up(sizeof(T) * (size_t)batch * kNB * kNB) +
+         3 * up(sizeof(int) * (size_t)batch * m);
 }
 
 template <class T>
