@@ -199,7 +199,24 @@ __global__ __launch_bounds__(kThreads) void leaf_schur_kernel(LeafArgs a) {
       double l[kNB];
 #pragma unroll
       for (int q = 0; q < kNB; ++q) l[q] = (q < kb) ? P[q * nloc + kb + r] : 0.0;
-      for (int cc = stripe; cc < nc; cc += kStripes) {
+      // four columns per iteration keep four loads in flight per thread
+      int cc = stripe;
+      for (; cc + 3 * kStripes < nc; cc += 4 * kStripes) {
+        double* ap[4];
+        double sv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          ap[u] = A + (size_t)(c0 + cc + u * kStripes) * nloc + k0 + kb + r;
+          sv[u] = *ap[u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+#pragma unroll
+          for (int q = 0; q < kNB; ++q) sv[u] -= l[q] * U[q * ncol + cc + u * kStripes];
+          *ap[u] = sv[u];
+        }
+      }
+      for (; cc < nc; cc += kStripes) {
         double* ap = A + (size_t)(c0 + cc) * nloc + k0 + kb + r;
         double s = *ap;
 #pragma unroll
