@@ -8,9 +8,22 @@ merge levels + right-hand side + preconditioned FGMRES solve.  The coefficient
 and boundary data are on the device before the timed region starts.
 
 Metric: skeleton DOF per second = 4 (N-1) n (n-1) / (build + solve time).
+The headline run is the mixed-precision path; the plain FP64 path runs on the
+same inputs beside it.
+
+Roofline: the dominant kernel is the leaf kernel (one launch per 1024
+elements).  Its launches inside the timed steps are bracketed by HIP events on
+the library's stream (library option HPS_OPT_TIMING); achieved = algorithmic
+leaf flops of the elements a launch builds / the mean launch duration.  The HBM
+traffic per launch comes from the rocprofv3 counter summary under profiles/
+(FETCH_SIZE and WRITE_SIZE, scaled by a plain copy kernel's readings), and is
+reported only while the leaf kernel source still matches the one measured.
 
 Prints ONE JSON line (see the repository documentation for the fields).
+--traffic-probe instead runs one 1 GiB device copy (the counter calibration)
+and one leaf build of the workload, for rocprofv3 --pmc runs.
 """
+import hashlib
 import argparse
 import json
 import math
@@ -26,7 +39,9 @@ sys.path.insert(0, ROOT)
 METRIC = "skeleton DOF/s to rel.res 1e-8, mixed vs FP64; served solves/s + p99 latency"
 UNIT = "skeleton DOF/s"
 MI355X_HBM_GBS = 8000.0
-MI355X_FP64_TFLOPS = 78.6
+MI355X_FP64_TFLOPS = 78.6   # FP64 vector FMA: 256 CU x 4 SIMD x 16 lanes x 2 flops x 2.4 GHz
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "leaf_kernel_64x64_N16_traffic.md")
+LEAF_SOURCE = os.path.join(ROOT, "paper_2511_00735_amd", "csrc", "leaf.hip")
 
 
 def parse():
@@ -45,7 +60,35 @@ def parse():
                     help="skip the plain FP64 run of the same workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-seconds", type=float, default=15.0)
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="one 1 GiB device copy, then one leaf build (for rocprofv3 --pmc runs)")
     return ap.parse_args()
+
+
+def leaf_flops_algorithmic(N):
+    """Flops of the leaf ItI map of one element as the method states it: dense
+    LU of the n_loc x n_loc complex element matrix, the solves for the 4(N-1)
+    boundary columns and the load column, and the product with the outgoing
+    impedance operator (8 real flops per complex multiply-add)."""
+    nloc = (N + 1) ** 2 - 4
+    return 8.0 / 3.0 * nloc ** 3 + 32.0 * (N - 1) * nloc ** 2 + 128.0 * (N - 1) ** 2 * (N + 2)
+
+
+def leaf_traffic_record():
+    """(bytes per launch, source hash) from the committed counter summary, or None."""
+    try:
+        lines = open(TRAFFIC_FILE).read().splitlines()
+    except OSError:
+        return None
+    rec = {}
+    for ln in lines:
+        if ln.startswith("- ") and ": " in ln:
+            k, v = ln[2:].split(": ", 1)
+            rec[k.strip()] = v.strip().strip("`")
+    try:
+        return float(rec["traffic_bytes_per_launch"]), rec["leaf_source_sha256"]
+    except KeyError:
+        return None
 
 
 def leaf_flops_executed(N):
@@ -155,10 +198,13 @@ def run_precision(args, pr, precision, hps, torch):
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    ctx.set_timing(True)
     t0 = time.perf_counter()
     infos = [step() for _ in range(args.steps)]
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    leaf_launches, leaf_ms, leaf_units = ctx.kernel_time(hps.HPS_KERNEL_LEAF)
+    ctx.set_timing(False)
 
     # phase timing with events on the library's stream (outside the timed loop)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
@@ -177,6 +223,7 @@ def run_precision(args, pr, precision, hps, torch):
         "info": infos[-1],
         "phase_ms": [ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2]), ev[2].elapsed_time(ev[3])],
         "g": g.clone(),
+        "leaf": (leaf_launches, leaf_ms, leaf_units),
     }
 
 
@@ -195,6 +242,25 @@ def main():
     pr.wave = workloads.PlaneWave(pr.kappa, pr.eta)
     dof = pr.skeleton_dof
 
+    if args.traffic_probe:
+        nbytes = 1 << 30
+        a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        ctx = hps.Context()
+        prec = hps.HPS_MIXED if args.precision == "mixed" else hps.HPS_FP64
+        prob = hps.Problem(ctx, hps.make_desc(pr.n, pr.N, pr.kappa, pr.eta, levels=pr.levels,
+                                              coarse_iters=pr.coarse_iters, precision=prec))
+        b_nodes = prob.coefficient_nodes(pr.b)
+        torch.cuda.synchronize()
+        prob.build_leaves(b_nodes)
+        ctx.sync()
+        print(json.dumps({"probe": "traffic", "copy_bytes_read": nbytes, "copy_bytes_written": nbytes,
+                          "leaf_elements": pr.n * pr.n}), flush=True)
+        return
+
     main_run = run_precision(args, pr, args.precision, hps, torch)
     ref = None
     if args.precision == "mixed" and not args.no_compare:
@@ -204,11 +270,25 @@ def main():
     merge_f, _ = merge_flops_executed(pr.n, pr.N, pr.levels)
     leaf_tf = leaf_f / (t_leaf * 1e-3) / 1e12
     merge_tf = merge_f / (t_merge * 1e-3) / 1e12
-    dominant = "merge" if t_merge >= t_leaf else "leaf"
-    ach = merge_tf if dominant == "merge" else leaf_tf
-    roof = {"bound": "mfma", "achieved": round(ach, 3), "peak": MI355X_FP64_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(ach / MI355X_FP64_TFLOPS, 4), "traffic": None,
-            "kernel": f"{dominant} phase (all launches of hps_{'merge_level' if dominant == 'merge' else 'build_leaves'})"}
+    # dominant kernel: the leaf kernel, timed per launch with HIP events
+    nl, lms, lunits = main_run["leaf"]
+    per_launch_ms = lms / max(nl, 1)
+    per_launch_units = lunits / max(nl, 1)
+    alg = leaf_flops_algorithmic(pr.N) * per_launch_units
+    ach = alg / (per_launch_ms * 1e-3) / 1e12
+    exe = leaf_flops_executed(pr.N) * per_launch_units / (per_launch_ms * 1e-3) / 1e12
+    traffic = None
+    rec = leaf_traffic_record()
+    if rec is not None:
+        src_hash = hashlib.sha256(open(LEAF_SOURCE, "rb").read()).hexdigest()
+        if src_hash == rec[1] and per_launch_units == 1024:
+            traffic = rec[0]
+    roof = {"bound": "alu", "achieved": round(ach, 3), "peak": MI355X_FP64_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(ach / MI355X_FP64_TFLOPS, 4), "traffic": traffic,
+            "kernel": "leaf_kernel (hps_build_leaves; FP64 vector FMA)",
+            "launches": nl, "units_per_launch": per_launch_units, "avg_launch_ms": round(per_launch_ms, 4),
+            "algorithmic_flops_per_launch": alg,
+            "executed_tflops": round(exe, 3)}
     info = main_run["info"]
     cfg = {"workload": (f"{pr.n}x{pr.n} elements, N={pr.N}, kappa=eta={pr.kappa:g}, "
                         f"8 seeded bumps (seed 3), plane-wave t, L={pr.levels}, "

@@ -129,9 +129,22 @@ const char* hps_last_error(const hps_ctx* ctx);
 hps_status hps_sync(hps_ctx* ctx);
 /* Options.  HPS_OPT_GRAPHS (default 1): replay the multigrid V-cycle from a HIP
    graph captured once per problem (on a private capture stream) instead of
-   launching its kernels one by one.  Results are bitwise identical either way. */
-enum { HPS_OPT_GRAPHS = 1 };
+   launching its kernels one by one.  Results are bitwise identical either way.
+   HPS_OPT_TIMING (default 0): profiling aid.  Setting it (either value)
+   synchronises and discards earlier records; while it is 1, every launch of a
+   timed kernel is bracketed by HIP events recorded on the context's stream (the
+   stream the kernel runs on; never inside a captured graph).
+   Returns HPS_ERR_ARG for an unknown option. */
+enum { HPS_OPT_GRAPHS = 1, HPS_OPT_TIMING = 2 };
 hps_status hps_set_option(hps_ctx* ctx, int32_t option, int32_t value);
+/* Timed kernels and their work unit:
+   HPS_KERNEL_LEAF: the leaf kernel of hps_build_leaves, one launch per chunk of
+   up to 1024 elements; unit = one element (its ItI map T and load H). */
+enum { HPS_KERNEL_LEAF = 0 };
+/* [host outputs] Launches, summed device time (ms, from the events) and units
+   processed by `kernel` since HPS_OPT_TIMING was last set.  Synchronises. */
+hps_status hps_kernel_time(hps_ctx* ctx, int32_t kernel, int64_t* launches, double* total_ms,
+                           int64_t* units);
 
 /* ---- sizing and host-side geometry -------------------------------------- */
 /* Exact device workspace (bytes) of one problem; the admission footprint. */

@@ -16,11 +16,20 @@
 #include "solve.h"
 #include "gemv.h"
 
+// One timed launch: events recorded on the context's stream around it.
+struct TimedLaunch {
+  hipEvent_t start, stop;
+  int kernel;
+  long long units;
+};
+
 struct hps_ctx {
   hipStream_t stream;
   std::string err;
   hipStream_t cap_stream = nullptr;  // private stream used only to capture graphs
   int use_graphs = 1;
+  int timing = 0;
+  std::vector<TimedLaunch> timed;
 };
 
 namespace hps {
@@ -281,7 +290,10 @@ Layout make_layout(const hps_desc* d) {
       need(lv.e, lv.m, lv.pairs);
       need(2 * lv.m, 2 * lv.e, lv.pairs);
     }
-    if (lay.nL > 0) need(lay.nL / 2, lay.nL / 2, 1);
+    if (lay.nL > 0) {  // the coarse pair-form product always goes through partial sums
+      const int ns = gemv_nsplit(lay.nL / 2, lay.nL / 2, 1);
+      mx = std::max(mx, (size_t)ns * (lay.nL / 2));
+    }
     lay.gpart_elems = 2 * mx + 64;
     lay.gpart_off = take(sizeof(cd) * lay.gpart_elems);
   }
@@ -665,27 +677,15 @@ hps_status cgs2(hps_problem* p, const cd* V, long long vstride, int nv, cd* w, l
   return HPS_OK;
 }
 
-// Coarse matvec w = M_L v on compact coarse vectors.  At the top level the
-// coarse system is the single pair's A_L; with the compact order [P.alpha; Q.beta]
-// it reads [v_P - T^Q_bb v_Q ; v_Q - T^P_aa v_P].  Below the top, the level-L
-// skeleton matvec runs on canonical scratch vectors.
+// Coarse matvec w = M_L v on compact coarse vectors below the top level: the
+// level-L skeleton matvec on canonical scratch vectors.  (At the top level the
+// coarse system is the single pair's A_L; coarse_solve forms that product from
+// split-K partial sums inside its Arnoldi step.)
 hps_status coarse_matvec(hps_problem* p, const cd* v, cd* w) {
   hps_ctx* c = p->ctx;
   hipStream_t st = c->stream;
   const Layout& lay = p->lay;
   const Level& top = lay.lev[lay.L];
-  if (lay.L == lay.Lmax) {
-    const int b = top.g.b;
-    const int m = lay.nL / 2;
-    const cd* T = Tlev(p, lay.L);
-    const int aP = top.g.off[3], bQ = top.g.off[2];   // P's top side, Q's bottom side
-    GemvDesc d[2] = {gdesc<cd>(m, m, Operand{T + (size_t)b * b, 0, b, im_off(bQ), im_off(bQ)}, vin_compact(v + m, 0),
-                           vout_compact(w, 0, v, 0), cmk(-1, 0)),
-                     gdesc<cd>(m, m, Operand{T, 0, b, im_off(aP), im_off(aP)}, vin_compact(v, 0),
-                           vout_compact(w + m, 0, v + m, 0), cmk(-1, 0))};
-    HIPCHK(c, zgemv_batched(d, 2, 1, at<cd>(p, lay.gpart_off), st));
-    return HPS_OK;
-  }
   const int* idx = at<int>(p, lay.cidx_off);
   cd* u1 = workv(p, 2);
   cd* u2 = workv(p, 3);
@@ -717,28 +717,41 @@ hps_status coarse_solve(hps_problem* p, cd* wv, cd* z) {
   const int* idx = at<int>(p, lay.cidx_off);
   cd* V = at<cd>(p, lay.cV_off);
   cd* w = at<cd>(p, lay.cw_off);
-  cd* x = at<cd>(p, lay.cx_off);
+  cd* wt = at<cd>(p, lay.cx_off);
   cd* H = at<cd>(p, lay.cH_off);
-  cd* y = at<cd>(p, lay.cy_off);
-  cd* sc = at<cd>(p, lay.cs_off);  // [0]: beta^2, [1]: |w|^2
-  cd* h2 = at<cd>(p, lay.hh_off);
-  cd* part = at<cd>(p, lay.part_off);
-  HIPCHK(c, index_gather(idx, nL, wv, w, st));
-  HIPCHK(c, multi_dot(w, 0, 1, w, nL, part, sc, false, st));
-  HIPCHK(c, normalize(w, sc, V, nL, nullptr, st));
-  HIPCHK(c, vfill(H, (long long)(k + 1) * k, cmk(0, 0), st));
+  cd* sc = at<cd>(p, lay.cs_off);  // [0]: beta^2
+  cd* part = at<cd>(p, lay.gpart_off);
+  HIPCHK(c, coarse_start(idx, nL, wv, V, H, (k + 1) * k, sc, st));
+  const bool pair_form = lay.L == lay.Lmax;
   for (int j = 0; j < k; ++j) {
-    hps_status s = coarse_matvec(p, V + (size_t)j * nL, w);
-    if (s != HPS_OK) return s;
-    s = cgs2(p, V, nL, j + 1, w, nL, H + (size_t)j * (k + 1), h2);
-    if (s != HPS_OK) return s;
-    HIPCHK(c, multi_dot(w, 0, 1, w, nL, part, sc + 1, false, st));
-    HIPCHK(c, normalize(w, sc + 1, V + (size_t)(j + 1) * nL, nL, H + (size_t)j * (k + 1) + j + 1, st));
+    const cd* vj = V + (size_t)j * nL;
+    CoarseW src{};
+    if (pair_form) {
+      // M_L v = [v_P - T^Q_bb v_Q ; v_Q - T^P_aa v_P] on [P.alpha; Q.beta]
+      const int b = top.g.b;
+      const int m = nL / 2;
+      const cd* T = Tlev(p, lay.L);
+      const int aP = top.g.off[3], bQ = top.g.off[2];   // P's top side, Q's bottom side
+      GemvDesc d[2] = {gdesc<cd>(m, m, Operand{T + (size_t)b * b, 0, b, im_off(bQ), im_off(bQ)},
+                                 vin_compact(vj + m, 0), vout_compact(nullptr, 0)),
+                       gdesc<cd>(m, m, Operand{T, 0, b, im_off(aP), im_off(aP)}, vin_compact(vj, 0),
+                                 vout_compact(nullptr, 0))};
+      GemvPartLayout pl{};
+      HIPCHK(c, zgemv_partials(d, 2, 1, part, &pl, st));
+      src.part = part;
+      src.poff0 = pl.poff[0];
+      src.poff1 = pl.poff[1];
+      src.ns0 = pl.nsplit[0];
+      src.ns1 = pl.nsplit[1];
+      src.m = m;
+    } else {
+      hps_status s = coarse_matvec(p, vj, w);
+      if (s != HPS_OK) return s;
+      src.w = w;
+    }
+    HIPCHK(c, coarse_arnoldi(V, nL, j, src, wt, H + (size_t)j * (k + 1), st));
   }
-  HIPCHK(c, hessenberg_lsq(H, k + 1, k, sc, y, nullptr, st));
-  HIPCHK(c, vfill(x, nL, cmk(0, 0), st));
-  HIPCHK(c, multi_axpy(V, nL, k, y, x, nL, +1, st));
-  HIPCHK(c, index_scatter(idx, nL, x, z, st));
+  HIPCHK(c, coarse_finish(H, k, sc, V, nL, idx, z, st));
   return HPS_OK;
 }
 
@@ -939,9 +952,41 @@ hps_status hps_ctx_create(void* hip_stream, hps_ctx** out) {
   return HPS_OK;
 }
 
+namespace {
+void drop_timed(hps_ctx* ctx) {
+  for (TimedLaunch& t : ctx->timed) {
+    (void)hipEventDestroy(t.start);
+    (void)hipEventDestroy(t.stop);
+  }
+  ctx->timed.clear();
+}
+}  // namespace
+
 hps_status hps_ctx_destroy(hps_ctx* ctx) {
-  if (ctx && ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+  if (ctx) {
+    (void)hipStreamSynchronize(ctx->stream);
+    drop_timed(ctx);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+  }
   delete ctx;
+  return HPS_OK;
+}
+
+hps_status hps_kernel_time(hps_ctx* ctx, int32_t kernel, int64_t* launches, double* total_ms, int64_t* units) {
+  if (!ctx || !launches || !total_ms || !units) return HPS_ERR_ARG;
+  if (kernel != HPS_KERNEL_LEAF) return fail(ctx, HPS_ERR_ARG, "unknown kernel id");
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  *launches = 0;
+  *total_ms = 0;
+  *units = 0;
+  for (const TimedLaunch& t : ctx->timed) {
+    if (t.kernel != kernel) continue;
+    float ms = 0;
+    HIPCHK(ctx, hipEventElapsedTime(&ms, t.start, t.stop));
+    *launches += 1;
+    *total_ms += ms;
+    *units += t.units;
+  }
   return HPS_OK;
 }
 
@@ -949,6 +994,12 @@ hps_status hps_set_option(hps_ctx* ctx, int32_t option, int32_t value) {
   if (!ctx) return HPS_ERR_ARG;
   if (option == HPS_OPT_GRAPHS) {
     ctx->use_graphs = value ? 1 : 0;
+    return HPS_OK;
+  }
+  if (option == HPS_OPT_TIMING) {
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    drop_timed(ctx);
+    ctx->timing = value ? 1 : 0;
     return HPS_OK;
   }
   return fail(ctx, HPS_ERR_ARG, "unknown option");
@@ -1132,7 +1183,19 @@ hps_status hps_build_leaves(hps_problem* const* pp, int32_t count, const double*
     for (int e0 = 0; e0 < lay.E; e0 += lay.leaf_chunk) {
       a.E0 = e0;
       a.count = std::min(lay.leaf_chunk, lay.E - e0);
+      TimedLaunch tl{};
+      if (p->ctx->timing) {
+        HIPCHK(p->ctx, hipEventCreate(&tl.start));
+        HIPCHK(p->ctx, hipEventCreate(&tl.stop));
+        tl.kernel = HPS_KERNEL_LEAF;
+        tl.units = a.count;
+        HIPCHK(p->ctx, hipEventRecord(tl.start, p->ctx->stream));
+      }
       HIPCHK(p->ctx, leaf_build(a, p->ctx->stream));
+      if (p->ctx->timing) {
+        HIPCHK(p->ctx, hipEventRecord(tl.stop, p->ctx->stream));
+        p->ctx->timed.push_back(tl);
+      }
     }
     if (lay.lev[1].f32) {
       // FP64 leaf maps serve the outer operator M_1; the FP32 copy feeds the

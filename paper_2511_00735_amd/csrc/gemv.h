@@ -62,6 +62,7 @@ struct GemvBatchT {
   int nsplit[kGemvMaxDesc];
   long long poff[kGemvMaxDesc];   // partial-sum offsets
   int batch;
+  int partials_only;              // every split writes partial sums; no epilogue
 };
 
 int gemv_nsplit(int M, int K, int batch);
@@ -69,6 +70,16 @@ int gemv_nsplit(int M, int K, int batch);
 // any of them is split along K (partial sums: at most gemv_nsplit * batch * M each).
 template <class M>
 hipError_t zgemv_batched(const GemvDescT<M>* d, int nd, int batch, cd* partial, hipStream_t st);
+// Partial sums only: descriptor i writes A x (alpha, y0 and y ignored) split
+// along K into partial[poff[i] + (s * batch + b) * M + r], s < nsplit[i], for
+// a consumer that sums them in split order.  One launch.
+struct GemvPartLayout {
+  long long poff[kGemvMaxDesc];
+  int nsplit[kGemvMaxDesc];
+};
+template <class M>
+hipError_t zgemv_partials(const GemvDescT<M>* d, int nd, int batch, cd* partial, GemvPartLayout* lay,
+                          hipStream_t st);
 
 // One V-cycle level with one workgroup per pair (levels with many small pairs).
 // Per pair j (children P = box 2j, Q = box 2j+1 of level g.level):

@@ -83,7 +83,7 @@ __global__ __launch_bounds__(kThreads) void gemv_kernel(GemvBatchT<Mt> gb, cd* p
   }
   red[grp][lane] = acc;
   __syncthreads();
-  if (nsplit == 1) {
+  if (nsplit == 1 && !gb.partials_only) {
     if (grp == 0 && r < d.M_) {
       const cd s = cadd(cadd(red[0][lane], red[1][lane]), cadd(red[2][lane], red[3][lane]));
       store_y(d.y, b, r, cmul(d.alpha, s));
@@ -242,6 +242,30 @@ hipError_t zgemv_batched(const GemvDescT<Mt>* d, int nd, int batch, cd* partial,
   return hipPeekAtLastError();
 }
 
+template <class Mt>
+hipError_t zgemv_partials(const GemvDescT<Mt>* d, int nd, int batch, cd* partial, GemvPartLayout* lay,
+                          hipStream_t st) {
+  if (nd <= 0 || nd > kGemvMaxDesc || batch <= 0 || !partial || !lay) return hipErrorInvalidValue;
+  GemvBatchT<Mt> gb{};
+  gb.batch = batch;
+  gb.partials_only = 1;
+  int gx = 0;
+  long long poff = 0;
+  for (int i = 0; i < nd; ++i) {
+    gb.d[i] = d[i];
+    const int tiles = (d[i].M_ + kRowsT - 1) / kRowsT;
+    const int ns = gemv_nsplit(d[i].M_, d[i].K, batch);
+    gb.nsplit[i] = ns;
+    gb.poff[i] = poff;
+    lay->nsplit[i] = ns;
+    lay->poff[i] = poff;
+    poff += (long long)ns * batch * d[i].M_;
+    gx = std::max(gx, tiles * ns);
+  }
+  hipLaunchKernelGGL(gemv_kernel<Mt>, dim3(gx, batch, nd), dim3(kThreads), 0, st, gb, partial);
+  return hipPeekAtLastError();
+}
+
 size_t small_level_lds(int m, int e) {
   return sizeof(cd) * (size_t)(std::max(4 * m + e, 2 * e + 4 * m) + kThreads);
 }
@@ -266,6 +290,7 @@ hipError_t vc_up_small(const SmallLevelT<Mt>& a, int pairs, cd* z, hipStream_t s
 
 template hipError_t zgemv_batched<cd>(const GemvDescT<cd>*, int, int, cd*, hipStream_t);
 template hipError_t zgemv_batched<cf>(const GemvDescT<cf>*, int, int, cd*, hipStream_t);
+template hipError_t zgemv_partials<cd>(const GemvDescT<cd>*, int, int, cd*, GemvPartLayout*, hipStream_t);
 template hipError_t vc_down_small<cd>(const SmallLevelT<cd>&, int, cd*, hipStream_t);
 template hipError_t vc_down_small<cf>(const SmallLevelT<cf>&, int, cd*, hipStream_t);
 template hipError_t vc_up_small<cd>(const SmallLevelT<cd>&, int, cd*, hipStream_t);

@@ -1,5 +1,5 @@
 // Leaf impedance-to-impedance maps (Sec. 3.1, eq. ItIOperator), one workgroup
-// per element.
+// per element, one launch per chunk of elements.
 //
 // With the element unknowns split into interior nodes (i) and boundary nodes
 // (G), the element matrix L of Sec. 3.1 is [[N_GG + i eta I, N_Gi], [L_iG, L_ii]]
@@ -14,6 +14,8 @@
 // [R | -q] in its trailing rows.  Only the 4p x 4p complex Cayley step remains.
 // This is the same T as the paper's complex n_loc x n_loc solve, computed with
 // about 1/7 of its flops and in real arithmetic.
+#include <algorithm>
+
 #include "common.h"
 #include "gj_small.h"
 #include "host.h"
@@ -94,7 +96,42 @@ __device__ inline double k_entry(const Dims& d, int r, int c, const double* D, c
   return 0.0;
 }
 
-__global__ __launch_bounds__(kThreads) void leaf_schur_kernel(LeafArgs a) {
+// T = -I + 2 i eta (R + i eta I)^-1 and H from [R | -q] in the trailing rows of
+// the reduced bordered matrix A; S: (4p)^2 complex LDS workspace.
+__device__ void leaf_cayley(const LeafArgs& a, const double* A, cd* S, int* ipiv, cd* colk) {
+  const Dims d = dims_of(a.N);
+  const int m = 4 * d.p, nloc = d.nloc, npiv = d.pp;
+  const int tid = threadIdx.x;
+  const int e = a.E0 + blockIdx.x;
+  for (int idx = tid; idx < m * m; idx += kThreads) {
+    const int r = idx % m, c = idx / m;
+    S[idx] = cmk(A[(size_t)(npiv + c) * nloc + npiv + r], r == c ? a.eta : 0.0);
+  }
+  __syncthreads();
+  gj_inplace_small(S, m, ipiv, colk, a.flag);
+  const int ix = e % a.n, iy = e / a.n;
+  cd* Tout = a.T + (size_t)morton_xy(ix, iy) * m * m;
+  const double te = 2.0 * a.eta;
+  for (int idx = tid; idx < m * m; idx += kThreads) {
+    const int r = idx % m, c = idx / m;
+    const cd z = S[idx];
+    Tout[idx] = cmk(-te * z.y - (r == c ? 1.0 : 0.0), te * z.x);
+  }
+  if (tid < m) {
+    cd q = cmk(0.0, 0.0);
+    if (a.s_nodes) {
+      for (int c = 0; c < m; ++c) {
+        const cd tc = cmk(A[(size_t)nloc * nloc + npiv + c], A[(size_t)(nloc + 1) * nloc + npiv + c]);
+        q = cfma(S[c * m + tid], tc, q);
+      }
+    }
+    a.H[(size_t)e * m + tid] = cmk(-te * q.y, te * q.x);
+  }
+}
+
+
+// One element per workgroup: the bordered real partial LU, then the Cayley step.
+__global__ __launch_bounds__(kThreads) void leaf_kernel(LeafArgs a) {
   extern __shared__ double lds[];
   __shared__ int piv_s[kNB];
   const Dims d = dims_of(a.N);
@@ -226,41 +263,10 @@ __global__ __launch_bounds__(kThreads) void leaf_schur_kernel(LeafArgs a) {
     }
     __syncthreads();
   }
-}
-
-__global__ __launch_bounds__(kThreads) void leaf_cayley_kernel(LeafArgs a) {
-  extern __shared__ cd S[];
-  __shared__ int ipiv[64];
-  __shared__ cd colk[64];
-  const Dims d = dims_of(a.N);
-  const int m = 4 * d.p, nloc = d.nloc, npiv = d.pp;
-  const int tid = threadIdx.x;
-  const int e = a.E0 + blockIdx.x;
-  const double* A = a.scratch + (size_t)blockIdx.x * nloc * d.ncol;
-  for (int idx = tid; idx < m * m; idx += kThreads) {
-    const int r = idx % m, c = idx / m;
-    S[idx] = cmk(A[(size_t)(npiv + c) * nloc + npiv + r], r == c ? a.eta : 0.0);
-  }
-  __syncthreads();
-  gj_inplace_small(S, m, ipiv, colk, a.flag);
-  const int ix = e % a.n, iy = e / a.n;
-  cd* Tout = a.T + (size_t)morton_xy(ix, iy) * m * m;
-  const double te = 2.0 * a.eta;
-  for (int idx = tid; idx < m * m; idx += kThreads) {
-    const int r = idx % m, c = idx / m;
-    const cd z = S[idx];
-    Tout[idx] = cmk(-te * z.y - (r == c ? 1.0 : 0.0), te * z.x);
-  }
-  if (tid < m) {
-    cd q = cmk(0.0, 0.0);
-    if (a.s_nodes) {
-      for (int c = 0; c < m; ++c) {
-        const cd tc = cmk(A[(size_t)nloc * nloc + npiv + c], A[(size_t)(nloc + 1) * nloc + npiv + c]);
-        q = cfma(S[c * m + tid], tc, q);
-      }
-    }
-    a.H[(size_t)e * m + tid] = cmk(-te * q.y, te * q.x);
-  }
+  // the factorisation's LDS is free again: the Cayley step reuses it
+  __shared__ int ipiv_c[64];
+  __shared__ cd colk_c[64];
+  leaf_cayley(a, A, reinterpret_cast<cd*>(lds), ipiv_c, colk_c);
 }
 
 }  // namespace
@@ -272,15 +278,12 @@ size_t leaf_scratch_doubles(int N, int count) {
 
 hipError_t leaf_build(const LeafArgs& a, hipStream_t st) {
   const int p = a.N - 1, nloc = p * p + 4 * p, ncol = nloc + 2;
-  const size_t lds1 = ((size_t)nloc * kNB + (size_t)kNB * ncol) * sizeof(double);
-  hipError_t e0 = allow_lds(leaf_schur_kernel, lds1);
+  const size_t lds_lu = ((size_t)nloc * kNB + (size_t)kNB * ncol) * sizeof(double);
+  const size_t lds_cayley = (size_t)(4 * p) * (4 * p) * sizeof(cd);
+  const size_t lds = std::max(lds_lu, lds_cayley);
+  hipError_t e0 = allow_lds(leaf_kernel, lds);
   if (e0 != hipSuccess) return e0;
-  hipLaunchKernelGGL(leaf_schur_kernel, dim3(a.count), dim3(kThreads), lds1, st, a);
-  hipError_t err = hipPeekAtLastError();
-  if (err != hipSuccess) return err;
-  const size_t lds2 = (size_t)(4 * p) * (4 * p) * sizeof(cd);
-  if ((err = allow_lds(leaf_cayley_kernel, lds2)) != hipSuccess) return err;
-  hipLaunchKernelGGL(leaf_cayley_kernel, dim3(a.count), dim3(kThreads), lds2, st, a);
+  hipLaunchKernelGGL(leaf_kernel, dim3(a.count), dim3(kThreads), lds, st, a);
   return hipPeekAtLastError();
 }
 

@@ -38,7 +38,26 @@ hipError_t multi_dot(const cd* V, long long vstride, int nvec, const cd* w, long
 hipError_t multi_axpy(const cd* V, long long vstride, int nvec, const cd* h, cd* w, long long n, int sign,
                       hipStream_t st);
 hipError_t normalize(const cd* w, const cd* nrm2, cd* out, long long n, cd* hout, hipStream_t st);
-hipError_t hessenberg_lsq(const cd* Hm, int ldh, int k, const cd* beta2, cd* y, int* kused,
-                          hipStream_t st);
+// Coarse k-step GMRES on compact coarse vectors of length n (one workgroup per
+// launch).  V: (k+1) x n basis, H: (k+1) x k Hessenberg (ld k+1).
+// start: V_0 = w / |w| with w = vec[idx], beta2 = |w|^2, H[0 .. hsize) = 0.
+hipError_t coarse_start(const int* idx, int n, const cd* vec, cd* V, cd* H, int hsize, cd* beta2,
+                        hipStream_t st);
+// The product w = M_L v_j: either given (w), or, for the top pair, v_j minus the
+// split-K partial sums of the two off-diagonal blocks (rows [0, m) from poff0,
+// rows [m, 2m) from poff1; ns splits each, partial[po + s*m + r]).
+struct CoarseW {
+  const cd* w;
+  const cd* part;
+  long long poff0, poff1;
+  int ns0, ns1;
+  int m;
+};
+// Arnoldi step j (0 <= j < kMaxCoarse): two-pass classical Gram-Schmidt,
+// V_{j+1} and column j of H.  wtmp: n scratch entries.
+hipError_t coarse_arnoldi(cd* V, int n, int j, const CoarseW& src, cd* wtmp, cd* Hcol, hipStream_t st);
+// y = argmin |beta e1 - H y| (Givens), vec[idx] = V y.
+hipError_t coarse_finish(const cd* H, int k, const cd* beta2, const cd* V, int n, const int* idx, cd* vec,
+                         hipStream_t st);
 
 }  // namespace hps

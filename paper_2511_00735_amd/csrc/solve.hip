@@ -260,12 +260,10 @@ __global__ void normalize_kernel(const cd* w, const cd* nrm2, cd* out, long long
 }
 
 // k-step GMRES least squares on the device: minimise |beta e1 - H y| for the
-// (k+1) x k Hessenberg H (column-major, ld = ldh) by Givens rotations; one thread.
-__global__ void hessenberg_lsq_kernel(const cd* Hm, int ldh, int k, const cd* beta2, cd* y,
-                                      int* kused) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  cd R[kMaxCoarse + 1][kMaxCoarse];
-  cd gv[kMaxCoarse + 1];
+// (k+1) x k Hessenberg H (column-major, ld ldh) by Givens rotations, one thread.
+// R: (kMaxCoarse+1) x kMaxCoarse and gv: kMaxCoarse+1 work arrays (LDS).
+__device__ void lsq_small(const cd* Hm, int ldh, int k, const cd* beta2, cd* y, int* kused,
+                          cd (*R)[kMaxCoarse], cd* gv) {
   const double beta = sqrt(fmax(beta2[0].x, 0.0));
   // the subdiagonal entries H[j+1][j] are the real Arnoldi norms; a (lucky)
   // breakdown h_{j+1,j} <= 1e-14 beta ends the Krylov space at j+1 vectors
@@ -301,6 +299,212 @@ __global__ void hessenberg_lsq_kernel(const cd* Hm, int ldh, int k, const cd* be
   }
   for (int i = kk; i < k; ++i) y[i] = cmk(0.0, 0.0);
   if (kused) *kused = kk;
+}
+
+// ---- the coarse k-step GMRES, one workgroup per launch ---------------------
+constexpr int kCT = 1024;
+
+// Sum over the workgroup (kCT threads) in a fixed order; valid in every thread.
+__device__ inline cd wg_sum(cd v, cd* red) {
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  cd r = cmk(0.0, 0.0);
+  for (int i = 0; i < kCT / 64; ++i) r = cadd(r, red[i]);
+  __syncthreads();
+  return r;
+}
+
+// V_0 = w / |w| with w = vec[idx]; beta2 = |w|^2; H = 0.
+__global__ __launch_bounds__(kCT) void coarse_start_kernel(const int* idx, int n, const cd* vec, cd* V, cd* H,
+                                                           int hsize, cd* beta2) {
+  __shared__ cd red[kCT / 64];
+  const int t = threadIdx.x;
+  cd acc = cmk(0.0, 0.0);
+  for (int i = t; i < n; i += kCT) {
+    const cd x = vec[idx[i]];
+    V[i] = x;
+    acc = cfma(cconj(x), x, acc);
+  }
+  const cd nr2 = wg_sum(acc, red);
+  if (t == 0) beta2[0] = nr2;
+  const double nr = sqrt(fmax(nr2.x, 0.0));
+  const double sc = nr > 0.0 ? 1.0 / nr : 0.0;
+  for (int i = t; i < n; i += kCT) V[i] = cscale(V[i], sc);
+  for (int i = t; i < hsize; i += kCT) H[i] = cmk(0.0, 0.0);
+}
+
+// Arnoldi step j: w = M v_j (given, or v_j minus the split-K partial sums of
+// the pair-form product), two passes of classical Gram-Schmidt against
+// V_0..V_j (dots in a fixed order), V_{j+1} = w / |w|, H column j.
+__global__ __launch_bounds__(kCT) void coarse_arnoldi_kernel(cd* V, int n, int j, CoarseW src, cd* w, cd* Hcol) {
+  __shared__ cd h[kMaxCoarse + 1], h2[kMaxCoarse + 1];
+  __shared__ cd red[kCT / 64];
+  const int t = threadIdx.x;
+  const cd* vj = V + (long long)j * n;
+  for (int i = t; i < n; i += kCT) {
+    cd x;
+    if (src.part) {
+      const bool second = i >= src.m;
+      const int r = second ? i - src.m : i;
+      const long long po = second ? src.poff1 : src.poff0;
+      const int ns = second ? src.ns1 : src.ns0;
+      cd acc = cmk(0.0, 0.0);
+      for (int q = 0; q < ns; ++q) acc = cadd(acc, src.part[po + (long long)q * src.m + r]);
+      x = csub(vj[i], acc);
+    } else {
+      x = src.w[i];
+    }
+    w[i] = x;
+  }
+  __syncthreads();
+  const int v = t >> 5, l = t & 31;
+  for (int pass = 0; pass < 2; ++pass) {
+    cd* hv = pass ? h2 : h;
+    cd acc = cmk(0.0, 0.0);
+    if (v <= j) {
+      const cd* Vv = V + (long long)v * n;
+      for (int i = l; i < n; i += 32) acc = cfma(cconj(Vv[i]), w[i], acc);
+    }
+    for (int off = 16; off > 0; off >>= 1) {
+      acc.x += __shfl_xor(acc.x, off);
+      acc.y += __shfl_xor(acc.y, off);
+    }
+    if (l == 0 && v <= j) hv[v] = acc;
+    __syncthreads();
+    for (int i = t; i < n; i += kCT) {
+      cd a = w[i];
+      for (int q = 0; q <= j; ++q) a = csub(a, cmul(hv[q], V[(long long)q * n + i]));
+      w[i] = a;
+    }
+    __syncthreads();
+  }
+  cd acc = cmk(0.0, 0.0);
+  for (int i = t; i < n; i += kCT) acc = cfma(cconj(w[i]), w[i], acc);
+  const cd nr2 = wg_sum(acc, red);
+  const double nr = sqrt(fmax(nr2.x, 0.0));
+  const double sc = nr > 0.0 ? 1.0 / nr : 0.0;
+  cd* vn = V + (long long)(j + 1) * n;
+  for (int i = t; i < n; i += kCT) vn[i] = cscale(w[i], sc);
+  if (t <= j) Hcol[t] = cadd(h[t], h2[t]);
+  if (t == 0) Hcol[j + 1] = cmk(nr, 0.0);
+}
+
+// Arnoldi step j for short coarse vectors (n <= EP * kCT) and few basis vectors
+// (j < kFastV): every thread keeps its EP entries of w and of V_0..V_j in
+// registers, so global memory is read once and each reduction is one
+// workgroup sum of j+1 values.  Same arithmetic as coarse_arnoldi_kernel up to
+// the order of the dot-product sums.
+constexpr int kFastV = 6;
+
+template <int EP, int NT>
+__global__ __launch_bounds__(NT) void coarse_arnoldi_fast_kernel(cd* V, int n, int j, CoarseW src, cd* Hcol) {
+  __shared__ cd red[NT / 64][kFastV];
+  __shared__ cd hs[kFastV], hsum[kFastV];
+  const int t = threadIdx.x;
+  const cd zero = cmk(0.0, 0.0);
+  cd vv[kFastV][EP];
+  cd w[EP];
+#pragma unroll
+  for (int e = 0; e < EP; ++e) {
+    const int i = t + e * NT;
+#pragma unroll
+    for (int v = 0; v < kFastV; ++v) vv[v][e] = (v <= j && i < n) ? V[(long long)v * n + i] : zero;
+  }
+  const cd* vj = V + (long long)j * n;
+#pragma unroll
+  for (int e = 0; e < EP; ++e) {
+    const int i = t + e * NT;
+    cd x = zero;
+    if (i < n) {
+      if (src.part) {
+        const bool second = i >= src.m;
+        const int r = second ? i - src.m : i;
+        const long long po = second ? src.poff1 : src.poff0;
+        const int ns = second ? src.ns1 : src.ns0;
+        cd acc = zero;
+        for (int q0 = 0; q0 < ns; q0 += 8) {
+          cd tmp[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) tmp[u] = q0 + u < ns ? src.part[po + (long long)(q0 + u) * src.m + r] : zero;
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            if (q0 + u < ns) acc = cadd(acc, tmp[u]);
+        }
+        x = csub(vj[i], acc);
+      } else {
+        x = src.w[i];
+      }
+    }
+    w[e] = x;
+  }
+  for (int pass = 0; pass < 2; ++pass) {
+    cd acc[kFastV];
+#pragma unroll
+    for (int v = 0; v < kFastV; ++v) {
+      acc[v] = zero;
+#pragma unroll
+      for (int e = 0; e < EP; ++e) acc[v] = cfma(cconj(vv[v][e]), w[e], acc[v]);
+      acc[v] = wave_sum(acc[v]);
+    }
+    if ((t & 63) == 0) {
+#pragma unroll
+      for (int v = 0; v < kFastV; ++v) red[t >> 6][v] = acc[v];
+    }
+    __syncthreads();
+    if (t < kFastV) {
+      cd r = zero;
+      for (int q = 0; q < NT / 64; ++q) r = cadd(r, red[q][t]);
+      hs[t] = r;
+      hsum[t] = pass ? cadd(hsum[t], r) : r;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < kFastV; ++v) {
+      if (v > j) continue;
+      const cd hv = hs[v];
+#pragma unroll
+      for (int e = 0; e < EP; ++e) w[e] = csub(w[e], cmul(hv, vv[v][e]));
+    }
+    __syncthreads();
+  }
+  cd acc = zero;
+#pragma unroll
+  for (int e = 0; e < EP; ++e) acc = cfma(cconj(w[e]), w[e], acc);
+  acc = wave_sum(acc);
+  if ((t & 63) == 0) red[t >> 6][0] = acc;
+  __syncthreads();
+  cd nr2 = zero;
+  for (int q = 0; q < NT / 64; ++q) nr2 = cadd(nr2, red[q][0]);
+  const double nr = sqrt(fmax(nr2.x, 0.0));
+  const double sc = nr > 0.0 ? 1.0 / nr : 0.0;
+  cd* vn = V + (long long)(j + 1) * n;
+#pragma unroll
+  for (int e = 0; e < EP; ++e) {
+    const int i = t + e * NT;
+    if (i < n) vn[i] = cscale(w[e], sc);
+  }
+  if (t == 0) {
+#pragma unroll
+    for (int v = 0; v < kFastV; ++v)
+      if (v <= j) Hcol[v] = hsum[v];
+    Hcol[j + 1] = cmk(nr, 0.0);
+  }
+}
+
+// y = argmin |beta e1 - H y|, x = V y, vec[idx] = x.
+__global__ __launch_bounds__(kCT) void coarse_finish_kernel(const cd* H, int k, const cd* beta2, const cd* V, int n,
+                                                            const int* idx, cd* vec) {
+  __shared__ cd y[kMaxCoarse];
+  __shared__ cd R[kMaxCoarse + 1][kMaxCoarse];
+  __shared__ cd gv[kMaxCoarse + 1];
+  if (threadIdx.x == 0) lsq_small(H, k + 1, k, beta2, y, nullptr, R, gv);
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += kCT) {
+    cd acc = cmk(0.0, 0.0);
+    for (int v = 0; v < k; ++v) acc = cadd(acc, cmul(y[v], V[(long long)v * n + i]));
+    vec[idx[i]] = acc;
+  }
 }
 
 inline int grid_for(long long n, int block = 256, int cap = 2048) {
@@ -406,9 +610,30 @@ hipError_t normalize(const cd* w, const cd* nrm2, cd* out, long long n, cd* hout
   return hipPeekAtLastError();
 }
 
-hipError_t hessenberg_lsq(const cd* Hm, int ldh, int k, const cd* beta2, cd* y, int* kused,
-                          hipStream_t st) {
-  hipLaunchKernelGGL(hessenberg_lsq_kernel, dim3(1), dim3(64), 0, st, Hm, ldh, k, beta2, y, kused);
+
+hipError_t coarse_start(const int* idx, int n, const cd* vec, cd* V, cd* H, int hsize, cd* beta2,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(coarse_start_kernel, dim3(1), dim3(kCT), 0, st, idx, n, vec, V, H, hsize, beta2);
+  return hipPeekAtLastError();
+}
+
+hipError_t coarse_arnoldi(cd* V, int n, int j, const CoarseW& src, cd* wtmp, cd* Hcol, hipStream_t st) {
+  if (j < 0 || j + 1 > kMaxCoarse) return hipErrorInvalidValue;
+  if (j < kFastV && n <= 4 * 256)
+    hipLaunchKernelGGL((coarse_arnoldi_fast_kernel<4, 256>), dim3(1), dim3(256), 0, st, V, n, j, src, Hcol);
+  else if (j < kFastV && n <= 8 * 256)
+    hipLaunchKernelGGL((coarse_arnoldi_fast_kernel<8, 256>), dim3(1), dim3(256), 0, st, V, n, j, src, Hcol);
+  else if (j < kFastV && n <= 16 * 256)
+    hipLaunchKernelGGL((coarse_arnoldi_fast_kernel<16, 256>), dim3(1), dim3(256), 0, st, V, n, j, src, Hcol);
+  else
+    hipLaunchKernelGGL(coarse_arnoldi_kernel, dim3(1), dim3(kCT), 0, st, V, n, j, src, wtmp, Hcol);
+  return hipPeekAtLastError();
+}
+
+hipError_t coarse_finish(const cd* H, int k, const cd* beta2, const cd* V, int n, const int* idx, cd* vec,
+                         hipStream_t st) {
+  if (k < 1 || k > kMaxCoarse) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(coarse_finish_kernel, dim3(1), dim3(kCT), 0, st, H, k, beta2, V, n, idx, vec);
   return hipPeekAtLastError();
 }
 

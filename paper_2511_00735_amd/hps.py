@@ -21,6 +21,8 @@ HPS_OK, HPS_NOT_CONVERGED = 0, 1
 HPS_ERR = {-1: "HPS_ERR_ARG", -2: "HPS_ERR_OOM", -3: "HPS_ERR_SINGULAR",
            -4: "HPS_ERR_STATE", -5: "HPS_ERR_HIP"}
 HPS_FP64, HPS_MIXED = 0, 1
+HPS_OPT_GRAPHS, HPS_OPT_TIMING = 1, 2
+HPS_KERNEL_LEAF = 0
 
 
 class HPSError(RuntimeError):
@@ -58,6 +60,8 @@ _SIGS = {
     "hps_last_error": ([_P], ctypes.c_char_p),
     "hps_sync": ([_P], ctypes.c_int),
     "hps_set_option": ([_P, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
+    "hps_kernel_time": ([_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
+                         ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
     "hps_workspace_bytes": ([ctypes.POINTER(Desc), ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "hps_gll_nodes": ([ctypes.c_int32, _P], ctypes.c_int),
     "hps_node_coords": ([ctypes.POINTER(Desc), _P, _P], ctypes.c_int),
@@ -167,10 +171,22 @@ class Context:
 
     def set_graphs(self, on):
         """Replay the V-cycle from a captured HIP graph (default) or launch eagerly."""
-        self.check(lib.hps_set_option(self.handle, 1, 1 if on else 0), "hps_set_option")
+        self.check(lib.hps_set_option(self.handle, HPS_OPT_GRAPHS, 1 if on else 0), "hps_set_option")
+
+    def set_timing(self, on):
+        """Bracket launches of the timed kernels with HIP events (discards old records)."""
+        self.check(lib.hps_set_option(self.handle, HPS_OPT_TIMING, 1 if on else 0), "hps_set_option")
+
+    def kernel_time(self, kernel=None):
+        """(launches, summed device ms, units) of a timed kernel since set_timing."""
+        kernel = HPS_KERNEL_LEAF if kernel is None else kernel
+        n, ms, u = ctypes.c_int64(), ctypes.c_double(), ctypes.c_int64()
+        self.check(lib.hps_kernel_time(self.handle, kernel, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(u)),
+                   "hps_kernel_time")
+        return n.value, ms.value, u.value
 
     def __del__(self):
-        if getattr(self, "handle", None):
+        if getattr(self, "handle", None) and lib is not None:
             lib.hps_ctx_destroy(self.handle)
             self.handle = None
 
@@ -201,7 +217,7 @@ class Problem:
         self.lmax = 2 * int(round(np.log2(self.n)))
 
     def __del__(self):
-        if getattr(self, "handle", None):
+        if getattr(self, "handle", None) and lib is not None:
             lib.hps_problem_destroy(self.handle)
             self.handle = None
 
