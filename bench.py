@@ -62,6 +62,9 @@ def parse():
     ap.add_argument("--cpu-sample-seconds", type=float, default=15.0)
     ap.add_argument("--traffic-probe", action="store_true",
                     help="one 1 GiB device copy, then one leaf build (for rocprofv3 --pmc runs)")
+    ap.add_argument("--serve-seconds", type=float, default=5.0,
+                    help="length of the request trace served beside the headline (0: skip)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 256-problem batch")
     return ap.parse_args()
 
 
@@ -227,6 +230,40 @@ def run_precision(args, pr, precision, hps, torch):
     }
 
 
+def run_batch_c4(hps, torch):
+    """The 256 seeded problems of mixed shapes as one batch (all arriving at
+    t = 0): grouped by shape through the serving loop, against the same
+    problems solved one at a time."""
+    from paper_2511_00735_amd import workloads
+    from paper_2511_00735_amd.serve import Server
+    probs = workloads.c4(256, seed=4)
+    out = {"problems": len(probs), "shapes": len(set((p.n, p.N) for p in probs)),
+           "skeleton_dof": int(sum(p.skeleton_dof for p in probs))}
+    for label, kw in (("batched", dict(workers=3, max_batch=64)), ("one_by_one", dict(workers=1, max_batch=1))):
+        srv = Server(precision="mixed", memory_budget=200 << 30, **kw)
+        _, summ = srv.run(probs)
+        out[label] = {k: summ[k] for k in ("makespan_s", "solves_per_s", "dof_per_s", "mean_batch",
+                                           "converged", "max_relres")}
+    out["batched_over_one_by_one"] = round(out["batched"]["dof_per_s"] / out["one_by_one"]["dof_per_s"], 3)
+    return out
+
+
+def run_serving(hps, torch, seconds):
+    """The first `seconds` of the seeded Poisson request trace (50 req/s, 10%
+    128x128 N=16 kappa=400), served in real time, mixed vs FP64."""
+    from paper_2511_00735_amd import workloads
+    from paper_2511_00735_amd.serve import Server
+    trace = workloads.c5(duration=seconds)
+    out = {"trace": (f"first {seconds:g} s of the seeded Poisson trace (50 req/s): {len(trace)} requests, "
+                     f"{sum(1 for r in trace if r.n == 128)} at 128x128 N=16 kappa=400"),
+           "workers": 3, "memory_budget_gib": 200}
+    for prec in ("mixed", "fp64"):
+        srv = Server(precision=prec, workers=3, max_batch=32, memory_budget=200 << 30)
+        _, summ = srv.run(trace)
+        out[prec] = summ
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -314,6 +351,10 @@ def main():
         "dtype": "c64+c128" if args.precision == "mixed" else "c128",
         "data": "synthetic", "config": cfg, "roofline": roof,
     }
+    if not args.no_batch:
+        cfg["batch_256_problems"] = run_batch_c4(hps, torch)
+    if args.serve_seconds > 0:
+        cfg["serving"] = run_serving(hps, torch, args.serve_seconds)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pr, args.cpu_sample_seconds)
     print(json.dumps(out), flush=True)

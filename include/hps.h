@@ -167,7 +167,31 @@ hps_status hps_problem_create(hps_ctx* ctx, const hps_desc* desc, void* workspac
 hps_status hps_problem_destroy(hps_problem* p);
 hps_status hps_level_view_get(const hps_problem* p, int32_t level, hps_level_view* out);
 
-/* ---- the hot path (batch-first: `count` problems per call) --------------- */
+/* ---- groups: cross-problem batching ------------------------------------- */
+/* A group holds `count` problems of one shape -- equal n, order, levels,
+   coarse_iters, restart and precision -- whose wavenumbers kappa[i] and
+   impedance parameters eta[i] may differ (desc->kappa and desc->eta are
+   ignored), as do their coefficients, sources and boundary data.  The group
+   lives in one caller-provided workspace; every hot-path call runs each step
+   for all of its problems in the same launches (the level-l boxes of all
+   problems form one batch; the Krylov iterations run in lock step with
+   per-problem scalars and stopping).  A group handle is passed to the hot-path
+   calls like a problem handle: their per-problem arrays (b_nodes, s_nodes, t,
+   rhs, g, r, z, info) list the problems of all handles in order, so a group
+   of `count` problems consumes `count` consecutive entries.
+   1 <= count <= 4096.  Results equal those of the problems solved one by one
+   up to rounding (summation order of split reductions). */
+hps_status hps_group_workspace_bytes(const hps_desc* desc, int32_t count, size_t* bytes);
+hps_status hps_group_create(hps_ctx* ctx, const hps_desc* desc, int32_t count, const double* kappa,
+                            const double* eta, void* workspace, size_t bytes, hps_problem** out);
+/* Number of problems behind a handle (1 for hps_problem_create). */
+int32_t hps_group_size(const hps_problem* p);
+/* Level view of problem `member` (0-based) of a group; hps_level_view_get is
+   member 0. */
+hps_status hps_member_level_view(const hps_problem* p, int32_t member, int32_t level, hps_level_view* out);
+
+/* ---- the hot path (batch-first: `count` handles per call; per-problem arrays
+   hold one entry per problem behind the handles, see groups above) ---------- */
 /* Leaf ItI maps T and loads H of every element (Sec. 3.1, eq. ItIOperator).
    b_nodes[i]: real [E][(N+1)^2], the coefficient b at the element nodes.
    s_nodes[i]: complex [E][(N+1)^2] source s at the nodes, or NULL (H = 0). */

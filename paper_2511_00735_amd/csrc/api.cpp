@@ -38,6 +38,9 @@ namespace {
 
 inline size_t up256(size_t b) { return (b + 255) & ~size_t(255); }
 
+constexpr int kWorkVectors = 9;  // canonical group vectors in a workspace (see workv)
+constexpr int kMaxGroup = 4096;  // problems in one group
+
 struct Level {
   Geom g;
   size_t T_off = 0;     // box maps: complex FP64, or FP32 when f32 (level 1: always FP64)
@@ -57,7 +60,12 @@ struct Level {
   size_t Z0_off = 0;    // complex FP64 [pairs][2m]: A^-1 r_x of the down sweep
 };
 
+// Workspace of a group of nq problems of one shape.  Every per-problem array
+// is repeated nq times, problem after problem, so that the boxes (and pairs) of
+// one level form one contiguous batch of nq * boxes entries and the canonical
+// vectors of the group one vector of nq * nslots entries.
 struct Layout {
+  int nq;
   int n, N, p, E, L, Lmax, k, restart;
   bool exact, mixed;
   size_t stage_off = 0;  // FP32 output of the last FP32 merge, widened into FP64 maps
@@ -70,6 +78,7 @@ struct Layout {
   size_t V_off, Z_off, work_off;  // Krylov bases and 5 canonical work vectors
   size_t cV_off, cw_off, cx_off, cidx_off, cH_off, cy_off, cs_off;  // coarse GMRES
   size_t part_off, hh_off, one_off, flag_off;
+  size_t ysol_off;                 // [nq][restart] FGMRES update coefficients
   size_t gpart_off, gpart_elems;  // split-K GEMV partial sums
   size_t total;
 };
@@ -201,8 +210,12 @@ const char* check_desc(const hps_desc* d) {
   return nullptr;
 }
 
-Layout make_layout(const hps_desc* d) {
+// Per-problem device scratch of the outer Arnoldi step: h (R+2), h2 (R+2), |w|^2, norm, spare.
+inline size_t hh_stride(int restart) { return (size_t)2 * (restart + 2) + 4; }
+
+Layout make_layout(const hps_desc* d, int nq) {
   Layout lay;
+  lay.nq = nq;
   lay.n = d->n;
   lay.N = d->order;
   lay.p = d->order - 1;
@@ -214,12 +227,13 @@ Layout make_layout(const hps_desc* d) {
   lay.k = lay.exact ? 0 : d->coarse_iters;
   lay.restart = d->restart ? d->restart : 60;
   lay.nslots = (long long)lay.E * 4 * lay.p;
-  lay.leaf_chunk = std::min(lay.E, 1024);
+  lay.leaf_chunk = (int)std::min<long long>((long long)lay.E * nq, 1024);
+  const size_t Q = (size_t)nq;
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off += up256(bytes); return o; };
   const int N1 = lay.N + 1;
   lay.tables_off = take(sizeof(double) * (2 * N1 * N1 + N1));
-  lay.H_off = take(sizeof(cd) * (size_t)lay.E * 4 * lay.p);
+  lay.H_off = take(sizeof(cd) * Q * lay.E * 4 * lay.p);
   lay.lev.resize(lay.L + 1);
   size_t merge_scratch = 0;
   for (int l = 1; l <= lay.L; ++l) {
@@ -228,30 +242,31 @@ Layout make_layout(const hps_desc* d) {
     // mixed precision: merges 1 .. L-3 (and the V-cycle on those levels) in FP32,
     // the top two merges, the coarse level and the outer operator in FP64
     lv.f32 = lay.mixed && l <= lay.L - 3;
-    const size_t nmap = (size_t)lv.g.nboxes * lv.g.b * lv.g.b;
+    const size_t nmap = Q * lv.g.nboxes * lv.g.b * lv.g.b;
     lv.T_off = take((l == 1 || !lv.f32 ? sizeof(cd) : sizeof(cf)) * nmap);
     if (l == 1 && lv.f32) lv.T32_off = take(sizeof(cf) * nmap);
     if (lay.mixed && l == lay.L - 2 && l >= 2) lay.stage_off = take(sizeof(cf) * nmap);
     if (l < lay.L || (lay.exact && l == lay.L)) {
       set_merge_geom(lv);
       const size_t es = lv.f32 ? sizeof(cf) : sizeof(cd);
-      lv.Ainv_off = take(es * (size_t)lv.pairs * 4 * lv.m * lv.m);
-      if (l < lay.L) lv.X_off = take(es * (size_t)lv.pairs * 4 * lv.m * lv.e);
+      const size_t np = Q * lv.pairs;
+      lv.Ainv_off = take(es * np * 4 * lv.m * lv.m);
+      if (l < lay.L) lv.X_off = take(es * np * 4 * lv.m * lv.e);
       lv.map_off = take(sizeof(int) * 2 * (size_t)lv.e);
-      lv.xtab_off = take(sizeof(int) * (size_t)lv.pairs * 2 * lv.m);
-      lv.ytab_off = take(sizeof(int) * (size_t)lv.pairs * 2 * lv.e);
-      lv.dtab_off = take(sizeof(int) * (size_t)lv.pairs * 2 * lv.e);
-      lv.Z0_off = take(sizeof(cd) * (size_t)lv.pairs * 2 * lv.m);
-      const size_t zbytes = sizeof(cd) * (size_t)lv.pairs * lv.m * 2 * lv.e;
-      merge_scratch = std::max(merge_scratch, up256(zbytes) + up256(inverse_scratch_bytes<cd>(lv.m, lv.pairs)));
+      lv.xtab_off = take(sizeof(int) * np * 2 * lv.m);
+      lv.ytab_off = take(sizeof(int) * np * 2 * lv.e);
+      lv.dtab_off = take(sizeof(int) * np * 2 * lv.e);
+      lv.Z0_off = take(sizeof(cd) * np * 2 * lv.m);
+      const size_t zbytes = sizeof(cd) * np * lv.m * 2 * lv.e;
+      merge_scratch = std::max(merge_scratch, up256(zbytes) + up256(inverse_scratch_bytes<cd>(lv.m, (int)np)));
     }
   }
   lay.scratch_bytes = std::max(merge_scratch, sizeof(double) * leaf_scratch_doubles(lay.N, lay.leaf_chunk));
   lay.scratch_off = take(lay.scratch_bytes);
-  const size_t vb = sizeof(cd) * (size_t)lay.nslots;
+  const size_t vb = sizeof(cd) * Q * lay.nslots;
   lay.V_off = take(vb * (lay.restart + 1));
   lay.Z_off = take(vb * lay.restart);
-  lay.work_off = take(up256(vb) * 7);
+  lay.work_off = take(up256(vb) * kWorkVectors);
   {
     Level& top = lay.lev[lay.L];
     int nL = 0;
@@ -264,16 +279,18 @@ Layout make_layout(const hps_desc* d) {
     lay.nL = nL;
   }
   const int kk = std::max(lay.k, 1);
-  lay.cV_off = take(sizeof(cd) * (size_t)(kk + 1) * std::max(lay.nL, 1));
-  lay.cw_off = take(sizeof(cd) * (size_t)std::max(lay.nL, 1));
-  lay.cx_off = take(sizeof(cd) * (size_t)std::max(lay.nL, 1));
-  lay.cidx_off = take(sizeof(int) * (size_t)std::max(lay.nL, 1));
-  lay.cH_off = take(sizeof(cd) * (size_t)(kk + 1) * kk);
-  lay.cy_off = take(sizeof(cd) * (size_t)(kk + 1));
-  lay.cs_off = take(sizeof(cd) * 8);
-  lay.part_off = take(sizeof(cd) * (size_t)(lay.restart + 2) * kMaxDotBlocks);
-  lay.hh_off = take(sizeof(cd) * (size_t)(2 * (lay.restart + 2) + 4));
+  const size_t nL1 = std::max(lay.nL, 1);
+  lay.cV_off = take(sizeof(cd) * Q * (kk + 1) * nL1);
+  lay.cw_off = take(sizeof(cd) * Q * nL1);
+  lay.cx_off = take(sizeof(cd) * Q * nL1);
+  lay.cidx_off = take(sizeof(int) * Q * nL1);
+  lay.cH_off = take(sizeof(cd) * Q * (kk + 1) * kk);
+  lay.cy_off = take(sizeof(cd) * Q * (kk + 1));
+  lay.cs_off = take(sizeof(cd) * Q * 8);
+  lay.part_off = take(sizeof(cd) * Q * (lay.restart + 2) * kMaxDotBlocks);
+  lay.hh_off = take(sizeof(cd) * Q * hh_stride(lay.restart));
   lay.one_off = take(sizeof(cd));
+  lay.ysol_off = take(sizeof(cd) * Q * lay.restart);
   {
     // split-K GEMV partials: at most two descriptors per launch, of the shapes
     // (2m x 2m), (e x m), (2m x 2e) per merge level and (nL/2 x nL/2) for the
@@ -286,13 +303,14 @@ Layout make_layout(const hps_desc* d) {
     for (int l = 1; l <= lay.L; ++l) {
       const Level& lv = lay.lev[l];
       if (!lv.has_merge) continue;
-      need(2 * lv.m, 2 * lv.m, lv.pairs);
-      need(lv.e, lv.m, lv.pairs);
-      need(2 * lv.m, 2 * lv.e, lv.pairs);
+      const int np = nq * lv.pairs;
+      need(2 * lv.m, 2 * lv.m, np);
+      need(lv.e, lv.m, np);
+      need(2 * lv.m, 2 * lv.e, np);
     }
     if (lay.nL > 0) {  // the coarse pair-form product always goes through partial sums
-      const int ns = gemv_nsplit(lay.nL / 2, lay.nL / 2, 1);
-      mx = std::max(mx, (size_t)ns * (lay.nL / 2));
+      const int ns = gemv_nsplit(lay.nL / 2, lay.nL / 2, nq);
+      mx = std::max(mx, (size_t)ns * nq * (lay.nL / 2));
     }
     lay.gpart_elems = 2 * mx + 64;
     lay.gpart_off = take(sizeof(cd) * lay.gpart_elems);
@@ -307,9 +325,12 @@ enum State { kCreated = 0, kLeaves = 1 };
 }  // namespace
 }  // namespace hps
 
+// A problem handle holds a group of lay.nq problems of one shape (one for
+// hps_problem_create); kappa and eta may differ between them.
 struct hps_problem {
   hps_ctx* ctx;
   hps_desc desc;
+  std::vector<double> kappa, eta;
   hps::Layout lay;
   char* ws;
   int state;
@@ -356,7 +377,7 @@ hps_status merge_impl(hps_problem* p, int l, const T* Tin, T* Tout) {
   hipStream_t st = c->stream;
   const Layout& lay = p->lay;
   const Level& lv = lay.lev[l];
-  const int b = lv.g.b, m = lv.m, e = lv.e, np = lv.pairs, m2 = 2 * m;
+  const int b = lv.g.b, m = lv.m, e = lv.e, np = lay.nq * lv.pairs, m2 = 2 * m;
   const long long pstride = 2LL * b * b;
   const T* TP = Tin;
   const T* TQ = Tin + (size_t)b * b;
@@ -413,6 +434,7 @@ hps_status merge_impl(hps_problem* p, int l, const T* Tin, T* Tout) {
     PhysSkip k{};
     k.enabled = 1;
     k.g = nx.g;
+    k.nbox = nx.g.nboxes;
     k.ymap = mp;
     k.row_y = row_y;
     k.row_off = row_off;
@@ -510,13 +532,14 @@ hps_status merge_one(hps_problem* p, int l) {
   hps_status s = merge_impl<cf>(p, l, Tmat<cf>(p, l), out);
   if (s != HPS_OK || nx.f32) return s;
   // the next merge runs in FP64: widen the level-(l+1) maps
-  HIPCHK(p->ctx, convert_c32_c64(out, Tlev(p, l + 1), (long long)nx.g.nboxes * nx.g.b * nx.g.b, p->ctx->stream));
+  HIPCHK(p->ctx, convert_c32_c64(out, Tlev(p, l + 1), (long long)lay.nq * nx.g.nboxes * nx.g.b * nx.g.b,
+                                 p->ctx->stream));
   return HPS_OK;
 }
 
 // ---- V-cycle -------------------------------------------------------------
-bool small_level(const Level& lv) {
-  return lv.pairs >= 128 && lv.m <= 256 && small_level_lds(lv.m, lv.e) <= 64 * 1024;
+bool small_level(const Level& lv, int nq) {
+  return nq * lv.pairs >= 128 && lv.m <= 256 && small_level_lds(lv.m, lv.e) <= 64 * 1024;
 }
 
 template <class M>
@@ -545,15 +568,6 @@ VecIn vin_compact(const cd* ptr, long long stride) {
   v.stride = stride;
   return v;
 }
-VecIn vin_gather(const cd* vec, const Geom& g, int which, IdxMap local, bool partner) {
-  VecIn v{};
-  v.vec = vec;
-  v.g = g;
-  v.which = which;
-  v.local = local;
-  v.partner = partner ? 1 : 0;
-  return v;
-}
 VecIn vin_table(const cd* vec, const int* tab, long long tstride) {
   VecIn v{};
   v.vec = vec;
@@ -576,14 +590,6 @@ VecOut vout_compact(cd* ptr, long long stride, const cd* y0 = nullptr, long long
   v.beta = cmk(1, 0);
   return v;
 }
-void vout_scatter(VecOut& v, cd* vec, const Geom& g, int which, IdxMap local, bool partner, bool add) {
-  v.vec = vec;
-  v.g = g;
-  v.which = which;
-  v.local = local;
-  v.partner = partner ? 1 : 0;
-  v.add = add ? 1 : 0;
-}
 template <class M>
 GemvDescT<M> gdesc(int Mr, int K, OperandT<M> A, VecIn x, VecOut y, cd alpha = cmk(1, 0)) {
   GemvDescT<M> d{};
@@ -605,11 +611,11 @@ hps_status vcycle_down_t(hps_problem* p, int l, cd* wv) {
   hps_ctx* c = p->ctx;
   hipStream_t st = c->stream;
   const Level& lv = p->lay.lev[l];
-  if (small_level(lv)) {
-    HIPCHK(c, vc_down_small(small_args<M>(p, lv), lv.pairs, wv, st));
+  if (small_level(lv, p->lay.nq)) {
+    HIPCHK(c, vc_down_small(small_args<M>(p, lv), p->lay.nq * lv.pairs, wv, st));
     return HPS_OK;
   }
-  const int b = lv.g.b, m = lv.m, e = lv.e, np = lv.pairs, m2 = 2 * m;
+  const int b = lv.g.b, m = lv.m, e = lv.e, np = p->lay.nq * lv.pairs, m2 = 2 * m;
   const long long ps = 2LL * b * b;
   const M* T = Tmat<M>(p, l);
   cd* Z0 = at<cd>(p, lv.Z0_off);
@@ -635,11 +641,11 @@ hps_status vcycle_up_t(hps_problem* p, int l, cd* z) {
   hps_ctx* c = p->ctx;
   hipStream_t st = c->stream;
   const Level& lv = p->lay.lev[l];
-  if (small_level(lv)) {
-    HIPCHK(c, vc_up_small(small_args<M>(p, lv), lv.pairs, z, st));
+  if (small_level(lv, p->lay.nq)) {
+    HIPCHK(c, vc_up_small(small_args<M>(p, lv), p->lay.nq * lv.pairs, z, st));
     return HPS_OK;
   }
-  const int m2 = 2 * lv.m, e2 = 2 * lv.e, np = lv.pairs;
+  const int m2 = 2 * lv.m, e2 = 2 * lv.e, np = p->lay.nq * lv.pairs;
   const cd* Z0 = at<cd>(p, lv.Z0_off);
   VecOut o = vout_compact(nullptr, 0, Z0, m2);
   vout_table(o, z, at<int>(p, lv.xtab_off), m2, false);
@@ -657,31 +663,37 @@ hps_status vcycle_up(hps_problem* p, int l, cd* z) {
   return p->lay.lev[l].f32 ? vcycle_up_t<cf>(p, l, z) : vcycle_up_t<cd>(p, l, z);
 }
 
+// Canonical group vectors (nq * nslots entries): 0 the V-cycle residual, 1 the
+// FGMRES residual, 2-3 coarse scratch, 4 the Arnoldi vector, 5-6 the captured
+// V-cycle's input and output, 7-8 the group's right-hand side and solution.
 cd* workv(hps_problem* p, int i) {
-  return reinterpret_cast<cd*>(p->ws + p->lay.work_off + i * up256(sizeof(cd) * (size_t)p->lay.nslots));
+  return reinterpret_cast<cd*>(p->ws + p->lay.work_off +
+                               i * up256(sizeof(cd) * (size_t)p->lay.nslots * p->lay.nq));
 }
 
-// Classical Gram-Schmidt, two passes, against V[0..nv); coefficients summed into
-// h[0..nv) (device), w updated in place.  h2: nv scratch entries.
-hps_status cgs2(hps_problem* p, const cd* V, long long vstride, int nv, cd* w, long long n, cd* h, cd* h2) {
+// Classical Gram-Schmidt, two passes, against V[0..nv) for each problem of
+// the group (segments of n entries): coefficients summed into h (problem q at
+// h + q*hs), w updated in place; h2: the same layout, scratch.
+hps_status cgs2(hps_problem* p, const cd* V, long long vstride, int nv, cd* w, long long n, cd* h, cd* h2,
+                long long hs) {
   hps_ctx* c = p->ctx;
   hipStream_t st = c->stream;
+  const int nq = p->lay.nq;
   cd* part = at<cd>(p, p->lay.part_off);
-  const cd* one = at<cd>(p, p->lay.one_off);
-  HIPCHK(c, multi_dot(V, vstride, nv, w, n, part, h, false, st));
-  HIPCHK(c, multi_axpy(V, vstride, nv, h, w, n, -1, st));
-  HIPCHK(c, multi_dot(V, vstride, nv, w, n, part, h2, false, st));
-  HIPCHK(c, multi_axpy(V, vstride, nv, h2, w, n, -1, st));
-  HIPCHK(c, multi_axpy(h2, 0, 1, one, h, nv, +1, st));
-  (void)one;
+  HIPCHK(c, multi_dot(V, vstride, nv, w, n, part, h, false, st, nq, hs));
+  HIPCHK(c, multi_axpy(V, vstride, nv, h, w, n, -1, st, nq, hs));
+  HIPCHK(c, multi_dot(V, vstride, nv, w, n, part, h2, false, st, nq, hs));
+  HIPCHK(c, multi_axpy(V, vstride, nv, h2, w, n, -1, st, nq, hs));
+  HIPCHK(c, add_strided(h, h2, nv, nq, hs, st));
   return HPS_OK;
 }
 
 // Coarse matvec w = M_L v on compact coarse vectors below the top level: the
-// level-L skeleton matvec on canonical scratch vectors.  (At the top level the
-// coarse system is the single pair's A_L; coarse_solve forms that product from
-// split-K partial sums inside its Arnoldi step.)
-hps_status coarse_matvec(hps_problem* p, const cd* v, cd* w) {
+// level-L skeleton matvec on canonical scratch vectors.  v: problem q's vector
+// at v + q*vstride; w: [nq][nL].  (At the top level the coarse system is the
+// single pair's A_L; coarse_solve forms that product from split-K partial sums
+// inside its Arnoldi step.)
+hps_status coarse_matvec(hps_problem* p, const cd* v, long long vstride, cd* w) {
   hps_ctx* c = p->ctx;
   hipStream_t st = c->stream;
   const Layout& lay = p->lay;
@@ -689,9 +701,9 @@ hps_status coarse_matvec(hps_problem* p, const cd* v, cd* w) {
   const int* idx = at<int>(p, lay.cidx_off);
   cd* u1 = workv(p, 2);
   cd* u2 = workv(p, 3);
-  HIPCHK(c, index_scatter(idx, lay.nL, v, u1, st));
-  HIPCHK(c, skeleton_apply(top.g, Tlev(p, lay.L), u1, u2, false, st));
-  HIPCHK(c, index_gather(idx, lay.nL, u2, w, st));
+  HIPCHK(c, index_scatter(idx, lay.nL, v, u1, st, lay.nq, vstride));
+  HIPCHK(c, skeleton_apply(top.g, Tlev(p, lay.L), u1, u2, false, st, lay.nq));
+  HIPCHK(c, index_gather(idx, lay.nL, u2, w, st, lay.nq));
   return HPS_OK;
 }
 
@@ -701,6 +713,7 @@ hps_status coarse_solve(hps_problem* p, cd* wv, cd* z) {
   hipStream_t st = c->stream;
   const Layout& lay = p->lay;
   const Level& top = lay.lev[lay.L];
+  const int nq = lay.nq;
   if (lay.exact) {
     // z at the top pair's shared face = A_L^-1 r_x
     const int m2 = 2 * top.m;
@@ -709,19 +722,21 @@ hps_status coarse_solve(hps_problem* p, cd* wv, cd* z) {
     vout_table(o, z, xtab, m2, false);
     GemvDesc d = gdesc<cd>(m2, m2, Operand{at<cd>(p, top.Ainv_off), (long long)m2 * m2, m2, im_off(0), im_off(0)},
                            vin_table(wv, xtab, m2), o);
-    HIPCHK(c, zgemv_batched(&d, 1, 1, at<cd>(p, lay.gpart_off), st));
+    HIPCHK(c, zgemv_batched(&d, 1, nq, at<cd>(p, lay.gpart_off), st));
     return HPS_OK;
   }
   const int nL = lay.nL, k = lay.k;
   if (nL == 0) return HPS_OK;
+  const long long vq = (long long)(k + 1) * nL;  // one problem's coarse basis
+  const int hsize = (k + 1) * k;
   const int* idx = at<int>(p, lay.cidx_off);
   cd* V = at<cd>(p, lay.cV_off);
   cd* w = at<cd>(p, lay.cw_off);
   cd* wt = at<cd>(p, lay.cx_off);
   cd* H = at<cd>(p, lay.cH_off);
-  cd* sc = at<cd>(p, lay.cs_off);  // [0]: beta^2
+  cd* sc = at<cd>(p, lay.cs_off);  // beta^2 per problem
   cd* part = at<cd>(p, lay.gpart_off);
-  HIPCHK(c, coarse_start(idx, nL, wv, V, H, (k + 1) * k, sc, st));
+  HIPCHK(c, coarse_start(idx, nL, wv, V, vq, H, hsize, sc, nq, st));
   const bool pair_form = lay.L == lay.Lmax;
   for (int j = 0; j < k; ++j) {
     const cd* vj = V + (size_t)j * nL;
@@ -731,27 +746,29 @@ hps_status coarse_solve(hps_problem* p, cd* wv, cd* z) {
       const int b = top.g.b;
       const int m = nL / 2;
       const cd* T = Tlev(p, lay.L);
+      const long long ts = 2LL * b * b;  // one problem's two top boxes
       const int aP = top.g.off[3], bQ = top.g.off[2];   // P's top side, Q's bottom side
-      GemvDesc d[2] = {gdesc<cd>(m, m, Operand{T + (size_t)b * b, 0, b, im_off(bQ), im_off(bQ)},
-                                 vin_compact(vj + m, 0), vout_compact(nullptr, 0)),
-                       gdesc<cd>(m, m, Operand{T, 0, b, im_off(aP), im_off(aP)}, vin_compact(vj, 0),
+      GemvDesc d[2] = {gdesc<cd>(m, m, Operand{T + (size_t)b * b, ts, b, im_off(bQ), im_off(bQ)},
+                                 vin_compact(vj + m, vq), vout_compact(nullptr, 0)),
+                       gdesc<cd>(m, m, Operand{T, ts, b, im_off(aP), im_off(aP)}, vin_compact(vj, vq),
                                  vout_compact(nullptr, 0))};
       GemvPartLayout pl{};
-      HIPCHK(c, zgemv_partials(d, 2, 1, part, &pl, st));
+      HIPCHK(c, zgemv_partials(d, 2, nq, part, &pl, st));
       src.part = part;
       src.poff0 = pl.poff[0];
       src.poff1 = pl.poff[1];
       src.ns0 = pl.nsplit[0];
       src.ns1 = pl.nsplit[1];
       src.m = m;
+      src.nb = nq;
     } else {
-      hps_status s = coarse_matvec(p, vj, w);
+      hps_status s = coarse_matvec(p, vj, vq, w);
       if (s != HPS_OK) return s;
       src.w = w;
     }
-    HIPCHK(c, coarse_arnoldi(V, nL, j, src, wt, H + (size_t)j * (k + 1), st));
+    HIPCHK(c, coarse_arnoldi(V, nL, vq, j, src, wt, H + (size_t)j * (k + 1), hsize, nq, st));
   }
-  HIPCHK(c, coarse_finish(H, k, sc, V, nL, idx, z, st));
+  HIPCHK(c, coarse_finish(H, k, hsize, sc, V, nL, vq, idx, z, nq, st));
   return HPS_OK;
 }
 
@@ -760,8 +777,9 @@ hps_status precond_one(hps_problem* p, const cd* r, cd* z) {
   hipStream_t st = c->stream;
   const Layout& lay = p->lay;
   cd* wv = workv(p, 0);
-  HIPCHK(c, vfill(z, lay.nslots, cmk(0, 0), st));
-  HIPCHK(c, vcopy(r, wv, lay.nslots, st));
+  const long long ntot = lay.nslots * lay.nq;
+  HIPCHK(c, vfill(z, ntot, cmk(0, 0), st));
+  HIPCHK(c, vcopy(r, wv, ntot, st));
   for (int l = 1; l < lay.L; ++l) {
     hps_status s = vcycle_down(p, l, wv);
     if (s != HPS_OK) return s;
@@ -781,7 +799,7 @@ hps_status precond_one(hps_problem* p, const cd* r, cd* z) {
 // application.  The graph holds no memset nodes and no host synchronisation.
 hps_status precond_graphed(hps_problem* p, const cd* r, cd* z) {
   hps_ctx* c = p->ctx;
-  const long long n = p->lay.nslots;
+  const long long n = p->lay.nslots * p->lay.nq;
   cd* rin = workv(p, 5);
   cd* zout = workv(p, 6);
   if (!p->pgraph && !p->graph_failed) {
@@ -841,101 +859,246 @@ hps_status read_flag(hps_problem* p) {
 // ---- outer flexible GMRES ------------------------------------------------
 typedef std::complex<double> zc;
 
-hps_status fgmres_one(hps_problem* p, const cd* rhs, cd* g, double tol, int maxit, hps_info* info) {
+// Flexible GMRES(R) for all nq problems of a group in lock step: every
+// iteration runs one V-cycle, one M_1 product and one CGS2 step for the whole
+// group and copies the group's Hessenberg columns to the host once; Givens
+// rotations, estimates and stopping are per problem.  A problem that has
+// converged (or reached maxit) stops taking part in the least-squares updates,
+// so its solution stays as it was.  rhs, g: group vectors.
+hps_status fgmres_group(hps_problem* p, const cd* rhs, cd* g, double tol, int maxit, hps_info* info) {
   hps_ctx* c = p->ctx;
   hipStream_t st = c->stream;
   const Layout& lay = p->lay;
+  const int nq = lay.nq;
   const long long n = lay.nslots;
+  const long long ntot = n * nq;
   const int R = lay.restart;
-  const size_t vb = (size_t)n;
+  const long long HS = (long long)hh_stride(R);
   cd* V = at<cd>(p, lay.V_off);
   cd* Z = at<cd>(p, lay.Z_off);
   cd* res = workv(p, 1);
   cd* w = workv(p, 4);
-  cd* hh = at<cd>(p, lay.hh_off);           // [0, R+2): h, [R+2, 2R+4): h2 ; [2R+4]: |w|^2, [2R+5]: norm
-  cd* part = at<cd>(p, lay.part_off);
+  cd* hh = at<cd>(p, lay.hh_off);  // per problem q at hh + q*HS: h [R+2], h2 [R+2], |w|^2, norm
   cd* hcol = hh;
   cd* h2 = hh + (R + 2);
   cd* nrm2 = hh + 2 * (R + 2);
   cd* hnorm = nrm2 + 1;
+  cd* part = at<cd>(p, lay.part_off);
+  cd* ysol = at<cd>(p, lay.ysol_off);
   const Geom& g1 = lay.lev[1].g;
   const cd* T1 = Tlev(p, 1);
-  info->status = HPS_OK;
-  info->iterations = 0;
-  info->relres_est = 0;
-  info->relres_true = 0;
-  // ||rhs||
-  cd hv[2];
-  HIPCHK(c, multi_dot(rhs, 0, 1, rhs, n, part, nrm2, false, st));
-  HIPCHK(c, hipMemcpyAsync(hv, nrm2, sizeof(cd), hipMemcpyDeviceToHost, st));
-  HIPCHK(c, hipStreamSynchronize(st));
-  const double bnorm = std::sqrt(std::max(hv[0].x, 0.0));
-  HIPCHK(c, vfill(g, n, cmk(0, 0), st));
-  if (bnorm == 0.0) return HPS_OK;
-  HIPCHK(c, vcopy(rhs, res, n, st));
-  int it = 0;
-  double est = 1.0;
-  std::vector<zc> Hm((size_t)(R + 1) * R), cs(R), sn(R), gv(R + 1);
-  std::vector<cd> host((size_t)2 * (R + 2) + 2);
-  while (true) {
-    HIPCHK(c, multi_dot(res, 0, 1, res, n, part, nrm2, false, st));
-    HIPCHK(c, hipMemcpyAsync(hv, nrm2, sizeof(cd), hipMemcpyDeviceToHost, st));
+  std::vector<cd> host((size_t)HS * nq);
+  auto fetch = [&]() -> hps_status {
+    HIPCHK(c, hipMemcpyAsync(host.data(), hh, sizeof(cd) * host.size(), hipMemcpyDeviceToHost, st));
     HIPCHK(c, hipStreamSynchronize(st));
-    const double beta = std::sqrt(std::max(hv[0].x, 0.0));
-    info->relres_true = beta / bnorm;
-    if (beta / bnorm <= tol || it >= maxit) break;
-    HIPCHK(c, normalize(res, nrm2, V, n, nullptr, st));
-    std::fill(gv.begin(), gv.end(), zc(0, 0));
-    gv[0] = beta;
-    int jend = 0;
-    for (int j = 0; j < R; ++j) {
-      hps_status s = precond_any(p, V + j * vb, Z + j * vb);
-      if (s != HPS_OK) return s;
-      HIPCHK(c, skeleton_apply(g1, T1, Z + j * vb, w, true, st));
-      s = cgs2(p, V, n, j + 1, w, n, hcol, h2);
-      if (s != HPS_OK) return s;
-      HIPCHK(c, multi_dot(w, 0, 1, w, n, part, nrm2, false, st));
-      HIPCHK(c, normalize(w, nrm2, V + (j + 1) * vb, n, hnorm, st));
-      HIPCHK(c, hipMemcpyAsync(host.data(), hh, sizeof(cd) * host.size(), hipMemcpyDeviceToHost, st));
-      HIPCHK(c, hipStreamSynchronize(st));
-      zc* col = &Hm[(size_t)j * (R + 1)];
-      for (int i = 0; i <= j; ++i) col[i] = zc(host[i].x, host[i].y);
-      col[j + 1] = zc(host[2 * (R + 2) + 1].x, 0.0);
-      for (int i = 0; i < j; ++i) {  // G_i = [[conj c, conj s], [-s, c]]
-        const zc t = std::conj(cs[i]) * col[i] + std::conj(sn[i]) * col[i + 1];
-        col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
-        col[i] = t;
+    return HPS_OK;
+  };
+  for (int q = 0; q < nq; ++q) info[q] = hps_info{HPS_OK, 0, 0.0, 0.0};
+  // ||rhs|| per problem
+  HIPCHK(c, multi_dot(rhs, 0, 1, rhs, n, part, nrm2, false, st, nq, HS));
+  hps_status s = fetch();
+  if (s != HPS_OK) return s;
+  std::vector<double> bnorm(nq);
+  for (int q = 0; q < nq; ++q) bnorm[q] = std::sqrt(std::max(host[q * HS + 2 * (R + 2)].x, 0.0));
+  HIPCHK(c, vfill(g, ntot, cmk(0, 0), st));
+  HIPCHK(c, vcopy(rhs, res, ntot, st));
+  std::vector<int> it(nq, 0), done(nq, 0), jend(nq, 0), live(nq, 0);
+  std::vector<double> est(nq, 1.0);
+  std::vector<std::vector<zc>> Hm(nq), cs(nq), sn(nq), gv(nq);
+  for (int q = 0; q < nq; ++q) {
+    Hm[q].assign((size_t)(R + 1) * R, zc(0, 0));
+    cs[q].assign(R, zc(0, 0));
+    sn[q].assign(R, zc(0, 0));
+    gv[q].assign(R + 1, zc(0, 0));
+    if (bnorm[q] == 0.0) done[q] = 1;  // g = 0 is exact
+  }
+  while (true) {
+    // true residual norms; a problem at tolerance or at maxit is done
+    HIPCHK(c, multi_dot(res, 0, 1, res, n, part, nrm2, false, st, nq, HS));
+    s = fetch();
+    if (s != HPS_OK) return s;
+    int active = 0;
+    for (int q = 0; q < nq; ++q) {
+      if (bnorm[q] == 0.0) continue;
+      const double beta = std::sqrt(std::max(host[q * HS + 2 * (R + 2)].x, 0.0));
+      info[q].relres_true = beta / bnorm[q];
+      if (info[q].relres_true <= tol || it[q] >= maxit) done[q] = 1;
+      live[q] = !done[q];
+      jend[q] = 0;
+      if (live[q]) {
+        ++active;
+        std::fill(gv[q].begin(), gv[q].end(), zc(0, 0));
+        gv[q][0] = beta;
       }
-      const double den = std::sqrt(std::norm(col[j]) + std::norm(col[j + 1]));
-      cs[j] = den > 0 ? col[j] / den : zc(1, 0);
-      sn[j] = den > 0 ? col[j + 1] / den : zc(0, 0);
-      col[j] = den;
-      col[j + 1] = 0;
-      gv[j + 1] = -sn[j] * gv[j];
-      gv[j] = std::conj(cs[j]) * gv[j];
-      ++it;
-      jend = j + 1;
-      est = std::abs(gv[j + 1]) / bnorm;
-      if (est <= tol || it >= maxit) break;
     }
-    std::vector<zc> yv(jend);
-    for (int i = jend - 1; i >= 0; --i) {
-      zc acc = gv[i];
-      for (int q = i + 1; q < jend; ++q) acc -= Hm[(size_t)q * (R + 1) + i] * yv[q];
-      yv[i] = acc / Hm[(size_t)i * (R + 1) + i];
+    if (active == 0) break;
+    HIPCHK(c, normalize(res, nrm2, V, n, nullptr, st, nq, HS, 0));
+    for (int j = 0; j < R; ++j) {
+      s = precond_any(p, V + (size_t)j * ntot, Z + (size_t)j * ntot);
+      if (s != HPS_OK) return s;
+      HIPCHK(c, skeleton_apply(g1, T1, Z + (size_t)j * ntot, w, true, st, nq));
+      s = cgs2(p, V, ntot, j + 1, w, n, hcol, h2, HS);
+      if (s != HPS_OK) return s;
+      HIPCHK(c, multi_dot(w, 0, 1, w, n, part, nrm2, false, st, nq, HS));
+      HIPCHK(c, normalize(w, nrm2, V + (size_t)(j + 1) * ntot, n, hnorm, st, nq, HS, HS));
+      s = fetch();
+      if (s != HPS_OK) return s;
+      int still = 0;
+      for (int q = 0; q < nq; ++q) {
+        if (!live[q]) continue;
+        const cd* hq = &host[q * HS];
+        zc* col = &Hm[q][(size_t)j * (R + 1)];
+        for (int i = 0; i <= j; ++i) col[i] = zc(hq[i].x, hq[i].y);
+        col[j + 1] = zc(hq[2 * (R + 2) + 1].x, 0.0);
+        for (int i = 0; i < j; ++i) {  // G_i = [[conj c, conj s], [-s, c]]
+          const zc t = std::conj(cs[q][i]) * col[i] + std::conj(sn[q][i]) * col[i + 1];
+          col[i + 1] = -sn[q][i] * col[i] + cs[q][i] * col[i + 1];
+          col[i] = t;
+        }
+        const double den = std::sqrt(std::norm(col[j]) + std::norm(col[j + 1]));
+        cs[q][j] = den > 0 ? col[j] / den : zc(1, 0);
+        sn[q][j] = den > 0 ? col[j + 1] / den : zc(0, 0);
+        col[j] = den;
+        col[j + 1] = 0;
+        gv[q][j + 1] = -sn[q][j] * gv[q][j];
+        gv[q][j] = std::conj(cs[q][j]) * gv[q][j];
+        ++it[q];
+        jend[q] = j + 1;
+        est[q] = std::abs(gv[q][j + 1]) / bnorm[q];
+        if (est[q] <= tol || it[q] >= maxit) live[q] = 0;
+        else ++still;
+      }
+      if (still == 0) break;
     }
-    std::vector<cd> yd(jend);
-    for (int i = 0; i < jend; ++i) yd[i] = cmk(yv[i].real(), yv[i].imag());
-    HIPCHK(c, hipMemcpyAsync(hcol, yd.data(), sizeof(cd) * jend, hipMemcpyHostToDevice, st));
-    HIPCHK(c, multi_axpy(Z, n, jend, hcol, g, n, +1, st));
+    // g += Z y per problem (y zero beyond a problem's own Krylov dimension)
+    int jmax = 0;
+    for (int q = 0; q < nq; ++q) jmax = std::max(jmax, jend[q]);
+    std::vector<cd> yd((size_t)nq * R, cmk(0, 0));
+    for (int q = 0; q < nq; ++q) {
+      const int je = jend[q];
+      std::vector<zc> yv(je);
+      for (int i = je - 1; i >= 0; --i) {
+        zc acc = gv[q][i];
+        for (int k = i + 1; k < je; ++k) acc -= Hm[q][(size_t)k * (R + 1) + i] * yv[k];
+        yv[i] = acc / Hm[q][(size_t)i * (R + 1) + i];
+      }
+      for (int i = 0; i < je; ++i) yd[(size_t)q * R + i] = cmk(yv[i].real(), yv[i].imag());
+    }
+    HIPCHK(c, hipMemcpyAsync(ysol, yd.data(), sizeof(cd) * yd.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(c, multi_axpy(Z, ntot, jmax, ysol, g, n, +1, st, nq, R));
     HIPCHK(c, hipStreamSynchronize(st));  // yd must outlive the copy
     // true residual
-    HIPCHK(c, skeleton_apply(g1, T1, g, w, true, st));
-    HIPCHK(c, axpby(cmk(1, 0), rhs, cmk(-1, 0), w, res, n, st));
+    HIPCHK(c, skeleton_apply(g1, T1, g, w, true, st, nq));
+    HIPCHK(c, axpby(cmk(1, 0), rhs, cmk(-1, 0), w, res, ntot, st));
   }
-  info->iterations = it;
-  info->relres_est = est;
-  info->status = (info->relres_true <= tol) ? HPS_OK : HPS_NOT_CONVERGED;
+  for (int q = 0; q < nq; ++q) {
+    info[q].iterations = it[q];
+    info[q].relres_est = bnorm[q] == 0.0 ? 0.0 : est[q];
+    info[q].status = (info[q].relres_true <= tol) ? HPS_OK : HPS_NOT_CONVERGED;
+  }
+  return HPS_OK;
+}
+
+}  // namespace
+
+namespace {
+
+hps_status group_create(hps_ctx* ctx, const hps_desc* desc, int count, const double* kappa, const double* eta,
+                        void* workspace, size_t bytes, hps_problem** out) {
+  if (!ctx || !out) return HPS_ERR_ARG;
+  if (const char* m = check_desc(desc)) return fail(ctx, HPS_ERR_ARG, m);
+  if (count < 1 || count > kMaxGroup) return fail(ctx, HPS_ERR_ARG, "group size out of range");
+  for (int q = 0; q < count; ++q)
+    if (!(std::isfinite(kappa[q]) && kappa[q] > 0 && std::isfinite(eta[q]) && eta[q] > 0))
+      return fail(ctx, HPS_ERR_ARG, "kappa and eta must be finite and > 0");
+  if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255))
+    return fail(ctx, HPS_ERR_ARG, "workspace must be a non-null 256-byte aligned device pointer");
+  Layout lay = make_layout(desc, count);
+  if (bytes < lay.total)
+    return fail(ctx, HPS_ERR_OOM, "workspace too small: need " + std::to_string(lay.total) + " bytes");
+  hps_problem* p = new hps_problem;
+  p->ctx = ctx;
+  p->desc = *desc;
+  p->kappa.assign(kappa, kappa + count);
+  p->eta.assign(eta, eta + count);
+  p->lay = lay;
+  p->ws = reinterpret_cast<char*>(workspace);
+  p->state = kCreated;
+  p->merged = 0;
+  p->have_T1 = false;
+  // small tables: GLL data, merge maps, slot tables (with each problem's offset
+  // into the group vectors), coarse index list, constants
+  GllTables t = gll_tables(desc->order);
+  std::vector<double> tab;
+  tab.insert(tab.end(), t.D.begin(), t.D.end());
+  tab.insert(tab.end(), t.w.begin(), t.w.end());
+  tab.insert(tab.end(), t.Kr.begin(), t.Kr.end());
+  HIPCHK(ctx, hipMemcpyAsync(p->ws + lay.tables_off, tab.data(), sizeof(double) * tab.size(),
+                             hipMemcpyHostToDevice, ctx->stream));
+  auto replicate = [&](const std::vector<int>& one) {
+    std::vector<int> all;
+    all.reserve(one.size() * count);
+    for (int q = 0; q < count; ++q)
+      for (int v : one) all.push_back(v < 0 ? -1 : (int)(v + (long long)q * lay.nslots));
+    return all;
+  };
+  // all uploads are ordered on the context's stream (after whatever last used
+  // this memory); the host copies stay alive until the synchronisation below
+  std::vector<std::vector<int>> keep;
+  auto upload = [&](size_t off, std::vector<int> v) -> hipError_t {
+    keep.push_back(std::move(v));
+    const std::vector<int>& h = keep.back();
+    return hipMemcpyAsync(p->ws + off, h.data(), sizeof(int) * h.size(), hipMemcpyHostToDevice, ctx->stream);
+  };
+  for (int l = 1; l <= lay.L; ++l) {
+    const Level& lv = lay.lev[l];
+    if (!lv.has_merge) continue;
+    std::vector<int> xt, yt, dt;
+    pair_tables(lv, xt, yt, dt);
+    HIPCHK(ctx, upload(lv.map_off, merge_map(lv)));
+    HIPCHK(ctx, upload(lv.xtab_off, replicate(xt)));
+    HIPCHK(ctx, upload(lv.ytab_off, replicate(yt)));
+    HIPCHK(ctx, upload(lv.dtab_off, replicate(dt)));
+  }
+  if (!lay.exact && lay.nL > 0) HIPCHK(ctx, upload(lay.cidx_off, replicate(coarse_slots(lay.lev[lay.L]))));
+  const cd one = cmk(1, 0);
+  HIPCHK(ctx, hipMemcpyAsync(p->ws + lay.one_off, &one, sizeof(cd), hipMemcpyHostToDevice, ctx->stream));
+  const int zero4[4] = {0, 0, 0, 0};
+  HIPCHK(ctx, hipMemcpyAsync(p->ws + lay.flag_off, zero4, sizeof(zero4), hipMemcpyHostToDevice, ctx->stream));
+  // Box maps of merged levels: entries on physical sides are never computed;
+  // they are kept at zero so that products with zero data stay zero.
+  for (int l = 2; l <= lay.L; ++l) {
+    const Level& lv = lay.lev[l];
+    const long long nmap = (long long)count * lv.g.nboxes * lv.g.b * lv.g.b;
+    HIPCHK(ctx, vfill(Tlev(p, l), lv.f32 ? (nmap + 1) / 2 : nmap, cmk(0, 0), ctx->stream));
+    if (lay.mixed && l == lay.L - 2 && l >= 2)
+      HIPCHK(ctx, vfill(at<cd>(p, lay.stage_off), (nmap + 1) / 2, cmk(0, 0), ctx->stream));
+  }
+  // Columns of X = A^-1 B on physical sides are likewise never computed.
+  for (int l = 1; l < lay.L; ++l) {
+    const Level& lv = lay.lev[l];
+    const long long nx = (long long)count * lv.pairs * 4 * lv.m * lv.e;
+    HIPCHK(ctx, vfill(at<cd>(p, lv.X_off), lv.f32 ? (nx + 1) / 2 : nx, cmk(0, 0), ctx->stream));
+  }
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  *out = p;
+  return HPS_OK;
+}
+
+// Visits the problems behind `count` handles in order: f(handle, member q,
+// index of that problem in the caller's per-problem arrays).
+template <class F>
+hps_status for_each_problem(hps_problem* const* pp, int count, F f) {
+  int base = 0;
+  for (int i = 0; i < count; ++i) {
+    hps_problem* p = pp[i];
+    if (!p) return HPS_ERR_ARG;
+    for (int q = 0; q < p->lay.nq; ++q) {
+      hps_status s = f(p, q, base + q);
+      if (s != HPS_OK) return s;
+    }
+    base += p->lay.nq;
+  }
   return HPS_OK;
 }
 
@@ -1015,7 +1178,13 @@ hps_status hps_sync(hps_ctx* ctx) {
 
 hps_status hps_workspace_bytes(const hps_desc* desc, size_t* bytes) {
   if (!bytes || check_desc(desc)) return HPS_ERR_ARG;
-  *bytes = make_layout(desc).total;
+  *bytes = make_layout(desc, 1).total;
+  return HPS_OK;
+}
+
+hps_status hps_group_workspace_bytes(const hps_desc* desc, int32_t count, size_t* bytes) {
+  if (!bytes || check_desc(desc) || count < 1 || count > kMaxGroup) return HPS_ERR_ARG;
+  *bytes = make_layout(desc, count).total;
   return HPS_OK;
 }
 
@@ -1071,67 +1240,17 @@ hps_status hps_slot_coords(const hps_desc* desc, double* x, double* y, double* n
 
 hps_status hps_problem_create(hps_ctx* ctx, const hps_desc* desc, void* workspace, size_t bytes,
                               hps_problem** out) {
-  if (!ctx || !out) return HPS_ERR_ARG;
-  if (const char* m = check_desc(desc)) return fail(ctx, HPS_ERR_ARG, m);
-  if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255))
-    return fail(ctx, HPS_ERR_ARG, "workspace must be a non-null 256-byte aligned device pointer");
-  Layout lay = make_layout(desc);
-  if (bytes < lay.total)
-    return fail(ctx, HPS_ERR_OOM, "workspace too small: need " + std::to_string(lay.total) + " bytes");
-  hps_problem* p = new hps_problem;
-  p->ctx = ctx;
-  p->desc = *desc;
-  p->lay = lay;
-  p->ws = reinterpret_cast<char*>(workspace);
-  p->state = kCreated;
-  p->merged = 0;
-  p->have_T1 = false;
-  // small tables: GLL data, merge maps, coarse index list, constants
-  GllTables t = gll_tables(desc->order);
-  std::vector<double> tab;
-  tab.insert(tab.end(), t.D.begin(), t.D.end());
-  tab.insert(tab.end(), t.w.begin(), t.w.end());
-  tab.insert(tab.end(), t.Kr.begin(), t.Kr.end());
-  HIPCHK(ctx, hipMemcpy(p->ws + lay.tables_off, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice));
-  for (int l = 1; l <= lay.L; ++l) {
-    const Level& lv = lay.lev[l];
-    if (!lv.has_merge) continue;
-    std::vector<int> mp = merge_map(lv);
-    HIPCHK(ctx, hipMemcpy(p->ws + lv.map_off, mp.data(), sizeof(int) * mp.size(), hipMemcpyHostToDevice));
-    std::vector<int> xt, yt, dt;
-    pair_tables(lv, xt, yt, dt);
-    HIPCHK(ctx, hipMemcpy(p->ws + lv.xtab_off, xt.data(), sizeof(int) * xt.size(), hipMemcpyHostToDevice));
-    HIPCHK(ctx, hipMemcpy(p->ws + lv.ytab_off, yt.data(), sizeof(int) * yt.size(), hipMemcpyHostToDevice));
-    HIPCHK(ctx, hipMemcpy(p->ws + lv.dtab_off, dt.data(), sizeof(int) * dt.size(), hipMemcpyHostToDevice));
-  }
-  if (!lay.exact && lay.nL > 0) {
-    std::vector<int> idx = coarse_slots(lay.lev[lay.L]);
-    HIPCHK(ctx, hipMemcpy(p->ws + lay.cidx_off, idx.data(), sizeof(int) * idx.size(), hipMemcpyHostToDevice));
-  }
-  const cd one = cmk(1, 0);
-  HIPCHK(ctx, hipMemcpy(p->ws + lay.one_off, &one, sizeof(cd), hipMemcpyHostToDevice));
-  // Box maps of merged levels: entries on physical sides are never computed;
-  // they are kept at zero so that products with zero data stay zero.
-  for (int l = 2; l <= lay.L; ++l) {
-    const Level& lv = lay.lev[l];
-    const long long nmap = (long long)lv.g.nboxes * lv.g.b * lv.g.b;
-    HIPCHK(ctx, vfill(Tlev(p, l), lv.f32 ? (nmap + 1) / 2 : nmap, cmk(0, 0), ctx->stream));
-    if (lay.mixed && l == lay.L - 2 && l >= 2)
-      HIPCHK(ctx, vfill(at<cd>(p, lay.stage_off), (nmap + 1) / 2, cmk(0, 0), ctx->stream));
-  }
-  // Columns of X = A^-1 B on physical sides are likewise never computed.
-  for (int l = 1; l < lay.L; ++l) {
-    const Level& lv = lay.lev[l];
-    const long long nx = (long long)lv.pairs * 4 * lv.m * lv.e;
-    HIPCHK(ctx, vfill(at<cd>(p, lv.X_off), lv.f32 ? (nx + 1) / 2 : nx, cmk(0, 0), ctx->stream));
-  }
-  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-  int zero4[4] = {0, 0, 0, 0};
-  HIPCHK(ctx, hipMemcpy(p->ws + lay.flag_off, zero4, sizeof(zero4), hipMemcpyHostToDevice));
-
-  *out = p;
-  return HPS_OK;
+  if (!desc) return HPS_ERR_ARG;
+  return group_create(ctx, desc, 1, &desc->kappa, &desc->eta, workspace, bytes, out);
 }
+
+hps_status hps_group_create(hps_ctx* ctx, const hps_desc* desc, int32_t count, const double* kappa,
+                            const double* eta, void* workspace, size_t bytes, hps_problem** out) {
+  if (!desc || !kappa || !eta) return HPS_ERR_ARG;
+  return group_create(ctx, desc, count, kappa, eta, workspace, bytes, out);
+}
+
+int32_t hps_group_size(const hps_problem* p) { return p ? p->lay.nq : 0; }
 
 hps_status hps_problem_destroy(hps_problem* p) {
   if (p && p->pgraph) (void)hipGraphExecDestroy(p->pgraph);
@@ -1139,39 +1258,49 @@ hps_status hps_problem_destroy(hps_problem* p) {
   return HPS_OK;
 }
 
-hps_status hps_level_view_get(const hps_problem* pc, int32_t level, hps_level_view* out) {
+hps_status hps_member_level_view(const hps_problem* pc, int32_t member, int32_t level, hps_level_view* out) {
   hps_problem* p = const_cast<hps_problem*>(pc);
-  if (!p || !out || level < 1 || level > p->lay.L) return HPS_ERR_ARG;
+  if (!p || !out || level < 1 || level > p->lay.L || member < 0 || member >= p->lay.nq) return HPS_ERR_ARG;
   const Level& lv = p->lay.lev[level];
+  const bool f32 = lv.f32;
+  const size_t es = f32 ? sizeof(cf) : sizeof(cd);
+  const size_t q = (size_t)member;
   out->level = level;
   out->boxes = lv.g.nboxes;
   out->box_nodes = lv.g.b;
   out->morton = 1;
-  out->T = p->ws + ((level == 1 && lv.f32) ? lv.T32_off : lv.T_off);
-  out->fp32 = lv.f32 ? 1 : 0;
+  const size_t nmap = (size_t)lv.g.nboxes * lv.g.b * lv.g.b;
+  if (level == 1 && f32) out->T = p->ws + lv.T32_off + q * nmap * sizeof(cf);
+  else out->T = p->ws + lv.T_off + q * nmap * (level == 1 ? sizeof(cd) : es);
+  out->fp32 = f32 ? 1 : 0;
   out->pairs = lv.has_merge ? lv.pairs : 0;
   out->shared_nodes = lv.has_merge ? lv.m : 0;
-  out->Ainv = lv.has_merge ? (const void*)(p->ws + lv.Ainv_off) : nullptr;
-  out->X = (lv.has_merge && lv.X_off) ? (const void*)(p->ws + lv.X_off) : nullptr;
+  out->Ainv = lv.has_merge ? (const void*)(p->ws + lv.Ainv_off + q * lv.pairs * 4 * lv.m * lv.m * es) : nullptr;
+  out->X = (lv.has_merge && lv.X_off) ? (const void*)(p->ws + lv.X_off + q * lv.pairs * 4 * lv.m * lv.e * es)
+                                      : nullptr;
   return HPS_OK;
+}
+
+hps_status hps_level_view_get(const hps_problem* pc, int32_t level, hps_level_view* out) {
+  return hps_member_level_view(pc, 0, level, out);
 }
 
 hps_status hps_build_leaves(hps_problem* const* pp, int32_t count, const double* const* b_nodes,
                             const double* const* s_nodes) {
   if (!pp || count <= 0 || !b_nodes) return HPS_ERR_ARG;
+  int base = 0;
   for (int i = 0; i < count; ++i) {
     hps_problem* p = pp[i];
-    if (!p || !b_nodes[i]) return p ? fail(p->ctx, HPS_ERR_ARG, "null b_nodes") : HPS_ERR_ARG;
+    if (!p) return HPS_ERR_ARG;
     const Layout& lay = p->lay;
+    for (int q = 0; q < lay.nq; ++q)
+      if (!b_nodes[base + q]) return fail(p->ctx, HPS_ERR_ARG, "null b_nodes");
     const int N1 = lay.N + 1;
     LeafArgs a{};
     a.n = lay.n;
     a.N = lay.N;
+    a.E = lay.E;
     a.h = 1.0 / lay.n;
-    a.kappa = p->desc.kappa;
-    a.eta = p->desc.eta;
-    a.b_nodes = b_nodes[i];
-    a.s_nodes = s_nodes ? s_nodes[i] : nullptr;
     const double* tab = at<double>(p, lay.tables_off);
     a.D = tab;
     a.w = tab + N1 * N1;
@@ -1180,15 +1309,29 @@ hps_status hps_build_leaves(hps_problem* const* pp, int32_t count, const double*
     a.T = Tlev(p, 1);
     a.H = at<cd>(p, lay.H_off);
     a.flag = at<int>(p, lay.flag_off);
-    for (int e0 = 0; e0 < lay.E; e0 += lay.leaf_chunk) {
-      a.E0 = e0;
-      a.count = std::min(lay.leaf_chunk, lay.E - e0);
+    const long long Gtot = (long long)lay.E * lay.nq;
+    for (long long G0 = 0; G0 < Gtot;) {
+      // one launch: at most leaf_chunk elements of at most kLeafMaxQ problems
+      const int q0 = (int)(G0 / lay.E);
+      const long long lim = std::min<long long>(Gtot, (long long)(q0 + kLeafMaxQ) * lay.E);
+      const int cnt = (int)std::min<long long>(lay.leaf_chunk, lim - G0);
+      a.G0 = (int)G0;
+      a.count = cnt;
+      a.q0 = q0;
+      for (int u = 0; u < kLeafMaxQ; ++u) {
+        const int q = q0 + u;
+        const bool ok = q < lay.nq;
+        a.b_nodes[u] = ok ? b_nodes[base + q] : nullptr;
+        a.s_nodes[u] = ok && s_nodes ? s_nodes[base + q] : nullptr;
+        a.kappa[u] = ok ? p->kappa[q] : 1.0;
+        a.eta[u] = ok ? p->eta[q] : 1.0;
+      }
       TimedLaunch tl{};
       if (p->ctx->timing) {
         HIPCHK(p->ctx, hipEventCreate(&tl.start));
         HIPCHK(p->ctx, hipEventCreate(&tl.stop));
         tl.kernel = HPS_KERNEL_LEAF;
-        tl.units = a.count;
+        tl.units = cnt;
         HIPCHK(p->ctx, hipEventRecord(tl.start, p->ctx->stream));
       }
       HIPCHK(p->ctx, leaf_build(a, p->ctx->stream));
@@ -1196,16 +1339,18 @@ hps_status hps_build_leaves(hps_problem* const* pp, int32_t count, const double*
         HIPCHK(p->ctx, hipEventRecord(tl.stop, p->ctx->stream));
         p->ctx->timed.push_back(tl);
       }
+      G0 += cnt;
     }
     if (lay.lev[1].f32) {
       // FP64 leaf maps serve the outer operator M_1; the FP32 copy feeds the
       // FP32 merges and the FP32 levels of the V-cycle
       const Level& l1 = lay.lev[1];
       HIPCHK(p->ctx, convert_c64_c32(Tlev(p, 1), at<cf>(p, l1.T32_off),
-                                     (long long)l1.g.nboxes * l1.g.b * l1.g.b, p->ctx->stream));
+                                     (long long)lay.nq * l1.g.nboxes * l1.g.b * l1.g.b, p->ctx->stream));
     }
     p->state = kLeaves;
     p->merged = 0;
+    base += lay.nq;
   }
   return HPS_OK;
 }
@@ -1228,42 +1373,62 @@ hps_status hps_merge_level(hps_problem* const* pp, int32_t count, int32_t level)
 
 hps_status hps_set_rhs(hps_problem* const* pp, int32_t count, const double* const* t, double* const* rhs) {
   if (!pp || count <= 0 || !t || !rhs) return HPS_ERR_ARG;
-  for (int i = 0; i < count; ++i) {
-    hps_problem* p = pp[i];
+  return for_each_problem(pp, count, [&](hps_problem* p, int q, int k) -> hps_status {
     hps_status s = check_ready(p, false);
     if (s != HPS_OK) return s;
-    if (!t[i] || !rhs[i]) return fail(p->ctx, HPS_ERR_ARG, "null t or rhs");
-    HIPCHK(p->ctx, rhs_build(p->lay.lev[1].g, Tlev(p, 1), at<cd>(p, p->lay.H_off),
-                             reinterpret_cast<const cd*>(t[i]), reinterpret_cast<cd*>(rhs[i]), p->ctx->stream));
-  }
-  return HPS_OK;
+    if (!t[k] || !rhs[k]) return fail(p->ctx, HPS_ERR_ARG, "null t or rhs");
+    const Layout& lay = p->lay;
+    const Geom& g1 = lay.lev[1].g;
+    const size_t m = (size_t)4 * lay.p;
+    HIPCHK(p->ctx, rhs_build(g1, Tlev(p, 1) + (size_t)q * lay.E * m * m, at<cd>(p, lay.H_off) + (size_t)q * lay.E * m,
+                             reinterpret_cast<const cd*>(t[k]), reinterpret_cast<cd*>(rhs[k]), p->ctx->stream));
+    return HPS_OK;
+  });
 }
 
 hps_status hps_skeleton_apply(hps_problem* const* pp, int32_t count, int32_t level, const double* const* g,
                               double* const* out) {
   if (!pp || count <= 0 || !g || !out) return HPS_ERR_ARG;
-  for (int i = 0; i < count; ++i) {
-    hps_problem* p = pp[i];
+  return for_each_problem(pp, count, [&](hps_problem* p, int q, int k) -> hps_status {
     hps_status s = check_ready(p, false);
     if (s != HPS_OK) return s;
     if (level < 1 || level > p->lay.L) return fail(p->ctx, HPS_ERR_ARG, "level out of range");
     if (level > p->merged + 1) return fail(p->ctx, HPS_ERR_STATE, "level maps not built yet");
     if (level > 1 && p->lay.lev[level].f32)
       return fail(p->ctx, HPS_ERR_ARG, "this level's maps are stored in FP32 (mixed precision)");
-    HIPCHK(p->ctx, skeleton_apply(p->lay.lev[level].g, Tlev(p, level), reinterpret_cast<const cd*>(g[i]),
-                                  reinterpret_cast<cd*>(out[i]), level == 1, p->ctx->stream));
-  }
-  return HPS_OK;
+    if (!g[k] || !out[k]) return fail(p->ctx, HPS_ERR_ARG, "null vector");
+    const Geom& gl = p->lay.lev[level].g;
+    HIPCHK(p->ctx, skeleton_apply(gl, Tlev(p, level) + (size_t)q * gl.nboxes * gl.b * gl.b,
+                                  reinterpret_cast<const cd*>(g[k]), reinterpret_cast<cd*>(out[k]), level == 1,
+                                  p->ctx->stream));
+    return HPS_OK;
+  });
 }
 
 hps_status hps_precond_apply(hps_problem* const* pp, int32_t count, const double* const* r, double* const* z) {
   if (!pp || count <= 0 || !r || !z) return HPS_ERR_ARG;
+  int base = 0;
   for (int i = 0; i < count; ++i) {
     hps_problem* p = pp[i];
     hps_status s = check_ready(p, true);
     if (s != HPS_OK) return s;
-    s = precond_any(p, reinterpret_cast<const cd*>(r[i]), reinterpret_cast<cd*>(z[i]));
+    const long long n = p->lay.nslots;
+    const int nq = p->lay.nq;
+    for (int q = 0; q < nq; ++q)
+      if (!r[base + q] || !z[base + q]) return fail(p->ctx, HPS_ERR_ARG, "null vector");
+    if (nq == 1) {
+      s = precond_any(p, reinterpret_cast<const cd*>(r[base]), reinterpret_cast<cd*>(z[base]));
+    } else {
+      cd* rg = workv(p, 7);
+      cd* zg = workv(p, 8);
+      for (int q = 0; q < nq; ++q)
+        HIPCHK(p->ctx, vcopy(reinterpret_cast<const cd*>(r[base + q]), rg + q * n, n, p->ctx->stream));
+      s = precond_any(p, rg, zg);
+      for (int q = 0; s == HPS_OK && q < nq; ++q)
+        HIPCHK(p->ctx, vcopy(zg + q * n, reinterpret_cast<cd*>(z[base + q]), n, p->ctx->stream));
+    }
     if (s != HPS_OK) return s;
+    base += nq;
   }
   return HPS_OK;
 }
@@ -1272,15 +1437,33 @@ hps_status hps_gmres_solve(hps_problem* const* pp, int32_t count, const double* 
                            double tol, int32_t maxit, hps_info* info) {
   if (!pp || count <= 0 || !rhs || !g || !info || !(tol > 0) || maxit < 0) return HPS_ERR_ARG;
   hps_status worst = HPS_OK;
+  int base = 0;
   for (int i = 0; i < count; ++i) {
     hps_problem* p = pp[i];
     hps_status s = check_ready(p, true);
     if (s != HPS_OK) return s;
-    s = fgmres_one(p, reinterpret_cast<const cd*>(rhs[i]), reinterpret_cast<cd*>(g[i]), tol, maxit, &info[i]);
+    const long long n = p->lay.nslots;
+    const int nq = p->lay.nq;
+    for (int q = 0; q < nq; ++q)
+      if (!rhs[base + q] || !g[base + q]) return fail(p->ctx, HPS_ERR_ARG, "null vector");
+    if (nq == 1) {
+      s = fgmres_group(p, reinterpret_cast<const cd*>(rhs[base]), reinterpret_cast<cd*>(g[base]), tol, maxit,
+                       &info[base]);
+    } else {
+      cd* rg = workv(p, 7);
+      cd* gg = workv(p, 8);
+      for (int q = 0; q < nq; ++q)
+        HIPCHK(p->ctx, vcopy(reinterpret_cast<const cd*>(rhs[base + q]), rg + q * n, n, p->ctx->stream));
+      s = fgmres_group(p, rg, gg, tol, maxit, &info[base]);
+      for (int q = 0; s == HPS_OK && q < nq; ++q)
+        HIPCHK(p->ctx, vcopy(gg + q * n, reinterpret_cast<cd*>(g[base + q]), n, p->ctx->stream));
+    }
     if (s != HPS_OK) return s;
     s = read_flag(p);
     if (s != HPS_OK) return s;
-    if (info[i].status == HPS_NOT_CONVERGED) worst = HPS_NOT_CONVERGED;
+    for (int q = 0; q < nq; ++q)
+      if (info[base + q].status == HPS_NOT_CONVERGED) worst = HPS_NOT_CONVERGED;
+    base += nq;
   }
   return worst;
 }

@@ -60,7 +60,7 @@ __global__ __launch_bounds__(64 * WM * WN) void zgemm_kernel(GemmArgsT<T> a) {
   if (a.skip.enabled) {
     __shared__ int live_r, live_c;
     int bx, by;
-    box_xy(a.skip.g, b, bx, by);
+    box_xy(a.skip.g, b % a.skip.nbox, bx, by);
     if (tid == 0) {
       live_r = a.skip.row_y ? 0 : 1;
       live_c = a.skip.col_y ? 0 : 1;
@@ -163,7 +163,7 @@ __global__ void zcopy2d_kernel(int M, int N, OperandT<T> S, T alpha, T* D, long 
   const int b = blockIdx.y;
   const long long total = (long long)M * N;
   int bx = 0, by = 0;
-  if (skip.enabled) box_xy(skip.g, b, bx, by);
+  if (skip.enabled) box_xy(skip.g, b % skip.nbox, bx, by);
   for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
        idx += (long long)gridDim.x * blockDim.x) {
     const int i = (int)(idx % M), j = (int)(idx / M);

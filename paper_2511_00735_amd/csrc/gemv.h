@@ -9,25 +9,19 @@ constexpr int kGemvKChunkMax = 2048;     // K entries staged in LDS per split
 constexpr int kGemvTargetBlocks = 1024;  // split-K aims at this many workgroups
 
 // Source of a GEMV's x vector for batch entry (pair) b: a compact array
-// p[b*stride + k]; or the canonical vector gathered through a slot table,
-// vec[tab[b*tstride + k]] (negative slot: 0); or the canonical vector gathered
-// at the slots of box 2b + which (box-local index local(k)), optionally across
-// the face, physical entries reading as 0.
+// p[b*stride + k], or the canonical vector gathered through a slot table,
+// vec[tab[b*tstride + k]] (negative slot: 0).
 struct VecIn {
   const cd* p;
   long long stride;
   const cd* vec;
   const int* tab;
   long long tstride;
-  Geom g;
-  int which;
-  IdxMap local;
-  int partner;
 };
 
 // Destination of y = alpha A x (+ beta y0): a compact array and/or a scatter into
-// the canonical vector (assign or add), through a slot table (negative slots
-// skipped) or through box-side geometry (physical entries skipped).
+// the canonical vector through a slot table (assign or add; negative slots
+// skipped).
 struct VecOut {
   cd* p;
   long long stride;
@@ -37,10 +31,6 @@ struct VecOut {
   cd* vec;
   const int* tab;
   long long tstride;
-  Geom g;
-  int which;
-  IdxMap local;
-  int partner;
   int add;
 };
 

@@ -18,33 +18,16 @@ constexpr int kThreads = 256;
 
 __device__ inline cd load_x(const VecIn& x, int b, int k) {
   if (x.p) return x.p[(long long)b * x.stride + k];
-  if (x.tab) {
-    const int s = x.tab[(long long)b * x.tstride + k];
-    return s >= 0 ? x.vec[s] : cmk(0.0, 0.0);
-  }
-  int bx, by;
-  box_xy(x.g, 2 * b + x.which, bx, by);
-  const int lk = imap(x.local, k);
-  if (side_physical(x.g, bx, by, side_of(x.g, lk))) return cmk(0.0, 0.0);
-  int s = box_slot(x.g, bx, by, lk);
-  if (x.partner) s = slot_partner(x.g.n, x.g.p, s);
-  return x.vec[s];
+  const int s = x.tab[(long long)b * x.tstride + k];
+  return s >= 0 ? x.vec[s] : cmk(0.0, 0.0);
 }
 
 __device__ inline void store_y(const VecOut& y, int b, int i, cd v) {
   if (y.y0) v = cfma(y.beta, y.y0[(long long)b * y.y0stride + i], v);
   if (y.p) y.p[(long long)b * y.stride + i] = v;
-  if (y.vec && y.tab) {
+  if (y.vec) {
     const int s = y.tab[(long long)b * y.tstride + i];
     if (s >= 0) y.vec[s] = y.add ? cadd(y.vec[s], v) : v;
-  } else if (y.vec) {
-    int bx, by;
-    box_xy(y.g, 2 * b + y.which, bx, by);
-    const int lk = imap(y.local, i);
-    if (side_physical(y.g, bx, by, side_of(y.g, lk))) return;
-    int s = box_slot(y.g, bx, by, lk);
-    if (y.partner) s = slot_partner(y.g.n, y.g.p, s);
-    y.vec[s] = y.add ? cadd(y.vec[s], v) : v;
   }
 }
 

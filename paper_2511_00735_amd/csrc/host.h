@@ -17,17 +17,22 @@ struct GllTables {
 GllTables gll_tables(int N);
 
 // ---- leaf kernels (leaf.hip) ------------------------------------------------
+constexpr int kLeafMaxQ = 32;  // problems one leaf launch may touch
+// Elements G in [G0, G0+count) of a group of problems with E elements each:
+// problem q = G / E, element e = G % E (canonical numbering).  Per-problem
+// inputs of problems q0 .. q0+kLeafMaxQ-1 travel in the kernel arguments.
 struct LeafArgs {
-  int n, N, E0, count;        // elements [E0, E0+count) in canonical numbering
-  double h, kappa, eta;
-  const double* b_nodes;      // [E][(N+1)^2]
-  const double* s_nodes;      // complex [E][(N+1)^2] or null
+  int n, N, E, G0, count, q0;
+  double h;
+  const double* b_nodes[kLeafMaxQ];  // [E][(N+1)^2] per problem
+  const double* s_nodes[kLeafMaxQ];  // complex [E][(N+1)^2] per problem, or null
+  double kappa[kLeafMaxQ], eta[kLeafMaxQ];
   const double* D;            // (N+1)^2 row-major reference D
   const double* w;            // N+1
   const double* Kr;           // (N+1)^2 reference stiffness
   double* scratch;            // count * nloc * ncol doubles
-  cd* T;                      // level-1 box maps, Morton order, [E][4p][4p] col-major
-  cd* H;                      // [E][4p] canonical element order
+  cd* T;                      // level-1 box maps, [q][E][4p][4p], Morton order within a problem
+  cd* H;                      // [q][E][4p] canonical element order
   int* flag;                  // device error flag (bit 1: singular pivot)
 };
 hipError_t leaf_build(const LeafArgs& a, hipStream_t st);
@@ -46,12 +51,13 @@ typedef OperandT<cd> Operand;
 typedef OperandT<cf> OperandF;
 // Output tiles of a merge whose rows (or columns) all lie on physical sides of
 // the merged box are never needed: the skeleton unknowns are interior
-// impedances only.  Batch entry b writes merged box b of level g.level; a y
-// index i (rows: i + row_off when row_y, columns: j + col_off when col_y) lands
-// at box-local position ymap[i].
+// impedances only.  Batch entry b writes merged box b % nbox of level g.level
+// (of problem b / nbox of a group); a y index i (rows: i + row_off when row_y,
+// columns: j + col_off when col_y) lands at box-local position ymap[i].
 struct PhysSkip {
   int enabled;
   Geom g;
+  int nbox;
   const int* ymap;
   int row_y, col_y;
   int row_off, col_off;

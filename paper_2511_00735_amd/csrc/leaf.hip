@@ -102,30 +102,33 @@ __device__ void leaf_cayley(const LeafArgs& a, const double* A, cd* S, int* ipiv
   const Dims d = dims_of(a.N);
   const int m = 4 * d.p, nloc = d.nloc, npiv = d.pp;
   const int tid = threadIdx.x;
-  const int e = a.E0 + blockIdx.x;
+  const int G = a.G0 + blockIdx.x;
+  const int q = G / a.E, e = G % a.E;
+  const double eta = a.eta[q - a.q0];
+  const double* snode = a.s_nodes[q - a.q0];
   for (int idx = tid; idx < m * m; idx += kThreads) {
     const int r = idx % m, c = idx / m;
-    S[idx] = cmk(A[(size_t)(npiv + c) * nloc + npiv + r], r == c ? a.eta : 0.0);
+    S[idx] = cmk(A[(size_t)(npiv + c) * nloc + npiv + r], r == c ? eta : 0.0);
   }
   __syncthreads();
   gj_inplace_small(S, m, ipiv, colk, a.flag);
   const int ix = e % a.n, iy = e / a.n;
-  cd* Tout = a.T + (size_t)morton_xy(ix, iy) * m * m;
-  const double te = 2.0 * a.eta;
+  cd* Tout = a.T + ((size_t)q * a.E + morton_xy(ix, iy)) * m * m;
+  const double te = 2.0 * eta;
   for (int idx = tid; idx < m * m; idx += kThreads) {
     const int r = idx % m, c = idx / m;
     const cd z = S[idx];
     Tout[idx] = cmk(-te * z.y - (r == c ? 1.0 : 0.0), te * z.x);
   }
   if (tid < m) {
-    cd q = cmk(0.0, 0.0);
-    if (a.s_nodes) {
+    cd acc = cmk(0.0, 0.0);
+    if (snode) {
       for (int c = 0; c < m; ++c) {
         const cd tc = cmk(A[(size_t)nloc * nloc + npiv + c], A[(size_t)(nloc + 1) * nloc + npiv + c]);
-        q = cfma(S[c * m + tid], tc, q);
+        acc = cfma(S[c * m + tid], tc, acc);
       }
     }
-    a.H[(size_t)e * m + tid] = cmk(-te * q.y, te * q.x);
+    a.H[(size_t)G * m + tid] = cmk(-te * acc.y, te * acc.x);
   }
 }
 
@@ -139,15 +142,17 @@ __global__ __launch_bounds__(kThreads) void leaf_kernel(LeafArgs a) {
   double* P = lds;                          // panel, nloc x kNB, column-major (ld nloc)
   double* U = lds + (size_t)nloc * kNB;     // U12 block, kNB x ncol, row-major (ld ncol)
   const int tid = threadIdx.x;
-  const int e = a.E0 + blockIdx.x;
+  const int G = a.G0 + blockIdx.x;
+  const int q = G / a.E, e = G % a.E;
   const int N1 = a.N + 1;
   double* A = a.scratch + (size_t)blockIdx.x * nloc * ncol;
-  const double* bnode = a.b_nodes + (size_t)e * N1 * N1;
-  const double* snode = a.s_nodes ? a.s_nodes + (size_t)e * 2 * N1 * N1 : nullptr;
+  const double* bnode = a.b_nodes[q - a.q0] + (size_t)e * N1 * N1;
+  const double* sq = a.s_nodes[q - a.q0];
+  const double* snode = sq ? sq + (size_t)e * 2 * N1 * N1 : nullptr;
 
   for (int idx = tid; idx < nloc * ncol; idx += kThreads) {
     const int r = idx % nloc, c = idx / nloc;
-    A[idx] = k_entry(d, r, c, a.D, a.w, a.Kr, bnode, snode, a.kappa, a.h);
+    A[idx] = k_entry(d, r, c, a.D, a.w, a.Kr, bnode, snode, a.kappa[q - a.q0], a.h);
   }
   __syncthreads();
 

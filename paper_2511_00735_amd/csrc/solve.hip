@@ -13,11 +13,17 @@ namespace {
 constexpr int kRows = 64;  // rows per workgroup of the streaming matvec kernels
 
 // out[Pi(s)] = g[Pi(s)] - (T^B g_B)[s] for every interior boundary slot s of
-// every level-l box B.  Grid (boxes, ceil(b / 64)), 64 threads.
+// every level-l box B, for each problem of a group (boxes and canonical vectors
+// of problem q follow those of problem q-1).  Grid (problems * boxes,
+// ceil(b / 64)), 64 threads.
 __global__ __launch_bounds__(kRows) void skeleton_apply_kernel(Geom g, const cd* T, const cd* gin,
-                                                               cd* out, int zero_physical) {
+                                                               cd* out, int zero_physical, long long nslots) {
   extern __shared__ cd gB[];
-  const int j = blockIdx.x;
+  const int jg = blockIdx.x;
+  const int j = jg % g.nboxes;
+  const long long so = (long long)(jg / g.nboxes) * nslots;
+  gin += so;
+  out += so;
   const int r0 = blockIdx.y * kRows;
   int bx, by;
   box_xy(g, j, bx, by);
@@ -44,7 +50,7 @@ __global__ __launch_bounds__(kRows) void skeleton_apply_kernel(Geom g, const cd*
     if (zero_physical) out[slot] = cmk(0.0, 0.0);
     return;
   }
-  const cd* Tb = T + (long long)j * b * b;
+  const cd* Tb = T + (long long)jg * b * b;
   cd acc = cmk(0.0, 0.0);
   for (int s = 0; s < 4; ++s) {
     if (phys_side[s]) continue;
@@ -92,80 +98,26 @@ __global__ __launch_bounds__(kRows) void rhs_kernel(Geom g, const cd* T, const c
   }
 }
 
-// y[b] = alpha A_b x[b] + beta y0[b];  A_b addressed as an Operand (M x K).
-__global__ __launch_bounds__(kRows) void zgemv_kernel(GemvArgs a) {
-  extern __shared__ cd xs[];
-  const int b = blockIdx.y;
-  const cd* x = a.x + (long long)b * a.xs;
-  for (int k = threadIdx.x; k < a.K; k += kRows) xs[k] = x[k];
-  __syncthreads();
-  const int r = blockIdx.x * kRows + threadIdx.x;
-  if (r >= a.M) return;
-  const cd* Ab = a.A.base + (long long)b * a.A.bstride;
-  const int row = imap(a.A.r, r);
-  cd acc = cmk(0.0, 0.0);
-  int k = 0;
-  for (; k + 3 < a.K; k += 4) {
-    const cd t0 = Ab[(long long)imap(a.A.c, k) * a.A.ld + row];
-    const cd t1 = Ab[(long long)imap(a.A.c, k + 1) * a.A.ld + row];
-    const cd t2 = Ab[(long long)imap(a.A.c, k + 2) * a.A.ld + row];
-    const cd t3 = Ab[(long long)imap(a.A.c, k + 3) * a.A.ld + row];
-    acc = cfma(t0, xs[k], acc);
-    acc = cfma(t1, xs[k + 1], acc);
-    acc = cfma(t2, xs[k + 2], acc);
-    acc = cfma(t3, xs[k + 3], acc);
-  }
-  for (; k < a.K; ++k) acc = cfma(Ab[(long long)imap(a.A.c, k) * a.A.ld + row], xs[k], acc);
-  cd out = cmul(a.alpha, acc);
-  if (a.y0) out = cfma(a.beta, a.y0[(long long)b * a.y0s + r], out);
-  a.y[(long long)b * a.ys + r] = out;
+// i in [0, nq * n): problem q = i / n, entry r = i % n.
+__global__ void index_gather_kernel(const int* idx, int n, long long ntot, const cd* vec, cd* out,
+                                    long long ostride) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < ntot;
+       i += (long long)gridDim.x * blockDim.x)
+    out[(i / n) * ostride + i % n] = vec[idx[i]];
 }
 
-// Per pair j (box 2j + which at level g.level): out[j][i] = vec[slot(k_i)]
-// (or vec at the partner slot), zero if k_i lies on a physical side.
-__global__ void pair_gather_kernel(Geom g, int which, IdxMap local, int len, const cd* vec, cd* out,
-                                   long long ostride, int use_partner) {
-  const int j = blockIdx.y;
-  int bx, by;
-  box_xy(g, 2 * j + which, bx, by);
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < len; i += gridDim.x * blockDim.x) {
-    const int k = imap(local, i);
-    const int s = side_of(g, k);
-    cd v = cmk(0.0, 0.0);
-    if (!side_physical(g, bx, by, s)) {
-      int slot = box_slot(g, bx, by, k);
-      if (use_partner) slot = slot_partner(g.n, g.p, slot);
-      v = vec[slot];
-    }
-    out[(long long)j * ostride + i] = v;
-  }
+__global__ void index_scatter_kernel(const int* idx, int n, long long ntot, const cd* in, long long istride,
+                                     cd* vec) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < ntot;
+       i += (long long)gridDim.x * blockDim.x)
+    vec[idx[i]] = in[(i / n) * istride + i % n];
 }
 
-// Inverse of pair_gather: vec[slot] (= or +=) in[j][i]; physical entries skipped.
-__global__ void pair_scatter_kernel(Geom g, int which, IdxMap local, int len, const cd* in,
-                                    long long istride, cd* vec, int use_partner, int add) {
-  const int j = blockIdx.y;
-  int bx, by;
-  box_xy(g, 2 * j + which, bx, by);
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < len; i += gridDim.x * blockDim.x) {
-    const int k = imap(local, i);
-    const int s = side_of(g, k);
-    if (side_physical(g, bx, by, s)) continue;
-    int slot = box_slot(g, bx, by, k);
-    if (use_partner) slot = slot_partner(g.n, g.p, slot);
-    const cd v = in[(long long)j * istride + i];
-    vec[slot] = add ? cadd(vec[slot], v) : v;
-  }
-}
-
-__global__ void index_gather_kernel(const int* idx, int n, const cd* vec, cd* out) {
+// a[q*stride + i] += b[q*stride + i], i < n, q < nq (grid.y = q).
+__global__ void add_strided_kernel(cd* a, const cd* b, int n, long long stride) {
+  const long long o = (long long)blockIdx.y * stride;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-    out[i] = vec[idx[i]];
-}
-
-__global__ void index_scatter_kernel(const int* idx, int n, const cd* in, cd* vec) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-    vec[idx[i]] = in[i];
+    a[o + i] = cadd(a[o + i], b[o + i]);
 }
 
 __global__ void fill_kernel(cd* v, long long n, cd val) {
@@ -211,11 +163,14 @@ __device__ inline cd block_sum(cd v) {
   return r;
 }
 
-// Stage 1: partial[v][blk] = sum over chunk blk of conj(V_v) . w   (grid (blocks, nvec))
+// Stage 1: partial[q][v][blk] = sum over chunk blk of conj(V_v) . w on the
+// segment of problem q (grid (blocks, nvec, problems)).
 __global__ __launch_bounds__(256) void dot_stage1_kernel(const cd* V, long long vstride, const cd* w,
                                                          long long n, cd* partial, int nblk) {
-  const int v = blockIdx.y;
-  const cd* Vv = V + (long long)v * vstride;
+  const int v = blockIdx.y, q = blockIdx.z;
+  const cd* Vv = V + (long long)v * vstride + (long long)q * n;
+  w += (long long)q * n;
+  partial += (long long)q * gridDim.y * nblk;
   const long long chunk = (n + nblk - 1) / nblk;
   const long long a0 = (long long)blockIdx.x * chunk;
   const long long a1 = a0 + chunk < n ? a0 + chunk : n;
@@ -225,35 +180,44 @@ __global__ __launch_bounds__(256) void dot_stage1_kernel(const cd* V, long long 
   if (threadIdx.x == 0) partial[(long long)v * nblk + blockIdx.x] = acc;
 }
 
-// Stage 2: out[v] = sum_blk partial[v][blk]; optional: out_norm[v] = sqrt(Re out[v]).
+// Stage 2: out[q * ostride + v] (+)= sum_blk partial[q][v][blk]  (grid (nvec, problems)).
 __global__ __launch_bounds__(256) void dot_stage2_kernel(const cd* partial, int nblk, cd* out,
-                                                         int accumulate) {
-  const int v = blockIdx.x;
+                                                         int accumulate, long long ostride) {
+  const int v = blockIdx.x, q = blockIdx.y;
+  partial += (long long)q * gridDim.x * nblk;
+  out += (long long)q * ostride;
   cd acc = cmk(0.0, 0.0);
   for (int i = threadIdx.x; i < nblk; i += blockDim.x) acc = cadd(acc, partial[(long long)v * nblk + i]);
   acc = block_sum(acc);
   if (threadIdx.x == 0) out[v] = accumulate ? cadd(out[v], acc) : acc;
 }
 
-// w -= sum_v h[v] V_v   (h on the device)
-__global__ void multi_axpy_kernel(const cd* V, long long vstride, int nvec, const cd* h, cd* w,
-                                  long long n, int sign) {
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+// w += sign * sum_v h[q * hstride + v] V_v on the segment of each problem q
+// (h on the device; entries i of [0, nq * n), q = i / n).
+__global__ void multi_axpy_kernel(const cd* V, long long vstride, int nvec, const cd* h, long long hstride,
+                                  cd* w, long long n, long long ntot, int sign) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < ntot;
        i += (long long)gridDim.x * blockDim.x) {
+    const cd* hq = h + (i / n) * hstride;
     cd acc = w[i];
     for (int v = 0; v < nvec; ++v) {
-      const cd t = cmul(h[v], V[(long long)v * vstride + i]);
+      const cd t = cmul(hq[v], V[(long long)v * vstride + i]);
       acc = sign > 0 ? cadd(acc, t) : csub(acc, t);
     }
     w[i] = acc;
   }
 }
 
-// out = w / sqrt(Re nrm2[0]); also stores the norm into hout (complex, im = 0).
-__global__ void normalize_kernel(const cd* w, const cd* nrm2, cd* out, long long n, cd* hout) {
-  const double nr = sqrt(fmax(nrm2[0].x, 0.0));
+// out = w / sqrt(Re nrm2[q * nstride]) on the segment of problem q (grid.y);
+// also stores the norm into hout[q * hstride] (complex, im = 0).
+__global__ void normalize_kernel(const cd* w, const cd* nrm2, long long nstride, cd* out, long long n, cd* hout,
+                                 long long hstride) {
+  const int q = blockIdx.y;
+  const double nr = sqrt(fmax(nrm2[(long long)q * nstride].x, 0.0));
   const double s = nr > 0.0 ? 1.0 / nr : 0.0;
-  if (blockIdx.x == 0 && threadIdx.x == 0 && hout) *hout = cmk(nr, 0.0);
+  if (blockIdx.x == 0 && threadIdx.x == 0 && hout) hout[(long long)q * hstride] = cmk(nr, 0.0);
+  w += (long long)q * n;
+  out += (long long)q * n;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x)
     out[i] = cscale(w[i], s);
@@ -316,10 +280,14 @@ __device__ inline cd wg_sum(cd v, cd* red) {
 }
 
 // V_0 = w / |w| with w = vec[idx]; beta2 = |w|^2; H = 0.
-__global__ __launch_bounds__(kCT) void coarse_start_kernel(const int* idx, int n, const cd* vec, cd* V, cd* H,
-                                                           int hsize, cd* beta2) {
+__global__ __launch_bounds__(kCT) void coarse_start_kernel(const int* idx, int n, const cd* vec, cd* V,
+                                                           long long vq, cd* H, int hsize, cd* beta2) {
   __shared__ cd red[kCT / 64];
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, q = blockIdx.x;
+  idx += (long long)q * n;
+  V += (long long)q * vq;
+  H += (long long)q * hsize;
+  beta2 += q;
   cd acc = cmk(0.0, 0.0);
   for (int i = t; i < n; i += kCT) {
     const cd x = vec[idx[i]];
@@ -337,10 +305,15 @@ __global__ __launch_bounds__(kCT) void coarse_start_kernel(const int* idx, int n
 // Arnoldi step j: w = M v_j (given, or v_j minus the split-K partial sums of
 // the pair-form product), two passes of classical Gram-Schmidt against
 // V_0..V_j (dots in a fixed order), V_{j+1} = w / |w|, H column j.
-__global__ __launch_bounds__(kCT) void coarse_arnoldi_kernel(cd* V, int n, int j, CoarseW src, cd* w, cd* Hcol) {
+__global__ __launch_bounds__(kCT) void coarse_arnoldi_kernel(cd* V, int n, long long vq, int j, CoarseW src,
+                                                             cd* w, cd* Hcol, int hsize) {
   __shared__ cd h[kMaxCoarse + 1], h2[kMaxCoarse + 1];
   __shared__ cd red[kCT / 64];
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, qp = blockIdx.x;
+  V += (long long)qp * vq;
+  w += (long long)qp * n;
+  Hcol += (long long)qp * hsize;
+  if (src.w) src.w += (long long)qp * n;
   const cd* vj = V + (long long)j * n;
   for (int i = t; i < n; i += kCT) {
     cd x;
@@ -350,7 +323,7 @@ __global__ __launch_bounds__(kCT) void coarse_arnoldi_kernel(cd* V, int n, int j
       const long long po = second ? src.poff1 : src.poff0;
       const int ns = second ? src.ns1 : src.ns0;
       cd acc = cmk(0.0, 0.0);
-      for (int q = 0; q < ns; ++q) acc = cadd(acc, src.part[po + (long long)q * src.m + r]);
+      for (int q = 0; q < ns; ++q) acc = cadd(acc, src.part[po + ((long long)q * src.nb + qp) * src.m + r]);
       x = csub(vj[i], acc);
     } else {
       x = src.w[i];
@@ -398,10 +371,14 @@ __global__ __launch_bounds__(kCT) void coarse_arnoldi_kernel(cd* V, int n, int j
 constexpr int kFastV = 6;
 
 template <int EP, int NT>
-__global__ __launch_bounds__(NT) void coarse_arnoldi_fast_kernel(cd* V, int n, int j, CoarseW src, cd* Hcol) {
+__global__ __launch_bounds__(NT) void coarse_arnoldi_fast_kernel(cd* V, int n, long long vq, int j, CoarseW src,
+                                                                cd* Hcol, int hsize) {
   __shared__ cd red[NT / 64][kFastV];
   __shared__ cd hs[kFastV], hsum[kFastV];
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, qp = blockIdx.x;
+  V += (long long)qp * vq;
+  Hcol += (long long)qp * hsize;
+  if (src.w) src.w += (long long)qp * n;
   const cd zero = cmk(0.0, 0.0);
   cd vv[kFastV][EP];
   cd w[EP];
@@ -426,7 +403,8 @@ __global__ __launch_bounds__(NT) void coarse_arnoldi_fast_kernel(cd* V, int n, i
         for (int q0 = 0; q0 < ns; q0 += 8) {
           cd tmp[8];
 #pragma unroll
-          for (int u = 0; u < 8; ++u) tmp[u] = q0 + u < ns ? src.part[po + (long long)(q0 + u) * src.m + r] : zero;
+          for (int u = 0; u < 8; ++u)
+            tmp[u] = q0 + u < ns ? src.part[po + ((long long)(q0 + u) * src.nb + qp) * src.m + r] : zero;
 #pragma unroll
           for (int u = 0; u < 8; ++u)
             if (q0 + u < ns) acc = cadd(acc, tmp[u]);
@@ -493,9 +471,14 @@ __global__ __launch_bounds__(NT) void coarse_arnoldi_fast_kernel(cd* V, int n, i
 }
 
 // y = argmin |beta e1 - H y|, x = V y, vec[idx] = x.
-__global__ __launch_bounds__(kCT) void coarse_finish_kernel(const cd* H, int k, const cd* beta2, const cd* V, int n,
-                                                            const int* idx, cd* vec) {
+__global__ __launch_bounds__(kCT) void coarse_finish_kernel(const cd* H, int k, int hsize, const cd* beta2,
+                                                            const cd* V, int n, long long vq, const int* idx, cd* vec) {
   __shared__ cd y[kMaxCoarse];
+  const int q = blockIdx.x;
+  H += (long long)q * hsize;
+  beta2 += q;
+  V += (long long)q * vq;
+  idx += (long long)q * n;
   __shared__ cd R[kMaxCoarse + 1][kMaxCoarse];
   __shared__ cd gv[kMaxCoarse + 1];
   if (threadIdx.x == 0) lsq_small(H, k + 1, k, beta2, y, nullptr, R, gv);
@@ -515,12 +498,13 @@ inline int grid_for(long long n, int block = 256, int cap = 2048) {
 }  // namespace
 
 hipError_t skeleton_apply(const Geom& g, const cd* T, const cd* gin, cd* out, bool zero_physical,
-                          hipStream_t st) {
-  dim3 grid(g.nboxes, (g.b + kRows - 1) / kRows);
+                          hipStream_t st, int nq) {
+  dim3 grid(g.nboxes * nq, (g.b + kRows - 1) / kRows);
+  const long long nslots = (long long)g.n * g.n * 4 * g.p;
   hipError_t e0 = allow_lds(skeleton_apply_kernel, (size_t)g.b * sizeof(cd));
   if (e0 != hipSuccess) return e0;
   hipLaunchKernelGGL(skeleton_apply_kernel, grid, dim3(kRows), (size_t)g.b * sizeof(cd), st, g, T, gin,
-                     out, zero_physical ? 1 : 0);
+                     out, zero_physical ? 1 : 0, nslots);
   return hipPeekAtLastError();
 }
 
@@ -529,40 +513,27 @@ hipError_t rhs_build(const Geom& g, const cd* T, const cd* H, const cd* t, cd* r
   return hipPeekAtLastError();
 }
 
-hipError_t zgemv(const GemvArgs& a, hipStream_t st) {
-  if (a.M <= 0 || a.batch <= 0) return hipSuccess;
-  dim3 grid((a.M + kRows - 1) / kRows, a.batch);
-  hipError_t e0 = allow_lds(zgemv_kernel, (size_t)std::max(a.K, 1) * sizeof(cd));
-  if (e0 != hipSuccess) return e0;
-  hipLaunchKernelGGL(zgemv_kernel, grid, dim3(kRows), (size_t)std::max(a.K, 1) * sizeof(cd), st, a);
+
+
+
+hipError_t index_gather(const int* idx, int n, const cd* vec, cd* out, hipStream_t st, int nq,
+                        long long ostride) {
+  const long long ntot = (long long)n * nq;
+  hipLaunchKernelGGL(index_gather_kernel, dim3(grid_for(ntot)), dim3(256), 0, st, idx, n, ntot, vec, out,
+                     ostride ? ostride : n);
   return hipPeekAtLastError();
 }
 
-hipError_t pair_gather(const Geom& g, int pairs, int which, IdxMap local, int len, const cd* vec,
-                       cd* out, long long ostride, bool partner, hipStream_t st) {
-  if (len <= 0 || pairs <= 0) return hipSuccess;
-  dim3 grid((len + 255) / 256, pairs);
-  hipLaunchKernelGGL(pair_gather_kernel, grid, dim3(256), 0, st, g, which, local, len, vec, out, ostride,
-                     partner ? 1 : 0);
+hipError_t index_scatter(const int* idx, int n, const cd* in, cd* vec, hipStream_t st, int nq,
+                         long long istride) {
+  const long long ntot = (long long)n * nq;
+  hipLaunchKernelGGL(index_scatter_kernel, dim3(grid_for(ntot)), dim3(256), 0, st, idx, n, ntot, in,
+                     istride ? istride : n, vec);
   return hipPeekAtLastError();
 }
 
-hipError_t pair_scatter(const Geom& g, int pairs, int which, IdxMap local, int len, const cd* in,
-                        long long istride, cd* vec, bool partner, bool add, hipStream_t st) {
-  if (len <= 0 || pairs <= 0) return hipSuccess;
-  dim3 grid((len + 255) / 256, pairs);
-  hipLaunchKernelGGL(pair_scatter_kernel, grid, dim3(256), 0, st, g, which, local, len, in, istride, vec,
-                     partner ? 1 : 0, add ? 1 : 0);
-  return hipPeekAtLastError();
-}
-
-hipError_t index_gather(const int* idx, int n, const cd* vec, cd* out, hipStream_t st) {
-  hipLaunchKernelGGL(index_gather_kernel, dim3(grid_for(n)), dim3(256), 0, st, idx, n, vec, out);
-  return hipPeekAtLastError();
-}
-
-hipError_t index_scatter(const int* idx, int n, const cd* in, cd* vec, hipStream_t st) {
-  hipLaunchKernelGGL(index_scatter_kernel, dim3(grid_for(n)), dim3(256), 0, st, idx, n, in, vec);
+hipError_t add_strided(cd* a, const cd* b, int n, int nq, long long stride, hipStream_t st) {
+  hipLaunchKernelGGL(add_strided_kernel, dim3(grid_for(n), nq), dim3(256), 0, st, a, b, n, stride);
   return hipPeekAtLastError();
 }
 
@@ -587,53 +558,62 @@ int dot_blocks(long long n) {
 }
 
 hipError_t multi_dot(const cd* V, long long vstride, int nvec, const cd* w, long long n, cd* partial,
-                     cd* out, bool accumulate, hipStream_t st) {
+                     cd* out, bool accumulate, hipStream_t st, int nq, long long ostride) {
+  if (nvec <= 0) return hipSuccess;
   const int nblk = dot_blocks(n);
-  hipLaunchKernelGGL(dot_stage1_kernel, dim3(nblk, nvec), dim3(256), 0, st, V, vstride, w, n, partial,
+  hipLaunchKernelGGL(dot_stage1_kernel, dim3(nblk, nvec, nq), dim3(256), 0, st, V, vstride, w, n, partial,
                      nblk);
   hipError_t err = hipPeekAtLastError();
   if (err != hipSuccess) return err;
-  hipLaunchKernelGGL(dot_stage2_kernel, dim3(nvec), dim3(256), 0, st, partial, nblk, out,
-                     accumulate ? 1 : 0);
+  hipLaunchKernelGGL(dot_stage2_kernel, dim3(nvec, nq), dim3(256), 0, st, partial, nblk, out,
+                     accumulate ? 1 : 0, ostride);
   return hipPeekAtLastError();
 }
 
 hipError_t multi_axpy(const cd* V, long long vstride, int nvec, const cd* h, cd* w, long long n, int sign,
-                      hipStream_t st) {
-  hipLaunchKernelGGL(multi_axpy_kernel, dim3(grid_for(n)), dim3(256), 0, st, V, vstride, nvec, h, w, n,
-                     sign);
+                      hipStream_t st, int nq, long long hstride) {
+  if (nvec <= 0) return hipSuccess;
+  const long long ntot = n * nq;
+  hipLaunchKernelGGL(multi_axpy_kernel, dim3(grid_for(ntot)), dim3(256), 0, st, V, vstride, nvec, h, hstride,
+                     w, n, ntot, sign);
   return hipPeekAtLastError();
 }
 
-hipError_t normalize(const cd* w, const cd* nrm2, cd* out, long long n, cd* hout, hipStream_t st) {
-  hipLaunchKernelGGL(normalize_kernel, dim3(grid_for(n)), dim3(256), 0, st, w, nrm2, out, n, hout);
+hipError_t normalize(const cd* w, const cd* nrm2, cd* out, long long n, cd* hout, hipStream_t st, int nq,
+                     long long nstride, long long hstride) {
+  hipLaunchKernelGGL(normalize_kernel, dim3(grid_for(n), nq), dim3(256), 0, st, w, nrm2, nstride, out, n, hout,
+                     hstride);
   return hipPeekAtLastError();
 }
 
 
-hipError_t coarse_start(const int* idx, int n, const cd* vec, cd* V, cd* H, int hsize, cd* beta2,
-                        hipStream_t st) {
-  hipLaunchKernelGGL(coarse_start_kernel, dim3(1), dim3(kCT), 0, st, idx, n, vec, V, H, hsize, beta2);
+hipError_t coarse_start(const int* idx, int n, const cd* vec, cd* V, long long vq, cd* H, int hsize, cd* beta2,
+                        int nq, hipStream_t st) {
+  hipLaunchKernelGGL(coarse_start_kernel, dim3(nq), dim3(kCT), 0, st, idx, n, vec, V, vq, H, hsize, beta2);
   return hipPeekAtLastError();
 }
 
-hipError_t coarse_arnoldi(cd* V, int n, int j, const CoarseW& src, cd* wtmp, cd* Hcol, hipStream_t st) {
+hipError_t coarse_arnoldi(cd* V, int n, long long vq, int j, const CoarseW& src, cd* wtmp, cd* Hcol, int hsize,
+                          int nq, hipStream_t st) {
   if (j < 0 || j + 1 > kMaxCoarse) return hipErrorInvalidValue;
   if (j < kFastV && n <= 4 * 256)
-    hipLaunchKernelGGL((coarse_arnoldi_fast_kernel<4, 256>), dim3(1), dim3(256), 0, st, V, n, j, src, Hcol);
+    hipLaunchKernelGGL((coarse_arnoldi_fast_kernel<4, 256>), dim3(nq), dim3(256), 0, st, V, n, vq, j, src, Hcol,
+                       hsize);
   else if (j < kFastV && n <= 8 * 256)
-    hipLaunchKernelGGL((coarse_arnoldi_fast_kernel<8, 256>), dim3(1), dim3(256), 0, st, V, n, j, src, Hcol);
+    hipLaunchKernelGGL((coarse_arnoldi_fast_kernel<8, 256>), dim3(nq), dim3(256), 0, st, V, n, vq, j, src, Hcol,
+                       hsize);
   else if (j < kFastV && n <= 16 * 256)
-    hipLaunchKernelGGL((coarse_arnoldi_fast_kernel<16, 256>), dim3(1), dim3(256), 0, st, V, n, j, src, Hcol);
+    hipLaunchKernelGGL((coarse_arnoldi_fast_kernel<16, 256>), dim3(nq), dim3(256), 0, st, V, n, vq, j, src, Hcol,
+                       hsize);
   else
-    hipLaunchKernelGGL(coarse_arnoldi_kernel, dim3(1), dim3(kCT), 0, st, V, n, j, src, wtmp, Hcol);
+    hipLaunchKernelGGL(coarse_arnoldi_kernel, dim3(nq), dim3(kCT), 0, st, V, n, vq, j, src, wtmp, Hcol, hsize);
   return hipPeekAtLastError();
 }
 
-hipError_t coarse_finish(const cd* H, int k, const cd* beta2, const cd* V, int n, const int* idx, cd* vec,
-                         hipStream_t st) {
+hipError_t coarse_finish(const cd* H, int k, int hsize, const cd* beta2, const cd* V, int n, long long vq,
+                         const int* idx, cd* vec, int nq, hipStream_t st) {
   if (k < 1 || k > kMaxCoarse) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(coarse_finish_kernel, dim3(1), dim3(kCT), 0, st, H, k, beta2, V, n, idx, vec);
+  hipLaunchKernelGGL(coarse_finish_kernel, dim3(nq), dim3(kCT), 0, st, H, k, hsize, beta2, V, n, vq, idx, vec);
   return hipPeekAtLastError();
 }
 

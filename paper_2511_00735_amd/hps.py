@@ -70,6 +70,12 @@ _SIGS = {
                            ctypes.c_int),
     "hps_problem_destroy": ([_P], ctypes.c_int),
     "hps_level_view_get": ([_P, ctypes.c_int32, ctypes.POINTER(LevelView)], ctypes.c_int),
+    "hps_member_level_view": ([_P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(LevelView)], ctypes.c_int),
+    "hps_group_workspace_bytes": ([ctypes.POINTER(Desc), ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)],
+                                  ctypes.c_int),
+    "hps_group_create": ([_P, ctypes.POINTER(Desc), ctypes.c_int32, _P, _P, _P, ctypes.c_size_t,
+                          ctypes.POINTER(_P)], ctypes.c_int),
+    "hps_group_size": ([_P], ctypes.c_int32),
     "hps_build_leaves": ([_PP, ctypes.c_int32, _PP, _PP], ctypes.c_int),
     "hps_merge_level": ([_PP, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
     "hps_set_rhs": ([_PP, ctypes.c_int32, _PP, _PP], ctypes.c_int),
@@ -213,6 +219,7 @@ class Problem:
                                          ctypes.c_size_t(workspace.numel() - self.ws_offset),
                                          ctypes.byref(h)), "hps_problem_create")
         self.handle = h
+        self.count = 1
         self.levels = desc.levels or 2 * int(round(np.log2(self.n)))
         self.lmax = 2 * int(round(np.log2(self.n)))
 
@@ -309,12 +316,104 @@ class Problem:
         return self._view(v.X, v.pairs * m2 * e2, bool(v.fp32)).view(v.pairs, e2, m2).transpose(1, 2)
 
 
+def group_workspace_bytes(desc, count):
+    b = ctypes.c_size_t()
+    rc = lib.hps_group_workspace_bytes(ctypes.byref(desc), count, ctypes.byref(b))
+    if rc != HPS_OK:
+        raise HPSError(rc, "hps_group_workspace_bytes")
+    return b.value
+
+
+class Group:
+    """`count` problems of one shape (kappa and eta per problem) batched in
+    every hot-path launch; per-problem inputs and outputs are lists."""
+
+    def __init__(self, ctx, desc, kappas, etas=None, workspace=None):
+        kappas = [float(k) for k in kappas]
+        etas = list(kappas) if etas is None else [float(e) for e in etas]
+        self.ctx = ctx
+        self.desc = desc
+        self.count = len(kappas)
+        self.n, self.N = desc.n, desc.order
+        self.p = self.N - 1
+        self.E = self.n * self.n
+        self.nslots = self.E * 4 * self.p
+        self.levels = desc.levels or 2 * int(round(np.log2(self.n)))
+        self.lmax = 2 * int(round(np.log2(self.n)))
+        self.bytes = group_workspace_bytes(desc, self.count)
+        if workspace is None:
+            workspace = torch.empty(self.bytes + 256, dtype=torch.uint8, device="cuda")
+        self._ws_tensor = workspace
+        base = workspace.data_ptr()
+        off = (-base) % 256
+        ka = (ctypes.c_double * self.count)(*kappas)
+        ea = (ctypes.c_double * self.count)(*etas)
+        h = ctypes.c_void_p()
+        ctx.check(lib.hps_group_create(ctx.handle, ctypes.byref(desc), self.count, ka, ea,
+                                       ctypes.c_void_p(base + off), ctypes.c_size_t(workspace.numel() - off),
+                                       ctypes.byref(h)), "hps_group_create")
+        self.handle = h
+
+    def __del__(self):
+        if getattr(self, "handle", None) and lib is not None:
+            lib.hps_problem_destroy(self.handle)
+            self.handle = None
+
+    def build_leaves(self, b_nodes, s_nodes=None):
+        build_leaves([self], b_nodes, s_nodes)
+
+    def merge_all(self):
+        top = self.levels if self.desc.coarse_iters == -1 else self.levels - 1
+        for level in range(1, top + 1):
+            merge_level([self], level)
+
+    def set_rhs(self, ts):
+        rhs = [torch.empty(self.nslots, dtype=torch.complex128, device="cuda") for _ in ts]
+        set_rhs([self], ts, rhs)
+        return rhs
+
+    def precond_apply(self, rs):
+        zs = [torch.empty(self.nslots, dtype=torch.complex128, device="cuda") for _ in rs]
+        precond_apply([self], rs, zs)
+        return zs
+
+    def gmres_solve(self, rhs, tol=1e-10, maxit=600, out=None):
+        out = out if out is not None else [torch.empty(self.nslots, dtype=torch.complex128, device="cuda")
+                                           for _ in rhs]
+        infos = gmres_solve([self], rhs, out, tol, maxit)
+        return out, infos
+
+    def member_view(self, member, level):
+        v = LevelView()
+        self.ctx.check(lib.hps_member_level_view(self.handle, member, level, ctypes.byref(v)), "member view")
+        return v
+
+    def level_T(self, member, level):
+        v = self.member_view(member, level)
+        b = v.box_nodes
+        off = v.T - self._ws_tensor.data_ptr()
+        size = 8 if v.fp32 else 16
+        raw = self._ws_tensor[off:off + size * v.boxes * b * b]
+        t = raw.view(torch.complex64 if v.fp32 else torch.complex128).view(v.boxes, b, b)
+        return t.transpose(1, 2)
+
+
 # ---- batch-first entry points (several problems per call) ------------------
 def _handles(problems):
     return _ptrs([p.handle.value for p in problems])
 
 
+def _nprob(problems, *arrays):
+    """Problems behind the handles; every per-problem array must list them all."""
+    total = sum(p.count for p in problems)
+    for a in arrays:
+        if a is not None and len(a) != total:
+            raise ValueError(f"per-problem array has {len(a)} entries for {total} problems")
+    return total
+
+
 def build_leaves(problems, b_nodes, s_nodes=None):
+    _nprob(problems, b_nodes, s_nodes)
     ctx = problems[0].ctx
     s = _ptrs([_dptr(x) for x in s_nodes]) if s_nodes is not None else None
     ctx.check(lib.hps_build_leaves(_handles(problems), len(problems),
@@ -327,19 +426,21 @@ def merge_level(problems, level):
 
 
 def set_rhs(problems, t, rhs):
+    _nprob(problems, t, rhs)
     problems[0].ctx.check(lib.hps_set_rhs(_handles(problems), len(problems),
                                           _ptrs([_dptr(x) for x in t]),
                                           _ptrs([_dptr(x) for x in rhs])), "hps_set_rhs")
 
 
 def precond_apply(problems, r, z):
+    _nprob(problems, r, z)
     problems[0].ctx.check(lib.hps_precond_apply(_handles(problems), len(problems),
                                                 _ptrs([_dptr(x) for x in r]),
                                                 _ptrs([_dptr(x) for x in z])), "hps_precond_apply")
 
 
 def gmres_solve(problems, rhs, g, tol=1e-10, maxit=600):
-    infos = (Info * len(problems))()
+    infos = (Info * _nprob(problems, rhs, g))()
     problems[0].ctx.check(lib.hps_gmres_solve(_handles(problems), len(problems),
                                               _ptrs([_dptr(x) for x in rhs]),
                                               _ptrs([_dptr(x) for x in g]), tol, maxit, infos),

@@ -13,20 +13,6 @@ from paper_2511_00735_amd import workloads
 pytestmark = pytest.mark.gpu
 
 
-@pytest.fixture(scope="module")
-def hps():
-    import torch
-    if not torch.cuda.is_available():
-        pytest.skip("no GPU")
-    from paper_2511_00735_amd import hps as _hps
-    return _hps
-
-
-@pytest.fixture(scope="module")
-def ctx(hps):
-    return hps.Context()
-
-
 def _bump(x, y):
     return 0.6 * np.exp(-((x - 0.4) ** 2 + (y - 0.6) ** 2) / 0.05) - 0.3 * np.sin(3 * x * y)
 

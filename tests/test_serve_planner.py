@@ -1,0 +1,72 @@
+"""Host-side batching and admission of the serving loop (no GPU)."""
+from dataclasses import dataclass
+
+import pytest
+
+from paper_2511_00735_amd.serve import Planner, Record, summarize
+
+
+@dataclass
+class Req:
+    name: str
+    n: int
+    N: int
+    arrival: float = 0.0
+
+
+def fp(shape, count):
+    n, N = shape
+    return count * n * n * N      # bytes proportional to elements x order
+
+
+def test_batches_one_shape_in_arrival_order():
+    pl = Planner(fp, budget=10 ** 9, max_batch=3)
+    reqs = [Req("a", 8, 8), Req("b", 16, 8), Req("c", 8, 8), Req("d", 8, 8), Req("e", 8, 8)]
+    for r in reqs:
+        pl.add(r)
+    batch, need = pl.take()
+    assert [r.name for r in batch] == ["a", "c", "d"]       # oldest fixes the shape; max_batch 3
+    assert need == fp((8, 8), 3)
+    batch, _ = pl.take()
+    assert [r.name for r in batch] == ["b"]
+    batch, _ = pl.take()
+    assert [r.name for r in batch] == ["e"]
+    assert pl.take() is None
+
+
+def test_admission_by_footprint_shrinks_then_waits():
+    one = fp((8, 8), 1)
+    pl = Planner(fp, budget=2 * one, max_batch=8)
+    for i in range(5):
+        pl.add(Req(f"r{i}", 8, 8))
+    batch, need = pl.take()
+    assert len(batch) == 2 and need == 2 * one            # shrunk to what fits
+    assert pl.take() is None                               # nothing left: waits
+    pl.release(need)
+    batch2, need2 = pl.take()
+    assert [r.name for r in batch2] == ["r2", "r3"]
+    pl.release(need2)
+    batch3, _ = pl.take()
+    assert [r.name for r in batch3] == ["r4"]
+
+
+def test_request_larger_than_budget_is_an_error():
+    pl = Planner(fp, budget=fp((8, 8), 1) - 1)
+    pl.add(Req("big", 8, 8))
+    with pytest.raises(ValueError):
+        pl.take()
+
+
+def test_summary_percentiles():
+    recs = []
+    for i in range(100):
+        r = Record(f"q{i}", 8, 8, arrival=0.01 * i, dof=10)
+        r.finish = r.arrival + 0.001 * (i + 1)
+        r.status = 0
+        r.relres = 1e-9
+        r.batch = 1
+        recs.append(r)
+    s = summarize(recs)
+    assert s["completed"] == 100 and s["converged"] == 100
+    assert abs(s["latency_p50_ms"] - 50.5) < 1e-6
+    assert abs(s["latency_p99_ms"] - 99.01) < 1e-6
