@@ -1,72 +1,79 @@
 // In-LDS Gauss-Jordan inversion with partial pivoting for one small complex
-// matrix per workgroup (m <= 64: one wave searches the pivot column, lane = row).
+// matrix per workgroup (m <= 64).
 #pragma once
 #include "common.h"
+#include "pivot.h"
 
-// S: m x m column-major in LDS (ld = m), inverted in place.
-// ipiv: LDS int[m]; colk: LDS cd[m]; must be called by all threads of the block
-// (blockDim.x >= 64).  Sets bit 2 of *flag on an exactly zero pivot.
+// S: m x m column-major in LDS (ld = m), inverted in place.  ipiv: LDS int[m];
+// colk: LDS T[m].  Called by every thread of the block; blockDim.x is a
+// multiple of 64 and at most 1024.  Sets bit 2 of *flag on a zero pivot.
+//
+// Each step k takes two barriers: (1) the row interchange k <-> pr on every
+// column but k, staging the pivot row and column k; (2) the elimination,
+// thread (row i = tid % 64, columns j = tid / 64 + G*t), which also forms the
+// next column's pivot candidates and reduces them per wavefront (DPP arg-max).
 template <class T>
 __device__ inline void gj_inplace_small(T* S, int m, int* ipiv, T* colk, int* flag) {
-  typedef typename cx<T>::real R;
-  const int tid = threadIdx.x;
-  const int nt = blockDim.x;
+  __shared__ T rowk[64];
+  __shared__ unsigned long long kw[16];
+  const int tid = threadIdx.x, nt = blockDim.x, nw = nt >> 6;
+  const int i = tid & 63, g = tid >> 6, G = nw;
+  const T zero = cx<T>::make(0.0, 0.0);
+  unsigned long long best = (g == 0 && i < m) ? hps::pivot_key(cabs2(S[i]), i) : 0ull;
+  best = hps::wave_max_key(best);
+  if ((tid & 63) == 0) kw[g] = best;
+  __syncthreads();
   for (int k = 0; k < m; ++k) {
-    if (tid < 64) {
-      R best = -1;
-      int bi = k;
-      for (int r = k + tid; r < m; r += 64) {
-        const R v = cabs2(S[k * m + r]);
-        if (v > best) { best = v; bi = r; }
-      }
-      for (int off = 32; off > 0; off >>= 1) {
-        const R ov = __shfl_xor(best, off);
-        const int oi = __shfl_xor(bi, off);
-        if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
-      }
-      if (tid == 0) {
-        ipiv[k] = bi;
-        if (!(best > 0)) atomicOr(flag, 2);
-      }
-    }
-    __syncthreads();
-    const int pr = ipiv[k];
-    if (pr != k) {
-      for (int j = tid; j < m; j += nt) {
-        const T t = S[j * m + k];
-        S[j * m + k] = S[j * m + pr];
-        S[j * m + pr] = t;
-      }
-      __syncthreads();
-    }
-    const T d = S[k * m + k];
-    const T inv = (cabs2(d) > 0) ? cinv(d) : cx<T>::make(0.0, 0.0);
-    __syncthreads();
+    unsigned long long kk = 0;
+    for (int w = 0; w < nw; ++w) kk = max(kk, kw[w]);
+    int pr = hps::pivot_row(kk);
+    const bool bad = (kk >> 32) <= 1u || pr < k || pr >= m;
+    if (bad) pr = k;
+    const T d = S[k * m + pr];
     for (int j = tid; j < m; j += nt) {
-      // row k scaled by 1/d (its diagonal becomes 1/d); column k saved
-      const T v = (j == k) ? cx<T>::make(1.0, 0.0) : S[j * m + k];
-      S[j * m + k] = cmul(v, inv);
-      colk[j] = (j == k) ? cx<T>::make(0.0, 0.0) : S[k * m + j];
+      if (j == k) continue;
+      const T u = S[j * m + pr];
+      if (pr != k) S[j * m + pr] = S[j * m + k];
+      rowk[j] = u;
+    }
+    for (int r = tid; r < m; r += nt) {
+      const int src = (r == pr) ? k : r;
+      colk[r] = (r == k) ? zero : S[k * m + src];
+    }
+    if (tid == 0) {
+      ipiv[k] = pr;
+      if (bad) atomicOr(flag, 2);
     }
     __syncthreads();
-    for (int idx = tid; idx < m * m; idx += nt) {
-      const int i = idx % m, j = idx / m;
-      if (i == k) continue;
-      const T base = (j == k) ? cx<T>::make(0.0, 0.0) : S[j * m + i];
-      const T f = colk[i];
-      const T rk = S[j * m + k];
-      S[j * m + i] = csub(base, cmul(f, rk));
+    const T inv = (cabs2(d) > 0) ? cinv(d) : zero;
+    best = 0;
+    if (i < m) {
+      const T ci = colk[i];
+      for (int j = g; j < m; j += G) {
+        T v;
+        if (i == k) {
+          v = (j == k) ? inv : cmul(rowk[j], inv);
+        } else if (j == k) {
+          v = csub(zero, cmul(ci, inv));
+        } else {
+          v = csub(S[j * m + i], cmul(ci, cmul(rowk[j], inv)));
+        }
+        S[j * m + i] = v;
+        if (j == k + 1 && i > k) best = max(best, hps::pivot_key(cabs2(v), i));
+      }
     }
+    best = hps::wave_max_key(best);
+    if ((tid & 63) == 0) kw[g] = best;
     __syncthreads();
   }
   // undo the row interchanges as column interchanges, last one first
-  for (int i = tid; i < m; i += nt) {
+  for (int r = tid; r < m; r += nt) {
     for (int k = m - 1; k >= 0; --k) {
       const int pr = ipiv[k];
       if (pr != k) {
-        const T t = S[k * m + i];
-        S[k * m + i] = S[pr * m + i];
-        S[pr * m + i] = t;
+        const T t = S[k * m + r];
+        S[k * m + r] = S[pr * m + r];
+        S[pr * m + r] = t;
       }
     }
   }

@@ -17,6 +17,7 @@
 #include "common.h"
 #include "gj_small.h"
 #include "host.h"
+#include "pivot.h"
 
 namespace hps {
 
@@ -77,32 +78,6 @@ __device__ inline T crecip(T a) {
   return cx<T>::make(a.x * s, -a.y * s);
 }
 
-// Pivot key: 1 + the FP32 bits of |v|^2 (monotonic for non-negative values;
-// 0 means "no candidate") in the high word, the complemented row in the low.
-template <class R>
-__device__ inline unsigned long long pivot_key(R v2, int r) {
-  const unsigned hi = __float_as_uint((float)v2) + 1u;
-  return ((unsigned long long)hi << 32) | (unsigned int)(0xFFFFFFFFu - (unsigned int)r);
-}
-
-// Largest key of the wave (every lane must call): maximum of the high words by
-// DPP row shifts within each 16-lane row and read-lanes across rows; among the
-// lanes holding that maximum, the lowest lane's key.
-__device__ inline unsigned long long wave_max_key(unsigned long long key) {
-  const unsigned hi = (unsigned)(key >> 32);
-  unsigned h = hi;
-  h = max(h, (unsigned)__builtin_amdgcn_update_dpp((int)h, (int)h, 0x111, 0xF, 0xF, false));
-  h = max(h, (unsigned)__builtin_amdgcn_update_dpp((int)h, (int)h, 0x112, 0xF, 0xF, false));
-  h = max(h, (unsigned)__builtin_amdgcn_update_dpp((int)h, (int)h, 0x114, 0xF, 0xF, false));
-  h = max(h, (unsigned)__builtin_amdgcn_update_dpp((int)h, (int)h, 0x118, 0xF, 0xF, false));
-  const unsigned m = max(max((unsigned)__builtin_amdgcn_readlane((int)h, 15), (unsigned)__builtin_amdgcn_readlane((int)h, 31)),
-                         max((unsigned)__builtin_amdgcn_readlane((int)h, 47), (unsigned)__builtin_amdgcn_readlane((int)h, 63)));
-  const unsigned long long bal = __ballot(hi == m);
-  const int l = __ffsll((long long)bal) - 1;
-  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)key, l);
-  return ((unsigned long long)m << 32) | lo;
-}
-
 // Step 1 of a block column: the panel A[k0:m, k0:k0+kb] of matrix blockIdx.x.
 // A partial-pivoting LU of the panel (rank-1 updates spread over (row, column
 // group) threads; the next pivot found during the update by a per-wave DPP
@@ -158,7 +133,7 @@ __global__ __launch_bounds__(kPanelThreads) void gj_panel_kernel(const T* A, int
   for (int c = 0; c < kb; ++c) {
     unsigned long long kk = 0;
     for (int w = 0; w < nw; ++w) kk = max(kk, kw[w]);
-    int pr = (int)(0xFFFFFFFFu - (unsigned int)(kk & 0xFFFFFFFFull));
+    int pr = pivot_row(kk);
     const bool bad = (kk >> 32) <= 1u || pr < c || pr >= rows;
     if (bad) pr = c;
     if (tid == 0 && bad) atomicOr(flag, 2);
