@@ -4,18 +4,18 @@
 #include "common.h"
 #include "pivot.h"
 
-// S: m x m column-major in LDS (ld = m), inverted in place.  ipiv: LDS int[m];
-// colk: LDS T[m].  Called by every thread of the block; blockDim.x is a
-// multiple of 64 and at most 1024.  Sets bit 2 of *flag on a zero pivot.
+// S: m x m column-major in LDS (ld = m), inverted in place.  LDS workspace:
+// ipiv int[64], colk and rowk T[64], kw u64[16].  Called by every thread of the
+// block; blockDim.x is a multiple of 64 and at most 1024.  Sets bit 2 of *flag
+// on a zero pivot.
 //
 // Each step k takes two barriers: (1) the row interchange k <-> pr on every
 // column but k, staging the pivot row and column k; (2) the elimination,
 // thread (row i = tid % 64, columns j = tid / 64 + G*t), which also forms the
 // next column's pivot candidates and reduces them per wavefront (DPP arg-max).
 template <class T>
-__device__ inline void gj_inplace_small(T* S, int m, int* ipiv, T* colk, int* flag) {
-  __shared__ T rowk[64];
-  __shared__ unsigned long long kw[16];
+__device__ inline void gj_inplace_small(T* S, int m, int* ipiv, T* colk, T* rowk, unsigned long long* kw,
+                                        int* flag) {
   const int tid = threadIdx.x, nt = blockDim.x, nw = nt >> 6;
   const int i = tid & 63, g = tid >> 6, G = nw;
   const T zero = cx<T>::make(0.0, 0.0);

@@ -30,7 +30,7 @@ struct LeafArgs {
   const double* D;            // (N+1)^2 row-major reference D
   const double* w;            // N+1
   const double* Kr;           // (N+1)^2 reference stiffness
-  double* scratch;            // count * nloc * ncol doubles
+  double* scratch;            // leaf_scratch_doubles(N, count) doubles, 16-byte aligned
   cd* T;                      // level-1 box maps, [q][E][4p][4p], Morton order within a problem
   cd* H;                      // [q][E][4p] canonical element order
   int* flag;                  // device error flag (bit 1: singular pivot)

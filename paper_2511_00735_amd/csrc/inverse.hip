@@ -32,7 +32,8 @@ __global__ __launch_bounds__(256) void inv_small_kernel(T* A, int m, int lda, lo
   extern __shared__ char smem[];
   T* S = reinterpret_cast<T*>(smem);
   __shared__ int ipiv[64];
-  __shared__ T colk[64];
+  __shared__ T colk[64], rowk[64];
+  __shared__ unsigned long long kw[16];
   T* Ab = A + (long long)blockIdx.x * bstride;
   for (int base = 0; base < m * m; base += 4 * 256) {
     T v[4];
@@ -48,7 +49,7 @@ __global__ __launch_bounds__(256) void inv_small_kernel(T* A, int m, int lda, lo
     }
   }
   __syncthreads();
-  gj_inplace_small(S, m, ipiv, colk, flag);
+  gj_inplace_small(S, m, ipiv, colk, rowk, kw, flag);
   for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
     const int r = idx % m, c = idx / m;
     Ab[(long long)c * lda + r] = S[idx];

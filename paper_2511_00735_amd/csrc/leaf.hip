@@ -14,278 +14,532 @@
 // [R | -q] in its trailing rows.  Only the 4p x 4p complex Cayley step remains.
 // This is the same T as the paper's complex n_loc x n_loc solve, computed with
 // about 1/7 of its flops and in real arithmetic.
+//
+// The reduction is a right-looking blocked LU with panels of kNB columns:
+//  * the panel (all remaining rows x kNB columns) sits in registers, each wave
+//    holding every fourth column; pivot rows are left where they are during
+//    the panel and only marked as used, so a column step needs one barrier:
+//    the wave holding the next column publishes it in LDS with its pivot key
+//    (64-bit modulus/row keys, DPP arg-max across the wavefront), and every
+//    wave reads the pivot row of its own columns by lane broadcasts;
+//  * multipliers stay unscaled in the panel, with 1/pivot kept per column;
+//    once the panel is done they are scaled into the panel's own (finished)
+//    columns of the element matrix, and the LDS is handed to U12 and L11;
+//  * the row interchanges are applied once per panel: the pivot rows of the
+//    trailing columns are gathered into U12, and the non-pivot rows among the
+//    first kNB move into the slots the pivot rows vacate;
+//  * U12 = L11^-1 A12 by per-column forward substitution in LDS, then the
+//    trailing update A22 -= L21 U12 with one row and four adjacent columns per
+//    thread (U12 read as 128-bit broadcasts, L21 rows from the element matrix).
+// With 32-column panels the LDS holds about 75 KB (two workgroups per CU) and
+// the trailing matrix is read and written once per 32 pivots.
 #include <algorithm>
 
 #include "common.h"
-#include "gj_small.h"
 #include "host.h"
+#include "pivot.h"
 
 namespace hps {
 
 namespace {
 
-constexpr int kNB = 16;       // panel width of the blocked LU
+constexpr int kNB = 32;          // panel width of the blocked LU
 constexpr int kThreads = 256;
-constexpr int kStripes = 8;   // column stripes of the trailing update
+constexpr int kWaves = kThreads / 64;
+constexpr int kCPW = kNB / kWaves;  // panel columns per wave
+constexpr int kMaxChunks = 5;    // 64-row chunks of a panel: n_loc <= 320 (N <= 16)
 
 struct Dims {
-  int N, p, pp, nloc, ncol;
+  int N, p, pp, nloc, ncol, ldu;
 };
 
-__device__ inline Dims dims_of(int N) {
+__host__ __device__ inline Dims dims_of(int N) {
   Dims d;
   d.N = N;
   d.p = N - 1;
   d.pp = d.p * d.p;
   d.nloc = d.pp + 4 * d.p;
   d.ncol = d.nloc + 2;
+  // row stride of U12 in LDS (at most ncol - min(kNB, pp) trailing columns):
+  // even (16-byte rows for 128-bit reads) and 2 mod 4, so that the rows of one
+  // column fall in different banks
+  d.ldu = ((d.ncol - (d.pp < kNB ? d.pp : kNB) + 3) & ~3) + 2;
   return d;
 }
 
-// Entry (r, c) of the bordered real matrix K of one element.
-// rows/cols: interior (i,j) -> (i-1)*p + (j-1); boundary l_k, r_k, b_k, t_k ->
-// pp + side*p + (k-1); extra columns nloc, nloc+1 = Re/Im of bt.
-__device__ inline double k_entry(const Dims& d, int r, int c, const double* D, const double* w,
-                                 const double* Kr, const double* bnode, const double* snode,
-                                 double kappa, double h) {
-  const int N = d.N, p = d.p, pp = d.pp, N1 = N + 1;
-  const double f = 2.0 / h;
-  if (r < pp) {
-    const int i = r / p + 1, j = r % p + 1;
-    if (c >= d.nloc) {
-      if (!snode) return 0.0;
-      const double s = snode[2 * (i * N1 + j) + (c - d.nloc)];
-      return 0.25 * h * h * w[i] * w[j] * s;
-    }
-    if (c < pp) {
-      const int i2 = c / p + 1, j2 = c % p + 1;
-      double v = 0.0;
-      if (j == j2) v += Kr[i * N1 + i2] * w[j];
-      if (i == i2) v += w[i] * Kr[j * N1 + j2];
-      if (i == i2 && j == j2) {
-        const double cc = kappa * kappa * (1.0 - bnode[i * N1 + j]);
-        v -= 0.25 * h * h * cc * w[i] * w[j];
-      }
-      return v;
-    }
-    const int s = (c - pp) / p, k = (c - pp) % p + 1;
-    if (s == 0) return (j == k) ? Kr[i * N1 + 0] * w[j] : 0.0;
-    if (s == 1) return (j == k) ? Kr[i * N1 + N] * w[j] : 0.0;
-    if (s == 2) return (i == k) ? w[i] * Kr[j * N1 + 0] : 0.0;
-    return (i == k) ? w[i] * Kr[j * N1 + N] : 0.0;
-  }
-  if (c >= d.nloc) return 0.0;
-  // normal-derivative row of boundary node (side s, index k)
-  const int s = (r - pp) / p, k = (r - pp) % p + 1;
-  const double sg = (s == 0 || s == 2) ? -f : f;    // outward normal sign
-  const int dr = (s == 0 || s == 2) ? 0 : N;         // D row of the boundary node
-  if (c < pp) {
-    const int i2 = c / p + 1, j2 = c % p + 1;
-    if (s < 2) return (j2 == k) ? sg * D[dr * N1 + i2] : 0.0;   // x-derivative along line j = k
-    return (i2 == k) ? sg * D[dr * N1 + j2] : 0.0;              // y-derivative along line i = k
-  }
-  const int s2 = (c - pp) / p, k2 = (c - pp) % p + 1;
-  if (k2 != k) return 0.0;
-  if (s < 2) {
-    if (s2 == 0) return sg * D[dr * N1 + 0];
-    if (s2 == 1) return sg * D[dr * N1 + N];
-    return 0.0;
-  }
-  if (s2 == 2) return sg * D[dr * N1 + 0];
-  if (s2 == 3) return sg * D[dr * N1 + N];
-  return 0.0;
+// doubles of one element's bordered matrix in the scratch buffer (256-byte
+// multiple, so every element's matrix starts 256-byte aligned)
+__host__ __device__ inline size_t elem_stride(const Dims& d) {
+  return ((size_t)d.nloc * d.ncol + 31) & ~(size_t)31;
 }
 
-// T = -I + 2 i eta (R + i eta I)^-1 and H from [R | -q] in the trailing rows of
-// the reduced bordered matrix A; S: (4p)^2 complex LDS workspace.
-__device__ void leaf_cayley(const LeafArgs& a, const double* A, cd* S, int* ipiv, cd* colk) {
-  const Dims d = dims_of(a.N);
-  const int m = 4 * d.p, nloc = d.nloc, npiv = d.pp;
+// Bordered real matrix K of one element, column-major (ld n_loc):
+// rows/cols: interior (i,j) -> (i-1)*p + (j-1); boundary l_k, r_k, b_k, t_k ->
+// pp + side*p + (k-1); extra columns nloc, nloc+1 = Re/Im of bt.
+// Written as a zero fill followed by the nonzeros: an interior row couples to
+// the 2p-1 interior nodes on its grid lines, four boundary nodes and the two
+// source columns; a normal-derivative row to p interior and two boundary nodes.
+__device__ void assemble(const Dims& d, double* A, const double* D, const double* w, const double* Kr,
+                         const double* bnode, const double* snode, double kappa, double h) {
   const int tid = threadIdx.x;
+  const int N = d.N, p = d.p, pp = d.pp, N1 = N + 1, nloc = d.nloc;
+  const size_t total = (size_t)nloc * d.ncol;
+  double2* A2 = reinterpret_cast<double2*>(A);
+  for (size_t i = tid; i < (total + 1) / 2; i += kThreads) A2[i] = make_double2(0.0, 0.0);
+  __syncthreads();
+  const double f = 2.0 / h;
+  const double hh = 0.25 * h * h;
+  const int si = 2 * p + 5, sb = p + 2;
+  const int items = pp * si + 4 * p * sb;
+  for (int it = tid; it < items; it += kThreads) {
+    int r, c;
+    double v;
+    if (it < pp * si) {
+      r = it / si;
+      const int s = it - r * si;
+      const int i = r / p + 1, j = r - (i - 1) * p + 1;
+      if (s < p) {                       // (i2, j): x-line, diagonal when i2 == i
+        const int i2 = s + 1;
+        c = s * p + (j - 1);
+        v = Kr[i * N1 + i2] * w[j];
+        if (i2 == i) {
+          const double cc = kappa * kappa * (1.0 - bnode[i * N1 + j]);
+          v += w[i] * Kr[j * N1 + j] - hh * cc * w[i] * w[j];
+        }
+      } else if (s < 2 * p - 1) {        // (i, j2), j2 != j: y-line
+        const int jj = s - p + 1;
+        const int j2 = jj + (jj >= j ? 1 : 0);
+        c = (i - 1) * p + (j2 - 1);
+        v = w[i] * Kr[j * N1 + j2];
+      } else if (s < 2 * p + 3) {        // boundary nodes l_j, r_j, b_i, t_i
+        const int side = s - (2 * p - 1);
+        if (side == 0) { c = pp + (j - 1);         v = Kr[i * N1 + 0] * w[j]; }
+        else if (side == 1) { c = pp + p + (j - 1); v = Kr[i * N1 + N] * w[j]; }
+        else if (side == 2) { c = pp + 2 * p + (i - 1); v = w[i] * Kr[j * N1 + 0]; }
+        else { c = pp + 3 * p + (i - 1);             v = w[i] * Kr[j * N1 + N]; }
+      } else {                           // Re / Im of the source term
+        if (!snode) continue;
+        const int part = s - (2 * p + 3);
+        c = nloc + part;
+        v = hh * w[i] * w[j] * snode[2 * (i * N1 + j) + part];
+      }
+    } else {
+      const int jt = it - pp * si;
+      const int rb = jt / sb;
+      const int t = jt - rb * sb;
+      const int side = rb / p, k = rb - side * p + 1;
+      r = pp + rb;
+      const bool lo = (side == 0 || side == 2);
+      const double sg = lo ? -f : f;     // outward normal sign
+      const int dr = lo ? 0 : N;         // D row of the boundary node
+      if (t < p) {
+        c = side < 2 ? t * p + (k - 1) : (k - 1) * p + t;
+        v = sg * D[dr * N1 + t + 1];
+      } else {
+        const int s2 = (side < 2 ? 0 : 2) + (t - p);
+        c = pp + s2 * p + (k - 1);
+        v = sg * D[dr * N1 + (t == p ? 0 : N)];
+      }
+    }
+    A[(size_t)c * nloc + r] = v;
+  }
+}
+
+// Broadcast of lane l's complex value to the whole wavefront (l uniform).
+__device__ inline cd readlane_cd(cd v, int l) {
+  const long long x = __double_as_longlong(v.x), y = __double_as_longlong(v.y);
+  const unsigned x0 = (unsigned)__builtin_amdgcn_readlane((int)x, l);
+  const unsigned x1 = (unsigned)__builtin_amdgcn_readlane((int)(x >> 32), l);
+  const unsigned y0 = (unsigned)__builtin_amdgcn_readlane((int)y, l);
+  const unsigned y1 = (unsigned)__builtin_amdgcn_readlane((int)(y >> 32), l);
+  return cmk(__longlong_as_double((long long)(((unsigned long long)x1 << 32) | x0)),
+             __longlong_as_double((long long)(((unsigned long long)y1 << 32) | y0)));
+}
+
+// T = -I + 2 i eta Z and H = 2 i eta Z (-q), Z = (R + i eta I)^-1, from [R | -q]
+// in the trailing rows of the reduced bordered matrix A.
+//
+// Z by Gauss-Jordan with the 4p x 4p complex matrix in registers: thread
+// (row i = lane, wave w) holds columns j = w + 4t.  Pivot rows stay where they
+// are (marked used); a step reads the pivot row by lane broadcasts, the pivot
+// column from LDS (published by the wave holding it, with the next pivot key),
+// and needs one barrier.  With pivot row pr_k at step k, the storage ends as
+// S[pr_k][j] = Z[k][pr_j].
+__device__ void leaf_cayley(const LeafArgs& a, const Dims& d, const double* A, double* lds) {
+  constexpr int kT = 16;  // columns per thread (4p <= 64)
+  const int m = 4 * d.p, nloc = d.nloc, npiv = d.pp;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int G = a.G0 + blockIdx.x;
   const int q = G / a.E, e = G % a.E;
   const double eta = a.eta[q - a.q0];
   const double* snode = a.s_nodes[q - a.q0];
-  for (int idx = tid; idx < m * m; idx += kThreads) {
-    const int r = idx % m, c = idx / m;
-    S[idx] = cmk(A[(size_t)(npiv + c) * nloc + npiv + r], r == c ? eta : 0.0);
+  cd* colbuf = reinterpret_cast<cd*>(lds);             // [2][64] pivot column
+  cd* hpart = colbuf + 128;                            // [kWaves][64] partial H
+  unsigned long long* kw = reinterpret_cast<unsigned long long*>(hpart + kWaves * 64);  // [2]
+  int* pivs = reinterpret_cast<int*>(kw + 2);          // [64] pivot row of each step
+  const bool row_ok = lane < m;
+  cd s[kT];
+#pragma unroll
+  for (int t = 0; t < kT; ++t) {
+    const int j = wave + kWaves * t;
+    s[t] = (row_ok && j < m) ? cmk(A[(size_t)(npiv + j) * nloc + npiv + lane], lane == j ? eta : 0.0)
+                             : cmk(0.0, 0.0);
+  }
+  if (wave == 0) {
+    colbuf[lane] = s[0];
+    unsigned long long key = row_ok ? pivot_key(cabs2(s[0]), lane) : 0ull;
+    key = wave_max_key(key);
+    if (lane == 0) kw[0] = key;
   }
   __syncthreads();
-  gj_inplace_small(S, m, ipiv, colk, a.flag);
+  bool used = false;
+  int myk = 0;
+#pragma unroll 1
+  for (int k = 0; k < m; ++k) {
+    const int b = k & 1;
+    const unsigned long long kk = kw[b];
+    const bool zero = (kk >> 32) <= 1u;
+    const int pr = min(max(pivot_row(kk), 0), m - 1);
+    const cd inv = zero ? cmk(0.0, 0.0) : cinv(colbuf[b * 64 + pr]);
+    const bool isp = lane == pr;
+    if (isp) { used = true; myk = k; }
+    if (tid == 0) {
+      pivs[k] = pr;
+      if (zero) atomicOr(a.flag, 2);
+    }
+    const cd f = isp ? cmk(0.0, 0.0) : cmul(colbuf[b * 64 + lane], inv);
+    const int tk = k >> 2, ok = k & 3;
+    const int kn = k + 1, tn = kn >> 2;
+    const bool pub = kn < m && wave == (kn & 3);
+    cd vn = cmk(0.0, 0.0);
+#pragma unroll
+    for (int t = 0; t < kT; ++t) {
+      if (wave + kWaves * t < m) {
+        const cd pv = readlane_cd(s[t], pr);
+        cd v;
+        if (wave == ok && t == tk) v = isp ? inv : cmk(-f.x, -f.y);
+        else v = isp ? cmul(pv, inv) : csub(s[t], cmul(f, pv));
+        s[t] = v;
+        if (t == tn) vn = v;
+      }
+    }
+    if (pub) {
+      colbuf[(kn & 1) * 64 + lane] = vn;
+      unsigned long long key = (row_ok && !used) ? pivot_key(cabs2(vn), lane) : 0ull;
+      key = wave_max_key(key);
+      if (lane == 0) kw[kn & 1] = key;
+    }
+    __syncthreads();
+  }
   const int ix = e % a.n, iy = e / a.n;
   cd* Tout = a.T + ((size_t)q * a.E + morton_xy(ix, iy)) * m * m;
   const double te = 2.0 * eta;
-  for (int idx = tid; idx < m * m; idx += kThreads) {
-    const int r = idx % m, c = idx / m;
-    const cd z = S[idx];
-    Tout[idx] = cmk(-te * z.y - (r == c ? 1.0 : 0.0), te * z.x);
-  }
-  if (tid < m) {
-    cd acc = cmk(0.0, 0.0);
-    if (snode) {
-      for (int c = 0; c < m; ++c) {
+  cd hacc = cmk(0.0, 0.0);
+#pragma unroll
+  for (int t = 0; t < kT; ++t) {
+    const int j = wave + kWaves * t;
+    if (row_ok && j < m) {
+      const int c = pivs[j];
+      const cd z = s[t];
+      Tout[(size_t)c * m + myk] = cmk(-te * z.y - (myk == c ? 1.0 : 0.0), te * z.x);
+      if (snode) {
         const cd tc = cmk(A[(size_t)nloc * nloc + npiv + c], A[(size_t)(nloc + 1) * nloc + npiv + c]);
-        acc = cfma(S[c * m + tid], tc, acc);
+        hacc = cfma(z, tc, hacc);
       }
     }
+  }
+  if (row_ok) hpart[wave * 64 + myk] = hacc;
+  __syncthreads();
+  if (tid < m) {
+    cd acc = hpart[tid];
+#pragma unroll
+    for (int w = 1; w < kWaves; ++w) acc = cadd(acc, hpart[w * 64 + tid]);
     a.H[(size_t)G * m + tid] = cmk(-te * acc.y, te * acc.x);
   }
 }
 
+// LDS doubles shared by the panel's pivot-column exchange and U12 + L11
+__host__ __device__ inline size_t leaf_region_doubles(const Dims& d) {
+  const size_t a = (size_t)2 * 64 * kMaxChunks, b = (size_t)kNB * d.ldu + (size_t)kNB * kNB;
+  return a > b ? a : b;
+}
 
-// One element per workgroup: the bordered real partial LU, then the Cayley step.
-__global__ __launch_bounds__(kThreads) void leaf_kernel(LeafArgs a) {
-  extern __shared__ double lds[];
-  __shared__ int piv_s[kNB];
+// LDS bytes: the LU phase (panel, U12, row map) and the Cayley phase
+size_t leaf_lds_bytes(int N) {
+  const Dims d = dims_of(N);
+  const size_t lu = leaf_region_doubles(d) * sizeof(double) + (size_t)d.nloc * sizeof(int);
+  const size_t cay = (size_t)(128 + kWaves * 64) * sizeof(cd) + 2 * sizeof(unsigned long long) + 64 * sizeof(int);
+  return std::max(lu, cay);
+}
+
+// One element per workgroup: assembly, the bordered real partial LU, then the
+// Cayley step.
+__global__ __launch_bounds__(kThreads, 2) void leaf_kernel(LeafArgs a) {
+  extern __shared__ __attribute__((aligned(16))) double lds[];
+  __shared__ int piv_s[kNB];              // panel-relative pivot row of each column
+  __shared__ int dsrc_s[kNB];             // row moved into the slot of pivot piv_s[c], or -1
+  __shared__ double dinv_s[kNB];          // 1 / pivot
+  __shared__ unsigned long long kw_s[2];  // next pivot key (double buffered)
   const Dims d = dims_of(a.N);
-  const int nloc = d.nloc, ncol = d.ncol, npiv = d.pp;
-  double* P = lds;                          // panel, nloc x kNB, column-major (ld nloc)
-  double* U = lds + (size_t)nloc * kNB;     // U12 block, kNB x ncol, row-major (ld ncol)
-  const int tid = threadIdx.x;
+  const int nloc = d.nloc, ncol = d.ncol, npiv = d.pp, ldu = d.ldu;
+  // LDS region: the pivot-column exchange while a panel is factorised, then
+  // U12 and L11
+  double* colbuf = lds;                     // [2][64 * kMaxChunks] pivot column
+  double* U = lds;                          // U12, kNB x ldu, row-major
+  double* L11 = lds + (size_t)kNB * ldu;    // scaled L11, row-major kNB x kNB
+  const size_t region = leaf_region_doubles(d);
+  int* rowmap = reinterpret_cast<int*>(lds + region);  // trailing slot -> panel row of its L21
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int G = a.G0 + blockIdx.x;
   const int q = G / a.E, e = G % a.E;
   const int N1 = a.N + 1;
-  double* A = a.scratch + (size_t)blockIdx.x * nloc * ncol;
-  const double* bnode = a.b_nodes[q - a.q0] + (size_t)e * N1 * N1;
+  double* A = a.scratch + (size_t)blockIdx.x * elem_stride(d);
   const double* sq = a.s_nodes[q - a.q0];
-  const double* snode = sq ? sq + (size_t)e * 2 * N1 * N1 : nullptr;
-
-  for (int idx = tid; idx < nloc * ncol; idx += kThreads) {
-    const int r = idx % nloc, c = idx / nloc;
-    A[idx] = k_entry(d, r, c, a.D, a.w, a.Kr, bnode, snode, a.kappa[q - a.q0], a.h);
-  }
+  assemble(d, A, a.D, a.w, a.Kr, a.b_nodes[q - a.q0] + (size_t)e * N1 * N1,
+           sq ? sq + (size_t)e * 2 * N1 * N1 : nullptr, a.kappa[q - a.q0], a.h);
   __syncthreads();
 
   for (int k0 = 0; k0 < npiv; k0 += kNB) {
     const int kb = min(kNB, npiv - k0);
-    const int rows = nloc - k0;
-    for (int idx = tid; idx < rows * kb; idx += kThreads) {
-      const int r = idx % rows, c = idx / rows;
-      P[c * nloc + r] = A[(size_t)(k0 + c) * nloc + k0 + r];
+    const int rows = nloc - k0;       // panel rows
+    const int cand = npiv - k0;       // pivot candidates: the interior rows
+    const int c0 = k0 + kb, nc = ncol - c0;
+    // the panel in registers: wave w holds columns j = w + kWaves * u, lane the
+    // rows t * 64 + lane
+    double xv[kMaxChunks][kCPW];
+#pragma unroll
+    for (int u = 0; u < kCPW; ++u) {
+      const int j = wave + kWaves * u;
+      const double* col = A + (size_t)(k0 + j) * nloc + k0;
+#pragma unroll
+      for (int t = 0; t < kMaxChunks; ++t) {
+        const int r = t * 64 + lane;
+        xv[t][u] = (j < kb && r < rows) ? col[r] : 0.0;
+      }
+    }
+    for (int r = tid; r < rows; r += kThreads) rowmap[r] = r;
+    if (wave == 0) {
+      unsigned long long best = 0;
+#pragma unroll
+      for (int t = 0; t < kMaxChunks; ++t) {
+        const int r = t * 64 + lane;
+        if (r < rows) colbuf[r] = xv[t][0];
+        if (r < cand) best = max(best, pivot_key(fabs(xv[t][0]), r));
+      }
+      best = wave_max_key(best);
+      if (lane == 0) kw_s[0] = best;
     }
     __syncthreads();
+
+    // ---- panel: one barrier per column ----
+    unsigned used = 0;   // bit t: row t*64 + lane is a pivot row of this panel
+#pragma unroll 1
     for (int c = 0; c < kb; ++c) {
-      if (tid < 64) {
-        double best = -1.0;
-        int bi = c;
-        for (int r = c + tid; r < npiv - k0; r += 64) {
-          const double v = fabs(P[c * nloc + r]);
-          if (v > best) { best = v; bi = r; }
+      const int bsel = c & 1;
+      const double* cb = colbuf + bsel * 64 * kMaxChunks;
+      const unsigned long long kk = kw_s[bsel];
+      const bool zero = (kk >> 32) <= 1u;
+      const int pr = min(max(pivot_row(kk), 0), cand - 1);
+      if (lane == (pr & 63)) used |= 1u << (pr >> 6);
+      const double inv = zero ? 0.0 : 1.0 / cb[pr];
+      if (tid == 0) {
+        piv_s[c] = pr;
+        dinv_s[c] = inv;
+        if (zero) atomicOr(a.flag, 2);
+      }
+      // the pivot row of this wave's columns, by lane broadcast
+      double pv[kCPW];
+      const int tp = pr >> 6, lp = pr & 63;
+#pragma unroll
+      for (int u = 0; u < kCPW; ++u) {
+        double x = xv[0][u];
+#pragma unroll
+        for (int t = 1; t < kMaxChunks; ++t)
+          if (tp == t) x = xv[t][u];
+        const long long xb = __double_as_longlong(x);
+        const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)xb, lp);
+        const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(xb >> 32), lp);
+        // zero for finished columns: their values stay exactly as they are
+        const int j = wave + kWaves * u;
+        pv[u] = (j > c && j < kb) ? __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo)) : 0.0;
+      }
+      const int cn = c + 1;
+      const bool keyw = cn < kb && wave == (cn & (kWaves - 1));
+      const int un = cn / kWaves;
+      unsigned long long best = 0;
+      double* cbn = colbuf + (bsel ^ 1) * 64 * kMaxChunks;
+#pragma unroll
+      for (int t = 0; t < kMaxChunks; ++t) {
+        const int r = t * 64 + lane;
+        const bool act = r < rows && !((used >> t) & 1u);
+        const double m = act ? cb[r] * inv : 0.0;
+        double vn = 0.0;
+#pragma unroll
+        for (int u = 0; u < kCPW; ++u) {
+          xv[t][u] -= m * pv[u];
+          if (u == un) vn = xv[t][u];
         }
-        for (int off = 32; off > 0; off >>= 1) {
-          const double ov = __shfl_xor(best, off);
-          const int oi = __shfl_xor(bi, off);
-          if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
-        }
-        if (tid == 0) {
-          piv_s[c] = bi;
-          if (!(best > 0.0)) atomicOr(a.flag, 2);
+        if (keyw) {
+          if (r < rows) cbn[r] = vn;
+          if (act && r < cand) best = max(best, pivot_key(fabs(vn), r));
         }
       }
-      __syncthreads();
-      const int pr = piv_s[c];
-      if (pr != c) {
-        for (int j = tid; j < kb; j += kThreads) {
-          const double t = P[j * nloc + c];
-          P[j * nloc + c] = P[j * nloc + pr];
-          P[j * nloc + pr] = t;
-        }
-        __syncthreads();
+      if (keyw) {
+        best = wave_max_key(best);
+        if (lane == 0) kw_s[bsel ^ 1] = best;
       }
-      const double piv = P[c * nloc + c];
-      const double inv = (piv != 0.0) ? 1.0 / piv : 0.0;
-      for (int r = c + 1 + tid; r < rows; r += kThreads) {
-        const double l = P[c * nloc + r] * inv;
-        P[c * nloc + r] = l;
-        for (int j = c + 1; j < kb; ++j) P[j * nloc + r] -= l * P[j * nloc + c];
+      if (c == kb - 1 && wave == 0) {
+        // pair the pivot rows beyond the first kb with the non-pivot rows
+        // among the first kb: those rows take the pivot rows' slots
+        bool isp = false;
+        if (lane < kb)
+          for (int qq = 0; qq < kb; ++qq) isp |= (piv_s[qq] == lane);
+        const unsigned long long nonpiv = __ballot(lane < kb && !isp);
+        const int y = lane < kb ? piv_s[lane] : 0;
+        const bool far = lane < kb && y >= kb;
+        const unsigned long long farm = __ballot(far);
+        if (far) {
+          const int rank = __popcll(farm & ((1ull << lane) - 1ull));
+          unsigned long long mm = nonpiv;
+          for (int k = 0; k < rank; ++k) mm &= mm - 1ull;
+          const int x = __ffsll((long long)mm) - 1;
+          dsrc_s[lane] = x;
+          rowmap[y] = x;
+        } else if (lane < kb) {
+          dsrc_s[lane] = -1;
+        }
       }
       __syncthreads();
     }
-    // row interchanges on the trailing columns
-    const int c0 = k0 + kb;
-    for (int col = c0 + tid; col < ncol; col += kThreads) {
-      double* Ac = A + (size_t)col * nloc + k0;
-      for (int c = 0; c < kb; ++c) {
-        const int pr = piv_s[c];
-        if (pr != c) {
-          const double t = Ac[c];
-          Ac[c] = Ac[pr];
-          Ac[pr] = t;
+
+    // ---- scaled multipliers to the (finished) panel columns of A ----
+#pragma unroll
+    for (int u = 0; u < kCPW; ++u) {
+      const int j = wave + kWaves * u;
+      if (j < kb) {
+        const double dj = dinv_s[j];
+        double* col = A + (size_t)(k0 + j) * nloc + k0;
+#pragma unroll
+        for (int t = 0; t < kMaxChunks; ++t) {
+          const int r = t * 64 + lane;
+          if (r < rows) col[r] = xv[t][u] * dj;
         }
       }
     }
     __syncthreads();
-    // U12 = L11^-1 A12 (unit lower triangular forward substitution)
-    const int nc = ncol - c0;
+    // L11 (scaled multipliers of the pivot rows) from the panel columns
+    for (int idx = tid; idx < kNB * kNB; idx += kThreads) {
+      const int qq = idx % kNB, r = idx / kNB;
+      L11[idx] = (qq < r && r < kb) ? A[(size_t)(k0 + qq) * nloc + k0 + piv_s[r]] : 0.0;
+    }
+    // ---- row interchanges on the trailing columns; U12 gathered ----
+    for (int idx = tid; idx < kNB * nc; idx += kThreads) {
+      const int qq = idx % kNB, cc = idx / kNB;
+      if (qq < kb) {
+        double* col = A + (size_t)(c0 + cc) * nloc + k0;
+        const int y = piv_s[qq];
+        U[qq * ldu + cc] = col[y];
+        const int x = dsrc_s[qq];
+        if (x >= 0) col[y] = col[x];
+      } else {
+        U[qq * ldu + cc] = 0.0;   // rows past a short last panel take part in the update
+      }
+    }
+    __syncthreads();
+    // ---- U12 = L11^-1 (pivot rows of A12): forward substitution per column ----
     for (int cc = tid; cc < nc; cc += kThreads) {
-      const double* Ac = A + (size_t)(c0 + cc) * nloc + k0;
       double u[kNB];
 #pragma unroll
-      for (int r = 0; r < kNB; ++r) {
-        if (r < kb) {
-          double s = Ac[r];
+      for (int r = 0; r < kNB; ++r) u[r] = r < kb ? U[r * ldu + cc] : 0.0;
 #pragma unroll
-          for (int q = 0; q < kNB; ++q)
-            if (q < r) s -= P[q * nloc + r] * u[q];
-          u[r] = s;
-          U[r * ncol + cc] = s;
-        }
+      for (int r = 1; r < kNB; ++r) {
+        double s = u[r];
+#pragma unroll
+        for (int qq = 0; qq < r; ++qq) s -= L11[r * kNB + qq] * u[qq];
+        u[r] = s;
+        asm volatile("" : "+v"(u[r])::"memory");
       }
+#pragma unroll
+      for (int r = 0; r < kNB; ++r)
+        if (r < kb) U[r * ldu + cc] = u[r];
     }
     __syncthreads();
-    // trailing update A22 -= L21 U12, rows k0+kb.., cols c0..
+    // ---- trailing update A22 -= L21 U12: one row x four adjacent columns ----
     const int tr = rows - kb;
-    const int items = tr * kStripes;
-    for (int it = tid; it < items; it += kThreads) {
-      const int r = it % tr, stripe = it / tr;
+    const int RB = (tr + 63) >> 6, CG = (nc + 3) >> 2;
+#pragma unroll 1
+    for (int rb = 0; rb < RB; ++rb) {
+      const int y = kb + rb * 64 + lane;       // panel-relative slot
+      const bool live = y < rows;
       double l[kNB];
+      {
+        const double* lrow = A + (size_t)k0 * nloc + k0 + (live ? rowmap[y] : 0);
 #pragma unroll
-      for (int q = 0; q < kNB; ++q) l[q] = (q < kb) ? P[q * nloc + kb + r] : 0.0;
-      // four columns per iteration keep four loads in flight per thread
-      int cc = stripe;
-      for (; cc + 3 * kStripes < nc; cc += 4 * kStripes) {
-        double* ap[4];
-        double sv[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          ap[u] = A + (size_t)(c0 + cc + u * kStripes) * nloc + k0 + kb + r;
-          sv[u] = *ap[u];
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-#pragma unroll
-          for (int q = 0; q < kNB; ++q) sv[u] -= l[q] * U[q * ncol + cc + u * kStripes];
-          *ap[u] = sv[u];
-        }
+        for (int qq = 0; qq < kNB; ++qq) l[qq] = (live && qq < kb) ? lrow[(size_t)qq * nloc] : 0.0;
       }
-      for (; cc < nc; cc += kStripes) {
-        double* ap = A + (size_t)(c0 + cc) * nloc + k0 + kb + r;
-        double s = *ap;
+      double* arow = A + (size_t)c0 * nloc + k0 + y;
+      int cg = wave;
+      double nx[4];
 #pragma unroll
-        for (int q = 0; q < kNB; ++q) s -= l[q] * U[q * ncol + cc];
-        *ap = s;
+      for (int u = 0; u < 4; ++u) {
+        const int cc = cg * 4 + u;
+        nx[u] = (live && cg < CG && cc < nc) ? arow[(size_t)cc * nloc] : 0.0;
+      }
+#pragma unroll 1
+      for (; cg < CG; cg += kWaves) {
+        double s[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) s[u] = nx[u];
+        const int cn = cg + kWaves;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int cc = cn * 4 + u;
+          nx[u] = (live && cn < CG && cc < nc) ? arow[(size_t)cc * nloc] : 0.0;
+        }
+        const double2* Ub = reinterpret_cast<const double2*>(U + cg * 4);
+        // four U12 rows at a time keep the register footprint at two waves per SIMD
+#pragma unroll
+        for (int q4 = 0; q4 < kNB; q4 += 4) {
+          double2 u01[4], u23[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            u01[k] = Ub[(q4 + k) * (ldu / 2)];
+            u23[k] = Ub[(q4 + k) * (ldu / 2) + 1];
+          }
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            s[0] -= l[q4 + k] * u01[k].x;
+            s[1] -= l[q4 + k] * u01[k].y;
+            s[2] -= l[q4 + k] * u23[k].x;
+            s[3] -= l[q4 + k] * u23[k].y;
+          }
+          // keeps the products in this group (not sunk into the guarded
+          // stores) and the next group's loads behind them
+          asm volatile("" : "+v"(s[0]), "+v"(s[1]), "+v"(s[2]), "+v"(s[3])::"memory");
+        }
+        if (live) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (cg * 4 + u < nc) arow[(size_t)(cg * 4 + u) * nloc] = s[u];
+        }
       }
     }
     __syncthreads();
   }
   // the factorisation's LDS is free again: the Cayley step reuses it
-  __shared__ int ipiv_c[64];
-  __shared__ cd colk_c[64];
-  leaf_cayley(a, A, reinterpret_cast<cd*>(lds), ipiv_c, colk_c);
+  leaf_cayley(a, d, A, lds);
 }
 
 }  // namespace
 
 size_t leaf_scratch_doubles(int N, int count) {
-  const int p = N - 1, nloc = p * p + 4 * p;
-  return (size_t)count * nloc * (nloc + 2);
+  return (size_t)count * elem_stride(dims_of(N));
 }
 
 hipError_t leaf_build(const LeafArgs& a, hipStream_t st) {
-  const int p = a.N - 1, nloc = p * p + 4 * p, ncol = nloc + 2;
-  const size_t lds_lu = ((size_t)nloc * kNB + (size_t)kNB * ncol) * sizeof(double);
-  const size_t lds_cayley = (size_t)(4 * p) * (4 * p) * sizeof(cd);
-  const size_t lds = std::max(lds_lu, lds_cayley);
+  const Dims d = dims_of(a.N);
+  if (d.nloc > 64 * kMaxChunks || 4 * d.p > 64) return hipErrorInvalidValue;
+  const size_t lds = leaf_lds_bytes(a.N);
   hipError_t e0 = allow_lds(leaf_kernel, lds);
   if (e0 != hipSuccess) return e0;
   hipLaunchKernelGGL(leaf_kernel, dim3(a.count), dim3(kThreads), lds, st, a);
