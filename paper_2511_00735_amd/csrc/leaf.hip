@@ -145,6 +145,39 @@ __device__ void assemble(const Dims& d, double* A, const double* D, const double
   }
 }
 
+// Lane l's double broadcast to the whole wavefront (l uniform).
+__device__ inline double readlane_d(double v, int l) {
+  const long long x = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)x, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(x >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Called by the one wave holding the next panel column (value of row t*64 +
+// lane in v[t]): publishes the column, picks its pivot among the unused
+// candidate rows and stores the pivot key and 1/pivot.
+__device__ inline void publish_pivot(const double (&v)[kMaxChunks], unsigned used, int rows, int cand,
+                                     double* cbn, unsigned long long* key_out, double* inv_out) {
+  const int lane = threadIdx.x & 63;
+  unsigned long long best = 0;
+#pragma unroll
+  for (int t = 0; t < kMaxChunks; ++t) {
+    const int r = t * 64 + lane;
+    if (r < rows) cbn[r] = v[t];
+    if (r < cand && !((used >> t) & 1u)) best = max(best, pivot_key(fabs(v[t]), r));
+  }
+  best = wave_max_key(best);
+  const int pn = min(max(pivot_row(best), 0), cand - 1);
+  double dn = 0.0;
+#pragma unroll
+  for (int t = 0; t < kMaxChunks; ++t)
+    if (t == (pn >> 6)) dn = readlane_d(v[t], pn & 63);
+  if (lane == 0) {
+    *key_out = best;
+    *inv_out = ((best >> 32) <= 1u) ? 0.0 : 1.0 / dn;
+  }
+}
+
 // Broadcast of lane l's complex value to the whole wavefront (l uniform).
 __device__ inline cd readlane_cd(cd v, int l) {
   const long long x = __double_as_longlong(v.x), y = __double_as_longlong(v.y);
@@ -154,6 +187,22 @@ __device__ inline cd readlane_cd(cd v, int l) {
   const unsigned y1 = (unsigned)__builtin_amdgcn_readlane((int)(y >> 32), l);
   return cmk(__longlong_as_double((long long)(((unsigned long long)x1 << 32) | x0)),
              __longlong_as_double((long long)(((unsigned long long)y1 << 32) | y0)));
+}
+
+// Called by the one wave holding the next column of the Cayley inverse (row
+// lane in v): publishes the column, picks its pivot among the unused rows and
+// stores the pivot key and 1/pivot.
+__device__ inline void cayley_publish(cd v, bool used, bool row_ok, cd* cbn, unsigned long long* key_out,
+                                      cd* inv_out) {
+  const int lane = threadIdx.x & 63;
+  cbn[lane] = v;
+  unsigned long long key = (row_ok && !used) ? pivot_key(cabs2(v), lane) : 0ull;
+  key = wave_max_key(key);
+  const cd d = readlane_cd(v, pivot_row(key) & 63);
+  if (lane == 0) {
+    *key_out = key;
+    *inv_out = ((key >> 32) <= 1u) ? cmk(0.0, 0.0) : cinv(d);
+  }
 }
 
 // T = -I + 2 i eta Z and H = 2 i eta Z (-q), Z = (R + i eta I)^-1, from [R | -q]
@@ -175,7 +224,8 @@ __device__ void leaf_cayley(const LeafArgs& a, const Dims& d, const double* A, d
   const double* snode = a.s_nodes[q - a.q0];
   cd* colbuf = reinterpret_cast<cd*>(lds);             // [2][64] pivot column
   cd* hpart = colbuf + 128;                            // [kWaves][64] partial H
-  unsigned long long* kw = reinterpret_cast<unsigned long long*>(hpart + kWaves * 64);  // [2]
+  cd* pinv = hpart + kWaves * 64;                      // [2] 1 / next pivot
+  unsigned long long* kw = reinterpret_cast<unsigned long long*>(pinv + 2);  // [2]
   int* pivs = reinterpret_cast<int*>(kw + 2);          // [64] pivot row of each step
   const bool row_ok = lane < m;
   cd s[kT];
@@ -185,12 +235,7 @@ __device__ void leaf_cayley(const LeafArgs& a, const Dims& d, const double* A, d
     s[t] = (row_ok && j < m) ? cmk(A[(size_t)(npiv + j) * nloc + npiv + lane], lane == j ? eta : 0.0)
                              : cmk(0.0, 0.0);
   }
-  if (wave == 0) {
-    colbuf[lane] = s[0];
-    unsigned long long key = row_ok ? pivot_key(cabs2(s[0]), lane) : 0ull;
-    key = wave_max_key(key);
-    if (lane == 0) kw[0] = key;
-  }
+  if (wave == 0) cayley_publish(s[0], false, row_ok, colbuf, kw, pinv);
   __syncthreads();
   bool used = false;
   int myk = 0;
@@ -198,9 +243,9 @@ __device__ void leaf_cayley(const LeafArgs& a, const Dims& d, const double* A, d
   for (int k = 0; k < m; ++k) {
     const int b = k & 1;
     const unsigned long long kk = kw[b];
+    const cd inv = pinv[b];
     const bool zero = (kk >> 32) <= 1u;
     const int pr = min(max(pivot_row(kk), 0), m - 1);
-    const cd inv = zero ? cmk(0.0, 0.0) : cinv(colbuf[b * 64 + pr]);
     const bool isp = lane == pr;
     if (isp) { used = true; myk = k; }
     if (tid == 0) {
@@ -209,25 +254,26 @@ __device__ void leaf_cayley(const LeafArgs& a, const Dims& d, const double* A, d
     }
     const cd f = isp ? cmk(0.0, 0.0) : cmul(colbuf[b * 64 + lane], inv);
     const int tk = k >> 2, ok = k & 3;
-    const int kn = k + 1, tn = kn >> 2;
-    const bool pub = kn < m && wave == (kn & 3);
-    cd vn = cmk(0.0, 0.0);
 #pragma unroll
     for (int t = 0; t < kT; ++t) {
       if (wave + kWaves * t < m) {
-        const cd pv = readlane_cd(s[t], pr);
-        cd v;
-        if (wave == ok && t == tk) v = isp ? inv : cmk(-f.x, -f.y);
-        else v = isp ? cmul(pv, inv) : csub(s[t], cmul(f, pv));
-        s[t] = v;
-        if (t == tn) vn = v;
+        if (wave == ok && t == tk) {
+          s[t] = isp ? inv : cmk(-f.x, -f.y);
+        } else {
+          const cd pv = readlane_cd(s[t], pr);
+          s[t] = isp ? cmul(pv, inv) : csub(s[t], cmul(f, pv));
+        }
       }
     }
-    if (pub) {
-      colbuf[(kn & 1) * 64 + lane] = vn;
-      unsigned long long key = (row_ok && !used) ? pivot_key(cabs2(vn), lane) : 0ull;
-      key = wave_max_key(key);
-      if (lane == 0) kw[kn & 1] = key;
+    // the wave holding column k + 1 publishes it with its pivot and 1/pivot
+    const int kn = k + 1;
+    if (kn < m && wave == (kn & 3)) {
+      const int tn = kn >> 2;
+      cd vn = cmk(0.0, 0.0);
+#pragma unroll
+      for (int t = 0; t < kT; ++t)
+        if (t == tn) vn = s[t];
+      cayley_publish(vn, used, row_ok, colbuf + (kn & 1) * 64, kw + (kn & 1), pinv + (kn & 1));
     }
     __syncthreads();
   }
@@ -268,7 +314,7 @@ __host__ __device__ inline size_t leaf_region_doubles(const Dims& d) {
 size_t leaf_lds_bytes(int N) {
   const Dims d = dims_of(N);
   const size_t lu = leaf_region_doubles(d) * sizeof(double) + (size_t)d.nloc * sizeof(int);
-  const size_t cay = (size_t)(128 + kWaves * 64) * sizeof(cd) + 2 * sizeof(unsigned long long) + 64 * sizeof(int);
+  const size_t cay = (size_t)(130 + kWaves * 64) * sizeof(cd) + 2 * sizeof(unsigned long long) + 64 * sizeof(int);
   return std::max(lu, cay);
 }
 
@@ -280,6 +326,7 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_kernel(LeafArgs a) {
   __shared__ int dsrc_s[kNB];             // row moved into the slot of pivot piv_s[c], or -1
   __shared__ double dinv_s[kNB];          // 1 / pivot
   __shared__ unsigned long long kw_s[2];  // next pivot key (double buffered)
+  __shared__ double pinv_s[2];            // 1 / next pivot
   const Dims d = dims_of(a.N);
   const int nloc = d.nloc, ncol = d.ncol, npiv = d.pp, ldu = d.ldu;
   // LDS region: the pivot-column exchange while a panel is factorised, then
@@ -319,15 +366,10 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_kernel(LeafArgs a) {
     }
     for (int r = tid; r < rows; r += kThreads) rowmap[r] = r;
     if (wave == 0) {
-      unsigned long long best = 0;
+      double v0[kMaxChunks];
 #pragma unroll
-      for (int t = 0; t < kMaxChunks; ++t) {
-        const int r = t * 64 + lane;
-        if (r < rows) colbuf[r] = xv[t][0];
-        if (r < cand) best = max(best, pivot_key(fabs(xv[t][0]), r));
-      }
-      best = wave_max_key(best);
-      if (lane == 0) kw_s[0] = best;
+      for (int t = 0; t < kMaxChunks; ++t) v0[t] = xv[t][0];
+      publish_pivot(v0, 0u, rows, cand, colbuf, kw_s, pinv_s);
     }
     __syncthreads();
 
@@ -338,55 +380,54 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_kernel(LeafArgs a) {
       const int bsel = c & 1;
       const double* cb = colbuf + bsel * 64 * kMaxChunks;
       const unsigned long long kk = kw_s[bsel];
+      const double inv = pinv_s[bsel];
       const bool zero = (kk >> 32) <= 1u;
       const int pr = min(max(pivot_row(kk), 0), cand - 1);
-      if (lane == (pr & 63)) used |= 1u << (pr >> 6);
-      const double inv = zero ? 0.0 : 1.0 / cb[pr];
+      const int tp = pr >> 6, lp = pr & 63;
+      if (lane == lp) used |= 1u << tp;
       if (tid == 0) {
         piv_s[c] = pr;
         dinv_s[c] = inv;
         if (zero) atomicOr(a.flag, 2);
       }
-      // the pivot row of this wave's columns, by lane broadcast
+      // the pivot row of this wave's open columns, by lane broadcast (zero for
+      // finished columns: their values stay exactly as they are)
       double pv[kCPW];
-      const int tp = pr >> 6, lp = pr & 63;
 #pragma unroll
-      for (int u = 0; u < kCPW; ++u) {
-        double x = xv[0][u];
+      for (int u = 0; u < kCPW; ++u) pv[u] = 0.0;
 #pragma unroll
-        for (int t = 1; t < kMaxChunks; ++t)
-          if (tp == t) x = xv[t][u];
-        const long long xb = __double_as_longlong(x);
-        const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)xb, lp);
-        const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(xb >> 32), lp);
-        // zero for finished columns: their values stay exactly as they are
-        const int j = wave + kWaves * u;
-        pv[u] = (j > c && j < kb) ? __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo)) : 0.0;
+      for (int t = 0; t < kMaxChunks; ++t) {
+        if (t == tp) {
+#pragma unroll
+          for (int u = 0; u < kCPW; ++u) {
+            const int j = wave + kWaves * u;
+            if (j > c && j < kb) pv[u] = readlane_d(xv[t][u], lp);
+          }
+        }
       }
-      const int cn = c + 1;
-      const bool keyw = cn < kb && wave == (cn & (kWaves - 1));
-      const int un = cn / kWaves;
-      unsigned long long best = 0;
-      double* cbn = colbuf + (bsel ^ 1) * 64 * kMaxChunks;
 #pragma unroll
       for (int t = 0; t < kMaxChunks; ++t) {
         const int r = t * 64 + lane;
         const bool act = r < rows && !((used >> t) & 1u);
         const double m = act ? cb[r] * inv : 0.0;
-        double vn = 0.0;
 #pragma unroll
-        for (int u = 0; u < kCPW; ++u) {
-          xv[t][u] -= m * pv[u];
-          if (u == un) vn = xv[t][u];
-        }
-        if (keyw) {
-          if (r < rows) cbn[r] = vn;
-          if (act && r < cand) best = max(best, pivot_key(fabs(vn), r));
-        }
+        for (int u = 0; u < kCPW; ++u) xv[t][u] -= m * pv[u];
       }
-      if (keyw) {
-        best = wave_max_key(best);
-        if (lane == 0) kw_s[bsel ^ 1] = best;
+      // the wave holding column c + 1 publishes it with its pivot and 1/pivot
+      const int cn = c + 1;
+      if (cn < kb && wave == (cn & (kWaves - 1))) {
+        const int un = cn / kWaves;
+        double vn[kMaxChunks];
+#pragma unroll
+        for (int t = 0; t < kMaxChunks; ++t) vn[t] = 0.0;
+#pragma unroll
+        for (int u = 0; u < kCPW; ++u)
+          if (u == un) {
+#pragma unroll
+            for (int t = 0; t < kMaxChunks; ++t) vn[t] = xv[t][u];
+          }
+        publish_pivot(vn, used, rows, cand, colbuf + (bsel ^ 1) * 64 * kMaxChunks, kw_s + (bsel ^ 1),
+                      pinv_s + (bsel ^ 1));
       }
       if (c == kb - 1 && wave == 0) {
         // pair the pivot rows beyond the first kb with the non-pivot rows
