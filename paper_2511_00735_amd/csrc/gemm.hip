@@ -8,7 +8,8 @@
 //   Re += Ar Br - Ai Bi,  Im += Ar Bi + Ai Br.
 // Tile: BM x BN per workgroup, waves arranged WM x WN, each wave owning
 // (BM/WM) x (BN/WN) outputs as 16x16 MFMA tiles; K staged through LDS in
-// chunks of KT complex.
+// chunks of KT complex, the next chunk's global loads issued into registers
+// before the current chunk is multiplied.
 #include "common.h"
 #include "host.h"
 
@@ -47,7 +48,7 @@ __global__ __launch_bounds__(64 * WM * WN) void zgemm_kernel(GemmArgsT<T> a) {
   constexpr int TM = BM / WM / 16;
   constexpr int TN = BN / WN / 16;
   __shared__ T As[KT][BM];
-  __shared__ T Bs[KT][BN];
+  __shared__ T Bs[KT][BN + 1];   // padded: the 16 k-rows of a column land in different banks
   const int b = blockIdx.y;
   const int tilesM = (a.M + BM - 1) / BM;
   const int m0 = (blockIdx.x % tilesM) * BM;
@@ -87,6 +88,44 @@ __global__ __launch_bounds__(64 * WM * WN) void zgemm_kernel(GemmArgsT<T> a) {
   const int wm = wave % WM, wn = wave / WM;
   const int lr = lane & 15, lk = lane >> 4;
 
+  // Fixed per-thread load slots: A(i, k) with i = tid % BM, k = tid / BM + s KSA;
+  // B(k, j) with k = tid % KT, j = tid / KT + s JSB.  Row and column maps that
+  // do not change along K are resolved once.
+  constexpr int SA = BM * KT / NT, SB = BN * KT / NT;
+  constexpr int KSA = NT / BM, JSB = NT / KT;
+  static_assert(SA * NT == BM * KT && SB * NT == BN * KT, "tile / thread mismatch");
+  const int ia = tid % BM, ka = tid / BM;
+  const int kb = tid % KT, jb = tid / KT;
+  const bool rowok = m0 + ia < a.M;
+  const long long rA = rowok ? imap(a.A.r, m0 + ia) : 0;
+  long long cB[SB];
+  bool colok[SB];
+#pragma unroll
+  for (int s = 0; s < SB; ++s) {
+    const int gj = n0 + jb + s * JSB;
+    colok[s] = gj < a.N;
+    cB[s] = colok[s] ? (long long)imap(a.B.c, gj) * a.B.ld : 0;
+  }
+  T ra[SA], rb[SB];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int s = 0; s < SA; ++s) {
+      const int gk = k0 + ka + s * KSA;
+      ra[s] = (rowok && gk < a.K) ? Ab[(long long)imap(a.A.c, gk) * a.A.ld + rA] : cx<T>::make(0.0, 0.0);
+    }
+    const int gk = k0 + kb;
+    const bool kok = gk < a.K;
+    const long long rB = kok ? imap(a.B.r, gk) : 0;
+#pragma unroll
+    for (int s = 0; s < SB; ++s) rb[s] = (kok && colok[s]) ? Bb[cB[s] + rB] : cx<T>::make(0.0, 0.0);
+  };
+  auto stash = [&]() {
+#pragma unroll
+    for (int s = 0; s < SA; ++s) As[ka + s * KSA][ia] = ra[s];
+#pragma unroll
+    for (int s = 0; s < SB; ++s) Bs[kb][jb + s * JSB] = rb[s];
+  };
+
   acc_t accr[TM][TN], acci[TM][TN];
 #pragma unroll
   for (int i = 0; i < TM; ++i)
@@ -96,22 +135,13 @@ __global__ __launch_bounds__(64 * WM * WN) void zgemm_kernel(GemmArgsT<T> a) {
       acci[i][j] = acc_t{0, 0, 0, 0};
     }
 
+  fetch(0);
+  stash();
+  __syncthreads();
   for (int k0 = 0; k0 < a.K; k0 += KT) {
-    for (int e = tid; e < BM * KT; e += NT) {
-      const int i = e % BM, k = e / BM;
-      const int gi = m0 + i, gk = k0 + k;
-      T v = cx<T>::make(0.0, 0.0);
-      if (gi < a.M && gk < a.K) v = Ab[(long long)imap(a.A.c, gk) * a.A.ld + imap(a.A.r, gi)];
-      As[k][i] = v;
-    }
-    for (int e = tid; e < BN * KT; e += NT) {
-      const int k = e % KT, j = e / KT;
-      const int gj = n0 + j, gk = k0 + k;
-      T v = cx<T>::make(0.0, 0.0);
-      if (gj < a.N && gk < a.K) v = Bb[(long long)imap(a.B.c, gj) * a.B.ld + imap(a.B.r, gk)];
-      Bs[k][j] = v;
-    }
-    __syncthreads();
+    // the next chunk's loads are in flight while this one is multiplied
+    const bool more = k0 + KT < a.K;
+    if (more) fetch(k0 + KT);
 #pragma unroll
     for (int kk = 0; kk < KT; kk += 4) {
       T av[TM], bv[TN];
@@ -130,6 +160,10 @@ __global__ __launch_bounds__(64 * WM * WN) void zgemm_kernel(GemmArgsT<T> a) {
         }
     }
     __syncthreads();
+    if (more) {
+      stash();
+      __syncthreads();
+    }
   }
 
   T* Db = a.D + (long long)b * a.Dstride;
@@ -201,7 +235,9 @@ hipError_t launch(const GemmArgsT<T>& a, hipStream_t st) {
 template <class T>
 hipError_t zgemm(const GemmArgsT<T>& a, hipStream_t st) {
   if (a.M <= 0 || a.N <= 0 || a.batch <= 0) return hipSuccess;
-  if (a.M >= 48 && a.N >= 48) return launch<T, 64, 64, 2, 2>(a, st);
+  // 64x64 tiles while they still give two workgroups per CU; 32x32 otherwise
+  const long long t64 = (long long)((a.M + 63) / 64) * ((a.N + 63) / 64) * a.batch;
+  if (a.M >= 48 && a.N >= 48 && t64 >= 512) return launch<T, 64, 64, 2, 2>(a, st);
   if (a.M >= 24 && a.N >= 24) return launch<T, 32, 32, 2, 2>(a, st);
   return launch<T, 16, 16, 1, 1>(a, st);
 }
