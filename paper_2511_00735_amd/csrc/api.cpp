@@ -752,8 +752,9 @@ hps_status coarse_solve(hps_problem* p, cd* wv, cd* z) {
                                  vin_compact(vj + m, vq), vout_compact(nullptr, 0)),
                        gdesc<cd>(m, m, Operand{T, ts, b, im_off(aP), im_off(aP)}, vin_compact(vj, vq),
                                  vout_compact(nullptr, 0))};
+      // at most 8 splits: the single-workgroup Arnoldi step reads every partial
       GemvPartLayout pl{};
-      HIPCHK(c, zgemv_partials(d, 2, nq, part, &pl, st));
+      HIPCHK(c, zgemv_partials(d, 2, nq, part, &pl, st, 8));
       src.part = part;
       src.poff0 = pl.poff[0];
       src.poff1 = pl.poff[1];

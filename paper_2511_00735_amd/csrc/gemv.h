@@ -62,14 +62,15 @@ template <class M>
 hipError_t zgemv_batched(const GemvDescT<M>* d, int nd, int batch, cd* partial, hipStream_t st);
 // Partial sums only: descriptor i writes A x (alpha, y0 and y ignored) split
 // along K into partial[poff[i] + (s * batch + b) * M + r], s < nsplit[i], for
-// a consumer that sums them in split order.  One launch.
+// a consumer that sums them in split order.  One launch.  max_split > 0 caps
+// the split count (a single-workgroup consumer reads fewer partials).
 struct GemvPartLayout {
   long long poff[kGemvMaxDesc];
   int nsplit[kGemvMaxDesc];
 };
 template <class M>
 hipError_t zgemv_partials(const GemvDescT<M>* d, int nd, int batch, cd* partial, GemvPartLayout* lay,
-                          hipStream_t st);
+                          hipStream_t st, int max_split = 0);
 
 // One V-cycle level with one workgroup per pair (levels with many small pairs).
 // Per pair j (children P = box 2j, Q = box 2j+1 of level g.level):

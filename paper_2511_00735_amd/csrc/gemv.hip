@@ -227,7 +227,7 @@ hipError_t zgemv_batched(const GemvDescT<Mt>* d, int nd, int batch, cd* partial,
 
 template <class Mt>
 hipError_t zgemv_partials(const GemvDescT<Mt>* d, int nd, int batch, cd* partial, GemvPartLayout* lay,
-                          hipStream_t st) {
+                          hipStream_t st, int max_split) {
   if (nd <= 0 || nd > kGemvMaxDesc || batch <= 0 || !partial || !lay) return hipErrorInvalidValue;
   GemvBatchT<Mt> gb{};
   gb.batch = batch;
@@ -237,7 +237,8 @@ hipError_t zgemv_partials(const GemvDescT<Mt>* d, int nd, int batch, cd* partial
   for (int i = 0; i < nd; ++i) {
     gb.d[i] = d[i];
     const int tiles = (d[i].M_ + kRowsT - 1) / kRowsT;
-    const int ns = gemv_nsplit(d[i].M_, d[i].K, batch);
+    int ns = gemv_nsplit(d[i].M_, d[i].K, batch);
+    if (max_split > 0 && ns > max_split && (d[i].K + max_split - 1) / max_split <= kGemvKChunkMax) ns = max_split;
     gb.nsplit[i] = ns;
     gb.poff[i] = poff;
     lay->nsplit[i] = ns;
@@ -273,7 +274,7 @@ hipError_t vc_up_small(const SmallLevelT<Mt>& a, int pairs, cd* z, hipStream_t s
 
 template hipError_t zgemv_batched<cd>(const GemvDescT<cd>*, int, int, cd*, hipStream_t);
 template hipError_t zgemv_batched<cf>(const GemvDescT<cf>*, int, int, cd*, hipStream_t);
-template hipError_t zgemv_partials<cd>(const GemvDescT<cd>*, int, int, cd*, GemvPartLayout*, hipStream_t);
+template hipError_t zgemv_partials<cd>(const GemvDescT<cd>*, int, int, cd*, GemvPartLayout*, hipStream_t, int);
 template hipError_t vc_down_small<cd>(const SmallLevelT<cd>&, int, cd*, hipStream_t);
 template hipError_t vc_down_small<cf>(const SmallLevelT<cf>&, int, cd*, hipStream_t);
 template hipError_t vc_up_small<cd>(const SmallLevelT<cd>&, int, cd*, hipStream_t);

@@ -140,13 +140,32 @@ __global__ void copy_kernel(const cd* src, cd* dst, long long n) {
 
 // ---- deterministic reductions -------------------------------------------
 // Wave-level sum in a fixed butterfly order.
-__device__ inline cd wave_sum(cd v) {
-  for (int off = 32; off > 0; off >>= 1) {
-    v.x += __shfl_xor(v.x, off);
-    v.y += __shfl_xor(v.y, off);
-  }
-  return v;
+// Lane l - s of the same 16-lane row (0 outside the row), by DPP.
+template <int kCtrl>
+__device__ inline double dpp_shr(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, kCtrl, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), kCtrl, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
+__device__ inline double lane_value(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)b, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Sum over the wavefront, returned to every lane: DPP row shifts by 1, 2, 4, 8
+// leave each 16-lane row's sum in its last lane; the four row sums are then
+// added in row order (deterministic).
+__device__ inline double wave_sum(double v) {
+  v += dpp_shr<0x111>(v);
+  v += dpp_shr<0x112>(v);
+  v += dpp_shr<0x114>(v);
+  v += dpp_shr<0x118>(v);
+  return (lane_value(v, 15) + lane_value(v, 31)) + (lane_value(v, 47) + lane_value(v, 63));
+}
+__device__ inline cd wave_sum(cd v) { return cmk(wave_sum(v.x), wave_sum(v.y)); }
 
 // Block-level sum (256 threads), result valid in thread 0.
 __device__ inline cd block_sum(cd v) {
@@ -389,32 +408,45 @@ __global__ __launch_bounds__(NT) void coarse_arnoldi_fast_kernel(cd* V, int n, l
     for (int v = 0; v < kFastV; ++v) vv[v][e] = (v <= j && i < n) ? V[(long long)v * n + i] : zero;
   }
   const cd* vj = V + (long long)j * n;
+  if (src.part) {
+    // w = v_j - (sum of the split-K partials, in split order); the partials of
+    // all EP entries of a thread are loaded together, four splits at a time
+    const cd* pp[EP];
+    int nse[EP];
 #pragma unroll
-  for (int e = 0; e < EP; ++e) {
-    const int i = t + e * NT;
-    cd x = zero;
-    if (i < n) {
-      if (src.part) {
-        const bool second = i >= src.m;
-        const int r = second ? i - src.m : i;
-        const long long po = second ? src.poff1 : src.poff0;
-        const int ns = second ? src.ns1 : src.ns0;
-        cd acc = zero;
-        for (int q0 = 0; q0 < ns; q0 += 8) {
-          cd tmp[8];
-#pragma unroll
-          for (int u = 0; u < 8; ++u)
-            tmp[u] = q0 + u < ns ? src.part[po + ((long long)(q0 + u) * src.nb + qp) * src.m + r] : zero;
-#pragma unroll
-          for (int u = 0; u < 8; ++u)
-            if (q0 + u < ns) acc = cadd(acc, tmp[u]);
-        }
-        x = csub(vj[i], acc);
-      } else {
-        x = src.w[i];
-      }
+    for (int e = 0; e < EP; ++e) {
+      const int i = t + e * NT;
+      const bool second = i >= src.m;
+      const int r = second ? i - src.m : i;
+      pp[e] = src.part + (second ? src.poff1 : src.poff0) + (long long)qp * src.m + r;
+      nse[e] = i < n ? (second ? src.ns1 : src.ns0) : 0;
+      w[e] = zero;
     }
-    w[e] = x;
+    const long long qs = (long long)src.nb * src.m;
+    const int nsmax = max(src.ns0, src.ns1);
+    for (int q0 = 0; q0 < nsmax; q0 += 4) {
+      cd tmp[4][EP];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int e = 0; e < EP; ++e) tmp[u][e] = q0 + u < nse[e] ? pp[e][(q0 + u) * qs] : zero;
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int e = 0; e < EP; ++e)
+          if (q0 + u < nse[e]) w[e] = cadd(w[e], tmp[u][e]);
+    }
+#pragma unroll
+    for (int e = 0; e < EP; ++e) {
+      const int i = t + e * NT;
+      w[e] = i < n ? csub(vj[i], w[e]) : zero;
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < EP; ++e) {
+      const int i = t + e * NT;
+      w[e] = i < n ? src.w[i] : zero;
+    }
   }
   for (int pass = 0; pass < 2; ++pass) {
     cd acc[kFastV];
@@ -596,7 +628,13 @@ hipError_t coarse_start(const int* idx, int n, const cd* vec, cd* V, long long v
 hipError_t coarse_arnoldi(cd* V, int n, long long vq, int j, const CoarseW& src, cd* wtmp, cd* Hcol, int hsize,
                           int nq, hipStream_t st) {
   if (j < 0 || j + 1 > kMaxCoarse) return hipErrorInvalidValue;
-  if (j < kFastV && n <= 4 * 256)
+  if (j < kFastV && n <= 1024)
+    hipLaunchKernelGGL((coarse_arnoldi_fast_kernel<1, 1024>), dim3(nq), dim3(1024), 0, st, V, n, vq, j, src, Hcol,
+                       hsize);
+  else if (j < kFastV && n <= 2 * 1024)
+    hipLaunchKernelGGL((coarse_arnoldi_fast_kernel<2, 1024>), dim3(nq), dim3(1024), 0, st, V, n, vq, j, src, Hcol,
+                       hsize);
+  else if (j < kFastV && n <= 4 * 256)
     hipLaunchKernelGGL((coarse_arnoldi_fast_kernel<4, 256>), dim3(nq), dim3(256), 0, st, V, n, vq, j, src, Hcol,
                        hsize);
   else if (j < kFastV && n <= 8 * 256)
