@@ -18,7 +18,6 @@ __device__ inline void gj_inplace_small(T* S, int m, int* ipiv, T* colk, T* rowk
                                         int* flag) {
   const int tid = threadIdx.x, nt = blockDim.x, nw = nt >> 6;
   const int i = tid & 63, g = tid >> 6, G = nw;
-  const T zero = cx<T>::make(0.0, 0.0);
   unsigned long long best = (g == 0 && i < m) ? hps::pivot_key(cabs2(S[i]), i) : 0ull;
   best = hps::wave_max_key(best);
   if ((tid & 63) == 0) kw[g] = best;
@@ -38,14 +37,14 @@ __device__ inline void gj_inplace_small(T* S, int m, int* ipiv, T* colk, T* rowk
     }
     for (int r = tid; r < m; r += nt) {
       const int src = (r == pr) ? k : r;
-      colk[r] = (r == k) ? zero : S[k * m + src];
+      colk[r] = (r == k) ? cx<T>::make(0.0, 0.0) : S[k * m + src];
     }
     if (tid == 0) {
       ipiv[k] = pr;
       if (bad) atomicOr(flag, 2);
     }
     __syncthreads();
-    const T inv = (cabs2(d) > 0) ? cinv(d) : zero;
+    const T inv = (cabs2(d) > 0) ? cinv(d) : cx<T>::make(0.0, 0.0);
     best = 0;
     if (i < m) {
       const T ci = colk[i];
@@ -54,7 +53,7 @@ __device__ inline void gj_inplace_small(T* S, int m, int* ipiv, T* colk, T* rowk
         if (i == k) {
           v = (j == k) ? inv : cmul(rowk[j], inv);
         } else if (j == k) {
-          v = csub(zero, cmul(ci, inv));
+          v = csub(cx<T>::make(0.0, 0.0), cmul(ci, inv));
         } else {
           v = csub(S[j * m + i], cmul(ci, cmul(rowk[j], inv)));
         }

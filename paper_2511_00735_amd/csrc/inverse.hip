@@ -231,7 +231,6 @@ __global__ __launch_bounds__(256) void gj_update_kernel(const T* A, int lda, lon
   const T* Db = dinv + (long long)b * kNB * kNB;
   const int tid = threadIdx.x;
   const int tx = tid % 16, ty = tid / 16;
-  const T zero = cx<T>::make(0.0, 0.0);
   T aout[4][4];
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
@@ -242,25 +241,25 @@ __global__ __launch_bounds__(256) void gj_update_kernel(const T* A, int lda, lon
     for (int v = 0; v < 4; ++v) {
       const int gj = j0 + ty + 16 * v;
       const bool ok = rowok && gj < m && !(gj >= k0 && gj < k0 + kb);
-      aout[u][v] = ok ? Ab[(long long)gj * lda + src] : zero;
+      aout[u][v] = ok ? Ab[(long long)gj * lda + src] : cx<T>::make(0.0, 0.0);
     }
   }
   for (int idx = tid; idx < kb * kb; idx += 256) Ds[(idx / kb) * kNB + idx % kb] = Db[idx];
   for (int idx = tid; idx < kb * BT; idx += 256) {
     const int q = idx % kb, j = idx / kb;
     const int gj = j0 + j;
-    Bp[q][j] = (gj < m) ? Ab[(long long)gj * lda + rm[k0 + q]] : zero;
+    Bp[q][j] = (gj < m) ? Ab[(long long)gj * lda + rm[k0 + q]] : cx<T>::make(0.0, 0.0);
   }
   for (int idx = tid; idx < BT * kb; idx += 256) {
     const int i = idx % BT, q = idx / BT;
     const int gi = i0 + i;
-    Ac[q][i] = (gi < m) ? Ab[(long long)(k0 + q) * lda + rm[gi]] : zero;
+    Ac[q][i] = (gi < m) ? Ab[(long long)(k0 + q) * lda + rm[gi]] : cx<T>::make(0.0, 0.0);
   }
   __syncthreads();
   for (int idx = tid; idx < kb * BT; idx += 256) {
     const int j = idx % BT, q = idx / BT;
     const int gj = j0 + j;
-    T v = zero;
+    T v = cx<T>::make(0.0, 0.0);
     if (gj >= k0 && gj < k0 + kb) {
       v = Ds[(gj - k0) * kNB + q];
     } else if (gj < m) {
@@ -273,7 +272,7 @@ __global__ __launch_bounds__(256) void gj_update_kernel(const T* A, int lda, lon
 #pragma unroll
   for (int u = 0; u < 4; ++u)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) acc[u][v] = zero;
+    for (int v = 0; v < 4; ++v) acc[u][v] = cx<T>::make(0.0, 0.0);
   for (int q = 0; q < kb; ++q) {
     T a[4], x[4];
 #pragma unroll

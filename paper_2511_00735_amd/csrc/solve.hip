@@ -398,14 +398,13 @@ __global__ __launch_bounds__(NT) void coarse_arnoldi_fast_kernel(cd* V, int n, l
   V += (long long)qp * vq;
   Hcol += (long long)qp * hsize;
   if (src.w) src.w += (long long)qp * n;
-  const cd zero = cmk(0.0, 0.0);
   cd vv[kFastV][EP];
   cd w[EP];
 #pragma unroll
   for (int e = 0; e < EP; ++e) {
     const int i = t + e * NT;
 #pragma unroll
-    for (int v = 0; v < kFastV; ++v) vv[v][e] = (v <= j && i < n) ? V[(long long)v * n + i] : zero;
+    for (int v = 0; v < kFastV; ++v) vv[v][e] = (v <= j && i < n) ? V[(long long)v * n + i] : cmk(0.0, 0.0);
   }
   const cd* vj = V + (long long)j * n;
   if (src.part) {
@@ -420,7 +419,7 @@ __global__ __launch_bounds__(NT) void coarse_arnoldi_fast_kernel(cd* V, int n, l
       const int r = second ? i - src.m : i;
       pp[e] = src.part + (second ? src.poff1 : src.poff0) + (long long)qp * src.m + r;
       nse[e] = i < n ? (second ? src.ns1 : src.ns0) : 0;
-      w[e] = zero;
+      w[e] = cmk(0.0, 0.0);
     }
     const long long qs = (long long)src.nb * src.m;
     const int nsmax = max(src.ns0, src.ns1);
@@ -429,7 +428,7 @@ __global__ __launch_bounds__(NT) void coarse_arnoldi_fast_kernel(cd* V, int n, l
 #pragma unroll
       for (int u = 0; u < 4; ++u)
 #pragma unroll
-        for (int e = 0; e < EP; ++e) tmp[u][e] = q0 + u < nse[e] ? pp[e][(q0 + u) * qs] : zero;
+        for (int e = 0; e < EP; ++e) tmp[u][e] = q0 + u < nse[e] ? pp[e][(q0 + u) * qs] : cmk(0.0, 0.0);
 #pragma unroll
       for (int u = 0; u < 4; ++u)
 #pragma unroll
@@ -439,20 +438,20 @@ __global__ __launch_bounds__(NT) void coarse_arnoldi_fast_kernel(cd* V, int n, l
 #pragma unroll
     for (int e = 0; e < EP; ++e) {
       const int i = t + e * NT;
-      w[e] = i < n ? csub(vj[i], w[e]) : zero;
+      w[e] = i < n ? csub(vj[i], w[e]) : cmk(0.0, 0.0);
     }
   } else {
 #pragma unroll
     for (int e = 0; e < EP; ++e) {
       const int i = t + e * NT;
-      w[e] = i < n ? src.w[i] : zero;
+      w[e] = i < n ? src.w[i] : cmk(0.0, 0.0);
     }
   }
   for (int pass = 0; pass < 2; ++pass) {
     cd acc[kFastV];
 #pragma unroll
     for (int v = 0; v < kFastV; ++v) {
-      acc[v] = zero;
+      acc[v] = cmk(0.0, 0.0);
 #pragma unroll
       for (int e = 0; e < EP; ++e) acc[v] = cfma(cconj(vv[v][e]), w[e], acc[v]);
       acc[v] = wave_sum(acc[v]);
@@ -463,7 +462,7 @@ __global__ __launch_bounds__(NT) void coarse_arnoldi_fast_kernel(cd* V, int n, l
     }
     __syncthreads();
     if (t < kFastV) {
-      cd r = zero;
+      cd r = cmk(0.0, 0.0);
       for (int q = 0; q < NT / 64; ++q) r = cadd(r, red[q][t]);
       hs[t] = r;
       hsum[t] = pass ? cadd(hsum[t], r) : r;
@@ -478,13 +477,13 @@ __global__ __launch_bounds__(NT) void coarse_arnoldi_fast_kernel(cd* V, int n, l
     }
     __syncthreads();
   }
-  cd acc = zero;
+  cd acc = cmk(0.0, 0.0);
 #pragma unroll
   for (int e = 0; e < EP; ++e) acc = cfma(cconj(w[e]), w[e], acc);
   acc = wave_sum(acc);
   if ((t & 63) == 0) red[t >> 6][0] = acc;
   __syncthreads();
-  cd nr2 = zero;
+  cd nr2 = cmk(0.0, 0.0);
   for (int q = 0; q < NT / 64; ++q) nr2 = cadd(nr2, red[q][0]);
   const double nr = sqrt(fmax(nr2.x, 0.0));
   const double sc = nr > 0.0 ? 1.0 / nr : 0.0;
@@ -628,11 +627,11 @@ hipError_t coarse_start(const int* idx, int n, const cd* vec, cd* V, long long v
 hipError_t coarse_arnoldi(cd* V, int n, long long vq, int j, const CoarseW& src, cd* wtmp, cd* Hcol, int hsize,
                           int nq, hipStream_t st) {
   if (j < 0 || j + 1 > kMaxCoarse) return hipErrorInvalidValue;
-  if (j < kFastV && n <= 1024)
-    hipLaunchKernelGGL((coarse_arnoldi_fast_kernel<1, 1024>), dim3(nq), dim3(1024), 0, st, V, n, vq, j, src, Hcol,
+  if (j < kFastV && n <= 2 * 512)
+    hipLaunchKernelGGL((coarse_arnoldi_fast_kernel<2, 512>), dim3(nq), dim3(512), 0, st, V, n, vq, j, src, Hcol,
                        hsize);
-  else if (j < kFastV && n <= 2 * 1024)
-    hipLaunchKernelGGL((coarse_arnoldi_fast_kernel<2, 1024>), dim3(nq), dim3(1024), 0, st, V, n, vq, j, src, Hcol,
+  else if (j < kFastV && n <= 4 * 512)
+    hipLaunchKernelGGL((coarse_arnoldi_fast_kernel<4, 512>), dim3(nq), dim3(512), 0, st, V, n, vq, j, src, Hcol,
                        hsize);
   else if (j < kFastV && n <= 4 * 256)
     hipLaunchKernelGGL((coarse_arnoldi_fast_kernel<4, 256>), dim3(nq), dim3(256), 0, st, V, n, vq, j, src, Hcol,
