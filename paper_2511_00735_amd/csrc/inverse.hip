@@ -207,6 +207,213 @@ __global__ __launch_bounds__(kPanelThreads) void gj_panel_kernel(const T* A, int
   for (int idx = tid; idx < kb * kb; idx += nt) Db[idx] = S[idx];
 }
 
+// Lane l's complex value broadcast to the wavefront (l uniform).
+__device__ inline cd readlane_c(cd v, int l) {
+  const long long x = __double_as_longlong(v.x), y = __double_as_longlong(v.y);
+  const unsigned x0 = (unsigned)__builtin_amdgcn_readlane((int)x, l);
+  const unsigned x1 = (unsigned)__builtin_amdgcn_readlane((int)(x >> 32), l);
+  const unsigned y0 = (unsigned)__builtin_amdgcn_readlane((int)y, l);
+  const unsigned y1 = (unsigned)__builtin_amdgcn_readlane((int)(y >> 32), l);
+  return cmk(__longlong_as_double((long long)(((unsigned long long)x1 << 32) | x0)),
+             __longlong_as_double((long long)(((unsigned long long)y1 << 32) | y0)));
+}
+__device__ inline cf readlane_c(cf v, int l) {
+  return cmkf(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.x), l)),
+              __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.y), l)));
+}
+
+// Called by the one wave holding the next panel column (column U of this
+// wave's registers, rows t*64 + lane): publishes the column, picks its pivot
+// among the unused rows, stores the pivot key and 1/pivot.
+template <int U, class T, int CH, int CPW>
+__device__ inline void panel_publish(const T (&x)[CH][CPW], unsigned used, int rows, T* cbn,
+                                     unsigned long long* key_out, T* inv_out) {
+  const int lane = threadIdx.x & 63;
+  unsigned long long best = 0;
+#pragma unroll
+  for (int t = 0; t < CH; ++t) {
+    const int r = t * 64 + lane;
+    if (r < rows) {
+      cbn[r] = x[t][U];
+      if (!((used >> t) & 1u)) best = max(best, pivot_key(cabs2(x[t][U]), r));
+    }
+  }
+  best = wave_max_key(best);
+  const int pn = min(max(pivot_row(best), 0), rows - 1);
+  T dn = cx<T>::make(0.0, 0.0);
+#pragma unroll
+  for (int t = 0; t < CH; ++t)
+    if (t == (pn >> 6)) dn = readlane_c(x[t][U], pn & 63);
+  if (lane == 0) {
+    *key_out = best;
+    *inv_out = ((best >> 32) <= 1u) ? cx<T>::make(0.0, 0.0) : crecip(dn);
+  }
+}
+
+// gj_panel with the panel in registers (1024 threads; rows <= 64 CH, kb <= 16
+// CPW): wave w holds panel columns j = w + 16u, lane the rows t*64 + lane.
+// Pivot rows stay where they are (marked used) during the panel LU, so a column
+// step takes one barrier: the wave holding the next column publishes it with
+// its pivot key and reciprocal, every wave reads the pivot row of its own
+// columns by lane broadcasts.  Only the pivot order is kept.  The row order of
+// the step: pivot rows first, the non-pivot rows among the first kb moved into
+// the slots the later pivot rows leave.  Dinv = (pivot block)^-1 then comes
+// from a Gauss-Jordan of the original pivot rows in pivot order (no further
+// pivoting), one entry per thread, one barrier per step.  Same outputs as
+// gj_panel_kernel.
+template <class T, int CH, int CPW>
+__global__ __launch_bounds__(1024) void gj_panel_reg_kernel(const T* A, int m, int lda, long long bstride, int k0,
+                                                             int kb, const int* rho_prev, int* rho, int* rowmap,
+                                                             T* dinv, int* flag) {
+  constexpr int NW = 16;
+  __shared__ T colbuf[2][64 * CH];
+  __shared__ unsigned long long kw_s[2];
+  __shared__ T pinv_s[2];
+  __shared__ int piv_s[kNB], dsrc_s[kNB];
+  const int rows = m - k0;
+  const T* Ab = A + (long long)blockIdx.x * bstride;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  T x[CH][CPW];
+#pragma unroll
+  for (int u = 0; u < CPW; ++u) {
+    const int j = wave + NW * u;
+#pragma unroll
+    for (int t = 0; t < CH; ++t) {
+      const int r = t * 64 + lane;
+      x[t][u] = (j < kb && r < rows) ? Ab[(long long)(k0 + j) * lda + k0 + r] : cx<T>::make(0.0, 0.0);
+    }
+  }
+  if (wave == 0) panel_publish<0>(x, 0u, rows, colbuf[0], kw_s, pinv_s);
+  __syncthreads();
+  unsigned used = 0;  // bit t: row t*64 + lane is a pivot row
+#pragma unroll 1
+  for (int c = 0; c < kb; ++c) {
+    const int b = c & 1;
+    const unsigned long long kk = kw_s[b];
+    const T inv = pinv_s[b];
+    const int pr = min(max(pivot_row(kk), 0), rows - 1);
+    const int tp = pr >> 6, lp = pr & 63;
+    if (lane == lp) used |= 1u << tp;
+    if (tid == 0) {
+      piv_s[c] = pr;
+      if ((kk >> 32) <= 1u) atomicOr(flag, 2);
+    }
+    T pv[CPW];
+#pragma unroll
+    for (int u = 0; u < CPW; ++u) pv[u] = cx<T>::make(0.0, 0.0);
+#pragma unroll
+    for (int t = 0; t < CH; ++t) {
+      if (t == tp) {
+#pragma unroll
+        for (int u = 0; u < CPW; ++u) {
+          const int j = wave + NW * u;
+          if (j > c && j < kb) pv[u] = readlane_c(x[t][u], lp);
+        }
+      }
+    }
+    // the wave holding column c + 1 publishes it (during the update) with its
+    // pivot and 1/pivot
+    const int cn = c + 1;
+    const bool own = cn < kb && wave == (cn % NW);
+    const int un = cn / NW;
+    T* cbn = colbuf[b ^ 1];
+    unsigned long long best = 0;
+#pragma unroll
+    for (int t = 0; t < CH; ++t) {
+      const int r = t * 64 + lane;
+      const bool act = r < rows && !((used >> t) & 1u);
+      const T l = act ? cmul(colbuf[b][r], inv) : cx<T>::make(0.0, 0.0);
+#pragma unroll
+      for (int u = 0; u < CPW; ++u) x[t][u] = csub(x[t][u], cmul(l, pv[u]));  // finished columns: pv = 0
+      if (own && r < rows) {
+        const T vn = (CPW == 1 || un == 0) ? x[t][0] : x[t][CPW - 1];
+        cbn[r] = vn;
+        if (act) best = max(best, pivot_key(cabs2(vn), r));
+      }
+    }
+    if (own) {
+      best = wave_max_key(best);
+      const T dn = cbn[min(max(pivot_row(best), 0), rows - 1)];
+      if (lane == 0) {
+        kw_s[b ^ 1] = best;
+        pinv_s[b ^ 1] = ((best >> 32) <= 1u) ? cx<T>::make(0.0, 0.0) : crecip(dn);
+      }
+    }
+    if (c == kb - 1 && wave == 0) {
+      // pair the pivot rows beyond the first kb with the non-pivot rows among
+      // the first kb: those rows take the pivot rows' slots
+      bool isp = false;
+      if (lane < kb)
+        for (int q = 0; q < kb; ++q) isp |= (piv_s[q] == lane);
+      const unsigned long long nonpiv = __ballot(lane < kb && !isp);
+      const int y = lane < kb ? piv_s[lane] : 0;
+      const bool far = lane < kb && y >= kb;
+      const unsigned long long farm = __ballot(far);
+      if (lane < kb) {
+        int xsrc = -1;
+        if (far) {
+          const int rank = __popcll(farm & ((1ull << lane) - 1ull));
+          unsigned long long mm = nonpiv;
+          for (int k = 0; k < rank; ++k) mm &= mm - 1ull;
+          xsrc = __ffsll((long long)mm) - 1;
+        }
+        dsrc_s[lane] = xsrc;
+      }
+    }
+    __syncthreads();
+  }
+  // the step's row order: rm[i] (new row i holds old row rm[i])
+  int* rm = rowmap + (long long)blockIdx.x * m;
+  int* ro = rho + (long long)blockIdx.x * m;
+  const int* rp = rho_prev ? rho_prev + (long long)blockIdx.x * m : nullptr;
+  for (int i = tid; i < m; i += 1024) {
+    int src = i;
+    if (i >= k0) {
+      const int r = i - k0;
+      int pr = r;
+      if (r < kb) {
+        pr = piv_s[r];
+      } else {
+        for (int q = 0; q < kb; ++q)
+          if (piv_s[q] == r) pr = dsrc_s[q];
+      }
+      src = k0 + pr;
+    }
+    rm[i] = src;
+    ro[i] = rp ? rp[src] : src;
+  }
+  // Dinv: Gauss-Jordan of S = A[k0 + piv, k0 : k0 + kb], thread (i, j) = (tid % 32, tid / 32)
+  const int gi = tid & 31, gj = tid >> 5;
+  const bool live = gi < kb && gj < kb;
+  T sv = live ? Ab[(long long)(k0 + gj) * lda + k0 + piv_s[gi]] : cx<T>::make(0.0, 0.0);
+  T* colS = colbuf[0];   // [2][32]: column k of S
+  __syncthreads();       // piv_s reads done with the panel buffers
+  if (gj == 0) colS[gi] = sv;
+  if (tid == 0) pinv_s[0] = crecip(sv);
+  __syncthreads();
+#pragma unroll 1
+  for (int k = 0; k < kb; ++k) {
+    const int b = k & 1;
+    const T inv = pinv_s[b];
+    // pivot row entry of this thread's column: thread (k, gj) = lane k or 32 + k of this wave
+    const T r0 = readlane_c(sv, k), r1 = readlane_c(sv, 32 + k);
+    const T rk = (lane < 32) ? r0 : r1;
+    const T ci = colbuf[b][gi];
+    T v;
+    if (gi == k) v = (gj == k) ? inv : cmul(rk, inv);
+    else if (gj == k) v = csub(cx<T>::make(0.0, 0.0), cmul(ci, inv));
+    else v = csub(sv, cmul(cmul(ci, inv), rk));
+    sv = live ? v : cx<T>::make(0.0, 0.0);
+    if (gj == k + 1 && k + 1 < kb) {
+      colbuf[b ^ 1][gi] = sv;
+      if (gi == k + 1) pinv_s[b ^ 1] = crecip(sv);
+    }
+    __syncthreads();
+  }
+  T* Db = dinv + (long long)blockIdx.x * kNB * kNB;
+  if (live) Db[gj * kb + gi] = sv;
+}
+
 // Step 2 of a block column: out-of-place update of the whole matrix, 64 x 64
 // tiles, 256 threads, each thread 4 x 4 outputs (rows i0 + tx + 16u, columns
 // j0 + ty + 16v), rows read through rowmap, P = C = [k0, k0+kb):
@@ -348,14 +555,26 @@ hipError_t inverse_blocked(T* A, int m, int lda, long long bstride, int batch, v
   int ldn = m;
   long long ns = (long long)m * m;
   const int tiles = (m + 63) / 64;
-  const int steps = (m + nbw - 1) / nbw;
+  // register panels: rows <= 512 with 32 columns, FP64 rows <= 1024 with 16
+  // columns; larger matrices keep the LDS panel
+  const int reg = m <= 512 ? 1 : (m <= 1024 && sizeof(T) == sizeof(cd) ? 2 : 0);
+  const int nb = reg == 1 ? kNB : (reg == 2 ? kNB / 2 : nbw);
+  static_assert(kNB == 32, "register panels hold 32 (16 x 2) columns");
+  const int steps = (m + nb - 1) / nb;
   for (int s_ = 0; s_ < steps; ++s_) {
-    const int k0 = s_ * nbw;
-    const int kb = std::min(nbw, m - k0);
+    const int k0 = s_ * nb;
+    const int kb = std::min(nb, m - k0);
     const int* rho_prev = s_ ? s.rho[(s_ - 1) & 1] : nullptr;
     int* rho = s.rho[s_ & 1];
-    hipLaunchKernelGGL(gj_panel_kernel<T>, dim3(batch), dim3(kPanelThreads), panel_lds_bytes<T>(m - k0, kb), st,
-                       cur, m, ldc, cs, k0, kb, rho_prev, rho, s.rowmap, s.dinv, flag);
+    if (reg == 1)
+      hipLaunchKernelGGL((gj_panel_reg_kernel<T, 8, 2>), dim3(batch), dim3(1024), 0, st, cur, m, ldc, cs, k0, kb,
+                         rho_prev, rho, s.rowmap, s.dinv, flag);
+    else if (reg == 2)
+      hipLaunchKernelGGL((gj_panel_reg_kernel<T, 16, 1>), dim3(batch), dim3(1024), 0, st, cur, m, ldc, cs, k0,
+                         kb, rho_prev, rho, s.rowmap, s.dinv, flag);
+    else
+      hipLaunchKernelGGL(gj_panel_kernel<T>, dim3(batch), dim3(kPanelThreads), panel_lds_bytes<T>(m - k0, kb), st,
+                         cur, m, ldc, cs, k0, kb, rho_prev, rho, s.rowmap, s.dinv, flag);
     if ((err = hipPeekAtLastError()) != hipSuccess) return err;
     // the last step writes straight into A, columns permuted, when it can
     const bool last_into_A = (s_ == steps - 1) && nxt == A;

@@ -117,6 +117,28 @@ def test_merge_levels(hps, ctx, name, n, N, kappa):
         assert boxes == 2 * v.pairs
 
 
+def test_large_pair_inverse_property(hps, ctx):
+    """Full-size A^-1 of the two top merge levels (m = 288 and 576: register
+    panels of 32 and 16 columns) against A formed from the GPU machine maps:
+    A A^-1 = I."""
+    from oracle import merge as omerge
+    n, N = 64, 10
+    print("[merge] n64_N10 top inverses", flush=True)
+    prob = gpu_problem(hps, ctx, n, N, 40.0, _bump, coarse_iters=-1)
+    L = prob.lmax
+    for level in (L - 1, L):
+        Tg = box_maps_by_xy(hps, prob, level)
+        Ai = prob.level_Ainv(level).cpu().numpy()
+        v = prob.level_view(level)
+        assert v.shared_nodes == (288 if level == L - 1 else 576)
+        for j in range(v.pairs):
+            P = hps.morton_box_xy(level, 2 * j)
+            Q = hps.morton_box_xy(level, 2 * j + 1)
+            blk = omerge.pair_blocks(level, N - 1, Tg[P], Tg[Q])
+            m2 = 2 * blk["m"]
+            assert np.abs(blk["A"] @ Ai[j] - np.eye(m2)).max() < 1e-9, (level, j)
+
+
 PRECOND_CASES = [(4, 6, 4, -1), (4, 6, 4, 3), (4, 6, 3, 4), (4, 6, 2, 2),
                  (16, 4, 8, 3),      # 128 pairs at level 1: one-workgroup-per-pair kernels
                  (16, 4, 6, 2)]      # coarse level below the top: level-6 skeleton matvec
