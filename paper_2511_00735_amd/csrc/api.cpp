@@ -443,72 +443,90 @@ hps_status merge_impl(hps_problem* p, int l, const T* Tin, T* Tout) {
     return k;
   };
   const PhysSkip sk_c0 = skip(0, 0, 1, 0), sk_ce = skip(0, 0, 1, e);
-  // Z = [T^P_{a,E1} | T^P_aa T^Q_{b,E2}]
-  HIPCHK(c, zcopy2d(m, e, np, Operand{TP, pstride, b, im_off(lv.a0), lv.E1}, one, Z, zs, m, im_off(0),
-                    im_off(0), st, &sk_c0));
+  // Every block below is written by a GEMM whose C operand (or B operand) is
+  // read in place from the children's box maps, so no block is staged by a
+  // copy: with y = [P.E1; Q.E2] split into its halves,
+  //   Zr       = T^P_aa T^Q_{b,E2}                  (m x e, in Z)
+  //   YQ[:, 1] = W^-1 T^P_{a,E1},  YQ[:, 2] = W^-1 Zr          (f^Q_b of y)
+  //   YP[:, 1] = T^Q_bb YQ[:, 1],  YP[:, 2] = T^Q_bb YQ[:, 2] + T^Q_{b,E2}
+  //   T_new(P.E1, P.E1) = T^P_{E1,a} YP[:, 1] + T^P_{E1,E1}, T_new(P.E1, Q.E2) = T^P_{E1,a} YP[:, 2]
+  //   T_new(Q.E2, P.E1) = T^Q_{E2,b} YQ[:, 1], T_new(Q.E2, Q.E2) = T^Q_{E2,b} YQ[:, 2] + T^Q_{E2,E2}
+  // (X = A^-1 B: rows [0, m) YQ, rows [m, 2m) YP.)
   {
     GemmArgs g{};
     g.M = m; g.N = e; g.K = m; g.batch = np;
     g.A = Operand{TP, pstride, b, im_off(lv.a0), im_off(lv.a0)};
     g.B = Operand{TQ, pstride, b, im_off(lv.b0), lv.E2};
     g.alpha = one; g.beta = zero; g.C = none;
-    g.D = Z; g.Dstride = zs; g.ldd = m; g.dr = im_off(0); g.dc = im_off(e);
+    g.D = Z; g.Dstride = zs; g.ldd = m; g.dr = im_off(0); g.dc = im_off(0);
     g.skip = sk_ce;
     HIPCHK(c, zgemm(g, st));
   }
-  // X = A^-1 B: rows [0, m) YQ = W^-1 Z (f^Q_b as a function of y), rows
-  // [m, 2m) YP = T^Q_bb YQ + [0 | T^Q_{b,E2}] (f^P_a)
   T* X = at<T>(p, lv.X_off);
   const long long xs = (long long)m2 * 2 * e;
   T* YQ = X;
   T* YP = X + m;
   {
     GemmArgs g{};
-    g.M = m; g.N = 2 * e; g.K = m; g.batch = np;
+    g.M = m; g.N = e; g.K = m; g.batch = np;
     g.A = Operand{A11, as, m2, im_off(0), im_off(0)};
-    g.B = Operand{Z, zs, m, im_off(0), im_off(0)};
     g.alpha = one; g.beta = zero; g.C = none;
-    g.D = YQ; g.Dstride = xs; g.ldd = m2; g.dr = im_off(0); g.dc = im_off(0);
+    g.D = YQ; g.Dstride = xs; g.ldd = m2; g.dr = im_off(0);
+    g.B = Operand{TP, pstride, b, im_off(lv.a0), lv.E1};
+    g.dc = im_off(0);
     g.skip = sk_c0;
     HIPCHK(c, zgemm(g, st));
+    g.B = Operand{Z, zs, m, im_off(0), im_off(0)};
+    g.dc = im_off(e);
+    g.skip = sk_ce;
+    HIPCHK(c, zgemm(g, st));
   }
-  HIPCHK(c, zcopy2d(m, e, np, none, one, YP, xs, m2, im_off(0), im_off(0), st, &sk_c0));
-  HIPCHK(c, zcopy2d(m, e, np, Operand{TQ, pstride, b, im_off(lv.b0), lv.E2}, one, YP, xs, m2, im_off(0),
-                    im_off(e), st, &sk_ce));
   {
     GemmArgs g{};
-    g.M = m; g.N = 2 * e; g.K = m; g.batch = np;
+    g.M = m; g.N = e; g.K = m; g.batch = np;
     g.A = Operand{TQ, pstride, b, im_off(lv.b0), im_off(lv.b0)};
+    g.alpha = one;
+    g.D = YP; g.Dstride = xs; g.ldd = m2; g.dr = im_off(0);
     g.B = Operand{YQ, xs, m2, im_off(0), im_off(0)};
-    g.alpha = one; g.beta = one; g.C = Operand{YP, xs, m2, im_off(0), im_off(0)};
-    g.D = YP; g.Dstride = xs; g.ldd = m2; g.dr = im_off(0); g.dc = im_off(0);
+    g.beta = zero; g.C = none; g.dc = im_off(0);
     g.skip = sk_c0;
     HIPCHK(c, zgemm(g, st));
+    g.B = Operand{YQ, xs, m2, im_off(0), im_off(e)};
+    g.beta = one; g.C = Operand{TQ, pstride, b, im_off(lv.b0), lv.E2}; g.dc = im_off(e);
+    g.skip = sk_ce;
+    HIPCHK(c, zgemm(g, st));
   }
-  // T_new = blkdiag(T^P_E1E1, T^Q_E2E2) + [T^P_{E1,a} YP ; T^Q_{E2,b} YQ], scattered
   T* Tn = Tout;
   const int bn = nx.g.b;
   const long long ns = (long long)bn * bn;
   const IdxMap rowP = im_tab(mp), rowQ = im_tab(mp + e), colP = im_tab(mp), colQ = im_tab(mp + e);
   const PhysSkip s00 = skip(1, 0, 1, 0), s0e = skip(1, 0, 1, e), se0 = skip(1, e, 1, 0), see = skip(1, e, 1, e);
-  HIPCHK(c, zcopy2d(e, e, np, Operand{TP, pstride, b, lv.E1, lv.E1}, one, Tn, ns, bn, rowP, colP, st, &s00));
-  HIPCHK(c, zcopy2d(e, e, np, none, one, Tn, ns, bn, rowP, colQ, st, &s0e));
-  HIPCHK(c, zcopy2d(e, e, np, none, one, Tn, ns, bn, rowQ, colP, st, &se0));
-  HIPCHK(c, zcopy2d(e, e, np, Operand{TQ, pstride, b, lv.E2, lv.E2}, one, Tn, ns, bn, rowQ, colQ, st, &see));
   {
     GemmArgs g{};
-    g.M = e; g.N = 2 * e; g.K = m; g.batch = np;
+    g.M = e; g.N = e; g.K = m; g.batch = np;
+    g.alpha = one;
+    g.D = Tn; g.Dstride = ns; g.ldd = bn;
+    // rows P.E1
     g.A = Operand{TP, pstride, b, lv.E1, im_off(lv.a0)};
+    g.dr = rowP;
     g.B = Operand{YP, xs, m2, im_off(0), im_off(0)};
-    g.alpha = one; g.beta = one; g.C = Operand{Tn, ns, bn, rowP, im_tab(mp)};
-    g.D = Tn; g.Dstride = ns; g.ldd = bn; g.dr = rowP; g.dc = im_tab(mp);
+    g.beta = one; g.C = Operand{TP, pstride, b, lv.E1, lv.E1}; g.dc = colP;
     g.skip = s00;
     HIPCHK(c, zgemm(g, st));
+    g.B = Operand{YP, xs, m2, im_off(0), im_off(e)};
+    g.beta = zero; g.C = none; g.dc = colQ;
+    g.skip = s0e;
+    HIPCHK(c, zgemm(g, st));
+    // rows Q.E2
     g.A = Operand{TQ, pstride, b, lv.E2, im_off(lv.b0)};
-    g.B = Operand{YQ, xs, m2, im_off(0), im_off(0)};
-    g.C = Operand{Tn, ns, bn, rowQ, im_tab(mp)};
     g.dr = rowQ;
+    g.B = Operand{YQ, xs, m2, im_off(0), im_off(0)};
+    g.beta = zero; g.C = none; g.dc = colP;
     g.skip = se0;
+    HIPCHK(c, zgemm(g, st));
+    g.B = Operand{YQ, xs, m2, im_off(0), im_off(e)};
+    g.beta = one; g.C = Operand{TQ, pstride, b, lv.E2, lv.E2}; g.dc = colQ;
+    g.skip = see;
     HIPCHK(c, zgemm(g, st));
   }
   return HPS_OK;
