@@ -98,12 +98,12 @@ __global__ void gemv_reduce_kernel(GemvBatchT<Mt> gb, const cd* partial) {
 
 // ---- one workgroup per pair: a whole V-cycle level ---------------------------
 // y[i] = (y0 ? y0[i] : 0) + sum_k A(rm(i), cm(k)) x[k]; x, y0, y in LDS.
-template <class Mt>
+template <class Mt, int NT>
 __device__ void wg_gemv(const Mt* A, int ld, IdxMap rm, IdxMap cm, int M, int K, const cd* x,
                         const cd* y0, cd* y, cd* red) {
   const int t = threadIdx.x;
   const int RT = M < kRowsT ? M : kRowsT;
-  const int G = kThreads / RT;
+  const int G = NT / RT;
   const int r = t % RT, g = t / RT;
   constexpr int U = 8;  // independent loads in flight per thread
   for (int r0 = 0; r0 < M; r0 += RT) {
@@ -135,8 +135,8 @@ __device__ void wg_gemv(const Mt* A, int ld, IdxMap rm, IdxMap cm, int M, int K,
 // Down sweep of one pair: z0 = A^-1 r_x (kept in Z0), then the exterior
 // residual rows across the kept faces receive C~ z0:
 // w[dtab(P.E1)] += T^P_{E1,a} z0_P, w[dtab(Q.E2)] += T^Q_{E2,b} z0_Q.
-template <class Mt>
-__global__ __launch_bounds__(kThreads) void vc_down_small_kernel(SmallLevelT<Mt> a, cd* vec) {
+template <class Mt, int NT>
+__global__ __launch_bounds__(NT) void vc_down_small_kernel(SmallLevelT<Mt> a, cd* vec) {
   extern __shared__ cd sm[];
   const int m = a.m, e = a.e, m2 = 2 * m;
   cd* r = sm;
@@ -149,26 +149,26 @@ __global__ __launch_bounds__(kThreads) void vc_down_small_kernel(SmallLevelT<Mt>
   const Mt* TQ = TP + bb;
   const int* xt = a.xtab + (long long)j * m2;
   const int* dt = a.dtab + (long long)j * 2 * e;
-  for (int i = t; i < m2; i += kThreads) r[i] = vec[xt[i]];
+  for (int i = t; i < m2; i += NT) r[i] = vec[xt[i]];
   __syncthreads();
-  wg_gemv(a.Ainv + (long long)j * m2 * m2, m2, im_off(0), im_off(0), m2, m2, r, nullptr, z0, red);
-  for (int i = t; i < m2; i += kThreads) a.Z0[(long long)j * m2 + i] = z0[i];
-  wg_gemv(TP, a.g.b, a.E1, im_off(a.a0), e, m, z0 + m, nullptr, dd, red);
-  for (int i = t; i < e; i += kThreads) {
+  wg_gemv<Mt, NT>(a.Ainv + (long long)j * m2 * m2, m2, im_off(0), im_off(0), m2, m2, r, nullptr, z0, red);
+  for (int i = t; i < m2; i += NT) a.Z0[(long long)j * m2 + i] = z0[i];
+  wg_gemv<Mt, NT>(TP, a.g.b, a.E1, im_off(a.a0), e, m, z0 + m, nullptr, dd, red);
+  for (int i = t; i < e; i += NT) {
     const int s = dt[i];
     if (s >= 0) vec[s] = cadd(vec[s], dd[i]);
   }
   __syncthreads();
-  wg_gemv(TQ, a.g.b, a.E2, im_off(a.b0), e, m, z0, nullptr, dd, red);
-  for (int i = t; i < e; i += kThreads) {
+  wg_gemv<Mt, NT>(TQ, a.g.b, a.E2, im_off(a.b0), e, m, z0, nullptr, dd, red);
+  for (int i = t; i < e; i += NT) {
     const int s = dt[e + i];
     if (s >= 0) vec[s] = cadd(vec[s], dd[i]);
   }
 }
 
 // Up sweep of one pair: x = z0 + X y with y the kept-face values of z.
-template <class Mt>
-__global__ __launch_bounds__(kThreads) void vc_up_small_kernel(SmallLevelT<Mt> a, cd* z) {
+template <class Mt, int NT>
+__global__ __launch_bounds__(NT) void vc_up_small_kernel(SmallLevelT<Mt> a, cd* z) {
   extern __shared__ cd sm[];
   const int m = a.m, e = a.e, m2 = 2 * m, e2 = 2 * e;
   cd* y = sm;
@@ -178,14 +178,14 @@ __global__ __launch_bounds__(kThreads) void vc_up_small_kernel(SmallLevelT<Mt> a
   const int j = blockIdx.x, t = threadIdx.x;
   const int* yt = a.ytab + (long long)j * e2;
   const int* xt = a.xtab + (long long)j * m2;
-  for (int i = t; i < e2; i += kThreads) {
+  for (int i = t; i < e2; i += NT) {
     const int s = yt[i];
     y[i] = s >= 0 ? z[s] : cmk(0.0, 0.0);
   }
-  for (int i = t; i < m2; i += kThreads) z0[i] = a.Z0[(long long)j * m2 + i];
+  for (int i = t; i < m2; i += NT) z0[i] = a.Z0[(long long)j * m2 + i];
   __syncthreads();
-  wg_gemv(a.X + (long long)j * m2 * e2, m2, im_off(0), im_off(0), m2, e2, y, z0, x, red);
-  for (int i = t; i < m2; i += kThreads) z[xt[i]] = x[i];
+  wg_gemv<Mt, NT>(a.X + (long long)j * m2 * e2, m2, im_off(0), im_off(0), m2, e2, y, z0, x, red);
+  for (int i = t; i < m2; i += NT) z[xt[i]] = x[i];
 }
 
 }  // namespace
@@ -250,26 +250,41 @@ hipError_t zgemv_partials(const GemvDescT<Mt>* d, int nd, int batch, cd* partial
   return hipPeekAtLastError();
 }
 
+// Threads per pair: 1024 when the level has at most 512 pairs (larger matrices,
+// fewer workgroups: more loads in flight per pair), 256 otherwise.
+constexpr int kSmallWide = 1024;
+inline bool small_wide(int pairs) { return pairs <= 512; }
+
 size_t small_level_lds(int m, int e) {
-  return sizeof(cd) * (size_t)(std::max(4 * m + e, 2 * e + 4 * m) + kThreads);
+  return sizeof(cd) * (size_t)(std::max(4 * m + e, 2 * e + 4 * m) + kSmallWide);
+}
+
+template <class Mt, int NT>
+hipError_t launch_down(const SmallLevelT<Mt>& a, int pairs, cd* vec, hipStream_t st) {
+  const size_t lds = small_level_lds(a.m, a.e);
+  hipError_t err = allow_lds(vc_down_small_kernel<Mt, NT>, lds);
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL((vc_down_small_kernel<Mt, NT>), dim3(pairs), dim3(NT), lds, st, a, vec);
+  return hipPeekAtLastError();
+}
+
+template <class Mt, int NT>
+hipError_t launch_up(const SmallLevelT<Mt>& a, int pairs, cd* z, hipStream_t st) {
+  const size_t lds = small_level_lds(a.m, a.e);
+  hipError_t err = allow_lds(vc_up_small_kernel<Mt, NT>, lds);
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL((vc_up_small_kernel<Mt, NT>), dim3(pairs), dim3(NT), lds, st, a, z);
+  return hipPeekAtLastError();
 }
 
 template <class Mt>
 hipError_t vc_down_small(const SmallLevelT<Mt>& a, int pairs, cd* vec, hipStream_t st) {
-  const size_t lds = small_level_lds(a.m, a.e);
-  hipError_t err = allow_lds(vc_down_small_kernel<Mt>, lds);
-  if (err != hipSuccess) return err;
-  hipLaunchKernelGGL(vc_down_small_kernel<Mt>, dim3(pairs), dim3(kThreads), lds, st, a, vec);
-  return hipPeekAtLastError();
+  return small_wide(pairs) ? launch_down<Mt, kSmallWide>(a, pairs, vec, st) : launch_down<Mt, kThreads>(a, pairs, vec, st);
 }
 
 template <class Mt>
 hipError_t vc_up_small(const SmallLevelT<Mt>& a, int pairs, cd* z, hipStream_t st) {
-  const size_t lds = small_level_lds(a.m, a.e);
-  hipError_t err = allow_lds(vc_up_small_kernel<Mt>, lds);
-  if (err != hipSuccess) return err;
-  hipLaunchKernelGGL(vc_up_small_kernel<Mt>, dim3(pairs), dim3(kThreads), lds, st, a, z);
-  return hipPeekAtLastError();
+  return small_wide(pairs) ? launch_up<Mt, kSmallWide>(a, pairs, z, st) : launch_up<Mt, kThreads>(a, pairs, z, st);
 }
 
 template hipError_t zgemv_batched<cd>(const GemvDescT<cd>*, int, int, cd*, hipStream_t);
