@@ -16,6 +16,10 @@
 // about 1/7 of its flops and in real arithmetic.
 //
 // The reduction is a right-looking blocked LU with panels of kNB columns:
+//  * K is never assembled in memory: the first panel, its U12 rows and its
+//    trailing update evaluate K's entries (a few dozen nonzeros per row) from
+//    their definition, and that first trailing update is the matrix's first
+//    write to global memory;
 //  * the panel (all remaining rows x kNB columns) sits in registers, each wave
 //    holding every fourth column; pivot rows are left where they are during
 //    the panel and only marked as used, so a column step needs one barrier:
@@ -73,27 +77,69 @@ __host__ __device__ inline size_t elem_stride(const Dims& d) {
   return ((size_t)d.nloc * d.ncol + 31) & ~(size_t)31;
 }
 
-// Bordered real matrix K of one element, column-major (ld n_loc):
-// rows/cols: interior (i,j) -> (i-1)*p + (j-1); boundary l_k, r_k, b_k, t_k ->
-// pp + side*p + (k-1); extra columns nloc, nloc+1 = Re/Im of bt.
-// Written as a zero fill followed by the nonzeros: an interior row couples to
-// the 2p-1 interior nodes on its grid lines, four boundary nodes and the two
-// source columns; a normal-derivative row to p interior and two boundary nodes.
-__device__ void assemble(const Dims& d, double* A, const double* D, const double* w, const double* Kr,
-                         const double* bnode, const double* snode, double kappa, double h) {
-  const int tid = threadIdx.x;
-  const int N = d.N, p = d.p, pp = d.pp, N1 = N + 1, nloc = d.nloc;
-  const size_t total = (size_t)nloc * d.ncol;
-  double2* A2 = reinterpret_cast<double2*>(A);
-  for (size_t i = tid; i < (total + 1) / 2; i += kThreads) A2[i] = make_double2(0.0, 0.0);
-  __syncthreads();
-  const double f = 2.0 / h;
-  const double hh = 0.25 * h * h;
-  const int si = 2 * p + 5, sb = p + 2;
-  const int items = pp * si + 4 * p * sb;
-  for (int it = tid; it < items; it += kThreads) {
-    int r, c;
-    double v;
+// Entry (r, c) of the bordered real matrix K of one element, evaluated from its
+// definition: rows/cols interior (i,j) -> (i-1)*p + (j-1); boundary l_k, r_k,
+// b_k, t_k -> pp + side*p + (k-1); extra columns nloc, nloc+1 = Re/Im of bt.
+// An interior row couples to the 2p-1 interior nodes on its grid lines, four
+// boundary nodes and the two source columns; a normal-derivative row to p
+// interior and two boundary nodes.  The first panel of the partial LU reads K
+// this way, so the matrix is never stored before its first trailing update.
+struct ElemK {
+  int N, p, pp, nloc;
+  const double* D;      // (N+1)^2 reference differentiation matrix
+  const double* w;      // N+1 GLL weights
+  const double* Kr;     // (N+1)^2 reference stiffness
+  const double* bnode;  // (N+1)^2 coefficient b at the element's nodes
+  const double* snode;  // complex (N+1)^2 source at the nodes, or null
+  double kappa, h;
+
+  __device__ double operator()(int r, int c) const {
+    const int N1 = N + 1;
+    if (r < pp) {
+      const int i = r / p + 1, j = r - (i - 1) * p + 1;
+      if (c >= nloc) {
+        if (!snode) return 0.0;
+        return 0.25 * h * h * w[i] * w[j] * snode[2 * (i * N1 + j) + (c - nloc)];
+      }
+      if (c < pp) {
+        const int i2 = c / p + 1, j2 = c - (i2 - 1) * p + 1;
+        double v = 0.0;
+        if (j == j2) v += Kr[i * N1 + i2] * w[j];
+        if (i == i2) v += w[i] * Kr[j * N1 + j2];
+        if (i == i2 && j == j2) v -= 0.25 * h * h * kappa * kappa * (1.0 - bnode[i * N1 + j]) * w[i] * w[j];
+        return v;
+      }
+      const int s = (c - pp) / p, k = c - pp - s * p + 1;
+      if (s == 0) return (j == k) ? Kr[i * N1 + 0] * w[j] : 0.0;
+      if (s == 1) return (j == k) ? Kr[i * N1 + N] * w[j] : 0.0;
+      if (s == 2) return (i == k) ? w[i] * Kr[j * N1 + 0] : 0.0;
+      return (i == k) ? w[i] * Kr[j * N1 + N] : 0.0;
+    }
+    if (c >= nloc) return 0.0;
+    // normal-derivative row of boundary node (side s, index k)
+    const int s = (r - pp) / p, k = r - pp - s * p + 1;
+    const bool lo = (s == 0 || s == 2);
+    const double sg = lo ? -2.0 / h : 2.0 / h;  // outward normal sign
+    const int dr = lo ? 0 : N;                   // D row of the boundary node
+    if (c < pp) {
+      const int i2 = c / p + 1, j2 = c - (i2 - 1) * p + 1;
+      if (s < 2) return (j2 == k) ? sg * D[dr * N1 + i2] : 0.0;   // x-derivative along line j = k
+      return (i2 == k) ? sg * D[dr * N1 + j2] : 0.0;              // y-derivative along line i = k
+    }
+    const int s2 = (c - pp) / p, k2 = c - pp - s2 * p + 1;
+    if (k2 != k) return 0.0;
+    if (s < 2) return s2 == 0 ? sg * D[dr * N1 + 0] : (s2 == 1 ? sg * D[dr * N1 + N] : 0.0);
+    return s2 == 2 ? sg * D[dr * N1 + 0] : (s2 == 3 ? sg * D[dr * N1 + N] : 0.0);
+  }
+
+  // The nonzeros of K one by one: it < items() enumerates (row, slot) pairs,
+  // 2p+5 slots per interior row (its x-line with the diagonal, its y-line, four
+  // boundary nodes, two source columns) and p+2 per boundary row.  False for a
+  // slot that holds no entry (the source columns without a source).
+  __device__ int items() const { return pp * (2 * p + 5) + 4 * p * (p + 2); }
+  __device__ bool item(int it, int& r, int& c, double& v) const {
+    const int N1 = N + 1, si = 2 * p + 5, sb = p + 2;
+    const double hh = 0.25 * h * h;
     if (it < pp * si) {
       r = it / si;
       const int s = it - r * si;
@@ -102,10 +148,7 @@ __device__ void assemble(const Dims& d, double* A, const double* D, const double
         const int i2 = s + 1;
         c = s * p + (j - 1);
         v = Kr[i * N1 + i2] * w[j];
-        if (i2 == i) {
-          const double cc = kappa * kappa * (1.0 - bnode[i * N1 + j]);
-          v += w[i] * Kr[j * N1 + j] - hh * cc * w[i] * w[j];
-        }
+        if (i2 == i) v += w[i] * Kr[j * N1 + j] - hh * kappa * kappa * (1.0 - bnode[i * N1 + j]) * w[i] * w[j];
       } else if (s < 2 * p - 1) {        // (i, j2), j2 != j: y-line
         const int jj = s - p + 1;
         const int j2 = jj + (jj >= j ? 1 : 0);
@@ -113,37 +156,35 @@ __device__ void assemble(const Dims& d, double* A, const double* D, const double
         v = w[i] * Kr[j * N1 + j2];
       } else if (s < 2 * p + 3) {        // boundary nodes l_j, r_j, b_i, t_i
         const int side = s - (2 * p - 1);
-        if (side == 0) { c = pp + (j - 1);         v = Kr[i * N1 + 0] * w[j]; }
+        if (side == 0) { c = pp + (j - 1); v = Kr[i * N1 + 0] * w[j]; }
         else if (side == 1) { c = pp + p + (j - 1); v = Kr[i * N1 + N] * w[j]; }
         else if (side == 2) { c = pp + 2 * p + (i - 1); v = w[i] * Kr[j * N1 + 0]; }
-        else { c = pp + 3 * p + (i - 1);             v = w[i] * Kr[j * N1 + N]; }
+        else { c = pp + 3 * p + (i - 1); v = w[i] * Kr[j * N1 + N]; }
       } else {                           // Re / Im of the source term
-        if (!snode) continue;
+        if (!snode) return false;
         const int part = s - (2 * p + 3);
         c = nloc + part;
         v = hh * w[i] * w[j] * snode[2 * (i * N1 + j) + part];
       }
-    } else {
-      const int jt = it - pp * si;
-      const int rb = jt / sb;
-      const int t = jt - rb * sb;
-      const int side = rb / p, k = rb - side * p + 1;
-      r = pp + rb;
-      const bool lo = (side == 0 || side == 2);
-      const double sg = lo ? -f : f;     // outward normal sign
-      const int dr = lo ? 0 : N;         // D row of the boundary node
-      if (t < p) {
-        c = side < 2 ? t * p + (k - 1) : (k - 1) * p + t;
-        v = sg * D[dr * N1 + t + 1];
-      } else {
-        const int s2 = (side < 2 ? 0 : 2) + (t - p);
-        c = pp + s2 * p + (k - 1);
-        v = sg * D[dr * N1 + (t == p ? 0 : N)];
-      }
+      return true;
     }
-    A[(size_t)c * nloc + r] = v;
+    const int jt = it - pp * si;
+    const int rb = jt / sb, t = jt - rb * sb;
+    const int side = rb / p, k = rb - side * p + 1;
+    r = pp + rb;
+    const bool lo = (side == 0 || side == 2);
+    const double sg = lo ? -2.0 / h : 2.0 / h;
+    const int dr = lo ? 0 : N;
+    if (t < p) {
+      c = side < 2 ? t * p + (k - 1) : (k - 1) * p + t;
+      v = sg * D[dr * N1 + t + 1];
+    } else {
+      c = pp + ((side < 2 ? 0 : 2) + (t - p)) * p + (k - 1);
+      v = sg * D[dr * N1 + (t == p ? 0 : N)];
+    }
+    return true;
   }
-}
+};
 
 // Lane l's double broadcast to the whole wavefront (l uniform).
 __device__ inline double readlane_d(double v, int l) {
@@ -307,13 +348,15 @@ __device__ void leaf_cayley(const LeafArgs& a, const Dims& d, const double* A, d
 // LDS doubles shared by the panel's pivot-column exchange and U12 + L11
 __host__ __device__ inline size_t leaf_region_doubles(const Dims& d) {
   const size_t a = (size_t)2 * 64 * kMaxChunks, b = (size_t)kNB * d.ldu + (size_t)kNB * kNB;
-  return a > b ? a : b;
+  const size_t c = (size_t)d.nloc * kNB;   // the first panel's columns of K
+  const size_t ab = a > b ? a : b;
+  return ab > c ? ab : c;
 }
 
 // LDS bytes: the LU phase (panel, U12, row map) and the Cayley phase
 size_t leaf_lds_bytes(int N) {
   const Dims d = dims_of(N);
-  const size_t lu = leaf_region_doubles(d) * sizeof(double) + (size_t)d.nloc * sizeof(int);
+  const size_t lu = leaf_region_doubles(d) * sizeof(double) + 2 * (size_t)d.nloc * sizeof(int);
   const size_t cay = (size_t)(130 + kWaves * 64) * sizeof(cd) + 2 * sizeof(unsigned long long) + 64 * sizeof(int);
   return std::max(lu, cay);
 }
@@ -336,15 +379,15 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_kernel(LeafArgs a) {
   double* L11 = lds + (size_t)kNB * ldu;    // scaled L11, row-major kNB x kNB
   const size_t region = leaf_region_doubles(d);
   int* rowmap = reinterpret_cast<int*>(lds + region);  // trailing slot -> panel row of its L21
+  int* slotof = rowmap + nloc;                         // first panel: row of K -> its trailing slot, or -1
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int G = a.G0 + blockIdx.x;
   const int q = G / a.E, e = G % a.E;
   const int N1 = a.N + 1;
   double* A = a.scratch + (size_t)blockIdx.x * elem_stride(d);
   const double* sq = a.s_nodes[q - a.q0];
-  assemble(d, A, a.D, a.w, a.Kr, a.b_nodes[q - a.q0] + (size_t)e * N1 * N1,
-           sq ? sq + (size_t)e * 2 * N1 * N1 : nullptr, a.kappa[q - a.q0], a.h);
-  __syncthreads();
+  const ElemK K{d.N, d.p, d.pp, nloc, a.D, a.w, a.Kr, a.b_nodes[q - a.q0] + (size_t)e * N1 * N1,
+                sq ? sq + (size_t)e * 2 * N1 * N1 : nullptr, a.kappa[q - a.q0], a.h};
 
   for (int k0 = 0; k0 < npiv; k0 += kNB) {
     const int kb = min(kNB, npiv - k0);
@@ -353,18 +396,31 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_kernel(LeafArgs a) {
     const int c0 = k0 + kb, nc = ncol - c0;
     // the panel in registers: wave w holds columns j = w + kWaves * u, lane the
     // rows t * 64 + lane
+    const bool first = k0 == 0;   // the first panel reads K itself
+    if (first) {
+      // K's first kb columns, evaluated once into the (still free) U12 area
+      for (int idx = tid; idx < rows * kb; idx += kThreads) {
+        const int r = idx % rows, c = idx / rows;
+        U[(size_t)c * nloc + r] = K(r, c);
+      }
+      __syncthreads();
+    }
     double xv[kMaxChunks][kCPW];
 #pragma unroll
     for (int u = 0; u < kCPW; ++u) {
       const int j = wave + kWaves * u;
-      const double* col = A + (size_t)(k0 + j) * nloc + k0;
+      const double* col = first ? U + (size_t)j * nloc : A + (size_t)(k0 + j) * nloc + k0;
 #pragma unroll
       for (int t = 0; t < kMaxChunks; ++t) {
         const int r = t * 64 + lane;
         xv[t][u] = (j < kb && r < rows) ? col[r] : 0.0;
       }
     }
-    for (int r = tid; r < rows; r += kThreads) rowmap[r] = r;
+    if (first) __syncthreads();   // the column exchange below reuses that LDS
+    for (int r = tid; r < rows; r += kThreads) {
+      rowmap[r] = r;
+      slotof[r] = r;
+    }
     if (wave == 0) {
       double v0[kMaxChunks];
 #pragma unroll
@@ -439,6 +495,7 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_kernel(LeafArgs a) {
         const int y = lane < kb ? piv_s[lane] : 0;
         const bool far = lane < kb && y >= kb;
         const unsigned long long farm = __ballot(far);
+        if (lane < kb) slotof[y] = -1;   // pivot rows leave the trailing block
         if (far) {
           const int rank = __popcll(farm & ((1ull << lane) - 1ull));
           unsigned long long mm = nonpiv;
@@ -446,6 +503,7 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_kernel(LeafArgs a) {
           const int x = __ffsll((long long)mm) - 1;
           dsrc_s[lane] = x;
           rowmap[y] = x;
+          slotof[x] = y;
         } else if (lane < kb) {
           dsrc_s[lane] = -1;
         }
@@ -476,7 +534,9 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_kernel(LeafArgs a) {
     // ---- row interchanges on the trailing columns; U12 gathered ----
     for (int idx = tid; idx < kNB * nc; idx += kThreads) {
       const int qq = idx % kNB, cc = idx / kNB;
-      if (qq < kb) {
+      if (qq < kb && first) {
+        U[qq * ldu + cc] = K(piv_s[qq], c0 + cc);   // the trailing update reads K through rowmap
+      } else if (qq < kb) {
         double* col = A + (size_t)(c0 + cc) * nloc + k0;
         const int y = piv_s[qq];
         U[qq * ldu + cc] = col[y];
@@ -524,7 +584,7 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_kernel(LeafArgs a) {
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int cc = cg * 4 + u;
-        nx[u] = (live && cg < CG && cc < nc) ? arow[(size_t)cc * nloc] : 0.0;
+        nx[u] = (live && cg < CG && cc < nc && !first) ? arow[(size_t)cc * nloc] : 0.0;
       }
 #pragma unroll 1
       for (; cg < CG; cg += kWaves) {
@@ -535,7 +595,7 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_kernel(LeafArgs a) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int cc = cn * 4 + u;
-          nx[u] = (live && cn < CG && cc < nc) ? arow[(size_t)cc * nloc] : 0.0;
+          nx[u] = (live && cn < CG && cc < nc && !first) ? arow[(size_t)cc * nloc] : 0.0;
         }
         const double2* Ub = reinterpret_cast<const double2*>(U + cg * 4);
         // four U12 rows at a time keep the register footprint at two waves per SIMD
@@ -566,6 +626,31 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_kernel(LeafArgs a) {
       }
     }
     __syncthreads();
+    if (first) {
+      // the first trailing update started from zero: add K's trailing entries
+      // at their rows' slots (each slot and column is touched once), eight at
+      // a time so that their loads are in flight together
+      const int items = K.items();
+      for (int base = tid; base < items; base += 8 * kThreads) {
+        double* adr[8];
+        double val[8], old[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          int r = 0, c = 0;
+          double v = 0.0;
+          const int it = base + u * kThreads;
+          const bool ok = it < items && K.item(it, r, c, v) && c >= c0 && slotof[r] >= 0;
+          adr[u] = ok ? A + (size_t)c * nloc + slotof[r] : nullptr;
+          val[u] = v;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) old[u] = adr[u] ? *adr[u] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (adr[u]) *adr[u] = old[u] + val[u];
+      }
+      __syncthreads();
+    }
   }
   // the factorisation's LDS is free again: the Cayley step reuses it
   leaf_cayley(a, d, A, lds);
