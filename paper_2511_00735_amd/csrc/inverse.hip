@@ -1,7 +1,7 @@
 // Batched in-place inversion of complex matrices (FP64 or FP32) by
 // Gauss-Jordan elimination with partial pivoting.
 //
-// m <= 64: the whole matrix sits in LDS, one workgroup per matrix.
+// m <= 64: the whole matrix sits in registers, one workgroup per matrix.
 // m  > 64: blocked Gauss-Jordan, two launches per block column C = [k0, k0+nb):
 //   1. gj_panel: partial-pivoting LU of the panel A[k0:m, C] in LDS picks nb
 //      pivot rows (as the row map of this step) and forms Dinv, the inverse of
@@ -15,7 +15,6 @@
 // last update (or a final copy) applies.  Work: m^3 complex multiply-adds in
 // 2 m / nb launches.
 #include "common.h"
-#include "gj_small.h"
 #include "host.h"
 #include "pivot.h"
 
@@ -25,36 +24,6 @@ namespace {
 
 constexpr int kNB = 32;        // widest block column
 constexpr int kPanelThreads = 1024;
-
-template <class T>
-__global__ __launch_bounds__(256) void inv_small_kernel(T* A, int m, int lda, long long bstride,
-                                                        int* flag) {
-  extern __shared__ char smem[];
-  T* S = reinterpret_cast<T*>(smem);
-  __shared__ int ipiv[64];
-  __shared__ T colk[64], rowk[64];
-  __shared__ unsigned long long kw[16];
-  T* Ab = A + (long long)blockIdx.x * bstride;
-  for (int base = 0; base < m * m; base += 4 * 256) {
-    T v[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int idx = base + q * 256 + threadIdx.x;
-      v[q] = idx < m * m ? Ab[(long long)(idx / m) * lda + idx % m] : cx<T>::make(0.0, 0.0);
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int idx = base + q * 256 + threadIdx.x;
-      if (idx < m * m) S[idx] = v[q];
-    }
-  }
-  __syncthreads();
-  gj_inplace_small(S, m, ipiv, colk, rowk, kw, flag);
-  for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
-    const int r = idx % m, c = idx / m;
-    Ab[(long long)c * lda + r] = S[idx];
-  }
-}
 
 // LDS bytes of gj_panel for m - k0 = rows and block width kb.
 template <class T>
@@ -220,6 +189,90 @@ __device__ inline cd readlane_c(cd v, int l) {
 __device__ inline cf readlane_c(cf v, int l) {
   return cmkf(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.x), l)),
               __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.y), l)));
+}
+
+// m <= 64: Gauss-Jordan with the matrix in registers, one workgroup (256
+// threads) per matrix: thread (row i = lane, wave w) holds columns j = w + 4t.
+// Pivot rows stay where they are (marked used); a step reads the pivot row by
+// lane broadcasts and the pivot column from LDS, where the wave holding it
+// published it with the next pivot key and reciprocal, and takes one barrier.
+// With pivot row pr_k at step k the registers end as S[pr_k][j] = A^-1[k][pr_j],
+// written back to A^-1's own positions.
+template <class T>
+__device__ inline void small_publish(T v, bool used, bool row_ok, T* cbn, unsigned long long* key_out,
+                                     T* inv_out) {
+  const int lane = threadIdx.x & 63;
+  cbn[lane] = v;
+  unsigned long long key = (row_ok && !used) ? pivot_key(cabs2(v), lane) : 0ull;
+  key = wave_max_key(key);
+  const T d = readlane_c(v, pivot_row(key) & 63);
+  if (lane == 0) {
+    *key_out = key;
+    *inv_out = ((key >> 32) <= 1u) ? cx<T>::make(0.0, 0.0) : crecip(d);
+  }
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void inv_small_kernel(T* A, int m, int lda, long long bstride, int* flag) {
+  constexpr int kT = 16, NW = 4;
+  __shared__ T colbuf[2][64];
+  __shared__ T pinv[2];
+  __shared__ unsigned long long kw[2];
+  __shared__ int pivs[64];
+  T* Ab = A + (long long)blockIdx.x * bstride;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const bool row_ok = lane < m;
+  T sv[kT];
+#pragma unroll
+  for (int t = 0; t < kT; ++t) {
+    const int j = wave + NW * t;
+    sv[t] = (row_ok && j < m) ? Ab[(long long)j * lda + lane] : cx<T>::make(0.0, 0.0);
+  }
+  if (wave == 0) small_publish(sv[0], false, row_ok, colbuf[0], kw, pinv);
+  __syncthreads();
+  bool used = false;
+  int myk = 0;
+#pragma unroll 1
+  for (int k = 0; k < m; ++k) {
+    const int b = k & 1;
+    const unsigned long long kk = kw[b];
+    const T inv = pinv[b];
+    const int pr = min(max(pivot_row(kk), 0), m - 1);
+    const bool isp = lane == pr;
+    if (isp) { used = true; myk = k; }
+    if (tid == 0) {
+      pivs[k] = pr;
+      if ((kk >> 32) <= 1u) atomicOr(flag, 2);
+    }
+    const T f = isp ? cx<T>::make(0.0, 0.0) : cmul(colbuf[b][lane], inv);
+    const int tk = k / NW, ok = k % NW;
+#pragma unroll
+    for (int t = 0; t < kT; ++t) {
+      if (wave + NW * t < m) {
+        if (wave == ok && t == tk) {
+          sv[t] = isp ? inv : csub(cx<T>::make(0.0, 0.0), f);
+        } else {
+          const T pv = readlane_c(sv[t], pr);
+          sv[t] = isp ? cmul(pv, inv) : csub(sv[t], cmul(f, pv));
+        }
+      }
+    }
+    const int kn = k + 1;
+    if (kn < m && wave == kn % NW) {
+      const int tn = kn / NW;
+      T vn = cx<T>::make(0.0, 0.0);
+#pragma unroll
+      for (int t = 0; t < kT; ++t)
+        if (t == tn) vn = sv[t];
+      small_publish(vn, used, row_ok, colbuf[kn & 1], kw + (kn & 1), pinv + (kn & 1));
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int t = 0; t < kT; ++t) {
+    const int j = wave + NW * t;
+    if (row_ok && j < m) Ab[(long long)pivs[j] * lda + myk] = sv[t];
+  }
 }
 
 // Called by the one wave holding the next panel column (column U of this
@@ -608,10 +661,7 @@ hipError_t zinverse(T* A, int m, int lda, long long bstride, int batch, void* sc
                     hipStream_t st) {
   if (m <= 0 || batch <= 0) return hipSuccess;
   if (m <= 64) {
-    hipError_t e0 = allow_lds(inv_small_kernel<T>, (size_t)m * m * sizeof(T));
-    if (e0 != hipSuccess) return e0;
-    hipLaunchKernelGGL(inv_small_kernel<T>, dim3(batch), dim3(256), (size_t)m * m * sizeof(T), st, A, m,
-                       lda, bstride, flag);
+    hipLaunchKernelGGL(inv_small_kernel<T>, dim3(batch), dim3(256), 0, st, A, m, lda, bstride, flag);
     return hipPeekAtLastError();
   }
   return inverse_blocked<T>(A, m, lda, bstride, batch, scratch, flag, st);
