@@ -1,8 +1,8 @@
 // Batched in-place inversion of complex matrices (FP64 or FP32) by
 // Gauss-Jordan elimination with partial pivoting.
 //
-// m <= 64: the whole matrix sits in registers, one workgroup per matrix.
-// m  > 64: blocked Gauss-Jordan, two launches per block column C = [k0, k0+nb):
+// m <= 128: the whole matrix sits in registers, one workgroup per matrix.
+// m  > 128: blocked Gauss-Jordan, two launches per block column C = [k0, k0+nb):
 //   1. gj_panel: partial-pivoting LU of the panel A[k0:m, C] in LDS picks nb
 //      pivot rows (as the row map of this step) and forms Dinv, the inverse of
 //      the pivot block, by an in-LDS Gauss-Jordan on those rows;
@@ -191,88 +191,112 @@ __device__ inline cf readlane_c(cf v, int l) {
               __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.y), l)));
 }
 
-// m <= 64: Gauss-Jordan with the matrix in registers, one workgroup (256
-// threads) per matrix: thread (row i = lane, wave w) holds columns j = w + 4t.
+// m <= 64 RC: Gauss-Jordan with the matrix in registers, one workgroup of NW
+// waves per matrix: thread (rows 64c + lane, wave w) holds columns j = w + NW t.
 // Pivot rows stay where they are (marked used); a step reads the pivot row by
 // lane broadcasts and the pivot column from LDS, where the wave holding it
 // published it with the next pivot key and reciprocal, and takes one barrier.
 // With pivot row pr_k at step k the registers end as S[pr_k][j] = A^-1[k][pr_j],
 // written back to A^-1's own positions.
-template <class T>
-__device__ inline void small_publish(T v, bool used, bool row_ok, T* cbn, unsigned long long* key_out,
-                                     T* inv_out) {
-  const int lane = threadIdx.x & 63;
-  cbn[lane] = v;
-  unsigned long long key = (row_ok && !used) ? pivot_key(cabs2(v), lane) : 0ull;
-  key = wave_max_key(key);
-  const T d = readlane_c(v, pivot_row(key) & 63);
-  if (lane == 0) {
-    *key_out = key;
-    *inv_out = ((key >> 32) <= 1u) ? cx<T>::make(0.0, 0.0) : crecip(d);
-  }
-}
-
-template <class T>
-__global__ __launch_bounds__(256) void inv_small_kernel(T* A, int m, int lda, long long bstride, int* flag) {
-  constexpr int kT = 16, NW = 4;
-  __shared__ T colbuf[2][64];
+template <class T, int NW, int RC>
+__global__ __launch_bounds__(64 * NW) void inv_small_kernel(T* A, int m, int lda, long long bstride, int* flag) {
+  constexpr int kT = 64 * RC / NW;  // columns per thread
+  __shared__ T colbuf[2][64 * RC];
   __shared__ T pinv[2];
   __shared__ unsigned long long kw[2];
-  __shared__ int pivs[64];
+  __shared__ int pivs[64 * RC];
   T* Ab = A + (long long)blockIdx.x * bstride;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const bool row_ok = lane < m;
-  T sv[kT];
+  T sv[RC][kT];
 #pragma unroll
-  for (int t = 0; t < kT; ++t) {
-    const int j = wave + NW * t;
-    sv[t] = (row_ok && j < m) ? Ab[(long long)j * lda + lane] : cx<T>::make(0.0, 0.0);
-  }
-  if (wave == 0) small_publish(sv[0], false, row_ok, colbuf[0], kw, pinv);
+  for (int c = 0; c < RC; ++c)
+#pragma unroll
+    for (int t = 0; t < kT; ++t) {
+      const int i = 64 * c + lane, j = wave + NW * t;
+      sv[c][t] = (i < m && j < m) ? Ab[(long long)j * lda + i] : cx<T>::make(0.0, 0.0);
+    }
+  unsigned used = 0;   // bit c: row 64c + lane is a pivot row
+  int myk[RC];
+#pragma unroll
+  for (int c = 0; c < RC; ++c) myk[c] = 0;
+  // the wave holding column kn publishes it with its pivot and reciprocal
+  auto publish = [&](int kn, int tn) {
+    const int b = kn & 1;
+    unsigned long long key = 0;
+    T vn[RC];
+#pragma unroll
+    for (int c = 0; c < RC; ++c) {
+      vn[c] = cx<T>::make(0.0, 0.0);
+#pragma unroll
+      for (int t = 0; t < kT; ++t)
+        if (t == tn) vn[c] = sv[c][t];
+      const int i = 64 * c + lane;
+      colbuf[b][i] = vn[c];
+      if (i < m && !((used >> c) & 1u)) key = max(key, pivot_key(cabs2(vn[c]), i));
+    }
+    key = wave_max_key(key);
+    const int pn = min(max(pivot_row(key), 0), m - 1);
+    T d = cx<T>::make(0.0, 0.0);
+#pragma unroll
+    for (int c = 0; c < RC; ++c)
+      if (c == (pn >> 6)) d = readlane_c(vn[c], pn & 63);
+    if (lane == 0) {
+      kw[b] = key;
+      pinv[b] = ((key >> 32) <= 1u) ? cx<T>::make(0.0, 0.0) : crecip(d);
+    }
+  };
+  if (wave == 0) publish(0, 0);
   __syncthreads();
-  bool used = false;
-  int myk = 0;
 #pragma unroll 1
   for (int k = 0; k < m; ++k) {
     const int b = k & 1;
     const unsigned long long kk = kw[b];
     const T inv = pinv[b];
     const int pr = min(max(pivot_row(kk), 0), m - 1);
-    const bool isp = lane == pr;
-    if (isp) { used = true; myk = k; }
+    const int cp = pr >> 6, lp = pr & 63;
+    if (lane == lp) {
+      used |= 1u << cp;
+#pragma unroll
+      for (int c = 0; c < RC; ++c)
+        if (c == cp) myk[c] = k;
+    }
     if (tid == 0) {
       pivs[k] = pr;
       if ((kk >> 32) <= 1u) atomicOr(flag, 2);
     }
-    const T f = isp ? cx<T>::make(0.0, 0.0) : cmul(colbuf[b][lane], inv);
+    T f[RC];
+#pragma unroll
+    for (int c = 0; c < RC; ++c)
+      f[c] = (64 * c + lane == pr) ? cx<T>::make(0.0, 0.0) : cmul(colbuf[b][64 * c + lane], inv);
     const int tk = k / NW, ok = k % NW;
 #pragma unroll
     for (int t = 0; t < kT; ++t) {
-      if (wave + NW * t < m) {
-        if (wave == ok && t == tk) {
-          sv[t] = isp ? inv : csub(cx<T>::make(0.0, 0.0), f);
-        } else {
-          const T pv = readlane_c(sv[t], pr);
-          sv[t] = isp ? cmul(pv, inv) : csub(sv[t], cmul(f, pv));
-        }
+      if (wave + NW * t >= m) continue;
+      if (wave == ok && t == tk) {
+#pragma unroll
+        for (int c = 0; c < RC; ++c)
+          sv[c][t] = (64 * c + lane == pr) ? inv : csub(cx<T>::make(0.0, 0.0), f[c]);
+      } else {
+        T pv = cx<T>::make(0.0, 0.0);
+#pragma unroll
+        for (int c = 0; c < RC; ++c)
+          if (c == cp) pv = readlane_c(sv[c][t], lp);
+#pragma unroll
+        for (int c = 0; c < RC; ++c)
+          sv[c][t] = (64 * c + lane == pr) ? cmul(pv, inv) : csub(sv[c][t], cmul(f[c], pv));
       }
     }
     const int kn = k + 1;
-    if (kn < m && wave == kn % NW) {
-      const int tn = kn / NW;
-      T vn = cx<T>::make(0.0, 0.0);
-#pragma unroll
-      for (int t = 0; t < kT; ++t)
-        if (t == tn) vn = sv[t];
-      small_publish(vn, used, row_ok, colbuf[kn & 1], kw + (kn & 1), pinv + (kn & 1));
-    }
+    if (kn < m && wave == kn % NW) publish(kn, kn / NW);
     __syncthreads();
   }
 #pragma unroll
-  for (int t = 0; t < kT; ++t) {
-    const int j = wave + NW * t;
-    if (row_ok && j < m) Ab[(long long)pivs[j] * lda + myk] = sv[t];
-  }
+  for (int c = 0; c < RC; ++c)
+#pragma unroll
+    for (int t = 0; t < kT; ++t) {
+      const int i = 64 * c + lane, j = wave + NW * t;
+      if (i < m && j < m) Ab[(long long)pivs[j] * lda + myk[c]] = sv[c][t];
+    }
 }
 
 // Called by the one wave holding the next panel column (column U of this
@@ -650,7 +674,7 @@ hipError_t inverse_blocked(T* A, int m, int lda, long long bstride, int batch, v
 
 template <class T>
 size_t inverse_scratch_bytes(int m, int batch) {
-  if (m <= 64) return 0;
+  if (m <= 128) return 0;
   auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
   return up(sizeof(T) * (size_t)batch * m * m) + up(sizeof(T) * (size_t)batch * kNB * kNB) +
          3 * up(sizeof(int) * (size_t)batch * m);
@@ -661,7 +685,11 @@ hipError_t zinverse(T* A, int m, int lda, long long bstride, int batch, void* sc
                     hipStream_t st) {
   if (m <= 0 || batch <= 0) return hipSuccess;
   if (m <= 64) {
-    hipLaunchKernelGGL(inv_small_kernel<T>, dim3(batch), dim3(256), 0, st, A, m, lda, bstride, flag);
+    hipLaunchKernelGGL((inv_small_kernel<T, 4, 1>), dim3(batch), dim3(256), 0, st, A, m, lda, bstride, flag);
+    return hipPeekAtLastError();
+  }
+  if (m <= 128) {
+    hipLaunchKernelGGL((inv_small_kernel<T, 16, 2>), dim3(batch), dim3(1024), 0, st, A, m, lda, bstride, flag);
     return hipPeekAtLastError();
   }
   return inverse_blocked<T>(A, m, lda, bstride, batch, scratch, flag, st);
