@@ -557,7 +557,7 @@ hps_status merge_one(hps_problem* p, int l) {
 
 // ---- V-cycle -------------------------------------------------------------
 bool small_level(const Level& lv, int nq) {
-  return nq * lv.pairs >= 128 && lv.m <= 256 && small_level_lds(lv.m, lv.e) <= 64 * 1024;
+  return vc_small_ok(lv.m, lv.e, nq * lv.pairs);
 }
 
 template <class M>

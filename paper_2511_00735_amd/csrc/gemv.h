@@ -92,7 +92,8 @@ struct SmallLevelT {
   const int* dtab;
   cd* Z0;
 };
-size_t small_level_lds(int m, int e);
+// Levels these kernels take: at least 128 pairs, 2m and 2e at most 1024.
+bool vc_small_ok(int m, int e, int pairs);
 template <class M>
 hipError_t vc_down_small(const SmallLevelT<M>& a, int pairs, cd* vec, hipStream_t st);
 template <class M>

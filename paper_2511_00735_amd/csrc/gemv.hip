@@ -46,15 +46,31 @@ __global__ __launch_bounds__(kThreads) void gemv_kernel(GemvBatchT<Mt> gb, cd* p
   const int k0 = split * kc;
   const int k1 = min(d.K, k0 + kc);
   const int t = threadIdx.x, lane = t & 63, grp = t >> 6;
+  const int r = tile * kRowsT + lane;
+  const bool rok = r < d.M_ && k0 < k1;
+  const Mt* Ab = d.A.base + (long long)b * d.A.bstride;
+  const long long row = imap(d.A.r, r < d.M_ ? r : 0);
+  // The first U entries of the thread are requested before x is staged (two
+  // dependent loads through the slot table), clamped into the operator; the
+  // barrier keeps them in flight together.
+  constexpr int U = 8;  // independent loads in flight per thread
+  Mt a0[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) a0[u] = cx<Mt>::make(0.0, 0.0);
+  if (k0 < k1) {  // uniform over the workgroup
+#pragma unroll
+    for (int u = 0; u < U; ++u) a0[u] = Ab[(long long)imap(d.A.c, min(k0 + grp + 4 * u, k1 - 1)) * d.A.ld + row];
+  }
   for (int k = k0 + t; k < k1; k += kThreads) xs[k - k0] = load_x(d.x, b, k);
   __syncthreads();
-  const int r = tile * kRowsT + lane;
   cd acc = cmk(0.0, 0.0);
-  if (r < d.M_) {
-    const Mt* Ab = d.A.base + (long long)b * d.A.bstride;
-    const long long row = imap(d.A.r, r);
-    int k = k0 + grp;
-    constexpr int U = 8;  // independent loads in flight per thread
+  if (rok) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = k0 + grp + 4 * u;
+      acc = cfma(k < k1 ? to_cd(a0[u]) : cmk(0.0, 0.0), xs[min(k, k1 - 1) - k0], acc);
+    }
+    int k = k0 + grp + 4 * U;
     for (; k + 4 * (U - 1) < k1; k += 4 * U) {
       Mt a[U];
 #pragma unroll
@@ -88,104 +104,197 @@ __global__ void gemv_reduce_kernel(GemvBatchT<Mt> gb, const cd* partial) {
   const int nsplit = gb.nsplit[blockIdx.z];
   if (nsplit == 1) return;
   const int b = blockIdx.y;
+  const long long ps = (long long)gb.batch * d.M_;  // between splits
   for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < d.M_; r += gridDim.x * blockDim.x) {
+    const cd* pp = partial + gb.poff[blockIdx.z] + (long long)b * d.M_ + r;
     cd s = cmk(0.0, 0.0);
-    for (int q = 0; q < nsplit; ++q)
-      s = cadd(s, partial[gb.poff[blockIdx.z] + ((long long)q * gb.batch + b) * d.M_ + r]);
+    int q = 0;
+    for (; q + 8 <= nsplit; q += 8) {  // eight loads in flight, summed in split order
+      cd v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = pp[(q + u) * ps];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s = cadd(s, v[u]);
+    }
+    for (; q < nsplit; ++q) s = cadd(s, pp[q * ps]);
     store_y(d.y, b, r, cmul(d.alpha, s));
   }
 }
 
-// ---- one workgroup per pair: a whole V-cycle level ---------------------------
-// y[i] = (y0 ? y0[i] : 0) + sum_k A(rm(i), cm(k)) x[k]; x, y0, y in LDS.
-template <class Mt, int NT>
-__device__ void wg_gemv(const Mt* A, int ld, IdxMap rm, IdxMap cm, int M, int K, const cd* x,
-                        const cd* y0, cd* y, cd* red) {
-  const int t = threadIdx.x;
-  const int RT = M < kRowsT ? M : kRowsT;
-  const int G = NT / RT;
-  const int r = t % RT, g = t / RT;
-  constexpr int U = 8;  // independent loads in flight per thread
-  for (int r0 = 0; r0 < M; r0 += RT) {
-    const int row = r0 + r;
-    cd acc = cmk(0.0, 0.0);
-    if (g < G && row < M) {
-      const long long ar = imap(rm, row);
-      int c = g;
-      for (; c + (U - 1) * G < K; c += U * G) {
-        Mt a[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) a[u] = A[(long long)imap(cm, c + u * G) * ld + ar];
-#pragma unroll
-        for (int u = 0; u < U; ++u) acc = cfma(to_cd(a[u]), x[c + u * G], acc);
-      }
-      for (; c < K; c += G) acc = cfma(to_cd(A[(long long)imap(cm, c) * ld + ar]), x[c], acc);
-    }
-    if (g < G) red[g * RT + r] = acc;
-    __syncthreads();
-    if (t < RT && r0 + t < M) {
-      cd s = y0 ? y0[r0 + t] : cmk(0.0, 0.0);
-      for (int q = 0; q < G; ++q) s = cadd(s, red[q * RT + t]);
-      y[r0 + t] = s;
-    }
-    __syncthreads();
-  }
-}
+// ---- two workgroups per pair: a whole V-cycle level ---------------------------
+// Levels with many small pairs are bound by the latency of their dependent
+// loads (slot index -> vector value -> product -> scatter), not by bandwidth:
+// every workgroup of such a level is resident at once, so the launch lasts as
+// long as one workgroup's chain of round trips.  Each half of a pair is
+// therefore independent work for its own workgroup, and every load that does
+// not depend on a computed value (slot indices, the operator entries of the
+// thread, the vector values read through those slots) is issued before the
+// first product is formed.
 
-// Down sweep of one pair: z0 = A^-1 r_x (kept in Z0), then the exterior
-// residual rows across the kept faces receive C~ z0:
-// w[dtab(P.E1)] += T^P_{E1,a} z0_P, w[dtab(Q.E2)] += T^Q_{E2,b} z0_Q.
+// One GEMV piece of a workgroup, y[i] = (y0 ? y0[i] : 0) + sum_k A(rm(i), cm(k)) x[k]
+// for i < M, k < K, with x, y0, y in LDS.  Rows go in tiles of RT = min(M, 64),
+// one row per lane; S tiles are in flight per pass, each with G column groups;
+// the first CAP columns of a thread in the first pass are prefetched into
+// registers by load(), the rest are read in run().
+template <class Mt, int NT, int CAP>
+struct RegGemv {
+  static_assert(CAP % 4 == 0, "prefetch groups of four");
+  Mt a[CAP];
+  int M, K, RT, S, G, slot, r, g, passes;
+  bool act;
+  __device__ void setup(int M_, int K_) {
+    M = M_;
+    K = K_;
+    RT = M < 64 ? M : 64;
+    const int tiles = (M + RT - 1) / RT;
+    S = min(tiles, NT / RT);
+    const int tpt = NT / S;
+    G = tpt / RT;
+    const int t = threadIdx.x;
+    slot = t / tpt;
+    const int u = t - slot * tpt;
+    r = u % RT;
+    g = u / RT;
+    act = slot < S && g < G;
+    passes = (tiles + S - 1) / S;
+  }
+  // Unconditional loads: indices outside the operator are clamped into it, and
+  // run() zeroes those entries; a barrier must separate load() from run(), so
+  // that the loads stay in flight together instead of sinking to their uses.
+  __device__ void load(const Mt* A, int ld, IdxMap rm, IdxMap cm) {
+    const int row = slot * RT + r;
+    const Mt* Ar = A + imap(rm, act && row < M ? row : 0);
+#pragma unroll
+    for (int c = 0; c < CAP; ++c) a[c] = Ar[(long long)imap(cm, min(g + c * G, K - 1)) * ld];
+  }
+  // red: NT entries of LDS.  Ends with the workgroup synchronised.
+  __device__ void run(const Mt* A, int ld, IdxMap rm, IdxMap cm, const cd* x, const cd* y0, cd* y, cd* red) {
+    for (int ps = 0; ps < passes; ++ps) {
+      const int row = (ps * S + slot) * RT + r;
+      cd acc = cmk(0.0, 0.0);
+      if (act && row < M) {
+        int c = 0;
+        if (ps == 0) {
+          // four entries at a time: the empty asm orders each group after the
+          // previous one's products, so that the compiler does not widen every
+          // prefetched entry (and read every x) ahead of the first product
+#pragma unroll
+          for (int q0 = 0; q0 < CAP; q0 += 4) {
+            int col[4];
+            Mt w[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              col[q] = g + (q0 + q) * G;
+              w[q] = a[q0 + q];
+            }
+            asm volatile("" : "+v"(acc.x), "+v"(acc.y), "+v"(col[0]), "+v"(col[1]), "+v"(col[2]), "+v"(col[3]),
+                         "+v"(w[0].x), "+v"(w[0].y), "+v"(w[1].x), "+v"(w[1].y), "+v"(w[2].x), "+v"(w[2].y),
+                         "+v"(w[3].x), "+v"(w[3].y));
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              acc = cfma(col[q] < K ? to_cd(w[q]) : cmk(0.0, 0.0), x[min(col[q], K - 1)], acc);
+          }
+          c = CAP;
+        }
+        const long long ar = imap(rm, row);
+        constexpr int U = sizeof(Mt) == sizeof(cd) ? 4 : 8;  // independent loads in flight per thread
+#pragma unroll 1
+        for (; g + (c + U - 1) * G < K; c += U) {
+          Mt v[U];
+#pragma unroll
+          for (int u = 0; u < U; ++u) v[u] = A[(long long)imap(cm, g + (c + u) * G) * ld + ar];
+#pragma unroll
+          for (int u = 0; u < U; ++u) acc = cfma(to_cd(v[u]), x[g + (c + u) * G], acc);
+        }
+#pragma unroll 1
+        for (; g + c * G < K; ++c) acc = cfma(to_cd(A[(long long)imap(cm, g + c * G) * ld + ar]), x[g + c * G], acc);
+      }
+      if (act) red[(slot * G + g) * RT + r] = acc;
+      __syncthreads();
+      for (int q = threadIdx.x; q < S * RT; q += NT) {
+        const int sl = q / RT, rr = q - sl * RT;
+        const int i = (ps * S + sl) * RT + rr;
+        if (i < M) {
+          cd sum = y0 ? y0[i] : cmk(0.0, 0.0);
+          for (int gg = 0; gg < G; ++gg) sum = cadd(sum, red[(sl * G + gg) * RT + rr]);
+          y[i] = sum;
+        }
+      }
+      __syncthreads();
+    }
+  }
+};
+
+// Register budgets (entries per thread prefetched per operator).
+template <class Mt> struct SmallCap { static constexpr int A = 8, T = 12, X = 16; };
+template <> struct SmallCap<cd> { static constexpr int A = 4, T = 8, X = 12; };
+
+// Down sweep, half h of pair j (workgroup 2j + h).  x = [Q.beta; P.alpha]:
+// h = 0 forms z0_P = rows [m, 2m) of A^-1 r_x and adds T^P_{E1,a} z0_P to the
+// slots across P's kept faces; h = 1 forms z0_Q = rows [0, m) and adds
+// T^Q_{E2,b} z0_Q across Q's.  The two halves touch disjoint slots, and no
+// other pair of the level reads or writes those slots.
 template <class Mt, int NT>
 __global__ __launch_bounds__(NT) void vc_down_small_kernel(SmallLevelT<Mt> a, cd* vec) {
   extern __shared__ cd sm[];
   const int m = a.m, e = a.e, m2 = 2 * m;
-  cd* r = sm;
-  cd* z0 = r + m2;
-  cd* dd = z0 + m2;
-  cd* red = dd + e;
-  const int j = blockIdx.x, t = threadIdx.x;
+  const int j = blockIdx.x >> 1, h = blockIdx.x & 1, t = threadIdx.x;
+  cd* r = sm;             // [2m] r_x
+  cd* z = r + m2;         // [m]  z0 half
+  cd* dv = z + m;         // [e]  vector values across the faces
+  cd* dd = dv + e;        // [e]  T z0 half
+  cd* red = dd + e;       // [NT]
+  int* ds = reinterpret_cast<int*>(red + NT);  // [e] slots across the faces
   const long long bb = (long long)a.g.b * a.g.b;
-  const Mt* TP = a.T + (2LL * j) * bb;
-  const Mt* TQ = TP + bb;
-  const int* xt = a.xtab + (long long)j * m2;
-  const int* dt = a.dtab + (long long)j * 2 * e;
-  for (int i = t; i < m2; i += NT) r[i] = vec[xt[i]];
-  __syncthreads();
-  wg_gemv<Mt, NT>(a.Ainv + (long long)j * m2 * m2, m2, im_off(0), im_off(0), m2, m2, r, nullptr, z0, red);
-  for (int i = t; i < m2; i += NT) a.Z0[(long long)j * m2 + i] = z0[i];
-  wg_gemv<Mt, NT>(TP, a.g.b, a.E1, im_off(a.a0), e, m, z0 + m, nullptr, dd, red);
-  for (int i = t; i < e; i += NT) {
-    const int s = dt[i];
-    if (s >= 0) vec[s] = cadd(vec[s], dd[i]);
+  const int xi = t < m2 ? a.xtab[(long long)j * m2 + t] : -1;
+  const int di = t < e ? a.dtab[(long long)j * 2 * e + h * e + t] : -1;
+  RegGemv<Mt, NT, SmallCap<Mt>::A> ga;
+  RegGemv<Mt, NT, SmallCap<Mt>::T> gt;
+  ga.setup(m, m2);
+  gt.setup(e, m);
+  const Mt* Ai = a.Ainv + (long long)j * m2 * m2;
+  const IdxMap arow = im_off(h == 0 ? m : 0);
+  const Mt* Th = a.T + (2LL * j + h) * bb;
+  const IdxMap trow = h == 0 ? a.E1 : a.E2;
+  const IdxMap tcol = im_off(h == 0 ? a.a0 : a.b0);
+  ga.load(Ai, m2, arow, im_off(0));
+  gt.load(Th, a.g.b, trow, tcol);
+  if (t < m2) r[t] = vec[xi];
+  if (t < e) {
+    ds[t] = di;
+    dv[t] = di >= 0 ? vec[di] : cmk(0.0, 0.0);
   }
   __syncthreads();
-  wg_gemv<Mt, NT>(TQ, a.g.b, a.E2, im_off(a.b0), e, m, z0, nullptr, dd, red);
-  for (int i = t; i < e; i += NT) {
-    const int s = dt[e + i];
-    if (s >= 0) vec[s] = cadd(vec[s], dd[i]);
-  }
+  ga.run(Ai, m2, arow, im_off(0), r, nullptr, z, red);
+  if (t < m) a.Z0[(long long)j * m2 + (h == 0 ? m : 0) + t] = z[t];
+  gt.run(Th, a.g.b, trow, tcol, z, dv, dd, red);
+  if (t < e && ds[t] >= 0) vec[ds[t]] = dd[t];
 }
 
-// Up sweep of one pair: x = z0 + X y with y the kept-face values of z.
+// Up sweep, half h of pair j: rows [h m, (h+1) m) of x = z0 + X y, y the
+// kept-face values of z, written into z at the shared-face slots.
 template <class Mt, int NT>
 __global__ __launch_bounds__(NT) void vc_up_small_kernel(SmallLevelT<Mt> a, cd* z) {
   extern __shared__ cd sm[];
   const int m = a.m, e = a.e, m2 = 2 * m, e2 = 2 * e;
-  cd* y = sm;
-  cd* z0 = y + e2;
-  cd* x = z0 + m2;
-  cd* red = x + m2;
-  const int j = blockIdx.x, t = threadIdx.x;
-  const int* yt = a.ytab + (long long)j * e2;
-  const int* xt = a.xtab + (long long)j * m2;
-  for (int i = t; i < e2; i += NT) {
-    const int s = yt[i];
-    y[i] = s >= 0 ? z[s] : cmk(0.0, 0.0);
-  }
-  for (int i = t; i < m2; i += NT) z0[i] = a.Z0[(long long)j * m2 + i];
+  const int j = blockIdx.x >> 1, h = blockIdx.x & 1, t = threadIdx.x;
+  cd* y = sm;          // [2e]
+  cd* z0 = y + e2;     // [m]
+  cd* x = z0 + m;      // [m]
+  cd* red = x + m;     // [NT]
+  const int yi = t < e2 ? a.ytab[(long long)j * e2 + t] : -1;
+  const int xi = t < m ? a.xtab[(long long)j * m2 + h * m + t] : -1;
+  const cd zv = t < m ? a.Z0[(long long)j * m2 + h * m + t] : cmk(0.0, 0.0);
+  RegGemv<Mt, NT, SmallCap<Mt>::X> gx;
+  gx.setup(m, e2);
+  const Mt* Xj = a.X + (long long)j * m2 * e2;
+  const IdxMap xrow = im_off(h * m);
+  gx.load(Xj, m2, xrow, im_off(0));
+  if (t < e2) y[t] = yi >= 0 ? z[yi] : cmk(0.0, 0.0);
+  if (t < m) z0[t] = zv;
   __syncthreads();
-  wg_gemv<Mt, NT>(a.X + (long long)j * m2 * e2, m2, im_off(0), im_off(0), m2, e2, y, z0, x, red);
-  for (int i = t; i < m2; i += NT) z[xt[i]] = x[i];
+  gx.run(Xj, m2, xrow, im_off(0), y, z0, x, red);
+  if (t < m) z[xi] = x[t];
 }
 
 }  // namespace
@@ -221,7 +330,7 @@ hipError_t zgemv_batched(const GemvDescT<Mt>* d, int nd, int batch, cd* partial,
   if (err != hipSuccess || !any_split) return err;
   int maxM = 0;
   for (int i = 0; i < nd; ++i) maxM = std::max(maxM, d[i].M_);
-  hipLaunchKernelGGL(gemv_reduce_kernel<Mt>, dim3((maxM + 255) / 256, batch, nd), dim3(256), 0, st, gb, partial);
+  hipLaunchKernelGGL(gemv_reduce_kernel<Mt>, dim3((maxM + 63) / 64, batch, nd), dim3(64), 0, st, gb, partial);
   return hipPeekAtLastError();
 }
 
@@ -250,41 +359,78 @@ hipError_t zgemv_partials(const GemvDescT<Mt>* d, int nd, int batch, cd* partial
   return hipPeekAtLastError();
 }
 
-// Threads per pair: 1024 when the level has at most 512 pairs (larger matrices,
-// fewer workgroups: more loads in flight per pair), 256 otherwise.
-constexpr int kSmallWide = 1024;
-inline bool small_wide(int pairs) { return pairs <= 512; }
+namespace {
 
-size_t small_level_lds(int m, int e) {
-  return sizeof(cd) * (size_t)(std::max(4 * m + e, 2 * e + 4 * m) + kSmallWide);
+// Threads per workgroup: at least one per slot index, and otherwise as many
+// as let the level's 2 x pairs workgroups be resident together (about
+// kSmallResident threads on the chip at these kernels' register use), but no
+// more than one per kSmallMinEntries operator entries.
+#ifndef HPS_SMALL_RESIDENT
+#define HPS_SMALL_RESIDENT 262144
+#endif
+#ifndef HPS_SMALL_MIN_ENTRIES
+#define HPS_SMALL_MIN_ENTRIES 4
+#endif
+constexpr long long kSmallResident = HPS_SMALL_RESIDENT;
+constexpr long long kSmallMinEntries = HPS_SMALL_MIN_ENTRIES;
+int small_threads(long long entries, int need, int pairs) {
+  int nt = 64;
+  while (nt < 1024 && 2LL * pairs * (2 * nt) <= kSmallResident && 2 * nt * kSmallMinEntries <= entries) nt *= 2;
+  while (nt < need) nt *= 2;
+  return nt;
 }
+size_t small_down_lds(int m, int e, int nt) { return sizeof(cd) * (size_t)(3 * m + 2 * e + nt) + sizeof(int) * e; }
+size_t small_up_lds(int m, int e, int nt) { return sizeof(cd) * (size_t)(2 * e + 2 * m + nt); }
 
 template <class Mt, int NT>
 hipError_t launch_down(const SmallLevelT<Mt>& a, int pairs, cd* vec, hipStream_t st) {
-  const size_t lds = small_level_lds(a.m, a.e);
+  const size_t lds = small_down_lds(a.m, a.e, NT);
   hipError_t err = allow_lds(vc_down_small_kernel<Mt, NT>, lds);
   if (err != hipSuccess) return err;
-  hipLaunchKernelGGL((vc_down_small_kernel<Mt, NT>), dim3(pairs), dim3(NT), lds, st, a, vec);
+  hipLaunchKernelGGL((vc_down_small_kernel<Mt, NT>), dim3(2 * pairs), dim3(NT), lds, st, a, vec);
   return hipPeekAtLastError();
 }
 
 template <class Mt, int NT>
 hipError_t launch_up(const SmallLevelT<Mt>& a, int pairs, cd* z, hipStream_t st) {
-  const size_t lds = small_level_lds(a.m, a.e);
+  const size_t lds = small_up_lds(a.m, a.e, NT);
   hipError_t err = allow_lds(vc_up_small_kernel<Mt, NT>, lds);
   if (err != hipSuccess) return err;
-  hipLaunchKernelGGL((vc_up_small_kernel<Mt, NT>), dim3(pairs), dim3(NT), lds, st, a, z);
+  hipLaunchKernelGGL((vc_up_small_kernel<Mt, NT>), dim3(2 * pairs), dim3(NT), lds, st, a, z);
   return hipPeekAtLastError();
+}
+
+}  // namespace
+
+bool vc_small_ok(int m, int e, int pairs) {
+  return pairs >= 128 && m >= 1 && e >= 1 && 2 * m <= 1024 && 2 * e <= 1024 &&
+         small_down_lds(m, e, 1024) <= 64 * 1024 && small_up_lds(m, e, 1024) <= 64 * 1024;
 }
 
 template <class Mt>
 hipError_t vc_down_small(const SmallLevelT<Mt>& a, int pairs, cd* vec, hipStream_t st) {
-  return small_wide(pairs) ? launch_down<Mt, kSmallWide>(a, pairs, vec, st) : launch_down<Mt, kThreads>(a, pairs, vec, st);
+  if (!vc_small_ok(a.m, a.e, pairs)) return hipErrorInvalidValue;
+  const int m = a.m, e = a.e;
+  switch (small_threads(2LL * m * m + (long long)e * m, std::max(2 * m, e), pairs)) {
+    case 64: return launch_down<Mt, 64>(a, pairs, vec, st);
+    case 128: return launch_down<Mt, 128>(a, pairs, vec, st);
+    case 256: return launch_down<Mt, 256>(a, pairs, vec, st);
+    case 512: return launch_down<Mt, 512>(a, pairs, vec, st);
+    default: return launch_down<Mt, 1024>(a, pairs, vec, st);
+  }
 }
 
 template <class Mt>
 hipError_t vc_up_small(const SmallLevelT<Mt>& a, int pairs, cd* z, hipStream_t st) {
-  return small_wide(pairs) ? launch_up<Mt, kSmallWide>(a, pairs, z, st) : launch_up<Mt, kThreads>(a, pairs, z, st);
+  if (!vc_small_ok(a.m, a.e, pairs)) return hipErrorInvalidValue;
+  const int m = a.m, e = a.e;
+  switch (small_threads(2LL * m * e, std::max(2 * e, m), pairs)) {
+    case 64: return launch_up<Mt, 64>(a, pairs, z, st);
+    case 128: return launch_up<Mt, 128>(a, pairs, z, st);
+    case 256: return launch_up<Mt, 256>(a, pairs, z, st);
+    case 512: return launch_up<Mt, 512>(a, pairs, z, st);
+    default: return launch_up<Mt, 1024>(a, pairs, z, st);
+  }
 }
 
 template hipError_t zgemv_batched<cd>(const GemvDescT<cd>*, int, int, cd*, hipStream_t);
