@@ -239,7 +239,7 @@ def run_batch_c4(hps, torch):
     probs = workloads.c4(256, seed=4)
     out = {"problems": len(probs), "shapes": len(set((p.n, p.N) for p in probs)),
            "skeleton_dof": int(sum(p.skeleton_dof for p in probs))}
-    # one untimed pass first: every group's first V-cycle captures its HIP graph
+    # one untimed pass first (first-call set-up of every group shape)
     Server(precision="mixed", memory_budget=200 << 30, workers=3, max_batch=64).run(probs)
     for label, kw in (("batched", dict(workers=3, max_batch=64)), ("one_by_one", dict(workers=1, max_batch=1))):
         srv = Server(precision="mixed", memory_budget=200 << 30, **kw)

@@ -127,9 +127,12 @@ hps_status hps_ctx_destroy(hps_ctx* ctx);
 const char* hps_last_error(const hps_ctx* ctx);
 /* Wait for the context's stream and report deferred device errors. */
 hps_status hps_sync(hps_ctx* ctx);
-/* Options.  HPS_OPT_GRAPHS (default 1): replay the multigrid V-cycle from a HIP
+/* Options.  HPS_OPT_GRAPHS (default 0): replay the multigrid V-cycle from a HIP
    graph captured once per problem (on a private capture stream) instead of
    launching its kernels one by one.  Results are bitwise identical either way.
+   The graph reads and writes buffers of its own (two vector copies per
+   application), so it pays only where the host cannot keep ahead of the GPU;
+   the solver's own loop launches eagerly fast enough.
    HPS_OPT_TIMING (default 0): profiling aid.  Setting it (either value)
    synchronises and discards earlier records; while it is 1, every launch of a
    timed kernel is bracketed by HIP events recorded on the context's stream (the

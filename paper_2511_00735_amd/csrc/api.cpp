@@ -27,7 +27,7 @@ struct hps_ctx {
   hipStream_t stream;
   std::string err;
   hipStream_t cap_stream = nullptr;  // private stream used only to capture graphs
-  int use_graphs = 1;
+  int use_graphs = 0;
   int timing = 0;
   std::vector<TimedLaunch> timed;
 };

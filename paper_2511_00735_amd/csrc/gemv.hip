@@ -31,11 +31,13 @@ __device__ inline void store_y(const VecOut& y, int b, int i, cd v) {
   }
 }
 
-// grid: x = row tile * nsplit (flattened), y = batch, z = descriptor.
-template <class Mt>
-__global__ __launch_bounds__(kThreads) void gemv_kernel(GemvBatchT<Mt> gb, cd* partial) {
+// grid: x = row tile * nsplit (flattened), y = batch, z = descriptor.  NT / 64
+// waves per workgroup, wave w taking columns k0 + w, k0 + w + NW, ...
+template <class Mt, int NT>
+__global__ __launch_bounds__(NT) void gemv_kernel(GemvBatchT<Mt> gb, cd* partial) {
+  constexpr int NW = NT / 64;
   __shared__ cd xs[kGemvKChunkMax];
-  __shared__ cd red[4][kRowsT];
+  __shared__ cd red[NW][kRowsT];
   const GemvDescT<Mt>& d = gb.d[blockIdx.z];
   const int tiles = (d.M_ + kRowsT - 1) / kRowsT;
   const int nsplit = gb.nsplit[blockIdx.z];
@@ -59,40 +61,37 @@ __global__ __launch_bounds__(kThreads) void gemv_kernel(GemvBatchT<Mt> gb, cd* p
   for (int u = 0; u < U; ++u) a0[u] = cx<Mt>::make(0.0, 0.0);
   if (k0 < k1) {  // uniform over the workgroup
 #pragma unroll
-    for (int u = 0; u < U; ++u) a0[u] = Ab[(long long)imap(d.A.c, min(k0 + grp + 4 * u, k1 - 1)) * d.A.ld + row];
+    for (int u = 0; u < U; ++u) a0[u] = Ab[(long long)imap(d.A.c, min(k0 + grp + NW * u, k1 - 1)) * d.A.ld + row];
   }
-  for (int k = k0 + t; k < k1; k += kThreads) xs[k - k0] = load_x(d.x, b, k);
+  for (int k = k0 + t; k < k1; k += NT) xs[k - k0] = load_x(d.x, b, k);
   __syncthreads();
   cd acc = cmk(0.0, 0.0);
   if (rok) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int k = k0 + grp + 4 * u;
+      const int k = k0 + grp + NW * u;
       acc = cfma(k < k1 ? to_cd(a0[u]) : cmk(0.0, 0.0), xs[min(k, k1 - 1) - k0], acc);
     }
-    int k = k0 + grp + 4 * U;
-    for (; k + 4 * (U - 1) < k1; k += 4 * U) {
+    int k = k0 + grp + NW * U;
+    for (; k + NW * (U - 1) < k1; k += NW * U) {
       Mt a[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) a[u] = Ab[(long long)imap(d.A.c, k + 4 * u) * d.A.ld + row];
+      for (int u = 0; u < U; ++u) a[u] = Ab[(long long)imap(d.A.c, k + NW * u) * d.A.ld + row];
 #pragma unroll
-      for (int u = 0; u < U; ++u) acc = cfma(to_cd(a[u]), xs[k + 4 * u - k0], acc);
+      for (int u = 0; u < U; ++u) acc = cfma(to_cd(a[u]), xs[k + NW * u - k0], acc);
     }
-    for (; k < k1; k += 4) acc = cfma(to_cd(Ab[(long long)imap(d.A.c, k) * d.A.ld + row]), xs[k - k0], acc);
+    for (; k < k1; k += NW) acc = cfma(to_cd(Ab[(long long)imap(d.A.c, k) * d.A.ld + row]), xs[k - k0], acc);
   }
   red[grp][lane] = acc;
   __syncthreads();
-  if (nsplit == 1 && !gb.partials_only) {
-    if (grp == 0 && r < d.M_) {
-      const cd s = cadd(cadd(red[0][lane], red[1][lane]), cadd(red[2][lane], red[3][lane]));
-      store_y(d.y, b, r, cmul(d.alpha, s));
-    }
-    return;
-  }
-  if (grp == 0 && r < d.M_) {
-    const cd s = cadd(cadd(red[0][lane], red[1][lane]), cadd(red[2][lane], red[3][lane]));
+  if (grp != 0 || r >= d.M_) return;
+  cd s = red[0][lane];
+#pragma unroll
+  for (int w = 1; w < NW; ++w) s = cadd(s, red[w][lane]);
+  if (nsplit == 1 && !gb.partials_only)
+    store_y(d.y, b, r, cmul(d.alpha, s));
+  else
     partial[gb.poff[blockIdx.z] + ((long long)split * gb.batch + b) * d.M_ + r] = s;
-  }
 }
 
 // Sum the split-K partials in split order (deterministic) and apply the epilogue.
@@ -197,7 +196,10 @@ struct RegGemv {
           c = CAP;
         }
         const long long ar = imap(rm, row);
-        constexpr int U = sizeof(Mt) == sizeof(cd) ? 4 : 8;  // independent loads in flight per thread
+#ifndef HPS_SMALL_U
+#define HPS_SMALL_U 8
+#endif
+        constexpr int U = sizeof(Mt) == sizeof(cd) ? 4 : HPS_SMALL_U;  // independent loads in flight per thread
 #pragma unroll 1
         for (; g + (c + U - 1) * G < K; c += U) {
           Mt v[U];
@@ -299,6 +301,19 @@ __global__ __launch_bounds__(NT) void vc_up_small_kernel(SmallLevelT<Mt> a, cd* 
 
 }  // namespace
 
+namespace {
+// Launches of few workgroups (a capped split count) take 16 waves per
+// workgroup, so that each thread still has about one batch of loads.
+template <class Mt>
+hipError_t launch_gemv(const GemvBatchT<Mt>& gb, int gx, int batch, int nd, cd* partial, hipStream_t st) {
+  if ((long long)gx * batch * nd < kGemvTargetBlocks / 2)
+    hipLaunchKernelGGL((gemv_kernel<Mt, 1024>), dim3(gx, batch, nd), dim3(1024), 0, st, gb, partial);
+  else
+    hipLaunchKernelGGL((gemv_kernel<Mt, kThreads>), dim3(gx, batch, nd), dim3(kThreads), 0, st, gb, partial);
+  return hipPeekAtLastError();
+}
+}  // namespace
+
 int gemv_nsplit(int M, int K, int batch) {
   const int tiles = (M + kRowsT - 1) / kRowsT;
   int ns = (kGemvTargetBlocks + tiles * batch - 1) / (tiles * batch);
@@ -325,8 +340,7 @@ hipError_t zgemv_batched(const GemvDescT<Mt>* d, int nd, int batch, cd* partial,
     gx = std::max(gx, tiles * ns);
   }
   if (any_split && !partial) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(gemv_kernel<Mt>, dim3(gx, batch, nd), dim3(kThreads), 0, st, gb, partial);
-  hipError_t err = hipPeekAtLastError();
+  hipError_t err = launch_gemv(gb, gx, batch, nd, partial, st);
   if (err != hipSuccess || !any_split) return err;
   int maxM = 0;
   for (int i = 0; i < nd; ++i) maxM = std::max(maxM, d[i].M_);
@@ -355,8 +369,7 @@ hipError_t zgemv_partials(const GemvDescT<Mt>* d, int nd, int batch, cd* partial
     poff += (long long)ns * batch * d[i].M_;
     gx = std::max(gx, tiles * ns);
   }
-  hipLaunchKernelGGL(gemv_kernel<Mt>, dim3(gx, batch, nd), dim3(kThreads), 0, st, gb, partial);
-  return hipPeekAtLastError();
+  return launch_gemv(gb, gx, batch, nd, partial, st);
 }
 
 namespace {
@@ -402,8 +415,11 @@ hipError_t launch_up(const SmallLevelT<Mt>& a, int pairs, cd* z, hipStream_t st)
 
 }  // namespace
 
+#ifndef HPS_SMALL_MIN_PAIRS
+#define HPS_SMALL_MIN_PAIRS 32
+#endif
 bool vc_small_ok(int m, int e, int pairs) {
-  return pairs >= 128 && m >= 1 && e >= 1 && 2 * m <= 1024 && 2 * e <= 1024 &&
+  return pairs >= HPS_SMALL_MIN_PAIRS && m >= 1 && e >= 1 && 2 * m <= 1024 && 2 * e <= 1024 &&
          small_down_lds(m, e, 1024) <= 64 * 1024 && small_up_lds(m, e, 1024) <= 64 * 1024;
 }
 

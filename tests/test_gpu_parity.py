@@ -303,3 +303,33 @@ def test_mixed_before_and_after_refinement(hps, ctx):
     rhs5 = prob5.set_rhs(prob5.boundary_data(pr.wave.t))
     g5, info5 = prob5.gmres_solve(rhs5, tol=1e-12)
     assert rel(g5.cpu().numpy(), oc["g"]) < 1e-10, info5
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_vcycle_direct_at_full_size(hps, ctx, precision):
+    """At the 64x64, N = 16, kappa = 200 size (every V-cycle code path: levels
+    with 32-2048 pairs on the two-workgroups-per-pair kernels with entries
+    beyond the register prefetch, split-K GEMVs of both block sizes), one
+    V-cycle with the exact top solve is the direct HPS solver: M (A g) = g for
+    the skeleton operator A.  A property of the method at any size, so no
+    oracle run is needed at this size.  Tolerances: FP64 1e-12 (rounding only;
+    measured 5e-15); mixed 2e-5 (FP32 operators below the top two merges;
+    measured 2e-6).  A wrong index in any kernel gives an O(1) error."""
+    import torch
+    from oracle import mesh
+    n, N, kappa = 64, 16, 200.0
+    print(f"[vcycle] n64_N16 {precision} direct", flush=True)
+    prec = hps.HPS_FP64 if precision == "fp64" else hps.HPS_MIXED
+    desc = hps.make_desc(n, N, kappa, coarse_iters=-1, precision=prec)
+    prob = hps.Problem(ctx, desc)
+    prob.build_leaves(prob.coefficient_nodes(workloads.zero_field))
+    prob.merge_all()
+    rng = np.random.default_rng(11)
+    g = rng.standard_normal(prob.nslots) + 1j * rng.standard_normal(prob.nslots)
+    g[mesh.physical_slot_mask(n, N - 1)] = 0
+    gd = torch.from_numpy(g).cuda()
+    r = prob.skeleton_apply(gd)
+    z = prob.precond_apply(r).cpu().numpy()
+    err = rel(z, g)
+    print(f"[vcycle] {precision} |M A g - g| / |g| = {err:.3e}", flush=True)
+    assert err < (1e-12 if precision == "fp64" else 2e-5), err
