@@ -397,11 +397,17 @@ __global__ __launch_bounds__(1024) void gj_panel_reg_kernel(const T* A, int m, i
     unsigned long long best = 0;
 #pragma unroll
     for (int t = 0; t < CH; ++t) {
+      // chunks past the live rows (uniform); not taken at CH = 16, where the
+      // extra control flow would push the 128-register budget into scratch
+      if (CH <= 8 && t * 64 >= rows) continue;
       const int r = t * 64 + lane;
       const bool act = r < rows && !((used >> t) & 1u);
       const T l = act ? cmul(colbuf[b][r], inv) : cx<T>::make(0.0, 0.0);
 #pragma unroll
-      for (int u = 0; u < CPW; ++u) x[t][u] = csub(x[t][u], cmul(l, pv[u]));  // finished columns: pv = 0
+      for (int u = 0; u < CPW; ++u) {
+        const int j = wave + NW * u;
+        if (j > c && j < kb) x[t][u] = csub(x[t][u], cmul(l, pv[u]));  // wave-uniform
+      }
       if (own && r < rows) {
         const T vn = (CPW == 1 || un == 0) ? x[t][0] : x[t][CPW - 1];
         cbn[r] = vn;
