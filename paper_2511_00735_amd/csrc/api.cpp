@@ -296,23 +296,24 @@ Layout make_layout(const hps_desc* d, int nq) {
     // (2m x 2m), (e x m), (2m x 2e) per merge level and (nL/2 x nL/2) for the
     // coarse pair
     size_t mx = 0;
-    auto need = [&](int M, int K, int batch) {
+    auto need = [&](int M, int K, int batch, bool always) {
       const int ns = gemv_nsplit(M, K, batch);
-      if (ns > 1) mx = std::max(mx, (size_t)ns * batch * M);
+      if (ns > 1 || always) mx = std::max(mx, (size_t)ns * batch * M);
     };
     for (int l = 1; l <= lay.L; ++l) {
       const Level& lv = lay.lev[l];
       if (!lv.has_merge) continue;
       const int np = nq * lv.pairs;
-      need(2 * lv.m, 2 * lv.m, np);
-      need(lv.e, lv.m, np);
-      need(2 * lv.m, 2 * lv.e, np);
+      need(2 * lv.m, 2 * lv.m, np, true);  // A^-1 r_x: partial sums even unsplit
+      need(lv.e, lv.m, np, false);
+      need(2 * lv.m, 2 * lv.e, np, false);
     }
     if (lay.nL > 0) {  // the coarse pair-form product always goes through partial sums
       const int ns = gemv_nsplit(lay.nL / 2, lay.nL / 2, nq);
       mx = std::max(mx, (size_t)ns * nq * (lay.nL / 2));
     }
-    lay.gpart_elems = 2 * mx + 64;
+    // two descriptors' partials, plus those of A^-1 r_x consumed by the T products
+    lay.gpart_elems = 3 * mx + 128;
     lay.gpart_off = take(sizeof(cd) * lay.gpart_elems);
   }
   lay.flag_off = take(sizeof(int) * 4);
@@ -586,6 +587,20 @@ VecIn vin_compact(const cd* ptr, long long stride) {
   v.stride = stride;
   return v;
 }
+// x = the sum of a (pM x pbatch) GEMV's split-K partials from row proff on;
+// row tile 0 stores it at save + b * save_stride + proff.
+VecIn vin_partials(const cd* ps, int pns, int pbatch, int pM, int proff, cd* save, long long save_stride) {
+  VecIn v{};
+  v.ps = ps;
+  v.pns = pns;
+  v.pbatch = pbatch;
+  v.pM = pM;
+  v.proff = proff;
+  v.save = save;
+  v.save_stride = save_stride;
+  v.save_off = proff;
+  return v;
+}
 VecIn vin_table(const cd* vec, const int* tab, long long tstride) {
   VecIn v{};
   v.vec = vec;
@@ -639,16 +654,22 @@ hps_status vcycle_down_t(hps_problem* p, int l, cd* wv) {
   cd* Z0 = at<cd>(p, lv.Z0_off);
   const int* dtab = at<int>(p, lv.dtab_off);
   cd* part = at<cd>(p, p->lay.gpart_off);
+  // z0 = A^-1 r_x as split-K partial sums only: the T products below sum them
+  // while staging their x (and row tile 0 stores z0 in Z0), so no reduction
+  // launch sits between the two products
   GemvDescT<M> d0 = gdesc<M>(m2, m2, OperandT<M>{at<M>(p, lv.Ainv_off), (long long)m2 * m2, m2, im_off(0), im_off(0)},
-                             vin_table(wv, at<int>(p, lv.xtab_off), m2), vout_compact(Z0, m2));
-  HIPCHK(c, zgemv_batched(&d0, 1, np, part, st));
+                             vin_table(wv, at<int>(p, lv.xtab_off), m2), vout_compact(nullptr, 0));
+  GemvPartLayout pl{};
+  HIPCHK(c, zgemv_partials(&d0, 1, np, part, &pl, st));
+  const cd* pz = part + pl.poff[0];
+  cd* part2 = part + up256(sizeof(cd) * (size_t)pl.nsplit[0] * np * m2) / sizeof(cd);
   VecOut oP{}, oQ{};
   vout_table(oP, wv, dtab, 2 * e, true);
   vout_table(oQ, wv, dtab + e, 2 * e, true);
-  GemvDescT<M> d[2] = {gdesc<M>(e, m, OperandT<M>{T, ps, b, lv.E1, im_off(lv.a0)}, vin_compact(Z0 + m, m2), oP),
+  GemvDescT<M> d[2] = {gdesc<M>(e, m, OperandT<M>{T, ps, b, lv.E1, im_off(lv.a0)}, vin_partials(pz, pl.nsplit[0], np, m2, m, Z0, m2), oP),
                        gdesc<M>(e, m, OperandT<M>{T + (size_t)b * b, ps, b, lv.E2, im_off(lv.b0)},
-                                vin_compact(Z0, m2), oQ)};
-  HIPCHK(c, zgemv_batched(d, 2, np, part, st));
+                                vin_partials(pz, pl.nsplit[0], np, m2, 0, Z0, m2), oQ)};
+  HIPCHK(c, zgemv_batched(d, 2, np, part2, st));
   return HPS_OK;
 }
 

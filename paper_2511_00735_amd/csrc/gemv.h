@@ -9,14 +9,22 @@ constexpr int kGemvKChunkMax = 2048;     // K entries staged in LDS per split
 constexpr int kGemvTargetBlocks = 1024;  // split-K aims at this many workgroups
 
 // Source of a GEMV's x vector for batch entry (pair) b: a compact array
-// p[b*stride + k], or the canonical vector gathered through a slot table,
-// vec[tab[b*tstride + k]] (negative slot: 0).
+// p[b*stride + k], the canonical vector gathered through a slot table,
+// vec[tab[b*tstride + k]] (negative slot: 0), or the sum in split order of
+// another GEMV's split-K partials, sum_s ps[(s*pbatch + b)*pM + proff + k]
+// (s < pns), which the workgroups of row tile 0 also store at
+// save[b*save_stride + save_off + k].
 struct VecIn {
   const cd* p;
   long long stride;
   const cd* vec;
   const int* tab;
   long long tstride;
+  const cd* ps;
+  int pns, pbatch, pM, proff;
+  cd* save;
+  long long save_stride;
+  int save_off;
 };
 
 // Destination of y = alpha A x (+ beta y0): a compact array and/or a scatter into

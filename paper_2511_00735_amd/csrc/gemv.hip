@@ -17,6 +17,21 @@ constexpr int kRowsT = 64;   // rows per tile (one per lane)
 constexpr int kThreads = 256;
 
 __device__ inline cd load_x(const VecIn& x, int b, int k) {
+  if (x.ps) {
+    const cd* pp = x.ps + (long long)b * x.pM + x.proff + k;
+    const long long ss = (long long)x.pbatch * x.pM;
+    cd s = cmk(0.0, 0.0);
+    int q = 0;
+    for (; q + 4 <= x.pns; q += 4) {  // four loads in flight, summed in split order
+      cd v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = pp[(q + u) * ss];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) s = cadd(s, v[u]);
+    }
+    for (; q < x.pns; ++q) s = cadd(s, pp[q * ss]);
+    return s;
+  }
   if (x.p) return x.p[(long long)b * x.stride + k];
   const int s = x.tab[(long long)b * x.tstride + k];
   return s >= 0 ? x.vec[s] : cmk(0.0, 0.0);
@@ -63,7 +78,11 @@ __global__ __launch_bounds__(NT) void gemv_kernel(GemvBatchT<Mt> gb, cd* partial
 #pragma unroll
     for (int u = 0; u < U; ++u) a0[u] = Ab[(long long)imap(d.A.c, min(k0 + grp + NW * u, k1 - 1)) * d.A.ld + row];
   }
-  for (int k = k0 + t; k < k1; k += NT) xs[k - k0] = load_x(d.x, b, k);
+  for (int k = k0 + t; k < k1; k += NT) {
+    const cd v = load_x(d.x, b, k);
+    xs[k - k0] = v;
+    if (d.x.save && tile == 0) d.x.save[(long long)b * d.x.save_stride + d.x.save_off + k] = v;
+  }
   __syncthreads();
   cd acc = cmk(0.0, 0.0);
   if (rok) {
@@ -452,6 +471,7 @@ hipError_t vc_up_small(const SmallLevelT<Mt>& a, int pairs, cd* z, hipStream_t s
 template hipError_t zgemv_batched<cd>(const GemvDescT<cd>*, int, int, cd*, hipStream_t);
 template hipError_t zgemv_batched<cf>(const GemvDescT<cf>*, int, int, cd*, hipStream_t);
 template hipError_t zgemv_partials<cd>(const GemvDescT<cd>*, int, int, cd*, GemvPartLayout*, hipStream_t, int);
+template hipError_t zgemv_partials<cf>(const GemvDescT<cf>*, int, int, cd*, GemvPartLayout*, hipStream_t, int);
 template hipError_t vc_down_small<cd>(const SmallLevelT<cd>&, int, cd*, hipStream_t);
 template hipError_t vc_down_small<cf>(const SmallLevelT<cf>&, int, cd*, hipStream_t);
 template hipError_t vc_up_small<cd>(const SmallLevelT<cd>&, int, cd*, hipStream_t);
