@@ -98,10 +98,12 @@ class Server:
     """Runs a request trace through the library in real time.
 
     precision: "mixed" or "fp64"; workers: concurrent batches (streams);
-    memory_budget: device bytes the admitted batches may hold together."""
+    memory_budget: device bytes the admitted batches may hold together;
+    graphs: each worker replays its V-cycles from HIP graphs (several host
+    threads launching at once)."""
 
     def __init__(self, precision="mixed", workers=3, max_batch=32, memory_budget=200 << 30, tol=1e-8,
-                 coarse_iters=5, restart=60, maxit=600, keep_solutions=False):
+                 coarse_iters=5, restart=60, maxit=600, keep_solutions=False, graphs=True):
         import torch
         from . import hps
         self.torch = torch
@@ -116,6 +118,7 @@ class Server:
         self.restart = restart
         self.maxit = maxit
         self.keep = keep_solutions
+        self.graphs = bool(graphs)
         self.solutions = {}
         self._coords = {}
         self._coord_lock = threading.Lock()
@@ -220,6 +223,7 @@ class Server:
         def worker():
             stream = torch.cuda.Stream()
             ctx = hps.Context(stream)
+            ctx.set_graphs(self.graphs)
             try:
                 while True:
                     with cond:
