@@ -131,8 +131,9 @@ hps_status hps_sync(hps_ctx* ctx);
    graph captured once per problem (on a private capture stream) instead of
    launching its kernels one by one.  Results are bitwise identical either way.
    The graph reads and writes buffers of its own (two vector copies per
-   application), so it pays only where the host cannot keep ahead of the GPU;
-   the solver's own loop launches eagerly fast enough.
+   application), so it pays only where the host cannot keep ahead of the GPU,
+   e.g. several host threads launching on one device at once; a single
+   solver loop launches eagerly fast enough.
    HPS_OPT_TIMING (default 0): profiling aid.  Setting it (either value)
    synchronises and discards earlier records; while it is 1, every launch of a
    timed kernel is bracketed by HIP events recorded on the context's stream (the
