@@ -11,13 +11,14 @@ Metric: skeleton DOF per second = 4 (N-1) n (n-1) / (build + solve time).
 The headline run is the mixed-precision path; the plain FP64 path runs on the
 same inputs beside it.
 
-Roofline: the dominant kernel is the leaf kernel (one launch per 1024
-elements).  Its launches inside the timed steps are bracketed by HIP events on
+Roofline: the dominant kernel is the leaf kernel (one launch per up to 4096
+elements: the whole 64x64 leaf level).  Its launches inside the timed steps are bracketed by HIP events on
 the library's stream (library option HPS_OPT_TIMING); achieved = algorithmic
 leaf flops of the elements a launch builds / the mean launch duration.  The HBM
 traffic per launch comes from the rocprofv3 counter summary under profiles/
 (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy kernel's readings), and is
-reported only while the leaf kernel source still matches the one measured.
+reported only while the leaf kernel source and the elements per launch still
+match the ones measured.
 
 Prints ONE JSON line (see the repository documentation for the fields).
 --traffic-probe instead runs one 1 GiB device copy (the counter calibration)
@@ -78,7 +79,8 @@ def leaf_flops_algorithmic(N):
 
 
 def leaf_traffic_record():
-    """(bytes per launch, source hash) from the committed counter summary, or None."""
+    """(bytes per launch, source hash, elements per launch) from the committed
+    counter summary, or None."""
     try:
         lines = open(TRAFFIC_FILE).read().splitlines()
     except OSError:
@@ -89,7 +91,8 @@ def leaf_traffic_record():
             k, v = ln[2:].split(": ", 1)
             rec[k.strip()] = v.strip().strip("`")
     try:
-        return float(rec["traffic_bytes_per_launch"]), rec["leaf_source_sha256"]
+        return (float(rec["traffic_bytes_per_launch"]), rec["leaf_source_sha256"],
+                float(rec["elements_per_launch"]))
     except KeyError:
         return None
 
@@ -320,7 +323,7 @@ def main():
     rec = leaf_traffic_record()
     if rec is not None:
         src_hash = hashlib.sha256(open(LEAF_SOURCE, "rb").read()).hexdigest()
-        if src_hash == rec[1] and per_launch_units == 1024:
+        if src_hash == rec[1] and per_launch_units == rec[2]:
             traffic = rec[0]
     roof = {"bound": "alu", "achieved": round(ach, 3), "peak": MI355X_FP64_TFLOPS, "unit": "TFLOP/s",
             "frac": round(ach / MI355X_FP64_TFLOPS, 4), "traffic": traffic,

@@ -16,6 +16,13 @@
 #include "solve.h"
 #include "gemv.h"
 
+// Elements per leaf launch (each holds its bordered matrix, ~0.65 MB at
+// N = 16, in the scratch buffer while it is factored).  One launch of many
+// rounds of workgroups ends with one tail instead of one per launch.
+#ifndef HPS_LEAF_CHUNK
+#define HPS_LEAF_CHUNK 4096
+#endif
+
 // One timed launch: events recorded on the context's stream around it.
 struct TimedLaunch {
   hipEvent_t start, stop;
@@ -227,7 +234,7 @@ Layout make_layout(const hps_desc* d, int nq) {
   lay.k = lay.exact ? 0 : d->coarse_iters;
   lay.restart = d->restart ? d->restart : 60;
   lay.nslots = (long long)lay.E * 4 * lay.p;
-  lay.leaf_chunk = (int)std::min<long long>((long long)lay.E * nq, 1024);
+  lay.leaf_chunk = (int)std::min<long long>((long long)lay.E * nq, HPS_LEAF_CHUNK);
   const size_t Q = (size_t)nq;
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off += up256(bytes); return o; };
