@@ -48,6 +48,10 @@ namespace hps {
 namespace {
 
 constexpr int kNB = 32;          // panel width of the blocked LU
+#ifndef HPS_LEAF_PF
+#define HPS_LEAF_PF 3
+#endif
+constexpr int kPF = HPS_LEAF_PF;  // trailing-update column groups in flight per lane
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 constexpr int kCPW = kNB / kWaves;  // panel columns per wave
@@ -579,23 +583,32 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_kernel(LeafArgs a) {
         for (int qq = 0; qq < kNB; ++qq) l[qq] = (live && qq < kb) ? lrow[(size_t)qq * nloc] : 0.0;
       }
       double* arow = A + (size_t)c0 * nloc + k0 + y;
-      int cg = wave;
-      double nx[4];
+      // kPF column groups of A22 in flight per lane (a ring indexed at compile
+      // time): one group's products take far less than a memory round trip
+      double nx[kPF][4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int cc = cg * 4 + u;
-        nx[u] = (live && cg < CG && cc < nc && !first) ? arow[(size_t)cc * nloc] : 0.0;
+      for (int p = 0; p < kPF; ++p) {
+        const int cgp = wave + p * kWaves;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int cc = cgp * 4 + u;
+          nx[p][u] = (live && cgp < CG && cc < nc && !first) ? arow[(size_t)cc * nloc] : 0.0;
+        }
       }
 #pragma unroll 1
-      for (; cg < CG; cg += kWaves) {
+      for (int cb = wave; cb < CG; cb += kWaves * kPF) {
+#pragma unroll
+      for (int p = 0; p < kPF; ++p) {
+        const int cg = cb + p * kWaves;
+        if (cg >= CG) break;   // uniform over the wave
         double s[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) s[u] = nx[u];
-        const int cn = cg + kWaves;
+        for (int u = 0; u < 4; ++u) s[u] = nx[p][u];
+        const int cn = cg + kPF * kWaves;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int cc = cn * 4 + u;
-          nx[u] = (live && cn < CG && cc < nc && !first) ? arow[(size_t)cc * nloc] : 0.0;
+          nx[p][u] = (live && cn < CG && cc < nc && !first) ? arow[(size_t)cc * nloc] : 0.0;
         }
         const double2* Ub = reinterpret_cast<const double2*>(U + cg * 4);
         // four U12 rows at a time keep the register footprint at two waves per SIMD
@@ -623,6 +636,7 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_kernel(LeafArgs a) {
           for (int u = 0; u < 4; ++u)
             if (cg * 4 + u < nc) arow[(size_t)(cg * 4 + u) * nloc] = s[u];
         }
+      }
       }
     }
     __syncthreads();
