@@ -536,18 +536,45 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_kernel(LeafArgs a) {
       L11[idx] = (qq < r && r < kb) ? A[(size_t)(k0 + qq) * nloc + k0 + piv_s[r]] : 0.0;
     }
     // ---- row interchanges on the trailing columns; U12 gathered ----
-    for (int idx = tid; idx < kNB * nc; idx += kThreads) {
-      const int qq = idx % kNB, cc = idx / kNB;
-      if (qq < kb && first) {
-        U[qq * ldu + cc] = K(piv_s[qq], c0 + cc);   // the trailing update reads K through rowmap
-      } else if (qq < kb) {
-        double* col = A + (size_t)(c0 + cc) * nloc + k0;
-        const int y = piv_s[qq];
-        U[qq * ldu + cc] = col[y];
-        const int x = dsrc_s[qq];
-        if (x >= 0) col[y] = col[x];
-      } else {
-        U[qq * ldu + cc] = 0.0;   // rows past a short last panel take part in the update
+    // Two passes, eight loads in flight per thread in each: the pivot rows of
+    // the trailing columns into U12 (rows past a short last panel are zero and
+    // take part in the update; the first panel reads K, whose trailing update
+    // goes through rowmap), then the non-pivot rows among the first kb into
+    // the vacated pivot slots.  A thread handles the same entries in both
+    // passes, so each slot is read before it is overwritten.
+    const int nu = kNB * nc;
+    for (int base = tid; base < nu; base += 8 * kThreads) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int idx = base + u * kThreads;
+        const int qq = idx % kNB, cc = idx / kNB;
+        v[u] = 0.0;
+        if (idx < nu && qq < kb)
+          v[u] = first ? K(piv_s[qq], c0 + cc) : A[(size_t)(c0 + cc) * nloc + k0 + piv_s[qq]];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int idx = base + u * kThreads;
+        if (idx < nu) U[(idx % kNB) * ldu + idx / kNB] = v[u];
+      }
+    }
+    if (!first) {
+      for (int base = tid; base < nu; base += 8 * kThreads) {
+        double v[8];
+        double* dst[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int idx = base + u * kThreads;
+          const int qq = idx % kNB, cc = idx / kNB;
+          const int x = (idx < nu && qq < kb) ? dsrc_s[qq] : -1;
+          double* col = A + (size_t)(c0 + cc) * nloc + k0;
+          dst[u] = x >= 0 ? col + piv_s[qq] : nullptr;
+          v[u] = x >= 0 ? col[x] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (dst[u]) *dst[u] = v[u];
       }
     }
     __syncthreads();
