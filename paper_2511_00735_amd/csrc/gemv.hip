@@ -292,30 +292,34 @@ __global__ __launch_bounds__(NT) void vc_down_small_kernel(SmallLevelT<Mt> a, cd
   if (t < e && ds[t] >= 0) vec[ds[t]] = dd[t];
 }
 
-// Up sweep, half h of pair j: rows [h m, (h+1) m) of x = z0 + X y, y the
-// kept-face values of z, written into z at the shared-face slots.
+// Up sweep, piece p of pair j (workgroup P j + p): rows [p R, p R + M) of
+// x = z0 + X y (R = ceil(2m / P), M = min(R, 2m - p R)), y the kept-face
+// values of z, written into z at the shared-face slots.  The rows are
+// independent, so levels with few pairs split them over more workgroups.
 template <class Mt, int NT>
-__global__ __launch_bounds__(NT) void vc_up_small_kernel(SmallLevelT<Mt> a, cd* z) {
+__global__ __launch_bounds__(NT) void vc_up_small_kernel(SmallLevelT<Mt> a, cd* z, int P) {
   extern __shared__ cd sm[];
   const int m = a.m, e = a.e, m2 = 2 * m, e2 = 2 * e;
-  const int j = blockIdx.x >> 1, h = blockIdx.x & 1, t = threadIdx.x;
+  const int j = blockIdx.x / P, pc = blockIdx.x - j * P, t = threadIdx.x;
+  const int R = (m2 + P - 1) / P, r0 = pc * R, M = min(R, m2 - r0);
+  if (M <= 0) return;   // uniform over the workgroup
   cd* y = sm;          // [2e]
-  cd* z0 = y + e2;     // [m]
-  cd* x = z0 + m;      // [m]
-  cd* red = x + m;     // [NT]
+  cd* z0 = y + e2;     // [R]
+  cd* x = z0 + R;      // [R]
+  cd* red = x + R;     // [NT]
   const int yi = t < e2 ? a.ytab[(long long)j * e2 + t] : -1;
-  const int xi = t < m ? a.xtab[(long long)j * m2 + h * m + t] : -1;
-  const cd zv = t < m ? a.Z0[(long long)j * m2 + h * m + t] : cmk(0.0, 0.0);
+  const int xi = t < M ? a.xtab[(long long)j * m2 + r0 + t] : -1;
+  const cd zv = t < M ? a.Z0[(long long)j * m2 + r0 + t] : cmk(0.0, 0.0);
   RegGemv<Mt, NT, SmallCap<Mt>::X> gx;
-  gx.setup(m, e2);
+  gx.setup(M, e2);
   const Mt* Xj = a.X + (long long)j * m2 * e2;
-  const IdxMap xrow = im_off(h * m);
+  const IdxMap xrow = im_off(r0);
   gx.load(Xj, m2, xrow, im_off(0));
   if (t < e2) y[t] = yi >= 0 ? z[yi] : cmk(0.0, 0.0);
-  if (t < m) z0[t] = zv;
+  if (t < M) z0[t] = zv;
   __syncthreads();
   gx.run(Xj, m2, xrow, im_off(0), y, z0, x, red);
-  if (t < m) z[xi] = x[t];
+  if (t < M) z[xi] = x[t];
 }
 
 }  // namespace
@@ -413,6 +417,10 @@ int small_threads(long long entries, int need, int pairs) {
 }
 size_t small_down_lds(int m, int e, int nt) { return sizeof(cd) * (size_t)(3 * m + 2 * e + nt) + sizeof(int) * e; }
 size_t small_up_lds(int m, int e, int nt) { return sizeof(cd) * (size_t)(2 * e + 2 * m + nt); }
+#ifndef HPS_SMALL_UP_WGS
+#define HPS_SMALL_UP_WGS 256
+#endif
+constexpr long long kSmallUpWGs = HPS_SMALL_UP_WGS;
 
 template <class Mt, int NT>
 hipError_t launch_down(const SmallLevelT<Mt>& a, int pairs, cd* vec, hipStream_t st) {
@@ -424,11 +432,11 @@ hipError_t launch_down(const SmallLevelT<Mt>& a, int pairs, cd* vec, hipStream_t
 }
 
 template <class Mt, int NT>
-hipError_t launch_up(const SmallLevelT<Mt>& a, int pairs, cd* z, hipStream_t st) {
+hipError_t launch_up(const SmallLevelT<Mt>& a, int pairs, int P, cd* z, hipStream_t st) {
   const size_t lds = small_up_lds(a.m, a.e, NT);
   hipError_t err = allow_lds(vc_up_small_kernel<Mt, NT>, lds);
   if (err != hipSuccess) return err;
-  hipLaunchKernelGGL((vc_up_small_kernel<Mt, NT>), dim3(2 * pairs), dim3(NT), lds, st, a, z);
+  hipLaunchKernelGGL((vc_up_small_kernel<Mt, NT>), dim3(P * pairs), dim3(NT), lds, st, a, z, P);
   return hipPeekAtLastError();
 }
 
@@ -459,12 +467,17 @@ template <class Mt>
 hipError_t vc_up_small(const SmallLevelT<Mt>& a, int pairs, cd* z, hipStream_t st) {
   if (!vc_small_ok(a.m, a.e, pairs)) return hipErrorInvalidValue;
   const int m = a.m, e = a.e;
-  switch (small_threads(2LL * m * e, std::max(2 * e, m), pairs)) {
-    case 64: return launch_up<Mt, 64>(a, pairs, z, st);
-    case 128: return launch_up<Mt, 128>(a, pairs, z, st);
-    case 256: return launch_up<Mt, 256>(a, pairs, z, st);
-    case 512: return launch_up<Mt, 512>(a, pairs, z, st);
-    default: return launch_up<Mt, 1024>(a, pairs, z, st);
+  // row pieces per pair: at least two, more while the level has fewer than
+  // kSmallUpWGs workgroups and a piece keeps at least 16 rows
+  int P = 2;
+  while ((long long)P * pairs < kSmallUpWGs && 2 * m >= 2 * P * 16) P *= 2;
+  const int R = (2 * m + P - 1) / P;
+  switch (small_threads((long long)R * 2 * e, std::max(2 * e, R), pairs * P / 2)) {
+    case 64: return launch_up<Mt, 64>(a, pairs, P, z, st);
+    case 128: return launch_up<Mt, 128>(a, pairs, P, z, st);
+    case 256: return launch_up<Mt, 256>(a, pairs, P, z, st);
+    case 512: return launch_up<Mt, 512>(a, pairs, P, z, st);
+    default: return launch_up<Mt, 1024>(a, pairs, P, z, st);
   }
 }
 
