@@ -687,7 +687,7 @@ hps_status vcycle_up_t(hps_problem* p, int l, cd* z) {
   hps_ctx* c = p->ctx;
   hipStream_t st = c->stream;
   const Level& lv = p->lay.lev[l];
-  if (small_level(lv, p->lay.nq)) {
+  if (vc_up_small_ok(lv.m, lv.e, p->lay.nq * lv.pairs)) {
     HIPCHK(c, vc_up_small(small_args<M>(p, lv), p->lay.nq * lv.pairs, z, st));
     return HPS_OK;
   }

@@ -100,8 +100,11 @@ struct SmallLevelT {
   const int* dtab;
   cd* Z0;
 };
-// Levels these kernels take: at least 128 pairs, 2m and 2e at most 1024.
+// Levels the down-sweep kernel takes (at least 32 pairs, 2m and 2e at most
+// 1024), and those the up-sweep kernel takes (any whose row piece and 2e
+// values fit its LDS).
 bool vc_small_ok(int m, int e, int pairs);
+bool vc_up_small_ok(int m, int e, int pairs);
 template <class M>
 hipError_t vc_down_small(const SmallLevelT<M>& a, int pairs, cd* vec, hipStream_t st);
 template <class M>

@@ -295,7 +295,8 @@ __global__ __launch_bounds__(NT) void vc_down_small_kernel(SmallLevelT<Mt> a, cd
 // Up sweep, piece p of pair j (workgroup P j + p): rows [p R, p R + M) of
 // x = z0 + X y (R = ceil(2m / P), M = min(R, 2m - p R)), y the kept-face
 // values of z, written into z at the shared-face slots.  The rows are
-// independent, so levels with few pairs split them over more workgroups.
+// independent, so levels with few pairs split them over many workgroups,
+// each of which forms complete rows (no partial sums to reduce).
 template <class Mt, int NT>
 __global__ __launch_bounds__(NT) void vc_up_small_kernel(SmallLevelT<Mt> a, cd* z, int P) {
   extern __shared__ cd sm[];
@@ -307,7 +308,10 @@ __global__ __launch_bounds__(NT) void vc_up_small_kernel(SmallLevelT<Mt> a, cd* 
   cd* z0 = y + e2;     // [R]
   cd* x = z0 + R;      // [R]
   cd* red = x + R;     // [NT]
-  const int yi = t < e2 ? a.ytab[(long long)j * e2 + t] : -1;
+  constexpr int kY = 4;   // y entries gathered per thread with their loads in flight together
+  int yi[kY];
+#pragma unroll
+  for (int u = 0; u < kY; ++u) yi[u] = t + u * NT < e2 ? a.ytab[(long long)j * e2 + t + u * NT] : -1;
   const int xi = t < M ? a.xtab[(long long)j * m2 + r0 + t] : -1;
   const cd zv = t < M ? a.Z0[(long long)j * m2 + r0 + t] : cmk(0.0, 0.0);
   RegGemv<Mt, NT, SmallCap<Mt>::X> gx;
@@ -315,7 +319,13 @@ __global__ __launch_bounds__(NT) void vc_up_small_kernel(SmallLevelT<Mt> a, cd* 
   const Mt* Xj = a.X + (long long)j * m2 * e2;
   const IdxMap xrow = im_off(r0);
   gx.load(Xj, m2, xrow, im_off(0));
-  if (t < e2) y[t] = yi >= 0 ? z[yi] : cmk(0.0, 0.0);
+#pragma unroll
+  for (int u = 0; u < kY; ++u)
+    if (t + u * NT < e2) y[t + u * NT] = yi[u] >= 0 ? z[yi[u]] : cmk(0.0, 0.0);
+  for (int i = t + kY * NT; i < e2; i += NT) {
+    const int s = a.ytab[(long long)j * e2 + i];
+    y[i] = s >= 0 ? z[s] : cmk(0.0, 0.0);
+  }
   if (t < M) z0[t] = zv;
   __syncthreads();
   gx.run(Xj, m2, xrow, im_off(0), y, z0, x, red);
@@ -416,11 +426,24 @@ int small_threads(long long entries, int need, int pairs) {
   return nt;
 }
 size_t small_down_lds(int m, int e, int nt) { return sizeof(cd) * (size_t)(3 * m + 2 * e + nt) + sizeof(int) * e; }
-size_t small_up_lds(int m, int e, int nt) { return sizeof(cd) * (size_t)(2 * e + 2 * m + nt); }
+// up-sweep LDS for pieces of R rows: y [2e], z0 and x [R], red [nt]
+size_t small_up_lds(int R, int e, int nt) { return sizeof(cd) * (size_t)(2 * e + 2 * R + nt); }
 #ifndef HPS_SMALL_UP_WGS
 #define HPS_SMALL_UP_WGS 256
 #endif
 constexpr long long kSmallUpWGs = HPS_SMALL_UP_WGS;
+#ifndef HPS_SMALL_UP_ROWS
+#define HPS_SMALL_UP_ROWS 4
+#endif
+constexpr int kSmallUpRows = HPS_SMALL_UP_ROWS;
+
+// Row pieces per pair for the up sweep: at least two, more while the level has
+// fewer than kSmallUpWGs workgroups and a piece keeps at least kSmallUpRows rows.
+int up_pieces(int m, int pairs) {
+  int P = 2;
+  while ((long long)P * pairs < kSmallUpWGs && 2 * m >= 2 * P * kSmallUpRows) P *= 2;
+  return P;
+}
 
 template <class Mt, int NT>
 hipError_t launch_down(const SmallLevelT<Mt>& a, int pairs, cd* vec, hipStream_t st) {
@@ -433,7 +456,7 @@ hipError_t launch_down(const SmallLevelT<Mt>& a, int pairs, cd* vec, hipStream_t
 
 template <class Mt, int NT>
 hipError_t launch_up(const SmallLevelT<Mt>& a, int pairs, int P, cd* z, hipStream_t st) {
-  const size_t lds = small_up_lds(a.m, a.e, NT);
+  const size_t lds = small_up_lds((2 * a.m + P - 1) / P, a.e, NT);
   hipError_t err = allow_lds(vc_up_small_kernel<Mt, NT>, lds);
   if (err != hipSuccess) return err;
   hipLaunchKernelGGL((vc_up_small_kernel<Mt, NT>), dim3(P * pairs), dim3(NT), lds, st, a, z, P);
@@ -445,9 +468,15 @@ hipError_t launch_up(const SmallLevelT<Mt>& a, int pairs, int P, cd* z, hipStrea
 #ifndef HPS_SMALL_MIN_PAIRS
 #define HPS_SMALL_MIN_PAIRS 32
 #endif
+bool vc_up_small_ok(int m, int e, int pairs) {
+  if (pairs < 1 || m < 1 || e < 1) return false;
+  const int P = up_pieces(m, pairs), R = (2 * m + P - 1) / P;
+  return R <= 1024 && small_up_lds(R, e, 1024) <= 64 * 1024;
+}
+
 bool vc_small_ok(int m, int e, int pairs) {
   return pairs >= HPS_SMALL_MIN_PAIRS && m >= 1 && e >= 1 && 2 * m <= 1024 && 2 * e <= 1024 &&
-         small_down_lds(m, e, 1024) <= 64 * 1024 && small_up_lds(m, e, 1024) <= 64 * 1024;
+         small_down_lds(m, e, 1024) <= 64 * 1024;
 }
 
 template <class Mt>
@@ -465,14 +494,11 @@ hipError_t vc_down_small(const SmallLevelT<Mt>& a, int pairs, cd* vec, hipStream
 
 template <class Mt>
 hipError_t vc_up_small(const SmallLevelT<Mt>& a, int pairs, cd* z, hipStream_t st) {
-  if (!vc_small_ok(a.m, a.e, pairs)) return hipErrorInvalidValue;
+  if (!vc_up_small_ok(a.m, a.e, pairs)) return hipErrorInvalidValue;
   const int m = a.m, e = a.e;
-  // row pieces per pair: at least two, more while the level has fewer than
-  // kSmallUpWGs workgroups and a piece keeps at least 16 rows
-  int P = 2;
-  while ((long long)P * pairs < kSmallUpWGs && 2 * m >= 2 * P * 16) P *= 2;
+  const int P = up_pieces(m, pairs);
   const int R = (2 * m + P - 1) / P;
-  switch (small_threads((long long)R * 2 * e, std::max(2 * e, R), pairs * P / 2)) {
+  switch (small_threads((long long)R * 2 * e, std::max(std::min(2 * e, 1024), R), pairs * P / 2)) {
     case 64: return launch_up<Mt, 64>(a, pairs, P, z, st);
     case 128: return launch_up<Mt, 128>(a, pairs, P, z, st);
     case 256: return launch_up<Mt, 256>(a, pairs, P, z, st);
