@@ -346,6 +346,10 @@ struct hps_problem {
   bool have_T1;
   hipGraphExec_t pgraph = nullptr;  // captured V-cycle (work vector 5 -> 6)
   bool graph_failed = false;
+  // pinned host copy of the group's Hessenberg columns, read back once per
+  // FGMRES iteration (a pageable destination is staged by the runtime)
+  cd* hbuf = nullptr;
+  size_t hbuf_elems = 0;
 };
 
 using namespace hps;
@@ -934,9 +938,17 @@ hps_status fgmres_group(hps_problem* p, const cd* rhs, cd* g, double tol, int ma
   cd* ysol = at<cd>(p, lay.ysol_off);
   const Geom& g1 = lay.lev[1].g;
   const cd* T1 = Tlev(p, 1);
-  std::vector<cd> host((size_t)HS * nq);
+  const size_t hn = (size_t)HS * nq;
+  if (p->hbuf_elems < hn) {
+    if (p->hbuf) (void)hipHostFree(p->hbuf);
+    p->hbuf = nullptr;
+    p->hbuf_elems = 0;
+    HIPCHK(c, hipHostMalloc(reinterpret_cast<void**>(&p->hbuf), sizeof(cd) * hn, hipHostMallocDefault));
+    p->hbuf_elems = hn;
+  }
+  const cd* host = p->hbuf;
   auto fetch = [&]() -> hps_status {
-    HIPCHK(c, hipMemcpyAsync(host.data(), hh, sizeof(cd) * host.size(), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipMemcpyAsync(p->hbuf, hh, sizeof(cd) * hn, hipMemcpyDeviceToHost, st));
     HIPCHK(c, hipStreamSynchronize(st));
     return HPS_OK;
   };
@@ -1301,6 +1313,7 @@ int32_t hps_group_size(const hps_problem* p) { return p ? p->lay.nq : 0; }
 
 hps_status hps_problem_destroy(hps_problem* p) {
   if (p && p->pgraph) (void)hipGraphExecDestroy(p->pgraph);
+  if (p && p->hbuf) (void)hipHostFree(p->hbuf);
   delete p;
   return HPS_OK;
 }
