@@ -346,10 +346,12 @@ struct hps_problem {
   bool have_T1;
   hipGraphExec_t pgraph = nullptr;  // captured V-cycle (work vector 5 -> 6)
   bool graph_failed = false;
-  // pinned host copy of the group's Hessenberg columns, read back once per
-  // FGMRES iteration (a pageable destination is staged by the runtime)
+  // pinned host copies (two, alternating) of the group's Hessenberg columns,
+  // read back once per FGMRES iteration (a pageable destination is staged by
+  // the runtime), and the events that mark each copy done
   cd* hbuf = nullptr;
   size_t hbuf_elems = 0;
+  hipEvent_t hev[2] = {nullptr, nullptr};
 };
 
 using namespace hps;
@@ -943,9 +945,11 @@ hps_status fgmres_group(hps_problem* p, const cd* rhs, cd* g, double tol, int ma
     if (p->hbuf) (void)hipHostFree(p->hbuf);
     p->hbuf = nullptr;
     p->hbuf_elems = 0;
-    HIPCHK(c, hipHostMalloc(reinterpret_cast<void**>(&p->hbuf), sizeof(cd) * hn, hipHostMallocDefault));
+    HIPCHK(c, hipHostMalloc(reinterpret_cast<void**>(&p->hbuf), sizeof(cd) * 2 * hn, hipHostMallocDefault));
     p->hbuf_elems = hn;
   }
+  for (int i = 0; i < 2; ++i)
+    if (!p->hev[i]) HIPCHK(c, hipEventCreateWithFlags(&p->hev[i], hipEventDisableTiming));
   const cd* host = p->hbuf;
   auto fetch = [&]() -> hps_status {
     HIPCHK(c, hipMemcpyAsync(p->hbuf, hh, sizeof(cd) * hn, hipMemcpyDeviceToHost, st));
@@ -992,20 +996,49 @@ hps_status fgmres_group(hps_problem* p, const cd* rhs, cd* g, double tol, int ma
     }
     if (active == 0) break;
     HIPCHK(c, normalize(res, nrm2, V, n, nullptr, st, nq, HS, 0));
-    for (int j = 0; j < R; ++j) {
-      s = precond_any(p, V + (size_t)j * ntot, Z + (size_t)j * ntot);
-      if (s != HPS_OK) return s;
+    // Iteration j on the device: V-cycle, M_1 product, CGS2, V_{j+1}, and its
+    // Hessenberg column copied to host buffer j % 2.  The next iteration needs
+    // nothing from the host, so it is enqueued before the host waits for this
+    // one's column (its writes to hh follow the copy in stream order), unless
+    // the convergence rate so far predicts that this one reaches the tolerance;
+    // a column computed past the stopping point is simply not used.
+    auto enqueue = [&](int j) -> hps_status {
+      hps_status e = precond_any(p, V + (size_t)j * ntot, Z + (size_t)j * ntot);
+      if (e != HPS_OK) return e;
       HIPCHK(c, skeleton_apply(g1, T1, Z + (size_t)j * ntot, w, true, st, nq));
-      s = cgs2(p, V, ntot, j + 1, w, n, hcol, h2, HS);
-      if (s != HPS_OK) return s;
+      e = cgs2(p, V, ntot, j + 1, w, n, hcol, h2, HS);
+      if (e != HPS_OK) return e;
       HIPCHK(c, multi_dot(w, 0, 1, w, n, part, nrm2, false, st, nq, HS));
       HIPCHK(c, normalize(w, nrm2, V + (size_t)(j + 1) * ntot, n, hnorm, st, nq, HS, HS));
-      s = fetch();
-      if (s != HPS_OK) return s;
+      HIPCHK(c, hipMemcpyAsync(p->hbuf + (size_t)(j & 1) * hn, hh, sizeof(cd) * hn, hipMemcpyDeviceToHost, st));
+      HIPCHK(c, hipEventRecord(p->hev[j & 1], st));
+      return HPS_OK;
+    };
+    std::vector<double> prev(nq, 1.0);
+    int enq = 0;  // iterations of this cycle enqueued
+    for (int j = 0; j < R; ++j) {
+      if (enq == j) {
+        s = enqueue(j);
+        if (s != HPS_OK) return s;
+        ++enq;
+      }
+      bool likely_last = false;
+      for (int q = 0; q < nq; ++q) {
+        if (!live[q] || j == 0) continue;
+        const double rate = std::min(1.0, est[q] / std::max(prev[q], 1e-300));
+        if (est[q] * rate <= 2.0 * tol || it[q] + 1 >= maxit) likely_last = true;
+      }
+      if (!likely_last && j + 1 < R) {
+        s = enqueue(j + 1);
+        if (s != HPS_OK) return s;
+        ++enq;
+      }
+      HIPCHK(c, hipEventSynchronize(p->hev[j & 1]));
       int still = 0;
       for (int q = 0; q < nq; ++q) {
         if (!live[q]) continue;
-        const cd* hq = &host[q * HS];
+        prev[q] = est[q];
+        const cd* hq = p->hbuf + (size_t)(j & 1) * hn + (size_t)q * HS;
         zc* col = &Hm[q][(size_t)j * (R + 1)];
         for (int i = 0; i <= j; ++i) col[i] = zc(hq[i].x, hq[i].y);
         col[j + 1] = zc(hq[2 * (R + 2) + 1].x, 0.0);
@@ -1314,6 +1347,8 @@ int32_t hps_group_size(const hps_problem* p) { return p ? p->lay.nq : 0; }
 hps_status hps_problem_destroy(hps_problem* p) {
   if (p && p->pgraph) (void)hipGraphExecDestroy(p->pgraph);
   if (p && p->hbuf) (void)hipHostFree(p->hbuf);
+  for (int i = 0; p && i < 2; ++i)
+    if (p->hev[i]) (void)hipEventDestroy(p->hev[i]);
   delete p;
   return HPS_OK;
 }
