@@ -37,6 +37,14 @@ struct hps_ctx {
   int use_graphs = 0;
   int timing = 0;
   std::vector<TimedLaunch> timed;
+  // pinned host copies (two, alternating) of a solve's Hessenberg columns,
+  // read back once per FGMRES iteration (a pageable destination is staged by
+  // the runtime), and the events that mark each copy done.  Held by the
+  // context and grown as needed, so that short-lived problems do not allocate
+  // and free pinned memory (a free can wait for the whole device).
+  void* hbuf = nullptr;
+  size_t hbuf_bytes = 0;
+  hipEvent_t hev[2] = {nullptr, nullptr};
 };
 
 namespace hps {
@@ -346,12 +354,6 @@ struct hps_problem {
   bool have_T1;
   hipGraphExec_t pgraph = nullptr;  // captured V-cycle (work vector 5 -> 6)
   bool graph_failed = false;
-  // pinned host copies (two, alternating) of the group's Hessenberg columns,
-  // read back once per FGMRES iteration (a pageable destination is staged by
-  // the runtime), and the events that mark each copy done
-  cd* hbuf = nullptr;
-  size_t hbuf_elems = 0;
-  hipEvent_t hev[2] = {nullptr, nullptr};
 };
 
 using namespace hps;
@@ -941,18 +943,21 @@ hps_status fgmres_group(hps_problem* p, const cd* rhs, cd* g, double tol, int ma
   const Geom& g1 = lay.lev[1].g;
   const cd* T1 = Tlev(p, 1);
   const size_t hn = (size_t)HS * nq;
-  if (p->hbuf_elems < hn) {
-    if (p->hbuf) (void)hipHostFree(p->hbuf);
-    p->hbuf = nullptr;
-    p->hbuf_elems = 0;
-    HIPCHK(c, hipHostMalloc(reinterpret_cast<void**>(&p->hbuf), sizeof(cd) * 2 * hn, hipHostMallocDefault));
-    p->hbuf_elems = hn;
+  if (c->hbuf_bytes < sizeof(cd) * 2 * hn) {
+    HIPCHK(c, hipStreamSynchronize(st));
+    if (c->hbuf) (void)hipHostFree(c->hbuf);
+    c->hbuf = nullptr;
+    c->hbuf_bytes = 0;
+    const size_t bytes = std::max<size_t>(sizeof(cd) * 2 * hn, 64 << 10);
+    HIPCHK(c, hipHostMalloc(&c->hbuf, bytes, hipHostMallocDefault));
+    c->hbuf_bytes = bytes;
   }
   for (int i = 0; i < 2; ++i)
-    if (!p->hev[i]) HIPCHK(c, hipEventCreateWithFlags(&p->hev[i], hipEventDisableTiming));
-  const cd* host = p->hbuf;
+    if (!c->hev[i]) HIPCHK(c, hipEventCreateWithFlags(&c->hev[i], hipEventDisableTiming));
+  cd* hbuf = static_cast<cd*>(c->hbuf);
+  const cd* host = hbuf;
   auto fetch = [&]() -> hps_status {
-    HIPCHK(c, hipMemcpyAsync(p->hbuf, hh, sizeof(cd) * hn, hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipMemcpyAsync(hbuf, hh, sizeof(cd) * hn, hipMemcpyDeviceToHost, st));
     HIPCHK(c, hipStreamSynchronize(st));
     return HPS_OK;
   };
@@ -1010,8 +1015,8 @@ hps_status fgmres_group(hps_problem* p, const cd* rhs, cd* g, double tol, int ma
       if (e != HPS_OK) return e;
       HIPCHK(c, multi_dot(w, 0, 1, w, n, part, nrm2, false, st, nq, HS));
       HIPCHK(c, normalize(w, nrm2, V + (size_t)(j + 1) * ntot, n, hnorm, st, nq, HS, HS));
-      HIPCHK(c, hipMemcpyAsync(p->hbuf + (size_t)(j & 1) * hn, hh, sizeof(cd) * hn, hipMemcpyDeviceToHost, st));
-      HIPCHK(c, hipEventRecord(p->hev[j & 1], st));
+      HIPCHK(c, hipMemcpyAsync(hbuf + (size_t)(j & 1) * hn, hh, sizeof(cd) * hn, hipMemcpyDeviceToHost, st));
+      HIPCHK(c, hipEventRecord(c->hev[j & 1], st));
       return HPS_OK;
     };
     std::vector<double> prev(nq, 1.0);
@@ -1033,12 +1038,12 @@ hps_status fgmres_group(hps_problem* p, const cd* rhs, cd* g, double tol, int ma
         if (s != HPS_OK) return s;
         ++enq;
       }
-      HIPCHK(c, hipEventSynchronize(p->hev[j & 1]));
+      HIPCHK(c, hipEventSynchronize(c->hev[j & 1]));
       int still = 0;
       for (int q = 0; q < nq; ++q) {
         if (!live[q]) continue;
         prev[q] = est[q];
-        const cd* hq = p->hbuf + (size_t)(j & 1) * hn + (size_t)q * HS;
+        const cd* hq = hbuf + (size_t)(j & 1) * hn + (size_t)q * HS;
         zc* col = &Hm[q][(size_t)j * (R + 1)];
         for (int i = 0; i <= j; ++i) col[i] = zc(hq[i].x, hq[i].y);
         col[j + 1] = zc(hq[2 * (R + 2) + 1].x, 0.0);
@@ -1222,6 +1227,9 @@ hps_status hps_ctx_destroy(hps_ctx* ctx) {
     (void)hipStreamSynchronize(ctx->stream);
     drop_timed(ctx);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    if (ctx->hbuf) (void)hipHostFree(ctx->hbuf);
+    for (int i = 0; i < 2; ++i)
+      if (ctx->hev[i]) (void)hipEventDestroy(ctx->hev[i]);
   }
   delete ctx;
   return HPS_OK;
@@ -1346,9 +1354,6 @@ int32_t hps_group_size(const hps_problem* p) { return p ? p->lay.nq : 0; }
 
 hps_status hps_problem_destroy(hps_problem* p) {
   if (p && p->pgraph) (void)hipGraphExecDestroy(p->pgraph);
-  if (p && p->hbuf) (void)hipHostFree(p->hbuf);
-  for (int i = 0; p && i < 2; ++i)
-    if (p->hev[i]) (void)hipEventDestroy(p->hev[i]);
   delete p;
   return HPS_OK;
 }
