@@ -406,45 +406,18 @@ hps_status merge_impl(hps_problem* p, int l, const T* Tin, T* Tout) {
   const T one = cx<T>::make(1, 0), zero = cx<T>::make(0, 0), mone = cx<T>::make(-1, 0);
   const Operand none{nullptr, 0, 0, im_off(0), im_off(0)};
   int* flag = at<int>(p, lay.flag_off);
-  // W = I - T^P_aa T^Q_bb, inverted in place in the (1,1) block of A^-1
-  {
-    GemmArgs g{};
-    g.M = m; g.N = m; g.K = m; g.batch = np;
-    g.A = Operand{TP, pstride, b, im_off(lv.a0), im_off(lv.a0)};
-    g.B = Operand{TQ, pstride, b, im_off(lv.b0), im_off(lv.b0)};
-    g.alpha = mone; g.beta = zero; g.C = none;
-    g.D = A11; g.Dstride = as; g.ldd = m2; g.dr = im_off(0); g.dc = im_off(0);
-    g.diag_add = one; g.has_diag = 1;
-    HIPCHK(c, zgemm(g, st));
-  }
+  const bool top = l == lay.L;   // exact top: only A^-1 is needed
   char* scr = at<char>(p, lay.scratch_off);
   const size_t zb = up256(sizeof(cd) * (size_t)np * m * 2 * e);
   T* Z = reinterpret_cast<T*>(scr);
   void* invs = scr + zb;
-  HIPCHK(c, zinverse<T>(A11, m, m2, as, np, invs, flag, st));
-  // A12 = W^-1 T^P_aa, A21 = T^Q_bb W^-1, A22 = I + T^Q_bb A12
-  {
-    GemmArgs g{};
-    g.M = m; g.N = m; g.K = m; g.batch = np;
-    g.alpha = one; g.beta = zero; g.C = none;
-    g.Dstride = as; g.ldd = m2; g.dr = im_off(0); g.dc = im_off(0);
-    g.A = Operand{A11, as, m2, im_off(0), im_off(0)};
-    g.B = Operand{TP, pstride, b, im_off(lv.a0), im_off(lv.a0)};
-    g.D = A12;
-    HIPCHK(c, zgemm(g, st));
-    g.A = Operand{TQ, pstride, b, im_off(lv.b0), im_off(lv.b0)};
-    g.B = Operand{A11, as, m2, im_off(0), im_off(0)};
-    g.D = A21;
-    HIPCHK(c, zgemm(g, st));
-    g.B = Operand{A12, as, m2, im_off(0), im_off(0)};
-    g.D = A22;
-    g.diag_add = one; g.has_diag = 1;
-    HIPCHK(c, zgemm(g, st));
-  }
-  if (l == lay.L) return HPS_OK;  // exact top: only A^-1 is needed
   const long long zs = (long long)m * 2 * e;
-  const Level& nx = lay.lev[l + 1];
-  const int* mp = at<int>(p, lv.map_off);
+  T* X = top ? nullptr : at<T>(p, lv.X_off);
+  const long long xs = (long long)m2 * 2 * e;
+  T* YQ = X;
+  T* YP = X ? X + m : nullptr;
+  const Level& nx = lay.lev[top ? l : l + 1];
+  const int* mp = top ? nullptr : at<int>(p, lv.map_off);
   // only rows/columns of the merged boxes' interior sides are ever needed
   auto skip = [&](int row_y, int row_off, int col_y, int col_off) {
     PhysSkip k{};
@@ -458,69 +431,98 @@ hps_status merge_impl(hps_problem* p, int l, const T* Tin, T* Tout) {
     k.col_off = col_off;
     return k;
   };
-  const PhysSkip sk_c0 = skip(0, 0, 1, 0), sk_ce = skip(0, 0, 1, e);
+  const PhysSkip sk_c0 = top ? PhysSkip{} : skip(0, 0, 1, 0), sk_ce = top ? PhysSkip{} : skip(0, 0, 1, e);
   // Every block below is written by a GEMM whose C operand (or B operand) is
   // read in place from the children's box maps, so no block is staged by a
   // copy: with y = [P.E1; Q.E2] split into its halves,
+  //   W        = I - T^P_aa T^Q_bb   (inverted in place: the (1,1) block of A^-1)
+  //   A12 = W^-1 T^P_aa,  A21 = T^Q_bb W^-1,  A22 = I + T^Q_bb A12
   //   Zr       = T^P_aa T^Q_{b,E2}                  (m x e, in Z)
   //   YQ[:, 1] = W^-1 T^P_{a,E1},  YQ[:, 2] = W^-1 Zr          (f^Q_b of y)
   //   YP[:, 1] = T^Q_bb YQ[:, 1],  YP[:, 2] = T^Q_bb YQ[:, 2] + T^Q_{b,E2}
   //   T_new(P.E1, P.E1) = T^P_{E1,a} YP[:, 1] + T^P_{E1,E1}, T_new(P.E1, Q.E2) = T^P_{E1,a} YP[:, 2]
   //   T_new(Q.E2, P.E1) = T^Q_{E2,b} YQ[:, 1], T_new(Q.E2, Q.E2) = T^Q_{E2,b} YQ[:, 2] + T^Q_{E2,E2}
-  // (X = A^-1 B: rows [0, m) YQ, rows [m, 2m) YP.)
-  {
+  // (X = A^-1 B: rows [0, m) YQ, rows [m, 2m) YP.)  Products that do not
+  // depend on each other share a launch: {W, Zr}, the inverse, {A12, A21,
+  // YQ}, {A22, YP}, {T_new}.
+  auto gemm = [&](int M_, int N_, int K_) {
     GemmArgs g{};
-    g.M = m; g.N = e; g.K = m; g.batch = np;
-    g.A = Operand{TP, pstride, b, im_off(lv.a0), im_off(lv.a0)};
-    g.B = Operand{TQ, pstride, b, im_off(lv.b0), lv.E2};
+    g.M = M_; g.N = N_; g.K = K_; g.batch = np;
     g.alpha = one; g.beta = zero; g.C = none;
-    g.D = Z; g.Dstride = zs; g.ldd = m; g.dr = im_off(0); g.dc = im_off(0);
-    g.skip = sk_ce;
-    HIPCHK(c, zgemm(g, st));
-  }
-  T* X = at<T>(p, lv.X_off);
-  const long long xs = (long long)m2 * 2 * e;
-  T* YQ = X;
-  T* YP = X + m;
+    return g;
+  };
+  const Operand Taa{TP, pstride, b, im_off(lv.a0), im_off(lv.a0)};
+  const Operand Tbb{TQ, pstride, b, im_off(lv.b0), im_off(lv.b0)};
+  const Operand Wi{A11, as, m2, im_off(0), im_off(0)};
+  GemmArgs grp[kGemmGroup];
+  int ng = 0;
   {
-    GemmArgs g{};
-    g.M = m; g.N = e; g.K = m; g.batch = np;
-    g.A = Operand{A11, as, m2, im_off(0), im_off(0)};
-    g.alpha = one; g.beta = zero; g.C = none;
-    g.D = YQ; g.Dstride = xs; g.ldd = m2; g.dr = im_off(0);
-    g.B = Operand{TP, pstride, b, im_off(lv.a0), lv.E1};
-    g.dc = im_off(0);
-    g.skip = sk_c0;
-    HIPCHK(c, zgemm(g, st));
-    g.B = Operand{Z, zs, m, im_off(0), im_off(0)};
-    g.dc = im_off(e);
-    g.skip = sk_ce;
-    HIPCHK(c, zgemm(g, st));
+    GemmArgs g = gemm(m, m, m);
+    g.A = Taa; g.B = Tbb; g.alpha = mone;
+    g.D = A11; g.Dstride = as; g.ldd = m2; g.dr = im_off(0); g.dc = im_off(0);
+    g.diag_add = one; g.has_diag = 1;
+    grp[ng++] = g;
+    if (!top) {
+      GemmArgs z = gemm(m, e, m);
+      z.A = Taa; z.B = Operand{TQ, pstride, b, im_off(lv.b0), lv.E2};
+      z.D = Z; z.Dstride = zs; z.ldd = m; z.dr = im_off(0); z.dc = im_off(0);
+      z.skip = sk_ce;
+      grp[ng++] = z;
+    }
+    HIPCHK(c, zgemm_group(grp, ng, st));
   }
+  HIPCHK(c, zinverse<T>(A11, m, m2, as, np, invs, flag, st));
+  ng = 0;
   {
-    GemmArgs g{};
-    g.M = m; g.N = e; g.K = m; g.batch = np;
-    g.A = Operand{TQ, pstride, b, im_off(lv.b0), im_off(lv.b0)};
-    g.alpha = one;
-    g.D = YP; g.Dstride = xs; g.ldd = m2; g.dr = im_off(0);
-    g.B = Operand{YQ, xs, m2, im_off(0), im_off(0)};
-    g.beta = zero; g.C = none; g.dc = im_off(0);
-    g.skip = sk_c0;
-    HIPCHK(c, zgemm(g, st));
-    g.B = Operand{YQ, xs, m2, im_off(0), im_off(e)};
-    g.beta = one; g.C = Operand{TQ, pstride, b, im_off(lv.b0), lv.E2}; g.dc = im_off(e);
-    g.skip = sk_ce;
-    HIPCHK(c, zgemm(g, st));
+    GemmArgs g = gemm(m, m, m);
+    g.Dstride = as; g.ldd = m2; g.dr = im_off(0); g.dc = im_off(0);
+    g.A = Wi; g.B = Taa; g.D = A12;
+    grp[ng++] = g;
+    g.A = Tbb; g.B = Wi; g.D = A21;
+    grp[ng++] = g;
+    if (!top) {
+      GemmArgs y = gemm(m, e, m);
+      y.A = Wi; y.D = YQ; y.Dstride = xs; y.ldd = m2; y.dr = im_off(0);
+      y.B = Operand{TP, pstride, b, im_off(lv.a0), lv.E1};
+      y.dc = im_off(0);
+      y.skip = sk_c0;
+      grp[ng++] = y;
+      y.B = Operand{Z, zs, m, im_off(0), im_off(0)};
+      y.dc = im_off(e);
+      y.skip = sk_ce;
+      grp[ng++] = y;
+    }
+    HIPCHK(c, zgemm_group(grp, ng, st));
   }
+  ng = 0;
+  {
+    GemmArgs g = gemm(m, m, m);
+    g.Dstride = as; g.ldd = m2; g.dr = im_off(0); g.dc = im_off(0);
+    g.A = Tbb; g.B = Operand{A12, as, m2, im_off(0), im_off(0)}; g.D = A22;
+    g.diag_add = one; g.has_diag = 1;
+    grp[ng++] = g;
+    if (!top) {
+      GemmArgs y = gemm(m, e, m);
+      y.A = Tbb; y.D = YP; y.Dstride = xs; y.ldd = m2; y.dr = im_off(0);
+      y.B = Operand{YQ, xs, m2, im_off(0), im_off(0)};
+      y.dc = im_off(0);
+      y.skip = sk_c0;
+      grp[ng++] = y;
+      y.B = Operand{YQ, xs, m2, im_off(0), im_off(e)};
+      y.beta = one; y.C = Operand{TQ, pstride, b, im_off(lv.b0), lv.E2}; y.dc = im_off(e);
+      y.skip = sk_ce;
+      grp[ng++] = y;
+    }
+    HIPCHK(c, zgemm_group(grp, ng, st));
+  }
+  if (top) return HPS_OK;
   T* Tn = Tout;
   const int bn = nx.g.b;
   const long long ns = (long long)bn * bn;
   const IdxMap rowP = im_tab(mp), rowQ = im_tab(mp + e), colP = im_tab(mp), colQ = im_tab(mp + e);
   const PhysSkip s00 = skip(1, 0, 1, 0), s0e = skip(1, 0, 1, e), se0 = skip(1, e, 1, 0), see = skip(1, e, 1, e);
   {
-    GemmArgs g{};
-    g.M = e; g.N = e; g.K = m; g.batch = np;
-    g.alpha = one;
+    GemmArgs g = gemm(e, e, m);
     g.D = Tn; g.Dstride = ns; g.ldd = bn;
     // rows P.E1
     g.A = Operand{TP, pstride, b, lv.E1, im_off(lv.a0)};
@@ -528,22 +530,23 @@ hps_status merge_impl(hps_problem* p, int l, const T* Tin, T* Tout) {
     g.B = Operand{YP, xs, m2, im_off(0), im_off(0)};
     g.beta = one; g.C = Operand{TP, pstride, b, lv.E1, lv.E1}; g.dc = colP;
     g.skip = s00;
-    HIPCHK(c, zgemm(g, st));
+    grp[0] = g;
     g.B = Operand{YP, xs, m2, im_off(0), im_off(e)};
     g.beta = zero; g.C = none; g.dc = colQ;
     g.skip = s0e;
-    HIPCHK(c, zgemm(g, st));
+    grp[1] = g;
     // rows Q.E2
     g.A = Operand{TQ, pstride, b, lv.E2, im_off(lv.b0)};
     g.dr = rowQ;
     g.B = Operand{YQ, xs, m2, im_off(0), im_off(0)};
     g.beta = zero; g.C = none; g.dc = colP;
     g.skip = se0;
-    HIPCHK(c, zgemm(g, st));
+    grp[2] = g;
     g.B = Operand{YQ, xs, m2, im_off(0), im_off(e)};
     g.beta = one; g.C = Operand{TQ, pstride, b, lv.E2, lv.E2}; g.dc = colQ;
     g.skip = see;
-    HIPCHK(c, zgemm(g, st));
+    grp[3] = g;
+    HIPCHK(c, zgemm_group(grp, 4, st));
   }
   return HPS_OK;
 }

@@ -41,18 +41,19 @@ template <> struct Mfma<cf> {
   __device__ static int row(int lk, int v) { return 4 * lk + v; }
 };
 
+// One BM x BN output tile (tile index `tile`, batch entry b) of a GEMM; every
+// thread of the workgroup calls it with the same arguments.
 template <class T, int BM, int BN, int WM, int WN>
-__global__ __launch_bounds__(64 * WM * WN) void zgemm_kernel(GemmArgsT<T> a) {
+__device__ __forceinline__ void gemm_tile(const GemmArgsT<T>& a, int tile, int b) {
   typedef typename Mfma<T>::acc acc_t;
   constexpr int NT = 64 * WM * WN;
   constexpr int TM = BM / WM / 16;
   constexpr int TN = BN / WN / 16;
   __shared__ T As[KT][BM];
   __shared__ T Bs[KT][BN + 1];   // padded: the 16 k-rows of a column land in different banks
-  const int b = blockIdx.y;
   const int tilesM = (a.M + BM - 1) / BM;
-  const int m0 = (blockIdx.x % tilesM) * BM;
-  const int n0 = (blockIdx.x / tilesM) * BN;
+  const int m0 = (tile % tilesM) * BM;
+  const int n0 = (tile / tilesM) * BN;
   const int tid = threadIdx.x;
   // Physical rows/columns of a live tile are written as exact zeros: their
   // inputs (skipped entries of earlier products) are never computed, so they
@@ -191,6 +192,25 @@ __global__ __launch_bounds__(64 * WM * WN) void zgemm_kernel(GemmArgsT<T> a) {
       }
 }
 
+template <class T, int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__(64 * WM * WN) void zgemm_kernel(GemmArgsT<T> a) {
+  gemm_tile<T, BM, BN, WM, WN>(a, blockIdx.x, blockIdx.y);
+}
+
+// Up to kGemmGroup independent GEMMs in one launch: z = GEMM, x = tile, y =
+// batch entry; workgroups past a GEMM's tiles or batch leave at once.
+template <class T>
+struct GemmGroupT {
+  GemmArgsT<T> g[kGemmGroup];
+};
+template <class T, int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__(64 * WM * WN) void zgemm_group_kernel(GemmGroupT<T> grp) {
+  const GemmArgsT<T>& a = grp.g[blockIdx.z];
+  const int tiles = ((a.M + BM - 1) / BM) * ((a.N + BN - 1) / BN);
+  if ((int)blockIdx.x >= tiles || (int)blockIdx.y >= a.batch) return;   // uniform over the workgroup
+  gemm_tile<T, BM, BN, WM, WN>(a, blockIdx.x, blockIdx.y);
+}
+
 template <class T>
 __global__ void zcopy2d_kernel(int M, int N, OperandT<T> S, T alpha, T* D, long long Dstride, int ldd,
                                IdxMap dr, IdxMap dc, PhysSkip skip) {
@@ -232,6 +252,20 @@ hipError_t launch(const GemmArgsT<T>& a, hipStream_t st) {
 
 }  // namespace
 
+template <class T, int BM, int BN, int WM, int WN>
+hipError_t launch_group(const GemmArgsT<T>* g, int n, hipStream_t st) {
+  GemmGroupT<T> grp{};
+  int tiles = 0, batch = 0;
+  for (int i = 0; i < n; ++i) {
+    grp.g[i] = g[i];
+    tiles = std::max(tiles, ((g[i].M + BM - 1) / BM) * ((g[i].N + BN - 1) / BN));
+    batch = std::max(batch, g[i].batch);
+  }
+  hipLaunchKernelGGL((zgemm_group_kernel<T, BM, BN, WM, WN>), dim3(tiles, batch, n), dim3(64 * WM * WN), 0, st,
+                     grp);
+  return hipPeekAtLastError();
+}
+
 template <class T>
 hipError_t zgemm(const GemmArgsT<T>& a, hipStream_t st) {
   if (a.M <= 0 || a.N <= 0 || a.batch <= 0) return hipSuccess;
@@ -240,6 +274,29 @@ hipError_t zgemm(const GemmArgsT<T>& a, hipStream_t st) {
   if (a.M >= 48 && a.N >= 48 && t64 >= 512) return launch<T, 64, 64, 2, 2>(a, st);
   if (a.M >= 24 && a.N >= 24) return launch<T, 32, 32, 2, 2>(a, st);
   return launch<T, 16, 16, 1, 1>(a, st);
+}
+
+template <class T>
+hipError_t zgemm_group(const GemmArgsT<T>* g, int n, hipStream_t st) {
+  if (n < 1 || n > kGemmGroup) return hipErrorInvalidValue;
+  // drop empty GEMMs; one left: the plain launch
+  GemmArgsT<T> live[kGemmGroup];
+  int k = 0;
+  for (int i = 0; i < n; ++i)
+    if (g[i].M > 0 && g[i].N > 0 && g[i].batch > 0) live[k++] = g[i];
+  if (k == 0) return hipSuccess;
+  if (k == 1) return zgemm(live[0], st);
+  // one tile shape for the group, by the same rule as a single GEMM applied to
+  // the smallest dimensions and the summed 64 x 64 tile count
+  int mn = 1 << 30;
+  long long t64 = 0;
+  for (int i = 0; i < k; ++i) {
+    mn = std::min(mn, std::min(live[i].M, live[i].N));
+    t64 += (long long)((live[i].M + 63) / 64) * ((live[i].N + 63) / 64) * live[i].batch;
+  }
+  if (mn >= 48 && t64 >= 512) return launch_group<T, 64, 64, 2, 2>(live, k, st);
+  if (mn >= 24) return launch_group<T, 32, 32, 2, 2>(live, k, st);
+  return launch_group<T, 16, 16, 1, 1>(live, k, st);
 }
 
 hipError_t convert_c64_c32(const cd* src, cf* dst, long long n, hipStream_t st) {
@@ -269,6 +326,8 @@ hipError_t zcopy2d(int M, int N, int batch, const OperandT<T>& S, T alpha, T* D,
 
 template hipError_t zgemm<cd>(const GemmArgsT<cd>&, hipStream_t);
 template hipError_t zgemm<cf>(const GemmArgsT<cf>&, hipStream_t);
+template hipError_t zgemm_group<cd>(const GemmArgsT<cd>*, int, hipStream_t);
+template hipError_t zgemm_group<cf>(const GemmArgsT<cf>*, int, hipStream_t);
 template hipError_t zcopy2d<cd>(int, int, int, const OperandT<cd>&, cd, cd*, long long, int, IdxMap,
                                 IdxMap, hipStream_t, const PhysSkip*);
 template hipError_t zcopy2d<cf>(int, int, int, const OperandT<cf>&, cf, cf*, long long, int, IdxMap,

@@ -81,6 +81,12 @@ typedef GemmArgsT<cd> GemmArgs;
 // D = alpha * A B + beta * C (+ diag_add I), all column-major; complex MFMA.
 template <class T>
 hipError_t zgemm(const GemmArgsT<T>& a, hipStream_t st);
+// Up to kGemmGroup independent GEMMs (none reads what another writes) in one
+// launch, one tile shape for all of them; GEMMs with an empty M, N or batch
+// are skipped.
+constexpr int kGemmGroup = 4;
+template <class T>
+hipError_t zgemm_group(const GemmArgsT<T>* g, int n, hipStream_t st);
 // D(dr(i), dc(j)) = alpha * S(sr(i), sc(j)) (S == null: zero), batched.
 template <class T>
 hipError_t zcopy2d(int M, int N, int batch, const OperandT<T>& S, T alpha, T* D,
