@@ -52,6 +52,10 @@ constexpr int kNB = 32;          // panel width of the blocked LU
 #define HPS_LEAF_PF 3
 #endif
 constexpr int kPF = HPS_LEAF_PF;  // trailing-update column groups in flight per lane
+#ifndef HPS_LEAF_ADD_B
+#define HPS_LEAF_ADD_B 16
+#endif
+constexpr int kAddB = HPS_LEAF_ADD_B;  // K entries added per thread with their loads in flight together
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 constexpr int kCPW = kNB / kWaves;  // panel columns per wave
@@ -138,15 +142,18 @@ struct ElemK {
 
   // The nonzeros of K one by one: it < items() enumerates (row, slot) pairs,
   // 2p+5 slots per interior row (its x-line with the diagonal, its y-line, four
-  // boundary nodes, two source columns) and p+2 per boundary row.  False for a
+  // boundary nodes, two source columns) and p+2 per boundary row, slot-major.  False for a
   // slot that holds no entry (the source columns without a source).
   __device__ int items() const { return pp * (2 * p + 5) + 4 * p * (p + 2); }
   __device__ bool item(int it, int& r, int& c, double& v) const {
-    const int N1 = N + 1, si = 2 * p + 5, sb = p + 2;
+    const int N1 = N + 1, si = 2 * p + 5;
     const double hh = 0.25 * h * h;
     if (it < pp * si) {
-      r = it / si;
-      const int s = it - r * si;
+      // rows fastest: the lanes of a wave take one slot kind of consecutive
+      // rows, so that y-line, top/bottom-node and source entries (a single
+      // column for a run of rows) are read and written contiguously
+      const int s = it / pp;
+      r = it - s * pp;
       const int i = r / p + 1, j = r - (i - 1) * p + 1;
       if (s < p) {                       // (i2, j): x-line, diagonal when i2 == i
         const int i2 = s + 1;
@@ -173,7 +180,7 @@ struct ElemK {
       return true;
     }
     const int jt = it - pp * si;
-    const int rb = jt / sb, t = jt - rb * sb;
+    const int t = jt / (4 * p), rb = jt - t * (4 * p);
     const int side = rb / p, k = rb - side * p + 1;
     r = pp + rb;
     const bool lo = (side == 0 || side == 2);
@@ -669,14 +676,14 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_kernel(LeafArgs a) {
     __syncthreads();
     if (first) {
       // the first trailing update started from zero: add K's trailing entries
-      // at their rows' slots (each slot and column is touched once), eight at
+      // at their rows' slots (each slot and column is touched once), kAddB at
       // a time so that their loads are in flight together
       const int items = K.items();
-      for (int base = tid; base < items; base += 8 * kThreads) {
-        double* adr[8];
-        double val[8], old[8];
+      for (int base = tid; base < items; base += kAddB * kThreads) {
+        double* adr[kAddB];
+        double val[kAddB], old[kAddB];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < kAddB; ++u) {
           int r = 0, c = 0;
           double v = 0.0;
           const int it = base + u * kThreads;
@@ -685,9 +692,9 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_kernel(LeafArgs a) {
           val[u] = v;
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) old[u] = adr[u] ? *adr[u] : 0.0;
+        for (int u = 0; u < kAddB; ++u) old[u] = adr[u] ? *adr[u] : 0.0;
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
+        for (int u = 0; u < kAddB; ++u)
           if (adr[u]) *adr[u] = old[u] + val[u];
       }
       __syncthreads();
