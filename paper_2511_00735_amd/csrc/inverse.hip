@@ -375,16 +375,24 @@ __global__ __launch_bounds__(1024) void gj_panel_reg_kernel(const T* A, int m, i
       piv_s[c] = pr;
       if ((kk >> 32) <= 1u) atomicOr(flag, 2);
     }
+    // pivot row entries of this wave's live columns, scaled by 1/pivot once
+    // (the column entries then multiply them directly); waves with no live
+    // column skip the step
     T pv[CPW];
+    bool wlive = false;
 #pragma unroll
-    for (int u = 0; u < CPW; ++u) pv[u] = cx<T>::make(0.0, 0.0);
+    for (int u = 0; u < CPW; ++u) {
+      pv[u] = cx<T>::make(0.0, 0.0);
+      const int j = wave + NW * u;
+      wlive |= (j > c && j < kb);
+    }
 #pragma unroll
     for (int t = 0; t < CH; ++t) {
       if (t == tp) {
 #pragma unroll
         for (int u = 0; u < CPW; ++u) {
           const int j = wave + NW * u;
-          if (j > c && j < kb) pv[u] = readlane_c(x[t][u], lp);
+          if (j > c && j < kb) pv[u] = cmul(readlane_c(x[t][u], lp), inv);
         }
       }
     }
@@ -395,23 +403,25 @@ __global__ __launch_bounds__(1024) void gj_panel_reg_kernel(const T* A, int m, i
     const int un = cn / NW;
     T* cbn = colbuf[b ^ 1];
     unsigned long long best = 0;
+    if (wlive) {
 #pragma unroll
-    for (int t = 0; t < CH; ++t) {
-      // chunks past the live rows (uniform); not taken at CH = 16, where the
-      // extra control flow would push the 128-register budget into scratch
-      if (CH <= 8 && t * 64 >= rows) continue;
-      const int r = t * 64 + lane;
-      const bool act = r < rows && !((used >> t) & 1u);
-      const T l = act ? cmul(colbuf[b][r], inv) : cx<T>::make(0.0, 0.0);
+      for (int t = 0; t < CH; ++t) {
+        // chunks past the live rows (uniform); not taken at CH = 16, where the
+        // extra control flow would push the 128-register budget into scratch
+        if (CH <= 8 && t * 64 >= rows) continue;
+        const int r = t * 64 + lane;
+        const bool act = r < rows && !((used >> t) & 1u);
+        const T l = act ? colbuf[b][r] : cx<T>::make(0.0, 0.0);
 #pragma unroll
-      for (int u = 0; u < CPW; ++u) {
-        const int j = wave + NW * u;
-        if (j > c && j < kb) x[t][u] = csub(x[t][u], cmul(l, pv[u]));  // wave-uniform
-      }
-      if (own && r < rows) {
-        const T vn = (CPW == 1 || un == 0) ? x[t][0] : x[t][CPW - 1];
-        cbn[r] = vn;
-        if (act) best = max(best, pivot_key(cabs2(vn), r));
+        for (int u = 0; u < CPW; ++u) {
+          const int j = wave + NW * u;
+          if (j > c && j < kb) x[t][u] = csub(x[t][u], cmul(l, pv[u]));  // wave-uniform
+        }
+        if (own && r < rows) {
+          const T vn = (CPW == 1 || un == 0) ? x[t][0] : x[t][CPW - 1];
+          cbn[r] = vn;
+          if (act) best = max(best, pivot_key(cabs2(vn), r));
+        }
       }
     }
     if (own) {
