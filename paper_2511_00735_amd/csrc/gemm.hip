@@ -108,23 +108,36 @@ __device__ __forceinline__ void gemm_tile(const GemmArgsT<T>& a, int tile, int b
     cB[s] = colok[s] ? (long long)imap(a.B.c, gj) * a.B.ld : 0;
   }
   T ra[SA], rb[SB];
+  bool va[SA], vb[SB];
+  // The chunk's K-direction map lookups (a table read or an offset) all come
+  // before its data loads, and the data loads are unconditional (an entry
+  // outside the operand reads offset 0 of the same matrix; its validity is
+  // applied when the chunk is stored to LDS): no wait separates the loads of
+  // a chunk, and none is needed before the multiply that they overlap.
   auto fetch = [&](int k0) {
+    long long offA[SA];
 #pragma unroll
     for (int s = 0; s < SA; ++s) {
       const int gk = k0 + ka + s * KSA;
-      ra[s] = (rowok && gk < a.K) ? Ab[(long long)imap(a.A.c, gk) * a.A.ld + rA] : cx<T>::make(0.0, 0.0);
+      va[s] = rowok && gk < a.K;
+      offA[s] = va[s] ? (long long)imap(a.A.c, gk) * a.A.ld + rA : 0;
     }
     const int gk = k0 + kb;
     const bool kok = gk < a.K;
     const long long rB = kok ? imap(a.B.r, gk) : 0;
 #pragma unroll
-    for (int s = 0; s < SB; ++s) rb[s] = (kok && colok[s]) ? Bb[cB[s] + rB] : cx<T>::make(0.0, 0.0);
+    for (int s = 0; s < SA; ++s) ra[s] = Ab[offA[s]];
+#pragma unroll
+    for (int s = 0; s < SB; ++s) {
+      vb[s] = kok && colok[s];
+      rb[s] = Bb[vb[s] ? cB[s] + rB : 0];
+    }
   };
   auto stash = [&]() {
 #pragma unroll
-    for (int s = 0; s < SA; ++s) As[ka + s * KSA][ia] = ra[s];
+    for (int s = 0; s < SA; ++s) As[ka + s * KSA][ia] = va[s] ? ra[s] : cx<T>::make(0.0, 0.0);
 #pragma unroll
-    for (int s = 0; s < SB; ++s) Bs[kb][jb + s * JSB] = rb[s];
+    for (int s = 0; s < SB; ++s) Bs[kb][jb + s * JSB] = vb[s] ? rb[s] : cx<T>::make(0.0, 0.0);
   };
 
   acc_t accr[TM][TN], acci[TM][TN];
