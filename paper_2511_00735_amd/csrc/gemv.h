@@ -80,8 +80,9 @@ template <class M>
 hipError_t zgemv_partials(const GemvDescT<M>* d, int nd, int batch, cd* partial, GemvPartLayout* lay,
                           hipStream_t st, int max_split = 0);
 
-// One V-cycle level with one workgroup per pair (levels with many small pairs).
-// Per pair j (children P = box 2j, Q = box 2j+1 of level g.level):
+// One V-cycle level of small pairs in one launch per direction: the down sweep
+// with two workgroups per pair (one per half of z0), the up sweep with the
+// pair's 2m rows split into pieces, one workgroup each.  Per pair j (children P = box 2j, Q = box 2j+1 of level g.level):
 //   Ainv  [2m][2m]  inverse of A = [[I, -T^P_aa], [-T^Q_bb, I]] on x = [Q.beta; P.alpha]
 //   X     [2m][2e]  A^-1 B, columns y = [P.E1; Q.E2]
 //   xtab  [2m]      canonical slots of x;  ytab [2e] slots of y (-1: physical);
