@@ -32,6 +32,11 @@ import os
 import sys
 import time
 
+# Blocks above 1 GiB are never split by PyTorch's caching allocator: a freed
+# workspace stays whole, so it is reused or released in one piece when a later
+# allocation (a larger serving batch) needs the memory.  Set before torch loads.
+os.environ.setdefault("PYTORCH_ALLOC_CONF", "max_split_size_mb:1024")
+
 import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))

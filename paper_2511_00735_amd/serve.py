@@ -53,12 +53,17 @@ class Planner:
     pending requests given the free memory.  ``footprint(shape, count)`` is the
     device bytes a batch of ``count`` requests of ``shape`` needs."""
 
-    def __init__(self, footprint: Callable[[tuple, int], int], budget: int, max_batch: int = 32):
+    def __init__(self, footprint: Callable[[tuple, int], int], budget: int, max_batch: int = 32,
+                 batch_budget: Optional[int] = None):
         self.footprint = footprint
         self.budget = int(budget)
         self.max_batch = int(max_batch)
+        # bytes one batch may take (a lone request may exceed it while it
+        # fits the free budget)
+        self.batch_budget = int(batch_budget) if batch_budget is not None else self.budget
         self.pending: List = []     # (arrival order) requests waiting
         self.in_use = 0
+        self.hold = False           # no admissions (a batch waits for the others to drain)
 
     @staticmethod
     def shape(req):
@@ -70,14 +75,17 @@ class Planner:
     def take(self):
         """Next batch (list of requests and its footprint), or None when the
         oldest request cannot be admitted yet (or nothing is pending)."""
-        if not self.pending:
+        if not self.pending or self.hold:
             return None
         key = self.shape(self.pending[0])
         same = [r for r in self.pending if self.shape(r) == key][: self.max_batch]
         free = self.budget - self.in_use
+        cap = min(free, self.batch_budget)
         count = len(same)
-        while count > 0 and self.footprint(key, count) > free:
+        while count > 0 and self.footprint(key, count) > cap:
             count -= 1
+        if count == 0 and self.footprint(key, 1) <= free:
+            count = 1
         if count == 0:
             if self.in_use == 0:
                 raise ValueError(f"a single {key} request needs {self.footprint(key, 1)} bytes, "
@@ -93,14 +101,23 @@ class Planner:
     def release(self, nbytes):
         self.in_use -= int(nbytes)
 
+    def requeue(self, batch):
+        """Puts the requests of a batch that could not run back among the
+        pending ones, in arrival order."""
+        self.pending = sorted(self.pending + list(batch), key=lambda r: r.arrival)
+
 
 class Server:
     """Runs a request trace through the library in real time.
 
     precision: "mixed" or "fp64"; workers: concurrent batches (streams);
-    memory_budget: device bytes the admitted batches may hold together;
+    memory_budget: device bytes the admitted batches may hold together, one
+    batch at most memory_budget / workers (a lone request may take more);
     graphs: each worker replays its V-cycles from HIP graphs (several host
-    threads launching at once)."""
+    threads launching at once).  A batch whose allocation fails (the caching
+    allocator's free memory split by other batches) goes back to the pending
+    requests; nothing is admitted until the running batches have finished and
+    the cache has been released, then batching resumes."""
 
     def __init__(self, precision="mixed", workers=3, max_batch=32, memory_budget=200 << 30, tol=1e-8,
                  coarse_iters=5, restart=60, maxit=600, keep_solutions=False, graphs=True):
@@ -194,10 +211,12 @@ class Server:
         """Serve `trace` (requests with .arrival in seconds, ascending);
         returns (records by name, summary dict)."""
         torch, hps = self.torch, self.hps
-        planner = Planner(self.footprint, self.budget, self.max_batch)
+        planner = Planner(self.footprint, self.budget, self.max_batch,
+                          batch_budget=self.budget // max(1, self.workers))
         records = {r.name: Record(r.name, r.n, r.N, r.arrival, dof=r.skeleton_dof) for r in trace}
         cond = threading.Condition()
         state = {"fed": 0, "done": False, "error": None}
+        retried = set()   # ids of requests whose batch ran out of memory once
         for shape in sorted(set((r.n, r.N) for r in trace)):
             self._node_data(*shape)
         self._t0 = time.perf_counter()
@@ -237,13 +256,36 @@ class Server:
                                 return
                             cond.wait(timeout=0.05)
                     batch, need = got
+                    oom = False
                     try:
                         with torch.cuda.stream(stream):
                             self._run_batch(ctx, batch, records)
-                    finally:
+                    except torch.OutOfMemoryError:
+                        if any(id(r) in retried for r in batch):
+                            raise
+                        oom = True
+                    if oom:
+                        # the device memory is there but split across other
+                        # batches' cached blocks: hand the batch back, admit
+                        # nothing until the running batches have finished,
+                        # release the cache; a batch that fails twice is an error
+                        retried.update(id(r) for r in batch)
                         with cond:
                             planner.release(need)
+                            planner.requeue(batch)
+                            planner.hold = True
                             cond.notify_all()
+                            while planner.in_use > 0 and state["error"] is None:
+                                cond.wait(timeout=0.05)
+                        torch.cuda.synchronize()
+                        torch.cuda.empty_cache()
+                        with cond:
+                            planner.hold = False
+                            cond.notify_all()
+                        continue
+                    with cond:
+                        planner.release(need)
+                        cond.notify_all()
             except BaseException as exc:  # surface the first failure to the caller
                 with cond:
                     state["error"] = exc

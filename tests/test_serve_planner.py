@@ -70,3 +70,41 @@ def test_summary_percentiles():
     assert s["completed"] == 100 and s["converged"] == 100
     assert abs(s["latency_p50_ms"] - 50.5) < 1e-6
     assert abs(s["latency_p99_ms"] - 99.01) < 1e-6
+
+
+def test_batch_budget_caps_a_batch_but_not_a_lone_request():
+    one = fp((8, 8), 1)
+    pl = Planner(fp, budget=10 * one, max_batch=8, batch_budget=3 * one)
+    for i in range(5):
+        pl.add(Req(f"r{i}", 8, 8, arrival=float(i)))
+    batch, need = pl.take()
+    assert [r.name for r in batch] == ["r0", "r1", "r2"] and need == 3 * one
+    # a request larger than the per-batch budget still runs alone while it
+    # fits the free budget
+    big = fp((16, 8), 1)
+    assert big > 3 * one
+    pl2 = Planner(fp, budget=10 * one, max_batch=8, batch_budget=3 * one)
+    pl2.add(Req("big", 16, 8))
+    pl2.add(Req("big2", 16, 8))
+    batch, need = pl2.take()
+    assert [r.name for r in batch] == ["big"] and need == big
+
+
+def test_hold_and_requeue_in_arrival_order():
+    one = fp((8, 8), 1)
+    pl = Planner(fp, budget=10 * one, max_batch=2)
+    reqs = [Req(f"r{i}", 8, 8, arrival=float(i)) for i in range(4)]
+    for r in reqs:
+        pl.add(r)
+    batch, need = pl.take()
+    assert [r.name for r in batch] == ["r0", "r1"]
+    # the batch could not run: its reservation is released, its requests go
+    # back ahead of the younger ones, and nothing is admitted during a hold
+    pl.release(need)
+    pl.requeue(batch)
+    assert [r.name for r in pl.pending] == ["r0", "r1", "r2", "r3"]
+    pl.hold = True
+    assert pl.take() is None
+    pl.hold = False
+    batch, _ = pl.take()
+    assert [r.name for r in batch] == ["r0", "r1"] and pl.in_use == 2 * one
