@@ -507,17 +507,18 @@ __global__ __launch_bounds__(1024) void gj_panel_reg_kernel(const T* A, int m, i
   if (live) Db[gj * kb + gi] = sv;
 }
 
-// Step 2 of a block column: out-of-place update of the whole matrix, 64 x 64
-// tiles, 256 threads, each thread 4 x 4 outputs (rows i0 + tx + 16u, columns
-// j0 + ty + 16v), rows read through rowmap, P = C = [k0, k0+kb):
+// Step 2 of a block column: out-of-place update of the whole matrix, BT x BT
+// tiles (64, or 32 where 64 would leave few workgroups), 256 threads, each
+// thread (BT/16)^2 outputs (rows i0 + tx + 16u, columns j0 + ty + 16v), rows
+// read through rowmap, P = C = [k0, k0+kb):
 //   X = Dinv A'[P, :] (Dinv on the C columns); rows in P: out = X;
 //   other rows: out = A'[i, ~C] - A'[i, C] X  (-A'[i, C] Dinv on C).
 // With colmap the output column j is written at colmap[j].
-template <class T>
+template <class T, int BT>
 __global__ __launch_bounds__(256) void gj_update_kernel(const T* A, int lda, long long astride, T* O, int ldo,
                                                         long long ostride, int m, int k0, int kb,
                                                         const int* rowmap, const T* dinv, const int* colmap) {
-  constexpr int BT = 64;
+  constexpr int U = BT / 16;
   __shared__ T Ds[kNB * kNB];
   __shared__ T Xs[kNB][BT];
   __shared__ T Bp[kNB][BT];     // A'[P, jtile]
@@ -531,14 +532,14 @@ __global__ __launch_bounds__(256) void gj_update_kernel(const T* A, int lda, lon
   const T* Db = dinv + (long long)b * kNB * kNB;
   const int tid = threadIdx.x;
   const int tx = tid % 16, ty = tid / 16;
-  T aout[4][4];
+  T aout[U][U];
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
+  for (int u = 0; u < U; ++u) {
     const int gi = i0 + tx + 16 * u;
     const bool rowok = gi < m && !(gi >= k0 && gi < k0 + kb);
     const int src = gi < m ? rm[gi] : 0;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
+    for (int v = 0; v < U; ++v) {
       const int gj = j0 + ty + 16 * v;
       const bool ok = rowok && gj < m && !(gj >= k0 && gj < k0 + kb);
       aout[u][v] = ok ? Ab[(long long)gj * lda + src] : cx<T>::make(0.0, 0.0);
@@ -568,29 +569,29 @@ __global__ __launch_bounds__(256) void gj_update_kernel(const T* A, int lda, lon
     Xs[q][j] = v;
   }
   __syncthreads();
-  T acc[4][4];
+  T acc[U][U];
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
+  for (int u = 0; u < U; ++u)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) acc[u][v] = cx<T>::make(0.0, 0.0);
+    for (int v = 0; v < U; ++v) acc[u][v] = cx<T>::make(0.0, 0.0);
   for (int q = 0; q < kb; ++q) {
-    T a[4], x[4];
+    T a[U], x[U];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) a[u] = Ac[q][tx + 16 * u];
+    for (int u = 0; u < U; ++u) a[u] = Ac[q][tx + 16 * u];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) x[v] = Xs[q][ty + 16 * v];
+    for (int v = 0; v < U; ++v) x[v] = Xs[q][ty + 16 * v];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < U; ++u)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) acc[u][v] = cfma(a[u], x[v], acc[u][v]);
+      for (int v = 0; v < U; ++v) acc[u][v] = cfma(a[u], x[v], acc[u][v]);
   }
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
+  for (int u = 0; u < U; ++u) {
     const int gi = i0 + tx + 16 * u;
     if (gi >= m) continue;
     const bool inP = gi >= k0 && gi < k0 + kb;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
+    for (int v = 0; v < U; ++v) {
       const int j = ty + 16 * v;
       const int gj = j0 + j;
       if (gj >= m) continue;
@@ -647,7 +648,11 @@ hipError_t inverse_blocked(T* A, int m, int lda, long long bstride, int batch, v
   T* nxt = s.buf;
   int ldn = m;
   long long ns = (long long)m * m;
-  const int tiles = (m + 63) / 64;
+  // 32 x 32 update tiles when 64 x 64 ones would give few workgroups (under
+  // 512 in FP32, 256 in FP64, whose 64 x 64 tiles fill a CU's LDS alone)
+  const long long w64 = (long long)((m + 63) / 64) * ((m + 63) / 64) * batch;
+  const bool tiles32 = w64 < (sizeof(T) == sizeof(cf) ? 512 : 256);
+  const int tiles = tiles32 ? (m + 31) / 32 : (m + 63) / 64;
   // register panels: rows <= 512 with 32 columns, FP64 rows <= 1024 with 16
   // columns; larger matrices keep the LDS panel
   const int reg = m <= 512 ? 1 : (m <= 1024 && sizeof(T) == sizeof(cd) ? 2 : 0);
@@ -671,8 +676,12 @@ hipError_t inverse_blocked(T* A, int m, int lda, long long bstride, int batch, v
     if ((err = hipPeekAtLastError()) != hipSuccess) return err;
     // the last step writes straight into A, columns permuted, when it can
     const bool last_into_A = (s_ == steps - 1) && nxt == A;
-    hipLaunchKernelGGL(gj_update_kernel<T>, dim3(tiles * tiles, batch), dim3(256), 0, st, cur, ldc, cs, nxt,
-                       ldn, ns, m, k0, kb, s.rowmap, s.dinv, last_into_A ? rho : nullptr);
+    if (tiles32)
+      hipLaunchKernelGGL((gj_update_kernel<T, 32>), dim3(tiles * tiles, batch), dim3(256), 0, st, cur, ldc, cs,
+                         nxt, ldn, ns, m, k0, kb, s.rowmap, s.dinv, last_into_A ? rho : nullptr);
+    else
+      hipLaunchKernelGGL((gj_update_kernel<T, 64>), dim3(tiles * tiles, batch), dim3(256), 0, st, cur, ldc, cs,
+                         nxt, ldn, ns, m, k0, kb, s.rowmap, s.dinv, last_into_A ? rho : nullptr);
     if ((err = hipPeekAtLastError()) != hipSuccess) return err;
     std::swap(cur, nxt);
     std::swap(ldc, ldn);
