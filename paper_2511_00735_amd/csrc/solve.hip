@@ -630,6 +630,9 @@ hipError_t coarse_arnoldi(cd* V, int n, long long vq, int j, const CoarseW& src,
   if (j < kFastV && n <= 2 * 512)
     hipLaunchKernelGGL((coarse_arnoldi_fast_kernel<2, 512>), dim3(nq), dim3(512), 0, st, V, n, vq, j, src, Hcol,
                        hsize);
+  else if (j < kFastV && n <= 2 * 1024)   // more loads in flight on the one CU
+    hipLaunchKernelGGL((coarse_arnoldi_fast_kernel<2, 1024>), dim3(nq), dim3(1024), 0, st, V, n, vq, j, src, Hcol,
+                       hsize);
   else if (j < kFastV && n <= 4 * 512)
     hipLaunchKernelGGL((coarse_arnoldi_fast_kernel<4, 512>), dim3(nq), dim3(512), 0, st, V, n, vq, j, src, Hcol,
                        hsize);
