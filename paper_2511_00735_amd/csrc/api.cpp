@@ -836,8 +836,7 @@ hps_status precond_one(hps_problem* p, const cd* r, cd* z) {
   const Layout& lay = p->lay;
   cd* wv = workv(p, 0);
   const long long ntot = lay.nslots * lay.nq;
-  HIPCHK(c, vfill(z, ntot, cmk(0, 0), st));
-  HIPCHK(c, vcopy(r, wv, ntot, st));
+  HIPCHK(c, vcopy_zero(r, wv, z, ntot, st));   // wv = r, z = 0
   for (int l = 1; l < lay.L; ++l) {
     hps_status s = vcycle_down(p, l, wv);
     if (s != HPS_OK) return s;

@@ -24,6 +24,8 @@ hipError_t add_strided(cd* a, const cd* b, int n, int nq, long long stride, hipS
 // out = a x + b y
 hipError_t axpby(cd a, const cd* x, cd b, const cd* y, cd* out, long long n, hipStream_t st);
 hipError_t vcopy(const cd* src, cd* dst, long long n, hipStream_t st);
+// dst = src and zero = 0 (n entries each) in one launch.
+hipError_t vcopy_zero(const cd* src, cd* dst, cd* zero, long long n, hipStream_t st);
 int dot_blocks(long long n);
 // Vectors of nq problems are stored one after the other (segments of n).
 // out[q*ostride + v] (+)= sum_i conj(V_v[q*n + i]) w[q*n + i], v < nvec;

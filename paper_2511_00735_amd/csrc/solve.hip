@@ -138,6 +138,14 @@ __global__ void copy_kernel(const cd* src, cd* dst, long long n) {
     dst[i] = src[i];
 }
 
+__global__ void copy_zero_kernel(const cd* src, cd* dst, cd* zero, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    dst[i] = src[i];
+    zero[i] = cmk(0.0, 0.0);
+  }
+}
+
 // ---- deterministic reductions -------------------------------------------
 // Wave-level sum in a fixed butterfly order.
 // Lane l - s of the same 16-lane row (0 outside the row), by DPP.
@@ -512,7 +520,14 @@ __global__ __launch_bounds__(kCT) void coarse_finish_kernel(const cd* H, int k, 
   idx += (long long)q * n;
   __shared__ cd R[kMaxCoarse + 1][kMaxCoarse];
   __shared__ cd gv[kMaxCoarse + 1];
-  if (threadIdx.x == 0) lsq_small(H, k + 1, k, beta2, y, nullptr, R, gv);
+  // H and beta^2 staged in LDS by the whole workgroup in one round trip: the
+  // serial solve below would otherwise wait on its global loads one by one
+  __shared__ cd Hs[(kMaxCoarse + 1) * kMaxCoarse];
+  __shared__ cd b2s;
+  for (int i = threadIdx.x; i < (k + 1) * k; i += kCT) Hs[i] = H[i];
+  if (threadIdx.x == 0) b2s = beta2[0];
+  __syncthreads();
+  if (threadIdx.x == 0) lsq_small(Hs, k + 1, k, &b2s, y, nullptr, R, gv);
   __syncthreads();
   for (int i = threadIdx.x; i < n; i += kCT) {
     cd acc = cmk(0.0, 0.0);
@@ -575,6 +590,11 @@ hipError_t vfill(cd* v, long long n, cd val, hipStream_t st) {
 
 hipError_t axpby(cd a, const cd* x, cd b, const cd* y, cd* out, long long n, hipStream_t st) {
   hipLaunchKernelGGL(axpby_kernel, dim3(grid_for(n)), dim3(256), 0, st, a, x, b, y, out, n);
+  return hipPeekAtLastError();
+}
+
+hipError_t vcopy_zero(const cd* src, cd* dst, cd* zero, long long n, hipStream_t st) {
+  hipLaunchKernelGGL(copy_zero_kernel, dim3(grid_for(n)), dim3(256), 0, st, src, dst, zero, n);
   return hipPeekAtLastError();
 }
 
