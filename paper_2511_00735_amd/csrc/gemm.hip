@@ -183,26 +183,48 @@ __device__ __forceinline__ void gemm_tile(const GemmArgsT<T>& a, int tile, int b
   T* Db = a.D + (long long)b * a.Dstride;
   const T* Cb = a.C.base ? a.C.base + (long long)b * a.C.bstride : nullptr;
   const bool use_c = (a.beta.x != 0.0 || a.beta.y != 0.0);
+  // one output entry (tile row r, column c) with its epilogue
+  auto emit = [&](int r, int c, T acc) {
+    const int gi = m0 + r, gj = n0 + c;
+    if (gi >= a.M || gj >= a.N) return;
+    T* dst = Db + (long long)imap(a.dc, gj) * a.ldd + imap(a.dr, gi);
+    if (a.skip.enabled && (dead_r[r] || dead_c[c])) {
+      *dst = cx<T>::make(0.0, 0.0);
+      return;
+    }
+    T out = cmul(a.alpha, acc);
+    if (use_c) out = cfma(a.beta, Cb[(long long)imap(a.C.c, gj) * a.C.ld + imap(a.C.r, gi)], out);
+    if (a.has_diag && gi == gj) out = cadd(out, a.diag_add);
+    *dst = out;
+  };
+  if constexpr (sizeof(T) == sizeof(cf) && BM <= 32) {
+    // small FP32 tiles (short K: the epilogue weighs most) go through LDS so
+    // that consecutive threads write (and read C at) consecutive rows of a
+    // column; in the MFMA layout the 16 lanes of a row group hold 16 different
+    // columns, one cache line each.  (64 x 64 FP32 tiles lost more to the
+    // larger LDS footprint than they gained.)
+    __shared__ T Cs[BN][BM + 1];
 #pragma unroll
-  for (int i = 0; i < TM; ++i)
+    for (int i = 0; i < TM; ++i)
 #pragma unroll
-    for (int j = 0; j < TN; ++j)
+      for (int j = 0; j < TN; ++j)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int gi = m0 + wm * (BM / WM) + i * 16 + Mfma<T>::row(lk, v);
-        const int gj = n0 + wn * (BN / WN) + j * 16 + lr;
-        if (gi < a.M && gj < a.N) {
-          if (a.skip.enabled && (dead_r[gi - m0] || dead_c[gj - n0])) {
-            Db[(long long)imap(a.dc, gj) * a.ldd + imap(a.dr, gi)] = cx<T>::make(0.0, 0.0);
-            continue;
-          }
-          T acc = cx<T>::make(accr[i][j][v], acci[i][j][v]);
-          T out = cmul(a.alpha, acc);
-          if (use_c) out = cfma(a.beta, Cb[(long long)imap(a.C.c, gj) * a.C.ld + imap(a.C.r, gi)], out);
-          if (a.has_diag && gi == gj) out = cadd(out, a.diag_add);
-          Db[(long long)imap(a.dc, gj) * a.ldd + imap(a.dr, gi)] = out;
-        }
-      }
+        for (int v = 0; v < 4; ++v)
+          Cs[wn * (BN / WN) + j * 16 + lr][wm * (BM / WM) + i * 16 + Mfma<T>::row(lk, v)] =
+              cx<T>::make(accr[i][j][v], acci[i][j][v]);
+    __syncthreads();
+#pragma unroll 4
+    for (int idx = tid; idx < BM * BN; idx += NT) emit(idx % BM, idx / BM, Cs[idx / BM][idx % BM]);
+  } else {
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          emit(wm * (BM / WM) + i * 16 + Mfma<T>::row(lk, v), wn * (BN / WN) + j * 16 + lr,
+               cx<T>::make(accr[i][j][v], acci[i][j][v]));
+  }
 }
 
 template <class T, int BM, int BN, int WM, int WN>
