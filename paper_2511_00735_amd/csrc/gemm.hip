@@ -49,8 +49,15 @@ __device__ __forceinline__ void gemm_tile(const GemmArgsT<T>& a, int tile, int b
   constexpr int NT = 64 * WM * WN;
   constexpr int TM = BM / WM / 16;
   constexpr int TN = BN / WN / 16;
-  __shared__ T As[KT][BM];
-  __shared__ T Bs[KT][BN + 1];   // padded: the 16 k-rows of a column land in different banks
+  // LDS: the K chunk (As, Bs[k] padded: the 16 k-rows of a column land in
+  // different banks); after the last chunk the same bytes hold the FP32 output
+  // tile (BM x BN, or half its columns per pass at 64 x 64) for the epilogue
+  constexpr int kCP = (sizeof(T) == sizeof(cf) && BM == 64) ? BN / 2 : BN;   // columns per epilogue pass
+  constexpr size_t kABytes = sizeof(T) * KT * BM, kBBytes = sizeof(T) * KT * (BN + 1);
+  constexpr size_t kCBytes = sizeof(T) == sizeof(cf) ? sizeof(T) * kCP * (BM + 1) : 0;
+  __shared__ __align__(16) unsigned char smem[(kABytes + kBBytes) > kCBytes ? (kABytes + kBBytes) : kCBytes];
+  T (*As)[BM] = reinterpret_cast<T (*)[BM]>(smem);
+  T (*Bs)[BN + 1] = reinterpret_cast<T (*)[BN + 1]>(smem + kABytes);
   const int tilesM = (a.M + BM - 1) / BM;
   const int m0 = (tile % tilesM) * BM;
   const int n0 = (tile / tilesM) * BN;
@@ -197,24 +204,35 @@ __device__ __forceinline__ void gemm_tile(const GemmArgsT<T>& a, int tile, int b
     if (a.has_diag && gi == gj) out = cadd(out, a.diag_add);
     *dst = out;
   };
-  if constexpr (sizeof(T) == sizeof(cf) && BM <= 32) {
-    // small FP32 tiles (short K: the epilogue weighs most) go through LDS so
-    // that consecutive threads write (and read C at) consecutive rows of a
-    // column; in the MFMA layout the 16 lanes of a row group hold 16 different
-    // columns, one cache line each.  (64 x 64 FP32 tiles lost more to the
-    // larger LDS footprint than they gained.)
-    __shared__ T Cs[BN][BM + 1];
+  // FP32 tiles with a short K (where the epilogue weighs most; every small
+  // tile) go through LDS (the K-chunk buffers, free after the last chunk's
+  // barrier) so that consecutive threads write (and read C at) consecutive
+  // rows of a column; in the MFMA layout the 16 lanes of a row group hold 16
+  // different columns, one cache line each.  64 x 64 tiles take two passes of
+  // 32 columns, written by the waves holding them; with a long K their extra
+  // barriers cost more than the coalescing gains.
+  bool via_lds = false;
+  if constexpr (sizeof(T) == sizeof(cf)) via_lds = BM <= 32 || a.K <= 64;
+  if (via_lds) {
+    T (*Cs)[BM + 1] = reinterpret_cast<T (*)[BM + 1]>(smem);
 #pragma unroll
-    for (int i = 0; i < TM; ++i)
+    for (int h = 0; h < BN / kCP; ++h) {
+      if (h) __syncthreads();   // the previous pass's reads are done
 #pragma unroll
-      for (int j = 0; j < TN; ++j)
+      for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
-          Cs[wn * (BN / WN) + j * 16 + lr][wm * (BM / WM) + i * 16 + Mfma<T>::row(lk, v)] =
-              cx<T>::make(accr[i][j][v], acci[i][j][v]);
-    __syncthreads();
+        for (int j = 0; j < TN; ++j) {
+          const int c = wn * (BN / WN) + j * 16 + lr - h * kCP;
+          if (c < 0 || c >= kCP) continue;   // wave-uniform: the column half of this wave
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            Cs[c][wm * (BM / WM) + i * 16 + Mfma<T>::row(lk, v)] = cx<T>::make(accr[i][j][v], acci[i][j][v]);
+        }
+      __syncthreads();
 #pragma unroll 4
-    for (int idx = tid; idx < BM * BN; idx += NT) emit(idx % BM, idx / BM, Cs[idx / BM][idx % BM]);
+      for (int idx = tid; idx < BM * kCP; idx += NT)
+        emit(idx % BM, h * kCP + idx / BM, Cs[idx / BM][idx % BM]);
+    }
   } else {
 #pragma unroll
     for (int i = 0; i < TM; ++i)
