@@ -282,6 +282,9 @@ def main():
         sys.exit(2)
     import torch
     from paper_2511_00735_amd import hps, workloads
+    # the caching allocator stays under 90% of the device, so that the HIP
+    # runtime's own allocations (queues, kernel scratch) always find memory
+    torch.cuda.set_per_process_memory_fraction(0.9)
 
     pr = workloads.c3()
     pr.n, pr.N, pr.kappa, pr.eta = args.n, args.order, args.kappa, args.kappa

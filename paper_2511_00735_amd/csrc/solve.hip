@@ -662,10 +662,7 @@ hipError_t coarse_arnoldi(cd* V, int n, long long vq, int j, const CoarseW& src,
   else if (j < kFastV && n <= 8 * 256)
     hipLaunchKernelGGL((coarse_arnoldi_fast_kernel<8, 256>), dim3(nq), dim3(256), 0, st, V, n, vq, j, src, Hcol,
                        hsize);
-  else if (j < kFastV && n <= 16 * 256)
-    hipLaunchKernelGGL((coarse_arnoldi_fast_kernel<16, 256>), dim3(nq), dim3(256), 0, st, V, n, vq, j, src, Hcol,
-                       hsize);
-  else
+  else   // (16 entries per thread would spill to scratch, which the runtime must allocate at dispatch)
     hipLaunchKernelGGL(coarse_arnoldi_kernel, dim3(nq), dim3(kCT), 0, st, V, n, vq, j, src, wtmp, Hcol, hsize);
   return hipPeekAtLastError();
 }

@@ -217,6 +217,10 @@ class Server:
         cond = threading.Condition()
         state = {"fed": 0, "done": False, "error": None}
         retried = set()   # ids of requests whose batch ran out of memory once
+        # cached blocks of earlier work go back to the device: the workers'
+        # new streams and their kernels' scratch are allocated by the runtime
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
         for shape in sorted(set((r.n, r.N) for r in trace)):
             self._node_data(*shape)
         self._t0 = time.perf_counter()
