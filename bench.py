@@ -12,13 +12,20 @@ The headline run is the mixed-precision path; the plain FP64 path runs on the
 same inputs beside it.
 
 Roofline: the dominant kernel is the leaf kernel (one launch per up to 4096
-elements: the whole 64x64 leaf level).  Its launches inside the timed steps are bracketed by HIP events on
-the library's stream (library option HPS_OPT_TIMING); achieved = algorithmic
-leaf flops of the elements a launch builds / the mean launch duration.  The HBM
-traffic per launch comes from the rocprofv3 counter summary under profiles/
-(FETCH_SIZE and WRITE_SIZE, scaled by a plain copy kernel's readings), and is
-reported only while the leaf kernel source and the elements per launch still
-match the ones measured.
+elements: the whole 64x64 leaf level).  Its launches inside the timed steps are
+bracketed by HIP events on the library's stream (library option
+HPS_OPT_TIMING); achieved = the flops the kernel executes for the elements a
+launch builds / the mean launch duration, against the FP64 peak.  The dense
+complex LU count of the method as stated (the n_loc x n_loc element solve) is
+reported beside it under its own key.  The HBM traffic per launch comes from
+the rocprofv3 counter summary under profiles/ (FETCH_SIZE and WRITE_SIZE,
+scaled by a plain copy kernel's readings), and is reported only while the leaf
+kernel source and the elements per launch still match the ones measured; it is
+set beside the algorithmic bytes (coefficient in, T and H out).
+
+Accuracy: every GPU solution is compared (outside the timed region) with the
+oracle's direct HPS solution of the same inputs, computed on the host; the
+oracle's run is also the CPU baseline.
 
 Prints ONE JSON line (see the repository documentation for the fields).
 --traffic-probe instead runs one 1 GiB device copy (the counter calibration)
@@ -65,10 +72,9 @@ def parse():
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the plain FP64 run of the same workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-seconds", type=float, default=15.0)
     ap.add_argument("--traffic-probe", action="store_true",
                     help="one 1 GiB device copy, then one leaf build (for rocprofv3 --pmc runs)")
-    ap.add_argument("--serve-seconds", type=float, default=5.0,
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="length of the request trace served beside the headline (0: skip)")
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-problem batch")
     return ap.parse_args()
@@ -81,6 +87,19 @@ def leaf_flops_algorithmic(N):
     impedance operator (8 real flops per complex multiply-add)."""
     nloc = (N + 1) ** 2 - 4
     return 8.0 / 3.0 * nloc ** 3 + 32.0 * (N - 1) * nloc ** 2 + 128.0 * (N - 1) ** 2 * (N + 2)
+
+
+def leaf_bytes_algorithmic(N):
+    """HBM bytes a leaf build must move per element: the coefficient at the
+    (N+1)^2 nodes in (FP64), the 4(N-1) x 4(N-1) complex FP64 map T and the
+    complex load H out."""
+    m = 4 * (N - 1)
+    return 8 * (N + 1) ** 2 + 16 * m * m + 16 * m
+
+
+def progress(msg):
+    """Progress line on stderr (stdout carries the one JSON result line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def leaf_traffic_record():
@@ -134,61 +153,84 @@ def merge_flops_executed(n, N, L):
     return tot, per_level
 
 
-def cpu_baseline(pr, sample_seconds):
-    """The oracle (CPU, FP64) timed on a bounded sample of the same workload and
-    scaled to the whole job: leaf maps of a sample of elements, and the merges
-    of a sample of pairs per level; the solve phase is bounded below by zero and
-    not included (the build dominates the oracle's time)."""
-    from oracle import gll, leaf, merge, mesh
-    n, N = pr.n, pr.N
-    p = N - 1
+def oracle_job(pr):
+    """The oracle's whole job on the host at all of its cores (NumPy/LAPACK's
+    default threading): leaf maps of every element, the merge hierarchy and the
+    direct HPS solve with the exact top-level solve (build + solve).  Returns
+    (g, seconds, phase seconds); g is the reference the GPU solutions are
+    compared with (outside any timed region)."""
+    from oracle import gll, leaf, merge, mesh, direct
+    n, N, p = pr.n, pr.N, pr.N - 1
+    t0 = time.perf_counter()
     xi = gll.gll_nodes(N)
     c = leaf.nodal_coefficient(N, n, pr.kappa, pr.b, xi)
-    E = n * n
-    t0 = time.perf_counter()
-    ns = 0
-    T_s = []
-    while time.perf_counter() - t0 < 0.4 * sample_seconds and ns < E:
-        k = min(64, E - ns)
-        T, _ = leaf.leaves(N, 1.0 / n, pr.kappa, pr.eta, c[ns:ns + k])
-        T_s.append(T)
-        ns += k
-    t_leaf = (time.perf_counter() - t0) * E / ns
-    T = np.concatenate(T_s)
-    # merges: time one pair per level, using sample maps of the right size
-    t_merge = 0.0
-    Tcur = [T[0], T[1 % len(T)]]
-    budget = 0.6 * sample_seconds
-    tm0 = time.perf_counter()
-    sampled_levels = 0
-    L = mesh.lmax(n) if not pr.levels else pr.levels
-    for level in range(1, L):
-        if time.perf_counter() - tm0 > budget:
-            break
-        t1 = time.perf_counter()
-        Tm, _, _ = merge.merge_pair(level, p, Tcur[0], Tcur[1])
-        dt = time.perf_counter() - t1
-        wx, wy = mesh.box_dims(level)
-        pairs = (n // wx) * (n // wy) // 2
-        t_merge += dt * pairs
-        Tcur = [Tm, Tm]
-        sampled_levels += 1
-    total = t_leaf + t_merge
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {
-        "value": pr.skeleton_dof / total if sampled_levels == L - 1 else None,
+    T, H = leaf.leaves(N, 1.0 / n, pr.kappa, pr.eta, c)
+    t1 = time.perf_counter()
+    hier = merge.build_hierarchy(n, p, T, H, top=mesh.lmax(n))
+    t2 = time.perf_counter()
+    xs, ys, nx, ny = mesh.canonical_slot_coords(n, N, xi)
+    g = direct.solve(n, p, T, H, pr.wave.t(xs, ys, nx, ny), hierarchy=hier)
+    t3 = time.perf_counter()
+    return g, t3 - t0, {"leaves": t1 - t0, "merges": t2 - t1, "downward_solve": t3 - t2}
+
+
+def oracle_thread_ratio(pr, levels=9):
+    """Time of the oracle at 1 thread over its time at all cores, on a bounded
+    sample of the same workload: the leaf maps of 64 elements and one pair
+    merge at each of levels 1..`levels`."""
+    from threadpoolctl import threadpool_limits
+    from oracle import gll, leaf, merge
+    n, N, p = pr.n, pr.N, pr.N - 1
+    xi = gll.gll_nodes(N)
+    c = leaf.nodal_coefficient(N, n, pr.kappa, pr.b, xi)[:64]
+
+    def sample():
+        t0 = time.perf_counter()
+        T, _ = leaf.leaves(N, 1.0 / n, pr.kappa, pr.eta, c)
+        cur = [T[0], T[1]]
+        for level in range(1, levels + 1):
+            Tm, _, _ = merge.merge_pair(level, p, cur[0], cur[1])
+            cur = [Tm, Tm]
+        return time.perf_counter() - t0
+
+    t_all = min(sample() for _ in range(2))
+    with threadpool_limits(1):
+        t_one = min(sample() for _ in range(2))
+    return t_one / t_all, t_one, t_all
+
+
+def cpu_baseline(pr):
+    """cpu_baseline: the oracle's whole job timed once at all host cores (its
+    solution is the reference of err_vs_oracle), and the same job at one
+    thread estimated with the 1-thread / all-core time ratio of a sample."""
+    g, secs, parts = oracle_job(pr)
+    ratio, t_one, t_all = oracle_thread_ratio(pr)
+    cores = len(os.sched_getaffinity(0))
+    threads = int(os.environ.get("OMP_NUM_THREADS", cores))
+    out = {
+        "value": round(pr.skeleton_dof / secs, 1),
         "unit": UNIT,
-        "cores": threads,
+        "cores": min(cores, threads),
         "kind": "oracle",
-        "sample": (f"oracle leaf maps of {ns}/{E} elements and one pair merge per level "
-                   f"({sampled_levels}/{L - 1} levels), scaled by element and pair counts; "
-                   f"build only (solve excluded), est. job {total:.1f} s"),
+        "sample": (f"the whole job once (not a sample): oracle leaf maps of all {pr.n * pr.n} elements, "
+                   f"merge hierarchy and direct HPS solve with the exact top solve, FP64, "
+                   f"{secs:.1f} s at {min(cores, threads)} threads "
+                   f"(leaves {parts['leaves']:.1f} s, merges {parts['merges']:.1f} s, "
+                   f"downward solve {parts['downward_solve']:.1f} s)"),
+        "one_thread": {
+            "value": round(pr.skeleton_dof / (secs * ratio), 1),
+            "estimate": (f"whole-job time x {ratio:.2f}, the 1-thread / all-core time ratio of a sample "
+                         f"(leaf maps of 64 elements and one pair merge at levels 1-9: "
+                         f"{t_one:.2f} s vs {t_all:.2f} s, best of 2)"),
+        },
     }
+    return out, g
 
 
 def run_precision(args, pr, precision, hps, torch):
     """Build + solve the workload `steps` times (after `warmup` untimed steps)
-    in one precision; returns timings, per-phase event times and the solution."""
+    in one precision; returns timings, the mean per-phase event times of the
+    timed steps and the solution."""
     ctx = hps.Context()
     stream = ctx.stream
     prec = hps.HPS_MIXED if precision == "mixed" else hps.HPS_FP64
@@ -200,39 +242,41 @@ def run_precision(args, pr, precision, hps, torch):
     rhs = torch.empty(prob.nslots, dtype=torch.complex128, device="cuda")
     g = torch.empty_like(rhs)
 
-    def step():
+    def step(ev=None):
+        # ev: four events recorded on the library's stream around the phases
+        if ev is not None:
+            ev[0].record(stream)
         prob.build_leaves(b_nodes)
+        if ev is not None:
+            ev[1].record(stream)
         prob.merge_all()
+        if ev is not None:
+            ev[2].record(stream)
         hps.set_rhs([prob], [t_data], [rhs])
-        return prob.gmres_solve(rhs, tol=pr.tol, maxit=600, out=g)[1]
+        info = prob.gmres_solve(rhs, tol=pr.tol, maxit=600, out=g)[1]
+        if ev is not None:
+            ev[3].record(stream)
+        return info
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
     ctx.set_timing(True)
     t0 = time.perf_counter()
-    infos = [step() for _ in range(args.steps)]
+    infos = [step(evs[i]) for i in range(args.steps)]
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     leaf_launches, leaf_ms, leaf_units = ctx.kernel_time(hps.HPS_KERNEL_LEAF)
     ctx.set_timing(False)
-
-    # phase timing with events on the library's stream (outside the timed loop)
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-    ev[0].record(stream)
-    prob.build_leaves(b_nodes)
-    ev[1].record(stream)
-    prob.merge_all()
-    ev[2].record(stream)
-    hps.set_rhs([prob], [t_data], [rhs])
-    prob.gmres_solve(rhs, tol=pr.tol, maxit=600, out=g)
-    ev[3].record(stream)
-    torch.cuda.synchronize()
+    phases = np.array([[e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]), e[2].elapsed_time(e[3])]
+                       for e in evs])
     return {
         "ms": 1e3 * dt / args.steps,
         "value": pr.skeleton_dof * args.steps / dt,
         "info": infos[-1],
-        "phase_ms": [ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2]), ev[2].elapsed_time(ev[3])],
+        "iterations_per_step": [i["iterations"] for i in infos],
+        "phase_ms": list(phases.mean(axis=0)),
         "g": g.clone(),
         "leaf": (leaf_launches, leaf_ms, leaf_units),
     }
@@ -264,13 +308,15 @@ def run_serving(hps, torch, seconds):
     from paper_2511_00735_amd import workloads
     from paper_2511_00735_amd.serve import Server
     trace = workloads.c5(duration=seconds)
-    out = {"trace": (f"first {seconds:g} s of the seeded Poisson trace (50 req/s): {len(trace)} requests, "
+    out = {"trace": (f"{seconds:g} s of the seeded Poisson trace (50 req/s): {len(trace)} requests, "
                      f"{sum(1 for r in trace if r.n == 128)} at 128x128 N=16 kappa=400"),
            "workers": 3, "memory_budget_gib": 200}
     for prec in ("mixed", "fp64"):
+        progress(f"serving {len(trace)} requests over {seconds:g} s, {prec}")
         srv = Server(precision=prec, workers=3, max_batch=32, memory_budget=200 << 30)
         _, summ = srv.run(trace)
         out[prec] = summ
+        progress(f"serving {prec}: {summ.get('solves_per_s')} solves/s, p99 {summ.get('latency_p99_ms')} ms")
     return out
 
 
@@ -324,9 +370,11 @@ def main():
     nl, lms, lunits = main_run["leaf"]
     per_launch_ms = lms / max(nl, 1)
     per_launch_units = lunits / max(nl, 1)
-    alg = leaf_flops_algorithmic(pr.N) * per_launch_units
-    ach = alg / (per_launch_ms * 1e-3) / 1e12
-    exe = leaf_flops_executed(pr.N) * per_launch_units / (per_launch_ms * 1e-3) / 1e12
+    per_launch_s = per_launch_ms * 1e-3
+    executed = leaf_flops_executed(pr.N) * per_launch_units
+    dense = leaf_flops_algorithmic(pr.N) * per_launch_units
+    ach = executed / per_launch_s / 1e12
+    alg_bytes = leaf_bytes_algorithmic(pr.N) * per_launch_units
     traffic = None
     rec = leaf_traffic_record()
     if rec is not None:
@@ -335,10 +383,14 @@ def main():
             traffic = rec[0]
     roof = {"bound": "alu", "achieved": round(ach, 3), "peak": MI355X_FP64_TFLOPS, "unit": "TFLOP/s",
             "frac": round(ach / MI355X_FP64_TFLOPS, 4), "traffic": traffic,
-            "kernel": "leaf_kernel (hps_build_leaves; FP64 vector FMA)",
+            "kernel": "leaf_kernel (hps_build_leaves; FP64)",
             "launches": nl, "units_per_launch": per_launch_units, "avg_launch_ms": round(per_launch_ms, 4),
-            "algorithmic_flops_per_launch": alg,
-            "executed_tflops": round(exe, 3)}
+            "executed_flops_per_launch": executed,
+            "algorithmic_bytes_per_launch": alg_bytes,
+            "traffic_over_algorithmic_bytes": None if traffic is None else round(traffic / alg_bytes, 1),
+            "hbm_gbs": None if traffic is None else round(traffic / per_launch_s / 1e9, 1),
+            "hbm_frac": None if traffic is None else round(traffic / per_launch_s / 1e9 / MI355X_HBM_GBS, 4),
+            "dense_lu_equivalent": {"flops_per_launch": dense, "tflops": round(dense / per_launch_s / 1e12, 3)}}
     info = main_run["info"]
     cfg = {"workload": (f"{pr.n}x{pr.n} elements, N={pr.N}, kappa=eta={pr.kappa:g}, "
                         f"8 seeded bumps (seed 3), plane-wave t, L={pr.levels}, "
@@ -346,7 +398,8 @@ def main():
            "precision": args.precision, "skeleton_dof": dof,
            "iterations": info["iterations"], "relres_true": info["relres_true"],
            "phase_ms": {"leaves": round(t_leaf, 3), "merges": round(t_merge, 3),
-                        "rhs+solve": round(t_solve, 3)},
+                        "rhs+solve": round(t_solve, 3),
+                        "note": f"mean over the {args.steps} timed steps (HIP events on the library's stream)"},
            "phase_tflops": {"leaves": round(leaf_tf, 3), "merges": round(merge_tf, 3)}}
     if ref is not None:
         gm, gf = main_run["g"], ref["g"]
@@ -364,12 +417,22 @@ def main():
         "dtype": "c64+c128" if args.precision == "mixed" else "c128",
         "data": "synthetic", "config": cfg, "roofline": roof,
     }
+    progress("headline done: %.1f DOF/s" % main_run["value"])
     if not args.no_batch:
         cfg["batch_256_problems"] = run_batch_c4(hps, torch)
+        progress("256-problem batch done")
     if args.serve_seconds > 0:
         cfg["serving"] = run_serving(hps, torch, args.serve_seconds)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(pr, args.cpu_sample_seconds)
+        progress("oracle on the host (whole job, then a 1-thread sample)")
+        out["cpu_baseline"], g_ref = cpu_baseline(pr)
+        g_ref = torch.from_numpy(g_ref)
+        err = {args.precision: float(torch.linalg.norm(main_run["g"].cpu() - g_ref) / torch.linalg.norm(g_ref))}
+        if ref is not None:
+            err["fp64"] = float(torch.linalg.norm(ref["g"].cpu() - g_ref) / torch.linalg.norm(g_ref))
+        err["reference"] = ("the oracle's direct HPS solution (exact discrete skeleton solution, FP64, host); "
+                            f"GPU solutions stop at relative residual {pr.tol:g}")
+        cfg["err_vs_oracle"] = err
     print(json.dumps(out), flush=True)
 
 

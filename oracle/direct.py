@@ -16,10 +16,15 @@ from . import mesh
 from .merge import build_hierarchy, merge_pair, merged_order
 
 
-def solve(n, p, leafT, leafH, t_slots):
-    """g in canonical slot layout (physical slots 0) by direct HPS."""
+def solve(n, p, leafT, leafH, t_slots, hierarchy=None):
+    """g in canonical slot layout (physical slots 0) by direct HPS.
+
+    hierarchy: the (T, H) that build_hierarchy(n, p, leafT, leafH) returns,
+    when the caller has already built it (it is not rebuilt then)."""
     Lm = mesh.lmax(n)
-    T, H = build_hierarchy(n, p, leafT, leafH, top=Lm)
+    if hierarchy is None:
+        hierarchy = build_hierarchy(n, p, leafT, leafH, top=Lm)
+    T, H = hierarchy
     root = mesh.box_slots(n, p, Lm + 1, 0, 0)
     incoming = {(0, 0): t_slots[root]}
     for level in range(Lm, 0, -1):

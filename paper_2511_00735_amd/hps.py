@@ -176,7 +176,7 @@ class Context:
         self.check(lib.hps_sync(self.handle), "hps_sync")
 
     def set_graphs(self, on):
-        """Replay the V-cycle from a captured HIP graph (default) or launch eagerly."""
+        """Replay the V-cycle from a captured HIP graph, or launch it eagerly (the default)."""
         self.check(lib.hps_set_option(self.handle, HPS_OPT_GRAPHS, 1 if on else 0), "hps_set_option")
 
     def set_timing(self, on):

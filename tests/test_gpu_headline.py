@@ -1,0 +1,147 @@
+"""GPU parity at the benchmark's own workload: 64x64 elements, GLL order 16,
+kappa = eta = 200, b = 8 seeded Gaussian bumps (seed 3), plane-wave impedance
+data, coarse level L = 12 with 5 coarse GMRES steps.
+
+Every quantity is compared with the CPU FP64 oracle run on the same seeded
+inputs (about a minute of host time, shared by the tests of this module):
+
+* all 4096 leaf ItI maps (Sec. 3.1): per map relative Frobenius error
+  <= 1e-11 and per entry |dT| <= 1e-11 max|T| (two FP64 eliminations of
+  the same map; the leaf systems have condition numbers ~1e2-1e4);
+* the FP64 flexible GMRES solution at tol 1e-12 against the oracle's direct
+  HPS solution (Sec. 4.2): <= 1e-10 relative (the FP64 target);
+* the mixed-precision path: one V-cycle with the exact top solve (direct HPS
+  on the FP32 tree, before refinement) <= 1e-5, and FGMRES on the FP64 outer
+  operator (after refinement) <= 1e-10;
+* sampled FP32 inverses of the shared-face blocks A at merge levels 8 and 9
+  (m = 240, the blocked Gauss-Jordan path), against the inverse of the
+  oracle's A: first-order perturbation bound cond(A) * (FP32 level error +
+  n u32), with the level error 2e-5 * level measured by the level-map test.
+"""
+import numpy as np
+import pytest
+
+from tests.gpu_cases import rel
+from paper_2511_00735_amd import workloads
+
+pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
+
+U32 = 2.0 ** -24
+
+
+@pytest.fixture(scope="module")
+def c3():
+    """The oracle's leaf maps, merge hierarchy and direct-HPS solution of the
+    64x64 workload (host, FP64)."""
+    import time
+    from oracle import gll, leaf, merge, mesh, direct
+    pr = workloads.c3()
+    n, N, p = pr.n, pr.N, pr.N - 1
+    t0 = time.perf_counter()
+    xi = gll.gll_nodes(N)
+    c = leaf.nodal_coefficient(N, n, pr.kappa, pr.b, xi)
+    T, H = leaf.leaves(N, 1.0 / n, pr.kappa, pr.eta, c)
+    t1 = time.perf_counter()
+    hier = merge.build_hierarchy(n, p, T, H, top=mesh.lmax(n))
+    xs, ys, nx, ny = mesh.canonical_slot_coords(n, N, xi)
+    t = pr.wave.t(xs, ys, nx, ny)
+    g = direct.solve(n, p, T, H, t, hierarchy=hier)
+    print(f"[c3 oracle] leaves {t1 - t0:.1f} s, hierarchy + direct solve "
+          f"{time.perf_counter() - t1:.1f} s", flush=True)
+    return dict(pr=pr, T=T, H=H, hier=hier[0], g=g)
+
+
+def _problem(hps, ctx, pr, precision, levels, coarse_iters):
+    prec = hps.HPS_MIXED if precision == "mixed" else hps.HPS_FP64
+    desc = hps.make_desc(pr.n, pr.N, pr.kappa, pr.eta, levels=levels, coarse_iters=coarse_iters,
+                         precision=prec)
+    prob = hps.Problem(ctx, desc)
+    prob.build_leaves(prob.coefficient_nodes(pr.b))
+    prob.merge_all()
+    rhs = prob.set_rhs(prob.boundary_data(pr.wave.t))
+    return prob, rhs
+
+
+def test_c3_all_leaf_maps(hps, ctx, c3):
+    import torch
+    pr = c3["pr"]
+    n = pr.n
+    print("[c3] leaf maps, FP64 problem", flush=True)
+    desc = hps.make_desc(pr.n, pr.N, pr.kappa, pr.eta, levels=12, coarse_iters=5)
+    prob = hps.Problem(ctx, desc)
+    prob.build_leaves(prob.coefficient_nodes(pr.b))
+    Tg = prob.level_T(1)
+    order = torch.tensor([bx + n * by for bx, by in (hps.morton_box_xy(1, j) for j in range(n * n))])
+    To = torch.from_numpy(c3["T"])[order]      # oracle maps in the GPU's storage order
+    d = Tg.cpu() - To
+    per_map = torch.linalg.matrix_norm(d) / torch.linalg.matrix_norm(To)
+    worst = int(per_map.argmax())
+    print(f"[c3] leaf maps: max per-map rel {per_map.max():.2e}, "
+          f"max entry {d.abs().max() / To.abs().max():.2e}", flush=True)
+    assert per_map.max() <= 1e-11, (worst, hps.morton_box_xy(1, worst), float(per_map.max()))
+    assert d.abs().amax(dim=(1, 2)).max() <= 1e-11 * To.abs().max()
+
+
+def test_c3_fp64_solution(hps, ctx, c3):
+    pr = c3["pr"]
+    print("[c3] FP64 FGMRES, L = 12, k = 5, tol 1e-12", flush=True)
+    prob, rhs = _problem(hps, ctx, pr, "fp64", 12, 5)
+    g, info = prob.gmres_solve(rhs, tol=1e-12, maxit=600)
+    err = rel(g.cpu().numpy(), c3["g"])
+    print(f"[c3] FP64: {info['iterations']} its, relres {info['relres_true']:.2e}, "
+          f"error vs oracle {err:.2e}", flush=True)
+    assert info["status"] == 0 and info["relres_true"] <= 1e-12
+    assert err <= 1e-10
+
+
+def test_c3_mixed_before_and_after_refinement(hps, ctx, c3):
+    pr = c3["pr"]
+    print("[c3] mixed direct HPS (exact top solve)", flush=True)
+    prob, rhs = _problem(hps, ctx, pr, "mixed", 0, -1)
+    g0 = prob.precond_apply(rhs).cpu().numpy()
+    before = rel(g0, c3["g"])
+    del prob
+    print("[c3] mixed FGMRES, L = 12, k = 5, tol 1e-12", flush=True)
+    prob, rhs = _problem(hps, ctx, pr, "mixed", 12, 5)
+    g, info = prob.gmres_solve(rhs, tol=1e-12, maxit=600)
+    after = rel(g.cpu().numpy(), c3["g"])
+    print(f"[c3] mixed: before refinement {before:.2e}, after {after:.2e} "
+          f"({info['iterations']} its, relres {info['relres_true']:.2e})", flush=True)
+    assert before <= 1e-5, before
+    assert info["status"] == 0 and info["relres_true"] <= 1e-12
+    assert after <= 1e-10, after
+
+
+@pytest.mark.parametrize("level", [8, 9])
+def test_c3_fp32_blocked_inverses(hps, ctx, c3, level):
+    from oracle import merge as omerge
+    pr = c3["pr"]
+    p = pr.N - 1
+    print(f"[c3] FP32 blocked inverses at level {level}", flush=True)
+    desc = hps.make_desc(pr.n, pr.N, pr.kappa, pr.eta, levels=12, coarse_iters=5,
+                         precision=hps.HPS_MIXED)
+    prob = hps.Problem(ctx, desc)
+    prob.build_leaves(prob.coefficient_nodes(pr.b))
+    for lv in range(1, level + 1):
+        prob.merge_level(lv)
+    v = prob.level_view(level)
+    assert v.fp32 == 1 and v.shared_nodes == 240
+    Ai = prob.level_Ainv(level).cpu().numpy().astype(np.complex128)
+    Tl = prob.level_T(level).cpu().numpy().astype(np.complex128)
+    m2 = 2 * v.shared_nodes
+    for j in range(0, v.pairs, max(1, v.pairs // 4)):
+        P = hps.morton_box_xy(level, 2 * j)
+        Q = hps.morton_box_xy(level, 2 * j + 1)
+        # the kernel: a backward-stable inverse of the GPU's own FP32 A
+        Ag = omerge.pair_blocks(level, p, Tl[2 * j], Tl[2 * j + 1])["A"]
+        res = np.linalg.norm(Ag @ Ai[j] - np.eye(m2), 2) / (np.linalg.norm(Ag, 2) * np.linalg.norm(Ai[j], 2))
+        # the FP32 chain: against the inverse of the oracle's A
+        Ao = omerge.pair_blocks(level, p, c3["hier"][level - 1][P], c3["hier"][level - 1][Q])["A"]
+        Aoi = np.linalg.inv(Ao)
+        cond = np.linalg.cond(Ao)
+        err = rel(Ai[j], Aoi)
+        bound = cond * (2e-5 * level + m2 * U32)
+        print(f"[c3] level {level} pair {j}: residual {res:.2e}, vs oracle {err:.2e} "
+              f"(cond {cond:.1f}, bound {bound:.2e})", flush=True)
+        assert res <= m2 * U32, (j, res)
+        assert err <= bound, (j, err, bound)

@@ -70,7 +70,8 @@ def test_rhs_and_skeleton_matvec(hps, ctx):
 MERGE_CASES = [
     ("c1", 4, 8, 10.0),
     ("n8_N5", 8, 5, 14.0),
-    ("n16_N6", 16, 6, 30.0),   # merged boxes up to m = 80 (blocked inverse), e = 160
+    ("n16_N6", 16, 6, 30.0),   # merged boxes up to m = 80 (register inverse, m <= 128), e = 160
+    ("n16_N16", 16, 16, 40.0),  # top merge m = 240: the blocked Gauss-Jordan inverse
 ]
 
 
@@ -247,7 +248,7 @@ def test_graph_replays_match_eager(hps, ctx):
                 assert torch.equal(zg, ze), rep
                 prob.skeleton_apply(r)          # unrelated eager work between replays
     finally:
-        ctx.set_graphs(True)
+        ctx.set_graphs(False)           # the library's default: eager launches
 
 
 # ---- mixed precision: FP32 lower merges, FP64 top merges / coarse / outer ----
