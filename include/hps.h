@@ -38,8 +38,16 @@
  *
  * Errors: every call returns hps_status; no exception crosses the ABI.  After a
  * failure hps_last_error(ctx) describes it.  Argument checks happen on the
- * host; zero pivots found on the device are reported as HPS_ERR_SINGULAR at the
- * next synchronising call (hps_gmres_solve, hps_sync).
+ * host.  Failures found on the device are recorded in the problem's workspace
+ * and reported at the next synchronising call (hps_gmres_solve, which checks
+ * before its first iteration and at exit, and hps_sync): an exact zero pivot
+ * in a leaf or merge factorisation as HPS_ERR_SINGULAR, its message naming the
+ * problem and the element (leaf) or the merge level and pair of the first one;
+ * a NaN or Inf in b_nodes or s_nodes as HPS_ERR_ARG, naming the problem and
+ * element (that element's leaf map is not built).  Leaf elements close to an
+ * interior Dirichlet resonance (a nearly singular interior block: its smallest
+ * pivot below 0.02 of its largest) are recomputed from the complex element
+ * system of Sec. 3.1 by partial-pivoting LU, so they keep full accuracy.
  */
 #ifndef HPS_H
 #define HPS_H
@@ -81,16 +89,24 @@ typedef struct {
   int32_t levels;        /* coarse level L, 1 <= L <= L_max; 0 => L_max         */
   int32_t coarse_iters;  /* k >= 1 GMRES steps on M_L; -1 => exact coarse solve
                             (requires L = L_max: direct HPS)                   */
-  int32_t gamma;         /* coarse calls per level, 1 = V-cycle [1]            */
+  int32_t gamma;         /* coarse calls per level, 1..4 (0 => 1) [1]: 1 is the
+                            V-cycle; gamma > 1 the gamma-cycle of Sec. 4.3, the
+                            coarse correction of every level being gamma
+                            stationary steps y += MG_{l+1}(r - M_{l+1} y) from
+                            y = 0 (MG_{l+1} is called gamma^(l-1) times per
+                            application at level l)                           */
   int32_t restart;       /* FGMRES restart length, 1..200 [60]                 */
 } hps_desc;
 
-/* Per-problem result of hps_gmres_solve ([host]). */
+/* Per-problem result of hps_gmres_solve ([host]).  Times are device times
+   from HIP events on the context's stream; a group's problems share theirs. */
 typedef struct {
   int32_t status;        /* HPS_OK or HPS_NOT_CONVERGED                        */
   int32_t iterations;    /* flexible GMRES iterations, counted across restarts */
   double relres_est;     /* Givens estimate of ||RHS - M g|| / ||RHS||          */
   double relres_true;    /* recomputed ||RHS - M g||_2 / ||RHS||_2 at exit      */
+  double t_build_s;      /* leaf build through the latest merge level (s)      */
+  double t_solve_s;      /* this call's flexible GMRES (s)                      */
 } hps_info;
 
 /* View of one level's stored operators (for inspection and testing). */
@@ -125,7 +141,8 @@ hps_status hps_ctx_create(void* hip_stream, hps_ctx** out);
 hps_status hps_ctx_destroy(hps_ctx* ctx);
 /* Last error message of this context ("" if none); valid until the next call. */
 const char* hps_last_error(const hps_ctx* ctx);
-/* Wait for the context's stream and report deferred device errors. */
+/* Wait for the context's stream and report the failures recorded on the
+   device by any live problem of this context (see Errors above). */
 hps_status hps_sync(hps_ctx* ctx);
 /* Options.  HPS_OPT_GRAPHS (default 0): replay the multigrid V-cycle from a HIP
    graph captured once per problem (on a private capture stream) instead of
@@ -143,7 +160,9 @@ enum { HPS_OPT_GRAPHS = 1, HPS_OPT_TIMING = 2 };
 hps_status hps_set_option(hps_ctx* ctx, int32_t option, int32_t value);
 /* Timed kernels and their work unit:
    HPS_KERNEL_LEAF: the leaf kernel of hps_build_leaves, one launch per chunk of
-   up to 1024 elements; unit = one element (its ItI map T and load H). */
+   up to 4096 elements (of at most 32 problems of a group); unit = one element
+   (its ItI map T and load H).  The interval also covers the fallback launch
+   of the elements near a resonance (none in most builds). */
 enum { HPS_KERNEL_LEAF = 0 };
 /* [host outputs] Launches, summed device time (ms, from the events) and units
    processed by `kernel` since HPS_OPT_TIMING was last set.  Synchronises. */
@@ -153,6 +172,13 @@ hps_status hps_kernel_time(hps_ctx* ctx, int32_t kernel, int64_t* launches, doub
 /* ---- sizing and host-side geometry -------------------------------------- */
 /* Exact device workspace (bytes) of one problem; the admission footprint. */
 hps_status hps_workspace_bytes(const hps_desc* desc, size_t* bytes);
+/* Admission by footprint: the most levels L (the coarse system M_L, Sec. 4.3)
+   whose workspace for `count` problems of this shape fits in `budget` bytes,
+   written to *levels (desc->levels is ignored).  More levels mean fewer
+   outer iterations and more memory (Table 1: PMem grows and It falls with
+   #levels).  HPS_ERR_OOM if not even L = 1 fits (L = L_max only, for the
+   exact coarse solve); host only. */
+hps_status hps_choose_levels(const hps_desc* desc, int32_t count, size_t budget, int32_t* levels);
 /* [host] GLL nodes on [-1, 1] of order N: xi[N+1], increasing. */
 hps_status hps_gll_nodes(int32_t order, double* xi);
 /* [host] physical coordinates of all element nodes, x[E][(N+1)^2], y[...]. */
@@ -211,12 +237,13 @@ hps_status hps_merge_level(hps_problem* const* p, int32_t count, int32_t level);
 hps_status hps_set_rhs(hps_problem* const* p, int32_t count,
                        const double* const* t, double* const* rhs);
 /* out = M_level g (canonical vectors; only level-`level` unknowns are read and
-   written).  Requires the level-`level` box maps in FP64 (always true for
-   level 1 and the coarse level; HPS_ERR_ARG for FP32 levels of mixed mode). */
+   written; level 1 also writes 0 at physical slots).  On the FP32 levels of
+   mixed precision the FP32 box maps are applied in FP64 arithmetic. */
 hps_status hps_skeleton_apply(hps_problem* const* p, int32_t count, int32_t level,
                               const double* const* g, double* const* out);
-/* z = MG(M_1) r, one V-cycle (gamma = 1) with the configured coarse solve
-   (Sec. 4.3).  r and z: complex canonical vectors; r is not modified. */
+/* z = MG(M_1) r, one V-cycle (gamma = 1) or gamma-cycle with the configured
+   coarse solve (Sec. 4.3).  r and z: complex canonical vectors; r is not
+   modified. */
 hps_status hps_precond_apply(hps_problem* const* p, int32_t count,
                              const double* const* r, double* const* z);
 /* Flexible GMRES(restart) on M_1 g = rhs, right-preconditioned by MG, x0 = 0,

@@ -45,6 +45,9 @@ struct hps_ctx {
   void* hbuf = nullptr;
   size_t hbuf_bytes = 0;
   hipEvent_t hev[2] = {nullptr, nullptr};
+  // live problem handles of this context, whose device error words
+  // hps_sync reads
+  std::vector<hps_problem*> problems;
 };
 
 namespace hps {
@@ -55,6 +58,7 @@ inline size_t up256(size_t b) { return (b + 255) & ~size_t(255); }
 
 constexpr int kWorkVectors = 9;  // canonical group vectors in a workspace (see workv)
 constexpr int kMaxGroup = 4096;  // problems in one group
+constexpr int kMaxGamma = 4;     // coarse calls per level of a gamma-cycle
 
 struct Level {
   Geom g;
@@ -82,6 +86,8 @@ struct Level {
 struct Layout {
   int nq;
   int n, N, p, E, L, Lmax, k, restart;
+  int gamma;             // coarse calls per level (1: V-cycle)
+  size_t gam_off = 0;    // gamma > 1: per level l < L the vectors W, Y, R, D (see mg_gamma)
   bool exact, mixed;
   size_t stage_off = 0;  // FP32 output of the last FP32 merge, widened into FP64 maps
   long long nslots;
@@ -93,6 +99,7 @@ struct Layout {
   size_t V_off, Z_off, work_off;  // Krylov bases and 5 canonical work vectors
   size_t cV_off, cw_off, cx_off, cidx_off, cH_off, cy_off, cs_off;  // coarse GMRES
   size_t part_off, hh_off, one_off, flag_off;
+  size_t fb_off;                   // int [1 + leaf_chunk]: the leaf fallback's element list
   size_t ysol_off;                 // [nq][restart] FGMRES update coefficients
   size_t gpart_off, gpart_elems;  // split-K GEMV partial sums
   size_t total;
@@ -219,7 +226,7 @@ const char* check_desc(const hps_desc* d) {
     return "coarse_iters must be -1 (exact) or 1..32";
   const int L = d->levels ? d->levels : Lmax;
   if (d->coarse_iters == -1 && L != Lmax) return "exact coarse solve requires levels = L_max";
-  if (d->gamma != 1 && d->gamma != 0) return "only gamma = 1 (V-cycle) is supported";
+  if (d->gamma < 0 || d->gamma > kMaxGamma) return "gamma must be in [1, 4] (0 => 1)";
   if (d->restart < 0 || d->restart > 200) return "restart must be in [1, 200]";
   if (d->precision != HPS_FP64 && d->precision != HPS_MIXED) return "precision must be HPS_FP64 or HPS_MIXED";
   return nullptr;
@@ -241,6 +248,7 @@ Layout make_layout(const hps_desc* d, int nq) {
   lay.mixed = (d->precision == HPS_MIXED);
   lay.k = lay.exact ? 0 : d->coarse_iters;
   lay.restart = d->restart ? d->restart : 60;
+  lay.gamma = d->gamma > 1 ? d->gamma : 1;
   lay.nslots = (long long)lay.E * 4 * lay.p;
   lay.leaf_chunk = (int)std::min<long long>((long long)lay.E * nq, HPS_LEAF_CHUNK);
   const size_t Q = (size_t)nq;
@@ -282,6 +290,7 @@ Layout make_layout(const hps_desc* d, int nq) {
   lay.V_off = take(vb * (lay.restart + 1));
   lay.Z_off = take(vb * lay.restart);
   lay.work_off = take(up256(vb) * kWorkVectors);
+  if (lay.gamma > 1) lay.gam_off = take(up256(vb) * 4 * (size_t)lay.L);
   {
     Level& top = lay.lev[lay.L];
     int nL = 0;
@@ -331,7 +340,8 @@ Layout make_layout(const hps_desc* d, int nq) {
     lay.gpart_elems = 3 * mx + 128;
     lay.gpart_off = take(sizeof(cd) * lay.gpart_elems);
   }
-  lay.flag_off = take(sizeof(int) * 4);
+  lay.flag_off = take(sizeof(int) * kFlagWords);
+  lay.fb_off = take(sizeof(int) * (1 + (size_t)lay.leaf_chunk));
   lay.total = off;
   return lay;
 }
@@ -354,6 +364,9 @@ struct hps_problem {
   bool have_T1;
   hipGraphExec_t pgraph = nullptr;  // captured V-cycle (work vector 5 -> 6)
   bool graph_failed = false;
+  // build and solve times (hps_info): events on the context's stream at the
+  // start of the leaf build, after its latest build step, and around a solve
+  hipEvent_t ev_build0 = nullptr, ev_build1 = nullptr, ev_solve0 = nullptr, ev_solve1 = nullptr;
 };
 
 using namespace hps;
@@ -471,7 +484,7 @@ hps_status merge_impl(hps_problem* p, int l, const T* Tin, T* Tout) {
     }
     HIPCHK(c, zgemm_group(grp, ng, st));
   }
-  HIPCHK(c, zinverse<T>(A11, m, m2, as, np, invs, flag, st));
+  HIPCHK(c, zinverse<T>(A11, m, m2, as, np, invs, flag, l, st));
   ng = 0;
   {
     GemmArgs g = gemm(m, m, m);
@@ -830,10 +843,16 @@ hps_status coarse_solve(hps_problem* p, cd* wv, cd* z) {
   return HPS_OK;
 }
 
+hps_status mg_gamma(hps_problem* p, int l, const cd* r, cd* z);
+
 hps_status precond_one(hps_problem* p, const cd* r, cd* z) {
   hps_ctx* c = p->ctx;
   hipStream_t st = c->stream;
   const Layout& lay = p->lay;
+  if (lay.gamma > 1) {
+    HIPCHK(c, vfill(z, lay.nslots * lay.nq, cmk(0, 0), st));
+    return mg_gamma(p, 1, r, z);
+  }
   cd* wv = workv(p, 0);
   const long long ntot = lay.nslots * lay.nq;
   HIPCHK(c, vcopy_zero(r, wv, z, ntot, st));   // wv = r, z = 0
@@ -848,6 +867,58 @@ hps_status precond_one(hps_problem* p, const cd* r, cd* z) {
     if (s != HPS_OK) return s;
   }
   return HPS_OK;
+}
+
+// gamma-cycle (gamma > 1, Sec. 4.3 "multiple coarse calls"): at every level
+// the coarse correction is a stationary iteration of gamma steps on the
+// level's Schur complement M_{l+1},
+//   y = 0;  repeat gamma times:  y += MG_{l+1}(r~ - M_{l+1} y),
+// with r~ the level-(l+1) residual left by the down sweep; gamma = 1 is the
+// V-cycle.  Vectors are canonical (only the level's unknowns are meaningful);
+// level l uses its own W (the residual, reduced in place by the down sweep),
+// Y (the iterate), R (the stationary residual) and D (the correction), so
+// the recursion needs no allocation.  r is read at level-l slots; z receives
+// MG_l r at level-l slots (other slots untouched).
+cd* gamv(hps_problem* p, int l, int which) {
+  const size_t vb = up256(sizeof(cd) * (size_t)p->lay.nslots * p->lay.nq);
+  return reinterpret_cast<cd*>(p->ws + p->lay.gam_off + ((size_t)(l - 1) * 4 + which) * vb);
+}
+
+hps_status mg_gamma(hps_problem* p, int l, const cd* r, cd* z) {
+  hps_ctx* c = p->ctx;
+  hipStream_t st = c->stream;
+  const Layout& lay = p->lay;
+  const long long ntot = lay.nslots * lay.nq;
+  if (l == lay.L) {
+    HIPCHK(c, vcopy(r, workv(p, 0), ntot, st));
+    return coarse_solve(p, workv(p, 0), z);
+  }
+  cd* W = gamv(p, l, 0);
+  cd* Y = gamv(p, l, 1);
+  cd* R = gamv(p, l, 2);
+  cd* D = gamv(p, l, 3);
+  HIPCHK(c, vcopy_zero(r, W, Y, ntot, st));   // W = r, Y = 0
+  hps_status s = vcycle_down(p, l, W);        // z0 in Z0; W at level-(l+1) slots = r~
+  if (s != HPS_OK) return s;
+  const Level& nx = lay.lev[l + 1];
+  for (int it = 0; it < lay.gamma; ++it) {
+    const cd* src = W;
+    if (it > 0) {
+      // R = r~ - M_{l+1} Y (M_{l+1} in the precision its maps are stored in)
+      if (nx.f32)
+        HIPCHK(c, skeleton_apply(nx.g, at<cf>(p, nx.T_off), Y, R, false, st, lay.nq));
+      else
+        HIPCHK(c, skeleton_apply(nx.g, Tlev(p, l + 1), Y, R, false, st, lay.nq));
+      HIPCHK(c, axpby(cmk(1, 0), W, cmk(-1, 0), R, R, ntot, st));
+      src = R;
+    }
+    HIPCHK(c, vfill(D, ntot, cmk(0, 0), st));
+    s = mg_gamma(p, l + 1, src, D);
+    if (s != HPS_OK) return s;
+    HIPCHK(c, axpby(cmk(1, 0), Y, cmk(1, 0), D, Y, ntot, st));
+  }
+  HIPCHK(c, vcopy(Y, z, ntot, st));            // z = y at level-(l+1) slots
+  return vcycle_up(p, l, z);                    // x = z0 + X y at the level's shared faces
 }
 
 // The V-cycle is a fixed sequence of launches for a given problem, so it is
@@ -904,12 +975,44 @@ hps_status check_ready(hps_problem* p, bool need_merges) {
   return HPS_OK;
 }
 
-hps_status read_flag(hps_problem* p) {
-  int f = 0;
-  HIPCHK(p->ctx, hipMemcpyAsync(&f, at<int>(p, p->lay.flag_off), sizeof(int), hipMemcpyDeviceToHost,
-                                p->ctx->stream));
+// Reads the problem's device error words (synchronises) and turns a recorded
+// failure into a status and a message naming where it happened; `first` is
+// the caller's index of the handle's first problem.
+hps_status read_flag(hps_problem* p, int first = 0) {
+  int f[kFlagWords];
+  HIPCHK(p->ctx, hipMemcpyAsync(f, at<int>(p, p->lay.flag_off), sizeof(f), hipMemcpyDeviceToHost, p->ctx->stream));
   HIPCHK(p->ctx, hipStreamSynchronize(p->ctx->stream));
-  if (f & 2) return fail(p->ctx, HPS_ERR_SINGULAR, "zero pivot in a leaf or merge factorisation");
+  const Layout& lay = p->lay;
+  auto word = [&](int i) {
+    unsigned long long v;
+    std::memcpy(&v, f + i, sizeof(v));
+    return v;
+  };
+  if (f[0] & kFlagNonFinite) {
+    const long long G = (long long)word(4);
+    const long long q = G / lay.E, e = G % lay.E;
+    return fail(p->ctx, HPS_ERR_ARG,
+                "non-finite value in b_nodes or s_nodes of problem " + std::to_string(first + q) + ", element " +
+                    std::to_string(e) + " (ix " + std::to_string(e % lay.n) + ", iy " + std::to_string(e / lay.n) +
+                    "); its leaf map was not built");
+  }
+  if (f[0] & kFlagSingular) {
+    const unsigned long long w = word(2);
+    const int level = (int)(w >> 40);
+    const long long idx = (long long)(w & ((1ull << 40) - 1));
+    std::string where;
+    if (level == 0) {
+      const long long q = idx / lay.E, e = idx % lay.E;
+      where = "the leaf map of problem " + std::to_string(first + q) + ", element " + std::to_string(e);
+    } else {
+      const int pairs = (level <= lay.L && lay.lev[level].has_merge) ? lay.lev[level].pairs : 1;
+      const long long q = idx / pairs, j = idx % pairs;
+      where = "merge level " + std::to_string(level) + " of problem " + std::to_string(first + q) + ", pair " +
+              std::to_string(j) + " (boxes " + std::to_string(2 * j) + " and " + std::to_string(2 * j + 1) +
+              " in merge-tree order)";
+    }
+    return fail(p->ctx, HPS_ERR_SINGULAR, "zero pivot in " + where);
+  }
   return HPS_OK;
 }
 
@@ -963,7 +1066,7 @@ hps_status fgmres_group(hps_problem* p, const cd* rhs, cd* g, double tol, int ma
     HIPCHK(c, hipStreamSynchronize(st));
     return HPS_OK;
   };
-  for (int q = 0; q < nq; ++q) info[q] = hps_info{HPS_OK, 0, 0.0, 0.0};
+  for (int q = 0; q < nq; ++q) info[q] = hps_info{HPS_OK, 0, 0.0, 0.0, 0.0, 0.0};
   // ||rhs|| per problem
   HIPCHK(c, multi_dot(rhs, 0, 1, rhs, n, part, nrm2, false, st, nq, HS));
   hps_status s = fetch();
@@ -1125,6 +1228,13 @@ hps_status group_create(hps_ctx* ctx, const hps_desc* desc, int count, const dou
   p->state = kCreated;
   p->merged = 0;
   p->have_T1 = false;
+  for (hipEvent_t* ev : {&p->ev_build0, &p->ev_build1, &p->ev_solve0, &p->ev_solve1}) {
+    const hipError_t e = hipEventCreate(ev);
+    if (e != hipSuccess) {
+      hps_problem_destroy(p);
+      return fail(ctx, HPS_ERR_HIP, std::string("HIP error: ") + hipGetErrorString(e) + " at hipEventCreate");
+    }
+  }
   // small tables: GLL data, merge maps, slot tables (with each problem's offset
   // into the group vectors), coarse index list, constants
   GllTables t = gll_tables(desc->order);
@@ -1162,8 +1272,9 @@ hps_status group_create(hps_ctx* ctx, const hps_desc* desc, int count, const dou
   if (!lay.exact && lay.nL > 0) HIPCHK(ctx, upload(lay.cidx_off, replicate(coarse_slots(lay.lev[lay.L]))));
   const cd one = cmk(1, 0);
   HIPCHK(ctx, hipMemcpyAsync(p->ws + lay.one_off, &one, sizeof(cd), hipMemcpyHostToDevice, ctx->stream));
-  const int zero4[4] = {0, 0, 0, 0};
-  HIPCHK(ctx, hipMemcpyAsync(p->ws + lay.flag_off, zero4, sizeof(zero4), hipMemcpyHostToDevice, ctx->stream));
+  // error words: no flags, no first failure (records keep a minimum)
+  const int words[kFlagWords] = {0, 0, -1, -1, -1, -1, 0, 0};
+  HIPCHK(ctx, hipMemcpyAsync(p->ws + lay.flag_off, words, sizeof(words), hipMemcpyHostToDevice, ctx->stream));
   // Box maps of merged levels: entries on physical sides are never computed;
   // they are kept at zero so that products with zero data stay zero.
   for (int l = 2; l <= lay.L; ++l) {
@@ -1180,6 +1291,7 @@ hps_status group_create(hps_ctx* ctx, const hps_desc* desc, int count, const dou
     HIPCHK(ctx, vfill(at<cd>(p, lv.X_off), lv.f32 ? (nx + 1) / 2 : nx, cmk(0, 0), ctx->stream));
   }
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  ctx->problems.push_back(p);
   *out = p;
   return HPS_OK;
 }
@@ -1226,6 +1338,7 @@ void drop_timed(hps_ctx* ctx) {
 
 hps_status hps_ctx_destroy(hps_ctx* ctx) {
   if (ctx) {
+    for (hps_problem* p : ctx->problems) p->ctx = nullptr;
     (void)hipStreamSynchronize(ctx->stream);
     drop_timed(ctx);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
@@ -1275,6 +1388,10 @@ const char* hps_last_error(const hps_ctx* ctx) { return ctx ? ctx->err.c_str() :
 hps_status hps_sync(hps_ctx* ctx) {
   if (!ctx) return HPS_ERR_ARG;
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  for (hps_problem* p : ctx->problems) {
+    const hps_status s = read_flag(p);
+    if (s != HPS_OK) return s;
+  }
   return HPS_OK;
 }
 
@@ -1282,6 +1399,22 @@ hps_status hps_workspace_bytes(const hps_desc* desc, size_t* bytes) {
   if (!bytes || check_desc(desc)) return HPS_ERR_ARG;
   *bytes = make_layout(desc, 1).total;
   return HPS_OK;
+}
+
+hps_status hps_choose_levels(const hps_desc* desc, int32_t count, size_t budget, int32_t* levels) {
+  if (!levels || check_desc(desc) || count < 1 || count > kMaxGroup) return HPS_ERR_ARG;
+  hps_desc d = *desc;
+  const int Lmax = 2 * ilog2(d.n);
+  // the exact coarse solve exists only at the top level
+  const int lo = d.coarse_iters == -1 ? Lmax : 1;
+  for (int L = Lmax; L >= lo; --L) {
+    d.levels = L;
+    if (make_layout(&d, count).total <= budget) {
+      *levels = L;
+      return HPS_OK;
+    }
+  }
+  return HPS_ERR_OOM;
 }
 
 hps_status hps_group_workspace_bytes(const hps_desc* desc, int32_t count, size_t* bytes) {
@@ -1355,7 +1488,14 @@ hps_status hps_group_create(hps_ctx* ctx, const hps_desc* desc, int32_t count, c
 int32_t hps_group_size(const hps_problem* p) { return p ? p->lay.nq : 0; }
 
 hps_status hps_problem_destroy(hps_problem* p) {
-  if (p && p->pgraph) (void)hipGraphExecDestroy(p->pgraph);
+  if (!p) return HPS_OK;
+  if (p->pgraph) (void)hipGraphExecDestroy(p->pgraph);
+  for (hipEvent_t ev : {p->ev_build0, p->ev_build1, p->ev_solve0, p->ev_solve1})
+    if (ev) (void)hipEventDestroy(ev);
+  if (p->ctx) {
+    std::vector<hps_problem*>& v = p->ctx->problems;
+    v.erase(std::remove(v.begin(), v.end(), p), v.end());
+  }
   delete p;
   return HPS_OK;
 }
@@ -1411,6 +1551,9 @@ hps_status hps_build_leaves(hps_problem* const* pp, int32_t count, const double*
     a.T = Tlev(p, 1);
     a.H = at<cd>(p, lay.H_off);
     a.flag = at<int>(p, lay.flag_off);
+    a.fb_list = at<int>(p, lay.fb_off);
+    HIPCHK(p->ctx, hipEventRecord(p->ev_build0, p->ctx->stream));
+    HIPCHK(p->ctx, flag_reset(a.flag, p->ctx->stream));   // a new build: earlier failures are gone
     const long long Gtot = (long long)lay.E * lay.nq;
     for (long long G0 = 0; G0 < Gtot;) {
       // one launch: at most leaf_chunk elements of at most kLeafMaxQ problems
@@ -1450,6 +1593,7 @@ hps_status hps_build_leaves(hps_problem* const* pp, int32_t count, const double*
       HIPCHK(p->ctx, convert_c64_c32(Tlev(p, 1), at<cf>(p, l1.T32_off),
                                      (long long)lay.nq * l1.g.nboxes * l1.g.b * l1.g.b, p->ctx->stream));
     }
+    HIPCHK(p->ctx, hipEventRecord(p->ev_build1, p->ctx->stream));
     p->state = kLeaves;
     p->merged = 0;
     base += lay.nq;
@@ -1468,6 +1612,7 @@ hps_status hps_merge_level(hps_problem* const* pp, int32_t count, int32_t level)
     if (level != p->merged + 1) return fail(p->ctx, HPS_ERR_STATE, "merge levels must run in order");
     hps_status s = merge_one(p, level);
     if (s != HPS_OK) return s;
+    HIPCHK(p->ctx, hipEventRecord(p->ev_build1, p->ctx->stream));
     p->merged = level;
   }
   return HPS_OK;
@@ -1496,13 +1641,16 @@ hps_status hps_skeleton_apply(hps_problem* const* pp, int32_t count, int32_t lev
     if (s != HPS_OK) return s;
     if (level < 1 || level > p->lay.L) return fail(p->ctx, HPS_ERR_ARG, "level out of range");
     if (level > p->merged + 1) return fail(p->ctx, HPS_ERR_STATE, "level maps not built yet");
-    if (level > 1 && p->lay.lev[level].f32)
-      return fail(p->ctx, HPS_ERR_ARG, "this level's maps are stored in FP32 (mixed precision)");
     if (!g[k] || !out[k]) return fail(p->ctx, HPS_ERR_ARG, "null vector");
-    const Geom& gl = p->lay.lev[level].g;
-    HIPCHK(p->ctx, skeleton_apply(gl, Tlev(p, level) + (size_t)q * gl.nboxes * gl.b * gl.b,
-                                  reinterpret_cast<const cd*>(g[k]), reinterpret_cast<cd*>(out[k]), level == 1,
-                                  p->ctx->stream));
+    const Level& lv = p->lay.lev[level];
+    const Geom& gl = lv.g;
+    const size_t moff = (size_t)q * gl.nboxes * gl.b * gl.b;
+    if (level > 1 && lv.f32)
+      HIPCHK(p->ctx, skeleton_apply(gl, at<cf>(p, lv.T_off) + moff, reinterpret_cast<const cd*>(g[k]),
+                                    reinterpret_cast<cd*>(out[k]), false, p->ctx->stream));
+    else
+      HIPCHK(p->ctx, skeleton_apply(gl, Tlev(p, level) + moff, reinterpret_cast<const cd*>(g[k]),
+                                    reinterpret_cast<cd*>(out[k]), level == 1, p->ctx->stream));
     return HPS_OK;
   });
 }
@@ -1548,6 +1696,11 @@ hps_status hps_gmres_solve(hps_problem* const* pp, int32_t count, const double* 
     const int nq = p->lay.nq;
     for (int q = 0; q < nq; ++q)
       if (!rhs[base + q] || !g[base + q]) return fail(p->ctx, HPS_ERR_ARG, "null vector");
+    // a failure recorded by the build (zero pivot, non-finite input) ends the
+    // call before any iteration
+    s = read_flag(p, base);
+    if (s != HPS_OK) return s;
+    HIPCHK(p->ctx, hipEventRecord(p->ev_solve0, p->ctx->stream));
     if (nq == 1) {
       s = fgmres_group(p, reinterpret_cast<const cd*>(rhs[base]), reinterpret_cast<cd*>(g[base]), tol, maxit,
                        &info[base]);
@@ -1561,10 +1714,17 @@ hps_status hps_gmres_solve(hps_problem* const* pp, int32_t count, const double* 
         HIPCHK(p->ctx, vcopy(gg + q * n, reinterpret_cast<cd*>(g[base + q]), n, p->ctx->stream));
     }
     if (s != HPS_OK) return s;
-    s = read_flag(p);
+    HIPCHK(p->ctx, hipEventRecord(p->ev_solve1, p->ctx->stream));
+    s = read_flag(p, base);
     if (s != HPS_OK) return s;
-    for (int q = 0; q < nq; ++q)
+    float tb = 0.0f, ts = 0.0f;
+    HIPCHK(p->ctx, hipEventElapsedTime(&tb, p->ev_build0, p->ev_build1));
+    HIPCHK(p->ctx, hipEventElapsedTime(&ts, p->ev_solve0, p->ev_solve1));
+    for (int q = 0; q < nq; ++q) {
+      info[base + q].t_build_s = 1e-3 * tb;
+      info[base + q].t_solve_s = 1e-3 * ts;
       if (info[base + q].status == HPS_NOT_CONVERGED) worst = HPS_NOT_CONVERGED;
+    }
     base += nq;
   }
   return worst;

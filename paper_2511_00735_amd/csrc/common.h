@@ -177,3 +177,25 @@ inline hipError_t allow_lds(K kernel, size_t bytes) {
   return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
+
+// Device error words of a problem (kFlagWords ints in its workspace):
+//   word 0: bits kFlagSingular (exact zero pivot), kFlagNonFinite (NaN or Inf
+//           in b_nodes or s_nodes);
+//   words 2-3: the first zero pivot as (level << 40) | batch index, kept as the
+//           minimum (level 0: the leaf build, index = element of the group;
+//           level l >= 1: merge l, index = pair of the group's level batch);
+//   words 4-5: the first element (index in the group) with a non-finite input.
+constexpr int kFlagWords = 8;
+constexpr int kFlagSingular = 2;
+constexpr int kFlagNonFinite = 4;
+__host__ __device__ inline unsigned long long flag_where(int level, long long index) {
+  return ((unsigned long long)level << 40) | (unsigned long long)index;
+}
+__device__ inline void flag_singular(int* flag, unsigned long long where) {
+  atomicOr(flag, kFlagSingular);
+  atomicMin(reinterpret_cast<unsigned long long*>(flag + 2), where);
+}
+__device__ inline void flag_nonfinite(int* flag, unsigned long long element) {
+  atomicOr(flag, kFlagNonFinite);
+  atomicMin(reinterpret_cast<unsigned long long*>(flag + 4), element);
+}

@@ -33,9 +33,17 @@ struct LeafArgs {
   double* scratch;            // leaf_scratch_doubles(N, count) doubles, 16-byte aligned
   cd* T;                      // level-1 box maps, [q][E][4p][4p], Morton order within a problem
   cd* H;                      // [q][E][4p] canonical element order
-  int* flag;                  // device error flag (bit 1: singular pivot)
+  int* flag;                  // the problem's error words (common.h)
+  int* fb_list;               // [1 + count]: count, then elements G whose interior
+                              // block is nearly singular (recomputed by the fallback)
 };
+// Leaf maps of elements G0 .. G0+count-1: the leaf kernel, then the complex
+// fallback for the elements it lists.
 hipError_t leaf_build(const LeafArgs& a, hipStream_t st);
+// Clears a problem's device error words (no failure recorded).
+hipError_t flag_reset(int* flag, hipStream_t st);
+// Scratch doubles of one launch of `count` elements (the leaf kernel's
+// bordered matrices, or the fallback's complex element systems).
 size_t leaf_scratch_doubles(int N, int count);
 
 // ---- batched complex GEMM and copies (gemm.hip) ---------------------------
@@ -104,10 +112,12 @@ __host__ __device__ inline bool y_physical(const PhysSkip& s, int bx, int by, in
 // ---- batched complex inversion (inverse.hip) -------------------------------
 // In-place inverse of `batch` m x m column-major matrices (stride `bstride`),
 // Gauss-Jordan with partial pivoting.  scratch: see inverse_scratch_bytes.
+// A zero pivot of matrix b is recorded in the problem's error words as
+// flag_where(level, b).
 template <class T>
 size_t inverse_scratch_bytes(int m, int batch);
 template <class T>
 hipError_t zinverse(T* A, int m, int lda, long long bstride, int batch, void* scratch,
-                    int* flag, hipStream_t st);
+                    int* flag, int level, hipStream_t st);
 
 }  // namespace hps

@@ -58,7 +58,7 @@ __device__ inline T crecip(T a) {
 template <class T>
 __global__ __launch_bounds__(kPanelThreads) void gj_panel_kernel(const T* A, int m, int lda, long long bstride,
                                                                  int k0, int kb, const int* rho_prev, int* rho,
-                                                                 int* rowmap, T* dinv, int* flag) {
+                                                                 int* rowmap, T* dinv, int* flag, int level) {
   extern __shared__ char smem[];
   const int rows = m - k0;
   T* Pn = reinterpret_cast<T*>(smem);          // rows x kb, column-major (ld rows)
@@ -106,7 +106,7 @@ __global__ __launch_bounds__(kPanelThreads) void gj_panel_kernel(const T* A, int
     int pr = pivot_row(kk);
     const bool bad = (kk >> 32) <= 1u || pr < c || pr >= rows;
     if (bad) pr = c;
-    if (tid == 0 && bad) atomicOr(flag, 2);
+    if (tid == 0 && bad) flag_singular(flag, flag_where(level, blockIdx.x));
     if (pr != c) {
       if (tid < kb) {
         const T t = Pn[tid * rows + c];
@@ -199,7 +199,7 @@ __device__ inline cf readlane_c(cf v, int l) {
 // With pivot row pr_k at step k the registers end as S[pr_k][j] = A^-1[k][pr_j],
 // written back to A^-1's own positions.
 template <class T, int NW, int RC>
-__global__ __launch_bounds__(64 * NW) void inv_small_kernel(T* A, int m, int lda, long long bstride, int* flag) {
+__global__ __launch_bounds__(64 * NW) void inv_small_kernel(T* A, int m, int lda, long long bstride, int* flag, int level) {
   constexpr int kT = 64 * RC / NW;  // columns per thread
   __shared__ T colbuf[2][64 * RC];
   __shared__ T pinv[2];
@@ -262,7 +262,7 @@ __global__ __launch_bounds__(64 * NW) void inv_small_kernel(T* A, int m, int lda
     }
     if (tid == 0) {
       pivs[k] = pr;
-      if ((kk >> 32) <= 1u) atomicOr(flag, 2);
+      if ((kk >> 32) <= 1u) flag_singular(flag, flag_where(level, blockIdx.x));
     }
     T f[RC];
 #pragma unroll
@@ -341,7 +341,7 @@ __device__ inline void panel_publish(const T (&x)[CH][CPW], unsigned used, int r
 template <class T, int CH, int CPW>
 __global__ __launch_bounds__(1024) void gj_panel_reg_kernel(const T* A, int m, int lda, long long bstride, int k0,
                                                              int kb, const int* rho_prev, int* rho, int* rowmap,
-                                                             T* dinv, int* flag) {
+                                                             T* dinv, int* flag, int level) {
   constexpr int NW = 16;
   __shared__ T colbuf[2][64 * CH];
   __shared__ unsigned long long kw_s[2];
@@ -373,7 +373,7 @@ __global__ __launch_bounds__(1024) void gj_panel_reg_kernel(const T* A, int m, i
     if (lane == lp) used |= 1u << tp;
     if (tid == 0) {
       piv_s[c] = pr;
-      if ((kk >> 32) <= 1u) atomicOr(flag, 2);
+      if ((kk >> 32) <= 1u) flag_singular(flag, flag_where(level, blockIdx.x));
     }
     // pivot row entries of this wave's live columns, scaled by 1/pivot once
     // (the column entries then multiply them directly); waves with no live
@@ -637,7 +637,7 @@ inline BlockScratch<T> carve(void* base, int m, int batch) {
 
 template <class T>
 hipError_t inverse_blocked(T* A, int m, int lda, long long bstride, int batch, void* scratch,
-                           int* flag, hipStream_t st) {
+                           int* flag, int level, hipStream_t st) {
   BlockScratch<T> s = carve<T>(scratch, m, batch);
   hipError_t err;
   const int nbw = panel_width<T>(m);
@@ -666,13 +666,13 @@ hipError_t inverse_blocked(T* A, int m, int lda, long long bstride, int batch, v
     int* rho = s.rho[s_ & 1];
     if (reg == 1)
       hipLaunchKernelGGL((gj_panel_reg_kernel<T, 8, 2>), dim3(batch), dim3(1024), 0, st, cur, m, ldc, cs, k0, kb,
-                         rho_prev, rho, s.rowmap, s.dinv, flag);
+                         rho_prev, rho, s.rowmap, s.dinv, flag, level);
     else if (reg == 2)
       hipLaunchKernelGGL((gj_panel_reg_kernel<T, 16, 1>), dim3(batch), dim3(1024), 0, st, cur, m, ldc, cs, k0,
-                         kb, rho_prev, rho, s.rowmap, s.dinv, flag);
+                         kb, rho_prev, rho, s.rowmap, s.dinv, flag, level);
     else
       hipLaunchKernelGGL(gj_panel_kernel<T>, dim3(batch), dim3(kPanelThreads), panel_lds_bytes<T>(m - k0, kb), st,
-                         cur, m, ldc, cs, k0, kb, rho_prev, rho, s.rowmap, s.dinv, flag);
+                         cur, m, ldc, cs, k0, kb, rho_prev, rho, s.rowmap, s.dinv, flag, level);
     if ((err = hipPeekAtLastError()) != hipSuccess) return err;
     // the last step writes straight into A, columns permuted, when it can
     const bool last_into_A = (s_ == steps - 1) && nxt == A;
@@ -707,22 +707,22 @@ size_t inverse_scratch_bytes(int m, int batch) {
 
 template <class T>
 hipError_t zinverse(T* A, int m, int lda, long long bstride, int batch, void* scratch, int* flag,
-                    hipStream_t st) {
+                    int level, hipStream_t st) {
   if (m <= 0 || batch <= 0) return hipSuccess;
   if (m <= 64) {
-    hipLaunchKernelGGL((inv_small_kernel<T, 4, 1>), dim3(batch), dim3(256), 0, st, A, m, lda, bstride, flag);
+    hipLaunchKernelGGL((inv_small_kernel<T, 4, 1>), dim3(batch), dim3(256), 0, st, A, m, lda, bstride, flag, level);
     return hipPeekAtLastError();
   }
   if (m <= 128) {
-    hipLaunchKernelGGL((inv_small_kernel<T, 16, 2>), dim3(batch), dim3(1024), 0, st, A, m, lda, bstride, flag);
+    hipLaunchKernelGGL((inv_small_kernel<T, 16, 2>), dim3(batch), dim3(1024), 0, st, A, m, lda, bstride, flag, level);
     return hipPeekAtLastError();
   }
-  return inverse_blocked<T>(A, m, lda, bstride, batch, scratch, flag, st);
+  return inverse_blocked<T>(A, m, lda, bstride, batch, scratch, flag, level, st);
 }
 
 template size_t inverse_scratch_bytes<cd>(int, int);
 template size_t inverse_scratch_bytes<cf>(int, int);
-template hipError_t zinverse<cd>(cd*, int, int, long long, int, void*, int*, hipStream_t);
-template hipError_t zinverse<cf>(cf*, int, int, long long, int, void*, int*, hipStream_t);
+template hipError_t zinverse<cd>(cd*, int, int, long long, int, void*, int*, int, hipStream_t);
+template hipError_t zinverse<cf>(cf*, int, int, long long, int, void*, int*, int, hipStream_t);
 
 }  // namespace hps

@@ -60,6 +60,14 @@ constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 constexpr int kCPW = kNB / kWaves;  // panel columns per wave
 constexpr int kMaxChunks = 5;    // 64-row chunks of a panel: n_loc <= 320 (N <= 16)
+// An element whose interior elimination meets a pivot below 0.02 times its
+// largest (in modulus) lies within about 1e-6 (relative, in kappa^2) of an
+// interior Dirichlet eigenvalue; rounding in the large term of its Schur
+// complement would then reach 1e-11 of T, so it is recomputed by the complex
+// elimination of the whole element system (no resonance: the impedance
+// problem is well posed).  Away from resonances the ratio stays near 0.05-0.3.
+constexpr float kNearSingular2 = 0.02f * 0.02f;
+constexpr int kFbBlocks = 32;    // workgroups of the fallback launch
 
 struct Dims {
   int N, p, pp, nloc, ncol, ldu;
@@ -302,7 +310,7 @@ __device__ void leaf_cayley(const LeafArgs& a, const Dims& d, const double* A, d
     if (isp) { used = true; myk = k; }
     if (tid == 0) {
       pivs[k] = pr;
-      if (zero) atomicOr(a.flag, 2);
+      if (zero) flag_singular(a.flag, flag_where(0, G));
     }
     const cd f = isp ? cmk(0.0, 0.0) : cmul(colbuf[b * 64 + lane], inv);
     const int tk = k >> 2, ok = k & 3;
@@ -399,6 +407,23 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_kernel(LeafArgs a) {
   const double* sq = a.s_nodes[q - a.q0];
   const ElemK K{d.N, d.p, d.pp, nloc, a.D, a.w, a.Kr, a.b_nodes[q - a.q0] + (size_t)e * N1 * N1,
                 sq ? sq + (size_t)e * 2 * N1 * N1 : nullptr, a.kappa[q - a.q0], a.h};
+  // a NaN or Inf among the element's inputs: recorded, and the element is
+  // skipped by the whole workgroup (the call then reports HPS_ERR_ARG)
+  {
+    bool bad = false;
+    for (int i = tid; i < N1 * N1; i += kThreads) {
+      bad |= !isfinite(K.bnode[i]);
+      if (K.snode) bad |= !isfinite(K.snode[2 * i]) || !isfinite(K.snode[2 * i + 1]);
+    }
+    if (__syncthreads_or(bad)) {
+      if (tid == 0) flag_nonfinite(a.flag, G);
+      return;
+    }
+  }
+  // smallest and largest squared pivot modulus of the interior elimination
+  // (thread 0): their ratio tells an element close to an interior Dirichlet
+  // resonance, whose Schur complement loses accuracy
+  float p2min = 3.0e38f, p2max = 0.0f;
 
   for (int k0 = 0; k0 < npiv; k0 += kNB) {
     const int kb = min(kNB, npiv - k0);
@@ -455,7 +480,9 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_kernel(LeafArgs a) {
       if (tid == 0) {
         piv_s[c] = pr;
         dinv_s[c] = inv;
-        if (zero) atomicOr(a.flag, 2);
+        const float p2 = zero ? 0.0f : __uint_as_float((unsigned)(kk >> 32) - 1u);
+        p2min = fminf(p2min, p2);
+        p2max = fmaxf(p2max, p2);
       }
       // the pivot row of this wave's open columns, by lane broadcast (zero for
       // finished columns: their values stay exactly as they are)
@@ -700,14 +727,140 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_kernel(LeafArgs a) {
       __syncthreads();
     }
   }
+  if (tid == 0 && !(p2min >= kNearSingular2 * p2max)) a.fb_list[1 + atomicAdd(a.fb_list, 1)] = G;
   // the factorisation's LDS is free again: the Cayley step reuses it
   leaf_cayley(a, d, A, lds);
 }
 
+// ---- fallback: the element system of Sec. 3.1 solved as it stands ----------
+// For the elements the leaf kernel lists (interior block nearly singular), the
+// complex n_loc x n_loc element matrix L (interior rows of the local operator,
+// boundary rows I_i = N_G + i eta E_G) is factored by LU with partial pivoting
+// over all rows, with the right-hand sides [E_G^T | bt] carried along; back
+// substitution gives X = L^-1 [E_G^T | bt], and T = I_o X_G-columns,
+// H = I_o x_bt with I_o = -(N_G - i eta E_G).  One workgroup per listed
+// element (grid-stride over the list), the system column-major in scratch.
+// Slow (one barrier-separated rank-1 update per pivot) and meant to be rare.
+__host__ __device__ inline size_t fb_stride(const Dims& d) {
+  return ((size_t)2 * d.nloc * (d.nloc + 4 * d.p + 1) + 31) & ~(size_t)31;
+}
+
+__global__ void fb_reset_kernel(int* list) { list[0] = 0; }
+
+__global__ void flag_reset_kernel(int* flag) {
+  const int i = threadIdx.x;
+  if (i < kFlagWords) flag[i] = (i >= 2 && i < 6) ? -1 : 0;
+}
+
+__global__ __launch_bounds__(kThreads) void leaf_fallback_kernel(LeafArgs a) {
+  __shared__ unsigned long long kw[kWaves];
+  const Dims d = dims_of(a.N);
+  const int nloc = d.nloc, npiv = d.pp, m = 4 * d.p, nrhs = m + 1, ncols = nloc + nrhs;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int N1 = a.N + 1;
+  // uniform values (scalar registers): the per-problem kernel arguments are
+  // then indexed in place
+  const int listed = __builtin_amdgcn_readfirstlane(a.fb_list[0]);
+  cd* S = reinterpret_cast<cd*>(a.scratch + (size_t)blockIdx.x * fb_stride(d));
+#define AT(r, c) S[(size_t)(c) * nloc + (r)]
+  for (int it = blockIdx.x; it < listed; it += gridDim.x) {
+    const int G = __builtin_amdgcn_readfirstlane(a.fb_list[1 + it]);
+    const int q = G / a.E, e = G % a.E;
+    const double eta = a.eta[q - a.q0];
+    const double* sq = a.s_nodes[q - a.q0];
+    const ElemK K{d.N, d.p, d.pp, nloc, a.D, a.w, a.Kr, a.b_nodes[q - a.q0] + (size_t)e * N1 * N1,
+                  sq ? sq + (size_t)e * 2 * N1 * N1 : nullptr, a.kappa[q - a.q0], a.h};
+    // [L | E_G^T | bt]: zeros, the identity columns, then K's nonzeros one by
+    // one (each entry once; the load's real and imaginary parts separately),
+    // then i eta on the diagonal of the boundary rows
+    for (int idx = tid; idx < nloc * ncols; idx += kThreads) {
+      const int r = idx % nloc, c = idx / nloc;
+      AT(r, c) = cmk((c >= nloc && c < nloc + m && r == npiv + (c - nloc)) ? 1.0 : 0.0, 0.0);
+    }
+    __syncthreads();
+    for (int it = tid; it < K.items(); it += kThreads) {
+      int r = 0, c = 0;
+      double v = 0.0;
+      if (!K.item(it, r, c, v)) continue;
+      if (c < nloc) AT(r, c).x = v;
+      else if (c == nloc) AT(r, nloc + m).x = v;
+      else AT(r, nloc + m).y = v;
+    }
+    __syncthreads();
+    for (int r = npiv + tid; r < nloc; r += kThreads) AT(r, r).y = eta;
+    __syncthreads();
+    for (int k = 0; k < nloc; ++k) {
+      unsigned long long key = 0;
+      for (int r = k + tid; r < nloc; r += kThreads) key = max(key, pivot_key(cabs2(AT(r, k)), r));
+      key = wave_max_key(key);
+      if (lane == 0) kw[wave] = key;
+      __syncthreads();
+      unsigned long long kk = kw[0];
+      for (int w = 1; w < kWaves; ++w) kk = max(kk, kw[w]);
+      const int pr = min(max(pivot_row(kk), k), nloc - 1);
+      if (tid == 0 && (kk >> 32) <= 1u) flag_singular(a.flag, flag_where(0, G));
+      if (pr != k)
+        for (int c = k + tid; c < ncols; c += kThreads) {
+          const cd t = AT(k, c);
+          AT(k, c) = AT(pr, c);
+          AT(pr, c) = t;
+        }
+      __syncthreads();
+      const cd inv = cinv(AT(k, k));
+      for (int r = k + 1 + tid; r < nloc; r += kThreads) AT(r, k) = cmul(AT(r, k), inv);
+      __syncthreads();
+      const int nr = nloc - k - 1, nc = ncols - k - 1;
+      for (int idx = tid; idx < nr * nc; idx += kThreads) {
+        const int r = k + 1 + idx % nr, c = k + 1 + idx / nr;
+        AT(r, c) = csub(AT(r, c), cmul(AT(r, k), AT(k, c)));
+      }
+      __syncthreads();
+    }
+    for (int k = nloc - 1; k >= 0; --k) {
+      const cd inv = cinv(AT(k, k));
+      for (int j = tid; j < nrhs; j += kThreads) AT(k, nloc + j) = cmul(AT(k, nloc + j), inv);
+      __syncthreads();
+      for (int idx = tid; idx < k * nrhs; idx += kThreads) {
+        const int i = idx % k, j = idx / k;
+        AT(i, nloc + j) = csub(AT(i, nloc + j), cmul(AT(i, k), AT(k, nloc + j)));
+      }
+      __syncthreads();
+    }
+    // T = I_o X on the boundary columns, H = I_o x on the load column; row i
+    // of N_G has p + 2 entries (K's items of boundary row i)
+    const int ix = e % a.n, iy = e / a.n;
+    cd* Tout = a.T + ((size_t)q * a.E + morton_xy(ix, iy)) * m * m;
+    const int nb0 = npiv * (2 * d.p + 5);   // first item of the boundary rows
+    for (int idx = tid; idx < m * nrhs; idx += kThreads) {
+      const int i = idx % m, j = idx / m;
+      cd acc = cmk(0.0, 0.0);
+      for (int t = 0; t < d.p + 2; ++t) {
+        int r = 0, c = 0;
+        double v = 0.0;
+        K.item(nb0 + t * m + i, r, c, v);
+        acc = cadd(acc, cscale(AT(c, nloc + j), v));
+      }
+      const cd xg = AT(npiv + i, nloc + j);
+      const cd tv = cmk(-acc.x - eta * xg.y, -acc.y + eta * xg.x);
+      if (j < m) Tout[(size_t)j * m + i] = tv;
+      else a.H[(size_t)G * m + i] = tv;
+    }
+    __syncthreads();
+  }
+}
+#undef AT
+
 }  // namespace
 
 size_t leaf_scratch_doubles(int N, int count) {
-  return (size_t)count * elem_stride(dims_of(N));
+  const Dims d = dims_of(N);
+  const int fb = count < kFbBlocks ? count : kFbBlocks;
+  return std::max((size_t)count * elem_stride(d), (size_t)fb * fb_stride(d));
+}
+
+hipError_t flag_reset(int* flag, hipStream_t st) {
+  hipLaunchKernelGGL(flag_reset_kernel, dim3(1), dim3(64), 0, st, flag);
+  return hipPeekAtLastError();
 }
 
 hipError_t leaf_build(const LeafArgs& a, hipStream_t st) {
@@ -716,7 +869,9 @@ hipError_t leaf_build(const LeafArgs& a, hipStream_t st) {
   const size_t lds = leaf_lds_bytes(a.N);
   hipError_t e0 = allow_lds(leaf_kernel, lds);
   if (e0 != hipSuccess) return e0;
+  hipLaunchKernelGGL(fb_reset_kernel, dim3(1), dim3(1), 0, st, a.fb_list);
   hipLaunchKernelGGL(leaf_kernel, dim3(a.count), dim3(kThreads), lds, st, a);
+  hipLaunchKernelGGL(leaf_fallback_kernel, dim3(std::min(a.count, kFbBlocks)), dim3(kThreads), 0, st, a);
   return hipPeekAtLastError();
 }
 

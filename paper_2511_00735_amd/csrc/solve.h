@@ -11,6 +11,9 @@ constexpr int kMaxDotBlocks = 512; // partial sums per vector in the two-stage d
 // their canonical vectors in gin / out.
 hipError_t skeleton_apply(const Geom& g, const cd* T, const cd* gin, cd* out, bool zero_physical,
                           hipStream_t st, int nq = 1);
+// The same with complex FP32 box maps (FP64 vectors and arithmetic).
+hipError_t skeleton_apply(const Geom& g, const cf* T, const cd* gin, cd* out, bool zero_physical,
+                          hipStream_t st, int nq = 1);
 hipError_t rhs_build(const Geom& g, const cd* T, const cd* H, const cd* t, cd* rhs, hipStream_t st);
 // nq lists of n indices one after the other: out[q*ostride + r] = vec[idx[q*n + r]]
 // (ostride 0: n) and vec[idx[q*n + r]] = in[q*istride + r].

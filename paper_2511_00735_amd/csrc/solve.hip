@@ -15,8 +15,10 @@ constexpr int kRows = 64;  // rows per workgroup of the streaming matvec kernels
 // out[Pi(s)] = g[Pi(s)] - (T^B g_B)[s] for every interior boundary slot s of
 // every level-l box B, for each problem of a group (boxes and canonical vectors
 // of problem q follow those of problem q-1).  Grid (problems * boxes,
-// ceil(b / 64)), 64 threads.
-__global__ __launch_bounds__(kRows) void skeleton_apply_kernel(Geom g, const cd* T, const cd* gin,
+// ceil(b / 64)), 64 threads.  M: the storage type of the box maps (complex
+// FP64, or FP32 on the FP32 levels of mixed precision); FP64 arithmetic.
+template <class M>
+__global__ __launch_bounds__(kRows) void skeleton_apply_kernel(Geom g, const M* T, const cd* gin,
                                                                cd* out, int zero_physical, long long nslots) {
   extern __shared__ cd gB[];
   const int jg = blockIdx.x;
@@ -50,21 +52,21 @@ __global__ __launch_bounds__(kRows) void skeleton_apply_kernel(Geom g, const cd*
     if (zero_physical) out[slot] = cmk(0.0, 0.0);
     return;
   }
-  const cd* Tb = T + (long long)jg * b * b;
+  const M* Tb = T + (long long)jg * b * b;
   cd acc = cmk(0.0, 0.0);
   for (int s = 0; s < 4; ++s) {
     if (phys_side[s]) continue;
     const int c1 = g.off[s + 1];
     int c = g.off[s];
     for (; c + 3 < c1; c += 4) {
-      const cd t0 = Tb[(long long)c * b + r], t1 = Tb[(long long)(c + 1) * b + r];
-      const cd t2 = Tb[(long long)(c + 2) * b + r], t3 = Tb[(long long)(c + 3) * b + r];
+      const cd t0 = to_cd(Tb[(long long)c * b + r]), t1 = to_cd(Tb[(long long)(c + 1) * b + r]);
+      const cd t2 = to_cd(Tb[(long long)(c + 2) * b + r]), t3 = to_cd(Tb[(long long)(c + 3) * b + r]);
       acc = cfma(t0, gB[c], acc);
       acc = cfma(t1, gB[c + 1], acc);
       acc = cfma(t2, gB[c + 2], acc);
       acc = cfma(t3, gB[c + 3], acc);
     }
-    for (; c < c1; ++c) acc = cfma(Tb[(long long)c * b + r], gB[c], acc);
+    for (; c < c1; ++c) acc = cfma(to_cd(Tb[(long long)c * b + r]), gB[c], acc);
   }
   const int ps = slot_partner(g.n, g.p, slot);
   out[ps] = csub(gin[ps], acc);
@@ -543,15 +545,28 @@ inline int grid_for(long long n, int block = 256, int cap = 2048) {
 
 }  // namespace
 
-hipError_t skeleton_apply(const Geom& g, const cd* T, const cd* gin, cd* out, bool zero_physical,
-                          hipStream_t st, int nq) {
+namespace {
+template <class M>
+hipError_t skeleton_apply_t(const Geom& g, const M* T, const cd* gin, cd* out, bool zero_physical,
+                            hipStream_t st, int nq) {
   dim3 grid(g.nboxes * nq, (g.b + kRows - 1) / kRows);
   const long long nslots = (long long)g.n * g.n * 4 * g.p;
-  hipError_t e0 = allow_lds(skeleton_apply_kernel, (size_t)g.b * sizeof(cd));
+  hipError_t e0 = allow_lds(skeleton_apply_kernel<M>, (size_t)g.b * sizeof(cd));
   if (e0 != hipSuccess) return e0;
-  hipLaunchKernelGGL(skeleton_apply_kernel, grid, dim3(kRows), (size_t)g.b * sizeof(cd), st, g, T, gin,
+  hipLaunchKernelGGL(skeleton_apply_kernel<M>, grid, dim3(kRows), (size_t)g.b * sizeof(cd), st, g, T, gin,
                      out, zero_physical ? 1 : 0, nslots);
   return hipPeekAtLastError();
+}
+}  // namespace
+
+hipError_t skeleton_apply(const Geom& g, const cd* T, const cd* gin, cd* out, bool zero_physical,
+                          hipStream_t st, int nq) {
+  return skeleton_apply_t(g, T, gin, out, zero_physical, st, nq);
+}
+
+hipError_t skeleton_apply(const Geom& g, const cf* T, const cd* gin, cd* out, bool zero_physical,
+                          hipStream_t st, int nq) {
+  return skeleton_apply_t(g, T, gin, out, zero_physical, st, nq);
 }
 
 hipError_t rhs_build(const Geom& g, const cd* T, const cd* H, const cd* t, cd* rhs, hipStream_t st) {

@@ -41,7 +41,8 @@ class Desc(ctypes.Structure):
 
 class Info(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iterations", ctypes.c_int32),
-                ("relres_est", ctypes.c_double), ("relres_true", ctypes.c_double)]
+                ("relres_est", ctypes.c_double), ("relres_true", ctypes.c_double),
+                ("t_build_s", ctypes.c_double), ("t_solve_s", ctypes.c_double)]
 
 
 class LevelView(ctypes.Structure):
@@ -76,6 +77,8 @@ _SIGS = {
     "hps_group_create": ([_P, ctypes.POINTER(Desc), ctypes.c_int32, _P, _P, _P, ctypes.c_size_t,
                           ctypes.POINTER(_P)], ctypes.c_int),
     "hps_group_size": ([_P], ctypes.c_int32),
+    "hps_choose_levels": ([ctypes.POINTER(Desc), ctypes.c_int32, ctypes.c_size_t, ctypes.POINTER(ctypes.c_int32)],
+                          ctypes.c_int),
     "hps_build_leaves": ([_PP, ctypes.c_int32, _PP, _PP], ctypes.c_int),
     "hps_merge_level": ([_PP, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
     "hps_set_rhs": ([_PP, ctypes.c_int32, _PP, _PP], ctypes.c_int),
@@ -125,6 +128,15 @@ def workspace_bytes(desc):
     rc = lib.hps_workspace_bytes(ctypes.byref(desc), ctypes.byref(out))
     if rc != HPS_OK:
         raise HPSError(rc, "invalid descriptor")
+    return out.value
+
+
+def choose_levels(desc, budget, count=1):
+    """Most levels L whose workspace for `count` problems fits `budget` bytes."""
+    out = ctypes.c_int32(0)
+    rc = lib.hps_choose_levels(ctypes.byref(desc), count, ctypes.c_size_t(int(budget)), ctypes.byref(out))
+    if rc != HPS_OK:
+        raise HPSError(rc, f"no level count fits {budget} bytes")
     return out.value
 
 
@@ -446,7 +458,7 @@ def gmres_solve(problems, rhs, g, tol=1e-10, maxit=600):
                                               _ptrs([_dptr(x) for x in g]), tol, maxit, infos),
                           "hps_gmres_solve")
     return [dict(status=i.status, iterations=i.iterations, relres_est=i.relres_est,
-                 relres_true=i.relres_true) for i in infos]
+                 relres_true=i.relres_true, t_build_s=i.t_build_s, t_solve_s=i.t_solve_s) for i in infos]
 
 
 def morton_box_xy(level, j):

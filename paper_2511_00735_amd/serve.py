@@ -11,9 +11,9 @@ launches.  Batching and admission are decided here, on the host:
   the shape, and younger requests of the same shape join it in arrival order,
   up to ``max_batch``;
 * a batch is admitted only when its exact device footprint (the group
-  workspace plus its input and output vectors) fits in what is left of the
-  memory budget; otherwise it shrinks, and if even the oldest request alone
-  does not fit, the worker waits until running batches release memory;
+  workspace plus its input and output vectors) fits in a worker's arena (a
+  fixed share of the memory budget, allocated once per worker); otherwise it
+  shrinks;
 * requests that arrive while other batches run are admitted as workers and
   memory free up, so builds and solves of different batches overlap on the
   device (one stream per worker).
@@ -63,7 +63,6 @@ class Planner:
         self.batch_budget = int(batch_budget) if batch_budget is not None else self.budget
         self.pending: List = []     # (arrival order) requests waiting
         self.in_use = 0
-        self.hold = False           # no admissions (a batch waits for the others to drain)
 
     @staticmethod
     def shape(req):
@@ -75,7 +74,7 @@ class Planner:
     def take(self):
         """Next batch (list of requests and its footprint), or None when the
         oldest request cannot be admitted yet (or nothing is pending)."""
-        if not self.pending or self.hold:
+        if not self.pending:
             return None
         key = self.shape(self.pending[0])
         same = [r for r in self.pending if self.shape(r) == key][: self.max_batch]
@@ -101,23 +100,21 @@ class Planner:
     def release(self, nbytes):
         self.in_use -= int(nbytes)
 
-    def requeue(self, batch):
-        """Puts the requests of a batch that could not run back among the
-        pending ones, in arrival order."""
-        self.pending = sorted(self.pending + list(batch), key=lambda r: r.arrival)
-
 
 class Server:
     """Runs a request trace through the library in real time.
 
     precision: "mixed" or "fp64"; workers: concurrent batches (streams);
-    memory_budget: device bytes the admitted batches may hold together, one
-    batch at most memory_budget / workers (a lone request may take more);
-    graphs: each worker replays its V-cycles from HIP graphs (several host
-    threads launching at once).  A batch whose allocation fails (the caching
-    allocator's free memory split by other batches) goes back to the pending
-    requests; nothing is admitted until the running batches have finished and
-    the cache has been released, then batching resumes."""
+    memory_budget: device bytes for all workers together.  Each worker holds
+    one arena of memory_budget / workers bytes, allocated once when it starts;
+    every batch it runs is carved out of that arena (the group workspace of
+    the library's exact footprint, each request's coefficient, boundary data,
+    right-hand side and solution, and the temporaries that evaluate the
+    inputs), so serving makes no device allocation per batch and the caching
+    allocator cannot fragment.  A batch never exceeds an arena; a request
+    that alone exceeds it is refused when the run starts.  graphs: each worker
+    replays its V-cycles from HIP graphs (several host threads launching at
+    once)."""
 
     def __init__(self, precision="mixed", workers=3, max_batch=32, memory_budget=200 << 30, tol=1e-8,
                  coarse_iters=5, restart=60, maxit=600, keep_solutions=False, graphs=True):
@@ -130,6 +127,7 @@ class Server:
         self.workers = int(workers)
         self.max_batch = int(max_batch)
         self.budget = int(memory_budget)
+        self.arena_bytes = (self.budget // max(1, self.workers)) & ~255
         self.tol = tol
         self.coarse_iters = coarse_iters
         self.restart = restart
@@ -140,18 +138,40 @@ class Server:
         self._coords = {}
         self._coord_lock = threading.Lock()
 
-    # ---- shapes and footprints -------------------------------------------
+    # ---- shapes, footprints and the arena layout ---------------------------
     def desc(self, n, N, kappa=1.0):
         return self.hps.make_desc(n, N, kappa, levels=0, coarse_iters=self.coarse_iters, restart=self.restart,
                                   precision=self.prec)
 
-    def footprint(self, shape, count):
+    @staticmethod
+    def _up(nbytes):
+        return (int(nbytes) + 255) & ~255
+
+    def layout(self, shape, count):
+        """Byte offsets of a batch inside an arena: the group workspace, then
+        per request b [E][(N+1)^2] (FP64) and the complex canonical vectors t,
+        rhs, g, then three FP64 temporaries for evaluating the inputs.
+        Returns (offsets dict, total bytes)."""
         n, N = shape
-        ws = self.hps.group_workspace_bytes(self.desc(n, N), count)
         E, p = n * n, N - 1
-        vec = 16 * E * 4 * p                      # one canonical complex vector
-        inputs = 8 * E * (N + 1) ** 2 + 3 * vec   # b at the nodes, t, rhs, g
-        return ws + 256 + count * inputs
+        nodes = 8 * E * (N + 1) ** 2
+        vec = 16 * E * 4 * p
+        off = {"ws": 0}
+        cur = self._up(self.hps.group_workspace_bytes(self.desc(n, N), count))
+        off["req"] = []
+        for _ in range(count):
+            r = {}
+            for key, nb in (("b", nodes), ("t", vec), ("rhs", vec), ("g", vec)):
+                r[key] = cur
+                cur += self._up(nb)
+            off["req"].append(r)
+        for key in ("tmpa", "tmpb", "tmpc"):
+            off[key] = cur
+            cur += self._up(nodes)
+        return off, cur
+
+    def footprint(self, shape, count):
+        return self.layout(shape, count)[1]
 
     def _node_data(self, n, N):
         """Device node and slot coordinates of a shape (cached)."""
@@ -167,62 +187,107 @@ class Server:
                 torch.cuda.synchronize()
             return self._coords[key]
 
-    # ---- synthetic inputs, evaluated on the device ------------------------
-    def _inputs(self, req, coords):
+    # ---- synthetic inputs, evaluated on the device into arena views --------
+    def _inputs_into(self, req, coords, b, t, tmpa, tmpb, tmpc):
         torch = self.torch
         x, y, sx, sy, nx, ny = coords
-        b = torch.zeros_like(x)
+        b.zero_()
         bm = req.b
         for a, cx, cy, w in zip(bm.a, bm.cx, bm.cy, bm.w):
-            b += float(a) * torch.exp(-((x - float(cx)) ** 2 + (y - float(cy)) ** 2) / float(w))
+            torch.sub(x, float(cx), out=tmpa)
+            tmpa.square_()
+            torch.sub(y, float(cy), out=tmpb)
+            tmpb.square_()
+            tmpa.add_(tmpb).div_(-float(w)).exp_()
+            b.add_(tmpa, alpha=float(a))
+        # t = i (kappa d.n + eta) exp(i kappa d.x) at the slots
         wv = req.wave
-        u = torch.exp(1j * wv.kappa * (wv.d[0] * sx + wv.d[1] * sy))
-        t = 1j * (wv.kappa * (wv.d[0] * nx + wv.d[1] * ny) + wv.eta) * u
-        return b.contiguous(), t.to(torch.complex128).contiguous()
+        ns = sx.numel()
+        ph, cf, tv = tmpa.view(-1)[:ns], tmpb.view(-1)[:ns], tmpc.view(-1)[:ns]
+        torch.mul(sx, wv.kappa * wv.d[0], out=ph)
+        ph.add_(sy, alpha=wv.kappa * wv.d[1])
+        torch.mul(nx, wv.kappa * wv.d[0], out=cf)
+        cf.add_(ny, alpha=wv.kappa * wv.d[1]).add_(wv.eta)
+        tr = torch.view_as_real(t)
+        torch.sin(ph, out=tv)
+        tv.mul_(cf).neg_()
+        tr[:, 0].copy_(tv)
+        torch.cos(ph, out=tv)
+        tv.mul_(cf)
+        tr[:, 1].copy_(tv)
+
+    def _views(self, arena, shape, count):
+        """Typed views of one batch's buffers inside `arena` (uint8)."""
+        torch = self.torch
+        n, N = shape
+        E, p = n * n, N - 1
+        off, total = self.layout(shape, count)
+        ws_bytes = self.hps.group_workspace_bytes(self.desc(n, N), count)
+        nodes, ns = E * (N + 1) ** 2, E * 4 * p
+
+        def f64(o, cnt):
+            return arena[o:o + 8 * cnt].view(torch.float64)
+
+        def c128(o, cnt):
+            return arena[o:o + 16 * cnt].view(torch.complex128)
+
+        reqs = [dict(b=f64(r["b"], nodes).view(E, (N + 1) ** 2), t=c128(r["t"], ns), rhs=c128(r["rhs"], ns),
+                     g=c128(r["g"], ns)) for r in off["req"]]
+        tmp = [f64(off[k], nodes).view(E, (N + 1) ** 2) for k in ("tmpa", "tmpb", "tmpc")]
+        return arena[0:ws_bytes], reqs, tmp
 
     # ---- one batch on one worker's stream ---------------------------------
-    def _run_batch(self, ctx, batch, records):
-        torch, hps = self.torch, self.hps
+    def _run_batch(self, ctx, arena, batch, records):
+        hps = self.hps
         n, N = batch[0].n, batch[0].N
         coords = self._node_data(n, N)
         t0 = time.perf_counter() - self._t0
         for r in batch:
             records[r.name].start = t0
             records[r.name].batch = len(batch)
-        desc = self.desc(n, N, batch[0].kappa)
-        group = hps.Group(ctx, desc, [r.kappa for r in batch], [r.eta for r in batch])
-        ins = [self._inputs(r, coords) for r in batch]
-        group.build_leaves([i[0] for i in ins])
+        ws, bufs, (tmpa, tmpb, tmpc) = self._views(arena, (n, N), len(batch))
+        group = hps.Group(ctx, self.desc(n, N, batch[0].kappa), [r.kappa for r in batch],
+                          [r.eta for r in batch], workspace=ws)
+        for r, v in zip(batch, bufs):
+            self._inputs_into(r, coords, v["b"], v["t"], tmpa, tmpb, tmpc)
+        group.build_leaves([v["b"] for v in bufs])
         group.merge_all()
-        rhs = group.set_rhs([i[1] for i in ins])
-        gs, infos = group.gmres_solve(rhs, tol=self.tol, maxit=self.maxit)
+        hps.set_rhs([group], [v["t"] for v in bufs], [v["rhs"] for v in bufs])
+        infos = hps.gmres_solve([group], [v["rhs"] for v in bufs], [v["g"] for v in bufs],
+                                self.tol, self.maxit)
         t1 = time.perf_counter() - self._t0
-        for r, info, g in zip(batch, infos, gs):
+        for r, info, v in zip(batch, infos, bufs):
             rec = records[r.name]
             rec.finish = t1
             rec.iterations = info["iterations"]
             rec.relres = info["relres_true"]
             rec.status = info["status"]
             if self.keep:
-                self.solutions[r.name] = g.clone()
-        del group, ins, rhs, gs
+                self.solutions[r.name] = v["g"].clone()
+        del group
 
     def run(self, trace):
         """Serve `trace` (requests with .arrival in seconds, ascending);
         returns (records by name, summary dict)."""
         torch, hps = self.torch, self.hps
-        planner = Planner(self.footprint, self.budget, self.max_batch,
-                          batch_budget=self.budget // max(1, self.workers))
+        for shape in sorted(set((r.n, r.N) for r in trace)):
+            need = self.footprint(shape, 1)
+            if need > self.arena_bytes:
+                raise ValueError(f"a single {shape} request needs {need} bytes, more than a worker's "
+                                 f"arena ({self.arena_bytes} bytes of the {self.budget}-byte budget)")
+        planner = Planner(self.footprint, self.arena_bytes * self.workers, self.max_batch,
+                          batch_budget=self.arena_bytes)
         records = {r.name: Record(r.name, r.n, r.N, r.arrival, dof=r.skeleton_dof) for r in trace}
         cond = threading.Condition()
         state = {"fed": 0, "done": False, "error": None}
-        retried = set()   # ids of requests whose batch ran out of memory once
-        # cached blocks of earlier work go back to the device: the workers'
-        # new streams and their kernels' scratch are allocated by the runtime
+        # cached blocks of earlier work go back to the device before the
+        # arenas are taken
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
         for shape in sorted(set((r.n, r.N) for r in trace)):
             self._node_data(*shape)
+        arenas = [torch.empty(self.arena_bytes, dtype=torch.uint8, device="cuda") for _ in range(self.workers)]
+        torch.cuda.synchronize()
         self._t0 = time.perf_counter()
 
         def feeder():
@@ -243,7 +308,7 @@ class Server:
                 state["done"] = True
                 cond.notify_all()
 
-        def worker():
+        def worker(arena):
             stream = torch.cuda.Stream()
             ctx = hps.Context(stream)
             ctx.set_graphs(self.graphs)
@@ -260,33 +325,8 @@ class Server:
                                 return
                             cond.wait(timeout=0.05)
                     batch, need = got
-                    oom = False
-                    try:
-                        with torch.cuda.stream(stream):
-                            self._run_batch(ctx, batch, records)
-                    except torch.OutOfMemoryError:
-                        if any(id(r) in retried for r in batch):
-                            raise
-                        oom = True
-                    if oom:
-                        # the device memory is there but split across other
-                        # batches' cached blocks: hand the batch back, admit
-                        # nothing until the running batches have finished,
-                        # release the cache; a batch that fails twice is an error
-                        retried.update(id(r) for r in batch)
-                        with cond:
-                            planner.release(need)
-                            planner.requeue(batch)
-                            planner.hold = True
-                            cond.notify_all()
-                            while planner.in_use > 0 and state["error"] is None:
-                                cond.wait(timeout=0.05)
-                        torch.cuda.synchronize()
-                        torch.cuda.empty_cache()
-                        with cond:
-                            planner.hold = False
-                            cond.notify_all()
-                        continue
+                    with torch.cuda.stream(stream):
+                        self._run_batch(ctx, arena, batch, records)
                     with cond:
                         planner.release(need)
                         cond.notify_all()
@@ -296,15 +336,18 @@ class Server:
                     cond.notify_all()
 
         threads = [threading.Thread(target=feeder, daemon=True)]
-        threads += [threading.Thread(target=worker, daemon=True) for _ in range(self.workers)]
+        threads += [threading.Thread(target=worker, args=(arenas[i],), daemon=True) for i in range(self.workers)]
         for th in threads:
             th.start()
         for th in threads:
             th.join()
         torch.cuda.synchronize()
+        del arenas
         if state["error"] is not None:
             raise state["error"]
-        return records, summarize(records.values())
+        summary = summarize(records.values())
+        summary["arena_gib_per_worker"] = round(self.arena_bytes / 2 ** 30, 2)
+        return records, summary
 
 
 def summarize(records):

@@ -17,6 +17,9 @@ these are synthetic stand-ins of the same shape):
   1-6 bumps, random plane-wave direction.
 * ``c5``: Poisson arrivals (mean gap 20 ms for 60 s); each request drawn as in
   c4, or with probability 0.1 a 128x128, N=16, kappa=400 problem.
+* ``x1``: the paper's own experiment: the Gaussian bump 1.5 exp(-160 r^2),
+  the scattering source of the incident wave exp(i kappa x), t = 0, N = 16,
+  9.6 points per wavelength (kappa = 670 on 64x64).
 """
 import math
 from dataclasses import dataclass, field
@@ -159,5 +162,42 @@ def c5(duration=60.0, rate=50.0, big_frac=0.1, seed=5, big_n=128, big_kappa=400.
     return out
 
 
+@dataclass
+class ZeroData:
+    """Zero impedance data t = 0 (the scattered-field problem)."""
+    kappa: float
+    eta: float
+
+    def t(self, x, y, nx, ny):
+        return np.zeros(np.broadcast(np.asarray(x), np.asarray(y)).shape, dtype=np.complex128)
+
+
+def x1_bump(x, y):
+    return 1.5 * np.exp(-160.0 * ((np.asarray(x) - 0.5) ** 2 + (np.asarray(y) - 0.5) ** 2))
+
+
+@dataclass
+class ScatteringSource:
+    """s = -kappa^2 b(x) exp(i kappa x): the source of the field scattered by
+    the coefficient b when the plane wave exp(i kappa x) is incident (the
+    total field solves the homogeneous equation)."""
+    kappa: float
+    b: Callable
+
+    def __call__(self, x, y):
+        x = np.asarray(x, dtype=np.float64)
+        return -self.kappa ** 2 * self.b(x, y) * np.exp(1j * self.kappa * x)
+
+
+def x1(n=64, N=16, points_per_wavelength=9.6, levels=0, coarse_iters=5):
+    """The paper's experiment (Sec. 5): b = 1.5 exp(-160 |x - (0.5, 0.5)|^2),
+    s = -kappa^2 b exp(i kappa x), t = 0, GLL order N, kappa from the points
+    per wavelength over the n N GLL intervals of a side: kappa = 2 pi n N /
+    points_per_wavelength (670.2 on the paper's 64 x 64, N = 16 mesh)."""
+    k = 2.0 * math.pi * n * N / points_per_wavelength
+    return Problem(n, N, k, k, x1_bump, ZeroData(k, k), s=ScatteringSource(k, x1_bump), levels=levels,
+                   coarse_iters=coarse_iters, tol=1e-8, name=f"x1_{n}")
+
+
 def by_name(name):
-    return {"c1": c1, "c2": c2, "c3": c3}[name]()
+    return {"c1": c1, "c2": c2, "c3": c3, "x1": x1}[name]()

@@ -1,0 +1,123 @@
+"""Failure handling through the C ABI, every condition forced from the host
+(every kernel still runs to its normal end):
+
+* an element tuned onto an interior Dirichlet resonance (its interior block
+  singular to rounding): the leaf map still matches the oracle's complex
+  element solve (the library recomputes such elements from the complex
+  element system of Sec. 3.1);
+* an exactly singular shared-face block A (T^P_aa = T^Q_bb = I written into
+  the leaf maps): HPS_ERR_SINGULAR naming the problem, level and pair;
+* maxit reached: HPS_NOT_CONVERGED with the last (best) iterate and its true
+  residual;
+* a NaN in the coefficient: HPS_ERR_ARG naming the element; a rebuild with
+  finite data clears it.
+"""
+import numpy as np
+import pytest
+
+from tests.gpu_cases import oracle_case, gpu_problem, rel, box_maps_by_xy
+from paper_2511_00735_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture
+def ctx(hps):
+    """A context per test: hps_sync reports the failures of every live problem
+    of its context, and a failed test's problem may outlive the test."""
+    import gc
+    c = hps.Context()
+    yield c
+    gc.collect()
+
+
+def _first_dirichlet_kappa(N, h):
+    """Smallest kappa at which the interior block of the b = 0 element
+    operator (stiffness - kappa^2 mass on the interior nodes) is singular."""
+    import scipy.linalg as sl
+    from oracle import leaf
+    keep, _, _, ii = leaf.index_sets(N)
+    ones = np.ones((N + 1) ** 2)
+    A = leaf.local_operator(N, h, 0 * ones)[np.ix_(keep, keep)][np.ix_(ii, ii)]
+    Mm = A - leaf.local_operator(N, h, ones)[np.ix_(keep, keep)][np.ix_(ii, ii)]
+    return float(np.sqrt(sl.eigh(A, Mm, eigvals_only=True)[0]))
+
+
+@pytest.mark.parametrize("offset", [0.0, 1e-9, 1e-6])
+def test_resonant_element_matches_oracle(hps, ctx, offset):
+    n, N = 2, 16
+    kappa = _first_dirichlet_kappa(N, 1.0 / n) * (1 + offset)
+    print(f"[resonance] kappa {kappa:.15g} (offset {offset:g})", flush=True)
+    wave = workloads.PlaneWave(kappa, kappa)
+    oc = oracle_case(n, N, kappa, workloads.zero_field, wave.t, None, with_direct=False)
+    prob = gpu_problem(hps, ctx, n, N, kappa, workloads.zero_field, merge=False)
+    Tg = box_maps_by_xy(hps, prob, 1)
+    for e in range(n * n):
+        assert rel(Tg[(e % n, e // n)], oc["T"][e]) < 1e-11, e
+
+
+def test_singular_shared_face_block_is_reported(hps, ctx):
+    import torch
+    n, N = 4, 4
+    p = N - 1
+    prob = gpu_problem(hps, ctx, n, N, 5.0, workloads.zero_field, merge=False)
+    # level-1 pair 0: P = element (0, 0) (shared side r), Q = element (1, 0)
+    # (shared side l); with both self-reflection blocks = I, W = I - I I = 0
+    T = prob.level_T(1)
+    eye = torch.eye(p, dtype=T.dtype, device=T.device)
+    assert hps.morton_box_xy(1, 0) == (0, 0) and hps.morton_box_xy(1, 1) == (1, 0)
+    T[0, p:2 * p, p:2 * p] = eye
+    T[1, 0:p, 0:p] = eye
+    prob.merge_all()
+    with pytest.raises(hps.HPSError) as ei:
+        ctx.sync()
+    assert ei.value.code == -3
+    msg = str(ei.value)
+    assert "merge level 1 of problem 0, pair 0" in msg, msg
+    rhs = prob.set_rhs(prob.boundary_data(workloads.PlaneWave(5.0, 5.0).t))
+    with pytest.raises(hps.HPSError) as ei:
+        prob.gmres_solve(rhs, tol=1e-10, maxit=50)
+    assert ei.value.code == -3
+
+
+def test_maxit_returns_best_iterate(hps, ctx):
+    import torch
+    pr = workloads.c2()
+    prob = gpu_problem(hps, ctx, pr.n, pr.N, pr.kappa, pr.b, levels=8, coarse_iters=2)
+    rhs = prob.set_rhs(prob.boundary_data(pr.wave.t))
+    res = []
+    for maxit in (1, 2, 3):
+        g, info = prob.gmres_solve(rhs, tol=1e-14, maxit=maxit)
+        assert info["status"] == 1 and info["iterations"] == maxit, info
+        r = rhs - prob.skeleton_apply(g)
+        true = float(torch.linalg.norm(r) / torch.linalg.norm(rhs))
+        assert abs(true - info["relres_true"]) <= 1e-12 + 1e-9 * true, (true, info)
+        assert info["t_build_s"] > 0 and info["t_solve_s"] > 0
+        res.append(true)
+    # each further iteration minimises over a larger Krylov space
+    assert res[0] >= res[1] >= res[2], res
+
+
+def test_nonfinite_coefficient_is_reported(hps, ctx):
+    n, N, kappa = 4, 6, 9.0
+    desc = hps.make_desc(n, N, kappa, coarse_iters=3)
+    prob = hps.Problem(ctx, desc)
+    b = prob.coefficient_nodes(workloads.zero_field)
+    b[5, 7] = float("nan")
+    prob.build_leaves(b)
+    prob.merge_all()
+    with pytest.raises(hps.HPSError) as ei:
+        ctx.sync()
+    assert ei.value.code == -1 and "element 5 (ix 1, iy 1)" in str(ei.value), str(ei.value)
+    rhs = prob.set_rhs(prob.boundary_data(workloads.PlaneWave(kappa, kappa).t))
+    with pytest.raises(hps.HPSError) as ei:
+        prob.gmres_solve(rhs, tol=1e-10)
+    assert ei.value.code == -1
+    # a rebuild with finite data clears the record
+    b[5, 7] = 0.0
+    prob.build_leaves(b)
+    prob.merge_all()
+    ctx.sync()
+    rhs = prob.set_rhs(prob.boundary_data(workloads.PlaneWave(kappa, kappa).t))
+    g, info = prob.gmres_solve(rhs, tol=1e-10)
+    assert info["status"] == 0

@@ -145,3 +145,31 @@ def test_c3_fp32_blocked_inverses(hps, ctx, c3, level):
               f"(cond {cond:.1f}, bound {bound:.2e})", flush=True)
         assert res <= m2 * U32, (j, res)
         assert err <= bound, (j, err, bound)
+
+
+# ---- the paper's own experiment (Sec. 5): Gaussian bump, scattering source,
+# t = 0, N = 16, 9.6 points per wavelength; the only workload with s != 0
+# (loads H on every level) at scale
+
+@pytest.mark.parametrize("n", [16, 64])
+def test_x1_scattering_matches_oracle(hps, ctx, n):
+    import time
+    from tests.gpu_cases import oracle_case
+    pr = workloads.x1(n)
+    print(f"[x1] {n}x{n}, kappa {pr.kappa:.2f}", flush=True)
+    t0 = time.perf_counter()
+    oc = oracle_case(pr.n, pr.N, pr.kappa, pr.b, pr.wave.t, pr.s)
+    print(f"[x1] oracle {time.perf_counter() - t0:.1f} s", flush=True)
+    for precision in ("fp64", "mixed"):
+        prec = hps.HPS_MIXED if precision == "mixed" else hps.HPS_FP64
+        desc = hps.make_desc(pr.n, pr.N, pr.kappa, pr.eta, coarse_iters=5, precision=prec)
+        prob = hps.Problem(ctx, desc)
+        prob.build_leaves(prob.coefficient_nodes(pr.b), prob.source_nodes(pr.s))
+        prob.merge_all()
+        rhs = prob.set_rhs(prob.boundary_data(pr.wave.t))
+        g, info = prob.gmres_solve(rhs, tol=1e-12, maxit=600)
+        err = rel(g.cpu().numpy(), oc["g"])
+        print(f"[x1] {n}x{n} {precision}: {info['iterations']} its, relres {info['relres_true']:.2e}, "
+              f"error vs oracle {err:.2e}", flush=True)
+        assert info["status"] == 0 and err <= 1e-10, (precision, err, info)
+        del prob

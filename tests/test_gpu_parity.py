@@ -162,6 +162,43 @@ def test_precond_apply(hps, ctx, n, N, levels, k):
     assert rel(z, zr) < 1e-10
 
 
+GAMMA_CASES = [  # n, N, levels, k, gamma, precision
+    (4, 6, 4, 3, 2, "fp64"), (4, 6, 3, 4, 2, "fp64"), (4, 6, 4, -1, 2, "fp64"),
+    (8, 5, 5, 3, 3, "fp64"),       # gamma = 3, coarse level below the top
+    (16, 4, 6, 2, 2, "fp64"),      # 128 pairs at level 1
+    (16, 4, 7, 3, 2, "mixed"),     # FP32 levels 1-4: M_{l+1} applied from FP32 maps
+]
+
+
+@pytest.mark.parametrize("n,N,levels,k,gamma,precision", GAMMA_CASES)
+def test_gamma_cycle_matches_oracle(hps, ctx, n, N, levels, k, gamma, precision):
+    """MG with gamma stationary coarse steps per level (Sec. 4.3) against the
+    oracle's gamma-cycle on the assembled M_l; FP64 to 1e-10, the mixed tree
+    (FP32 maps below the top two merges) to 1e-4."""
+    import torch
+    from oracle import multigrid, mesh
+    kappa = 8.0
+    print(f"[gamma] n={n} N={N} L={levels} k={k} gamma={gamma} {precision}", flush=True)
+    wave = workloads.PlaneWave(kappa, kappa)
+    oc = oracle_case(n, N, kappa, _bump, wave.t, None, with_direct=False)
+    prec = hps.HPS_MIXED if precision == "mixed" else hps.HPS_FP64
+    desc = hps.make_desc(n, N, kappa, levels=levels, coarse_iters=k, gamma=gamma, precision=prec)
+    prob = hps.Problem(ctx, desc)
+    prob.build_leaves(prob.coefficient_nodes(_bump))
+    prob.merge_all()
+    hier = multigrid.Hierarchy(n, N - 1, oc["T"], levels=levels)
+    rng = np.random.default_rng(levels * 10 + gamma)
+    r = rng.standard_normal(prob.nslots) + 1j * rng.standard_normal(prob.nslots)
+    r[mesh.physical_slot_mask(n, N - 1)] = 0
+    z = prob.precond_apply(torch.from_numpy(r).cuda()).cpu().numpy()
+    zr = hier.apply(r, None if k < 0 else k, gamma=gamma)
+    err = rel(z, zr)
+    assert err < (1e-10 if precision == "fp64" else 1e-4), err
+    if gamma > 1 and k > 0:
+        # gamma = 1 is a different operator (unless the coarse solve is exact)
+        assert rel(hier.apply(r, k, gamma=1), zr) > 1e-8
+
+
 SOLVE_CASES = [
     # name, workload, levels, k
     ("c1_direct", "c1", 4, -1),

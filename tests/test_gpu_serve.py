@@ -1,5 +1,6 @@
 """The serving loop: requests that arrive together are batched and overlap on
-the device; each result is the same as the request solved alone."""
+the device; each result is the same as the request solved alone, and a sample
+of them matches the oracle."""
 import math
 
 import numpy as np
@@ -43,9 +44,14 @@ def test_served_results_equal_alone(hps, ctx, precision):
     for pr in trace:
         desc = hps.make_desc(pr.n, pr.N, pr.kappa, levels=0, coarse_iters=3, precision=prec)
         prob = hps.Problem(ctx, desc)
-        b, t = srv._inputs(pr, srv._node_data(pr.n, pr.N))
+        b, t = prob.coefficient_nodes(pr.b), prob.boundary_data(pr.wave.t)
         prob.build_leaves(b)
         prob.merge_all()
         g, info = prob.gmres_solve(prob.set_rhs(t), tol=1e-12, maxit=600)
         assert info["relres_true"] <= 1e-12
         assert rel(srv.solutions[pr.name].cpu().numpy(), g.cpu().numpy()) < 1e-10, pr.name
+    # and a sample of the served results against the oracle's direct solution
+    from tests.gpu_cases import oracle_case
+    for pr in trace[:5]:
+        oc = oracle_case(pr.n, pr.N, pr.kappa, pr.b, pr.wave.t)
+        assert rel(srv.solutions[pr.name].cpu().numpy(), oc["g"]) < 1e-10, pr.name

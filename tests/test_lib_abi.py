@@ -81,3 +81,30 @@ def test_morton_box_order_is_a_bijection(hps):
                     assert (qx, qy) == (px + 1, py) and px % 2 == 0
                 else:
                     assert (qx, qy) == (px, py + 1) and py % 2 == 0
+
+
+def test_choose_levels_is_the_most_levels_that_fit(hps):
+    d = hps.make_desc(64, 16, 200.0, coarse_iters=5)
+    sizes = {}
+    for L in range(1, 13):
+        sizes[L] = hps.workspace_bytes(hps.make_desc(64, 16, 200.0, levels=L, coarse_iters=5))
+    assert all(sizes[L] < sizes[L + 1] for L in range(1, 12))   # more levels, more memory
+    for L in range(1, 13):
+        assert hps.choose_levels(d, sizes[L]) == L
+        if L > 1:
+            assert hps.choose_levels(d, sizes[L] - 1) == L - 1
+    with pytest.raises(hps.HPSError):
+        hps.choose_levels(d, sizes[1] - 1)
+    ex = hps.make_desc(64, 16, 200.0, coarse_iters=-1)
+    with pytest.raises(hps.HPSError):       # exact coarse space: only L = L_max
+        hps.choose_levels(ex, hps.workspace_bytes(ex) - 1)
+    assert hps.choose_levels(hps.make_desc(16, 8, 20.0), 1 << 40, count=8) == 8
+
+
+def test_gamma_descriptor(hps):
+    base = hps.workspace_bytes(hps.make_desc(16, 8, 20.0, levels=6))
+    g2 = hps.workspace_bytes(hps.make_desc(16, 8, 20.0, levels=6, gamma=2))
+    assert g2 > base                        # per-level vectors of the gamma-cycle
+    for bad in (5, -1):
+        with pytest.raises(hps.HPSError):
+            hps.workspace_bytes(hps.make_desc(16, 8, 20.0, gamma=bad))

@@ -90,21 +90,33 @@ def test_batch_budget_caps_a_batch_but_not_a_lone_request():
     assert [r.name for r in batch] == ["big"] and need == big
 
 
-def test_hold_and_requeue_in_arrival_order():
-    one = fp((8, 8), 1)
-    pl = Planner(fp, budget=10 * one, max_batch=2)
-    reqs = [Req(f"r{i}", 8, 8, arrival=float(i)) for i in range(4)]
-    for r in reqs:
-        pl.add(r)
-    batch, need = pl.take()
-    assert [r.name for r in batch] == ["r0", "r1"]
-    # the batch could not run: its reservation is released, its requests go
-    # back ahead of the younger ones, and nothing is admitted during a hold
-    pl.release(need)
-    pl.requeue(batch)
-    assert [r.name for r in pl.pending] == ["r0", "r1", "r2", "r3"]
-    pl.hold = True
-    assert pl.take() is None
-    pl.hold = False
-    batch, _ = pl.take()
-    assert [r.name for r in batch] == ["r0", "r1"] and pl.in_use == 2 * one
+def test_arena_layout_is_aligned_disjoint_and_exact():
+    """A batch's buffers inside a worker's arena: 256-byte aligned, disjoint,
+    the group workspace first at the library's exact footprint (host-side
+    sizing through the C ABI; no GPU)."""
+    from paper_2511_00735_amd.serve import Server
+    from paper_2511_00735_amd import hps
+    srv = Server(precision="mixed", workers=2, memory_budget=64 << 30)
+    for shape, count in (((8, 8), 1), ((16, 12), 5), ((32, 16), 3)):
+        off, total = srv.layout(shape, count)
+        ws = hps.group_workspace_bytes(srv.desc(*shape), count)
+        n, N = shape
+        E, p = n * n, N - 1
+        spans = [(0, ws)]
+        for r in off["req"]:
+            spans += [(r["b"], 8 * E * (N + 1) ** 2)] + [(r[k], 16 * E * 4 * p) for k in ("t", "rhs", "g")]
+        spans += [(off[k], 8 * E * (N + 1) ** 2) for k in ("tmpa", "tmpb", "tmpc")]
+        spans.sort()
+        for (o1, l1), (o2, _) in zip(spans, spans[1:]):
+            assert o1 % 256 == 0 and o1 + l1 <= o2
+        assert spans[-1][0] + spans[-1][1] <= total == srv.footprint(shape, count)
+        assert srv.footprint(shape, count + 1) > total
+
+
+def test_request_larger_than_an_arena_is_refused():
+    from paper_2511_00735_amd.serve import Server
+    from paper_2511_00735_amd import workloads
+    pr = workloads.c3()
+    srv = Server(precision="fp64", workers=4, memory_budget=4 << 30)   # 1 GiB arenas
+    with pytest.raises(ValueError):
+        srv.run([pr])
