@@ -77,6 +77,7 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="length of the request trace served beside the headline (0: skip)")
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-problem batch")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the Table 1 sweep on the paper's workload")
     return ap.parse_args()
 
 
@@ -302,6 +303,56 @@ def run_batch_c4(hps, torch):
     return out
 
 
+def run_table1_sweep(hps, torch, precision="fp64"):
+    """The paper's Table 1 on its own experiment (X1: Gaussian bump, scattering
+    source, t = 0, 64x64, N = 16, kappa = 670): every (#levels L, gamma,
+    coarse iterations k) cell of the table -- gamma = 1 with k in {4, 5, 6}
+    for L = 2..12, gamma = 2 with k in {2, 3, 4} for L = 2..7 -- plus the
+    exact coarse space (direct HPS), each built and solved once to a relative
+    residual of 1e-8 (FGMRES(60), x0 = 0).  Per cell: PMem = the problem's
+    device workspace in MB (the library's exact footprint), It, Bt = leaf
+    build + merges, St = right-hand side + solve (device times from the
+    library's events).  One workspace, sized for the largest cell, serves
+    every cell."""
+    from paper_2511_00735_amd import workloads
+    pr = workloads.x1(64)
+    prec = hps.HPS_MIXED if precision == "mixed" else hps.HPS_FP64
+    cells = [(L, 1, k) for L in range(2, 13) for k in (4, 5, 6)]
+    cells += [(L, 2, k) for L in range(2, 8) for k in (2, 3, 4)]
+    cells += [(12, 1, -1)]
+    descs = {c: hps.make_desc(pr.n, pr.N, pr.kappa, pr.eta, levels=c[0], coarse_iters=c[2], gamma=c[1],
+                              precision=prec) for c in cells}
+    nbytes = max(hps.workspace_bytes(d) for d in descs.values())
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+    ctx = hps.Context()
+    rows = []
+    b_nodes = s_nodes = t_data = None
+    for c in cells:
+        d = descs[c]
+        prob = hps.Problem(ctx, d, workspace=ws)
+        if b_nodes is None:
+            b_nodes, s_nodes = prob.coefficient_nodes(pr.b), prob.source_nodes(pr.s)
+            t_data = prob.boundary_data(pr.wave.t)
+        prob.build_leaves(b_nodes, s_nodes)
+        prob.merge_all()
+        rhs = prob.set_rhs(t_data)
+        _, info = prob.gmres_solve(rhs, tol=1e-8, maxit=600)
+        L, gamma, k = c
+        rows.append({"levels": L, "gamma": gamma, "coarse_iters": "exact" if k < 0 else k,
+                     "pmem_mb": round(hps.workspace_bytes(d) / 1e6, 1), "iterations": info["iterations"],
+                     "build_ms": round(1e3 * info["t_build_s"], 2), "solve_ms": round(1e3 * info["t_solve_s"], 2),
+                     "relres": info["relres_true"], "converged": info["status"] == 0})
+        del prob
+    best = min((r for r in rows if r["converged"]), key=lambda r: r["build_ms"] + r["solve_ms"])
+    return {"workload": (f"the paper's experiment: 64x64 elements, N=16, kappa=eta={pr.kappa:.1f} (9.6 points per "
+                         "wavelength), b = 1.5 exp(-160 r^2), s = -kappa^2 b exp(i kappa x), t = 0, "
+                         f"FGMRES(60) to 1e-8, {precision}"),
+            "columns": "levels, gamma, coarse_iters, pmem_mb, iterations, build_ms, solve_ms, relres",
+            "rows": [[r["levels"], r["gamma"], r["coarse_iters"], r["pmem_mb"], r["iterations"], r["build_ms"],
+                      r["solve_ms"], r["relres"]] for r in rows],
+            "best": {**best, "dof_per_s": round(pr.skeleton_dof / (1e-3 * (best["build_ms"] + best["solve_ms"])), 1)}}
+
+
 def run_serving(hps, torch, seconds):
     """The first `seconds` of the seeded Poisson request trace (50 req/s, 10%
     128x128 N=16 kappa=400), served in real time, mixed vs FP64."""
@@ -418,6 +469,9 @@ def main():
         "data": "synthetic", "config": cfg, "roofline": roof,
     }
     progress("headline done: %.1f DOF/s" % main_run["value"])
+    if not args.no_sweep:
+        cfg["table1_sweep"] = run_table1_sweep(hps, torch)
+        progress("Table 1 sweep done")
     if not args.no_batch:
         cfg["batch_256_problems"] = run_batch_c4(hps, torch)
         progress("256-problem batch done")

@@ -246,6 +246,23 @@ hps_status hps_skeleton_apply(hps_problem* const* p, int32_t count, int32_t leve
    modified. */
 hps_status hps_precond_apply(hps_problem* const* p, int32_t count,
                              const double* const* r, double* const* z);
+/* Field recovery (Sec. 3.1): with the skeleton solution g known, each
+   element's incoming impedances f are known on all four sides (g on interior
+   sides, the boundary data t on physical sides), and its nodal field solves
+   the element system L u = [bt on the interior nodes; f on the side nodes]
+   (complex LU with partial pivoting per element).  The four corner nodes
+   carry no unknown (Sec. 3.1 removes them); each corner value is the mean of
+   the two extrapolations, along the two sides meeting there, of the
+   degree-(N-2) polynomial through the side's N-1 nodal values (a reading: the
+   paper leaves corners unspecified).
+   b_nodes, s_nodes (NULL: no source): as for hps_build_leaves; t, g: complex
+   canonical vectors; u[i]: complex [E][(N+1)^2] output, flat node index
+   i*(N+1)+j.  Requires hps_build_leaves; uses the workspace's scratch (no
+   other state is changed).  Zero pivots: HPS_ERR_SINGULAR at the next
+   synchronising call. */
+hps_status hps_recover_field(hps_problem* const* p, int32_t count, const double* const* b_nodes,
+                             const double* const* s_nodes, const double* const* t, const double* const* g,
+                             double* const* u);
 /* Flexible GMRES(restart) on M_1 g = rhs, right-preconditioned by MG, x0 = 0,
    until ||rhs - M_1 g|| <= tol ||rhs|| or maxit iterations (Sec. 4.3, Sec. 5).
    g: complex canonical output.  info[count] ([host]) receives per-problem

@@ -1683,6 +1683,66 @@ hps_status hps_precond_apply(hps_problem* const* pp, int32_t count, const double
   return HPS_OK;
 }
 
+hps_status hps_recover_field(hps_problem* const* pp, int32_t count, const double* const* b_nodes,
+                             const double* const* s_nodes, const double* const* t, const double* const* g,
+                             double* const* u) {
+  if (!pp || count <= 0 || !b_nodes || !t || !g || !u) return HPS_ERR_ARG;
+  int base = 0;
+  for (int i = 0; i < count; ++i) {
+    hps_problem* p = pp[i];
+    hps_status s = check_ready(p, false);
+    if (s != HPS_OK) return s;
+    const Layout& lay = p->lay;
+    for (int q = 0; q < lay.nq; ++q)
+      if (!b_nodes[base + q] || !t[base + q] || !g[base + q] || !u[base + q])
+        return fail(p->ctx, HPS_ERR_ARG, "null b_nodes, t, g or u");
+    const int N = lay.N, N1 = N + 1;
+    FieldArgs a{};
+    a.n = lay.n;
+    a.N = N;
+    a.E = lay.E;
+    a.h = 1.0 / lay.n;
+    const double* tab = at<double>(p, lay.tables_off);
+    a.D = tab;
+    a.w = tab + N1 * N1;
+    a.Kr = tab + N1 * N1 + N1;
+    a.scratch = at<double>(p, lay.scratch_off);
+    a.flag = at<int>(p, lay.flag_off);
+    // Lagrange weights of the degree-(N-2) polynomial through the inner GLL
+    // nodes, evaluated at -1 and +1 (the corner extrapolation)
+    const GllTables gt = gll_tables(N);
+    for (int k = 1; k < N; ++k) {
+      double wl = 1.0, wr = 1.0;
+      for (int j = 1; j < N; ++j) {
+        if (j == k) continue;
+        wl *= (-1.0 - gt.xi[j]) / (gt.xi[k] - gt.xi[j]);
+        wr *= (1.0 - gt.xi[j]) / (gt.xi[k] - gt.xi[j]);
+      }
+      a.xl[k - 1] = wl;
+      a.xr[k - 1] = wr;
+    }
+    const int per = (int)std::min<size_t>(1024, lay.scratch_bytes / (sizeof(double) * field_scratch_doubles(N, 1)));
+    if (per < 1) return fail(p->ctx, HPS_ERR_OOM, "workspace scratch too small for the field recovery");
+    for (int q0 = 0; q0 < lay.nq; q0 += kFieldMaxQ) {
+      const int nq = std::min(kFieldMaxQ, lay.nq - q0);
+      for (int k = 0; k < nq; ++k) {
+        const int qq = base + q0 + k;
+        a.b_nodes[k] = b_nodes[qq];
+        a.s_nodes[k] = s_nodes ? s_nodes[qq] : nullptr;
+        a.t[k] = reinterpret_cast<const cd*>(t[qq]);
+        a.g[k] = reinterpret_cast<const cd*>(g[qq]);
+        a.u[k] = reinterpret_cast<cd*>(u[qq]);
+        a.kappa[k] = p->kappa[q0 + k];
+        a.eta[k] = p->eta[q0 + k];
+      }
+      a.count = nq * lay.E;
+      HIPCHK(p->ctx, field_recover(a, per, p->ctx->stream));
+    }
+    base += lay.nq;
+  }
+  return HPS_OK;
+}
+
 hps_status hps_gmres_solve(hps_problem* const* pp, int32_t count, const double* const* rhs, double* const* g,
                            double tol, int32_t maxit, hps_info* info) {
   if (!pp || count <= 0 || !rhs || !g || !info || !(tol > 0) || maxit < 0) return HPS_ERR_ARG;

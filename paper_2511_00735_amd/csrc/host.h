@@ -40,6 +40,28 @@ struct LeafArgs {
 // Leaf maps of elements G0 .. G0+count-1: the leaf kernel, then the complex
 // fallback for the elements it lists.
 hipError_t leaf_build(const LeafArgs& a, hipStream_t st);
+// Field recovery (Sec. 3.1) for elements G in [0, count) of a group of
+// problems (q = G / E): u [q][E][(N+1)^2] complex at all nodes from the
+// skeleton solution g and boundary data t (canonical vectors per problem).
+constexpr int kFieldMaxQ = 64;  // problems of one launch
+struct FieldArgs {
+  int n, N, E, count;
+  double h;
+  const double* b_nodes[kFieldMaxQ];
+  const double* s_nodes[kFieldMaxQ];
+  const cd* g[kFieldMaxQ];
+  const cd* t[kFieldMaxQ];
+  cd* u[kFieldMaxQ];
+  double kappa[kFieldMaxQ], eta[kFieldMaxQ];
+  const double* D;
+  const double* w;
+  const double* Kr;
+  double xl[16], xr[16];       // corner extrapolation weights at xi = -1, +1
+  double* scratch;             // field_scratch_doubles(N, blocks)
+  int* flag;
+};
+size_t field_scratch_doubles(int N, int blocks);
+hipError_t field_recover(const FieldArgs& a, int blocks, hipStream_t st);
 // Clears a problem's device error words (no failure recorded).
 hipError_t flag_reset(int* flag, hipStream_t st);
 // Scratch doubles of one launch of `count` elements (the leaf kernel's

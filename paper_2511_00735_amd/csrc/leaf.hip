@@ -732,6 +732,88 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_kernel(LeafArgs a) {
   leaf_cayley(a, d, A, lds);
 }
 
+__global__ void fb_reset_kernel(int* list) { list[0] = 0; }
+
+__global__ void flag_reset_kernel(int* flag) {
+  const int i = threadIdx.x;
+  if (i < kFlagWords) flag[i] = (i >= 2 && i < 6) ? -1 : 0;
+}
+
+// The complex element matrix L of Sec. 3.1 into columns [0, nloc) of S
+// (column-major, ld nloc, rows and columns in ElemK's order): K's nonzeros one
+// by one (each entry once), i eta on the diagonal of the boundary rows.
+// Columns [nloc, ncols) are zeroed for the caller's right-hand sides; the
+// load's real and imaginary parts (K's columns nloc, nloc + 1) go to column
+// `load_col` when it is >= 0.  Ends with a barrier.
+__device__ void element_assemble(cd* S, const ElemK& K, const Dims& d, double eta, int ncols, int load_col) {
+  const int nloc = d.nloc, tid = threadIdx.x;
+  for (int idx = tid; idx < nloc * ncols; idx += kThreads) S[idx] = cmk(0.0, 0.0);
+  __syncthreads();
+  for (int it = tid; it < K.items(); it += kThreads) {
+    int r = 0, c = 0;
+    double v = 0.0;
+    if (!K.item(it, r, c, v)) continue;
+    if (c < nloc) S[(size_t)c * nloc + r].x = v;
+    else if (load_col >= 0) {
+      if (c == nloc) S[(size_t)load_col * nloc + r].x = v;
+      else S[(size_t)load_col * nloc + r].y = v;
+    }
+  }
+  __syncthreads();
+  for (int r = d.pp + tid; r < nloc; r += kThreads) S[(size_t)r * nloc + r].y = eta;
+  __syncthreads();
+}
+
+// Solves L X = B in place: S = [L | B] (nloc x (nloc + nrhs), column-major,
+// ld nloc); LU with partial pivoting over all rows, the right-hand sides
+// carried along, then back substitution.  On return columns [nloc, nloc +
+// nrhs) hold X.  A zero pivot is recorded as flag_where(0, elem).  Ends with
+// a barrier.
+__device__ void element_lu_solve(cd* S, int nloc, int nrhs, int* flag, long long elem) {
+  __shared__ unsigned long long kw[kWaves];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int ncols = nloc + nrhs;
+#define AT(r, c) S[(size_t)(c) * nloc + (r)]
+  for (int k = 0; k < nloc; ++k) {
+    unsigned long long key = 0;
+    for (int r = k + tid; r < nloc; r += kThreads) key = max(key, pivot_key(cabs2(AT(r, k)), r));
+    key = wave_max_key(key);
+    if (lane == 0) kw[wave] = key;
+    __syncthreads();
+    unsigned long long kk = kw[0];
+    for (int w = 1; w < kWaves; ++w) kk = max(kk, kw[w]);
+    const int pr = min(max(pivot_row(kk), k), nloc - 1);
+    if (tid == 0 && (kk >> 32) <= 1u) flag_singular(flag, flag_where(0, elem));
+    if (pr != k)
+      for (int c = k + tid; c < ncols; c += kThreads) {
+        const cd t = AT(k, c);
+        AT(k, c) = AT(pr, c);
+        AT(pr, c) = t;
+      }
+    __syncthreads();
+    const cd inv = cinv(AT(k, k));
+    for (int r = k + 1 + tid; r < nloc; r += kThreads) AT(r, k) = cmul(AT(r, k), inv);
+    __syncthreads();
+    const int nr = nloc - k - 1, nc = ncols - k - 1;
+    for (int idx = tid; idx < nr * nc; idx += kThreads) {
+      const int r = k + 1 + idx % nr, c = k + 1 + idx / nr;
+      AT(r, c) = csub(AT(r, c), cmul(AT(r, k), AT(k, c)));
+    }
+    __syncthreads();
+  }
+  for (int k = nloc - 1; k >= 0; --k) {
+    const cd inv = cinv(AT(k, k));
+    for (int j = tid; j < nrhs; j += kThreads) AT(k, nloc + j) = cmul(AT(k, nloc + j), inv);
+    __syncthreads();
+    for (int idx = tid; idx < k * nrhs; idx += kThreads) {
+      const int i = idx % k, j = idx / k;
+      AT(i, nloc + j) = csub(AT(i, nloc + j), cmul(AT(i, k), AT(k, nloc + j)));
+    }
+    __syncthreads();
+  }
+#undef AT
+}
+
 // ---- fallback: the element system of Sec. 3.1 solved as it stands ----------
 // For the elements the leaf kernel lists (interior block nearly singular), the
 // complex n_loc x n_loc element matrix L (interior rows of the local operator,
@@ -745,24 +827,15 @@ __host__ __device__ inline size_t fb_stride(const Dims& d) {
   return ((size_t)2 * d.nloc * (d.nloc + 4 * d.p + 1) + 31) & ~(size_t)31;
 }
 
-__global__ void fb_reset_kernel(int* list) { list[0] = 0; }
-
-__global__ void flag_reset_kernel(int* flag) {
-  const int i = threadIdx.x;
-  if (i < kFlagWords) flag[i] = (i >= 2 && i < 6) ? -1 : 0;
-}
-
 __global__ __launch_bounds__(kThreads) void leaf_fallback_kernel(LeafArgs a) {
-  __shared__ unsigned long long kw[kWaves];
   const Dims d = dims_of(a.N);
-  const int nloc = d.nloc, npiv = d.pp, m = 4 * d.p, nrhs = m + 1, ncols = nloc + nrhs;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nloc = d.nloc, npiv = d.pp, m = 4 * d.p, nrhs = m + 1;
+  const int tid = threadIdx.x;
   const int N1 = a.N + 1;
   // uniform values (scalar registers): the per-problem kernel arguments are
   // then indexed in place
   const int listed = __builtin_amdgcn_readfirstlane(a.fb_list[0]);
   cd* S = reinterpret_cast<cd*>(a.scratch + (size_t)blockIdx.x * fb_stride(d));
-#define AT(r, c) S[(size_t)(c) * nloc + (r)]
   for (int it = blockIdx.x; it < listed; it += gridDim.x) {
     const int G = __builtin_amdgcn_readfirstlane(a.fb_list[1 + it]);
     const int q = G / a.E, e = G % a.E;
@@ -770,62 +843,11 @@ __global__ __launch_bounds__(kThreads) void leaf_fallback_kernel(LeafArgs a) {
     const double* sq = a.s_nodes[q - a.q0];
     const ElemK K{d.N, d.p, d.pp, nloc, a.D, a.w, a.Kr, a.b_nodes[q - a.q0] + (size_t)e * N1 * N1,
                   sq ? sq + (size_t)e * 2 * N1 * N1 : nullptr, a.kappa[q - a.q0], a.h};
-    // [L | E_G^T | bt]: zeros, the identity columns, then K's nonzeros one by
-    // one (each entry once; the load's real and imaginary parts separately),
-    // then i eta on the diagonal of the boundary rows
-    for (int idx = tid; idx < nloc * ncols; idx += kThreads) {
-      const int r = idx % nloc, c = idx / nloc;
-      AT(r, c) = cmk((c >= nloc && c < nloc + m && r == npiv + (c - nloc)) ? 1.0 : 0.0, 0.0);
-    }
+    // [L | E_G^T | bt]
+    element_assemble(S, K, d, eta, nloc + nrhs, nloc + m);
+    for (int j = tid; j < m; j += kThreads) S[(size_t)(nloc + j) * nloc + npiv + j] = cmk(1.0, 0.0);
     __syncthreads();
-    for (int it = tid; it < K.items(); it += kThreads) {
-      int r = 0, c = 0;
-      double v = 0.0;
-      if (!K.item(it, r, c, v)) continue;
-      if (c < nloc) AT(r, c).x = v;
-      else if (c == nloc) AT(r, nloc + m).x = v;
-      else AT(r, nloc + m).y = v;
-    }
-    __syncthreads();
-    for (int r = npiv + tid; r < nloc; r += kThreads) AT(r, r).y = eta;
-    __syncthreads();
-    for (int k = 0; k < nloc; ++k) {
-      unsigned long long key = 0;
-      for (int r = k + tid; r < nloc; r += kThreads) key = max(key, pivot_key(cabs2(AT(r, k)), r));
-      key = wave_max_key(key);
-      if (lane == 0) kw[wave] = key;
-      __syncthreads();
-      unsigned long long kk = kw[0];
-      for (int w = 1; w < kWaves; ++w) kk = max(kk, kw[w]);
-      const int pr = min(max(pivot_row(kk), k), nloc - 1);
-      if (tid == 0 && (kk >> 32) <= 1u) flag_singular(a.flag, flag_where(0, G));
-      if (pr != k)
-        for (int c = k + tid; c < ncols; c += kThreads) {
-          const cd t = AT(k, c);
-          AT(k, c) = AT(pr, c);
-          AT(pr, c) = t;
-        }
-      __syncthreads();
-      const cd inv = cinv(AT(k, k));
-      for (int r = k + 1 + tid; r < nloc; r += kThreads) AT(r, k) = cmul(AT(r, k), inv);
-      __syncthreads();
-      const int nr = nloc - k - 1, nc = ncols - k - 1;
-      for (int idx = tid; idx < nr * nc; idx += kThreads) {
-        const int r = k + 1 + idx % nr, c = k + 1 + idx / nr;
-        AT(r, c) = csub(AT(r, c), cmul(AT(r, k), AT(k, c)));
-      }
-      __syncthreads();
-    }
-    for (int k = nloc - 1; k >= 0; --k) {
-      const cd inv = cinv(AT(k, k));
-      for (int j = tid; j < nrhs; j += kThreads) AT(k, nloc + j) = cmul(AT(k, nloc + j), inv);
-      __syncthreads();
-      for (int idx = tid; idx < k * nrhs; idx += kThreads) {
-        const int i = idx % k, j = idx / k;
-        AT(i, nloc + j) = csub(AT(i, nloc + j), cmul(AT(i, k), AT(k, nloc + j)));
-      }
-      __syncthreads();
-    }
+    element_lu_solve(S, nloc, nrhs, a.flag, G);
     // T = I_o X on the boundary columns, H = I_o x on the load column; row i
     // of N_G has p + 2 entries (K's items of boundary row i)
     const int ix = e % a.n, iy = e / a.n;
@@ -838,9 +860,9 @@ __global__ __launch_bounds__(kThreads) void leaf_fallback_kernel(LeafArgs a) {
         int r = 0, c = 0;
         double v = 0.0;
         K.item(nb0 + t * m + i, r, c, v);
-        acc = cadd(acc, cscale(AT(c, nloc + j), v));
+        acc = cadd(acc, cscale(S[(size_t)(nloc + j) * nloc + c], v));
       }
-      const cd xg = AT(npiv + i, nloc + j);
+      const cd xg = S[(size_t)(nloc + j) * nloc + npiv + i];
       const cd tv = cmk(-acc.x - eta * xg.y, -acc.y + eta * xg.x);
       if (j < m) Tout[(size_t)j * m + i] = tv;
       else a.H[(size_t)G * m + i] = tv;
@@ -848,9 +870,90 @@ __global__ __launch_bounds__(kThreads) void leaf_fallback_kernel(LeafArgs a) {
     __syncthreads();
   }
 }
-#undef AT
+
+// ---- field recovery (Sec. 3.1): u = L^-1 [bt; f] per element ---------------
+// f: the element's incoming impedances (g on interior sides, t on physical
+// sides).  u at the non-corner nodes from the element solve; each corner the
+// mean of the two extrapolations along its sides (weights xl at xi = -1, xr at
+// xi = +1 of the degree-(N-2) polynomial through the side's inner nodes).
+__host__ __device__ inline size_t field_stride(const Dims& d) {
+  return ((size_t)2 * d.nloc * (d.nloc + 1) + 31) & ~(size_t)31;
+}
+
+__global__ __launch_bounds__(kThreads) void field_kernel(FieldArgs a) {
+  const Dims d = dims_of(a.N);
+  const int nloc = d.nloc, npiv = d.pp, p = d.p, N = a.N, N1 = N + 1;
+  const int tid = threadIdx.x;
+  cd* S = reinterpret_cast<cd*>(a.scratch + (size_t)blockIdx.x * field_stride(d));
+  __shared__ cd uc[4][2];   // corner extrapolations: [corner][along y, along x]
+  for (int G = blockIdx.x; G < a.count; G += gridDim.x) {
+    const int q = G / a.E, e = G % a.E;
+    const int ix = e % a.n, iy = e / a.n;
+    const double eta = a.eta[q];
+    const double* sq = a.s_nodes[q];
+    const ElemK K{d.N, d.p, d.pp, nloc, a.D, a.w, a.Kr, a.b_nodes[q] + (size_t)e * N1 * N1,
+                  sq ? sq + (size_t)e * 2 * N1 * N1 : nullptr, a.kappa[q], a.h};
+    element_assemble(S, K, d, eta, nloc + 1, nloc);
+    // boundary rows: the incoming impedances of the element's four sides
+    const cd* g = a.g[q];
+    const cd* t = a.t[q];
+    for (int k = tid; k < 4 * p; k += kThreads) {
+      const int side = k / p;
+      const bool phys = (side == 0 && ix == 0) || (side == 1 && ix == a.n - 1) || (side == 2 && iy == 0) ||
+                        (side == 3 && iy == a.n - 1);
+      const size_t slot = (size_t)e * 4 * p + k;
+      S[(size_t)nloc * nloc + npiv + k] = phys ? t[slot] : g[slot];
+    }
+    __syncthreads();
+    element_lu_solve(S, nloc, 1, a.flag, G);
+    const cd* x = S + (size_t)nloc * nloc;
+    cd* u = a.u[q] + (size_t)e * N1 * N1;
+    // interior nodes (i, j) = row (i-1) p + (j-1); side nodes after them
+    for (int r = tid; r < nloc; r += kThreads) {
+      int node;
+      if (r < npiv) {
+        node = (r / p + 1) * N1 + (r % p + 1);
+      } else {
+        const int side = (r - npiv) / p, k = (r - npiv) % p + 1;
+        node = side == 0 ? k : (side == 1 ? N * N1 + k : (side == 2 ? k * N1 : k * N1 + N));
+      }
+      u[node] = x[r];
+    }
+    // corners (0,0), (0,N), (N,0), (N,N): extrapolate along the side in y
+    // (nodes (i, k)) and along the side in x (nodes (k, j))
+    if (tid < 8) {
+      const int corner = tid >> 1, dir = tid & 1;
+      const int ci = (corner & 2) ? N : 0, cj = (corner & 1) ? N : 0;
+      const double* wgt = dir == 0 ? (cj ? a.xr : a.xl) : (ci ? a.xr : a.xl);
+      cd acc = cmk(0.0, 0.0);
+      for (int k = 1; k < N; ++k) {
+        // row of the side node in the solve's order
+        int r;
+        if (dir == 0) r = npiv + (ci ? p : 0) + (k - 1);        // side l (i = 0) or r (i = N), node j = k
+        else r = npiv + (cj ? 3 * p : 2 * p) + (k - 1);          // side b (j = 0) or t (j = N), node i = k
+        acc = cadd(acc, cscale(x[r], wgt[k - 1]));
+      }
+      uc[corner][dir] = acc;
+    }
+    __syncthreads();
+    if (tid < 4) {
+      const int ci = (tid & 2) ? N : 0, cj = (tid & 1) ? N : 0;
+      u[ci * N1 + cj] = cscale(cadd(uc[tid][0], uc[tid][1]), 0.5);
+    }
+    __syncthreads();
+  }
+}
 
 }  // namespace
+
+size_t field_scratch_doubles(int N, int blocks) { return (size_t)blocks * field_stride(dims_of(N)); }
+
+hipError_t field_recover(const FieldArgs& a, int blocks, hipStream_t st) {
+  const Dims d = dims_of(a.N);
+  if (d.nloc > 64 * kMaxChunks || blocks < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(field_kernel, dim3(std::min(blocks, a.count)), dim3(kThreads), 0, st, a);
+  return hipPeekAtLastError();
+}
 
 size_t leaf_scratch_doubles(int N, int count) {
   const Dims d = dims_of(N);

@@ -84,6 +84,7 @@ _SIGS = {
     "hps_set_rhs": ([_PP, ctypes.c_int32, _PP, _PP], ctypes.c_int),
     "hps_skeleton_apply": ([_PP, ctypes.c_int32, ctypes.c_int32, _PP, _PP], ctypes.c_int),
     "hps_precond_apply": ([_PP, ctypes.c_int32, _PP, _PP], ctypes.c_int),
+    "hps_recover_field": ([_PP, ctypes.c_int32, _PP, _PP, _PP, _PP, _PP], ctypes.c_int),
     "hps_gmres_solve": ([_PP, ctypes.c_int32, _PP, _PP, ctypes.c_double, ctypes.c_int32,
                          ctypes.POINTER(Info)], ctypes.c_int),
 }
@@ -290,6 +291,12 @@ class Problem:
         infos = gmres_solve([self], [rhs], [out], tol, maxit)
         return out, infos[0]
 
+    def recover_field(self, b_nodes, t, g, s_nodes=None):
+        """Nodal field u [E, (N+1)^2] of every element from the solution g."""
+        u = torch.empty((self.E, (self.N + 1) ** 2), dtype=torch.complex128, device="cuda")
+        recover_field([self], [b_nodes], None if s_nodes is None else [s_nodes], [t], [g], [u])
+        return u
+
     # ---- inspection -------------------------------------------------------
     def level_view(self, level):
         v = LevelView()
@@ -449,6 +456,15 @@ def precond_apply(problems, r, z):
     problems[0].ctx.check(lib.hps_precond_apply(_handles(problems), len(problems),
                                                 _ptrs([_dptr(x) for x in r]),
                                                 _ptrs([_dptr(x) for x in z])), "hps_precond_apply")
+
+
+def recover_field(problems, b_nodes, s_nodes, t, g, u):
+    _nprob(problems, b_nodes, s_nodes, t, g, u)
+    s = _ptrs([_dptr(x) for x in s_nodes]) if s_nodes is not None else None
+    problems[0].ctx.check(lib.hps_recover_field(_handles(problems), len(problems),
+                                                _ptrs([_dptr(x) for x in b_nodes]), s,
+                                                _ptrs([_dptr(x) for x in t]), _ptrs([_dptr(x) for x in g]),
+                                                _ptrs([_dptr(x) for x in u])), "hps_recover_field")
 
 
 def gmres_solve(problems, rhs, g, tol=1e-10, maxit=600):
