@@ -272,6 +272,30 @@ hps_status hps_gmres_solve(hps_problem* const* p, int32_t count,
                            const double* const* rhs, double* const* g,
                            double tol, int32_t maxit, hps_info* info);
 
+/* ---- leaf maps without device allocation --------------------------------- */
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc): the leaf
+   ItI maps T and loads H of `count` elements of side h (Sec. 3.1, eq.
+   ItIOperator; the same kernels as hps_build_leaves), with every buffer the
+   kernels need beyond the inputs and outputs -- error words, the fallback
+   list, GLL tables, per-element scratch -- in one 64 MiB file-scope device
+   array that each GPU the library runs on holds until the process ends.  No
+   hipMalloc, hipFree or allocating library call is made.
+   b_nodes: real [count][(N+1)^2] (the coefficient b at the element nodes,
+   flat index i*(N+1)+j); s_nodes: complex [count][(N+1)^2] or NULL (H = 0);
+   T: complex [count][4(N-1)][4(N-1)] column-major, element after element (no
+   Morton placement); H: complex [count][4(N-1)].  All device pointers, on
+   the context's stream; synchronises.  count is limited by the array: at most
+   102 elements at N = 16, 304 at N = 12, 1372 at N = 8, 4096 for N <= 5
+   (HPS_ERR_ARG beyond, its message giving the limit).  Errors as for
+   hps_build_leaves (HPS_ERR_ARG for a NaN or Inf input, HPS_ERR_SINGULAR),
+   naming the element.  Every call on a GPU shares that GPU's array: calls
+   that overlap on one GPU (several streams or host threads) race and must be
+   serialised by the caller. */
+hps_status hps_leaf_maps_noalloc(hps_ctx* ctx, int32_t order, double h, double kappa, double eta,
+                                 int32_t count, const double* b_nodes, const double* s_nodes,
+                                 double* T, double* H);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1315,6 +1315,12 @@ hps_status for_each_problem(hps_problem* const* pp, int count, F f) {
 
 }  // namespace
 
+// Context access for the library's other sources.
+void hps_ctx_set_error(hps_ctx* ctx, const char* msg) {
+  if (ctx) ctx->err = msg;
+}
+void* hps_ctx_stream(hps_ctx* ctx) { return ctx ? static_cast<void*>(ctx->stream) : nullptr; }
+
 // ============================ C ABI ========================================
 extern "C" {
 

@@ -36,6 +36,7 @@ struct LeafArgs {
   int* flag;                  // the problem's error words (common.h)
   int* fb_list;               // [1 + count]: count, then elements G whose interior
                               // block is nearly singular (recomputed by the fallback)
+  int linear_out;             // 1: T of element G at T + G*(4p)^2 (no Morton placement)
 };
 // Leaf maps of elements G0 .. G0+count-1: the leaf kernel, then the complex
 // fallback for the elements it lists.

@@ -338,7 +338,7 @@ __device__ void leaf_cayley(const LeafArgs& a, const Dims& d, const double* A, d
     __syncthreads();
   }
   const int ix = e % a.n, iy = e / a.n;
-  cd* Tout = a.T + ((size_t)q * a.E + morton_xy(ix, iy)) * m * m;
+  cd* Tout = a.T + (a.linear_out ? (size_t)G : ((size_t)q * a.E + morton_xy(ix, iy))) * m * m;
   const double te = 2.0 * eta;
   cd hacc = cmk(0.0, 0.0);
 #pragma unroll
@@ -851,7 +851,7 @@ __global__ __launch_bounds__(kThreads) void leaf_fallback_kernel(LeafArgs a) {
     // T = I_o X on the boundary columns, H = I_o x on the load column; row i
     // of N_G has p + 2 entries (K's items of boundary row i)
     const int ix = e % a.n, iy = e / a.n;
-    cd* Tout = a.T + ((size_t)q * a.E + morton_xy(ix, iy)) * m * m;
+    cd* Tout = a.T + (a.linear_out ? (size_t)G : ((size_t)q * a.E + morton_xy(ix, iy))) * m * m;
     const int nb0 = npiv * (2 * d.p + 5);   // first item of the boundary rows
     for (int idx = tid; idx < m * nrhs; idx += kThreads) {
       const int i = idx % m, j = idx / m;

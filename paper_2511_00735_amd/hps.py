@@ -77,6 +77,8 @@ _SIGS = {
     "hps_group_create": ([_P, ctypes.POINTER(Desc), ctypes.c_int32, _P, _P, _P, ctypes.c_size_t,
                           ctypes.POINTER(_P)], ctypes.c_int),
     "hps_group_size": ([_P], ctypes.c_int32),
+    "hps_leaf_maps_noalloc": ([_P, ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                               ctypes.c_int32, _P, _P, _P, _P], ctypes.c_int),
     "hps_choose_levels": ([ctypes.POINTER(Desc), ctypes.c_int32, ctypes.c_size_t, ctypes.POINTER(ctypes.c_int32)],
                           ctypes.c_int),
     "hps_build_leaves": ([_PP, ctypes.c_int32, _PP, _PP], ctypes.c_int),
@@ -130,6 +132,15 @@ def workspace_bytes(desc):
     if rc != HPS_OK:
         raise HPSError(rc, "invalid descriptor")
     return out.value
+
+
+def leaf_maps_noalloc(ctx, order, h, kappa, eta, b_nodes, s_nodes, T, H):
+    """Leaf maps of b_nodes.shape[0] elements into T ([E][4p][4p] column-major)
+    and H ([E][4p]) with no device allocation (the library's static scratch)."""
+    count = b_nodes.shape[0]
+    ctx.check(lib.hps_leaf_maps_noalloc(ctx.handle, order, float(h), float(kappa), float(eta), count,
+                                        _dptr(b_nodes), _dptr(s_nodes), _dptr(T), _dptr(H)),
+              "hps_leaf_maps_noalloc")
 
 
 def choose_levels(desc, budget, count=1):
