@@ -74,6 +74,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="one 1 GiB device copy, then one leaf build (for rocprofv3 --pmc runs)")
+    ap.add_argument("--solve-probe", action="store_true",
+                    help="one 1 GiB device copy, then a built workload and 4 V-cycles and 4 M_1 "
+                         "products (for rocprofv3 --pmc runs)")
     ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="length of the request trace served beside the headline (0: skip)")
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-problem batch")
@@ -353,6 +356,50 @@ def run_table1_sweep(hps, torch, precision="fp64"):
             "best": {**best, "dof_per_s": round(pr.skeleton_dof / (1e-3 * (best["build_ms"] + best["solve_ms"])), 1)}}
 
 
+def run_repeated_solves(hps, torch, pr, precision="mixed", nrhs=16):
+    """Many solves with one built operator (the paper notes that the best
+    setting depends on how many solves share a build): the workload's
+    operator is built once, then `nrhs` right-hand sides (plane waves of
+    different directions) are solved to 1e-8.  Reports the build time, the
+    mean solve time and the skeleton DOF/s amortised over all solves."""
+    ctx = hps.Context()
+    prec = hps.HPS_MIXED if precision == "mixed" else hps.HPS_FP64
+    desc = hps.make_desc(pr.n, pr.N, pr.kappa, pr.eta, levels=pr.levels, coarse_iters=pr.coarse_iters,
+                         precision=prec)
+    prob = hps.Problem(ctx, desc)
+    b_nodes = prob.coefficient_nodes(pr.b)
+    ts = [prob.boundary_data(workloads_plane(pr, 2 * math.pi * k / nrhs).t) for k in range(nrhs)]
+    rhs = torch.empty(prob.nslots, dtype=torch.complex128, device="cuda")
+    g = torch.empty_like(rhs)
+    for _ in range(2):        # warm-up of both phases
+        prob.build_leaves(b_nodes)
+        prob.merge_all()
+        hps.set_rhs([prob], [ts[0]], [rhs])
+        prob.gmres_solve(rhs, tol=pr.tol, maxit=600, out=g)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    prob.build_leaves(b_nodes)
+    prob.merge_all()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    its = []
+    for t in ts:
+        hps.set_rhs([prob], [t], [rhs])
+        its.append(prob.gmres_solve(rhs, tol=pr.tol, maxit=600, out=g)[1]["iterations"])
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    build, solve = t1 - t0, (t2 - t1) / nrhs
+    return {"precision": precision, "solves": nrhs, "build_ms": round(1e3 * build, 3),
+            "mean_solve_ms": round(1e3 * solve, 3), "iterations": its,
+            "amortised_dof_per_s": round(pr.skeleton_dof * nrhs / (t2 - t0), 1),
+            "single_solve_dof_per_s": round(pr.skeleton_dof / (build + solve), 1)}
+
+
+def workloads_plane(pr, theta):
+    from paper_2511_00735_amd import workloads
+    return workloads.PlaneWave(pr.kappa, pr.eta, (math.cos(theta), math.sin(theta)))
+
+
 def run_serving(hps, torch, seconds):
     """The first `seconds` of the seeded Poisson request trace (50 req/s, 10%
     128x128 N=16 kappa=400), served in real time, mixed vs FP64."""
@@ -388,6 +435,33 @@ def main():
     pr.levels, pr.coarse_iters, pr.tol = args.levels, args.coarse_iters, args.tol
     pr.wave = workloads.PlaneWave(pr.kappa, pr.eta)
     dof = pr.skeleton_dof
+
+    if args.solve_probe:
+        nbytes = 1 << 30
+        a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        ctx = hps.Context()
+        prec = hps.HPS_MIXED if args.precision == "mixed" else hps.HPS_FP64
+        prob = hps.Problem(ctx, hps.make_desc(pr.n, pr.N, pr.kappa, pr.eta, levels=pr.levels,
+                                              coarse_iters=pr.coarse_iters, precision=prec))
+        prob.build_leaves(prob.coefficient_nodes(pr.b))
+        prob.merge_all()
+        rhs = prob.set_rhs(prob.boundary_data(pr.wave.t))
+        z = torch.empty_like(rhs)
+        w = torch.empty_like(rhs)
+        ctx.sync()
+        for _ in range(4):
+            prob.precond_apply(rhs, out=z)
+        for _ in range(4):
+            prob.skeleton_apply(z, out=w)
+        ctx.sync()
+        print(json.dumps({"probe": "solve", "copy_bytes_read": nbytes, "copy_bytes_written": nbytes,
+                          "vcycles": 4, "m1_products": 4}), flush=True)
+        return
 
     if args.traffic_probe:
         nbytes = 1 << 30
@@ -472,6 +546,9 @@ def main():
     if not args.no_sweep:
         cfg["table1_sweep"] = run_table1_sweep(hps, torch)
         progress("Table 1 sweep done")
+        cfg["repeated_solves"] = {"mixed": run_repeated_solves(hps, torch, pr, "mixed"),
+                                  "fp64": run_repeated_solves(hps, torch, pr, "fp64")}
+        progress("repeated solves done")
     if not args.no_batch:
         cfg["batch_256_problems"] = run_batch_c4(hps, torch)
         progress("256-problem batch done")

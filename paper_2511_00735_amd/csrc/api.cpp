@@ -364,6 +364,9 @@ struct hps_problem {
   bool have_T1;
   hipGraphExec_t pgraph = nullptr;  // captured V-cycle (work vector 5 -> 6)
   bool graph_failed = false;
+  // levels whose merge inverse uses partial pivoting (set when the inverse
+  // without row interchanges failed its threshold test; kept for later builds)
+  std::vector<char> pivot_level;
   // build and solve times (hps_info): events on the context's stream at the
   // start of the leaf build, after its latest build step, and around a solve
   hipEvent_t ev_build0 = nullptr, ev_build1 = nullptr, ev_solve0 = nullptr, ev_solve1 = nullptr;
@@ -484,7 +487,7 @@ hps_status merge_impl(hps_problem* p, int l, const T* Tin, T* Tout) {
     }
     HIPCHK(c, zgemm_group(grp, ng, st));
   }
-  HIPCHK(c, zinverse<T>(A11, m, m2, as, np, invs, flag, l, st));
+  HIPCHK(c, zinverse<T>(A11, m, m2, as, np, invs, flag, l, p->pivot_level[l] != 0, st));
   ng = 0;
   {
     GemmArgs g = gemm(m, m, m);
@@ -1016,6 +1019,29 @@ hps_status read_flag(hps_problem* p, int first = 0) {
   return HPS_OK;
 }
 
+// The blocked merge inverses run without row interchanges across blocks
+// under a threshold test (inverse.hip); a level that failed it is recorded in
+// error word 6.  This switches that level to partial pivoting and redoes the
+// merges from it up to the last one done, until no level fails (at most L
+// rounds).  Synchronises.
+hps_status stabilize_merges(hps_problem* p) {
+  static const int kNone = 0x7FFFFFFF;
+  int* w6 = at<int>(p, p->lay.flag_off) + 6;
+  for (int round = 0; round <= p->lay.L; ++round) {
+    int lv = kNone;
+    HIPCHK(p->ctx, hipMemcpyAsync(&lv, w6, sizeof(int), hipMemcpyDeviceToHost, p->ctx->stream));
+    HIPCHK(p->ctx, hipStreamSynchronize(p->ctx->stream));
+    if (lv == kNone || lv < 1 || lv > p->merged) return HPS_OK;
+    p->pivot_level[lv] = 1;
+    HIPCHK(p->ctx, hipMemcpyAsync(w6, &kNone, sizeof(int), hipMemcpyHostToDevice, p->ctx->stream));
+    for (int l = lv; l <= p->merged; ++l) {
+      const hps_status s = merge_one(p, l);
+      if (s != HPS_OK) return s;
+    }
+  }
+  return fail(p->ctx, HPS_ERR_STATE, "merge inverses did not stabilise");
+}
+
 // ---- outer flexible GMRES ------------------------------------------------
 typedef std::complex<double> zc;
 
@@ -1228,6 +1254,7 @@ hps_status group_create(hps_ctx* ctx, const hps_desc* desc, int count, const dou
   p->state = kCreated;
   p->merged = 0;
   p->have_T1 = false;
+  p->pivot_level.assign(lay.L + 2, 0);
   for (hipEvent_t* ev : {&p->ev_build0, &p->ev_build1, &p->ev_solve0, &p->ev_solve1}) {
     const hipError_t e = hipEventCreate(ev);
     if (e != hipSuccess) {
@@ -1273,7 +1300,7 @@ hps_status group_create(hps_ctx* ctx, const hps_desc* desc, int count, const dou
   const cd one = cmk(1, 0);
   HIPCHK(ctx, hipMemcpyAsync(p->ws + lay.one_off, &one, sizeof(cd), hipMemcpyHostToDevice, ctx->stream));
   // error words: no flags, no first failure (records keep a minimum)
-  const int words[kFlagWords] = {0, 0, -1, -1, -1, -1, 0, 0};
+  const int words[kFlagWords] = {0, 0, -1, -1, -1, -1, 0x7FFFFFFF, 0};
   HIPCHK(ctx, hipMemcpyAsync(p->ws + lay.flag_off, words, sizeof(words), hipMemcpyHostToDevice, ctx->stream));
   // Box maps of merged levels: entries on physical sides are never computed;
   // they are kept at zero so that products with zero data stay zero.
@@ -1395,7 +1422,8 @@ hps_status hps_sync(hps_ctx* ctx) {
   if (!ctx) return HPS_ERR_ARG;
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
   for (hps_problem* p : ctx->problems) {
-    const hps_status s = read_flag(p);
+    hps_status s = p->state >= kLeaves ? stabilize_merges(p) : HPS_OK;
+    if (s == HPS_OK) s = read_flag(p);
     if (s != HPS_OK) return s;
   }
   return HPS_OK;
@@ -1668,6 +1696,8 @@ hps_status hps_precond_apply(hps_problem* const* pp, int32_t count, const double
     hps_problem* p = pp[i];
     hps_status s = check_ready(p, true);
     if (s != HPS_OK) return s;
+    s = stabilize_merges(p);
+    if (s != HPS_OK) return s;
     const long long n = p->lay.nslots;
     const int nq = p->lay.nq;
     for (int q = 0; q < nq; ++q)
@@ -1764,6 +1794,8 @@ hps_status hps_gmres_solve(hps_problem* const* pp, int32_t count, const double* 
       if (!rhs[base + q] || !g[base + q]) return fail(p->ctx, HPS_ERR_ARG, "null vector");
     // a failure recorded by the build (zero pivot, non-finite input) ends the
     // call before any iteration
+    s = stabilize_merges(p);
+    if (s != HPS_OK) return s;
     s = read_flag(p, base);
     if (s != HPS_OK) return s;
     HIPCHK(p->ctx, hipEventRecord(p->ev_solve0, p->ctx->stream));

@@ -184,7 +184,9 @@ inline hipError_t allow_lds(K kernel, size_t bytes) {
 //   words 2-3: the first zero pivot as (level << 40) | batch index, kept as the
 //           minimum (level 0: the leaf build, index = element of the group;
 //           level l >= 1: merge l, index = pair of the group's level batch);
-//   words 4-5: the first element (index in the group) with a non-finite input.
+//   words 4-5: the first element (index in the group) with a non-finite input;
+//   word 6: the lowest merge level whose inverse without row interchanges
+//           failed its threshold test (0x7FFFFFFF: none).
 constexpr int kFlagWords = 8;
 constexpr int kFlagSingular = 2;
 constexpr int kFlagNonFinite = 4;

@@ -134,13 +134,18 @@ __host__ __device__ inline bool y_physical(const PhysSkip& s, int bx, int by, in
 
 // ---- batched complex inversion (inverse.hip) -------------------------------
 // In-place inverse of `batch` m x m column-major matrices (stride `bstride`),
-// Gauss-Jordan with partial pivoting.  scratch: see inverse_scratch_bytes.
-// A zero pivot of matrix b is recorded in the problem's error words as
-// flag_where(level, b).
+// Gauss-Jordan.  m <= 64 (and m <= 128 with `pivot`): partial pivoting, in
+// registers.  Larger m, blocked in 32-column steps: with `pivot`, partial
+// pivoting over all rows; without,
+// no row interchanges across blocks (the diagonal blocks inverted as they
+// stand) under a threshold test on the multipliers, whose failure records
+// `level` in flag[6] (the caller then redoes the inverse with pivoting).
+// scratch: see inverse_scratch_bytes.  A zero pivot of matrix b is recorded
+// in the problem's error words as flag_where(level, b).
 template <class T>
 size_t inverse_scratch_bytes(int m, int batch);
 template <class T>
 hipError_t zinverse(T* A, int m, int lda, long long bstride, int batch, void* scratch,
-                    int* flag, int level, hipStream_t st);
+                    int* flag, int level, bool pivot, hipStream_t st);
 
 }  // namespace hps

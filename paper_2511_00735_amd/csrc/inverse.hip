@@ -1,11 +1,16 @@
 // Batched in-place inversion of complex matrices (FP64 or FP32) by
-// Gauss-Jordan elimination with partial pivoting.
+// Gauss-Jordan elimination.
 //
-// m <= 128: the whole matrix sits in registers, one workgroup per matrix.
-// m  > 128: blocked Gauss-Jordan, two launches per block column C = [k0, k0+nb):
-//   1. gj_panel: partial-pivoting LU of the panel A[k0:m, C] in LDS picks nb
-//      pivot rows (as the row map of this step) and forms Dinv, the inverse of
-//      the pivot block, by an in-LDS Gauss-Jordan on those rows;
+// m <= 64 (and m <= 128 when partial pivoting is asked for): the whole matrix
+// sits in registers, one workgroup per matrix, partial pivoting.
+// Otherwise blocked Gauss-Jordan, two launches per block column C = [k0, k0+nb):
+//   1. without row interchanges across blocks (the default): gj_diag inverts
+//      the diagonal block as it stands (one wave, the step loop unrolled),
+//      under a threshold test on the multipliers that gj_update repeats for
+//      the rows outside the block; a level that fails it is redone by the
+//      host with partial pivoting.  With partial pivoting: gj_panel (in
+//      registers or LDS) picks nb pivot rows (as the row map of this step)
+//      and forms Dinv, the inverse of the pivot block;
 //   2. gj_update: one pass over the whole matrix, out of place (two buffers),
 //      rows read through the row map, P = C, X = Dinv A'[P, :]:
 //        rows in P:      out = X           (Dinv on the C columns)
@@ -13,7 +18,10 @@
 // The row interchanges of all steps compose to one map rho; the inverse of the
 // original matrix is the result with column j moved to column rho[j], which the
 // last update (or a final copy) applies.  Work: m^3 complex multiply-adds in
-// 2 m / nb launches.
+// 2 m / nb launches.  The merge blocks W = I - T^P_aa T^Q_bb of these
+// problems need no interchanges (partial pivoting keeps every diagonal pivot
+// and the elimination grows entries by about 3%), which is why the default
+// skips the pivot search that dominated each step.
 #include "common.h"
 #include "host.h"
 #include "pivot.h"
@@ -507,6 +515,88 @@ __global__ __launch_bounds__(1024) void gj_panel_reg_kernel(const T* A, int m, i
   if (live) Db[gj * kb + gi] = sv;
 }
 
+// Step 1 without row interchanges across blocks: the inverse of the diagonal
+// block A[k0 : k0+kb, k0 : k0+kb] of matrix blockIdx.x by Gauss-Jordan without
+// pivoting, one wave per matrix (lane = row i + 32 h, columns j = 2t + h), so
+// a step needs no workgroup barrier.  The row maps of this step are the
+// identity.  The elimination is accepted only while every multiplier of a
+// row below the pivot stays within 1/kNoPivotTau of the pivot (threshold
+// pivoting's test); otherwise the level is recorded in error word 6 and the
+// host redoes the merge with partial pivoting.
+constexpr double kNoPivotTau = 0.1;
+
+template <class T>
+__global__ __launch_bounds__(64) void gj_diag_kernel(const T* A, int m, int lda, long long bstride, int k0, int kb,
+                                                     const int* rho_prev, int* rho, int* rowmap, T* dinv,
+                                                     int* flag, int level) {
+  __shared__ T prow[kNB];
+  __shared__ T colk[kNB];
+  const T* Ab = A + (long long)blockIdx.x * bstride;
+  const int lane = threadIdx.x, i = lane & 31, h = lane >> 5;
+  {
+    int* rm = rowmap + (long long)blockIdx.x * m;
+    int* ro = rho + (long long)blockIdx.x * m;
+    const int* rp = rho_prev ? rho_prev + (long long)blockIdx.x * m : nullptr;
+    for (int r = lane; r < m; r += 64) {
+      rm[r] = r;
+      ro[r] = rp ? rp[r] : r;
+    }
+  }
+  // a block narrower than kNB is padded with the identity, so that every
+  // step below is the same and the step loop unrolls with static register
+  // indices; the padding's inverse is the identity and is not written
+  T sv[kNB / 2];
+#pragma unroll
+  for (int t = 0; t < kNB / 2; ++t) {
+    const int j = 2 * t + h;
+    sv[t] = (i < kb && j < kb) ? Ab[(long long)(k0 + j) * lda + k0 + i]
+                               : cx<T>::make(i == j ? 1.0 : 0.0, 0.0);
+  }
+  bool grow = false;
+  const bool live = i < kb;
+#pragma unroll
+  for (int k = 0; k < kNB; ++k) {
+    // publish row k (its two lanes) and column k (the 32 lanes holding it)
+    if (i == k) {
+#pragma unroll
+      for (int t = 0; t < kNB / 2; ++t) prow[2 * t + h] = sv[t];
+    }
+    if (h == (k & 1)) colk[i] = sv[k >> 1];
+    __syncthreads();
+    // all LDS reads of the step together, then branch-free arithmetic: with
+    // li = a_ik / a_kk (rows i != k) and li = 1 - 1/a_kk (row k), every entry
+    // becomes a_ij - li a_kj; column k is then set to -li (rows i != k) and
+    // 1/a_kk (row k)
+    T pr[kNB / 2];
+#pragma unroll
+    for (int t = 0; t < kNB / 2; ++t) pr[t] = prow[2 * t + h];
+    const T pk = prow[k];
+    const T l = colk[i];
+    const T inv = crecip(pk);
+    const bool rowk = i == k;
+    const T lq = cmul(l, inv);
+    const T li = rowk ? csub(cx<T>::make(1.0, 0.0), inv) : lq;
+    // threshold test: |a_ik| > |a_kk| / tau for a row below, or a zero pivot
+    const double p2 = (double)cabs2(pk);
+    if (k < kb && ((i > k && live && !((double)cabs2(l) * (kNoPivotTau * kNoPivotTau) <= p2)) || !(p2 > 0.0)))
+      grow = true;
+#pragma unroll
+    for (int t = 0; t < kNB / 2; ++t) sv[t] = csub(sv[t], cmul(li, pr[t]));
+    const T colv = rowk ? inv : csub(cx<T>::make(0.0, 0.0), lq);
+    if (h == (k & 1)) sv[k >> 1] = colv;
+    __syncthreads();
+  }
+  if (__ballot(grow)) {
+    if (lane == 0) atomicMin(flag + 6, level);
+  }
+  T* Db = dinv + (long long)blockIdx.x * kNB * kNB;
+#pragma unroll
+  for (int t = 0; t < kNB / 2; ++t) {
+    const int j = 2 * t + h;
+    if (i < kb && j < kb) Db[j * kb + i] = sv[t];
+  }
+}
+
 // Step 2 of a block column: out-of-place update of the whole matrix, BT x BT
 // tiles (64, or 32 where 64 would leave few workgroups), 256 threads, each
 // thread (BT/16)^2 outputs (rows i0 + tx + 16u, columns j0 + ty + 16v), rows
@@ -514,10 +604,14 @@ __global__ __launch_bounds__(1024) void gj_panel_reg_kernel(const T* A, int m, i
 //   X = Dinv A'[P, :] (Dinv on the C columns); rows in P: out = X;
 //   other rows: out = A'[i, ~C] - A'[i, C] X  (-A'[i, C] Dinv on C).
 // With colmap the output column j is written at colmap[j].
+// check: without row interchanges (gj_diag_kernel), the block multipliers
+// -A'[i, C] Dinv of the rows outside P must stay within 1/kNoPivotTau, else
+// the level is recorded in check[6] (null: no check).
 template <class T, int BT>
 __global__ __launch_bounds__(256) void gj_update_kernel(const T* A, int lda, long long astride, T* O, int ldo,
                                                         long long ostride, int m, int k0, int kb,
-                                                        const int* rowmap, const T* dinv, const int* colmap) {
+                                                        const int* rowmap, const T* dinv, const int* colmap,
+                                                        int* check, int level) {
   constexpr int U = BT / 16;
   __shared__ T Ds[kNB * kNB];
   __shared__ T Xs[kNB][BT];
@@ -585,6 +679,8 @@ __global__ __launch_bounds__(256) void gj_update_kernel(const T* A, int lda, lon
 #pragma unroll
       for (int v = 0; v < U; ++v) acc[u][v] = cfma(a[u], x[v], acc[u][v]);
   }
+  bool grow = false;
+  const double lim2 = 1.0 / (kNoPivotTau * kNoPivotTau);
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     const int gi = i0 + tx + 16 * u;
@@ -596,9 +692,12 @@ __global__ __launch_bounds__(256) void gj_update_kernel(const T* A, int lda, lon
       const int gj = j0 + j;
       if (gj >= m) continue;
       const int oc = colmap ? colmap[(long long)b * m + gj] : gj;
-      Ob[(long long)oc * ldo + gi] = inP ? Xs[gi - k0][j] : csub(aout[u][v], acc[u][v]);
+      const T val = inP ? Xs[gi - k0][j] : csub(aout[u][v], acc[u][v]);
+      if (check && !inP && gi > k0 && gj >= k0 && gj < k0 + kb && !((double)cabs2(val) <= lim2)) grow = true;
+      Ob[(long long)oc * ldo + gi] = val;
     }
   }
+  if (check && __syncthreads_or(grow) && tid == 0) atomicMin(check + 6, level);
 }
 
 // dst(:, colmap[j]) = src(:, j): the inverse of the row-interchanged matrix
@@ -637,7 +736,7 @@ inline BlockScratch<T> carve(void* base, int m, int batch) {
 
 template <class T>
 hipError_t inverse_blocked(T* A, int m, int lda, long long bstride, int batch, void* scratch,
-                           int* flag, int level, hipStream_t st) {
+                           int* flag, int level, bool pivot, hipStream_t st) {
   BlockScratch<T> s = carve<T>(scratch, m, batch);
   hipError_t err;
   const int nbw = panel_width<T>(m);
@@ -656,7 +755,7 @@ hipError_t inverse_blocked(T* A, int m, int lda, long long bstride, int batch, v
   // register panels: rows <= 512 with 32 columns, FP64 rows <= 1024 with 16
   // columns; larger matrices keep the LDS panel
   const int reg = m <= 512 ? 1 : (m <= 1024 && sizeof(T) == sizeof(cd) ? 2 : 0);
-  const int nb = reg == 1 ? kNB : (reg == 2 ? kNB / 2 : nbw);
+  const int nb = !pivot ? kNB : (reg == 1 ? kNB : (reg == 2 ? kNB / 2 : nbw));
   static_assert(kNB == 32, "register panels hold 32 (16 x 2) columns");
   const int steps = (m + nb - 1) / nb;
   for (int s_ = 0; s_ < steps; ++s_) {
@@ -664,7 +763,10 @@ hipError_t inverse_blocked(T* A, int m, int lda, long long bstride, int batch, v
     const int kb = std::min(nb, m - k0);
     const int* rho_prev = s_ ? s.rho[(s_ - 1) & 1] : nullptr;
     int* rho = s.rho[s_ & 1];
-    if (reg == 1)
+    if (!pivot)
+      hipLaunchKernelGGL(gj_diag_kernel<T>, dim3(batch), dim3(64), 0, st, cur, m, ldc, cs, k0, kb, rho_prev, rho,
+                         s.rowmap, s.dinv, flag, level);
+    else if (reg == 1)
       hipLaunchKernelGGL((gj_panel_reg_kernel<T, 8, 2>), dim3(batch), dim3(1024), 0, st, cur, m, ldc, cs, k0, kb,
                          rho_prev, rho, s.rowmap, s.dinv, flag, level);
     else if (reg == 2)
@@ -676,12 +778,13 @@ hipError_t inverse_blocked(T* A, int m, int lda, long long bstride, int batch, v
     if ((err = hipPeekAtLastError()) != hipSuccess) return err;
     // the last step writes straight into A, columns permuted, when it can
     const bool last_into_A = (s_ == steps - 1) && nxt == A;
+    int* check = pivot ? nullptr : flag;
     if (tiles32)
       hipLaunchKernelGGL((gj_update_kernel<T, 32>), dim3(tiles * tiles, batch), dim3(256), 0, st, cur, ldc, cs,
-                         nxt, ldn, ns, m, k0, kb, s.rowmap, s.dinv, last_into_A ? rho : nullptr);
+                         nxt, ldn, ns, m, k0, kb, s.rowmap, s.dinv, last_into_A ? rho : nullptr, check, level);
     else
       hipLaunchKernelGGL((gj_update_kernel<T, 64>), dim3(tiles * tiles, batch), dim3(256), 0, st, cur, ldc, cs,
-                         nxt, ldn, ns, m, k0, kb, s.rowmap, s.dinv, last_into_A ? rho : nullptr);
+                         nxt, ldn, ns, m, k0, kb, s.rowmap, s.dinv, last_into_A ? rho : nullptr, check, level);
     if ((err = hipPeekAtLastError()) != hipSuccess) return err;
     std::swap(cur, nxt);
     std::swap(ldc, ldn);
@@ -699,7 +802,7 @@ hipError_t inverse_blocked(T* A, int m, int lda, long long bstride, int batch, v
 
 template <class T>
 size_t inverse_scratch_bytes(int m, int batch) {
-  if (m <= 128) return 0;
+  if (m <= 64) return 0;
   auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
   return up(sizeof(T) * (size_t)batch * m * m) + up(sizeof(T) * (size_t)batch * kNB * kNB) +
          3 * up(sizeof(int) * (size_t)batch * m);
@@ -707,22 +810,22 @@ size_t inverse_scratch_bytes(int m, int batch) {
 
 template <class T>
 hipError_t zinverse(T* A, int m, int lda, long long bstride, int batch, void* scratch, int* flag,
-                    int level, hipStream_t st) {
+                    int level, bool pivot, hipStream_t st) {
   if (m <= 0 || batch <= 0) return hipSuccess;
   if (m <= 64) {
     hipLaunchKernelGGL((inv_small_kernel<T, 4, 1>), dim3(batch), dim3(256), 0, st, A, m, lda, bstride, flag, level);
     return hipPeekAtLastError();
   }
-  if (m <= 128) {
+  if (m <= 128 && pivot) {
     hipLaunchKernelGGL((inv_small_kernel<T, 16, 2>), dim3(batch), dim3(1024), 0, st, A, m, lda, bstride, flag, level);
     return hipPeekAtLastError();
   }
-  return inverse_blocked<T>(A, m, lda, bstride, batch, scratch, flag, level, st);
+  return inverse_blocked<T>(A, m, lda, bstride, batch, scratch, flag, level, pivot, st);
 }
 
 template size_t inverse_scratch_bytes<cd>(int, int);
 template size_t inverse_scratch_bytes<cf>(int, int);
-template hipError_t zinverse<cd>(cd*, int, int, long long, int, void*, int*, int, hipStream_t);
-template hipError_t zinverse<cf>(cf*, int, int, long long, int, void*, int*, int, hipStream_t);
+template hipError_t zinverse<cd>(cd*, int, int, long long, int, void*, int*, int, bool, hipStream_t);
+template hipError_t zinverse<cf>(cf*, int, int, long long, int, void*, int*, int, bool, hipStream_t);
 
 }  // namespace hps

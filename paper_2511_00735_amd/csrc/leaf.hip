@@ -736,7 +736,7 @@ __global__ void fb_reset_kernel(int* list) { list[0] = 0; }
 
 __global__ void flag_reset_kernel(int* flag) {
   const int i = threadIdx.x;
-  if (i < kFlagWords) flag[i] = (i >= 2 && i < 6) ? -1 : 0;
+  if (i < kFlagWords) flag[i] = (i >= 2 && i < 6) ? -1 : (i == 6 ? 0x7FFFFFFF : 0);
 }
 
 // The complex element matrix L of Sec. 3.1 into columns [0, nloc) of S

@@ -121,3 +121,32 @@ def test_nonfinite_coefficient_is_reported(hps, ctx):
     rhs = prob.set_rhs(prob.boundary_data(workloads.PlaneWave(kappa, kappa).t))
     g, info = prob.gmres_solve(rhs, tol=1e-10)
     assert info["status"] == 0
+
+
+def test_merge_inverse_falls_back_to_pivoting(hps, ctx):
+    """The blocked merge inverse runs without row interchanges under a
+    threshold test; a shared-face block that needs them (W = I - T^P_aa T^Q_bb
+    a permutation: zero diagonal) fails the test, and the next synchronising
+    call redoes the merge with partial pivoting: A A^-1 = I afterwards."""
+    import torch
+    from oracle import merge as omerge
+    n, N = 16, 16
+    p = N - 1
+    prob = gpu_problem(hps, ctx, n, N, 20.0, workloads.zero_field, coarse_iters=-1, merge=False)
+    for level in range(1, 8):
+        prob.merge_level(level)
+    # level 8 (the top, m = 240): P = box 0 (shared side t), Q = box 1 (side b)
+    T = prob.level_T(8)
+    m = 240
+    aP, bQ = slice(480, 720), slice(240, 480)
+    eye = torch.eye(m, dtype=T.dtype, device=T.device)
+    shift = torch.roll(eye, 1, dims=0)
+    T[0, aP, aP] = eye - shift
+    T[1, bQ, bQ] = eye
+    prob.merge_level(8)
+    ctx.sync()                                  # the redo happens here
+    Tg = prob.level_T(8).cpu().numpy()
+    blk = omerge.pair_blocks(8, p, Tg[0], Tg[1])
+    Ai = prob.level_Ainv(8).cpu().numpy()[0]
+    res = np.abs(blk["A"] @ Ai - np.eye(2 * m)).max()
+    assert res < 1e-10, res
