@@ -178,6 +178,19 @@ inline hipError_t allow_lds(K kernel, size_t bytes) {
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
+// Values that are the same in every lane of a wave (the wave index, data read
+// from one LDS address) held in scalar registers, so that conditions on them
+// compile to scalar branches instead of divergent ones.
+__device__ inline int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ inline unsigned long long wave_uniform(unsigned long long v) {
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+  return ((unsigned long long)hi << 32) | lo;
+}
+__device__ inline double wave_uniform(double v) {
+  return __longlong_as_double((long long)wave_uniform((unsigned long long)__double_as_longlong(v)));
+}
+
 // Device error words of a problem (kFlagWords ints in its workspace):
 //   word 0: bits kFlagSingular (exact zero pivot), kFlagNonFinite (NaN or Inf
 //           in b_nodes or s_nodes);

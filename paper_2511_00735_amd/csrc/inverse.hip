@@ -214,7 +214,7 @@ __global__ __launch_bounds__(64 * NW) void inv_small_kernel(T* A, int m, int lda
   __shared__ unsigned long long kw[2];
   __shared__ int pivs[64 * RC];
   T* Ab = A + (long long)blockIdx.x * bstride;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = wave_uniform(tid >> 6);
   T sv[RC][kT];
 #pragma unroll
   for (int c = 0; c < RC; ++c)
@@ -258,7 +258,7 @@ __global__ __launch_bounds__(64 * NW) void inv_small_kernel(T* A, int m, int lda
 #pragma unroll 1
   for (int k = 0; k < m; ++k) {
     const int b = k & 1;
-    const unsigned long long kk = kw[b];
+    const unsigned long long kk = wave_uniform(kw[b]);
     const T inv = pinv[b];
     const int pr = min(max(pivot_row(kk), 0), m - 1);
     const int cp = pr >> 6, lp = pr & 63;
@@ -357,7 +357,7 @@ __global__ __launch_bounds__(1024) void gj_panel_reg_kernel(const T* A, int m, i
   __shared__ int piv_s[kNB], dsrc_s[kNB];
   const int rows = m - k0;
   const T* Ab = A + (long long)blockIdx.x * bstride;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = wave_uniform(tid >> 6);
   T x[CH][CPW];
 #pragma unroll
   for (int u = 0; u < CPW; ++u) {
@@ -374,7 +374,7 @@ __global__ __launch_bounds__(1024) void gj_panel_reg_kernel(const T* A, int m, i
 #pragma unroll 1
   for (int c = 0; c < kb; ++c) {
     const int b = c & 1;
-    const unsigned long long kk = kw_s[b];
+    const unsigned long long kk = wave_uniform(kw_s[b]);
     const T inv = pinv_s[b];
     const int pr = min(max(pivot_row(kk), 0), rows - 1);
     const int tp = pr >> 6, lp = pr & 63;

@@ -277,7 +277,7 @@ __device__ inline void cayley_publish(cd v, bool used, bool row_ok, cd* cbn, uns
 __device__ void leaf_cayley(const LeafArgs& a, const Dims& d, const double* A, double* lds) {
   constexpr int kT = 16;  // columns per thread (4p <= 64)
   const int m = 4 * d.p, nloc = d.nloc, npiv = d.pp;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = wave_uniform(tid >> 6);
   const int G = a.G0 + blockIdx.x;
   const int q = G / a.E, e = G % a.E;
   const double eta = a.eta[q - a.q0];
@@ -302,7 +302,7 @@ __device__ void leaf_cayley(const LeafArgs& a, const Dims& d, const double* A, d
 #pragma unroll 1
   for (int k = 0; k < m; ++k) {
     const int b = k & 1;
-    const unsigned long long kk = kw[b];
+    const unsigned long long kk = wave_uniform(kw[b]);
     const cd inv = pinv[b];
     const bool zero = (kk >> 32) <= 1u;
     const int pr = min(max(pivot_row(kk), 0), m - 1);
@@ -399,7 +399,7 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_kernel(LeafArgs a) {
   const size_t region = leaf_region_doubles(d);
   int* rowmap = reinterpret_cast<int*>(lds + region);  // trailing slot -> panel row of its L21
   int* slotof = rowmap + nloc;                         // first panel: row of K -> its trailing slot, or -1
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = wave_uniform(tid >> 6);
   const int G = a.G0 + blockIdx.x;
   const int q = G / a.E, e = G % a.E;
   const int N1 = a.N + 1;
@@ -471,8 +471,8 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_kernel(LeafArgs a) {
     for (int c = 0; c < kb; ++c) {
       const int bsel = c & 1;
       const double* cb = colbuf + bsel * 64 * kMaxChunks;
-      const unsigned long long kk = kw_s[bsel];
-      const double inv = pinv_s[bsel];
+      const unsigned long long kk = wave_uniform(kw_s[bsel]);
+      const double inv = wave_uniform(pinv_s[bsel]);
       const bool zero = (kk >> 32) <= 1u;
       const int pr = min(max(pivot_row(kk), 0), cand - 1);
       const int tp = pr >> 6, lp = pr & 63;
