@@ -99,6 +99,7 @@ struct Layout {
   size_t V_off, Z_off, work_off;  // Krylov bases and 5 canonical work vectors
   size_t cV_off, cw_off, cx_off, cidx_off, cH_off, cy_off, cs_off;  // coarse GMRES
   size_t part_off, hh_off, one_off, flag_off;
+  size_t jctr_off;                 // int: the FGMRES iteration index of the captured iteration
   size_t fb_off;                   // int [1 + leaf_chunk]: the leaf fallback's element list
   size_t ysol_off;                 // [nq][restart] FGMRES update coefficients
   size_t gpart_off, gpart_elems;  // split-K GEMV partial sums
@@ -314,6 +315,7 @@ Layout make_layout(const hps_desc* d, int nq) {
   lay.part_off = take(sizeof(cd) * Q * (lay.restart + 2) * kMaxDotBlocks);
   lay.hh_off = take(sizeof(cd) * Q * hh_stride(lay.restart));
   lay.one_off = take(sizeof(cd));
+  lay.jctr_off = take(sizeof(int));
   lay.ysol_off = take(sizeof(cd) * Q * lay.restart);
   {
     // split-K GEMV partials: at most two descriptors per launch, of the shapes
@@ -364,6 +366,8 @@ struct hps_problem {
   bool have_T1;
   hipGraphExec_t pgraph = nullptr;  // captured V-cycle (work vector 5 -> 6)
   bool graph_failed = false;
+  hipGraphExec_t igraph = nullptr;  // captured FGMRES iteration (index on the device)
+  bool igraph_failed = false;
   // levels whose merge inverse uses partial pivoting (set when the inverse
   // without row interchanges failed its threshold test; kept for later builds)
   std::vector<char> pivot_level;
@@ -747,17 +751,19 @@ cd* workv(hps_problem* p, int i) {
 // Classical Gram-Schmidt, two passes, against V[0..nv) for each problem of
 // the group (segments of n entries): coefficients summed into h (problem q at
 // h + q*hs), w updated in place; h2: the same layout, scratch.
+// With nvdev set the vector count is *nvdev + 1, read on the device, and nv
+// is the largest it may be.
 hps_status cgs2(hps_problem* p, const cd* V, long long vstride, int nv, cd* w, long long n, cd* h, cd* h2,
-                long long hs) {
+                long long hs, const int* nvdev = nullptr) {
   hps_ctx* c = p->ctx;
   hipStream_t st = c->stream;
   const int nq = p->lay.nq;
   cd* part = at<cd>(p, p->lay.part_off);
-  HIPCHK(c, multi_dot(V, vstride, nv, w, n, part, h, false, st, nq, hs));
-  HIPCHK(c, multi_axpy(V, vstride, nv, h, w, n, -1, st, nq, hs));
-  HIPCHK(c, multi_dot(V, vstride, nv, w, n, part, h2, false, st, nq, hs));
-  HIPCHK(c, multi_axpy(V, vstride, nv, h2, w, n, -1, st, nq, hs));
-  HIPCHK(c, add_strided(h, h2, nv, nq, hs, st));
+  HIPCHK(c, multi_dot(V, vstride, nv, w, n, part, h, false, st, nq, hs, nvdev));
+  HIPCHK(c, multi_axpy(V, vstride, nv, h, w, n, -1, st, nq, hs, nvdev));
+  HIPCHK(c, multi_dot(V, vstride, nv, w, n, part, h2, false, st, nq, hs, nvdev));
+  HIPCHK(c, multi_axpy(V, vstride, nv, h2, w, n, -1, st, nq, hs, nvdev));
+  HIPCHK(c, add_strided(h, h2, nv, nq, hs, st, nvdev));
   return HPS_OK;
 }
 
@@ -1051,6 +1057,72 @@ typedef std::complex<double> zc;
 // rotations, estimates and stopping are per problem.  A problem that has
 // converged (or reached maxit) stops taking part in the least-squares updates,
 // so its solution stays as it was.  rhs, g: group vectors.
+// One FGMRES iteration with its index j read on the device (the int at
+// jctr_off): V_j into the V-cycle's input vector, the preconditioner, its
+// output into Z_j, the M_1 product, CGS2 against V_0..V_j, V_{j+1} with its
+// norm, then j + 1.  Every launch has the same arguments for every j, so one
+// captured graph serves all iterations of all cycles.
+hps_status iteration_kernels(hps_problem* p) {
+  hps_ctx* c = p->ctx;
+  hipStream_t st = c->stream;
+  const Layout& lay = p->lay;
+  const int nq = lay.nq;
+  const long long n = lay.nslots, ntot = n * nq;
+  const int R = lay.restart;
+  const long long HS = (long long)hh_stride(R);
+  cd* V = at<cd>(p, lay.V_off);
+  cd* Z = at<cd>(p, lay.Z_off);
+  cd* w = workv(p, 4);
+  cd* rin = workv(p, 5);
+  cd* zout = workv(p, 6);
+  cd* hh = at<cd>(p, lay.hh_off);
+  cd* nrm2 = hh + 2 * (R + 2);
+  cd* part = at<cd>(p, lay.part_off);
+  int* jctr = at<int>(p, lay.jctr_off);
+  HIPCHK(c, vcopy_at(V, rin, ntot, jctr, nullptr, ntot, st));
+  hps_status s = precond_one(p, rin, zout);
+  if (s != HPS_OK) return s;
+  HIPCHK(c, vcopy_at(zout, Z, ntot, nullptr, jctr, ntot, st));
+  HIPCHK(c, skeleton_apply(lay.lev[1].g, Tlev(p, 1), zout, w, true, st, nq));
+  s = cgs2(p, V, ntot, R, w, n, hh, hh + (R + 2), HS, jctr);
+  if (s != HPS_OK) return s;
+  HIPCHK(c, multi_dot(w, 0, 1, w, n, part, nrm2, false, st, nq, HS));
+  HIPCHK(c, normalize(w, nrm2, V, n, nrm2 + 1, st, nq, HS, HS, jctr, ntot));
+  HIPCHK(c, counter_add(jctr, 1, st));
+  return HPS_OK;
+}
+
+// Captures iteration_kernels into p->igraph on first use; the caller has just
+// run them eagerly (so every kernel attribute is set outside the capture).  A
+// capture that fails leaves the problem on eager launches.
+void capture_iteration(hps_problem* p) {
+  hps_ctx* c = p->ctx;
+  if (p->igraph || p->igraph_failed) return;
+  p->igraph_failed = true;
+  if (!c->cap_stream && hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipGetLastError();
+    return;
+  }
+  hipStream_t saved = c->stream;
+  c->stream = c->cap_stream;
+  hipGraph_t graph = nullptr;
+  hps_status s = HPS_ERR_HIP;
+  hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed);
+  if (e == hipSuccess) {
+    s = iteration_kernels(p);
+    e = hipStreamEndCapture(c->stream, &graph);
+  }
+  c->stream = saved;
+  if (e == hipSuccess && s == HPS_OK && graph) e = hipGraphInstantiate(&p->igraph, graph, nullptr, nullptr, 0);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (e == hipSuccess && s == HPS_OK && p->igraph) {
+    p->igraph_failed = false;
+  } else {
+    p->igraph = nullptr;
+    (void)hipGetLastError();
+  }
+}
+
 hps_status fgmres_group(hps_problem* p, const cd* rhs, cd* g, double tol, int maxit, hps_info* info) {
   hps_ctx* c = p->ctx;
   hipStream_t st = c->stream;
@@ -1087,6 +1159,9 @@ hps_status fgmres_group(hps_problem* p, const cd* rhs, cd* g, double tol, int ma
     if (!c->hev[i]) HIPCHK(c, hipEventCreateWithFlags(&c->hev[i], hipEventDisableTiming));
   cd* hbuf = static_cast<cd*>(c->hbuf);
   const cd* host = hbuf;
+  // graphs on: every iteration replays one captured graph
+  int* jctr = at<int>(p, lay.jctr_off);
+  bool graphed = c->use_graphs != 0 && !p->igraph_failed;
   auto fetch = [&]() -> hps_status {
     HIPCHK(c, hipMemcpyAsync(hbuf, hh, sizeof(cd) * hn, hipMemcpyDeviceToHost, st));
     HIPCHK(c, hipStreamSynchronize(st));
@@ -1132,6 +1207,7 @@ hps_status fgmres_group(hps_problem* p, const cd* rhs, cd* g, double tol, int ma
     }
     if (active == 0) break;
     HIPCHK(c, normalize(res, nrm2, V, n, nullptr, st, nq, HS, 0));
+    if (graphed) HIPCHK(c, counter_set(jctr, 0, st));
     // Iteration j on the device: V-cycle, M_1 product, CGS2, V_{j+1}, and its
     // Hessenberg column copied to host buffer j % 2.  The next iteration needs
     // nothing from the host, so it is enqueued before the host waits for this
@@ -1139,6 +1215,22 @@ hps_status fgmres_group(hps_problem* p, const cd* rhs, cd* g, double tol, int ma
     // the convergence rate so far predicts that this one reaches the tolerance;
     // a column computed past the stopping point is simply not used.
     auto enqueue = [&](int j) -> hps_status {
+      if (graphed) {
+        // the iteration graph (the device index equals j: set to 0 above,
+        // advanced once per iteration in stream order)
+        if (p->igraph) {
+          HIPCHK(c, hipGraphLaunch(p->igraph, st));
+        } else {
+          hps_status e = iteration_kernels(p);
+          if (e != HPS_OK) return e;
+          HIPCHK(c, hipStreamSynchronize(st));
+          capture_iteration(p);
+          if (!p->igraph) graphed = false;  // later iterations of this cycle use the eager path
+        }
+        HIPCHK(c, hipMemcpyAsync(hbuf + (size_t)(j & 1) * hn, hh, sizeof(cd) * hn, hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipEventRecord(c->hev[j & 1], st));
+        return HPS_OK;
+      }
       hps_status e = precond_any(p, V + (size_t)j * ntot, Z + (size_t)j * ntot);
       if (e != HPS_OK) return e;
       HIPCHK(c, skeleton_apply(g1, T1, Z + (size_t)j * ntot, w, true, st, nq));
@@ -1524,6 +1616,7 @@ int32_t hps_group_size(const hps_problem* p) { return p ? p->lay.nq : 0; }
 hps_status hps_problem_destroy(hps_problem* p) {
   if (!p) return HPS_OK;
   if (p->pgraph) (void)hipGraphExecDestroy(p->pgraph);
+  if (p->igraph) (void)hipGraphExecDestroy(p->igraph);
   for (hipEvent_t ev : {p->ev_build0, p->ev_build1, p->ev_solve0, p->ev_solve1})
     if (ev) (void)hipEventDestroy(ev);
   if (p->ctx) {

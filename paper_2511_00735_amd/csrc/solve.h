@@ -22,25 +22,39 @@ hipError_t index_gather(const int* idx, int n, const cd* vec, cd* out, hipStream
 hipError_t index_scatter(const int* idx, int n, const cd* in, cd* vec, hipStream_t st, int nq = 1,
                          long long istride = 0);
 hipError_t vfill(cd* v, long long n, cd val, hipStream_t st);
-// a[q*stride + i] += b[q*stride + i] for i < n, q < nq
-hipError_t add_strided(cd* a, const cd* b, int n, int nq, long long stride, hipStream_t st);
+// a[q*stride + i] += b[q*stride + i] for i < n, q < nq (ndev set: n = *ndev + 1,
+// n passed as the largest value it may take)
+hipError_t add_strided(cd* a, const cd* b, int n, int nq, long long stride, hipStream_t st,
+                       const int* ndev = nullptr);
 // out = a x + b y
 hipError_t axpby(cd a, const cd* x, cd b, const cd* y, cd* out, long long n, hipStream_t st);
 hipError_t vcopy(const cd* src, cd* dst, long long n, hipStream_t st);
+// dst = src with src displaced by (*isrc) * stride or dst by (*idst) * stride
+// (indices held on the device; null: none).
+hipError_t vcopy_at(const cd* src, cd* dst, long long n, const int* isrc, const int* idst, long long stride,
+                    hipStream_t st);
+// *c = value, or *c += value, on the stream (one tiny launch, no memset).
+hipError_t counter_set(int* c, int value, hipStream_t st);
+hipError_t counter_add(int* c, int value, hipStream_t st);
 // dst = src and zero = 0 (n entries each) in one launch.
 hipError_t vcopy_zero(const cd* src, cd* dst, cd* zero, long long n, hipStream_t st);
 int dot_blocks(long long n);
 // Vectors of nq problems are stored one after the other (segments of n).
 // out[q*ostride + v] (+)= sum_i conj(V_v[q*n + i]) w[q*n + i], v < nvec;
-// partial: nq * nvec * dot_blocks(n) entries.
+// partial: nq * nvec * dot_blocks(n) entries.  With nvdev set the vector count
+// is read on the device, *nvdev + 1, and nvec is the largest it may be (the
+// launch's size; entries v > *nvdev of out are left as they were).
 hipError_t multi_dot(const cd* V, long long vstride, int nvec, const cd* w, long long n, cd* partial,
-                     cd* out, bool accumulate, hipStream_t st, int nq = 1, long long ostride = 0);
-// w[q*n + i] += sign * sum_v h[q*hstride + v] V_v[q*n + i]
+                     cd* out, bool accumulate, hipStream_t st, int nq = 1, long long ostride = 0,
+                     const int* nvdev = nullptr);
+// w[q*n + i] += sign * sum_v h[q*hstride + v] V_v[q*n + i] (nvdev as above)
 hipError_t multi_axpy(const cd* V, long long vstride, int nvec, const cd* h, cd* w, long long n, int sign,
-                      hipStream_t st, int nq = 1, long long hstride = 0);
-// out[q*n + i] = w[q*n + i] / sqrt(Re nrm2[q*nstride]); hout[q*hstride] = the norm
+                      hipStream_t st, int nq = 1, long long hstride = 0, const int* nvdev = nullptr);
+// out[q*n + i] = w[q*n + i] / sqrt(Re nrm2[q*nstride]); hout[q*hstride] = the
+// norm.  With jdev set, out is displaced by (*jdev + 1) * jstride.
 hipError_t normalize(const cd* w, const cd* nrm2, cd* out, long long n, cd* hout, hipStream_t st, int nq = 1,
-                     long long nstride = 0, long long hstride = 0);
+                     long long nstride = 0, long long hstride = 0, const int* jdev = nullptr,
+                     long long jstride = 0);
 // Coarse k-step GMRES on compact coarse vectors of length n, one workgroup per
 // problem q < nq.  Problem q's basis is V + q*vq ((k+1) x n), its Hessenberg
 // H + q*hsize ((k+1) x k, ld k+1), its index list idx + q*n, beta2[q].

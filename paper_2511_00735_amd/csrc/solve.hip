@@ -115,8 +115,10 @@ __global__ void index_scatter_kernel(const int* idx, int n, long long ntot, cons
     vec[idx[i]] = in[(i / n) * istride + i % n];
 }
 
-// a[q*stride + i] += b[q*stride + i], i < n, q < nq (grid.y = q).
-__global__ void add_strided_kernel(cd* a, const cd* b, int n, long long stride) {
+// a[q*stride + i] += b[q*stride + i], i < n, q < nq (grid.y = q); with ndev
+// set, n = *ndev + 1.
+__global__ void add_strided_kernel(cd* a, const cd* b, int n, long long stride, const int* ndev) {
+  if (ndev) n = *ndev + 1;
   const long long o = (long long)blockIdx.y * stride;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
     a[o + i] = cadd(a[o + i], b[o + i]);
@@ -138,6 +140,21 @@ __global__ void copy_kernel(const cd* src, cd* dst, long long n) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x)
     dst[i] = src[i];
+}
+
+// dst = src with either end displaced by a device-held index: src + (*isrc) *
+// stride or dst + (*idst) * stride (null: no displacement).
+__global__ void copy_at_kernel(const cd* src, cd* dst, long long n, const int* isrc, const int* idst,
+                               long long stride) {
+  if (isrc) src += (long long)*isrc * stride;
+  if (idst) dst += (long long)*idst * stride;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+__global__ void counter_kernel(int* c, int value, int add) {
+  if (threadIdx.x == 0) *c = add ? *c + value : value;
 }
 
 __global__ void copy_zero_kernel(const cd* src, cd* dst, cd* zero, long long n) {
@@ -195,8 +212,9 @@ __device__ inline cd block_sum(cd v) {
 // Stage 1: partial[q][v][blk] = sum over chunk blk of conj(V_v) . w on the
 // segment of problem q (grid (blocks, nvec, problems)).
 __global__ __launch_bounds__(256) void dot_stage1_kernel(const cd* V, long long vstride, const cd* w,
-                                                         long long n, cd* partial, int nblk) {
+                                                         long long n, cd* partial, int nblk, const int* nvdev) {
   const int v = blockIdx.y, q = blockIdx.z;
+  if (nvdev && v > *nvdev) return;   // device count (nvdev + 1 vectors; uniform per workgroup)
   const cd* Vv = V + (long long)v * vstride + (long long)q * n;
   w += (long long)q * n;
   partial += (long long)q * gridDim.y * nblk;
@@ -211,8 +229,9 @@ __global__ __launch_bounds__(256) void dot_stage1_kernel(const cd* V, long long 
 
 // Stage 2: out[q * ostride + v] (+)= sum_blk partial[q][v][blk]  (grid (nvec, problems)).
 __global__ __launch_bounds__(256) void dot_stage2_kernel(const cd* partial, int nblk, cd* out,
-                                                         int accumulate, long long ostride) {
+                                                         int accumulate, long long ostride, const int* nvdev) {
   const int v = blockIdx.x, q = blockIdx.y;
+  if (nvdev && v > *nvdev) return;
   partial += (long long)q * gridDim.x * nblk;
   out += (long long)q * ostride;
   cd acc = cmk(0.0, 0.0);
@@ -224,7 +243,8 @@ __global__ __launch_bounds__(256) void dot_stage2_kernel(const cd* partial, int 
 // w += sign * sum_v h[q * hstride + v] V_v on the segment of each problem q
 // (h on the device; entries i of [0, nq * n), q = i / n).
 __global__ void multi_axpy_kernel(const cd* V, long long vstride, int nvec, const cd* h, long long hstride,
-                                  cd* w, long long n, long long ntot, int sign) {
+                                  cd* w, long long n, long long ntot, int sign, const int* nvdev) {
+  if (nvdev) nvec = *nvdev + 1;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < ntot;
        i += (long long)gridDim.x * blockDim.x) {
     const cd* hq = h + (i / n) * hstride;
@@ -240,8 +260,9 @@ __global__ void multi_axpy_kernel(const cd* V, long long vstride, int nvec, cons
 // out = w / sqrt(Re nrm2[q * nstride]) on the segment of problem q (grid.y);
 // also stores the norm into hout[q * hstride] (complex, im = 0).
 __global__ void normalize_kernel(const cd* w, const cd* nrm2, long long nstride, cd* out, long long n, cd* hout,
-                                 long long hstride) {
+                                 long long hstride, const int* jdev, long long jstride) {
   const int q = blockIdx.y;
+  if (jdev) out += (long long)(*jdev + 1) * jstride;   // V_{j+1} with j on the device
   const double nr = sqrt(fmax(nrm2[(long long)q * nstride].x, 0.0));
   const double s = nr > 0.0 ? 1.0 / nr : 0.0;
   if (blockIdx.x == 0 && threadIdx.x == 0 && hout) hout[(long long)q * hstride] = cmk(nr, 0.0);
@@ -593,8 +614,8 @@ hipError_t index_scatter(const int* idx, int n, const cd* in, cd* vec, hipStream
   return hipPeekAtLastError();
 }
 
-hipError_t add_strided(cd* a, const cd* b, int n, int nq, long long stride, hipStream_t st) {
-  hipLaunchKernelGGL(add_strided_kernel, dim3(grid_for(n), nq), dim3(256), 0, st, a, b, n, stride);
+hipError_t add_strided(cd* a, const cd* b, int n, int nq, long long stride, hipStream_t st, const int* ndev) {
+  hipLaunchKernelGGL(add_strided_kernel, dim3(grid_for(n), nq), dim3(256), 0, st, a, b, n, stride, ndev);
   return hipPeekAtLastError();
 }
 
@@ -618,37 +639,53 @@ hipError_t vcopy(const cd* src, cd* dst, long long n, hipStream_t st) {
   return hipPeekAtLastError();
 }
 
+hipError_t vcopy_at(const cd* src, cd* dst, long long n, const int* isrc, const int* idst, long long stride,
+                    hipStream_t st) {
+  hipLaunchKernelGGL(copy_at_kernel, dim3(grid_for(n)), dim3(256), 0, st, src, dst, n, isrc, idst, stride);
+  return hipPeekAtLastError();
+}
+
+hipError_t counter_set(int* c, int value, hipStream_t st) {
+  hipLaunchKernelGGL(counter_kernel, dim3(1), dim3(64), 0, st, c, value, 0);
+  return hipPeekAtLastError();
+}
+
+hipError_t counter_add(int* c, int value, hipStream_t st) {
+  hipLaunchKernelGGL(counter_kernel, dim3(1), dim3(64), 0, st, c, value, 1);
+  return hipPeekAtLastError();
+}
+
 int dot_blocks(long long n) {
   long long b = (n + 2047) / 2048;
   return (int)(b < 1 ? 1 : (b > kMaxDotBlocks ? kMaxDotBlocks : b));
 }
 
 hipError_t multi_dot(const cd* V, long long vstride, int nvec, const cd* w, long long n, cd* partial,
-                     cd* out, bool accumulate, hipStream_t st, int nq, long long ostride) {
+                     cd* out, bool accumulate, hipStream_t st, int nq, long long ostride, const int* nvdev) {
   if (nvec <= 0) return hipSuccess;
   const int nblk = dot_blocks(n);
   hipLaunchKernelGGL(dot_stage1_kernel, dim3(nblk, nvec, nq), dim3(256), 0, st, V, vstride, w, n, partial,
-                     nblk);
+                     nblk, nvdev);
   hipError_t err = hipPeekAtLastError();
   if (err != hipSuccess) return err;
   hipLaunchKernelGGL(dot_stage2_kernel, dim3(nvec, nq), dim3(256), 0, st, partial, nblk, out,
-                     accumulate ? 1 : 0, ostride);
+                     accumulate ? 1 : 0, ostride, nvdev);
   return hipPeekAtLastError();
 }
 
 hipError_t multi_axpy(const cd* V, long long vstride, int nvec, const cd* h, cd* w, long long n, int sign,
-                      hipStream_t st, int nq, long long hstride) {
+                      hipStream_t st, int nq, long long hstride, const int* nvdev) {
   if (nvec <= 0) return hipSuccess;
   const long long ntot = n * nq;
   hipLaunchKernelGGL(multi_axpy_kernel, dim3(grid_for(ntot)), dim3(256), 0, st, V, vstride, nvec, h, hstride,
-                     w, n, ntot, sign);
+                     w, n, ntot, sign, nvdev);
   return hipPeekAtLastError();
 }
 
 hipError_t normalize(const cd* w, const cd* nrm2, cd* out, long long n, cd* hout, hipStream_t st, int nq,
-                     long long nstride, long long hstride) {
+                     long long nstride, long long hstride, const int* jdev, long long jstride) {
   hipLaunchKernelGGL(normalize_kernel, dim3(grid_for(n), nq), dim3(256), 0, st, w, nrm2, nstride, out, n, hout,
-                     hstride);
+                     hstride, jdev, jstride);
   return hipPeekAtLastError();
 }
 

@@ -138,3 +138,25 @@ def test_group_argument_checks(hps, ctx):
     b = probe.coefficient_nodes(workloads.zero_field)
     with pytest.raises(ValueError):
         grp.build_leaves([b])            # two problems need two arrays
+
+
+def test_group_iteration_graph_matches_eager(hps, ctx):
+    """A group's FGMRES iterations replayed from the captured iteration graph give
+    bitwise the eager group solve for every member."""
+    import torch
+    members = _members(3, 11)
+    grp, _, ts = _group(hps, ctx, 8, 6, members, coarse_iters=3)
+    rhs = grp.set_rhs(ts)
+    ctx.set_graphs(False)
+    ge, ie = grp.gmres_solve(rhs, tol=1e-10)
+    ge = [g.clone() for g in ge]
+    ctx.set_graphs(True)
+    try:
+        for rep in range(2):
+            gg, ig = grp.gmres_solve(rhs, tol=1e-10)
+            ctx.sync()
+            for q in range(len(members)):
+                assert ig[q]["iterations"] == ie[q]["iterations"], (rep, q)
+                assert torch.equal(gg[q], ge[q]), (rep, q)
+    finally:
+        ctx.set_graphs(False)

@@ -288,6 +288,34 @@ def test_graph_replays_match_eager(hps, ctx):
         ctx.set_graphs(False)           # the library's default: eager launches
 
 
+@pytest.mark.parametrize("restart", [60, 6])
+def test_iteration_graph_solve_matches_eager(hps, ctx, restart):
+    """With graphs on, every FGMRES iteration (V-cycle, M_1 product, CGS2, next
+    basis vector) replays one captured graph whose iteration index is held on
+    the device.  Solves repeated with eager library work in between, and with
+    restarted cycles (restart 6), give bitwise the eager solve's iterate,
+    iteration count and true residual."""
+    import torch
+    n, N, kappa = 16, 5, 12.0
+    prob = gpu_problem(hps, ctx, n, N, kappa, _bump, levels=0, coarse_iters=2, restart=restart)
+    rhs = prob.set_rhs(prob.boundary_data(workloads.PlaneWave(kappa, kappa).t))
+    ctx.set_graphs(False)
+    ge, ie = prob.gmres_solve(rhs, tol=1e-10)
+    ge = ge.clone()
+    assert ie["status"] == 0 and (restart == 60 or ie["iterations"] > restart)
+    ctx.set_graphs(True)
+    try:
+        for rep in range(3):
+            gg, ig = prob.gmres_solve(rhs, tol=1e-10)
+            ctx.sync()
+            assert (ig["status"], ig["iterations"]) == (ie["status"], ie["iterations"]), rep
+            assert ig["relres_true"] == ie["relres_true"], rep
+            assert torch.equal(gg, ge), rep
+            prob.skeleton_apply(rhs)        # unrelated eager work between solves
+    finally:
+        ctx.set_graphs(False)
+
+
 # ---- mixed precision: FP32 lower merges, FP64 top merges / coarse / outer ----
 
 def _mixed_problem(hps, ctx, pr, coarse_iters, levels=0):
