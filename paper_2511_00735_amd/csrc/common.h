@@ -182,6 +182,20 @@ inline hipError_t allow_lds(K kernel, size_t bytes) {
 // from one LDS address) held in scalar registers, so that conditions on them
 // compile to scalar branches instead of divergent ones.
 __device__ inline int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Logical index of workgroup b of a 1-D grid of G workgroups such that each
+// XCD's workgroups take one contiguous range: the dispatcher deals hardware
+// indices round-robin over the 8 XCDs (b % 8), so neighbouring logical
+// workgroups, which share the cache lines at their boundaries, then run
+// behind one L2.  A bijection on [0, G) for any G.
+#ifndef HPS_XCDS
+#define HPS_XCDS 8
+#endif
+__device__ inline int xcd_swizzle(int b, int G) {
+  const int q = G / HPS_XCDS, r = G % HPS_XCDS;  // XCD x runs q + (x < r) of them
+  const int x = b % HPS_XCDS, k = b / HPS_XCDS;
+  return x * q + min(x, r) + k;
+}
 __device__ inline unsigned long long wave_uniform(unsigned long long v) {
   const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
   const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));

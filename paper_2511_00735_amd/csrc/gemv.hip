@@ -259,7 +259,8 @@ template <class Mt, int NT>
 __global__ __launch_bounds__(NT) void vc_down_small_kernel(SmallLevelT<Mt> a, cd* vec) {
   extern __shared__ cd sm[];
   const int m = a.m, e = a.e, m2 = 2 * m;
-  const int j = blockIdx.x >> 1, h = blockIdx.x & 1, t = threadIdx.x;
+  const int bid = xcd_swizzle(blockIdx.x, gridDim.x);
+  const int j = bid >> 1, h = bid & 1, t = threadIdx.x;
   cd* r = sm;             // [2m] r_x
   cd* z = r + m2;         // [m]  z0 half
   cd* dv = z + m;         // [e]  vector values across the faces
@@ -301,7 +302,8 @@ template <class Mt, int NT>
 __global__ __launch_bounds__(NT) void vc_up_small_kernel(SmallLevelT<Mt> a, cd* z, int P) {
   extern __shared__ cd sm[];
   const int m = a.m, e = a.e, m2 = 2 * m, e2 = 2 * e;
-  const int j = blockIdx.x / P, pc = blockIdx.x - j * P, t = threadIdx.x;
+  const int bid = xcd_swizzle(blockIdx.x, gridDim.x);
+  const int j = bid / P, pc = bid - j * P, t = threadIdx.x;
   const int R = (m2 + P - 1) / P, r0 = pc * R, M = min(R, m2 - r0);
   if (M <= 0) return;   // uniform over the workgroup
   cd* y = sm;          // [2e]
