@@ -23,8 +23,8 @@ from .leaf import index_sets, local_operator, normal_rows, element_1d
 
 def solve(n, N, kappa, eta, c_all, s_all, t_slots):
     p = N - 1
-    h = 1.0 / n
-    E = n * n
+    h = mesh.element_size(n)
+    E = mesh.num_elements(n)
     keep, sides, iG, ii = index_sets(N)
     nloc = len(keep)
     NG = normal_rows(N, h)                      # 4p x nloc, rows in [l;r;b;t] order

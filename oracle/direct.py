@@ -29,10 +29,10 @@ def solve(n, p, leafT, leafH, t_slots, hierarchy=None):
     incoming = {(0, 0): t_slots[root]}
     for level in range(Lm, 0, -1):
         nxt = {}
-        perm = merged_order(level, p)
+        perm = merged_order(level, p, n)
         for (P, Q, Mb) in mesh.pairs(n, level):
             _, _, blk = merge_pair(level, p, T[level - 1][P], T[level - 1][Q],
-                                   H[level - 1][P], H[level - 1][Q])
+                                   H[level - 1][P], H[level - 1][Q], n)
             y = np.empty(len(perm), dtype=complex)
             y[perm] = incoming[Mb]
             x = np.linalg.solve(blk["A"], blk["B"] @ y + blk["h"])
@@ -46,9 +46,9 @@ def solve(n, p, leafT, leafH, t_slots, hierarchy=None):
             fQ[blk["ib"]] = x[:m]
             nxt[P], nxt[Q] = fP, fQ
         incoming = nxt
-    g = np.zeros(n * n * 4 * p, dtype=complex)
+    g = np.zeros(mesh.num_elements(n) * 4 * p, dtype=complex)
     for (bx, by), f in incoming.items():
-        e = bx + n * by
+        e = mesh.element_of(n, bx, by)
         g[e * 4 * p:(e + 1) * 4 * p] = f
     g[mesh.physical_slot_mask(n, p)] = 0.0
     return g

@@ -62,8 +62,9 @@ def fields(n, N, eta, c_all, s_all, g, t_slots):
     p = N - 1
     phys = mesh.physical_slot_mask(n, p)
     inc = np.where(phys, t_slots, g)
-    out = np.empty((n * n, (N + 1) ** 2), dtype=complex)
-    for e in range(n * n):
+    E = mesh.num_elements(n)
+    out = np.empty((E, (N + 1) ** 2), dtype=complex)
+    for e in range(E):
         f = inc[e * 4 * p:(e + 1) * 4 * p]
-        out[e] = element_field(N, 1.0 / n, eta, c_all[e], None if s_all is None else s_all[e], f)
+        out[e] = element_field(N, mesh.element_size(n), eta, c_all[e], None if s_all is None else s_all[e], f)
     return out

@@ -24,6 +24,7 @@ Test infrastructure only (see the package docstring).
 """
 import numpy as np
 
+from . import mesh
 from .gll import gll
 from .mesh import L_, R_, B_, T_
 
@@ -155,4 +156,4 @@ def nodal_coefficient(N, n, kappa, b_fn, xi):
     from .mesh import element_node_coords
     X, Y = element_node_coords(n, N, xi)
     b = b_fn(X, Y)
-    return (kappa ** 2 * (1.0 - b)).reshape(n * n, (N + 1) ** 2)
+    return (kappa ** 2 * (1.0 - b)).reshape(mesh.num_elements(n), (N + 1) ** 2)

@@ -30,15 +30,16 @@ from . import mesh
 from .mesh import L_, R_, B_, T_
 
 
-def _ranges(level, p):
-    off = mesh.side_offsets(level, p)
+def _ranges(level, p, n=None):
+    off = mesh.side_offsets(level, p, n)
     return {s: np.arange(off[s], off[s + 1]) for s in range(4)}
 
 
-def pair_blocks(level, p, TP, TQ, HP=None, HQ=None):
-    """The blocks A, B, Ct, D, h of one pair and the index bookkeeping."""
-    rg = _ranges(level, p)
-    if mesh.merge_axis(level) == "x":
+def pair_blocks(level, p, TP, TQ, HP=None, HQ=None, n=None):
+    """The blocks A, B, Ct, D, h of one pair and the index bookkeeping (n: the
+    mesh, needed only on rectangular meshes)."""
+    rg = _ranges(level, p, n)
+    if mesh.merge_axis(level, n) == "x":
         a, b = R_, L_
     else:
         a, b = T_, B_
@@ -65,11 +66,11 @@ def pair_blocks(level, p, TP, TQ, HP=None, HQ=None):
     return dict(A=A, B=Bm, Ct=Ct, D=D, h=h, hE=hE, ia=ia, ib=ib, E1=E1, E2=E2, m=m)
 
 
-def merged_order(level, p):
+def merged_order(level, p, n=None):
     """perm such that T_merged = T_pair[perm][:, perm] (y order -> [l;r;b;t])."""
-    wx, wy = mesh.box_dims(level)
+    wx, wy = mesh.box_dims(level, n)
     # children's exterior sides in y order, with their lengths
-    if mesh.merge_axis(level) == "x":
+    if mesh.merge_axis(level, n) == "x":
         # y = [P.l, P.b, P.t, Q.r, Q.b, Q.t]; merged l=P.l, r=Q.r, b=[P.b,Q.b], t=[P.t,Q.t]
         segs = ["Pl", "Pb", "Pt", "Qr", "Qb", "Qt"]
         lens = [wy * p, wx * p, wx * p, wy * p, wx * p, wx * p]
@@ -84,15 +85,15 @@ def merged_order(level, p):
     return np.concatenate([np.arange(start[s], start[s] + ln[s]) for s in target])
 
 
-def merge_pair(level, p, TP, TQ, HP=None, HQ=None):
+def merge_pair(level, p, TP, TQ, HP=None, HQ=None, n=None):
     """(T_merged, H_merged, blocks) for one pair at merge `level`."""
-    blk = pair_blocks(level, p, TP, TQ, HP, HQ)
+    blk = pair_blocks(level, p, TP, TQ, HP, HQ, n)
     X = np.linalg.solve(blk["A"], blk["B"])
     Tpair = blk["D"] + blk["Ct"] @ X
     Hpair = None
     if HP is not None:
         Hpair = blk["hE"] + blk["Ct"] @ np.linalg.solve(blk["A"], blk["h"])
-    perm = merged_order(level, p)
+    perm = merged_order(level, p, n)
     Tm = Tpair[np.ix_(perm, perm)]
     Hm = None if Hpair is None else Hpair[perm]
     return Tm, Hm, blk
@@ -103,15 +104,17 @@ def build_hierarchy(n, p, leafT, leafH=None, top=None):
     (bx, by) -> T (and H if leafH is given).  Merge l produces level l+1."""
     Lm = mesh.lmax(n)
     top = Lm if top is None else top
-    T = [{(e % n, e // n): leafT[e] for e in range(n * n)}]
-    H = [None if leafH is None else {(e % n, e // n): leafH[e] for e in range(n * n)}]
+    nx = mesh.dims(n)[0]
+    E = mesh.num_elements(n)
+    T = [{(e % nx, e // nx): leafT[e] for e in range(E)}]
+    H = [None if leafH is None else {(e % nx, e // nx): leafH[e] for e in range(E)}]
     for level in range(1, top):
         Tn, Hn = {}, ({} if leafH is not None else None)
         for (P, Q, Mb) in mesh.pairs(n, level):
             HP = HQ = None
             if leafH is not None:
                 HP, HQ = H[-1][P], H[-1][Q]
-            Tm, Hm, _ = merge_pair(level, p, T[-1][P], T[-1][Q], HP, HQ)
+            Tm, Hm, _ = merge_pair(level, p, T[-1][P], T[-1][Q], HP, HQ, n)
             Tn[Mb] = Tm
             if Hn is not None:
                 Hn[Mb] = Hm

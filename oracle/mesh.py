@@ -4,7 +4,10 @@ Conventions (the paper fixes some of them, the rest are readings):
 
 * n x n square elements of side h = 1/n on (0,1)^2, element e = ix + n*iy
   (x fastest, as the Fig. 1 element numbering: column (e-1) mod 4, row
-  floor((e-1)/4)).
+  floor((e-1)/4)).  A rectangular mesh of nx x ny elements (both powers of
+  two; `n` given as the pair (nx, ny)) takes square elements of side
+  h = 1/max(nx, ny) on (0, nx h) x (0, ny h) and e = ix + nx*iy (an extension:
+  the paper's mesh is square).
 * Element nodes (i, j), i the x-index, j the y-index, both 0..N; flat index
   i*(N+1) + j (x slow, matching the Kronecker order K_x (x) M_y of Sec. 3.1).
 * Sides in the order l, r, b, t (Sec. 3.1); side l holds nodes (0, j),
@@ -15,7 +18,10 @@ Conventions (the paper fixes some of them, the rest are readings):
 * Merge level l (l = 1 .. L_max = log2(n^2)): boxes of level l are
   2^floor(l/2) x 2^floor((l-1)/2) elements; merge l joins pairs of level-l
   boxes along x when l is odd and along y when l is even (Fig. 1: F_1 are the
-  vertical faces, Grid 2 holds 2-wide, 1-tall boxes).  In a pair (P, Q), P is
+  vertical faces, Grid 2 holds 2-wide, 1-tall boxes).  On a 2^a x 2^b mesh
+  (L_max = a + b) the merges alternate x, y while both directions have merges
+  left (the first 2 min(a, b) levels) and then all run along the longer
+  direction.  In a pair (P, Q), P is
   the left/bottom box (shared side alpha = r or t) and Q the right/top box
   (beta = l or b).
 * A box's local boundary order is [l; r; b; t], each side the concatenation of
@@ -37,43 +43,68 @@ def log2i(n):
     return q
 
 
+def dims(n):
+    """(nx, ny): `n` is the side of a square mesh or the pair (nx, ny)."""
+    if np.isscalar(n):
+        return int(n), int(n)
+    return int(n[0]), int(n[1])
+
+
+def num_elements(n):
+    nx, ny = dims(n)
+    return nx * ny
+
+
+def element_size(n):
+    nx, ny = dims(n)
+    return 1.0 / max(nx, ny)
+
+
 def lmax(n):
-    return 2 * log2i(n)
+    nx, ny = dims(n)
+    return log2i(nx) + log2i(ny)
 
 
-def box_dims(level):
-    """(wx, wy) in elements of a level-`level` box."""
-    return 2 ** (level // 2), 2 ** ((level - 1) // 2)
+def merge_axis(level, n=None):
+    """Axis of merge `level`; n (the mesh) matters only past the alternating levels."""
+    a, b = (0, 0) if n is None else (log2i(dims(n)[0]), log2i(dims(n)[1]))
+    if n is None or level <= 2 * min(a, b):
+        return "x" if level % 2 == 1 else "y"
+    return "x" if a > b else "y"
+
+
+def box_dims(level, n=None):
+    """(wx, wy) in elements of a level-`level` box: 2 to the number of merges
+    along x and along y among merges 1..level-1."""
+    dx = sum(merge_axis(l, n) == "x" for l in range(1, level))
+    return 2 ** dx, 2 ** (level - 1 - dx)
 
 
 def box_grid(n, level):
-    wx, wy = box_dims(level)
-    return n // wx, n // wy
+    nx, ny = dims(n)
+    wx, wy = box_dims(level, n)
+    return nx // wx, ny // wy
 
 
-def merge_axis(level):
-    return "x" if level % 2 == 1 else "y"
-
-
-def side_len(level, side, p):
-    wx, wy = box_dims(level)
+def side_len(level, side, p, n=None):
+    wx, wy = box_dims(level, n)
     return (wy if side in (L_, R_) else wx) * p
 
 
-def box_perimeter(level, p):
-    wx, wy = box_dims(level)
+def box_perimeter(level, p, n=None):
+    wx, wy = box_dims(level, n)
     return 2 * (wx + wy) * p
 
 
-def side_offsets(level, p):
+def side_offsets(level, p, n=None):
     """Start of each side in the box-local [l; r; b; t] order."""
-    wx, wy = box_dims(level)
+    wx, wy = box_dims(level, n)
     lens = [wy * p, wy * p, wx * p, wx * p]
     return np.concatenate([[0], np.cumsum(lens)])
 
 
 def element_of(n, ix, iy):
-    return ix + n * iy
+    return ix + dims(n)[0] * iy
 
 
 def slot(n, p, e, side, k):
@@ -82,19 +113,20 @@ def slot(n, p, e, side, k):
 
 def neighbour(n, e, side):
     """(e', side') across `side` of element e, or None on the physical boundary."""
-    ix, iy = e % n, e // n
+    nx, ny = dims(n)
+    ix, iy = e % nx, e // nx
     if side == L_:
         return None if ix == 0 else (e - 1, R_)
     if side == R_:
-        return None if ix == n - 1 else (e + 1, L_)
+        return None if ix == nx - 1 else (e + 1, L_)
     if side == B_:
-        return None if iy == 0 else (e - n, T_)
-    return None if iy == n - 1 else (e + n, B_)
+        return None if iy == 0 else (e - nx, T_)
+    return None if iy == ny - 1 else (e + nx, B_)
 
 
 def box_side_slots(n, p, level, bx, by, side):
     """Canonical slots of one side of box (bx, by), increasing coordinate."""
-    wx, wy = box_dims(level)
+    wx, wy = box_dims(level, n)
     out = []
     if side in (L_, R_):
         ix = bx * wx if side == L_ else bx * wx + wx - 1
@@ -123,13 +155,13 @@ def box_side_physical(n, level, bx, by, side):
 def box_local_physical_mask(n, p, level, bx, by):
     """Boolean mask over the box-local boundary order: True on physical nodes."""
     return np.concatenate([
-        np.full(side_len(level, s, p), box_side_physical(n, level, bx, by, s))
+        np.full(side_len(level, s, p, n), box_side_physical(n, level, bx, by, s))
         for s in range(4)])
 
 
 def slot_partner(n, p):
     """Array: partner[s] = slot across the face from s, -1 if s is physical."""
-    E = n * n
+    E = num_elements(n)
     partner = -np.ones(E * 4 * p, dtype=np.int64)
     for e in range(E):
         for s in range(4):
@@ -160,7 +192,7 @@ def pairs(n, level):
     P, Q in the level-`level` box grid, M the merged box at level+1."""
     nbx, nby = box_grid(n, level)
     out = []
-    if merge_axis(level) == "x":
+    if merge_axis(level, n) == "x":
         for by in range(nby):
             for px in range(nbx // 2):
                 out.append(((2 * px, by), (2 * px + 1, by), (px, by)))
@@ -174,10 +206,11 @@ def pairs(n, level):
 def element_node_coords(n, N, xi):
     """Physical node coordinates: arrays x[E, N+1, N+1], y[E, N+1, N+1]
     indexed [e, i, j] (i: x-index, j: y-index)."""
-    h = 1.0 / n
-    E = n * n
-    ix = np.arange(E) % n
-    iy = np.arange(E) // n
+    h = element_size(n)
+    nx, _ = dims(n)
+    E = num_elements(n)
+    ix = np.arange(E) % nx
+    iy = np.arange(E) // nx
     xr = (1.0 + xi) * h / 2
     X = ix[:, None, None] * h + xr[None, :, None] + 0 * xr[None, None, :]
     Y = iy[:, None, None] * h + xr[None, None, :] + 0 * xr[None, :, None]
@@ -200,7 +233,7 @@ def canonical_slot_coords(n, N, xi):
     """Coordinates (x, y) and outward normals (nx, ny) of every canonical slot."""
     p = N - 1
     X, Y = element_node_coords(n, N, xi)
-    E = n * n
+    E = num_elements(n)
     xs = np.zeros(E * 4 * p)
     ys = np.zeros(E * 4 * p)
     nx = np.zeros(E * 4 * p)
@@ -217,7 +250,7 @@ def canonical_slot_coords(n, N, xi):
 
 
 def physical_slot_mask(n, p):
-    E = n * n
+    E = num_elements(n)
     mask = np.zeros(E * 4 * p, dtype=bool)
     for e in range(E):
         for s in range(4):

@@ -27,7 +27,7 @@ def assemble(n, p, level, boxT):
 
     boxT: dict (bx, by) -> box ItI map in box-local [l; r; b; t] order."""
     unk = mesh.interior_slots(n, p, level)
-    where = -np.ones(n * n * 4 * p, dtype=np.int64)
+    where = -np.ones(mesh.num_elements(n) * 4 * p, dtype=np.int64)
     where[unk] = np.arange(len(unk))
     partner = mesh.slot_partner(n, p)
     rows, cols, vals = [list(range(len(unk)))], [list(range(len(unk)))], [np.ones(len(unk))]
@@ -55,7 +55,7 @@ def rhs(n, p, leafT, leafH, t_slots):
 
     leafT [E, 4p, 4p], leafH [E, 4p]; t_slots: incoming data t at every
     canonical slot (only physical slots are read)."""
-    E = n * n
+    E = mesh.num_elements(n)
     phys = mesh.physical_slot_mask(n, p)
     partner = mesh.slot_partner(n, p)
     out = np.zeros(E * 4 * p, dtype=complex)
@@ -71,7 +71,8 @@ def rhs(n, p, leafT, leafH, t_slots):
 
 def leaf_boxT(n, leafT):
     """Level-1 boxes are the elements; box-local order equals the element's."""
-    return {(e % n, e // n): leafT[e] for e in range(n * n)}
+    nx = mesh.dims(n)[0]
+    return {(e % nx, e // nx): leafT[e] for e in range(mesh.num_elements(n))}
 
 
 def apply(n, p, level, boxT, g):
