@@ -81,7 +81,8 @@ typedef enum { HPS_FP64 = 0, HPS_MIXED = 1 } hps_precision;
    levels run in complex FP32 (FP32 MFMA, FP64 vectors); merges L-2 and L-1,
    the coarse solve, Arnoldi and all residuals run in FP64. */
 typedef struct {
-  int32_t n;             /* elements per side, power of two, 2 <= n <= 1024   */
+  int32_t n;             /* elements along x (per side of a square mesh), a
+                            power of two, 1 <= n <= 1024 (ny below)           */
   int32_t order;         /* GLL order N, 2 <= N <= 16                          */
   double kappa;          /* wavenumber kappa > 0 (c = kappa^2 (1 - b))         */
   double eta;            /* impedance parameter eta > 0 (the paper: eta=kappa) */
@@ -96,6 +97,13 @@ typedef struct {
                             y = 0 (MG_{l+1} is called gamma^(l-1) times per
                             application at level l)                           */
   int32_t restart;       /* FGMRES restart length, 1..200 [60]                 */
+  int32_t ny;            /* elements along y, a power of two in [1, 1024];
+                            0 => n (a square mesh).  An nx x ny mesh (nx = n,
+                            nx ny >= 2) takes square elements of side
+                            h = 1/max(nx, ny) on (0, nx h) x (0, ny h), element
+                            e = ix + nx iy; merges alternate x, y while both
+                            directions have merges left, then run along the
+                            longer one (L_max = log2(nx ny))                   */
 } hps_desc;
 
 /* Per-problem result of hps_gmres_solve ([host]).  Times are device times

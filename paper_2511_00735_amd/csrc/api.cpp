@@ -85,7 +85,7 @@ struct Level {
 // vectors of the group one vector of nq * nslots entries.
 struct Layout {
   int nq;
-  int n, N, p, E, L, Lmax, k, restart;
+  int nx, ny, N, p, E, L, Lmax, k, restart;  // mesh nx x ny elements
   int gamma;             // coarse calls per level (1: V-cycle)
   size_t gam_off = 0;    // gamma > 1: per level l < L the vectors W, Y, R, D (see mg_gamma)
   bool exact, mixed;
@@ -106,15 +106,20 @@ struct Layout {
   size_t total;
 };
 
+// Elements along y (0 in the descriptor: a square mesh) and the element side:
+// square elements of side 1 / max(nx, ny) on (0, nx h) x (0, ny h).
+inline int desc_ny(const hps_desc* d) { return d->ny ? d->ny : d->n; }
+inline double element_size(int nx, int ny) { return 1.0 / std::max(nx, ny); }
+
 int ilog2(int v) {
   int q = 0;
   while ((1 << q) < v) ++q;
   return q;
 }
 
-Level make_level(int n, int p, int l) {
+Level make_level(int nx, int ny, int p, int l) {
   Level lv;
-  lv.g = make_geom(n, p, l);
+  lv.g = make_geom(nx, ny, p, l);
   return lv;
 }
 
@@ -123,7 +128,7 @@ void set_merge_geom(Level& lv) {
   const Geom& g = lv.g;
   lv.has_merge = true;
   lv.pairs = g.nboxes / 2;
-  lv.axis = (g.level % 2 == 1) ? 0 : 1;
+  lv.axis = merge_axis_of(g.ax, g.ay, g.level);
   if (lv.axis == 0) {  // x-merge: alpha = r of P, beta = l of Q
     lv.m = g.off[2] - g.off[1];
     lv.a0 = g.off[1];
@@ -208,7 +213,7 @@ void pair_tables(const Level& lv, std::vector<int>& xt, std::vector<int>& yt, st
         } else {
           const int s = box_slot(g, bx, by, k);
           yt.push_back(s);
-          dt.push_back(slot_partner(g.n, g.p, s));
+          dt.push_back(slot_partner(g.nx, g.ny, g.p, s));
         }
       }
     }
@@ -217,11 +222,14 @@ void pair_tables(const Level& lv, std::vector<int>& xt, std::vector<int>& yt, st
 
 const char* check_desc(const hps_desc* d) {
   if (!d) return "null descriptor";
-  if (d->n < 2 || d->n > 1024 || (d->n & (d->n - 1))) return "n must be a power of two in [2, 1024]";
+  const int ny = desc_ny(d);
+  if (d->n < 1 || d->n > 1024 || (d->n & (d->n - 1)) || ny < 1 || ny > 1024 || (ny & (ny - 1)) ||
+      d->n * ny < 2)
+    return "n and ny must be powers of two in [1, 1024] with at least two elements";
   if (d->order < 2 || d->order > 16) return "order N must be in [2, 16]";
   if (!(std::isfinite(d->kappa) && d->kappa > 0)) return "kappa must be finite and > 0";
   if (!(std::isfinite(d->eta) && d->eta > 0)) return "eta must be finite and > 0";
-  const int Lmax = 2 * ilog2(d->n);
+  const int Lmax = ilog2(d->n) + ilog2(ny);
   if (d->levels < 0 || d->levels > Lmax) return "levels out of range";
   if (d->coarse_iters == 0 || d->coarse_iters < -1 || d->coarse_iters > kMaxCoarse)
     return "coarse_iters must be -1 (exact) or 1..32";
@@ -239,11 +247,12 @@ inline size_t hh_stride(int restart) { return (size_t)2 * (restart + 2) + 4; }
 Layout make_layout(const hps_desc* d, int nq) {
   Layout lay;
   lay.nq = nq;
-  lay.n = d->n;
+  lay.nx = d->n;
+  lay.ny = desc_ny(d);
   lay.N = d->order;
   lay.p = d->order - 1;
-  lay.E = d->n * d->n;
-  lay.Lmax = 2 * ilog2(d->n);
+  lay.E = lay.nx * lay.ny;
+  lay.Lmax = ilog2(lay.nx) + ilog2(lay.ny);
   lay.L = d->levels ? d->levels : lay.Lmax;
   lay.exact = (d->coarse_iters == -1);
   lay.mixed = (d->precision == HPS_MIXED);
@@ -262,7 +271,7 @@ Layout make_layout(const hps_desc* d, int nq) {
   size_t merge_scratch = 0;
   for (int l = 1; l <= lay.L; ++l) {
     Level& lv = lay.lev[l];
-    lv = make_level(lay.n, lay.p, l);
+    lv = make_level(lay.nx, lay.ny, lay.p, l);
     // mixed precision: merges 1 .. L-3 (and the V-cycle on those levels) in FP32,
     // the top two merges, the coarse level and the outer operator in FP64
     lv.f32 = lay.mixed && l <= lay.L - 3;
@@ -826,7 +835,10 @@ hps_status coarse_solve(hps_problem* p, cd* wv, cd* z) {
       const int m = nL / 2;
       const cd* T = Tlev(p, lay.L);
       const long long ts = 2LL * b * b;  // one problem's two top boxes
-      const int aP = top.g.off[3], bQ = top.g.off[2];   // P's top side, Q's bottom side
+      // the shared face: P's right and Q's left side (a merge along x, e.g. the
+      // last merge of a wide rectangular mesh), else P's top and Q's bottom
+      const bool along_x = merge_axis_of(top.g.ax, top.g.ay, lay.L) == 0;
+      const int aP = along_x ? top.g.off[1] : top.g.off[3], bQ = along_x ? top.g.off[0] : top.g.off[2];
       GemvDesc d[2] = {gdesc<cd>(m, m, Operand{T + (size_t)b * b, ts, b, im_off(bQ), im_off(bQ)},
                                  vin_compact(vj + m, vq), vout_compact(nullptr, 0)),
                        gdesc<cd>(m, m, Operand{T, ts, b, im_off(aP), im_off(aP)}, vin_compact(vj, vq),
@@ -1002,7 +1014,7 @@ hps_status read_flag(hps_problem* p, int first = 0) {
     const long long q = G / lay.E, e = G % lay.E;
     return fail(p->ctx, HPS_ERR_ARG,
                 "non-finite value in b_nodes or s_nodes of problem " + std::to_string(first + q) + ", element " +
-                    std::to_string(e) + " (ix " + std::to_string(e % lay.n) + ", iy " + std::to_string(e / lay.n) +
+                    std::to_string(e) + " (ix " + std::to_string(e % lay.nx) + ", iy " + std::to_string(e / lay.nx) +
                     "); its leaf map was not built");
   }
   if (f[0] & kFlagSingular) {
@@ -1530,7 +1542,7 @@ hps_status hps_workspace_bytes(const hps_desc* desc, size_t* bytes) {
 hps_status hps_choose_levels(const hps_desc* desc, int32_t count, size_t budget, int32_t* levels) {
   if (!levels || check_desc(desc) || count < 1 || count > kMaxGroup) return HPS_ERR_ARG;
   hps_desc d = *desc;
-  const int Lmax = 2 * ilog2(d.n);
+  const int Lmax = ilog2(d.n) + ilog2(desc_ny(&d));
   // the exact coarse solve exists only at the top level
   const int lo = d.coarse_iters == -1 ? Lmax : 1;
   for (int L = Lmax; L >= lo; --L) {
@@ -1558,11 +1570,11 @@ hps_status hps_gll_nodes(int32_t order, double* xi) {
 
 hps_status hps_node_coords(const hps_desc* desc, double* x, double* y) {
   if (check_desc(desc) || !x || !y) return HPS_ERR_ARG;
-  const int n = desc->n, N = desc->order, N1 = N + 1;
-  const double h = 1.0 / n;
+  const int nx = desc->n, ny = desc_ny(desc), N = desc->order, N1 = N + 1;
+  const double h = element_size(nx, ny);
   GllTables t = gll_tables(N);
-  for (int e = 0; e < n * n; ++e) {
-    const int ix = e % n, iy = e / n;
+  for (int e = 0; e < nx * ny; ++e) {
+    const int ix = e % nx, iy = e / nx;
     for (int i = 0; i <= N; ++i)
       for (int j = 0; j <= N; ++j) {
         const size_t q = (size_t)e * N1 * N1 + i * N1 + j;
@@ -1575,12 +1587,12 @@ hps_status hps_node_coords(const hps_desc* desc, double* x, double* y) {
 
 hps_status hps_slot_coords(const hps_desc* desc, double* x, double* y, double* nx, double* ny) {
   if (check_desc(desc) || !x || !y || !nx || !ny) return HPS_ERR_ARG;
-  const int n = desc->n, N = desc->order, p = N - 1;
-  const double h = 1.0 / n;
+  const int mx = desc->n, my = desc_ny(desc), N = desc->order, p = N - 1;
+  const double h = element_size(mx, my);
   GllTables t = gll_tables(N);
   const double nrm[4][2] = {{-1, 0}, {1, 0}, {0, -1}, {0, 1}};
-  for (int e = 0; e < n * n; ++e) {
-    const int ix = e % n, iy = e / n;
+  for (int e = 0; e < mx * my; ++e) {
+    const int ix = e % mx, iy = e / mx;
     for (int s = 0; s < 4; ++s)
       for (int k = 0; k < p; ++k) {
         const size_t q = ((size_t)e * 4 + s) * p + k;
@@ -1666,10 +1678,13 @@ hps_status hps_build_leaves(hps_problem* const* pp, int32_t count, const double*
       if (!b_nodes[base + q]) return fail(p->ctx, HPS_ERR_ARG, "null b_nodes");
     const int N1 = lay.N + 1;
     LeafArgs a{};
-    a.n = lay.n;
+    a.nx = lay.nx;
+    a.ny = lay.ny;
+    a.ax = ilog2(lay.nx);
+    a.ay = ilog2(lay.ny);
     a.N = lay.N;
     a.E = lay.E;
-    a.h = 1.0 / lay.n;
+    a.h = element_size(lay.nx, lay.ny);
     const double* tab = at<double>(p, lay.tables_off);
     a.D = tab;
     a.w = tab + N1 * N1;
@@ -1827,10 +1842,11 @@ hps_status hps_recover_field(hps_problem* const* pp, int32_t count, const double
         return fail(p->ctx, HPS_ERR_ARG, "null b_nodes, t, g or u");
     const int N = lay.N, N1 = N + 1;
     FieldArgs a{};
-    a.n = lay.n;
+    a.nx = lay.nx;
+    a.ny = lay.ny;
     a.N = N;
     a.E = lay.E;
-    a.h = 1.0 / lay.n;
+    a.h = element_size(lay.nx, lay.ny);
     const double* tab = at<double>(p, lay.tables_off);
     a.D = tab;
     a.w = tab + N1 * N1;

@@ -80,26 +80,66 @@ __host__ __device__ inline IdxMap im_gap(int off, int gap_start, int gap_len) {
 __host__ __device__ inline IdxMap im_tab(const int* tab) { return IdxMap{tab, 0, 1 << 30, 0}; }
 
 // ---------------------------------------------------------------------------
-// Merge-tree geometry.  Level l (1-based) boxes are wx x wy elements with
-// wx = 2^floor(l/2), wy = 2^floor((l-1)/2).  Boxes of every level are stored in
-// merge-tree order: box j covers the elements whose Morton code (x bits at even
-// positions, y bits at odd positions) shifted right by l-1 equals j, so the
-// pair merged at level l is (2j, 2j+1) and produces box j of level l+1.
+// Merge-tree geometry of an nx x ny mesh (both powers of two, 2^ax x 2^ay).
+// Merge l (1-based) joins pairs of level-l boxes along x when l is odd and
+// along y when l is even while both directions have merges left (the first
+// 2 min(ax, ay) merges; all of them on a square mesh), and along the longer
+// direction after that.  A level-l box is 2^dx x 2^dy elements, dx and dy
+// the merges along x and y among merges 1..l-1.  Boxes of every level are
+// stored in merge-tree order: an element's tree code has bit l-1 equal to the
+// bit of its x or y index that merge l consumes (the next unused one of that
+// direction), and box j of level l covers the elements whose code shifted
+// right by l-1 equals j, so the pair merged at level l is (2j, 2j+1) and
+// produces box j of level l+1.  On a square mesh the code is the Morton code
+// (x bits at even positions, y bits at odd positions).
 struct Geom {
-  int n, p, level;
+  int nx, ny, ax, ay, p, level;
   int wx, wy, nbx, nby, nboxes, b;
   int off[5];  // side offsets in the box-local [l; r; b; t] order
 };
 
-inline Geom make_geom(int n, int p, int level) {
+// 0: merge l runs along x, 1: along y.
+__host__ __device__ inline int merge_axis_of(int ax, int ay, int l) {
+  const int c = ax < ay ? ax : ay;
+  if (l <= 2 * c) return (l & 1) ? 0 : 1;
+  return ax > ay ? 0 : 1;
+}
+
+// Merges along x (dx) and y (dy) among merges 1..l-1.
+__host__ __device__ inline void merges_before(int ax, int ay, int l, int& dx, int& dy) {
+  const int c = ax < ay ? ax : ay, k = l - 1;
+  if (k <= 2 * c) {
+    dx = (k + 1) / 2;
+    dy = k / 2;
+  } else if (ax > ay) {
+    dx = k - c;
+    dy = c;
+  } else {
+    dx = c;
+    dy = k - c;
+  }
+}
+
+inline int log2_exact(int v) {
+  int q = 0;
+  while ((1 << q) < v) ++q;
+  return q;
+}
+
+inline Geom make_geom(int nx, int ny, int p, int level) {
   Geom g;
-  g.n = n;
+  g.nx = nx;
+  g.ny = ny;
+  g.ax = log2_exact(nx);
+  g.ay = log2_exact(ny);
   g.p = p;
   g.level = level;
-  g.wx = 1 << (level / 2);
-  g.wy = 1 << ((level - 1) / 2);
-  g.nbx = n / g.wx;
-  g.nby = n / g.wy;
+  int dx, dy;
+  merges_before(g.ax, g.ay, level, dx, dy);
+  g.wx = 1 << dx;
+  g.wy = 1 << dy;
+  g.nbx = nx / g.wx;
+  g.nby = ny / g.wy;
   g.nboxes = g.nbx * g.nby;
   g.off[0] = 0;
   g.off[1] = g.wy * p;
@@ -110,30 +150,39 @@ inline Geom make_geom(int n, int p, int level) {
   return g;
 }
 
-__host__ __device__ inline uint32_t morton_xy(uint32_t x, uint32_t y) {
+// Tree code of element (x, y) (its level-1 box index) and its inverse.
+__host__ __device__ inline uint32_t tree_code(int ax, int ay, uint32_t x, uint32_t y) {
+  const int c = ax < ay ? ax : ay;
   uint32_t code = 0;
-  for (int k = 0; k < 16; ++k) {
+  for (int k = 0; k < c; ++k) {
     code |= ((x >> k) & 1u) << (2 * k);
     code |= ((y >> k) & 1u) << (2 * k + 1);
   }
+  code |= (ax > ay ? (x >> c) : (y >> c)) << (2 * c);
   return code;
 }
 
-__host__ __device__ inline void box_xy(const Geom& g, int j, int& bx, int& by) {
-  const int shift = g.level - 1;
-  const uint32_t code = (uint32_t)j << shift;
-  uint32_t ex = 0, ey = 0;
-  for (int k = 0; k < 16; ++k) {
-    ex |= ((code >> (2 * k)) & 1u) << k;
-    ey |= ((code >> (2 * k + 1)) & 1u) << k;
+__host__ __device__ inline void tree_decode(int ax, int ay, uint32_t code, uint32_t& x, uint32_t& y) {
+  const int c = ax < ay ? ax : ay;
+  x = 0;
+  y = 0;
+  for (int k = 0; k < c; ++k) {
+    x |= ((code >> (2 * k)) & 1u) << k;
+    y |= ((code >> (2 * k + 1)) & 1u) << k;
   }
-  bx = (int)(ex >> ((shift + 1) / 2));
-  by = (int)(ey >> (shift / 2));
+  if (ax > ay) x |= (code >> (2 * c)) << c;
+  else y |= (code >> (2 * c)) << c;
+}
+
+__host__ __device__ inline void box_xy(const Geom& g, int j, int& bx, int& by) {
+  uint32_t ex, ey;
+  tree_decode(g.ax, g.ay, (uint32_t)j << (g.level - 1), ex, ey);
+  bx = (int)(ex / (uint32_t)g.wx);
+  by = (int)(ey / (uint32_t)g.wy);
 }
 
 __host__ __device__ inline int box_index(const Geom& g, int bx, int by) {
-  const int shift = g.level - 1;
-  return (int)(morton_xy((uint32_t)bx * g.wx, (uint32_t)by * g.wy) >> shift);
+  return (int)(tree_code(g.ax, g.ay, (uint32_t)bx * g.wx, (uint32_t)by * g.wy) >> (g.level - 1));
 }
 
 __host__ __device__ inline int side_of(const Geom& g, int k) {
@@ -155,19 +204,20 @@ __host__ __device__ inline int box_slot(const Geom& g, int bx, int by, int k) {
   else if (s == 1) { ex = bx * g.wx + g.wx - 1; ey = by * g.wy + q; }
   else if (s == 2) { ex = bx * g.wx + q; ey = by * g.wy; }
   else { ex = bx * g.wx + q; ey = by * g.wy + g.wy - 1; }
-  return ((ex + g.n * ey) * 4 + s) * g.p + r;
+  return ((ex + g.nx * ey) * 4 + s) * g.p + r;
 }
 
-// Slot across the face from canonical slot `s`, or -1 on the physical boundary.
-__host__ __device__ inline int slot_partner(int n, int p, int s) {
+// Slot across the face from canonical slot `s` of an nx x ny mesh, or -1 on
+// the physical boundary.
+__host__ __device__ inline int slot_partner(int nx, int ny, int p, int s) {
   const int k = s % p;
   const int side = (s / p) & 3;
   const int e = s / (4 * p);
-  const int ix = e % n, iy = e / n;
+  const int ix = e % nx, iy = e / nx;
   if (side == 0) return ix == 0 ? -1 : (((e - 1) * 4 + 1) * p + k);
-  if (side == 1) return ix == n - 1 ? -1 : (((e + 1) * 4 + 0) * p + k);
-  if (side == 2) return iy == 0 ? -1 : (((e - n) * 4 + 3) * p + k);
-  return iy == n - 1 ? -1 : (((e + n) * 4 + 2) * p + k);
+  if (side == 1) return ix == nx - 1 ? -1 : (((e + 1) * 4 + 0) * p + k);
+  if (side == 2) return iy == 0 ? -1 : (((e - nx) * 4 + 3) * p + k);
+  return iy == ny - 1 ? -1 : (((e + nx) * 4 + 2) * p + k);
 }
 
 // Allow up to `bytes` of dynamic LDS for `kernel` (gfx950 has 160 KB per CU).

@@ -22,7 +22,8 @@ constexpr int kLeafMaxQ = 32;  // problems one leaf launch may touch
 // problem q = G / E, element e = G % E (canonical numbering).  Per-problem
 // inputs of problems q0 .. q0+kLeafMaxQ-1 travel in the kernel arguments.
 struct LeafArgs {
-  int n, N, E, G0, count, q0;
+  int nx, ny, ax, ay;  // mesh nx x ny = 2^ax x 2^ay elements (element e = ix + nx iy)
+  int N, E, G0, count, q0;
   double h;
   const double* b_nodes[kLeafMaxQ];  // [E][(N+1)^2] per problem
   const double* s_nodes[kLeafMaxQ];  // complex [E][(N+1)^2] per problem, or null
@@ -31,7 +32,7 @@ struct LeafArgs {
   const double* w;            // N+1
   const double* Kr;           // (N+1)^2 reference stiffness
   double* scratch;            // leaf_scratch_doubles(N, count) doubles, 16-byte aligned
-  cd* T;                      // level-1 box maps, [q][E][4p][4p], Morton order within a problem
+  cd* T;                      // level-1 box maps, [q][E][4p][4p], merge-tree order within a problem
   cd* H;                      // [q][E][4p] canonical element order
   int* flag;                  // the problem's error words (common.h)
   int* fb_list;               // [1 + count]: count, then elements G whose interior
@@ -46,7 +47,7 @@ hipError_t leaf_build(const LeafArgs& a, hipStream_t st);
 // skeleton solution g and boundary data t (canonical vectors per problem).
 constexpr int kFieldMaxQ = 64;  // problems of one launch
 struct FieldArgs {
-  int n, N, E, count;
+  int nx, ny, N, E, count;
   double h;
   const double* b_nodes[kFieldMaxQ];
   const double* s_nodes[kFieldMaxQ];

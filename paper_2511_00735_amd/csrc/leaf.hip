@@ -337,8 +337,8 @@ __device__ void leaf_cayley(const LeafArgs& a, const Dims& d, const double* A, d
     }
     __syncthreads();
   }
-  const int ix = e % a.n, iy = e / a.n;
-  cd* Tout = a.T + (a.linear_out ? (size_t)G : ((size_t)q * a.E + morton_xy(ix, iy))) * m * m;
+  const int ix = e % a.nx, iy = e / a.nx;
+  cd* Tout = a.T + (a.linear_out ? (size_t)G : ((size_t)q * a.E + tree_code(a.ax, a.ay, ix, iy))) * m * m;
   const double te = 2.0 * eta;
   cd hacc = cmk(0.0, 0.0);
 #pragma unroll
@@ -850,8 +850,8 @@ __global__ __launch_bounds__(kThreads) void leaf_fallback_kernel(LeafArgs a) {
     element_lu_solve(S, nloc, nrhs, a.flag, G);
     // T = I_o X on the boundary columns, H = I_o x on the load column; row i
     // of N_G has p + 2 entries (K's items of boundary row i)
-    const int ix = e % a.n, iy = e / a.n;
-    cd* Tout = a.T + (a.linear_out ? (size_t)G : ((size_t)q * a.E + morton_xy(ix, iy))) * m * m;
+    const int ix = e % a.nx, iy = e / a.nx;
+    cd* Tout = a.T + (a.linear_out ? (size_t)G : ((size_t)q * a.E + tree_code(a.ax, a.ay, ix, iy))) * m * m;
     const int nb0 = npiv * (2 * d.p + 5);   // first item of the boundary rows
     for (int idx = tid; idx < m * nrhs; idx += kThreads) {
       const int i = idx % m, j = idx / m;
@@ -888,7 +888,7 @@ __global__ __launch_bounds__(kThreads) void field_kernel(FieldArgs a) {
   __shared__ cd uc[4][2];   // corner extrapolations: [corner][along y, along x]
   for (int G = blockIdx.x; G < a.count; G += gridDim.x) {
     const int q = G / a.E, e = G % a.E;
-    const int ix = e % a.n, iy = e / a.n;
+    const int ix = e % a.nx, iy = e / a.nx;
     const double eta = a.eta[q];
     const double* sq = a.s_nodes[q];
     const ElemK K{d.N, d.p, d.pp, nloc, a.D, a.w, a.Kr, a.b_nodes[q] + (size_t)e * N1 * N1,
@@ -899,8 +899,8 @@ __global__ __launch_bounds__(kThreads) void field_kernel(FieldArgs a) {
     const cd* t = a.t[q];
     for (int k = tid; k < 4 * p; k += kThreads) {
       const int side = k / p;
-      const bool phys = (side == 0 && ix == 0) || (side == 1 && ix == a.n - 1) || (side == 2 && iy == 0) ||
-                        (side == 3 && iy == a.n - 1);
+      const bool phys = (side == 0 && ix == 0) || (side == 1 && ix == a.nx - 1) || (side == 2 && iy == 0) ||
+                        (side == 3 && iy == a.ny - 1);
       const size_t slot = (size_t)e * 4 * p + k;
       S[(size_t)nloc * nloc + npiv + k] = phys ? t[slot] : g[slot];
     }

@@ -112,7 +112,8 @@ extern "C" hps_status hps_leaf_maps_noalloc(hps_ctx* ctx, int32_t order, double 
   if (e != hipSuccess) return fail(HPS_ERR_HIP, std::string("upload: ") + hipGetErrorString(e));
   int* flag = reinterpret_cast<int*>(base + c.flag);
   LeafArgs a{};
-  a.n = count;
+  a.nx = count;   // elements in call order (the output is linear, so no tree order)
+  a.ny = 1;
   a.N = order;
   a.E = count;
   a.G0 = 0;

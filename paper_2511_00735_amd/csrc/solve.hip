@@ -68,7 +68,7 @@ __global__ __launch_bounds__(kRows) void skeleton_apply_kernel(Geom g, const M* 
     }
     for (; c < c1; ++c) acc = cfma(to_cd(Tb[(long long)c * b + r]), gB[c], acc);
   }
-  const int ps = slot_partner(g.n, g.p, slot);
+  const int ps = slot_partner(g.nx, g.ny, g.p, slot);
   out[ps] = csub(gin[ps], acc);
 }
 
@@ -77,10 +77,10 @@ __global__ __launch_bounds__(kRows) void rhs_kernel(Geom g, const cd* T, const c
                                                     cd* rhs) {
   __shared__ cd tl[256];
   const int e = blockIdx.x;
-  const int n = g.n, p = g.p, m = 4 * p;
-  const int ix = e % n, iy = e / n;
-  const cd* Te = T + (long long)morton_xy(ix, iy) * m * m;
-  bool phys[4] = {ix == 0, ix == n - 1, iy == 0, iy == n - 1};
+  const int p = g.p, m = 4 * p;
+  const int ix = e % g.nx, iy = e / g.nx;
+  const cd* Te = T + (long long)tree_code(g.ax, g.ay, ix, iy) * m * m;
+  bool phys[4] = {ix == 0, ix == g.nx - 1, iy == 0, iy == g.ny - 1};
   for (int k = threadIdx.x; k < m; k += kRows) {
     const int s = k / p;
     tl[k] = phys[s] ? t[(long long)e * m + k] : cmk(0.0, 0.0);
@@ -96,7 +96,7 @@ __global__ __launch_bounds__(kRows) void rhs_kernel(Geom g, const cd* T, const c
     cd acc = H ? H[(long long)e * m + r] : cmk(0.0, 0.0);
     for (int c = 0; c < m; ++c)
       if (phys[c / p]) acc = cfma(Te[(long long)c * m + r], tl[c], acc);
-    rhs[slot_partner(n, p, slot)] = acc;
+    rhs[slot_partner(g.nx, g.ny, p, slot)] = acc;
   }
 }
 
@@ -571,7 +571,7 @@ template <class M>
 hipError_t skeleton_apply_t(const Geom& g, const M* T, const cd* gin, cd* out, bool zero_physical,
                             hipStream_t st, int nq) {
   dim3 grid(g.nboxes * nq, (g.b + kRows - 1) / kRows);
-  const long long nslots = (long long)g.n * g.n * 4 * g.p;
+  const long long nslots = (long long)g.nx * g.ny * 4 * g.p;
   hipError_t e0 = allow_lds(skeleton_apply_kernel<M>, (size_t)g.b * sizeof(cd));
   if (e0 != hipSuccess) return e0;
   hipLaunchKernelGGL(skeleton_apply_kernel<M>, grid, dim3(kRows), (size_t)g.b * sizeof(cd), st, g, T, gin,
@@ -591,7 +591,7 @@ hipError_t skeleton_apply(const Geom& g, const cf* T, const cd* gin, cd* out, bo
 }
 
 hipError_t rhs_build(const Geom& g, const cd* T, const cd* H, const cd* t, cd* rhs, hipStream_t st) {
-  hipLaunchKernelGGL(rhs_kernel, dim3(g.n * g.n), dim3(kRows), 0, st, g, T, H, t, rhs);
+  hipLaunchKernelGGL(rhs_kernel, dim3(g.nx * g.ny), dim3(kRows), 0, st, g, T, H, t, rhs);
   return hipPeekAtLastError();
 }
 

@@ -36,7 +36,12 @@ class Desc(ctypes.Structure):
                 ("kappa", ctypes.c_double), ("eta", ctypes.c_double),
                 ("precision", ctypes.c_int32), ("levels", ctypes.c_int32),
                 ("coarse_iters", ctypes.c_int32), ("gamma", ctypes.c_int32),
-                ("restart", ctypes.c_int32)]
+                ("restart", ctypes.c_int32), ("ny", ctypes.c_int32)]
+
+
+def mesh_dims(desc):
+    """(nx, ny) elements of a descriptor (ny 0: the square n x n mesh)."""
+    return desc.n, (desc.ny or desc.n)
 
 
 class Info(ctypes.Structure):
@@ -121,9 +126,10 @@ def _dptr(t):
 
 
 def make_desc(n, order, kappa, eta=None, levels=0, coarse_iters=5, restart=60,
-              precision=HPS_FP64, gamma=1):
+              precision=HPS_FP64, gamma=1, ny=0):
+    """n: elements along x (n x n when ny is 0); ny: elements along y."""
     return Desc(n, order, float(kappa), float(kappa if eta is None else eta), precision,
-                levels, coarse_iters, gamma, restart)
+                levels, coarse_iters, gamma, restart, ny)
 
 
 def workspace_bytes(desc):
@@ -161,7 +167,8 @@ def gll_nodes(order):
 
 
 def node_coords(desc):
-    E, N1 = desc.n * desc.n, desc.order + 1
+    nx, ny = mesh_dims(desc)
+    E, N1 = nx * ny, desc.order + 1
     x = np.zeros(E * N1 * N1)
     y = np.zeros(E * N1 * N1)
     rc = lib.hps_node_coords(ctypes.byref(desc), x.ctypes.data, y.ctypes.data)
@@ -171,7 +178,8 @@ def node_coords(desc):
 
 
 def slot_coords(desc):
-    ns = desc.n * desc.n * 4 * (desc.order - 1)
+    nx, ny = mesh_dims(desc)
+    ns = nx * ny * 4 * (desc.order - 1)
     arrs = [np.zeros(ns) for _ in range(4)]
     rc = lib.hps_slot_coords(ctypes.byref(desc), *[a.ctypes.data for a in arrs])
     if rc != HPS_OK:
@@ -228,8 +236,9 @@ class Problem:
         self.ctx = ctx
         self.desc = desc
         self.n, self.N = desc.n, desc.order
+        self.nx, self.ny = mesh_dims(desc)
         self.p = self.N - 1
-        self.E = self.n * self.n
+        self.E = self.nx * self.ny
         self.nslots = self.E * 4 * self.p
         self.bytes = workspace_bytes(desc)
         if workspace is None:
@@ -244,8 +253,8 @@ class Problem:
                                          ctypes.byref(h)), "hps_problem_create")
         self.handle = h
         self.count = 1
-        self.levels = desc.levels or 2 * int(round(np.log2(self.n)))
-        self.lmax = 2 * int(round(np.log2(self.n)))
+        self.lmax = int(round(np.log2(self.nx))) + int(round(np.log2(self.ny)))
+        self.levels = desc.levels or self.lmax
 
     def __del__(self):
         if getattr(self, "handle", None) and lib is not None:
@@ -365,11 +374,12 @@ class Group:
         self.desc = desc
         self.count = len(kappas)
         self.n, self.N = desc.n, desc.order
+        self.nx, self.ny = mesh_dims(desc)
         self.p = self.N - 1
-        self.E = self.n * self.n
+        self.E = self.nx * self.ny
         self.nslots = self.E * 4 * self.p
-        self.levels = desc.levels or 2 * int(round(np.log2(self.n)))
-        self.lmax = 2 * int(round(np.log2(self.n)))
+        self.lmax = int(round(np.log2(self.nx))) + int(round(np.log2(self.ny)))
+        self.levels = desc.levels or self.lmax
         self.bytes = group_workspace_bytes(desc, self.count)
         if workspace is None:
             workspace = torch.empty(self.bytes + 256, dtype=torch.uint8, device="cuda")
@@ -488,12 +498,32 @@ def gmres_solve(problems, rhs, g, tol=1e-10, maxit=600):
                  relres_true=i.relres_true, t_build_s=i.t_build_s, t_solve_s=i.t_solve_s) for i in infos]
 
 
+def tree_box_xy(level, j, nx=None, ny=None):
+    """(bx, by) of box j of a level in the library's merge-tree storage order on
+    an nx x ny mesh (None: a square mesh, where the order is the Morton order).
+    Bit l-1 of an element's tree code is the next unused bit of its x index if
+    merge l runs along x, else of its y index."""
+    ax = ay = 64
+    if nx is not None:
+        ax, ay = int(round(np.log2(nx))), int(round(np.log2(ny)))
+    c = min(ax, ay)
+    code = j << (level - 1)
+    ex = ey = dx = dy = 0
+    for bit in range(40):
+        l = bit + 1
+        along_x = (l % 2 == 1) if l <= 2 * c else ax > ay
+        if along_x:
+            ex |= ((code >> bit) & 1) << dx
+            dx += 1
+        else:
+            ey |= ((code >> bit) & 1) << dy
+            dy += 1
+    # merges along x and y before this level
+    mx = sum(1 for l in range(1, level) if ((l % 2 == 1) if l <= 2 * c else ax > ay))
+    my = (level - 1) - mx
+    return ex >> mx, ey >> my
+
+
 def morton_box_xy(level, j):
-    """(bx, by) of box j of a level in the library's merge-tree storage order."""
-    shift = level - 1
-    code = j << shift
-    ex = ey = 0
-    for k in range(16):
-        ex |= ((code >> (2 * k)) & 1) << k
-        ey |= ((code >> (2 * k + 1)) & 1) << k
-    return ex >> ((shift + 1) // 2), ey >> (shift // 2)
+    """(bx, by) of box j of a level of a square mesh (merge-tree = Morton order)."""
+    return tree_box_xy(level, j)

@@ -108,3 +108,14 @@ def test_gamma_descriptor(hps):
     for bad in (5, -1):
         with pytest.raises(hps.HPSError):
             hps.workspace_bytes(hps.make_desc(16, 8, 20.0, gamma=bad))
+
+
+def test_rect_descriptor_checks(hps):
+    """Rectangular meshes: both sides powers of two, at least two elements;
+    ny = 0 is the square mesh; levels bounded by log2(nx ny)."""
+    for nx, ny in [(3, 4), (4, 6), (1, 1), (2048, 1)]:
+        with pytest.raises(hps.HPSError):
+            hps.workspace_bytes(hps.make_desc(nx, 4, 5.0, ny=ny))
+    assert hps.workspace_bytes(hps.make_desc(8, 4, 5.0, ny=8)) == hps.workspace_bytes(hps.make_desc(8, 4, 5.0))
+    with pytest.raises(hps.HPSError):
+        hps.workspace_bytes(hps.make_desc(8, 4, 5.0, ny=2, levels=5))   # L_max = 4
