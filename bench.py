@@ -395,6 +395,43 @@ def run_repeated_solves(hps, torch, pr, precision="mixed", nrhs=16):
             "single_solve_dof_per_s": round(pr.skeleton_dof / (build + solve), 1)}
 
 
+def run_rectangles(hps, torch, pr, precision="mixed", steps=3):
+    """The workload's 4096 elements, N and kappa on rectangular meshes
+    (128 x 32 and 32 x 128 elements of side 1/128, all 12 merge levels, the
+    same coarse solve and tolerance): build + solve per step, DOF/s and
+    iterations, beside the square 64 x 64 mesh of the headline."""
+    out = {}
+    prec = hps.HPS_MIXED if precision == "mixed" else hps.HPS_FP64
+    for nx, ny in ((128, 32), (32, 128)):
+        ctx = hps.Context()
+        desc = hps.make_desc(nx, pr.N, pr.kappa, pr.eta, coarse_iters=pr.coarse_iters, precision=prec, ny=ny)
+        prob = hps.Problem(ctx, desc)
+        b_nodes = prob.coefficient_nodes(pr.b)
+        t = prob.boundary_data(pr.wave.t)
+        rhs = torch.empty(prob.nslots, dtype=torch.complex128, device="cuda")
+        g = torch.empty_like(rhs)
+        dof = 4 * (pr.N - 1) * nx * ny - 2 * (pr.N - 1) * (nx + ny)
+
+        def step():
+            prob.build_leaves(b_nodes)
+            prob.merge_all()
+            hps.set_rhs([prob], [t], [rhs])
+            return prob.gmres_solve(rhs, tol=pr.tol, maxit=600, out=g)[1]
+
+        step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            info = step()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / steps * 1e3
+        out[f"{nx}x{ny}"] = {"skeleton_dof": dof, "ms_per_step": round(ms, 3),
+                             "dof_per_s": round(dof / ms * 1e3, 1), "iterations": info["iterations"],
+                             "relres_true": info["relres_true"]}
+        del prob, ctx
+    return {"precision": precision, "levels": 12, "meshes": out}
+
+
 def workloads_plane(pr, theta):
     from paper_2511_00735_amd import workloads
     return workloads.PlaneWave(pr.kappa, pr.eta, (math.cos(theta), math.sin(theta)))
@@ -549,6 +586,8 @@ def main():
         cfg["repeated_solves"] = {"mixed": run_repeated_solves(hps, torch, pr, "mixed"),
                                   "fp64": run_repeated_solves(hps, torch, pr, "fp64")}
         progress("repeated solves done")
+        cfg["rectangular_meshes"] = run_rectangles(hps, torch, pr)
+        progress("rectangular meshes done")
     if not args.no_batch:
         cfg["batch_256_problems"] = run_batch_c4(hps, torch)
         progress("256-problem batch done")
