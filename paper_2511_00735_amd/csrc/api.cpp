@@ -77,6 +77,9 @@ struct Level {
   size_t ytab_off = 0;  // int32 [pairs][2e]: canonical slots of y (-1: physical)
   size_t dtab_off = 0;  // int32 [pairs][2e]: slots across the face of y (-1: physical)
   size_t Z0_off = 0;    // complex FP64 [pairs][2m]: A^-1 r_x of the down sweep
+  // levels 1..K of a fused V-cycle launch: the slot tables as positions in the
+  // level-(K+1) box's LDS vector (int32 [pairs][2m], [pairs][2e], [pairs][2e])
+  size_t xl_off = 0, dl_off = 0, yl_off = 0;
 };
 
 // Workspace of a group of nq problems of one shape.  Every per-problem array
@@ -100,6 +103,10 @@ struct Layout {
   size_t cV_off, cw_off, cx_off, cidx_off, cH_off, cy_off, cs_off;  // coarse GMRES
   size_t part_off, hh_off, one_off, flag_off;
   size_t jctr_off;                 // int: the FGMRES iteration index of the captured iteration
+  // V-cycle levels 1..fuse in one launch per direction (0: none): per
+  // level-(fuse+1) box, fnloc local slots and their canonical slots (down and up sets)
+  int fuse = 0, fnloc = 0;
+  size_t fgd_off = 0, fgu_off = 0;
   size_t fb_off;                   // int [1 + leaf_chunk]: the leaf fallback's element list
   size_t ysol_off;                 // [nq][restart] FGMRES update coefficients
   size_t gpart_off, gpart_elems;  // split-K GEMV partial sums
@@ -220,6 +227,64 @@ void pair_tables(const Level& lv, std::vector<int>& xt, std::vector<int>& yt, st
   }
 }
 
+// Tables of the fused levels 1..K for one problem.  Box B of level K+1 holds
+// its elements' slots at local index (lx + wx ly) 4p + (side p + k).  The down
+// sweep's local set is the box's slots off its boundary plus, at the position
+// of each boundary slot, the slot across it (-1 where physical); the up sweep's
+// is every slot of the box.
+struct FusedTables {
+  std::vector<int> gdown, gup;
+  std::vector<std::vector<int>> xl, dl, yl;   // index: level
+};
+
+FusedTables fused_tables(const Layout& lay) {
+  const int K = lay.fuse, p = lay.p, m4 = 4 * p, nx = lay.nx, ny = lay.ny;
+  const Geom& gb = lay.lev[K + 1].g;
+  const int nloc = gb.wx * gb.wy * m4;
+  FusedTables ft;
+  ft.gdown.assign((size_t)gb.nboxes * nloc, -1);
+  ft.gup.assign((size_t)gb.nboxes * nloc, -1);
+  auto local_of = [&](int bx, int by, int s) {
+    const int e = s / m4, ix = e % nx, iy = e / nx;
+    const int lx = ix - bx * gb.wx, ly = iy - by * gb.wy;
+    if (lx < 0 || lx >= gb.wx || ly < 0 || ly >= gb.wy) return -1;
+    return (lx + gb.wx * ly) * m4 + s % m4;
+  };
+  for (int jb = 0; jb < gb.nboxes; ++jb) {
+    int bx, by;
+    box_xy(gb, jb, bx, by);
+    for (int i = 0; i < nloc; ++i) {
+      const int le = i / m4, ix = bx * gb.wx + le % gb.wx, iy = by * gb.wy + le / gb.wx;
+      const int s = (ix + nx * iy) * m4 + i % m4;
+      const int ps = slot_partner(nx, ny, p, s);
+      const bool boundary = ps < 0 || local_of(bx, by, ps) < 0;
+      ft.gup[(size_t)jb * nloc + i] = s;
+      ft.gdown[(size_t)jb * nloc + i] = boundary ? ps : s;
+    }
+  }
+  ft.xl.resize(K + 1);
+  ft.dl.resize(K + 1);
+  ft.yl.resize(K + 1);
+  for (int l = 1; l <= K; ++l) {
+    const Level& lv = lay.lev[l];
+    std::vector<int> xt, yt, dt;
+    pair_tables(lv, xt, yt, dt);
+    const int m2 = 2 * lv.m, e2 = 2 * lv.e;
+    for (int j = 0; j < lv.pairs; ++j) {
+      int bx, by;
+      box_xy(gb, j >> (K - l), bx, by);
+      for (int i = 0; i < m2; ++i) ft.xl[l].push_back(local_of(bx, by, xt[(size_t)j * m2 + i]));
+      for (int i = 0; i < e2; ++i) {
+        const int y = yt[(size_t)j * e2 + i], d = dt[(size_t)j * e2 + i];
+        ft.yl[l].push_back(y < 0 ? -1 : local_of(bx, by, y));
+        // across the face: inside the box, or outside it at the kept slot's position
+        ft.dl[l].push_back(d < 0 ? -1 : (local_of(bx, by, d) >= 0 ? local_of(bx, by, d) : local_of(bx, by, y)));
+      }
+    }
+  }
+  return ft;
+}
+
 const char* check_desc(const hps_desc* d) {
   if (!d) return "null descriptor";
   const int ny = desc_ny(d);
@@ -243,6 +308,40 @@ const char* check_desc(const hps_desc* d) {
 
 // Per-problem device scratch of the outer Arnoldi step: h (R+2), h2 (R+2), |w|^2, norm, spare.
 inline size_t hh_stride(int restart) { return (size_t)2 * (restart + 2) + 4; }
+
+// Shape-only arguments of the fused launch over levels 1..K (for the checks).
+FusedArgs fused_shape(const Layout& lay, int K) {
+  FusedArgs a{};
+  const Geom& gb = lay.lev[K + 1].g;
+  a.nloc = gb.wx * gb.wy * 4 * lay.p;
+  a.nloc_pad = (a.nloc + 3) & ~3;
+  for (int l = 1; l <= K; ++l) {
+    const Level& lv = lay.lev[l];
+    a.lev[l - 1].m = lv.m;
+    a.lev[l - 1].e = lv.e;
+  }
+  return a;
+}
+
+// The V-cycle's levels 1..K run in one launch per direction (one workgroup per
+// level-(K+1) box) when every one of them is a merged level of the level-1
+// precision with enough pairs for the two-workgroups-per-pair kernels and the
+// box's slots and the largest level's group buffers fit the LDS; K = 4 at
+// most (groups of 64 threads per pair half at level 1), 2 at least.
+void choose_fuse(Layout& lay) {
+  lay.fuse = 0;
+  if (lay.gamma > 1) return;   // the gamma-cycle revisits levels one at a time
+  int K = 0;
+  for (int k = 1; k <= kFuseMax && k + 1 <= lay.L; ++k) {
+    const Level& lv = lay.lev[k];
+    if (!lv.has_merge || lv.f32 != lay.lev[1].f32 || !vc_small_ok(lv.m, lv.e, lay.nq * lv.pairs)) break;
+    K = k;
+  }
+  while (K >= 2 && !fused_ok(fused_shape(lay, K), K)) --K;
+  if (K < 2) return;
+  lay.fuse = K;
+  lay.fnloc = fused_shape(lay, K).nloc;
+}
 
 Layout make_layout(const hps_desc* d, int nq) {
   Layout lay;
@@ -325,6 +424,19 @@ Layout make_layout(const hps_desc* d, int nq) {
   lay.hh_off = take(sizeof(cd) * Q * hh_stride(lay.restart));
   lay.one_off = take(sizeof(cd));
   lay.jctr_off = take(sizeof(int));
+  choose_fuse(lay);
+  if (lay.fuse) {
+    const Geom& gb = lay.lev[lay.fuse + 1].g;
+    lay.fgd_off = take(sizeof(int) * Q * gb.nboxes * lay.fnloc);
+    lay.fgu_off = take(sizeof(int) * Q * gb.nboxes * lay.fnloc);
+    for (int l = 1; l <= lay.fuse; ++l) {
+      Level& lv = lay.lev[l];
+      const size_t np = Q * lv.pairs;
+      lv.xl_off = take(sizeof(int) * np * 2 * lv.m);
+      lv.dl_off = take(sizeof(int) * np * 2 * lv.e);
+      lv.yl_off = take(sizeof(int) * np * 2 * lv.e);
+    }
+  }
   lay.ysol_off = take(sizeof(cd) * Q * lay.restart);
   {
     // split-K GEMV partials: at most two descriptors per launch, of the shapes
@@ -741,6 +853,35 @@ hps_status vcycle_up_t(hps_problem* p, int l, cd* z) {
   return HPS_OK;
 }
 
+// Levels 1..fuse of the down (r updated in place) or up (z) sweep in one launch.
+hipError_t fused_levels(hps_problem* p, bool down, cd* vec) {
+  const Layout& lay = p->lay;
+  const int K = lay.fuse;
+  FusedArgs a = fused_shape(lay, K);
+  a.gdown = at<int>(p, lay.fgd_off);
+  a.gup = at<int>(p, lay.fgu_off);
+  const bool f32 = lay.lev[1].f32;
+  for (int l = 1; l <= K; ++l) {
+    const Level& lv = lay.lev[l];
+    FusedLevel& L = a.lev[l - 1];
+    L.a0 = lv.a0;
+    L.b0 = lv.b0;
+    L.b = lv.g.b;
+    L.E1 = lv.E1;
+    L.E2 = lv.E2;
+    L.T = f32 ? (const void*)Tmat<cf>(p, l) : (const void*)Tmat<cd>(p, l);
+    L.Ainv = p->ws + lv.Ainv_off;
+    L.X = p->ws + lv.X_off;
+    L.xl = at<int>(p, lv.xl_off);
+    L.dl = at<int>(p, lv.dl_off);
+    L.yl = at<int>(p, lv.yl_off);
+    L.Z0 = at<cd>(p, lv.Z0_off);
+  }
+  const int boxes = lay.nq * lay.lev[K + 1].g.nboxes;
+  return f32 ? vc_fused<cf>(a, K, boxes, vec, down, p->ctx->stream)
+             : vc_fused<cd>(a, K, boxes, vec, down, p->ctx->stream);
+}
+
 hps_status vcycle_down(hps_problem* p, int l, cd* wv) {
   return p->lay.lev[l].f32 ? vcycle_down_t<cf>(p, l, wv) : vcycle_down_t<cd>(p, l, wv);
 }
@@ -877,16 +1018,18 @@ hps_status precond_one(hps_problem* p, const cd* r, cd* z) {
   cd* wv = workv(p, 0);
   const long long ntot = lay.nslots * lay.nq;
   HIPCHK(c, vcopy_zero(r, wv, z, ntot, st));   // wv = r, z = 0
-  for (int l = 1; l < lay.L; ++l) {
+  if (lay.fuse) HIPCHK(c, fused_levels(p, true, wv));
+  for (int l = lay.fuse + 1; l < lay.L; ++l) {
     hps_status s = vcycle_down(p, l, wv);
     if (s != HPS_OK) return s;
   }
   hps_status s = coarse_solve(p, wv, z);
   if (s != HPS_OK) return s;
-  for (int l = lay.L - 1; l >= 1; --l) {
+  for (int l = lay.L - 1; l > lay.fuse; --l) {
     s = vcycle_up(p, l, z);
     if (s != HPS_OK) return s;
   }
+  if (lay.fuse) HIPCHK(c, fused_levels(p, false, z));
   return HPS_OK;
 }
 
@@ -1401,6 +1544,22 @@ hps_status group_create(hps_ctx* ctx, const hps_desc* desc, int count, const dou
     HIPCHK(ctx, upload(lv.dtab_off, replicate(dt)));
   }
   if (!lay.exact && lay.nL > 0) HIPCHK(ctx, upload(lay.cidx_off, replicate(coarse_slots(lay.lev[lay.L]))));
+  if (lay.fuse) {
+    FusedTables ft = fused_tables(lay);
+    auto copies = [&](const std::vector<int>& one) {   // local indices: the same for every problem
+      std::vector<int> all;
+      all.reserve(one.size() * count);
+      for (int q = 0; q < count; ++q) all.insert(all.end(), one.begin(), one.end());
+      return all;
+    };
+    HIPCHK(ctx, upload(lay.fgd_off, replicate(ft.gdown)));
+    HIPCHK(ctx, upload(lay.fgu_off, replicate(ft.gup)));
+    for (int l = 1; l <= lay.fuse; ++l) {
+      HIPCHK(ctx, upload(lay.lev[l].xl_off, copies(ft.xl[l])));
+      HIPCHK(ctx, upload(lay.lev[l].dl_off, copies(ft.dl[l])));
+      HIPCHK(ctx, upload(lay.lev[l].yl_off, copies(ft.yl[l])));
+    }
+  }
   const cd one = cmk(1, 0);
   HIPCHK(ctx, hipMemcpyAsync(p->ws + lay.one_off, &one, sizeof(cd), hipMemcpyHostToDevice, ctx->stream));
   // error words: no flags, no first failure (records keep a minimum)

@@ -111,4 +111,35 @@ hipError_t vc_down_small(const SmallLevelT<M>& a, int pairs, cd* vec, hipStream_
 template <class M>
 hipError_t vc_up_small(const SmallLevelT<M>& a, int pairs, cd* z, hipStream_t st);
 
+// Levels 1..K (2 <= K <= kFuseMax) of the V-cycle in one launch, one
+// workgroup of 1024 threads per level-(K+1) box (`boxes` of them, problem after
+// problem), the box's slot values held in LDS.  Level l's pairs of box B are
+// B 2^(K-l) .. (B+1) 2^(K-l) - 1.  Tables hold local slot indices (positions
+// in the box's LDS vector); gdown/gup map each local index of box B to its
+// canonical slot (the down sweep's set: the box's non-boundary slots and the
+// slots across its boundary, -1 unused; the up sweep's: all slots of the
+// box's elements).  The operators are those of the per-level kernels.
+constexpr int kFuseMax = 4;
+struct FusedLevel {
+  int m, e, a0, b0, b;
+  IdxMap E1, E2;
+  const void* T;      // level-l box maps (storage type of the launch)
+  const void* Ainv;
+  const void* X;
+  const int* xl;      // [pairs][2m] local indices of x
+  const int* dl;      // [pairs][2e] local indices across y (-1: physical)
+  const int* yl;      // [pairs][2e] local indices of y (-1: physical)
+  cd* Z0;
+};
+struct FusedArgs {
+  int nloc, nloc_pad;
+  const int* gdown;   // [boxes][nloc]
+  const int* gup;     // [boxes][nloc]
+  FusedLevel lev[kFuseMax];
+};
+size_t fused_lds_bytes(const FusedArgs& a, int K, bool down);
+bool fused_ok(const FusedArgs& a, int K);
+template <class M>
+hipError_t vc_fused(const FusedArgs& a, int K, int boxes, cd* vec, bool down, hipStream_t st);
+
 }  // namespace hps

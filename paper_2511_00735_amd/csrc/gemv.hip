@@ -158,9 +158,13 @@ template <class Mt, int NT, int CAP>
 struct RegGemv {
   static_assert(CAP % 4 == 0, "prefetch groups of four");
   Mt a[CAP];
-  int M, K, RT, S, G, slot, r, g, passes;
+  int M, K, RT, S, G, slot, r, g, passes, tid;
   bool act;
-  __device__ void setup(int M_, int K_) {
+  // t: the thread's index among the NT threads that form this product (the
+  // workgroup's, or one group's of a workgroup split into equal groups that
+  // all run products of one shape, so that they meet the same barriers)
+  __device__ void setup(int M_, int K_, int t = threadIdx.x) {
+    tid = t;
     M = M_;
     K = K_;
     RT = M < 64 ? M : 64;
@@ -168,7 +172,6 @@ struct RegGemv {
     S = min(tiles, NT / RT);
     const int tpt = NT / S;
     G = tpt / RT;
-    const int t = threadIdx.x;
     slot = t / tpt;
     const int u = t - slot * tpt;
     r = u % RT;
@@ -232,7 +235,7 @@ struct RegGemv {
       }
       if (act) red[(slot * G + g) * RT + r] = acc;
       __syncthreads();
-      for (int q = threadIdx.x; q < S * RT; q += NT) {
+      for (int q = tid; q < S * RT; q += NT) {
         const int sl = q / RT, rr = q - sl * RT;
         const int i = (ps * S + sl) * RT + rr;
         if (i < M) {
@@ -332,6 +335,135 @@ __global__ __launch_bounds__(NT) void vc_up_small_kernel(SmallLevelT<Mt> a, cd* 
   __syncthreads();
   gx.run(Xj, m2, xrow, im_off(0), y, z0, x, red);
   if (t < M) z[xi] = x[t];
+}
+
+
+// ---- levels 1..K in one launch: one workgroup per level-(K+1) box ------------
+// Below level K+1 a box's pairs touch only the slots of its own elements and,
+// in the down sweep, the slots across its boundary (the rows of the kept faces'
+// neighbours), which no other box touches before level K+1.  One workgroup of
+// 1024 threads therefore runs all K levels of one box with the box's slot
+// values in LDS: the level-l pairs of the box (2^(K-l) of them, consecutive in
+// merge-tree order) split the threads into equal groups, so every group runs
+// products of one shape and meets the same barriers.  Only the operators and
+// z0 go through global memory; the vector is read and written once.
+constexpr int kFusedThreads = 1024;
+
+template <class Mt, int NTG>
+__device__ void fused_down_level(const FusedLevel& L, int box, int ppb, cd* v, cd* w, int tid) {
+  const int m = L.m, e = L.e, m2 = 2 * m;
+  const int grp = tid / NTG, t = tid - grp * NTG;
+  const int j = box * ppb + (grp >> 1), h = grp & 1;
+  const int reg = 3 * m + 2 * e + NTG + (e + 3) / 4;   // one group's LDS, in cd
+  cd* r = w + (long long)grp * reg;   // [2m] r_x
+  cd* z = r + m2;                      // [m]  z0 half
+  cd* dv = z + m;                      // [e]  values across the kept faces
+  cd* dd = dv + e;                     // [e]  T z0 half
+  cd* red = dd + e;                    // [NTG]
+  int* ds = reinterpret_cast<int*>(red + NTG);   // [e]
+  const long long bb = (long long)L.b * L.b;
+  const Mt* T = static_cast<const Mt*>(L.T);
+  const Mt* Ai = static_cast<const Mt*>(L.Ainv) + (long long)j * m2 * m2;
+  const IdxMap arow = im_off(h == 0 ? m : 0);
+  const Mt* Th = T + (2LL * j + h) * bb;
+  const IdxMap trow = h == 0 ? L.E1 : L.E2;
+  const IdxMap tcol = im_off(h == 0 ? L.a0 : L.b0);
+  RegGemv<Mt, NTG, SmallCap<Mt>::A> ga;
+  RegGemv<Mt, NTG, SmallCap<Mt>::T> gt;
+  ga.setup(m, m2, t);
+  gt.setup(e, m, t);
+  ga.load(Ai, m2, arow, im_off(0));
+  gt.load(Th, L.b, trow, tcol);
+  for (int i = t; i < m2; i += NTG) r[i] = v[L.xl[(long long)j * m2 + i]];
+  for (int i = t; i < e; i += NTG) {
+    const int di = L.dl[(long long)j * 2 * e + h * e + i];
+    ds[i] = di;
+    dv[i] = di >= 0 ? v[di] : cmk(0.0, 0.0);
+  }
+  __syncthreads();
+  ga.run(Ai, m2, arow, im_off(0), r, nullptr, z, red);
+  for (int i = t; i < m; i += NTG) L.Z0[(long long)j * m2 + (h == 0 ? m : 0) + i] = z[i];
+  gt.run(Th, L.b, trow, tcol, z, dv, dd, red);
+  for (int i = t; i < e; i += NTG)
+    if (ds[i] >= 0) v[ds[i]] = dd[i];
+  __syncthreads();
+}
+
+template <class Mt, int NTP>
+__device__ void fused_up_level(const FusedLevel& L, int box, int ppb, cd* v, cd* w, int tid) {
+  const int m2 = 2 * L.m, e2 = 2 * L.e;
+  const int grp = tid / NTP, t = tid - grp * NTP;
+  const int j = box * ppb + grp;
+  const int reg = e2 + 2 * m2 + NTP;
+  cd* y = w + (long long)grp * reg;   // [2e]
+  cd* z0 = y + e2;                     // [2m]
+  cd* x = z0 + m2;                     // [2m]
+  cd* red = x + m2;                    // [NTP]
+  const Mt* Xj = static_cast<const Mt*>(L.X) + (long long)j * m2 * e2;
+  RegGemv<Mt, NTP, SmallCap<Mt>::X> gx;
+  gx.setup(m2, e2, t);
+  gx.load(Xj, m2, im_off(0), im_off(0));
+  for (int i = t; i < e2; i += NTP) {
+    const int yi = L.yl[(long long)j * e2 + i];
+    y[i] = yi >= 0 ? v[yi] : cmk(0.0, 0.0);
+  }
+  for (int i = t; i < m2; i += NTP) z0[i] = L.Z0[(long long)j * m2 + i];
+  __syncthreads();
+  gx.run(Xj, m2, im_off(0), im_off(0), y, z0, x, red);
+  for (int i = t; i < m2; i += NTP) v[L.xl[(long long)j * m2 + i]] = x[i];
+  __syncthreads();
+}
+
+// Level l of K (1-based) of the down sweep: 2^(K-l) pairs per box, a group of
+// 512 >> (K - l) threads per pair half.
+template <class Mt, int K, int l>
+__device__ inline void fused_down_from(const FusedArgs& a, int box, cd* v, cd* w, int tid) {
+  if constexpr (l <= K) {
+    constexpr int kGroup = (kFusedThreads / 2) >> (K - l);
+    fused_down_level<Mt, kGroup>(a.lev[l - 1], box, 1 << (K - l), v, w, tid);
+    fused_down_from<Mt, K, l + 1>(a, box, v, w, tid);
+  }
+}
+
+template <class Mt, int K, int l>
+__device__ inline void fused_up_from(const FusedArgs& a, int box, cd* v, cd* w, int tid) {
+  if constexpr (l >= 1) {
+    constexpr int kGroup = kFusedThreads >> (K - l);
+    fused_up_level<Mt, kGroup>(a.lev[l - 1], box, 1 << (K - l), v, w, tid);
+    fused_up_from<Mt, K, l - 1>(a, box, v, w, tid);
+  }
+}
+
+template <class Mt, int K>
+__global__ __launch_bounds__(kFusedThreads) void vc_down_fused_kernel(FusedArgs a, cd* vec) {
+  extern __shared__ cd sm[];
+  const int box = blockIdx.x, tid = threadIdx.x;
+  cd* v = sm;
+  cd* w = sm + a.nloc_pad;
+  const int* gs = a.gdown + (long long)box * a.nloc;
+  for (int i = tid; i < a.nloc; i += kFusedThreads) {
+    const int s = gs[i];
+    v[i] = s >= 0 ? vec[s] : cmk(0.0, 0.0);
+  }
+  __syncthreads();
+  fused_down_from<Mt, K, 1>(a, box, v, w, tid);
+  for (int i = tid; i < a.nloc; i += kFusedThreads) {
+    const int s = gs[i];
+    if (s >= 0) vec[s] = v[i];
+  }
+}
+
+template <class Mt, int K>
+__global__ __launch_bounds__(kFusedThreads) void vc_up_fused_kernel(FusedArgs a, cd* z) {
+  extern __shared__ cd sm[];
+  const int box = blockIdx.x, tid = threadIdx.x;
+  cd* v = sm;
+  cd* w = sm + a.nloc_pad;
+  const int* gs = a.gup + (long long)box * a.nloc;
+  for (int i = tid; i < a.nloc; i += kFusedThreads) v[i] = z[gs[i]];
+  __syncthreads();
+  fused_up_from<Mt, K, K>(a, box, v, w, tid);
+  for (int i = tid; i < a.nloc; i += kFusedThreads) z[gs[i]] = v[i];
 }
 
 }  // namespace
@@ -509,6 +641,63 @@ hipError_t vc_up_small(const SmallLevelT<Mt>& a, int pairs, cd* z, hipStream_t s
   }
 }
 
+size_t fused_lds_bytes(const FusedArgs& a, int K, bool down) {
+  size_t need = 0;
+  for (int l = 1; l <= K; ++l) {
+    const FusedLevel& L = a.lev[l - 1];
+    size_t groups, reg;
+    if (down) {
+      const int ntg = (kFusedThreads / 2) >> (K - l);
+      groups = (size_t)2 << (K - l);
+      reg = 3 * L.m + 2 * L.e + ntg + (L.e + 3) / 4;
+    } else {
+      const int ntp = kFusedThreads >> (K - l);
+      groups = (size_t)1 << (K - l);
+      reg = 2 * L.e + 4 * L.m + ntp;
+    }
+    need = std::max(need, groups * reg);
+  }
+  return sizeof(cd) * ((size_t)a.nloc_pad + need);
+}
+
+bool fused_ok(const FusedArgs& a, int K) {
+  if (K < 2 || K > kFuseMax) return false;
+  for (int l = 1; l <= K; ++l) {
+    const FusedLevel& L = a.lev[l - 1];
+    if (L.m < 1 || L.e < 1 || 2 * L.m > 1024 || 2 * L.e > 4096) return false;
+  }
+  return fused_lds_bytes(a, K, true) <= 160 * 1024 && fused_lds_bytes(a, K, false) <= 160 * 1024;
+}
+
+namespace {
+template <class Mt, int K>
+hipError_t launch_fused(const FusedArgs& a, int boxes, cd* vec, bool down, hipStream_t st) {
+  const size_t lds = fused_lds_bytes(a, K, down);
+  if (down) {
+    hipError_t err = allow_lds(vc_down_fused_kernel<Mt, K>, lds);
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL((vc_down_fused_kernel<Mt, K>), dim3(boxes), dim3(kFusedThreads), lds, st, a, vec);
+  } else {
+    hipError_t err = allow_lds(vc_up_fused_kernel<Mt, K>, lds);
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL((vc_up_fused_kernel<Mt, K>), dim3(boxes), dim3(kFusedThreads), lds, st, a, vec);
+  }
+  return hipPeekAtLastError();
+}
+}  // namespace
+
+template <class Mt>
+hipError_t vc_fused(const FusedArgs& a, int K, int boxes, cd* vec, bool down, hipStream_t st) {
+  if (!fused_ok(a, K) || boxes < 1) return hipErrorInvalidValue;
+  switch (K) {
+    case 2: return launch_fused<Mt, 2>(a, boxes, vec, down, st);
+    case 3: return launch_fused<Mt, 3>(a, boxes, vec, down, st);
+    default: return launch_fused<Mt, 4>(a, boxes, vec, down, st);
+  }
+}
+
+template hipError_t vc_fused<cd>(const FusedArgs&, int, int, cd*, bool, hipStream_t);
+template hipError_t vc_fused<cf>(const FusedArgs&, int, int, cd*, bool, hipStream_t);
 template hipError_t zgemv_batched<cd>(const GemvDescT<cd>*, int, int, cd*, hipStream_t);
 template hipError_t zgemv_batched<cf>(const GemvDescT<cf>*, int, int, cd*, hipStream_t);
 template hipError_t zgemv_partials<cd>(const GemvDescT<cd>*, int, int, cd*, GemvPartLayout*, hipStream_t, int);
