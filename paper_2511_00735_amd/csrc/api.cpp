@@ -965,8 +965,12 @@ hps_status coarse_solve(hps_problem* p, cd* wv, cd* z) {
   cd* H = at<cd>(p, lay.cH_off);
   cd* sc = at<cd>(p, lay.cs_off);  // beta^2 per problem
   cd* part = at<cd>(p, lay.gpart_off);
-  HIPCHK(c, coarse_start(idx, nL, wv, V, vq, H, hsize, sc, nq, st));
   const bool pair_form = lay.L == lay.Lmax;
+  // pair form on short coarse vectors: the start and the finish run inside the
+  // first and last Arnoldi launches, and the first product reads w0 = wv[idx]
+  const bool fold = pair_form && coarse_fast_ok(nL, k);
+  const CoarseEnds ends{idx, wv, z, sc, k};
+  if (!fold) HIPCHK(c, coarse_start(idx, nL, wv, V, vq, H, hsize, sc, nq, st));
   for (int j = 0; j < k; ++j) {
     const cd* vj = V + (size_t)j * nL;
     CoarseW src{};
@@ -980,10 +984,11 @@ hps_status coarse_solve(hps_problem* p, cd* wv, cd* z) {
       // last merge of a wide rectangular mesh), else P's top and Q's bottom
       const bool along_x = merge_axis_of(top.g.ax, top.g.ay, lay.L) == 0;
       const int aP = along_x ? top.g.off[1] : top.g.off[3], bQ = along_x ? top.g.off[0] : top.g.off[2];
+      const bool w0 = fold && j == 0;   // the product of w0 = wv[idx] (V_0 is formed after it)
       GemvDesc d[2] = {gdesc<cd>(m, m, Operand{T + (size_t)b * b, ts, b, im_off(bQ), im_off(bQ)},
-                                 vin_compact(vj + m, vq), vout_compact(nullptr, 0)),
-                       gdesc<cd>(m, m, Operand{T, ts, b, im_off(aP), im_off(aP)}, vin_compact(vj, vq),
-                                 vout_compact(nullptr, 0))};
+                                 w0 ? vin_table(wv, idx + m, nL) : vin_compact(vj + m, vq), vout_compact(nullptr, 0)),
+                       gdesc<cd>(m, m, Operand{T, ts, b, im_off(aP), im_off(aP)},
+                                 w0 ? vin_table(wv, idx, nL) : vin_compact(vj, vq), vout_compact(nullptr, 0))};
       // at most 8 splits: the single-workgroup Arnoldi step reads every partial
       GemvPartLayout pl{};
       HIPCHK(c, zgemv_partials(d, 2, nq, part, &pl, st, 8));
@@ -999,9 +1004,9 @@ hps_status coarse_solve(hps_problem* p, cd* wv, cd* z) {
       if (s != HPS_OK) return s;
       src.w = w;
     }
-    HIPCHK(c, coarse_arnoldi(V, nL, vq, j, src, wt, H + (size_t)j * (k + 1), hsize, nq, st));
+    HIPCHK(c, coarse_arnoldi(V, nL, vq, j, src, wt, H + (size_t)j * (k + 1), hsize, nq, st, fold ? &ends : nullptr));
   }
-  HIPCHK(c, coarse_finish(H, k, hsize, sc, V, nL, vq, idx, z, nq, st));
+  if (!fold) HIPCHK(c, coarse_finish(H, k, hsize, sc, V, nL, vq, idx, z, nq, st));
   return HPS_OK;
 }
 

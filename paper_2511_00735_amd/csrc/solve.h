@@ -72,11 +72,25 @@ struct CoarseW {
   int ns0, ns1;
   int m, nb;
 };
+// The k-step GMRES's start and end folded into its first and last Arnoldi
+// steps (register kernels only: coarse_fast_ok(n, k)): step 0 gathers
+// w0 = vin[idx] itself (the product src was formed from w0, not from V_0),
+// writes V_0 = w0/|w0|, beta2 and H = 0; step k-1 solves the least squares
+// and scatters vout[idx] = V y instead of forming V_k (coarse_start and
+// coarse_finish are then not launched).
+struct CoarseEnds {
+  const int* idx;     // [nq][n] coarse index lists
+  const cd* vin;      // gathered at step 0
+  cd* vout;           // scattered at step k-1
+  cd* beta2;          // [nq]
+  int k;
+};
+bool coarse_fast_ok(int n, int k);
 // Arnoldi step j (0 <= j < kMaxCoarse): two-pass classical Gram-Schmidt,
 // V_{j+1} and column j of H (Hcol = H + j*(k+1), per problem + q*hsize).
 // wtmp: nq * n scratch entries.
 hipError_t coarse_arnoldi(cd* V, int n, long long vq, int j, const CoarseW& src, cd* wtmp, cd* Hcol, int hsize,
-                          int nq, hipStream_t st);
+                          int nq, hipStream_t st, const CoarseEnds* ends = nullptr);
 // y = argmin |beta e1 - H y| (Givens), vec[idx] = V y, per problem.
 hipError_t coarse_finish(const cd* H, int k, int hsize, const cd* beta2, const cd* V, int n, long long vq,
                          const int* idx, cd* vec, int nq, hipStream_t st);

@@ -420,22 +420,120 @@ __global__ __launch_bounds__(kCT) void coarse_arnoldi_kernel(cd* V, int n, long 
 // the order of the dot-product sums.
 constexpr int kFastV = 6;
 
+// The least squares of lsq_small for k <= kFastV in one wavefront (called by
+// all 64 lanes of a wave): lane q holds column q of R in registers; rotation j
+// is formed in lane j and applied by lanes j..kk-1 (and to the right-hand side
+// in every lane); the back substitution sums R[i][q] y_q across the lanes.  The
+// same rotations as lsq_small; only the back substitution's sums are added in
+// another order.  Hs: (k+1) x k column-major (ld k+1); y[0..k) to LDS.
+__device__ void lsq_wave(const cd* Hs, int ldh, int k, double beta, cd* y) {
+  const int lane = threadIdx.x & 63;
+  int kk = k;
+  for (int j = 0; j < k; ++j) {
+    if (!(Hs[(long long)j * ldh + j + 1].x > 1e-14 * beta)) {
+      kk = j + 1;
+      break;
+    }
+  }
+  cd hc[kFastV + 1], g[kFastV + 1];
+#pragma unroll
+  for (int i = 0; i <= kFastV; ++i) {
+    hc[i] = (lane < kk && i <= lane + 1 && i <= kk) ? Hs[(long long)lane * ldh + i] : cmk(0.0, 0.0);
+    g[i] = cmk(i == 0 ? beta : 0.0, 0.0);
+  }
+#pragma unroll
+  for (int j = 0; j < kFastV; ++j) {
+    if (j < kk) {
+      const cd a = hc[j], b = hc[j + 1];   // meaningful in lane j
+      const double den = sqrt(cabs2(a) + cabs2(b));
+      cd c = den > 0 ? cscale(a, 1.0 / den) : cmk(1.0, 0.0);
+      cd s = den > 0 ? cscale(b, 1.0 / den) : cmk(0.0, 0.0);
+      c = cmk(lane_value(c.x, j), lane_value(c.y, j));
+      s = cmk(lane_value(s.x, j), lane_value(s.y, j));
+      if (lane >= j && lane < kk) {
+        const cd u = hc[j], v = hc[j + 1];
+        hc[j] = cadd(cmul(cconj(c), u), cmul(cconj(s), v));
+        hc[j + 1] = csub(cmul(c, v), cmul(s, u));
+      }
+      const cd gu = g[j], gw = g[j + 1];
+      g[j] = cadd(cmul(cconj(c), gu), cmul(cconj(s), gw));
+      g[j + 1] = csub(cmul(c, gw), cmul(s, gu));
+    }
+  }
+  cd yq = cmk(0.0, 0.0);   // y of this lane's column
+#pragma unroll
+  for (int i = kFastV - 1; i >= 0; --i) {
+    if (i < kk) {
+      const cd sum = wave_sum((lane > i && lane < kk) ? cmul(hc[i], yq) : cmk(0.0, 0.0));
+      const cd acc = csub(g[i], sum);
+      const cd rii = cmk(lane_value(hc[i].x, i), lane_value(hc[i].y, i));
+      const cd yi = cabs2(rii) > 0 ? cmul(acc, cinv(rii)) : cmk(0.0, 0.0);
+      if (lane == i) yq = yi;
+    }
+  }
+  if (lane < k) y[lane] = lane < kk ? yq : cmk(0.0, 0.0);
+}
+
 template <int EP, int NT>
 __global__ __launch_bounds__(NT) void coarse_arnoldi_fast_kernel(cd* V, int n, long long vq, int j, CoarseW src,
-                                                                cd* Hcol, int hsize) {
+                                                                cd* Hcol, int hsize, CoarseEnds ends) {
   __shared__ cd red[NT / 64][kFastV];
   __shared__ cd hs[kFastV], hsum[kFastV];
   const int t = threadIdx.x, qp = blockIdx.x;
   V += (long long)qp * vq;
   Hcol += (long long)qp * hsize;
   if (src.w) src.w += (long long)qp * n;
+  const bool first = ends.idx && j == 0, last = ends.idx && j == ends.k - 1;
+  // last step: the scatter's slot indices are loaded now, so that their
+  // latency passes during the Arnoldi step
+  int sidx[EP];
+  if (last) {
+#pragma unroll
+    for (int e = 0; e < EP; ++e) {
+      const int i = t + e * NT;
+      sidx[e] = i < n ? ends.idx[(long long)qp * n + i] : 0;
+    }
+  }
   cd vv[kFastV][EP];
   cd w[EP];
+  double inv_beta = 1.0;   // first step: w0 = vec[idx] unnormalised, V_0 = w0 / beta
+  if (first) {
+    // the start of the k-step GMRES in this launch: V_0 = w0 / |w0|, beta^2,
+    // H = 0 (the product below was formed from w0 itself)
+    const int* idx = ends.idx + (long long)qp * n;
+    cd acc = cmk(0.0, 0.0);
 #pragma unroll
-  for (int e = 0; e < EP; ++e) {
-    const int i = t + e * NT;
+    for (int e = 0; e < EP; ++e) {
+      const int i = t + e * NT;
+      vv[0][e] = i < n ? ends.vin[idx[i]] : cmk(0.0, 0.0);
+      acc = cfma(cconj(vv[0][e]), vv[0][e], acc);
 #pragma unroll
-    for (int v = 0; v < kFastV; ++v) vv[v][e] = (v <= j && i < n) ? V[(long long)v * n + i] : cmk(0.0, 0.0);
+      for (int v = 1; v < kFastV; ++v) vv[v][e] = cmk(0.0, 0.0);
+    }
+    acc = wave_sum(acc);
+    if ((t & 63) == 0) red[t >> 6][0] = acc;
+    __syncthreads();
+    cd b2 = cmk(0.0, 0.0);
+    for (int q = 0; q < NT / 64; ++q) b2 = cadd(b2, red[q][0]);
+    const double beta = sqrt(fmax(b2.x, 0.0));
+    inv_beta = beta > 0.0 ? 1.0 / beta : 0.0;
+#pragma unroll
+    for (int e = 0; e < EP; ++e) {
+      const int i = t + e * NT;
+      vv[0][e] = cscale(vv[0][e], inv_beta);
+      if (i < n) V[i] = vv[0][e];
+    }
+    cd* H = Hcol;   // column 0 is the start of the problem's H
+    for (int i = t; i < hsize; i += NT) H[i] = cmk(0.0, 0.0);
+    if (t == 0) ends.beta2[qp] = b2;
+    __syncthreads();   // red is reused below; H is zeroed before column 0 is written
+  } else {
+#pragma unroll
+    for (int e = 0; e < EP; ++e) {
+      const int i = t + e * NT;
+#pragma unroll
+      for (int v = 0; v < kFastV; ++v) vv[v][e] = (v <= j && i < n) ? V[(long long)v * n + i] : cmk(0.0, 0.0);
+    }
   }
   const cd* vj = V + (long long)j * n;
   if (src.part) {
@@ -466,10 +564,11 @@ __global__ __launch_bounds__(NT) void coarse_arnoldi_fast_kernel(cd* V, int n, l
         for (int e = 0; e < EP; ++e)
           if (q0 + u < nse[e]) w[e] = cadd(w[e], tmp[u][e]);
     }
+    // first step: the product is of w0, so M V_0 = (w0 - partials) / beta
 #pragma unroll
     for (int e = 0; e < EP; ++e) {
       const int i = t + e * NT;
-      w[e] = i < n ? csub(vj[i], w[e]) : cmk(0.0, 0.0);
+      w[e] = i < n ? (first ? csub(vv[0][e], cscale(w[e], inv_beta)) : csub(vj[i], w[e])) : cmk(0.0, 0.0);
     }
   } else {
 #pragma unroll
@@ -518,17 +617,42 @@ __global__ __launch_bounds__(NT) void coarse_arnoldi_fast_kernel(cd* V, int n, l
   for (int q = 0; q < NT / 64; ++q) nr2 = cadd(nr2, red[q][0]);
   const double nr = sqrt(fmax(nr2.x, 0.0));
   const double sc = nr > 0.0 ? 1.0 / nr : 0.0;
-  cd* vn = V + (long long)(j + 1) * n;
+  if (!last) {
+    cd* vn = V + (long long)(j + 1) * n;
+#pragma unroll
+    for (int e = 0; e < EP; ++e) {
+      const int i = t + e * NT;
+      if (i < n) vn[i] = cscale(w[e], sc);
+    }
+    if (t == 0) {
+#pragma unroll
+      for (int v = 0; v < kFastV; ++v)
+        if (v <= j) Hcol[v] = hsum[v];
+      Hcol[j + 1] = cmk(nr, 0.0);
+    }
+    return;
+  }
+  // last step: the least-squares solve and z = V y, with V_0..V_{k-1} of this
+  // thread's entries still in registers (V_k is not needed)
+  __shared__ cd Hs[(kFastV + 1) * kFastV];
+  __shared__ cd y[kFastV];
+  __shared__ cd b2s;
+  const int k = ends.k, ldh = k + 1;
+  const cd* H = Hcol - (long long)j * ldh;   // the problem's H
+  if (t < j * ldh) Hs[t] = H[t];   // columns 0..j-1 (j * ldh <= 30 < NT)
+  if (t < ldh) Hs[j * ldh + t] = t <= j ? hsum[t] : (t == j + 1 ? cmk(nr, 0.0) : cmk(0.0, 0.0));
+  if (t == 0) b2s = ends.beta2[qp];   // (k = 1: written by this launch, by this thread)
+  __syncthreads();
+  if (t < 64) lsq_wave(Hs, ldh, k, sqrt(fmax(b2s.x, 0.0)), y);
+  __syncthreads();
 #pragma unroll
   for (int e = 0; e < EP; ++e) {
     const int i = t + e * NT;
-    if (i < n) vn[i] = cscale(w[e], sc);
-  }
-  if (t == 0) {
+    cd acc = cmk(0.0, 0.0);
 #pragma unroll
     for (int v = 0; v < kFastV; ++v)
-      if (v <= j) Hcol[v] = hsum[v];
-    Hcol[j + 1] = cmk(nr, 0.0);
+      if (v < k) acc = cadd(acc, cmul(y[v], vv[v][e]));
+    if (i < n) ends.vout[sidx[e]] = acc;
   }
 }
 
@@ -696,24 +820,35 @@ hipError_t coarse_start(const int* idx, int n, const cd* vec, cd* V, long long v
   return hipPeekAtLastError();
 }
 
+bool coarse_fast_ok(int n, int k) {
+  return k >= 1 && k <= kFastV && n <= 2 * 1024;
+}
+
 hipError_t coarse_arnoldi(cd* V, int n, long long vq, int j, const CoarseW& src, cd* wtmp, cd* Hcol, int hsize,
-                          int nq, hipStream_t st) {
+                          int nq, hipStream_t st, const CoarseEnds* ends) {
   if (j < 0 || j + 1 > kMaxCoarse) return hipErrorInvalidValue;
+  const CoarseEnds none{};
+  if (ends) {
+    // the fused start and end exist only on the register kernels
+    if (!coarse_fast_ok(n, ends->k) || !ends->idx || !ends->vin || !ends->vout || !ends->beta2 || !src.part)
+      return hipErrorInvalidValue;
+  }
+  const CoarseEnds& ce = ends ? *ends : none;
   if (j < kFastV && n <= 2 * 512)
     hipLaunchKernelGGL((coarse_arnoldi_fast_kernel<2, 512>), dim3(nq), dim3(512), 0, st, V, n, vq, j, src, Hcol,
-                       hsize);
+                       hsize, ce);
   else if (j < kFastV && n <= 2 * 1024)   // more loads in flight on the one CU
     hipLaunchKernelGGL((coarse_arnoldi_fast_kernel<2, 1024>), dim3(nq), dim3(1024), 0, st, V, n, vq, j, src, Hcol,
-                       hsize);
+                       hsize, ce);
   else if (j < kFastV && n <= 4 * 512)
     hipLaunchKernelGGL((coarse_arnoldi_fast_kernel<4, 512>), dim3(nq), dim3(512), 0, st, V, n, vq, j, src, Hcol,
-                       hsize);
+                       hsize, ce);
   else if (j < kFastV && n <= 4 * 256)
     hipLaunchKernelGGL((coarse_arnoldi_fast_kernel<4, 256>), dim3(nq), dim3(256), 0, st, V, n, vq, j, src, Hcol,
-                       hsize);
+                       hsize, ce);
   else if (j < kFastV && n <= 8 * 256)
     hipLaunchKernelGGL((coarse_arnoldi_fast_kernel<8, 256>), dim3(nq), dim3(256), 0, st, V, n, vq, j, src, Hcol,
-                       hsize);
+                       hsize, ce);
   else   // (16 entries per thread would spill to scratch, which the runtime must allocate at dispatch)
     hipLaunchKernelGGL(coarse_arnoldi_kernel, dim3(nq), dim3(kCT), 0, st, V, n, vq, j, src, wtmp, Hcol, hsize);
   return hipPeekAtLastError();
