@@ -152,13 +152,16 @@ const char* hps_last_error(const hps_ctx* ctx);
 /* Wait for the context's stream and report the failures recorded on the
    device by any live problem of this context (see Errors above). */
 hps_status hps_sync(hps_ctx* ctx);
-/* Options.  HPS_OPT_GRAPHS (default 0): replay the multigrid V-cycle from a HIP
-   graph captured once per problem (on a private capture stream) instead of
-   launching its kernels one by one.  Results are bitwise identical either way.
-   The graph reads and writes buffers of its own (two vector copies per
-   application), so it pays only where the host cannot keep ahead of the GPU,
-   e.g. several host threads launching on one device at once; a single
-   solver loop launches eagerly fast enough.
+/* Options.  HPS_OPT_GRAPHS (default 0): replay HIP graphs captured once per
+   problem (on a private capture stream) instead of launching kernels one by
+   one: in hps_gmres_solve, one graph per FGMRES iteration (V-cycle, M_1
+   product, CGS2, next basis vector; the iteration index is held on the device,
+   so the same graph serves every iteration), and in hps_precond_apply the
+   V-cycle.  Results are bitwise identical either way.  The graphs read and
+   write buffers of their own (two vector copies per application), so they pay
+   only where the host cannot keep ahead of the GPU, e.g. several host threads
+   launching on one device at once; a single solver loop launches eagerly fast
+   enough.
    HPS_OPT_TIMING (default 0): profiling aid.  Setting it (either value)
    synchronises and discards earlier records; while it is 1, every launch of a
    timed kernel is bracketed by HIP events recorded on the context's stream (the

@@ -208,7 +208,8 @@ class Context:
         self.check(lib.hps_sync(self.handle), "hps_sync")
 
     def set_graphs(self, on):
-        """Replay the V-cycle from a captured HIP graph, or launch it eagerly (the default)."""
+        """Replay captured HIP graphs (each FGMRES iteration of a solve, and the V-cycle of
+        precond_apply), or launch eagerly (the default)."""
         self.check(lib.hps_set_option(self.handle, HPS_OPT_GRAPHS, 1 if on else 0), "hps_set_option")
 
     def set_timing(self, on):
