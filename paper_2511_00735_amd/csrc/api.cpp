@@ -899,8 +899,9 @@ cd* workv(hps_problem* p, int i) {
 }
 
 // Classical Gram-Schmidt, two passes, against V[0..nv) for each problem of
-// the group (segments of n entries): coefficients summed into h (problem q at
-// h + q*hs), w updated in place; h2: the same layout, scratch.
+// the group (segments of n entries): the passes' coefficients in h and h2
+// (problem q at + q*hs; the Hessenberg column is their sum, which the host
+// forms when it reads them back), w updated in place.
 // With nvdev set the vector count is *nvdev + 1, read on the device, and nv
 // is the largest it may be.
 hps_status cgs2(hps_problem* p, const cd* V, long long vstride, int nv, cd* w, long long n, cd* h, cd* h2,
@@ -913,7 +914,6 @@ hps_status cgs2(hps_problem* p, const cd* V, long long vstride, int nv, cd* w, l
   HIPCHK(c, multi_axpy(V, vstride, nv, h, w, n, -1, st, nq, hs, nvdev));
   HIPCHK(c, multi_dot(V, vstride, nv, w, n, part, h2, false, st, nq, hs, nvdev));
   HIPCHK(c, multi_axpy(V, vstride, nv, h2, w, n, -1, st, nq, hs, nvdev));
-  HIPCHK(c, add_strided(h, h2, nv, nq, hs, st, nvdev));
   return HPS_OK;
 }
 
@@ -1428,7 +1428,7 @@ hps_status fgmres_group(hps_problem* p, const cd* rhs, cd* g, double tol, int ma
         prev[q] = est[q];
         const cd* hq = hbuf + (size_t)(j & 1) * hn + (size_t)q * HS;
         zc* col = &Hm[q][(size_t)j * (R + 1)];
-        for (int i = 0; i <= j; ++i) col[i] = zc(hq[i].x, hq[i].y);
+        for (int i = 0; i <= j; ++i) col[i] = zc(hq[i].x + hq[R + 2 + i].x, hq[i].y + hq[R + 2 + i].y);
         col[j + 1] = zc(hq[2 * (R + 2) + 1].x, 0.0);
         for (int i = 0; i < j; ++i) {  // G_i = [[conj c, conj s], [-s, c]]
           const zc t = std::conj(cs[q][i]) * col[i] + std::conj(sn[q][i]) * col[i + 1];

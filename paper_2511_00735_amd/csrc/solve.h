@@ -22,10 +22,6 @@ hipError_t index_gather(const int* idx, int n, const cd* vec, cd* out, hipStream
 hipError_t index_scatter(const int* idx, int n, const cd* in, cd* vec, hipStream_t st, int nq = 1,
                          long long istride = 0);
 hipError_t vfill(cd* v, long long n, cd val, hipStream_t st);
-// a[q*stride + i] += b[q*stride + i] for i < n, q < nq (ndev set: n = *ndev + 1,
-// n passed as the largest value it may take)
-hipError_t add_strided(cd* a, const cd* b, int n, int nq, long long stride, hipStream_t st,
-                       const int* ndev = nullptr);
 // out = a x + b y
 hipError_t axpby(cd a, const cd* x, cd b, const cd* y, cd* out, long long n, hipStream_t st);
 hipError_t vcopy(const cd* src, cd* dst, long long n, hipStream_t st);

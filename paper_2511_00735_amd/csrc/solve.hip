@@ -115,15 +115,6 @@ __global__ void index_scatter_kernel(const int* idx, int n, long long ntot, cons
     vec[idx[i]] = in[(i / n) * istride + i % n];
 }
 
-// a[q*stride + i] += b[q*stride + i], i < n, q < nq (grid.y = q); with ndev
-// set, n = *ndev + 1.
-__global__ void add_strided_kernel(cd* a, const cd* b, int n, long long stride, const int* ndev) {
-  if (ndev) n = *ndev + 1;
-  const long long o = (long long)blockIdx.y * stride;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-    a[o + i] = cadd(a[o + i], b[o + i]);
-}
-
 __global__ void fill_kernel(cd* v, long long n, cd val) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x)
@@ -735,11 +726,6 @@ hipError_t index_scatter(const int* idx, int n, const cd* in, cd* vec, hipStream
   const long long ntot = (long long)n * nq;
   hipLaunchKernelGGL(index_scatter_kernel, dim3(grid_for(ntot)), dim3(256), 0, st, idx, n, ntot, in,
                      istride ? istride : n, vec);
-  return hipPeekAtLastError();
-}
-
-hipError_t add_strided(cd* a, const cd* b, int n, int nq, long long stride, hipStream_t st, const int* ndev) {
-  hipLaunchKernelGGL(add_strided_kernel, dim3(grid_for(n), nq), dim3(256), 0, st, a, b, n, stride, ndev);
   return hipPeekAtLastError();
 }
 
