@@ -35,8 +35,11 @@
 //  * U12 = L11^-1 A12 by per-column forward substitution in LDS, then the
 //    trailing update A22 -= L21 U12 with one row and four adjacent columns per
 //    thread (U12 read as 128-bit broadcasts, L21 rows from the element matrix).
-// With 32-column panels the LDS holds about 75 KB (two workgroups per CU) and
-// the trailing matrix is read and written once per 32 pivots.
+// With 20-column panels the LDS holds about 49 KB at N = 16, so three
+// workgroups share a CU (their 163 registers per lane allow three waves per
+// SIMD); the trailing matrix is read and written once per 20 pivots.  (32-column
+// panels halve the residency at about 75 KB and measured 6 % slower; 16 and 24
+// columns, with three and two workgroups, slower still.)
 #include <algorithm>
 
 #include "common.h"
@@ -47,9 +50,16 @@ namespace hps {
 
 namespace {
 
-constexpr int kNB = 32;          // panel width of the blocked LU
+#ifndef HPS_LEAF_NB
+#define HPS_LEAF_NB 20
+#endif
+constexpr int kNB = HPS_LEAF_NB;  // panel width of the blocked LU (a multiple of 4)
+static_assert(kNB % 4 == 0, "panel columns are dealt to four waves and updated four at a time");
+#ifndef HPS_LEAF_OCC
+#define HPS_LEAF_OCC 3            // workgroups per CU the register budget is set for
+#endif
 #ifndef HPS_LEAF_PF
-#define HPS_LEAF_PF 3
+#define HPS_LEAF_PF 4
 #endif
 constexpr int kPF = HPS_LEAF_PF;  // trailing-update column groups in flight per lane
 #ifndef HPS_LEAF_ADD_B
@@ -382,7 +392,7 @@ size_t leaf_lds_bytes(int N) {
 
 // One element per workgroup: assembly, the bordered real partial LU, then the
 // Cayley step.
-__global__ __launch_bounds__(kThreads, 2) void leaf_kernel(LeafArgs a) {
+__global__ __launch_bounds__(kThreads, HPS_LEAF_OCC) void leaf_kernel(LeafArgs a) {
   extern __shared__ __attribute__((aligned(16))) double lds[];
   __shared__ int piv_s[kNB];              // panel-relative pivot row of each column
   __shared__ int dsrc_s[kNB];             // row moved into the slot of pivot piv_s[c], or -1
