@@ -4,7 +4,7 @@
  * Interpretation of Hierarchical Poincare-Steklov Solvers"):
  *     -Lap u - kappa^2 (1 - b(x)) u = s   in (0,1)^2,
  *     d_n u + i eta u = t                 on the boundary.
- * Discretisation (Sec. 3): n x n square elements, tensor GLL grid of order N per
+ * Discretisation (Sec. 3): n x n square elements (or nx x ny, hps_desc.ny), tensor GLL grid of order N per
  * element, corner nodes removed; leaf impedance-to-impedance maps T and loads H
  * (eq. ItIOperator); skeleton system M g = RHS on the interior incoming
  * impedances (Sec. 3.2).  Solver (Sec. 4): nested-dissection merge tree whose
@@ -15,8 +15,9 @@
  *
  * Conventions shared by every entry point:
  *  - Complex numbers are interleaved (re, im) doubles.
- *  - Elements e = ix + n*iy; element nodes (i, j) (i along x), flat index
- *    i*(N+1) + j, x_i = ix*h + (1 + xi_i) h/2 with GLL nodes xi on [-1, 1].
+ *  - Elements e = ix + n*iy (n elements along x); element nodes (i, j) (i along
+ *    x), flat index i*(N+1) + j, x_i = ix*h + (1 + xi_i) h/2 with GLL nodes xi
+ *    on [-1, 1] and h = 1/n (1/max(nx, ny) on a rectangular mesh).
  *  - Canonical skeleton layout ("canonical vector"): slot (e, side, k) at flat
  *    index (e*4 + side)*(N-1) + k, sides l=0, r=1, b=2, t=3, k = 0..N-2 by
  *    increasing coordinate; length E*4*(N-1) complex.  A slot holds the
@@ -27,7 +28,9 @@
  *    face, so M = I - Pi T_blk (the rows of eq. faceequations).
  *  - Merge level l = 1 .. L_max = log2(n^2); level-l boxes are
  *    2^floor(l/2) x 2^floor((l-1)/2) elements; merge l pairs boxes along x for
- *    odd l and along y for even l (Fig. 1).
+ *    odd l and along y for even l (Fig. 1).  On an nx x ny mesh (L_max =
+ *    log2(nx ny)) the merges alternate so while both directions have merges
+ *    left and then run along the longer direction.
  *
  * Memory: the caller owns all device memory.  Each problem lives in ONE
  * caller-provided device workspace of hps_workspace_bytes() bytes; the library
@@ -122,9 +125,12 @@ typedef struct {
   int32_t level;         /* l                                                  */
   int32_t boxes;         /* number of level-l boxes                            */
   int32_t box_nodes;     /* b = box perimeter in nodes (box map is b x b)      */
-  int32_t morton;        /* 1: boxes stored in merge-tree (Morton) order: box
-                            index j covers elements whose Morton code (x bits
-                            even, y bits odd) shifted right by l-1 equals j     */
+  int32_t morton;        /* 1: boxes stored in merge-tree order: box index j
+                            covers the elements whose tree code shifted right
+                            by l-1 equals j; bit l-1 of the code is the bit of
+                            the element's x or y index that merge l consumes
+                            (on a square mesh the Morton code: x bits even,
+                            y bits odd)                                         */
   const void* T;         /* complex [boxes][b][b], column-major, box-local
                             boundary order [l; r; b; t]; FP64                  */
   int32_t pairs;         /* pairs merged at this level (0 at the top)          */
