@@ -29,17 +29,26 @@
 //  * multipliers stay unscaled in the panel, with 1/pivot kept per column;
 //    once the panel is done they are scaled into the panel's own (finished)
 //    columns of the element matrix, and the LDS is handed to U12 and L11;
-//  * the row interchanges are applied once per panel: the pivot rows of the
-//    trailing columns are gathered into U12, and the non-pivot rows among the
-//    first kNB move into the slots the pivot rows vacate;
-//  * U12 = L11^-1 A12 by per-column forward substitution in LDS, then the
-//    trailing update A22 -= L21 U12 with one row and four adjacent columns per
-//    thread (U12 read as 128-bit broadcasts, L21 rows from the element matrix).
-// With 20-column panels the LDS holds about 49 KB at N = 16, so three
-// workgroups share a CU (their 163 registers per lane allow three waves per
-// SIMD); the trailing matrix is read and written once per 20 pivots.  (32-column
-// panels halve the residency at about 75 KB and measured 6 % slower; 16 and 24
-// columns, with three and two workgroups, slower still.)
+//  * the row interchanges are applied once per panel (chunk by chunk, below):
+//    the pivot rows of the trailing columns are gathered into U12, and the
+//    non-pivot rows among the first kNB move into the slots the pivot rows
+//    vacate;
+//  * the trailing columns are taken in chunks whose U12 rows fit the LDS
+//    (at most 208 columns): per chunk the row interchanges, U12 = L11^-1 A12
+//    by per-column forward substitution in LDS, then the trailing update
+//    A22 -= L21 U12 with one row and four adjacent columns per thread (U12
+//    read as 128-bit broadcasts, L21 rows from the element matrix, three
+//    column groups of A22 in flight per lane).
+// With 24-column panels and chunks of at most 208 columns the LDS holds about
+// 48 KB at N = 16, so three workgroups share a CU (their 164 registers per
+// lane allow three waves per SIMD); the trailing matrix is read and written
+// once per 24 pivots.  Measured per 4096-element launch at N = 16: 7.44 ms,
+// against 7.86 ms with 20-column panels (one chunk) and 7.5-7.7 ms with 24 and
+// 28 columns in chunks of 144 or 176 columns.  The same update on the FP64
+// matrix cores (16x16x4 tiles of A22^T -= U12^T L21^T, L21 held per row
+// block) measured 10.8 ms at 20 columns: the tiles' registers leave no room
+// at three workgroups per CU for loads in flight ahead of the products, and
+// the FP64 matrix rate of this part equals its vector rate.
 #include <algorithm>
 
 #include "common.h"
@@ -51,7 +60,7 @@ namespace hps {
 namespace {
 
 #ifndef HPS_LEAF_NB
-#define HPS_LEAF_NB 20
+#define HPS_LEAF_NB 24
 #endif
 constexpr int kNB = HPS_LEAF_NB;  // panel width of the blocked LU (a multiple of 4)
 static_assert(kNB % 4 == 0, "panel columns are dealt to four waves and updated four at a time");
@@ -59,7 +68,7 @@ static_assert(kNB % 4 == 0, "panel columns are dealt to four waves and updated f
 #define HPS_LEAF_OCC 3            // workgroups per CU the register budget is set for
 #endif
 #ifndef HPS_LEAF_PF
-#define HPS_LEAF_PF 4
+#define HPS_LEAF_PF 3
 #endif
 constexpr int kPF = HPS_LEAF_PF;  // trailing-update column groups in flight per lane
 #ifndef HPS_LEAF_ADD_B
@@ -70,6 +79,11 @@ constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 constexpr int kCPW = kNB / kWaves;  // panel columns per wave
 constexpr int kMaxChunks = 5;    // 64-row chunks of a panel: n_loc <= 320 (N <= 16)
+#ifndef HPS_LEAF_CW
+#define HPS_LEAF_CW 208
+#endif
+constexpr int kCWMax = HPS_LEAF_CW;  // trailing columns whose U12 rows share the LDS at a time
+static_assert(kCWMax % 4 == 0, "trailing columns are updated four at a time");
 // An element whose interior elimination meets a pivot below 0.02 times its
 // largest (in modulus) lies within about 1e-6 (relative, in kappa^2) of an
 // interior Dirichlet eigenvalue; rounding in the large term of its Schur
@@ -90,10 +104,10 @@ __host__ __device__ inline Dims dims_of(int N) {
   d.pp = d.p * d.p;
   d.nloc = d.pp + 4 * d.p;
   d.ncol = d.nloc + 2;
-  // row stride of U12 in LDS (at most ncol - min(kNB, pp) trailing columns):
-  // even (16-byte rows for 128-bit reads) and 2 mod 4, so that the rows of one
-  // column fall in different banks
-  d.ldu = ((d.ncol - (d.pp < kNB ? d.pp : kNB) + 3) & ~3) + 2;
+  // row stride of U12 in LDS, which holds at most kCWMax trailing columns at a
+  // time: 2 mod 4, so that the rows of one column fall in different banks
+  const int nc0 = d.ncol - (d.pp < kNB ? d.pp : kNB);
+  d.ldu = (((nc0 < kCWMax ? nc0 : kCWMax) + 3) & ~3) + 2;
   return d;
 }
 
@@ -377,7 +391,7 @@ __device__ void leaf_cayley(const LeafArgs& a, const Dims& d, const double* A, d
 // LDS doubles shared by the panel's pivot-column exchange and U12 + L11
 __host__ __device__ inline size_t leaf_region_doubles(const Dims& d) {
   const size_t a = (size_t)2 * 64 * kMaxChunks, b = (size_t)kNB * d.ldu + (size_t)kNB * kNB;
-  const size_t c = (size_t)d.nloc * kNB;   // the first panel's columns of K
+  const size_t c = (size_t)d.nloc * kWaves;   // the first panel's columns of K, kWaves at least at a time
   const size_t ab = a > b ? a : b;
   return ab > c ? ab : c;
 }
@@ -443,26 +457,47 @@ __global__ __launch_bounds__(kThreads, HPS_LEAF_OCC) void leaf_kernel(LeafArgs a
     // the panel in registers: wave w holds columns j = w + kWaves * u, lane the
     // rows t * 64 + lane
     const bool first = k0 == 0;   // the first panel reads K itself
-    if (first) {
-      // K's first kb columns, evaluated once into the (still free) U12 area
-      for (int idx = tid; idx < rows * kb; idx += kThreads) {
-        const int r = idx % rows, c = idx / rows;
-        U[(size_t)c * nloc + r] = K(r, c);
-      }
-      __syncthreads();
-    }
     double xv[kMaxChunks][kCPW];
+    if (first) {
+      // K's first kb columns, evaluated into the (still free) U12 area as many
+      // at a time as it holds (a multiple of kWaves)
 #pragma unroll
-    for (int u = 0; u < kCPW; ++u) {
-      const int j = wave + kWaves * u;
-      const double* col = first ? U + (size_t)j * nloc : A + (size_t)(k0 + j) * nloc + k0;
+      for (int u = 0; u < kCPW; ++u)
 #pragma unroll
-      for (int t = 0; t < kMaxChunks; ++t) {
-        const int r = t * 64 + lane;
-        xv[t][u] = (j < kb && r < rows) ? col[r] : 0.0;
+        for (int t = 0; t < kMaxChunks; ++t) xv[t][u] = 0.0;
+      const int kst = min(kNB, (int)(region / nloc) / kWaves * kWaves);
+      for (int s0 = 0; s0 < kb; s0 += kst) {
+        for (int idx = tid; idx < rows * kst; idx += kThreads) {
+          const int r = idx % rows, c = s0 + idx / rows;
+          if (c < kb) U[(size_t)(c - s0) * nloc + r] = K(r, c);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kCPW; ++u) {
+          const int j = wave + kWaves * u;
+          if (j >= s0 && j < s0 + kst && j < kb) {
+            const double* col = U + (size_t)(j - s0) * nloc;
+#pragma unroll
+            for (int t = 0; t < kMaxChunks; ++t) {
+              const int r = t * 64 + lane;
+              xv[t][u] = r < rows ? col[r] : 0.0;
+            }
+          }
+        }
+        __syncthreads();   // the next batch, or the column exchange below, reuses that LDS
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < kCPW; ++u) {
+        const int j = wave + kWaves * u;
+        const double* col = A + (size_t)(k0 + j) * nloc + k0;
+#pragma unroll
+        for (int t = 0; t < kMaxChunks; ++t) {
+          const int r = t * 64 + lane;
+          xv[t][u] = (j < kb && r < rows) ? col[r] : 0.0;
+        }
       }
     }
-    if (first) __syncthreads();   // the column exchange below reuses that LDS
     for (int r = tid; r < rows; r += kThreads) {
       rowmap[r] = r;
       slotof[r] = r;
@@ -579,138 +614,149 @@ __global__ __launch_bounds__(kThreads, HPS_LEAF_OCC) void leaf_kernel(LeafArgs a
       const int qq = idx % kNB, r = idx / kNB;
       L11[idx] = (qq < r && r < kb) ? A[(size_t)(k0 + qq) * nloc + k0 + piv_s[r]] : 0.0;
     }
-    // ---- row interchanges on the trailing columns; U12 gathered ----
-    // Two passes, eight loads in flight per thread in each: the pivot rows of
-    // the trailing columns into U12 (rows past a short last panel are zero and
-    // take part in the update; the first panel reads K, whose trailing update
-    // goes through rowmap), then the non-pivot rows among the first kb into
-    // the vacated pivot slots.  A thread handles the same entries in both
-    // passes, so each slot is read before it is overwritten.
-    const int nu = kNB * nc;
-    for (int base = tid; base < nu; base += 8 * kThreads) {
-      double v[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int idx = base + u * kThreads;
-        const int qq = idx % kNB, cc = idx / kNB;
-        v[u] = 0.0;
-        if (idx < nu && qq < kb)
-          v[u] = first ? K(piv_s[qq], c0 + cc) : A[(size_t)(c0 + cc) * nloc + k0 + piv_s[qq]];
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int idx = base + u * kThreads;
-        if (idx < nu) U[(idx % kNB) * ldu + idx / kNB] = v[u];
-      }
-    }
-    if (!first) {
+    // ---- the trailing columns in chunks of at most ldu - 2, whose U12 rows
+    // share the LDS: row interchanges, U12, trailing update ----
+    const int cwmax = ldu - 2;
+    const int nch = (nc + cwmax - 1) / cwmax;
+    const int cwid = (nc + nch - 1) / nch;
+    for (int cs = 0; cs < nc; cs += cwid) {
+      const int cw = min(cwid, nc - cs);
+      // Two passes, eight loads in flight per thread in each: the pivot rows of
+      // the chunk's columns into U12 (rows past a short last panel are zero
+      // and take part in the update; the first panel reads K, whose trailing
+      // update goes through rowmap), then the non-pivot rows among the first
+      // kb into the vacated pivot slots.  A thread handles the same entries in
+      // both passes, so each slot is read before it is overwritten.
+      const int nu = kNB * cw;
       for (int base = tid; base < nu; base += 8 * kThreads) {
         double v[8];
-        double* dst[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
           const int idx = base + u * kThreads;
-          const int qq = idx % kNB, cc = idx / kNB;
-          const int x = (idx < nu && qq < kb) ? dsrc_s[qq] : -1;
-          double* col = A + (size_t)(c0 + cc) * nloc + k0;
-          dst[u] = x >= 0 ? col + piv_s[qq] : nullptr;
-          v[u] = x >= 0 ? col[x] : 0.0;
+          const int qq = idx % kNB, cc = cs + idx / kNB;
+          v[u] = 0.0;
+          if (idx < nu && qq < kb)
+            v[u] = first ? K(piv_s[qq], c0 + cc) : A[(size_t)(c0 + cc) * nloc + k0 + piv_s[qq]];
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
-          if (dst[u]) *dst[u] = v[u];
+        for (int u = 0; u < 8; ++u) {
+          const int idx = base + u * kThreads;
+          if (idx < nu) U[(idx % kNB) * ldu + idx / kNB] = v[u];
+        }
       }
-    }
-    __syncthreads();
-    // ---- U12 = L11^-1 (pivot rows of A12): forward substitution per column ----
-    for (int cc = tid; cc < nc; cc += kThreads) {
-      double u[kNB];
+      if (!first) {
+        for (int base = tid; base < nu; base += 8 * kThreads) {
+          double v[8];
+          double* dst[8];
 #pragma unroll
-      for (int r = 0; r < kNB; ++r) u[r] = r < kb ? U[r * ldu + cc] : 0.0;
+          for (int u = 0; u < 8; ++u) {
+            const int idx = base + u * kThreads;
+            const int qq = idx % kNB, cc = cs + idx / kNB;
+            const int x = (idx < nu && qq < kb) ? dsrc_s[qq] : -1;
+            double* col = A + (size_t)(c0 + cc) * nloc + k0;
+            dst[u] = x >= 0 ? col + piv_s[qq] : nullptr;
+            v[u] = x >= 0 ? col[x] : 0.0;
+          }
 #pragma unroll
-      for (int r = 1; r < kNB; ++r) {
-        double s = u[r];
-#pragma unroll
-        for (int qq = 0; qq < r; ++qq) s -= L11[r * kNB + qq] * u[qq];
-        u[r] = s;
-        asm volatile("" : "+v"(u[r])::"memory");
+          for (int u = 0; u < 8; ++u)
+            if (dst[u]) *dst[u] = v[u];
+        }
       }
+      __syncthreads();
+      // U12 = L11^-1 (pivot rows of A12): forward substitution per column
+      for (int cl = tid; cl < cw; cl += kThreads) {
+        double u[kNB];
 #pragma unroll
-      for (int r = 0; r < kNB; ++r)
-        if (r < kb) U[r * ldu + cc] = u[r];
-    }
-    __syncthreads();
-    // ---- trailing update A22 -= L21 U12: one row x four adjacent columns ----
-    const int tr = rows - kb;
-    const int RB = (tr + 63) >> 6, CG = (nc + 3) >> 2;
-#pragma unroll 1
-    for (int rb = 0; rb < RB; ++rb) {
-      const int y = kb + rb * 64 + lane;       // panel-relative slot
-      const bool live = y < rows;
-      double l[kNB];
+        for (int r = 0; r < kNB; ++r) u[r] = r < kb ? U[r * ldu + cl] : 0.0;
+#pragma unroll
+        for (int r = 1; r < kNB; ++r) {
+          double s = u[r];
+#pragma unroll
+          for (int qq = 0; qq < r; ++qq) s -= L11[r * kNB + qq] * u[qq];
+          u[r] = s;
+          asm volatile("" : "+v"(u[r])::"memory");
+        }
+#pragma unroll
+        for (int r = 0; r < kNB; ++r)
+          if (r < kb) U[r * ldu + cl] = u[r];
+      }
+      __syncthreads();
+      // A22 -= L21 U12: one row x four adjacent columns per thread (U12 read
+      // as 128-bit broadcasts, L21 rows from the element matrix)
       {
-        const double* lrow = A + (size_t)k0 * nloc + k0 + (live ? rowmap[y] : 0);
-#pragma unroll
-        for (int qq = 0; qq < kNB; ++qq) l[qq] = (live && qq < kb) ? lrow[(size_t)qq * nloc] : 0.0;
-      }
-      double* arow = A + (size_t)c0 * nloc + k0 + y;
-      // kPF column groups of A22 in flight per lane (a ring indexed at compile
-      // time): one group's products take far less than a memory round trip
-      double nx[kPF][4];
-#pragma unroll
-      for (int p = 0; p < kPF; ++p) {
-        const int cgp = wave + p * kWaves;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int cc = cgp * 4 + u;
-          nx[p][u] = (live && cgp < CG && cc < nc && !first) ? arow[(size_t)cc * nloc] : 0.0;
-        }
-      }
+        const int tr = rows - kb;
+        const int RB = (tr + 63) >> 6, CG = (cw + 3) >> 2;
 #pragma unroll 1
-      for (int cb = wave; cb < CG; cb += kWaves * kPF) {
+        for (int rb = 0; rb < RB; ++rb) {
+          const int y = kb + rb * 64 + lane;       // panel-relative slot
+          const bool live = y < rows;
+          double l[kNB];
+          {
+            const double* lrow = A + (size_t)k0 * nloc + k0 + (live ? rowmap[y] : 0);
 #pragma unroll
-      for (int p = 0; p < kPF; ++p) {
-        const int cg = cb + p * kWaves;
-        if (cg >= CG) break;   // uniform over the wave
-        double s[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) s[u] = nx[p][u];
-        const int cn = cg + kPF * kWaves;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int cc = cn * 4 + u;
-          nx[p][u] = (live && cn < CG && cc < nc && !first) ? arow[(size_t)cc * nloc] : 0.0;
-        }
-        const double2* Ub = reinterpret_cast<const double2*>(U + cg * 4);
-        // four U12 rows at a time keep the register footprint at two waves per SIMD
-#pragma unroll
-        for (int q4 = 0; q4 < kNB; q4 += 4) {
-          double2 u01[4], u23[4];
-#pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            u01[k] = Ub[(q4 + k) * (ldu / 2)];
-            u23[k] = Ub[(q4 + k) * (ldu / 2) + 1];
+            for (int qq = 0; qq < kNB; ++qq) l[qq] = (live && qq < kb) ? lrow[(size_t)qq * nloc] : 0.0;
           }
+          double* arow = A + (size_t)(c0 + cs) * nloc + k0 + y;
+          // kPF column groups of A22 in flight per lane (a ring indexed at
+          // compile time): one group's products take far less than a memory
+          // round trip
+          double nx[kPF][4];
 #pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            s[0] -= l[q4 + k] * u01[k].x;
-            s[1] -= l[q4 + k] * u01[k].y;
-            s[2] -= l[q4 + k] * u23[k].x;
-            s[3] -= l[q4 + k] * u23[k].y;
+          for (int p = 0; p < kPF; ++p) {
+            const int cgp = wave + p * kWaves;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const int cc = cgp * 4 + u;
+              nx[p][u] = (live && cgp < CG && cc < cw && !first) ? arow[(size_t)cc * nloc] : 0.0;
+            }
           }
-          // keeps the products in this group (not sunk into the guarded
-          // stores) and the next group's loads behind them
-          asm volatile("" : "+v"(s[0]), "+v"(s[1]), "+v"(s[2]), "+v"(s[3])::"memory");
-        }
-        if (live) {
+#pragma unroll 1
+          for (int cb = wave; cb < CG; cb += kWaves * kPF) {
 #pragma unroll
-          for (int u = 0; u < 4; ++u)
-            if (cg * 4 + u < nc) arow[(size_t)(cg * 4 + u) * nloc] = s[u];
+            for (int p = 0; p < kPF; ++p) {
+              const int cg = cb + p * kWaves;
+              if (cg >= CG) break;   // uniform over the wave
+              double sacc[4];
+#pragma unroll
+              for (int u = 0; u < 4; ++u) sacc[u] = nx[p][u];
+              const int cn = cg + kPF * kWaves;
+#pragma unroll
+              for (int u = 0; u < 4; ++u) {
+                const int cc = cn * 4 + u;
+                nx[p][u] = (live && cn < CG && cc < cw && !first) ? arow[(size_t)cc * nloc] : 0.0;
+              }
+              const double2* Ub = reinterpret_cast<const double2*>(U + cg * 4);
+              // four U12 rows at a time keep the register footprint down
+#pragma unroll
+              for (int q4 = 0; q4 < kNB; q4 += 4) {
+                double2 u01[4], u23[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                  u01[k] = Ub[(q4 + k) * (ldu / 2)];
+                  u23[k] = Ub[(q4 + k) * (ldu / 2) + 1];
+                }
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                  sacc[0] -= l[q4 + k] * u01[k].x;
+                  sacc[1] -= l[q4 + k] * u01[k].y;
+                  sacc[2] -= l[q4 + k] * u23[k].x;
+                  sacc[3] -= l[q4 + k] * u23[k].y;
+                }
+                // keeps the products in this group (not sunk into the guarded
+                // stores) and the next group's loads behind them
+                asm volatile("" : "+v"(sacc[0]), "+v"(sacc[1]), "+v"(sacc[2]), "+v"(sacc[3])::"memory");
+              }
+              if (live) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                  if (cg * 4 + u < cw) arow[(size_t)(cg * 4 + u) * nloc] = sacc[u];
+              }
+            }
+          }
         }
       }
-      }
+      __syncthreads();   // the next chunk's U12 reuses the LDS
     }
-    __syncthreads();
     if (first) {
       // the first trailing update started from zero: add K's trailing entries
       // at their rows' slots (each slot and column is touched once), kAddB at
