@@ -899,21 +899,26 @@ cd* workv(hps_problem* p, int i) {
 }
 
 // Classical Gram-Schmidt, two passes, against V[0..nv) for each problem of
-// the group (segments of n entries): the passes' coefficients in h and h2
-// (problem q at + q*hs; the Hessenberg column is their sum, which the host
-// forms when it reads them back), w updated in place.
+// the group (segments of n entries), then the normalisation: the passes'
+// coefficients in h and h2 (problem q at + q*hs; the Hessenberg column is
+// their sum, which the host forms when it reads them back), the new basis
+// vector in out (displaced by (*jdev + 1) * jstride with jdev set) and its
+// norm in hout (+ q*hs).  The second pass's dot products also give |w'|^2
+// (into nrm2 + q*hs), and its update is fused with the normalisation: with V
+// orthonormal |w''|^2 = |w'|^2 - |h2|^2.  w holds w' afterwards.
 // With nvdev set the vector count is *nvdev + 1, read on the device, and nv
 // is the largest it may be.
-hps_status cgs2(hps_problem* p, const cd* V, long long vstride, int nv, cd* w, long long n, cd* h, cd* h2,
-                long long hs, const int* nvdev = nullptr) {
+hps_status cgs2_normalize(hps_problem* p, const cd* V, long long vstride, int nv, cd* w, long long n, cd* h,
+                          cd* h2, cd* nrm2, cd* out, cd* hout, long long hs, const int* nvdev = nullptr,
+                          const int* jdev = nullptr, long long jstride = 0) {
   hps_ctx* c = p->ctx;
   hipStream_t st = c->stream;
   const int nq = p->lay.nq;
   cd* part = at<cd>(p, p->lay.part_off);
   HIPCHK(c, multi_dot(V, vstride, nv, w, n, part, h, false, st, nq, hs, nvdev));
   HIPCHK(c, multi_axpy(V, vstride, nv, h, w, n, -1, st, nq, hs, nvdev));
-  HIPCHK(c, multi_dot(V, vstride, nv, w, n, part, h2, false, st, nq, hs, nvdev));
-  HIPCHK(c, multi_axpy(V, vstride, nv, h2, w, n, -1, st, nq, hs, nvdev));
+  HIPCHK(c, multi_dot(V, vstride, nv, w, n, part, h2, false, st, nq, hs, nvdev, nrm2));
+  HIPCHK(c, axpy_normalize(V, vstride, nv, h2, hs, w, n, nrm2, hs, out, hout, hs, st, nq, nvdev, jdev, jstride));
   return HPS_OK;
 }
 
@@ -1219,8 +1224,8 @@ typedef std::complex<double> zc;
 // so its solution stays as it was.  rhs, g: group vectors.
 // One FGMRES iteration with its index j read on the device (the int at
 // jctr_off): V_j into the V-cycle's input vector, the preconditioner, its
-// output into Z_j, the M_1 product, CGS2 against V_0..V_j, V_{j+1} with its
-// norm, then j + 1.  Every launch has the same arguments for every j, so one
+// output into Z_j, the M_1 product, CGS2 against V_0..V_j with V_{j+1} and its
+// norm formed by the second pass's update, then j + 1.  Every launch has the same arguments for every j, so one
 // captured graph serves all iterations of all cycles.
 hps_status iteration_kernels(hps_problem* p) {
   hps_ctx* c = p->ctx;
@@ -1237,17 +1242,14 @@ hps_status iteration_kernels(hps_problem* p) {
   cd* zout = workv(p, 6);
   cd* hh = at<cd>(p, lay.hh_off);
   cd* nrm2 = hh + 2 * (R + 2);
-  cd* part = at<cd>(p, lay.part_off);
   int* jctr = at<int>(p, lay.jctr_off);
   HIPCHK(c, vcopy_at(V, rin, ntot, jctr, nullptr, ntot, st));
   hps_status s = precond_one(p, rin, zout);
   if (s != HPS_OK) return s;
   HIPCHK(c, vcopy_at(zout, Z, ntot, nullptr, jctr, ntot, st));
   HIPCHK(c, skeleton_apply(lay.lev[1].g, Tlev(p, 1), zout, w, true, st, nq));
-  s = cgs2(p, V, ntot, R, w, n, hh, hh + (R + 2), HS, jctr);
+  s = cgs2_normalize(p, V, ntot, R, w, n, hh, hh + (R + 2), nrm2, V, nrm2 + 1, HS, jctr, jctr, ntot);
   if (s != HPS_OK) return s;
-  HIPCHK(c, multi_dot(w, 0, 1, w, n, part, nrm2, false, st, nq, HS));
-  HIPCHK(c, normalize(w, nrm2, V, n, nrm2 + 1, st, nq, HS, HS, jctr, ntot));
   HIPCHK(c, counter_add(jctr, 1, st));
   return HPS_OK;
 }
@@ -1394,10 +1396,8 @@ hps_status fgmres_group(hps_problem* p, const cd* rhs, cd* g, double tol, int ma
       hps_status e = precond_any(p, V + (size_t)j * ntot, Z + (size_t)j * ntot);
       if (e != HPS_OK) return e;
       HIPCHK(c, skeleton_apply(g1, T1, Z + (size_t)j * ntot, w, true, st, nq));
-      e = cgs2(p, V, ntot, j + 1, w, n, hcol, h2, HS);
+      e = cgs2_normalize(p, V, ntot, j + 1, w, n, hcol, h2, nrm2, V + (size_t)(j + 1) * ntot, hnorm, HS);
       if (e != HPS_OK) return e;
-      HIPCHK(c, multi_dot(w, 0, 1, w, n, part, nrm2, false, st, nq, HS));
-      HIPCHK(c, normalize(w, nrm2, V + (size_t)(j + 1) * ntot, n, hnorm, st, nq, HS, HS));
       HIPCHK(c, hipMemcpyAsync(hbuf + (size_t)(j & 1) * hn, hh, sizeof(cd) * hn, hipMemcpyDeviceToHost, st));
       HIPCHK(c, hipEventRecord(c->hev[j & 1], st));
       return HPS_OK;

@@ -37,12 +37,22 @@ hipError_t vcopy_zero(const cd* src, cd* dst, cd* zero, long long n, hipStream_t
 int dot_blocks(long long n);
 // Vectors of nq problems are stored one after the other (segments of n).
 // out[q*ostride + v] (+)= sum_i conj(V_v[q*n + i]) w[q*n + i], v < nvec;
-// partial: nq * nvec * dot_blocks(n) entries.  With nvdev set the vector count
-// is read on the device, *nvdev + 1, and nvec is the largest it may be (the
-// launch's size; entries v > *nvdev of out are left as they were).
+// partial: nq * (nvec + 1) * dot_blocks(n) entries.  With nvdev set the
+// vector count is read on the device, *nvdev + 1, and nvec is the largest it
+// may be (the launch's size; entries v > *nvdev of out are left as they were).
+// With selfout set, conj(w) . w of problem q also goes to selfout[q*ostride].
 hipError_t multi_dot(const cd* V, long long vstride, int nvec, const cd* w, long long n, cd* partial,
                      cd* out, bool accumulate, hipStream_t st, int nq = 1, long long ostride = 0,
-                     const int* nvdev = nullptr);
+                     const int* nvdev = nullptr, cd* selfout = nullptr);
+// Second Gram-Schmidt update and normalisation in one pass (V orthonormal):
+// out[q*n + i] = (w - sum_v h[q*hstride + v] V_v)[q*n + i] / r_q with
+// r_q^2 = Re nrm2[q*nstride] - sum_v |h[q*hstride + v]|^2 (nrm2 holding |w|^2),
+// hout[q*houtstride] = r_q; nvdev and jdev (out displaced by (*jdev + 1) *
+// jstride) as for multi_axpy and normalize.
+hipError_t axpy_normalize(const cd* V, long long vstride, int nvec, const cd* h, long long hstride, const cd* w,
+                          long long n, const cd* nrm2, long long nstride, cd* out, cd* hout, long long houtstride,
+                          hipStream_t st, int nq = 1, const int* nvdev = nullptr, const int* jdev = nullptr,
+                          long long jstride = 0);
 // w[q*n + i] += sign * sum_v h[q*hstride + v] V_v[q*n + i] (nvdev as above)
 hipError_t multi_axpy(const cd* V, long long vstride, int nvec, const cd* h, cd* w, long long n, int sign,
                       hipStream_t st, int nq = 1, long long hstride = 0, const int* nvdev = nullptr);

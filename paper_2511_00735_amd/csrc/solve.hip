@@ -201,12 +201,15 @@ __device__ inline cd block_sum(cd v) {
 }
 
 // Stage 1: partial[q][v][blk] = sum over chunk blk of conj(V_v) . w on the
-// segment of problem q (grid (blocks, nvec, problems)).
+// segment of problem q (grid (blocks, nvec, problems)); with self set, the
+// last grid row takes conj(w) . w instead.
 __global__ __launch_bounds__(256) void dot_stage1_kernel(const cd* V, long long vstride, const cd* w,
-                                                         long long n, cd* partial, int nblk, const int* nvdev) {
+                                                         long long n, cd* partial, int nblk, const int* nvdev,
+                                                         int self) {
   const int v = blockIdx.y, q = blockIdx.z;
-  if (nvdev && v > *nvdev) return;   // device count (nvdev + 1 vectors; uniform per workgroup)
-  const cd* Vv = V + (long long)v * vstride + (long long)q * n;
+  const bool selfrow = self && v == (int)gridDim.y - 1;
+  if (!selfrow && nvdev && v > *nvdev) return;   // device count (nvdev + 1 vectors; uniform per workgroup)
+  const cd* Vv = (selfrow ? w : V + (long long)v * vstride) + (long long)q * n;
   w += (long long)q * n;
   partial += (long long)q * gridDim.y * nblk;
   const long long chunk = (n + nblk - 1) / nblk;
@@ -218,17 +221,25 @@ __global__ __launch_bounds__(256) void dot_stage1_kernel(const cd* V, long long 
   if (threadIdx.x == 0) partial[(long long)v * nblk + blockIdx.x] = acc;
 }
 
-// Stage 2: out[q * ostride + v] (+)= sum_blk partial[q][v][blk]  (grid (nvec, problems)).
+// Stage 2: out[q * ostride + v] (+)= sum_blk partial[q][v][blk]  (grid (nvec, problems));
+// with selfout set, the last grid row's sum goes to selfout[q * ostride].
 __global__ __launch_bounds__(256) void dot_stage2_kernel(const cd* partial, int nblk, cd* out,
-                                                         int accumulate, long long ostride, const int* nvdev) {
+                                                         int accumulate, long long ostride, const int* nvdev,
+                                                         cd* selfout) {
   const int v = blockIdx.x, q = blockIdx.y;
-  if (nvdev && v > *nvdev) return;
+  const bool selfrow = selfout && v == (int)gridDim.x - 1;
+  if (!selfrow && nvdev && v > *nvdev) return;
   partial += (long long)q * gridDim.x * nblk;
   out += (long long)q * ostride;
   cd acc = cmk(0.0, 0.0);
   for (int i = threadIdx.x; i < nblk; i += blockDim.x) acc = cadd(acc, partial[(long long)v * nblk + i]);
   acc = block_sum(acc);
-  if (threadIdx.x == 0) out[v] = accumulate ? cadd(out[v], acc) : acc;
+  if (threadIdx.x == 0) {
+    if (selfrow)
+      selfout[(long long)q * ostride] = acc;
+    else
+      out[v] = accumulate ? cadd(out[v], acc) : acc;
+  }
 }
 
 // w += sign * sum_v h[q * hstride + v] V_v on the segment of each problem q
@@ -245,6 +256,45 @@ __global__ void multi_axpy_kernel(const cd* V, long long vstride, int nvec, cons
       acc = sign > 0 ? cadd(acc, t) : csub(acc, t);
     }
     w[i] = acc;
+  }
+}
+
+// The second Gram-Schmidt pass's update and the normalisation in one pass over
+// the vectors, on the segment of problem q (grid.y): w'' = w' - sum_v h[v] V_v
+// (v <= *nvdev with nvdev set, else v < nvec, summed in that order), and with
+// V orthonormal |w''|^2 = |w'|^2 - sum_v |h[v]|^2 (|w'|^2 in Re nrm2[q *
+// nstride]); out = w'' / |w''| (displaced by (*jdev + 1) * jstride with jdev
+// set) and hout[q * hstride] = |w''|.
+__global__ __launch_bounds__(256) void axpy_normalize_kernel(const cd* V, long long vstride, int nvec, const cd* h,
+                                                             long long hstride, const cd* w, long long n,
+                                                             const cd* nrm2, long long nstride, cd* out, cd* hout,
+                                                             long long houtstride, const int* nvdev,
+                                                             const int* jdev, long long jstride) {
+  __shared__ double sc_s;
+  const int q = blockIdx.y;
+  if (nvdev) nvec = *nvdev + 1;
+  if (jdev) out += (long long)(*jdev + 1) * jstride;
+  const cd* hq = h + (long long)q * hstride;
+  if (threadIdx.x < 64) {
+    double a = 0.0;
+    for (int v = threadIdx.x; v < nvec; v += 64) a += cabs2(hq[v]);
+    for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o);
+    if (threadIdx.x == 0) {
+      const double nr = sqrt(fmax(nrm2[(long long)q * nstride].x - a, 0.0));
+      sc_s = nr > 0.0 ? 1.0 / nr : 0.0;
+      if (blockIdx.x == 0 && hout) hout[(long long)q * houtstride] = cmk(nr, 0.0);
+    }
+  }
+  __syncthreads();
+  const double s = sc_s;
+  w += (long long)q * n;
+  out += (long long)q * n;
+  const long long qo = (long long)q * n;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    cd acc = w[i];
+    for (int v = 0; v < nvec; ++v) acc = csub(acc, cmul(hq[v], V[(long long)v * vstride + qo + i]));
+    out[i] = cscale(acc, s);
   }
 }
 
@@ -771,15 +821,26 @@ int dot_blocks(long long n) {
 }
 
 hipError_t multi_dot(const cd* V, long long vstride, int nvec, const cd* w, long long n, cd* partial,
-                     cd* out, bool accumulate, hipStream_t st, int nq, long long ostride, const int* nvdev) {
+                     cd* out, bool accumulate, hipStream_t st, int nq, long long ostride, const int* nvdev,
+                     cd* selfout) {
   if (nvec <= 0) return hipSuccess;
   const int nblk = dot_blocks(n);
-  hipLaunchKernelGGL(dot_stage1_kernel, dim3(nblk, nvec, nq), dim3(256), 0, st, V, vstride, w, n, partial,
-                     nblk, nvdev);
+  const int rows = nvec + (selfout ? 1 : 0);
+  hipLaunchKernelGGL(dot_stage1_kernel, dim3(nblk, rows, nq), dim3(256), 0, st, V, vstride, w, n, partial,
+                     nblk, nvdev, selfout ? 1 : 0);
   hipError_t err = hipPeekAtLastError();
   if (err != hipSuccess) return err;
-  hipLaunchKernelGGL(dot_stage2_kernel, dim3(nvec, nq), dim3(256), 0, st, partial, nblk, out,
-                     accumulate ? 1 : 0, ostride, nvdev);
+  hipLaunchKernelGGL(dot_stage2_kernel, dim3(rows, nq), dim3(256), 0, st, partial, nblk, out,
+                     accumulate ? 1 : 0, ostride, nvdev, selfout);
+  return hipPeekAtLastError();
+}
+
+hipError_t axpy_normalize(const cd* V, long long vstride, int nvec, const cd* h, long long hstride, const cd* w,
+                          long long n, const cd* nrm2, long long nstride, cd* out, cd* hout, long long houtstride,
+                          hipStream_t st, int nq, const int* nvdev, const int* jdev, long long jstride) {
+  if (nvec <= 0) return hipSuccess;
+  hipLaunchKernelGGL(axpy_normalize_kernel, dim3(grid_for(n), nq), dim3(256), 0, st, V, vstride, nvec, h, hstride,
+                     w, n, nrm2, nstride, out, hout, houtstride, nvdev, jdev, jstride);
   return hipPeekAtLastError();
 }
 
