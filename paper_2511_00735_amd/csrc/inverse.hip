@@ -597,6 +597,108 @@ __global__ __launch_bounds__(64) void gj_diag_kernel(const T* A, int m, int lda,
   }
 }
 
+// Look-ahead of the no-pivot path, run by one extra workgroup (256 threads)
+// of the update launch of step k: the pivot block of step k + 1 as that update
+// will leave it, P = A[K1, K1] - A[K1, K0] Dk A[K0, K1] (K0 = [k0, k0+kb),
+// K1 = [k1, k1+kb1), Dk the inverse of this step's pivot block, ld kb), from
+// the same inputs as the update, and its inverse into Dn (ld kb1) by the same
+// Gauss-Jordan steps and threshold test as gj_diag_kernel.  Thread (i, g)
+// holds row i, columns 4g..4g+3; S0..S3 are kNB x kNB entries of LDS each
+// (column-major, ld kNB): A[K1, K0], Dk, A[K0, K1] and A[K1, K0] Dk.
+// Component-wise choice between two complex values (a choice between whole
+// vector-type values can leave a private copy behind).
+template <class T>
+__device__ inline T csel(bool c, const T& a, const T& b) {
+  return cx<T>::make(c ? a.x : b.x, c ? a.y : b.y);
+}
+
+template <class T>
+__device__ __forceinline__ void gj_next_diag(const T* Ab, int lda, int k0, int kb, int k1, int kb1, const T* Dk, T* Dn,
+                             T* S0, T* S1, T* S2, T* S3, int* check, int level) {
+  constexpr int W = kNB * kNB;
+  const int tid = threadIdx.x, i = tid & 31, g = tid >> 5, j0 = 4 * g;
+  const T zero = cx<T>::make(0.0, 0.0);
+  for (int idx = tid; idx < W; idx += 256) {
+    const int r = idx & 31, c = idx >> 5;   // row r, column c (column-major, ld kNB)
+    const bool a0 = r < kb1 && c < kb, a1 = r < kb && c < kb, a2 = r < kb && c < kb1;
+    // loads from clamped (valid) addresses, zeros chosen outside
+    S0[idx] = csel(a0, Ab[(long long)(k0 + (a0 ? c : 0)) * lda + k1 + (a0 ? r : 0)], zero);
+    S1[idx] = csel(a1, Dk[a1 ? c * kb + r : 0], zero);
+    S2[idx] = csel(a2, Ab[(long long)(k1 + (a2 ? c : 0)) * lda + k0 + (a2 ? r : 0)], zero);
+  }
+  // this thread's four entries of the pivot block (the identity past kb1), as
+  // four scalars so that every index below is static
+  auto init = [&](int j) {
+    const bool in = i < kb1 && j < kb1;
+    return csel(in, Ab[(long long)(k1 + (in ? j : 0)) * lda + k1 + (in ? i : 0)], cx<T>::make(i == j ? 1.0 : 0.0, 0.0));
+  };
+  T p0 = init(j0), p1 = init(j0 + 1), p2 = init(j0 + 2), p3 = init(j0 + 3);
+  __syncthreads();
+  // S3 = A[K1, K0] Dk
+  for (int u = 0; u < 4; ++u) {
+    const int j = j0 + u;
+    T t = zero;
+    for (int r = 0; r < kNB; ++r) t = cfma(S0[r * kNB + i], S1[j * kNB + r], t);
+    S3[j * kNB + i] = t;
+  }
+  __syncthreads();
+  // P -= S3 A[K0, K1] (rows and columns past kb1 keep the identity)
+  auto prod = [&](int j) {
+    T t = zero;
+    for (int r = 0; r < kNB; ++r) t = cfma(S3[r * kNB + i], S2[j * kNB + r], t);
+    return t;
+  };
+  if (i < kb1) {
+    if (j0 < kb1) p0 = csub(p0, prod(j0));
+    if (j0 + 1 < kb1) p1 = csub(p1, prod(j0 + 1));
+    if (j0 + 2 < kb1) p2 = csub(p2, prod(j0 + 2));
+    if (j0 + 3 < kb1) p3 = csub(p3, prod(j0 + 3));
+  }
+  __syncthreads();   // S0 and S1 are reused for row and column k below
+  T* prow = S0;
+  T* colk = S1;
+  bool grow = false;
+  const bool live = i < kb1;
+  for (int k = 0; k < kNB; ++k) {
+    const int kg = k >> 2, ku = k & 3;
+    if (i == k) {
+      prow[j0] = p0;
+      prow[j0 + 1] = p1;
+      prow[j0 + 2] = p2;
+      prow[j0 + 3] = p3;
+    }
+    if (g == kg) colk[i] = csel(ku == 0, p0, csel(ku == 1, p1, csel(ku == 2, p2, p3)));
+    __syncthreads();
+    const T pk = prow[k];
+    const T l = colk[i];
+    const T r0 = prow[j0], r1 = prow[j0 + 1], r2 = prow[j0 + 2], r3 = prow[j0 + 3];
+    __syncthreads();   // row and column k read before the next step writes them
+    const T inv = crecip(pk);
+    const bool rowk = i == k;
+    const T lq = cmul(l, inv);
+    const T li = csel(rowk, csub(cx<T>::make(1.0, 0.0), inv), lq);
+    const double p2k = (double)cabs2(pk);
+    if (k < kb1 && ((i > k && live && !((double)cabs2(l) * (kNoPivotTau * kNoPivotTau) <= p2k)) || !(p2k > 0.0)))
+      grow = true;
+    p0 = csub(p0, cmul(li, r0));
+    p1 = csub(p1, cmul(li, r1));
+    p2 = csub(p2, cmul(li, r2));
+    p3 = csub(p3, cmul(li, r3));
+    const T colv = csel(rowk, inv, csub(zero, lq));
+    p0 = csel(g == kg && ku == 0, colv, p0);
+    p1 = csel(g == kg && ku == 1, colv, p1);
+    p2 = csel(g == kg && ku == 2, colv, p2);
+    p3 = csel(g == kg && ku == 3, colv, p3);
+  }
+  if (i < kb1) {
+    if (j0 < kb1) Dn[j0 * kb1 + i] = p0;
+    if (j0 + 1 < kb1) Dn[(j0 + 1) * kb1 + i] = p1;
+    if (j0 + 2 < kb1) Dn[(j0 + 2) * kb1 + i] = p2;
+    if (j0 + 3 < kb1) Dn[(j0 + 3) * kb1 + i] = p3;
+  }
+  if (__syncthreads_or(grow) && tid == 0 && check) atomicMin(check + 6, level);
+}
+
 // Step 2 of a block column: out-of-place update of the whole matrix, BT x BT
 // tiles (64, or 32 where 64 would leave few workgroups), 256 threads, each
 // thread (BT/16)^2 outputs (rows i0 + tx + 16u, columns j0 + ty + 16v), rows
@@ -611,13 +713,23 @@ template <class T, int BT>
 __global__ __launch_bounds__(256) void gj_update_kernel(const T* A, int lda, long long astride, T* O, int ldo,
                                                         long long ostride, int m, int k0, int kb,
                                                         const int* rowmap, const T* dinv, const int* colmap,
-                                                        int* check, int level) {
+                                                        int* check, int level, T* dnext, int k1, int kb1,
+                                                        int la_after) {
   constexpr int U = BT / 16;
+  static_assert(BT >= 32, "the look-ahead workgroup reuses Xs, Bp and Ac as 4 kNB x kNB blocks");
   __shared__ T Ds[kNB * kNB];
   __shared__ T Xs[kNB][BT];
   __shared__ T Bp[kNB][BT];     // A'[P, jtile]
   __shared__ T Ac[kNB][BT + 1]; // A'[itile, C], transposed
   const int tiles = (m + BT - 1) / BT;
+  if (dnext && !la_after && (int)blockIdx.x == tiles * tiles) {
+    // the workgroup past the tiles: the next step's pivot block inverse (no
+    // row interchanges; Xs, Bp, Ac and Ds hold the four kNB x kNB blocks it needs)
+    const int b = blockIdx.y;
+    gj_next_diag<T>(A + (long long)b * astride, lda, k0, kb, k1, kb1, dinv + (long long)b * kNB * kNB,
+                    dnext + (long long)b * kNB * kNB, &Xs[0][0], &Bp[0][0], &Ac[0][0], Ds, check, level);
+    return;
+  }
   const int i0 = (blockIdx.x % tiles) * BT, j0 = (blockIdx.x / tiles) * BT;
   const int b = blockIdx.y;
   const T* Ab = A + (long long)b * astride;
@@ -698,6 +810,14 @@ __global__ __launch_bounds__(256) void gj_update_kernel(const T* A, int lda, lon
     }
   }
   if (check && __syncthreads_or(grow) && tid == 0) atomicMin(check + 6, level);
+  if (dnext && la_after && (int)blockIdx.x == tiles * tiles - 1) {
+    // no room for an extra workgroup beside the tiles: the last tile's
+    // workgroup forms the next pivot block inverse after its tile (its LDS is
+    // free again; the barrier of the flag test above ordered every use)
+    __syncthreads();
+    gj_next_diag<T>(Ab, lda, k0, kb, k1, kb1, Db, dnext + (long long)b * kNB * kNB, &Xs[0][0], &Bp[0][0],
+                    &Ac[0][0], Ds, check, level);
+  }
 }
 
 // dst(:, colmap[j]) = src(:, j): the inverse of the row-interchanged matrix
@@ -708,7 +828,7 @@ __global__ void permute_cols_kernel(const T* S, int lds, long long sstride, T* A
   const int b = blockIdx.z, j = blockIdx.y;
   const T* Sb = S + (long long)b * sstride;
   T* Ab = A + (long long)b * bstride;
-  const int oc = colmap[(long long)b * m + j];
+  const int oc = colmap ? colmap[(long long)b * m + j] : j;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x)
     Ab[(long long)oc * lda + i] = Sb[(long long)j * lds + i];
 }
@@ -716,7 +836,7 @@ __global__ void permute_cols_kernel(const T* S, int lds, long long sstride, T* A
 template <class T>
 struct BlockScratch {
   T* buf;       // [batch][m][m] second buffer (ld m)
-  T* dinv;      // [batch][kNB][kNB]
+  T* dinv;      // [2][batch][kNB][kNB] (alternating pivot block inverses without pivoting)
   int* rho[2];  // [batch][m] composed row maps (alternating)
   int* rowmap;  // [batch][m]
 };
@@ -727,7 +847,7 @@ inline BlockScratch<T> carve(void* base, int m, int batch) {
   char* p = (char*)base;
   auto take = [&](size_t bytes) { char* q = p; p += (bytes + 255) & ~size_t(255); return q; };
   s.buf = (T*)take(sizeof(T) * (size_t)batch * m * m);
-  s.dinv = (T*)take(sizeof(T) * (size_t)batch * kNB * kNB);
+  s.dinv = (T*)take(sizeof(T) * (size_t)2 * batch * kNB * kNB);
   s.rho[0] = (int*)take(sizeof(int) * (size_t)batch * m);
   s.rho[1] = (int*)take(sizeof(int) * (size_t)batch * m);
   s.rowmap = (int*)take(sizeof(int) * (size_t)batch * m);
@@ -758,15 +878,33 @@ hipError_t inverse_blocked(T* A, int m, int lda, long long bstride, int batch, v
   const int nb = !pivot ? kNB : (reg == 1 ? kNB : (reg == 2 ? kNB / 2 : nbw));
   static_assert(kNB == 32, "register panels hold 32 (16 x 2) columns");
   const int steps = (m + nb - 1) / nb;
+  // update workgroups resident on the chip at once
+  long long resident = 0;
+  if (!pivot) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if ((err = hipGetDevice(&dev)) != hipSuccess) return err;
+    if ((err = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return err;
+    err = tiles32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, gj_update_kernel<T, 32>, 256, 0)
+                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, gj_update_kernel<T, 64>, 256, 0);
+    if (err != hipSuccess) return err;
+    resident = (long long)cus * per_cu;
+  }
   for (int s_ = 0; s_ < steps; ++s_) {
     const int k0 = s_ * nb;
     const int kb = std::min(nb, m - k0);
     const int* rho_prev = s_ ? s.rho[(s_ - 1) & 1] : nullptr;
     int* rho = s.rho[s_ & 1];
-    if (!pivot)
-      hipLaunchKernelGGL(gj_diag_kernel<T>, dim3(batch), dim3(64), 0, st, cur, m, ldc, cs, k0, kb, rho_prev, rho,
-                         s.rowmap, s.dinv, flag, level);
-    else if (reg == 1)
+    // without row interchanges the pivot block of step s_ + 1 is inverted by
+    // an extra workgroup of step s_'s update launch (from that launch's
+    // inputs); the two inverses alternate between the halves of s.dinv
+    T* dcur = pivot ? s.dinv : s.dinv + (size_t)(s_ & 1) * batch * kNB * kNB;
+    T* dnext = (!pivot && s_ + 1 < steps) ? s.dinv + (size_t)((s_ + 1) & 1) * batch * kNB * kNB : nullptr;
+    const int k1 = k0 + nb, kb1 = dnext ? std::min(nb, m - k1) : 0;
+    if (!pivot) {
+      if (s_ == 0)   // the first pivot block (and the identity row map)
+        hipLaunchKernelGGL(gj_diag_kernel<T>, dim3(batch), dim3(64), 0, st, cur, m, ldc, cs, k0, kb, rho_prev, rho,
+                           s.rowmap, dcur, flag, level);
+    } else if (reg == 1)
       hipLaunchKernelGGL((gj_panel_reg_kernel<T, 8, 2>), dim3(batch), dim3(1024), 0, st, cur, m, ldc, cs, k0, kb,
                          rho_prev, rho, s.rowmap, s.dinv, flag, level);
     else if (reg == 2)
@@ -777,14 +915,22 @@ hipError_t inverse_blocked(T* A, int m, int lda, long long bstride, int batch, v
                          cur, m, ldc, cs, k0, kb, rho_prev, rho, s.rowmap, s.dinv, flag, level);
     if ((err = hipPeekAtLastError()) != hipSuccess) return err;
     // the last step writes straight into A, columns permuted, when it can
+    // (no row interchanges: the columns stay where they are)
     const bool last_into_A = (s_ == steps - 1) && nxt == A;
+    const int* colmap = (last_into_A && pivot) ? rho : nullptr;
     int* check = pivot ? nullptr : flag;
+    // the look-ahead takes a workgroup of its own when the launch's tiles
+    // leave room on the chip for it, else it follows the last tile of each
+    // matrix in that tile's workgroup
+    const int la_after = (dnext && (long long)(tiles * tiles + 1) * batch > resident &&
+                          (long long)tiles * tiles * batch <= resident) ? 1 : 0;
+    const int wgs = tiles * tiles + ((dnext && !la_after) ? 1 : 0);
     if (tiles32)
-      hipLaunchKernelGGL((gj_update_kernel<T, 32>), dim3(tiles * tiles, batch), dim3(256), 0, st, cur, ldc, cs,
-                         nxt, ldn, ns, m, k0, kb, s.rowmap, s.dinv, last_into_A ? rho : nullptr, check, level);
+      hipLaunchKernelGGL((gj_update_kernel<T, 32>), dim3(wgs, batch), dim3(256), 0, st, cur, ldc, cs, nxt, ldn, ns,
+                         m, k0, kb, s.rowmap, dcur, colmap, check, level, dnext, k1, kb1, la_after);
     else
-      hipLaunchKernelGGL((gj_update_kernel<T, 64>), dim3(tiles * tiles, batch), dim3(256), 0, st, cur, ldc, cs,
-                         nxt, ldn, ns, m, k0, kb, s.rowmap, s.dinv, last_into_A ? rho : nullptr, check, level);
+      hipLaunchKernelGGL((gj_update_kernel<T, 64>), dim3(wgs, batch), dim3(256), 0, st, cur, ldc, cs, nxt, ldn, ns,
+                         m, k0, kb, s.rowmap, dcur, colmap, check, level, dnext, k1, kb1, la_after);
     if ((err = hipPeekAtLastError()) != hipSuccess) return err;
     std::swap(cur, nxt);
     std::swap(ldc, ldn);
@@ -792,7 +938,7 @@ hipError_t inverse_blocked(T* A, int m, int lda, long long bstride, int batch, v
   }
   if (cur != A) {
     hipLaunchKernelGGL(permute_cols_kernel<T>, dim3((m + 255) / 256, m, batch), dim3(256), 0, st, cur, ldc, cs, A,
-                       lda, bstride, m, s.rho[(steps - 1) & 1]);
+                       lda, bstride, m, pivot ? s.rho[(steps - 1) & 1] : nullptr);
     if ((err = hipPeekAtLastError()) != hipSuccess) return err;
   }
   return hipSuccess;
@@ -804,7 +950,7 @@ template <class T>
 size_t inverse_scratch_bytes(int m, int batch) {
   if (m <= 64) return 0;
   auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
-  return up(sizeof(T) * (size_t)batch * m * m) + up(sizeof(T) * (size_t)batch * kNB * kNB) +
+  return up(sizeof(T) * (size_t)batch * m * m) + up(sizeof(T) * (size_t)2 * batch * kNB * kNB) +
          3 * up(sizeof(int) * (size_t)batch * m);
 }
 
