@@ -3,14 +3,16 @@
 //
 // m <= 64 (and m <= 128 when partial pivoting is asked for): the whole matrix
 // sits in registers, one workgroup per matrix, partial pivoting.
-// Otherwise blocked Gauss-Jordan, two launches per block column C = [k0, k0+nb):
-//   1. without row interchanges across blocks (the default): gj_diag inverts
-//      the diagonal block as it stands (one wave, the step loop unrolled),
-//      under a threshold test on the multipliers that gj_update repeats for
-//      the rows outside the block; a level that fails it is redone by the
-//      host with partial pivoting.  With partial pivoting: gj_panel (in
-//      registers or LDS) picks nb pivot rows (as the row map of this step)
-//      and forms Dinv, the inverse of the pivot block;
+// Otherwise blocked Gauss-Jordan over block columns C = [k0, k0+nb):
+//   1. without row interchanges across blocks (the default): the diagonal
+//      block is inverted as it stands (gj_diag for the first block; each
+//      later one by a look-ahead workgroup of the previous step's update
+//      launch, from that launch's inputs), under a threshold test on the
+//      multipliers that gj_update repeats for the rows outside the block; a
+//      level that fails it is redone by the host with partial pivoting, so a
+//      step is one launch.  With partial pivoting (two launches per step):
+//      gj_panel (in registers or LDS) picks nb pivot rows (as the row map of
+//      this step) and forms Dinv, the inverse of the pivot block;
 //   2. gj_update: one pass over the whole matrix, out of place (two buffers),
 //      rows read through the row map, P = C, X = Dinv A'[P, :]:
 //        rows in P:      out = X           (Dinv on the C columns)
@@ -18,10 +20,11 @@
 // The row interchanges of all steps compose to one map rho; the inverse of the
 // original matrix is the result with column j moved to column rho[j], which the
 // last update (or a final copy) applies.  Work: m^3 complex multiply-adds in
-// 2 m / nb launches.  The merge blocks W = I - T^P_aa T^Q_bb of these
-// problems need no interchanges (partial pivoting keeps every diagonal pivot
-// and the elimination grows entries by about 3%), which is why the default
-// skips the pivot search that dominated each step.
+// m / nb launches (2 m / nb with partial pivoting).  The merge blocks
+// W = I - T^P_aa T^Q_bb of these problems need no interchanges (partial
+// pivoting keeps every diagonal pivot and the elimination grows entries by
+// about 3%), which is why the default skips the pivot search that dominated
+// each step.
 #include "common.h"
 #include "host.h"
 #include "pivot.h"
