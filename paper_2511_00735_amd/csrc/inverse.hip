@@ -657,12 +657,15 @@ __device__ __forceinline__ void gj_next_diag(const T* Ab, int lda, int k0, int k
     if (j0 + 2 < kb1) p2 = csub(p2, prod(j0 + 2));
     if (j0 + 3 < kb1) p3 = csub(p3, prod(j0 + 3));
   }
-  __syncthreads();   // S0 and S1 are reused for row and column k below
-  T* prow = S0;
-  T* colk = S1;
+  __syncthreads();   // S0 and S1 hold rows and columns k below
   bool grow = false;
   const bool live = i < kb1;
   for (int k = 0; k < kNB; ++k) {
+    // row and column k in one of two buffers (alternating), so that one
+    // barrier per step orders both the writes before the reads and this
+    // step's reads before the writes two steps on
+    T* prow = S0 + (k & 1) * kNB;
+    T* colk = S1 + (k & 1) * kNB;
     const int kg = k >> 2, ku = k & 3;
     if (i == k) {
       prow[j0] = p0;
@@ -675,7 +678,6 @@ __device__ __forceinline__ void gj_next_diag(const T* Ab, int lda, int k0, int k
     const T pk = prow[k];
     const T l = colk[i];
     const T r0 = prow[j0], r1 = prow[j0 + 1], r2 = prow[j0 + 2], r3 = prow[j0 + 3];
-    __syncthreads();   // row and column k read before the next step writes them
     const T inv = crecip(pk);
     const bool rowk = i == k;
     const T lq = cmul(l, inv);
