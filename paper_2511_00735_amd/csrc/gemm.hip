@@ -4,8 +4,10 @@
 // box maps (a side, all sides but one, a permuted scatter) are read and written
 // in place.
 //
-// Complex product by the 4M scheme on real MFMA tiles:
-//   Re += Ar Br - Ai Bi,  Im += Ar Bi + Ai Br.
+// Complex product by the 3M scheme on real MFMA tiles (three real products per
+// complex one instead of four):
+//   t1 += Ar Br,  t2 += Ai Bi,  t3 += (Ar + Ai)(Br + Bi);
+//   Re = t1 - t2,  Im = t3 - t1 - t2.
 // Tile: BM x BN per workgroup, waves arranged WM x WN, each wave owning
 // (BM/WM) x (BN/WN) outputs as 16x16 MFMA tiles; K staged through LDS in
 // chunks of KT complex, the next chunk's global loads issued into registers
@@ -147,13 +149,17 @@ __device__ __forceinline__ void gemm_tile(const GemmArgsT<T>& a, int tile, int b
     for (int s = 0; s < SB; ++s) Bs[kb][jb + s * JSB] = vb[s] ? rb[s] : cx<T>::make(0.0, 0.0);
   };
 
-  acc_t accr[TM][TN], acci[TM][TN];
+  // complex products by the 3M scheme: t1 = Ar Br, t2 = Ai Bi and
+  // t3 = (Ar + Ai)(Br + Bi), then Re = t1 - t2, Im = t3 - t1 - t2 (three real
+  // MFMAs per complex product instead of four)
+  acc_t t1[TM][TN], t2[TM][TN], t3[TM][TN];
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
     for (int j = 0; j < TN; ++j) {
-      accr[i][j] = acc_t{0, 0, 0, 0};
-      acci[i][j] = acc_t{0, 0, 0, 0};
+      t1[i][j] = acc_t{0, 0, 0, 0};
+      t2[i][j] = acc_t{0, 0, 0, 0};
+      t3[i][j] = acc_t{0, 0, 0, 0};
     }
 
   fetch(0);
@@ -170,14 +176,18 @@ __device__ __forceinline__ void gemm_tile(const GemmArgsT<T>& a, int tile, int b
       for (int i = 0; i < TM; ++i) av[i] = As[kk + lk][wm * (BM / WM) + i * 16 + lr];
 #pragma unroll
       for (int j = 0; j < TN; ++j) bv[j] = Bs[kk + lk][wn * (BN / WN) + j * 16 + lr];
+      decltype(av[0].x) as[TM], bs[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) as[i] = av[i].x + av[i].y;
+#pragma unroll
+      for (int j = 0; j < TN; ++j) bs[j] = bv[j].x + bv[j].y;
 #pragma unroll
       for (int i = 0; i < TM; ++i)
 #pragma unroll
         for (int j = 0; j < TN; ++j) {
-          accr[i][j] = Mfma<T>::mma(av[i].x, bv[j].x, accr[i][j]);
-          accr[i][j] = Mfma<T>::mma(-av[i].y, bv[j].y, accr[i][j]);
-          acci[i][j] = Mfma<T>::mma(av[i].x, bv[j].y, acci[i][j]);
-          acci[i][j] = Mfma<T>::mma(av[i].y, bv[j].x, acci[i][j]);
+          t1[i][j] = Mfma<T>::mma(av[i].x, bv[j].x, t1[i][j]);
+          t2[i][j] = Mfma<T>::mma(av[i].y, bv[j].y, t2[i][j]);
+          t3[i][j] = Mfma<T>::mma(as[i], bs[j], t3[i][j]);
         }
     }
     __syncthreads();
@@ -187,6 +197,14 @@ __device__ __forceinline__ void gemm_tile(const GemmArgsT<T>& a, int tile, int b
     }
   }
 
+  acc_t accr[TM][TN], acci[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      accr[i][j] = t1[i][j] - t2[i][j];
+      acci[i][j] = t3[i][j] - t1[i][j] - t2[i][j];
+    }
   T* Db = a.D + (long long)b * a.Dstride;
   const T* Cb = a.C.base ? a.C.base + (long long)b * a.C.bstride : nullptr;
   const bool use_c = (a.beta.x != 0.0 || a.beta.y != 0.0);
