@@ -1,8 +1,8 @@
 // Batched in-place inversion of complex matrices (FP64 or FP32) by
 // Gauss-Jordan elimination.
 //
-// m <= 64 (and m <= 128 when partial pivoting is asked for): the whole matrix
-// sits in registers, one workgroup per matrix, partial pivoting.
+// m <= 32 (m <= 128 when partial pivoting is asked for): the whole matrix sits
+// in registers, one workgroup per matrix, partial pivoting.
 // Otherwise blocked Gauss-Jordan over block columns C = [k0, k0+nb):
 //   1. without row interchanges across blocks (the default): the diagonal
 //      block is inverted as it stands (gj_diag for the first block; each
@@ -34,6 +34,7 @@ namespace hps {
 namespace {
 
 constexpr int kNB = 32;        // widest block column
+constexpr int kSmallNoPivot = 32;   // largest order inverted in registers without pivoting
 constexpr int kPanelThreads = 1024;
 
 // LDS bytes of gj_panel for m - k0 = rows and block width kb.
@@ -953,7 +954,7 @@ hipError_t inverse_blocked(T* A, int m, int lda, long long bstride, int batch, v
 
 template <class T>
 size_t inverse_scratch_bytes(int m, int batch) {
-  if (m <= 64) return 0;
+  if (m <= kSmallNoPivot) return 0;
   auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
   return up(sizeof(T) * (size_t)batch * m * m) + up(sizeof(T) * (size_t)2 * batch * kNB * kNB) +
          3 * up(sizeof(int) * (size_t)batch * m);
@@ -963,7 +964,9 @@ template <class T>
 hipError_t zinverse(T* A, int m, int lda, long long bstride, int batch, void* scratch, int* flag,
                     int level, bool pivot, hipStream_t st) {
   if (m <= 0 || batch <= 0) return hipSuccess;
-  if (m <= 64) {
+  // without interchanges the blocked path (one launch per 32-column step)
+  // beats the register inverse's 2 us column steps from two block columns on
+  if (m <= kSmallNoPivot || (m <= 64 && pivot)) {
     hipLaunchKernelGGL((inv_small_kernel<T, 4, 1>), dim3(batch), dim3(256), 0, st, A, m, lda, bstride, flag, level);
     return hipPeekAtLastError();
   }
