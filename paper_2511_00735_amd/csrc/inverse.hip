@@ -601,7 +601,7 @@ __global__ __launch_bounds__(64) void gj_diag_kernel(const T* A, int m, int lda,
   }
 }
 
-// Look-ahead of the no-pivot path, run by one extra workgroup (256 threads)
+// Look-ahead of the no-pivot path, run by one extra workgroup (workgroup 0, 256 threads)
 // of the update launch of step k: the pivot block of step k + 1 as that update
 // will leave it, P = A[K1, K1] - A[K1, K0] Dk A[K0, K1] (K0 = [k0, k0+kb),
 // K1 = [k1, k1+kb1), Dk the inverse of this step's pivot block, ld kb), from
@@ -719,8 +719,7 @@ template <class T, int BT>
 __global__ __launch_bounds__(256) void gj_update_kernel(const T* A, int lda, long long astride, T* O, int ldo,
                                                         long long ostride, int m, int k0, int kb,
                                                         const int* rowmap, const T* dinv, const int* colmap,
-                                                        int* check, int level, T* dnext, int k1, int kb1,
-                                                        int la_after) {
+                                                        int* check, int level, T* dnext, int k1, int kb1) {
   constexpr int U = BT / 16;
   static_assert(BT >= 32, "the look-ahead workgroup reuses Xs, Bp and Ac as 4 kNB x kNB blocks");
   __shared__ T Ds[kNB * kNB];
@@ -728,15 +727,17 @@ __global__ __launch_bounds__(256) void gj_update_kernel(const T* A, int lda, lon
   __shared__ T Bp[kNB][BT];     // A'[P, jtile]
   __shared__ T Ac[kNB][BT + 1]; // A'[itile, C], transposed
   const int tiles = (m + BT - 1) / BT;
-  if (dnext && !la_after && (int)blockIdx.x == tiles * tiles) {
-    // the workgroup past the tiles: the next step's pivot block inverse (no
-    // row interchanges; Xs, Bp, Ac and Ds hold the four kNB x kNB blocks it needs)
+  if (dnext && blockIdx.x == 0) {
+    // workgroup 0, dispatched first: the next step's pivot block inverse (no
+    // row interchanges; Xs, Bp, Ac and Ds hold the four kNB x kNB blocks it
+    // needs), formed while the tiles (workgroups 1, 2, ...) are updated
     const int b = blockIdx.y;
     gj_next_diag<T>(A + (long long)b * astride, lda, k0, kb, k1, kb1, dinv + (long long)b * kNB * kNB,
                     dnext + (long long)b * kNB * kNB, &Xs[0][0], &Bp[0][0], &Ac[0][0], Ds, check, level);
     return;
   }
-  const int i0 = (blockIdx.x % tiles) * BT, j0 = (blockIdx.x / tiles) * BT;
+  const int tile = dnext ? (int)blockIdx.x - 1 : (int)blockIdx.x;
+  const int i0 = (tile % tiles) * BT, j0 = (tile / tiles) * BT;
   const int b = blockIdx.y;
   const T* Ab = A + (long long)b * astride;
   T* Ob = O + (long long)b * ostride;
@@ -816,14 +817,6 @@ __global__ __launch_bounds__(256) void gj_update_kernel(const T* A, int lda, lon
     }
   }
   if (check && __syncthreads_or(grow) && tid == 0) atomicMin(check + 6, level);
-  if (dnext && la_after && (int)blockIdx.x == tiles * tiles - 1) {
-    // no room for an extra workgroup beside the tiles: the last tile's
-    // workgroup forms the next pivot block inverse after its tile (its LDS is
-    // free again; the barrier of the flag test above ordered every use)
-    __syncthreads();
-    gj_next_diag<T>(Ab, lda, k0, kb, k1, kb1, Db, dnext + (long long)b * kNB * kNB, &Xs[0][0], &Bp[0][0],
-                    &Ac[0][0], Ds, check, level);
-  }
 }
 
 // dst(:, colmap[j]) = src(:, j): the inverse of the row-interchanged matrix
@@ -884,17 +877,6 @@ hipError_t inverse_blocked(T* A, int m, int lda, long long bstride, int batch, v
   const int nb = !pivot ? kNB : (reg == 1 ? kNB : (reg == 2 ? kNB / 2 : nbw));
   static_assert(kNB == 32, "register panels hold 32 (16 x 2) columns");
   const int steps = (m + nb - 1) / nb;
-  // update workgroups resident on the chip at once
-  long long resident = 0;
-  if (!pivot) {
-    int dev = 0, cus = 0, per_cu = 0;
-    if ((err = hipGetDevice(&dev)) != hipSuccess) return err;
-    if ((err = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return err;
-    err = tiles32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, gj_update_kernel<T, 32>, 256, 0)
-                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, gj_update_kernel<T, 64>, 256, 0);
-    if (err != hipSuccess) return err;
-    resident = (long long)cus * per_cu;
-  }
   for (int s_ = 0; s_ < steps; ++s_) {
     const int k0 = s_ * nb;
     const int kb = std::min(nb, m - k0);
@@ -925,18 +907,16 @@ hipError_t inverse_blocked(T* A, int m, int lda, long long bstride, int batch, v
     const bool last_into_A = (s_ == steps - 1) && nxt == A;
     const int* colmap = (last_into_A && pivot) ? rho : nullptr;
     int* check = pivot ? nullptr : flag;
-    // the look-ahead takes a workgroup of its own when the launch's tiles
-    // leave room on the chip for it, else it follows the last tile of each
-    // matrix in that tile's workgroup
-    const int la_after = (dnext && (long long)(tiles * tiles + 1) * batch > resident &&
-                          (long long)tiles * tiles * batch <= resident) ? 1 : 0;
-    const int wgs = tiles * tiles + ((dnext && !la_after) ? 1 : 0);
+    // the look-ahead is workgroup 0 of each matrix, so that it starts at once
+    // even where the tiles fill the chip (a tile, not the look-ahead, then
+    // waits for a free slot)
+    const int wgs = tiles * tiles + (dnext ? 1 : 0);
     if (tiles32)
       hipLaunchKernelGGL((gj_update_kernel<T, 32>), dim3(wgs, batch), dim3(256), 0, st, cur, ldc, cs, nxt, ldn, ns,
-                         m, k0, kb, s.rowmap, dcur, colmap, check, level, dnext, k1, kb1, la_after);
+                         m, k0, kb, s.rowmap, dcur, colmap, check, level, dnext, k1, kb1);
     else
       hipLaunchKernelGGL((gj_update_kernel<T, 64>), dim3(wgs, batch), dim3(256), 0, st, cur, ldc, cs, nxt, ldn, ns,
-                         m, k0, kb, s.rowmap, dcur, colmap, check, level, dnext, k1, kb1, la_after);
+                         m, k0, kb, s.rowmap, dcur, colmap, check, level, dnext, k1, kb1);
     if ((err = hipPeekAtLastError()) != hipSuccess) return err;
     std::swap(cur, nxt);
     std::swap(ldc, ldn);
