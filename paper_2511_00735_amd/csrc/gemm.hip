@@ -1,5 +1,5 @@
-// Batched complex FP64 GEMM on the CDNA4 matrix cores (v_mfma_f64_16x16x4f64)
-// and batched strided copies.  All matrices are column-major; operands are
+// Batched complex GEMM (FP64 or FP32 storage) on the CDNA4 matrix cores
+// (v_mfma_f64_16x16x4f64, v_mfma_f32_16x16x4f32) and batched strided copies.  All matrices are column-major; operands are
 // addressed through IdxMap row/column selections so that sub-blocks of the
 // box maps (a side, all sides but one, a permuted scatter) are read and written
 // in place.
@@ -10,8 +10,8 @@
 //   Re = t1 - t2,  Im = t3 - t1 - t2.
 // Tile: BM x BN per workgroup, waves arranged WM x WN, each wave owning
 // (BM/WM) x (BN/WN) outputs as 16x16 MFMA tiles; K staged through LDS in
-// chunks of KT complex, the next chunk's global loads issued into registers
-// before the current chunk is multiplied.
+// chunks of KT complex, the next chunk's global loads (FP32: the next two
+// chunks') issued into registers before the current chunk is multiplied.
 #include "common.h"
 #include "host.h"
 
@@ -162,13 +162,8 @@ __device__ __forceinline__ void gemm_tile(const GemmArgsT<T>& a, int tile, int b
       t3[i][j] = acc_t{0, 0, 0, 0};
     }
 
-  fetch(0);
-  stash();
-  __syncthreads();
-  for (int k0 = 0; k0 < a.K; k0 += KT) {
-    // the next chunk's loads are in flight while this one is multiplied
-    const bool more = k0 + KT < a.K;
-    if (more) fetch(k0 + KT);
+  // the chunk in LDS times its 3M products
+  auto mult = [&]() {
 #pragma unroll
     for (int kk = 0; kk < KT; kk += 4) {
       T av[TM], bv[TN];
@@ -190,10 +185,56 @@ __device__ __forceinline__ void gemm_tile(const GemmArgsT<T>& a, int tile, int b
           t3[i][j] = Mfma<T>::mma(as[i], bs[j], t3[i][j]);
         }
     }
+  };
+  if constexpr (sizeof(T) == sizeof(cf)) {
+    // FP32: two chunks ahead (chunk c in LDS, chunk c + 1 in the second
+    // register set, chunk c + 2 being fetched into the first): a chunk's
+    // products take half as long as in FP64, and one chunk of lead left the
+    // loads exposed.  (FP64 tiles keep one chunk: a second register set
+    // would halve their occupancy.)
+    T ra2[SA], rb2[SB];
+    bool va2[SA], vb2[SB];
+    auto swap_sets = [&]() {
+#pragma unroll
+      for (int s = 0; s < SA; ++s) {
+        const T t = ra[s]; ra[s] = ra2[s]; ra2[s] = t;
+        const bool v = va[s]; va[s] = va2[s]; va2[s] = v;
+      }
+#pragma unroll
+      for (int s = 0; s < SB; ++s) {
+        const T t = rb[s]; rb[s] = rb2[s]; rb2[s] = t;
+        const bool v = vb[s]; vb[s] = vb2[s]; vb2[s] = v;
+      }
+    };
+    fetch(0);
+    stash();
+    if (KT < a.K) fetch(KT);
+    swap_sets();   // chunk 1 in the second set
     __syncthreads();
-    if (more) {
-      stash();
+    for (int k0 = 0; k0 < a.K; k0 += KT) {
+      if (k0 + 2 * KT < a.K) fetch(k0 + 2 * KT);   // into the first set
+      mult();
       __syncthreads();
+      if (k0 + KT < a.K) {
+        swap_sets();   // chunk c + 1 to the first set, chunk c + 2 to the second
+        stash();
+        __syncthreads();
+      }
+    }
+  } else {
+    fetch(0);
+    stash();
+    __syncthreads();
+    for (int k0 = 0; k0 < a.K; k0 += KT) {
+      // the next chunk's loads are in flight while this one is multiplied
+      const bool more = k0 + KT < a.K;
+      if (more) fetch(k0 + KT);
+      mult();
+      __syncthreads();
+      if (more) {
+        stash();
+        __syncthreads();
+      }
     }
   }
 
