@@ -111,6 +111,8 @@ struct GemmArgsT {
 };
 typedef GemmArgsT<cd> GemmArgs;
 // D = alpha * A B + beta * C (+ diag_add I), all column-major; complex MFMA.
+// The maps along K (A's columns, B's rows) must be offsets with an optional
+// gap (im_off, im_gap), not tables: hipErrorInvalidValue otherwise.
 template <class T>
 hipError_t zgemm(const GemmArgsT<T>& a, hipStream_t st);
 // Up to kGemmGroup independent GEMMs (none reads what another writes) in one
@@ -135,7 +137,7 @@ __host__ __device__ inline bool y_physical(const PhysSkip& s, int bx, int by, in
 
 // ---- batched complex inversion (inverse.hip) -------------------------------
 // In-place inverse of `batch` m x m column-major matrices (stride `bstride`),
-// Gauss-Jordan.  m <= 64 (and m <= 128 with `pivot`): partial pivoting, in
+// Gauss-Jordan.  m <= 32 (and m <= 128 with `pivot`): partial pivoting, in
 // registers.  Larger m, blocked in 32-column steps: with `pivot`, partial
 // pivoting over all rows; without,
 // no row interchanges across blocks (the diagonal blocks inverted as they
