@@ -73,6 +73,11 @@ struct IdxMap {
 __host__ __device__ inline int imap(const IdxMap& m, int i) {
   return m.map ? m.map[i] : m.off + i + (i >= m.gap_start ? m.gap_len : 0);
 }
+// The same map when it is known not to be a table: no load, so that a loop
+// evaluating it does not wait on the loads it has in flight.
+__host__ __device__ inline int imap_arith(const IdxMap& m, int i) {
+  return m.off + i + (i >= m.gap_start ? m.gap_len : 0);
+}
 __host__ __device__ inline IdxMap im_off(int off) { return IdxMap{nullptr, off, 1 << 30, 0}; }
 __host__ __device__ inline IdxMap im_gap(int off, int gap_start, int gap_len) {
   return IdxMap{nullptr, off, gap_start, gap_len};

@@ -24,10 +24,6 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int KT = 16;
 
-// A map along K (offset plus gap; tables are refused by the host): no load, so
-// the loop's waits count only the operand loads in flight.
-__device__ inline int kmap(const IdxMap& m, int i) { return m.off + i + (i >= m.gap_start ? m.gap_len : 0); }
-
 // One 16x16x4 real MFMA per precision, and where its result lands: lane l,
 // element v -> row(l, v), column l % 16 (the two layouts differ; both were
 // checked on gfx950).
@@ -133,11 +129,11 @@ __device__ __forceinline__ void gemm_tile(const GemmArgsT<T>& a, int tile, int b
     for (int s = 0; s < SA; ++s) {
       const int gk = k0 + ka + s * KSA;
       va[s] = rowok && gk < a.K;
-      offA[s] = va[s] ? (long long)kmap(a.A.c, gk) * a.A.ld + rA : 0;
+      offA[s] = va[s] ? (long long)imap_arith(a.A.c, gk) * a.A.ld + rA : 0;
     }
     const int gk = k0 + kb;
     const bool kok = gk < a.K;
-    const long long rB = kok ? kmap(a.B.r, gk) : 0;
+    const long long rB = kok ? imap_arith(a.B.r, gk) : 0;
 #pragma unroll
     for (int s = 0; s < SA; ++s) ra[s] = Ab[offA[s]];
 #pragma unroll
@@ -385,7 +381,7 @@ hipError_t launch_group(const GemmArgsT<T>* g, int n, hipStream_t st) {
 template <class T>
 hipError_t zgemm(const GemmArgsT<T>& a, hipStream_t st) {
   if (a.M <= 0 || a.N <= 0 || a.batch <= 0) return hipSuccess;
-  if (a.A.c.map || a.B.r.map) return hipErrorInvalidValue;   // K maps are offsets (kmap)
+  if (a.A.c.map || a.B.r.map) return hipErrorInvalidValue;   // K maps are offsets (imap_arith)
   // 64x64 tiles while they still give two workgroups per CU; 32x32 otherwise
   const long long t64 = (long long)((a.M + 63) / 64) * ((a.N + 63) / 64) * a.batch;
   if (a.M >= 48 && a.N >= 48 && t64 >= 512) return launch<T, 64, 64, 2, 2>(a, st);
@@ -400,7 +396,7 @@ hipError_t zgemm_group(const GemmArgsT<T>* g, int n, hipStream_t st) {
   GemmArgsT<T> live[kGemmGroup];
   int k = 0;
   for (int i = 0; i < n; ++i) {
-    if (g[i].A.c.map || g[i].B.r.map) return hipErrorInvalidValue;   // K maps are offsets (kmap)
+    if (g[i].A.c.map || g[i].B.r.map) return hipErrorInvalidValue;   // K maps are offsets (imap_arith)
     if (g[i].M > 0 && g[i].N > 0 && g[i].batch > 0) live[k++] = g[i];
   }
   if (k == 0) return hipSuccess;

@@ -43,7 +43,8 @@ struct VecOut {
 };
 
 // The matrix may be stored in complex FP64 (M = cd) or FP32 (M = cf); x, y and
-// the accumulation are always FP64.
+// the accumulation are always FP64.  Its column map must be an offset with an
+// optional gap, not a table (hipErrorInvalidValue otherwise).
 template <class M>
 struct GemvDescT {
   int M_, K;

@@ -76,7 +76,7 @@ __global__ __launch_bounds__(NT) void gemv_kernel(GemvBatchT<Mt> gb, cd* partial
   for (int u = 0; u < U; ++u) a0[u] = cx<Mt>::make(0.0, 0.0);
   if (k0 < k1) {  // uniform over the workgroup
 #pragma unroll
-    for (int u = 0; u < U; ++u) a0[u] = Ab[(long long)imap(d.A.c, min(k0 + grp + NW * u, k1 - 1)) * d.A.ld + row];
+    for (int u = 0; u < U; ++u) a0[u] = Ab[(long long)imap_arith(d.A.c, min(k0 + grp + NW * u, k1 - 1)) * d.A.ld + row];
   }
   for (int k = k0 + t; k < k1; k += NT) {
     const cd v = load_x(d.x, b, k);
@@ -95,11 +95,11 @@ __global__ __launch_bounds__(NT) void gemv_kernel(GemvBatchT<Mt> gb, cd* partial
     for (; k + NW * (U - 1) < k1; k += NW * U) {
       Mt a[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) a[u] = Ab[(long long)imap(d.A.c, k + NW * u) * d.A.ld + row];
+      for (int u = 0; u < U; ++u) a[u] = Ab[(long long)imap_arith(d.A.c, k + NW * u) * d.A.ld + row];
 #pragma unroll
       for (int u = 0; u < U; ++u) acc = cfma(to_cd(a[u]), xs[k + NW * u - k0], acc);
     }
-    for (; k < k1; k += NW) acc = cfma(to_cd(Ab[(long long)imap(d.A.c, k) * d.A.ld + row]), xs[k - k0], acc);
+    for (; k < k1; k += NW) acc = cfma(to_cd(Ab[(long long)imap_arith(d.A.c, k) * d.A.ld + row]), xs[k - k0], acc);
   }
   red[grp][lane] = acc;
   __syncthreads();
@@ -492,6 +492,8 @@ int gemv_nsplit(int M, int K, int batch) {
 template <class Mt>
 hipError_t zgemv_batched(const GemvDescT<Mt>* d, int nd, int batch, cd* partial, hipStream_t st) {
   if (nd <= 0 || nd > kGemvMaxDesc || batch <= 0) return hipErrorInvalidValue;
+  for (int i = 0; i < nd; ++i)
+    if (d[i].A.c.map) return hipErrorInvalidValue;   // column maps are offsets (imap_arith)
   GemvBatchT<Mt> gb{};
   gb.batch = batch;
   int gx = 0;
@@ -519,6 +521,8 @@ template <class Mt>
 hipError_t zgemv_partials(const GemvDescT<Mt>* d, int nd, int batch, cd* partial, GemvPartLayout* lay,
                           hipStream_t st, int max_split) {
   if (nd <= 0 || nd > kGemvMaxDesc || batch <= 0 || !partial || !lay) return hipErrorInvalidValue;
+  for (int i = 0; i < nd; ++i)
+    if (d[i].A.c.map) return hipErrorInvalidValue;   // column maps are offsets (imap_arith)
   GemvBatchT<Mt> gb{};
   gb.batch = batch;
   gb.partials_only = 1;
