@@ -29,6 +29,8 @@
 #include "host.h"
 #include "pivot.h"
 
+#include <climits>
+
 namespace hps {
 
 namespace {
@@ -726,19 +728,22 @@ __global__ __launch_bounds__(256) void gj_update_kernel(const T* A, int lda, lon
   __shared__ T Xs[kNB][BT];
   __shared__ T Bp[kNB][BT];     // A'[P, jtile]
   __shared__ T Ac[kNB][BT + 1]; // A'[itile, C], transposed
-  const int tiles = (m + BT - 1) / BT;
-  if (dnext && blockIdx.x == 0) {
-    // workgroup 0, dispatched first: the next step's pivot block inverse (no
-    // row interchanges; Xs, Bp, Ac and Ds hold the four kNB x kNB blocks it
-    // needs), formed while the tiles (workgroups 1, 2, ...) are updated
-    const int b = blockIdx.y;
+  const int tiles = (m + BT - 1) / BT, per = tiles * tiles;
+  // one flat grid: with a look-ahead, workgroups 0 .. batch-1 are the
+  // matrices' look-aheads (dispatched first), then each matrix's tiles
+  const int nla = dnext ? (int)gridDim.x / (per + 1) : 0;
+  if ((int)blockIdx.x < nla) {
+    // the next step's pivot block inverse of matrix blockIdx.x (no row
+    // interchanges; Xs, Bp, Ac and Ds hold the four kNB x kNB blocks it
+    // needs), formed while the tiles are updated
+    const int b = blockIdx.x;
     gj_next_diag<T>(A + (long long)b * astride, lda, k0, kb, k1, kb1, dinv + (long long)b * kNB * kNB,
                     dnext + (long long)b * kNB * kNB, &Xs[0][0], &Bp[0][0], &Ac[0][0], Ds, check, level);
     return;
   }
-  const int tile = dnext ? (int)blockIdx.x - 1 : (int)blockIdx.x;
+  const int q = (int)blockIdx.x - nla;
+  const int tile = q % per, b = q / per;
   const int i0 = (tile % tiles) * BT, j0 = (tile / tiles) * BT;
-  const int b = blockIdx.y;
   const T* Ab = A + (long long)b * astride;
   T* Ob = O + (long long)b * ostride;
   const int* rm = rowmap + (long long)b * m;
@@ -866,10 +871,12 @@ hipError_t inverse_blocked(T* A, int m, int lda, long long bstride, int batch, v
   T* nxt = s.buf;
   int ldn = m;
   long long ns = (long long)m * m;
-  // 32 x 32 update tiles when 64 x 64 ones would give few workgroups (under
-  // 512 in FP32, 256 in FP64, whose 64 x 64 tiles fill a CU's LDS alone)
+  // 32 x 32 update tiles when 64 x 64 ones would give under 512 workgroups:
+  // then a step lasts about as long as its look-ahead (FP64 m = 480 in four
+  // matrices: 44 us per step with 256 tiles of 64 x 64, which fill the chip
+  // at one per CU, against ~29 us with 900 of 32 x 32)
   const long long w64 = (long long)((m + 63) / 64) * ((m + 63) / 64) * batch;
-  const bool tiles32 = w64 < (sizeof(T) == sizeof(cf) ? 512 : 256);
+  const bool tiles32 = w64 < 512;
   const int tiles = tiles32 ? (m + 31) / 32 : (m + 63) / 64;
   // register panels: rows <= 512 with 32 columns, FP64 rows <= 1024 with 16
   // columns; larger matrices keep the LDS panel
@@ -907,16 +914,17 @@ hipError_t inverse_blocked(T* A, int m, int lda, long long bstride, int batch, v
     const bool last_into_A = (s_ == steps - 1) && nxt == A;
     const int* colmap = (last_into_A && pivot) ? rho : nullptr;
     int* check = pivot ? nullptr : flag;
-    // the look-ahead is workgroup 0 of each matrix, so that it starts at once
-    // even where the tiles fill the chip (a tile, not the look-ahead, then
-    // waits for a free slot)
-    const int wgs = tiles * tiles + (dnext ? 1 : 0);
+    // the look-aheads are the launch's first workgroups, so that they start at
+    // once even where the tiles fill the chip (tiles, not look-aheads, then
+    // wait for free slots)
+    const long long wgs = (long long)(tiles * tiles + (dnext ? 1 : 0)) * batch;
+    if (wgs > INT_MAX) return hipErrorInvalidValue;
     if (tiles32)
-      hipLaunchKernelGGL((gj_update_kernel<T, 32>), dim3(wgs, batch), dim3(256), 0, st, cur, ldc, cs, nxt, ldn, ns,
-                         m, k0, kb, s.rowmap, dcur, colmap, check, level, dnext, k1, kb1);
+      hipLaunchKernelGGL((gj_update_kernel<T, 32>), dim3((unsigned)wgs), dim3(256), 0, st, cur, ldc, cs, nxt, ldn,
+                         ns, m, k0, kb, s.rowmap, dcur, colmap, check, level, dnext, k1, kb1);
     else
-      hipLaunchKernelGGL((gj_update_kernel<T, 64>), dim3(wgs, batch), dim3(256), 0, st, cur, ldc, cs, nxt, ldn, ns,
-                         m, k0, kb, s.rowmap, dcur, colmap, check, level, dnext, k1, kb1);
+      hipLaunchKernelGGL((gj_update_kernel<T, 64>), dim3((unsigned)wgs), dim3(256), 0, st, cur, ldc, cs, nxt, ldn,
+                         ns, m, k0, kb, s.rowmap, dcur, colmap, check, level, dnext, k1, kb1);
     if ((err = hipPeekAtLastError()) != hipSuccess) return err;
     std::swap(cur, nxt);
     std::swap(ldc, ldn);
