@@ -460,6 +460,7 @@ __global__ __launch_bounds__(kCT) void coarse_arnoldi_kernel(cd* V, int n, long 
 // workgroup sum of j+1 values.  Same arithmetic as coarse_arnoldi_kernel up to
 // the order of the dot-product sums.
 constexpr int kFastV = 6;
+constexpr int kFastSplits = 8;   // split-K partials summed in one round of loads
 
 // The least squares of lsq_small for k <= kFastV in one wavefront (called by
 // all 64 lanes of a wave): lane q holds column q of R in registers; rotation j
@@ -568,50 +569,75 @@ __global__ __launch_bounds__(NT) void coarse_arnoldi_fast_kernel(cd* V, int n, l
     for (int i = t; i < hsize; i += NT) H[i] = cmk(0.0, 0.0);
     if (t == 0) ends.beta2[qp] = b2;
     __syncthreads();   // red is reused below; H is zeroed before column 0 is written
-  } else {
+  }
+  // later steps load V_0..V_j after the split-K partials below, so that the
+  // partials' loads are in flight together without V's registers
+  auto load_v = [&]() {
 #pragma unroll
     for (int e = 0; e < EP; ++e) {
       const int i = t + e * NT;
 #pragma unroll
       for (int v = 0; v < kFastV; ++v) vv[v][e] = (v <= j && i < n) ? V[(long long)v * n + i] : cmk(0.0, 0.0);
     }
-  }
-  const cd* vj = V + (long long)j * n;
+  };
   if (src.part) {
-    // w = v_j - (sum of the split-K partials, in split order); the partials of
-    // all EP entries of a thread are loaded together, four splits at a time
+    // w = v_j - (sum of the split-K partials, in split order)
     const cd* pp[EP];
-    int nse[EP];
+    int nse[EP], nsa[EP];
 #pragma unroll
     for (int e = 0; e < EP; ++e) {
-      const int i = t + e * NT;
-      const bool second = i >= src.m;
-      const int r = second ? i - src.m : i;
+      const int i = t + e * NT, ic = min(i, n - 1);   // ic: a valid address for every lane
+      const bool second = ic >= src.m;
+      const int r = second ? ic - src.m : ic;
       pp[e] = src.part + (second ? src.poff1 : src.poff0) + (long long)qp * src.m + r;
-      nse[e] = i < n ? (second ? src.ns1 : src.ns0) : 0;
+      nsa[e] = second ? src.ns1 : src.ns0;
+      nse[e] = i < n ? nsa[e] : 0;
       w[e] = cmk(0.0, 0.0);
     }
     const long long qs = (long long)src.nb * src.m;
     const int nsmax = max(src.ns0, src.ns1);
-    for (int q0 = 0; q0 < nsmax; q0 += 4) {
-      cd tmp[4][EP];
+    if (nsmax <= kFastSplits) {
+      // every split of every entry in one round: unconditional loads (clamped
+      // to the entry's last split), so that no branch makes the compiler wait
+      // between them
+      cd tmp[kFastSplits][EP];
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int u = 0; u < kFastSplits; ++u)
 #pragma unroll
-        for (int e = 0; e < EP; ++e) tmp[u][e] = q0 + u < nse[e] ? pp[e][(q0 + u) * qs] : cmk(0.0, 0.0);
+        for (int e = 0; e < EP; ++e) tmp[u][e] = pp[e][(long long)min(u, nsa[e] - 1) * qs];
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int u = 0; u < kFastSplits; ++u)
 #pragma unroll
         for (int e = 0; e < EP; ++e)
-          if (q0 + u < nse[e]) w[e] = cadd(w[e], tmp[u][e]);
+          if (u < nse[e]) w[e] = cadd(w[e], tmp[u][e]);
+    } else {
+      for (int q0 = 0; q0 < nsmax; q0 += 4) {   // four splits at a time
+        cd tmp[4][EP];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int e = 0; e < EP; ++e) tmp[u][e] = q0 + u < nse[e] ? pp[e][(q0 + u) * qs] : cmk(0.0, 0.0);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int e = 0; e < EP; ++e)
+            if (q0 + u < nse[e]) w[e] = cadd(w[e], tmp[u][e]);
+      }
     }
-    // first step: the product is of w0, so M V_0 = (w0 - partials) / beta
+    if (!first) load_v();
+    // first step: the product is of w0, so M V_0 = (w0 - partials) / beta;
+    // later ones: v_j - partials, v_j from the registers just loaded
 #pragma unroll
     for (int e = 0; e < EP; ++e) {
       const int i = t + e * NT;
-      w[e] = i < n ? (first ? csub(vv[0][e], cscale(w[e], inv_beta)) : csub(vj[i], w[e])) : cmk(0.0, 0.0);
+      cd vje = vv[0][e];
+#pragma unroll
+      for (int v = 1; v < kFastV; ++v)
+        if (v == j) vje = vv[v][e];
+      w[e] = i < n ? (first ? csub(vv[0][e], cscale(w[e], inv_beta)) : csub(vje, w[e])) : cmk(0.0, 0.0);
     }
   } else {
+    if (!first) load_v();
 #pragma unroll
     for (int e = 0; e < EP; ++e) {
       const int i = t + e * NT;
@@ -873,7 +899,7 @@ bool coarse_fast_ok(int n, int k) {
 
 hipError_t coarse_arnoldi(cd* V, int n, long long vq, int j, const CoarseW& src, cd* wtmp, cd* Hcol, int hsize,
                           int nq, hipStream_t st, const CoarseEnds* ends) {
-  if (j < 0 || j + 1 > kMaxCoarse) return hipErrorInvalidValue;
+  if (n < 1 || j < 0 || j + 1 > kMaxCoarse) return hipErrorInvalidValue;
   const CoarseEnds none{};
   if (ends) {
     // the fused start and end exist only on the register kernels
