@@ -253,17 +253,33 @@ struct RegGemv {
 template <class Mt> struct SmallCap { static constexpr int A = 8, T = 12, X = 16; };
 template <> struct SmallCap<cd> { static constexpr int A = 4, T = 8, X = 12; };
 
-// Down sweep, half h of pair j (workgroup 2j + h).  x = [Q.beta; P.alpha]:
+// The map i -> m(i + r0).
+__device__ inline IdxMap im_shift(IdxMap m, int r0) {
+  if (m.map) {
+    m.map += r0;
+  } else {
+    m.off += r0;
+    m.gap_start -= r0;
+  }
+  return m;
+}
+
+// Down sweep, half h of pair j, row piece pc of P (workgroup (2j + h) P + pc;
+// levels with few pairs split each half's T rows over P workgroups, each of
+// which forms the whole z0 half again).  x = [Q.beta; P.alpha]:
 // h = 0 forms z0_P = rows [m, 2m) of A^-1 r_x and adds T^P_{E1,a} z0_P to the
 // slots across P's kept faces; h = 1 forms z0_Q = rows [0, m) and adds
 // T^Q_{E2,b} z0_Q across Q's.  The two halves touch disjoint slots, and no
 // other pair of the level reads or writes those slots.
 template <class Mt, int NT>
-__global__ __launch_bounds__(NT) void vc_down_small_kernel(SmallLevelT<Mt> a, cd* vec) {
+__global__ __launch_bounds__(NT) void vc_down_small_kernel(SmallLevelT<Mt> a, cd* vec, int P) {
   extern __shared__ cd sm[];
   const int m = a.m, e = a.e, m2 = 2 * m;
   const int bid = xcd_swizzle(blockIdx.x, gridDim.x);
-  const int j = bid >> 1, h = bid & 1, t = threadIdx.x;
+  const int jh = bid / P, pc = bid - jh * P;
+  const int j = jh >> 1, h = jh & 1, t = threadIdx.x;
+  const int R = (e + P - 1) / P, r0 = pc * R, Me = min(R, e - r0);   // this piece's T rows
+  if (Me <= 0) return;   // uniform over the workgroup
   cd* r = sm;             // [2m] r_x
   cd* z = r + m2;         // [m]  z0 half
   cd* dv = z + m;         // [e]  vector values across the faces
@@ -272,28 +288,28 @@ __global__ __launch_bounds__(NT) void vc_down_small_kernel(SmallLevelT<Mt> a, cd
   int* ds = reinterpret_cast<int*>(red + NT);  // [e] slots across the faces
   const long long bb = (long long)a.g.b * a.g.b;
   const int xi = t < m2 ? a.xtab[(long long)j * m2 + t] : -1;
-  const int di = t < e ? a.dtab[(long long)j * 2 * e + h * e + t] : -1;
+  const int di = t < Me ? a.dtab[(long long)j * 2 * e + h * e + r0 + t] : -1;
   RegGemv<Mt, NT, SmallCap<Mt>::A> ga;
   RegGemv<Mt, NT, SmallCap<Mt>::T> gt;
   ga.setup(m, m2);
-  gt.setup(e, m);
+  gt.setup(Me, m);
   const Mt* Ai = a.Ainv + (long long)j * m2 * m2;
   const IdxMap arow = im_off(h == 0 ? m : 0);
   const Mt* Th = a.T + (2LL * j + h) * bb;
-  const IdxMap trow = h == 0 ? a.E1 : a.E2;
+  const IdxMap trow = im_shift(h == 0 ? a.E1 : a.E2, r0);
   const IdxMap tcol = im_off(h == 0 ? a.a0 : a.b0);
   ga.load(Ai, m2, arow, im_off(0));
   gt.load(Th, a.g.b, trow, tcol);
   if (t < m2) r[t] = vec[xi];
-  if (t < e) {
+  if (t < Me) {
     ds[t] = di;
     dv[t] = di >= 0 ? vec[di] : cmk(0.0, 0.0);
   }
   __syncthreads();
   ga.run(Ai, m2, arow, im_off(0), r, nullptr, z, red);
-  if (t < m) a.Z0[(long long)j * m2 + (h == 0 ? m : 0) + t] = z[t];
+  if (pc == 0 && t < m) a.Z0[(long long)j * m2 + (h == 0 ? m : 0) + t] = z[t];
   gt.run(Th, a.g.b, trow, tcol, z, dv, dd, red);
-  if (t < e && ds[t] >= 0) vec[ds[t]] = dd[t];
+  if (t < Me && ds[t] >= 0) vec[ds[t]] = dd[t];
 }
 
 // Up sweep, piece p of pair j (workgroup P j + p): rows [p R, p R + M) of
@@ -583,12 +599,24 @@ int up_pieces(int m, int pairs) {
   return P;
 }
 
+// T-row pieces per pair half for the down sweep: more while the level has
+// fewer than kSmallDownWGs workgroups and a piece keeps at least 64 rows.
+#ifndef HPS_SMALL_DOWN_WGS
+#define HPS_SMALL_DOWN_WGS 256
+#endif
+int down_pieces(int e, int pairs) {
+  int P = 1;
+  while (2LL * P * pairs < HPS_SMALL_DOWN_WGS && e >= 2 * P * 64 && P < 4) P *= 2;
+  return P;
+}
+
 template <class Mt, int NT>
 hipError_t launch_down(const SmallLevelT<Mt>& a, int pairs, cd* vec, hipStream_t st) {
   const size_t lds = small_down_lds(a.m, a.e, NT);
   hipError_t err = allow_lds(vc_down_small_kernel<Mt, NT>, lds);
   if (err != hipSuccess) return err;
-  hipLaunchKernelGGL((vc_down_small_kernel<Mt, NT>), dim3(2 * pairs), dim3(NT), lds, st, a, vec);
+  const int P = down_pieces(a.e, pairs);
+  hipLaunchKernelGGL((vc_down_small_kernel<Mt, NT>), dim3(2 * pairs * P), dim3(NT), lds, st, a, vec, P);
   return hipPeekAtLastError();
 }
 
